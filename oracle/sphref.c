@@ -1,0 +1,912 @@
+/*
+ * sphref.c -- plain FP64 CPU oracle of the feature-aware SPH relaxation step.
+ *
+ * TEST INFRASTRUCTURE ONLY (see sphref.h): used by the tests, the smoke check
+ * and the benchmark's CPU baseline; never by the GPU product path.
+ *
+ * The code follows the paper section by section:
+ *   geometry and features ........ sec. 3.1-3.2 (level set, feature tags,
+ *                                   particle types P_si, P_c, P_s, P_+)
+ *   target feature size .......... sec. 2.2, Eq. (target_mesh_gen)
+ *   kernel ....................... Wendland C2 with support 2h (the paper only
+ *                                   names a cut-off radius r_c, sec. 2.3)
+ *   Shepard term gamma ........... sec. 3.3, Eq. (gamma_disc_renormSPH)
+ *   pressure force + boundary .... sec. 3.3, Eq. (sph_pressure_force_disc_weighted)
+ *   viscous force ................ sec. 2.3, Eq. (momentum_equation_discretized),
+ *                                   Eq. (viscosity_coefficient)
+ *   time step per feature ........ sec. 3.5, Eq. (fa_time_step_size)
+ *   particle volume, V-bar ....... sec. 3.4.2, Eqs. (particle_volume),
+ *                                   (volume_integral)
+ *   two-phase control ............ sec. 3.4.2-3.4.4, Eq. (momentum_equation_new)
+ *   step order ................... Algorithm 1 (flowchart)
+ * Points the paper leaves open are resolved by named readings R1..R26, the
+ * same list the design document keeps; each appears where it is used.
+ *
+ * Built with gcc -O2 -ffp-contract=off: no fused multiply-add anywhere, so
+ * every expression rounds exactly as written.
+ */
+#include "sphref.h"
+
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define MAXF 64
+#define MAXH 32
+
+static __thread char g_err[256];
+static void set_err(const char *m) { snprintf(g_err, sizeof g_err, "%s", m); }
+const char *sphref_last_error(void) { return g_err; }
+
+/* ------------------------------------------------------------------ */
+/* features (sec. 3.2)                                                  */
+/* ------------------------------------------------------------------ */
+enum { T_SI = 0, T_C = 1, T_S = 2, T_V = 3 };
+enum { K_VOL, K_BOXSIDE, K_HOLE, K_EDGE3, K_CORNER };
+
+typedef struct {
+  int type, k, kind;
+  int axis, side;           /* BOXSIDE: normal axis and side; EDGE3: direction axis */
+  int fax[2], fsd[2];       /* EDGE3: the two fixed axes and their sides */
+  int hole;                 /* HOLE: hole index */
+  int bits;                 /* CORNER: side bit per axis */
+} feat_t;
+
+typedef struct {
+  int dim;
+  double lo[3], hi[3];
+  int nh;
+  double hc[MAXH][3], hr[MAXH];
+  int nf;
+  feat_t f[MAXF];
+} geo_t;
+
+static int geo_build(const sphref_geometry *g, geo_t *G) {
+  memset(G, 0, sizeof *G);
+  if (!g || (g->dim != 2 && g->dim != 3)) { set_err("dim must be 2 or 3"); return -1; }
+  if (g->n_holes < 0 || g->n_holes > MAXH) { set_err("bad hole count"); return -1; }
+  G->dim = g->dim;
+  for (int a = 0; a < 3; ++a) { G->lo[a] = g->lo[a]; G->hi[a] = g->hi[a]; }
+  for (int a = 0; a < g->dim; ++a)
+    if (!(g->lo[a] < g->hi[a])) { set_err("empty box"); return -1; }
+  G->nh = g->n_holes;
+  for (int q = 0; q < G->nh; ++q) {
+    const double *H = g->holes + 15 * q;
+    if (!(H[3] > 0) || H[4] != H[3] || H[5] != H[3]) {
+      set_err("only discs / balls (equal semi-axes) are supported");
+      return -1;
+    }
+    for (int a = 0; a < 3; ++a) G->hc[q][a] = H[a];
+    G->hr[q] = H[3];
+  }
+  int D = G->dim, nf = 0;
+  G->f[nf++] = (feat_t){.type = T_V, .k = D, .kind = K_VOL};
+  for (int a = 0; a < D; ++a)
+    for (int s = 0; s < 2; ++s)
+      G->f[nf++] = (feat_t){.type = D == 2 ? T_C : T_S, .k = D - 1,
+                            .kind = K_BOXSIDE, .axis = a, .side = s};
+  for (int q = 0; q < G->nh; ++q)
+    G->f[nf++] = (feat_t){.type = D == 2 ? T_C : T_S, .k = D - 1,
+                          .kind = K_HOLE, .hole = q};
+  if (D == 3) {
+    for (int a = 0; a < 3; ++a) {
+      int b = a == 0 ? 1 : 0, c = a == 2 ? 1 : 2;
+      for (int q = 0; q < 4; ++q) {
+        feat_t e = {.type = T_C, .k = 1, .kind = K_EDGE3, .axis = a};
+        e.fax[0] = b; e.fsd[0] = q & 1;
+        e.fax[1] = c; e.fsd[1] = (q >> 1) & 1;
+        G->f[nf++] = e;
+      }
+    }
+  }
+  for (int c = 0; c < (1 << D); ++c)
+    G->f[nf++] = (feat_t){.type = T_SI, .k = 0, .kind = K_CORNER, .bits = c};
+  G->nf = nf;
+  return 0;
+}
+
+/* fb bounds fi: the lower-dimensional feature fb lies on the boundary of fi
+ * (reading R12: the boundary relation of sec. 3.3 is taken between adjacent
+ * features; a volume is bounded by every lower-dimensional feature). */
+static int bounds(const geo_t *G, int fi, int fb) {
+  const feat_t *A = &G->f[fi], *B = &G->f[fb];
+  if (B->k >= A->k) return 0;
+  switch (A->kind) {
+    case K_VOL: return 1;
+    case K_BOXSIDE:
+      if (B->kind == K_CORNER) return ((B->bits >> A->axis) & 1) == A->side;
+      if (B->kind == K_EDGE3)
+        return (B->fax[0] == A->axis && B->fsd[0] == A->side) ||
+               (B->fax[1] == A->axis && B->fsd[1] == A->side);
+      return 0;
+    case K_EDGE3:
+      if (B->kind == K_CORNER)
+        return ((B->bits >> A->fax[0]) & 1) == A->fsd[0] &&
+               ((B->bits >> A->fax[1]) & 1) == A->fsd[1];
+      return 0;
+    default: return 0;
+  }
+}
+
+static double sg(int side) { return side ? 1.0 : -1.0; }
+
+/* outward normal n_b of feature fi's boundary at boundary particle b
+ * (sec. 3.3, Eq. (gradient_operator_renormSPH_bypart): n points out of the
+ * domain of i; reading R13 for edges and corners). */
+static void bnormal(const geo_t *G, int fi, int fb, const double *xb, double *n) {
+  const feat_t *A = &G->f[fi], *B = &G->f[fb];
+  int D = G->dim;
+  n[0] = n[1] = n[2] = 0.0;
+  if (A->kind == K_VOL) {
+    if (B->kind == K_BOXSIDE) {
+      n[B->axis] = sg(B->side);
+    } else if (B->kind == K_HOLE) {
+      /* out of the domain = into the hole, towards its centre */
+      double d[3] = {0, 0, 0}, s = 0.0;
+      for (int a = 0; a < D; ++a) { d[a] = G->hc[B->hole][a] - xb[a]; s = s + d[a] * d[a]; }
+      double r = sqrt(s);
+      for (int a = 0; a < D; ++a) n[a] = d[a] / r;
+    } else if (B->kind == K_EDGE3) {
+      double inv = 1.0 / sqrt(2.0);
+      n[B->fax[0]] = sg(B->fsd[0]) * inv;
+      n[B->fax[1]] = sg(B->fsd[1]) * inv;
+    } else if (B->kind == K_CORNER) {
+      double inv = 1.0 / sqrt((double)D);
+      for (int a = 0; a < D; ++a) n[a] = sg((B->bits >> a) & 1) * inv;
+    }
+  } else if (A->kind == K_BOXSIDE && D == 3) {
+    if (B->kind == K_EDGE3) {
+      int o = B->fax[0] == A->axis ? 1 : 0;   /* the fixed axis that is not the face normal */
+      n[B->fax[o]] = sg(B->fsd[o]);
+    } else if (B->kind == K_CORNER) {
+      double inv = 1.0 / sqrt(2.0);
+      for (int a = 0; a < 3; ++a)
+        if (a != A->axis) n[a] = sg((B->bits >> a) & 1) * inv;
+    }
+  } else if (A->kind == K_BOXSIDE && D == 2) {
+    int o = 1 - A->axis;                      /* the edge runs along axis o */
+    n[o] = sg((B->bits >> o) & 1);
+  } else if (A->kind == K_EDGE3) {
+    n[A->axis] = sg((B->bits >> A->axis) & 1);
+  }
+}
+
+/* tangent projection T_i u of sec. 3.6's "map onto feature k" (reading R18):
+ * identity for volume particles, remove the normal part on surfaces, keep the
+ * tangent part on curves, zero for singular particles. */
+static void tproject(const geo_t *G, int fi, const double *x, double *u) {
+  const feat_t *A = &G->f[fi];
+  int D = G->dim;
+  switch (A->kind) {
+    case K_VOL: return;
+    case K_BOXSIDE: u[A->axis] = 0.0; return;
+    case K_EDGE3: {
+      double keep = u[A->axis];
+      u[0] = u[1] = u[2] = 0.0;
+      u[A->axis] = keep;
+      return;
+    }
+    case K_HOLE: {
+      const double *c = G->hc[A->hole];
+      if (D == 2) {
+        double t0 = -(x[1] - c[1]), t1 = x[0] - c[0];
+        double tl = sqrt(t0 * t0 + t1 * t1);
+        t0 = t0 / tl; t1 = t1 / tl;
+        double ut = u[0] * t0 + u[1] * t1;
+        u[0] = ut * t0; u[1] = ut * t1;
+      } else {
+        double m[3], s = 0.0;
+        for (int a = 0; a < 3; ++a) { m[a] = x[a] - c[a]; s = s + m[a] * m[a]; }
+        double r = sqrt(s);
+        for (int a = 0; a < 3; ++a) m[a] = m[a] / r;
+        double un = u[0] * m[0] + u[1] * m[1] + u[2] * m[2];
+        for (int a = 0; a < 3; ++a) u[a] = u[a] - un * m[a];
+      }
+      return;
+    }
+    default: u[0] = u[1] = u[2] = 0.0; return;
+  }
+}
+
+static double clampd(double v, double lo, double hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+/* closest-point projection of x onto feature fi (reading R18) */
+static void pproject(const geo_t *G, int fi, double *x) {
+  const feat_t *A = &G->f[fi];
+  int D = G->dim;
+  switch (A->kind) {
+    case K_BOXSIDE:
+      for (int a = 0; a < D; ++a) x[a] = clampd(x[a], G->lo[a], G->hi[a]);
+      x[A->axis] = A->side ? G->hi[A->axis] : G->lo[A->axis];
+      return;
+    case K_EDGE3:
+      x[A->axis] = clampd(x[A->axis], G->lo[A->axis], G->hi[A->axis]);
+      for (int q = 0; q < 2; ++q)
+        x[A->fax[q]] = A->fsd[q] ? G->hi[A->fax[q]] : G->lo[A->fax[q]];
+      return;
+    case K_HOLE: {
+      const double *c = G->hc[A->hole];
+      double d[3] = {0, 0, 0}, s = 0.0;
+      for (int a = 0; a < D; ++a) { d[a] = x[a] - c[a]; s = s + d[a] * d[a]; }
+      double r = sqrt(s);
+      for (int a = 0; a < D; ++a) x[a] = c[a] + G->hr[A->hole] * (d[a] / r);
+      return;
+    }
+    case K_CORNER:
+      for (int a = 0; a < D; ++a) x[a] = ((A->bits >> a) & 1) ? G->hi[a] : G->lo[a];
+      return;
+    default: return;
+  }
+}
+
+/* phi(x) > 0: strictly inside the box and strictly outside every hole (sec. 2.1) */
+static int inside(const geo_t *G, const double *x) {
+  int D = G->dim;
+  for (int a = 0; a < D; ++a)
+    if (!(x[a] > G->lo[a] && x[a] < G->hi[a])) return 0;
+  for (int q = 0; q < G->nh; ++q) {
+    double s = 0.0;
+    for (int a = 0; a < D; ++a) { double d = x[a] - G->hc[q][a]; s = s + d * d; }
+    double r = G->hr[q];
+    if (!(s > r * r)) return 0;
+  }
+  return 1;
+}
+
+/* ------------------------------------------------------------------ */
+/* target feature size h_t(x) (sec. 2.2; reading R3: h_i = h_t(x_i))    */
+/* ------------------------------------------------------------------ */
+static double h_at(const geo_t *G, const sphref_sizing *S, const double *x) {
+  int D = G->dim;
+  if (S->kind == 0) return S->h0;
+  if (S->kind == 1) {
+    double s = 0.0;
+    for (int a = 0; a < D; ++a) { double d = x[a] - S->point[a]; s = s + d * d; }
+    return S->h0 + S->grad * sqrt(s);
+  }
+  double dmin = INFINITY;
+  for (int q = 0; q < G->nh; ++q) {
+    double s = 0.0;
+    for (int a = 0; a < D; ++a) { double d = x[a] - G->hc[q][a]; s = s + d * d; }
+    double d = fabs(sqrt(s) - G->hr[q]);
+    if (d < dmin) dmin = d;
+  }
+  if (S->dcap < dmin) dmin = S->dcap;
+  return S->h0 * (1.0 + S->grad * dmin);
+}
+
+/* ------------------------------------------------------------------ */
+/* kernel: Wendland C2, support 2h, intrinsic dimension k (reading R1,R2) */
+/* ------------------------------------------------------------------ */
+static double kalpha(int k) {
+  if (k == 1) return 5.0 / 8.0;
+  if (k == 2) return 7.0 / (4.0 * M_PI);
+  return 21.0 / (16.0 * M_PI);
+}
+static double hpow(double h, int k) {
+  double p = 1.0;
+  for (int e = 0; e < k; ++e) p = p * h;
+  return p;
+}
+double sphref_W(int32_t k, double r, double h) {
+  double q = r / h;
+  if (!(q < 2.0)) return 0.0;
+  double t = 1.0 - 0.5 * q;
+  double w = k == 1 ? t * t * t * (1.0 + 1.5 * q) : t * t * t * t * (1.0 + 2.0 * q);
+  return kalpha(k) * w / hpow(h, k);
+}
+double sphref_dWdr(int32_t k, double r, double h) {
+  double q = r / h;
+  if (!(q < 2.0)) return 0.0;
+  double t = 1.0 - 0.5 * q;
+  double dw = k == 1 ? -3.0 * q * t * t : -5.0 * q * t * t * t;
+  return kalpha(k) * dw / hpow(h, k + 1);
+}
+/* (dW/dr)/r, the same quantity written so that it stays finite at r = 0:
+ * with q = r/h, (dW/dr)/r = alpha * (w'(q)/q) / h^(k+2). */
+static double dWdr_over_r(int k, double r, double h) {
+  double q = r / h;
+  if (!(q < 2.0)) return 0.0;
+  double t = 1.0 - 0.5 * q;
+  double dwq = k == 1 ? -3.0 * t * t : -5.0 * t * t * t;
+  return kalpha(k) * dwq / hpow(h, k + 2);
+}
+
+/* ------------------------------------------------------------------ */
+/* job                                                                  */
+/* ------------------------------------------------------------------ */
+enum { PH_ONE = 1, PH_RAMP = 2, PH_TWO = 3, PH_FROZEN = 4 };
+
+typedef struct {
+  int phase, n_ph, reset_next, nring, nwin, count;
+  double dt_prev, dt1, dt, esys, vbar, a_last, a_prev;
+  double ring[64];
+} grp_t;
+
+struct sphref_job {
+  geo_t G;
+  sphref_sizing S;
+  sphref_params P;
+  int64_t n;
+  double *x, *v, *h, *ap, *a, *vt, *Vt, *gam, *eta;
+  int32_t *f;
+  grp_t g[MAXF];
+  /* neighbour lists of the current step */
+  int64_t *off;
+  int32_t *nb;
+  int8_t *rel;
+  int64_t cap;
+  /* counters */
+  int64_t steps, escaped, inter_total, inter_last;
+  int state_error;
+};
+
+static int ftype(const sphref_job *J, int64_t i) { return J->G.f[J->f[i]].type; }
+
+int32_t sphref_n_features(const sphref_geometry *g) {
+  geo_t G;
+  if (geo_build(g, &G)) return -1;
+  return G.nf;
+}
+int32_t sphref_feature_type(const sphref_geometry *g, int32_t f) {
+  geo_t G;
+  if (geo_build(g, &G) || f < 0 || f >= G.nf) return -1;
+  return G.f[f].type;
+}
+double sphref_h_at(const sphref_geometry *g, const sphref_sizing *s, const double *x) {
+  geo_t G;
+  if (geo_build(g, &G)) return NAN;
+  return h_at(&G, s, x);
+}
+int32_t sphref_project(const sphref_geometry *g, int32_t f, double *x) {
+  geo_t G;
+  if (geo_build(g, &G) || f < 0 || f >= G.nf) return -1;
+  pproject(&G, f, x);
+  return 0;
+}
+int32_t sphref_boundary_normal(const sphref_geometry *g, int32_t fi, int32_t fb,
+                               const double *xb, double *n) {
+  geo_t G;
+  if (geo_build(g, &G) || fi < 0 || fb < 0 || fi >= G.nf || fb >= G.nf) return -1;
+  if (!bounds(&G, fi, fb)) { n[0] = n[1] = n[2] = 0.0; return 0; }
+  bnormal(&G, fi, fb, xb, n);
+  return 1;
+}
+
+static void grp_init(grp_t *g) {
+  memset(g, 0, sizeof *g);
+  g->phase = PH_ONE;
+  g->esys = INFINITY;
+}
+
+int32_t sphref_create(const sphref_geometry *g, const sphref_sizing *s,
+                      const sphref_params *p, int64_t n, const double *xyz,
+                      const int32_t *feature, sphref_job **out) {
+  if (!out || !s || !p || n < 0 || (n > 0 && (!xyz || !feature))) { set_err("bad argument"); return -1; }
+  *out = NULL;
+  sphref_job *J = calloc(1, sizeof *J);
+  if (!J) { set_err("out of memory"); return -1; }
+  if (geo_build(g, &J->G)) { free(J); return -1; }
+  if (p->window_samples < 1 || p->window_samples > 64 || p->sample_every < 1 ||
+      p->reset_period < 1 || p->ramp_halving < 1) {
+    set_err("bad control parameters");
+    free(J);
+    return -1;
+  }
+  J->S = *s;
+  J->P = *p;
+  J->n = n;
+  size_t n3 = (size_t)(n > 0 ? n : 1) * 3;
+  J->x = calloc(n3, sizeof(double));
+  J->v = calloc(n3, sizeof(double));
+  J->ap = calloc(n3, sizeof(double));
+  J->a = calloc(n3, sizeof(double));
+  J->vt = calloc(n3, sizeof(double));
+  J->h = calloc(n3 / 3, sizeof(double));
+  J->Vt = calloc(n3 / 3, sizeof(double));
+  J->gam = calloc(n3 / 3, sizeof(double));
+  J->eta = calloc(n3 / 3, sizeof(double));
+  J->f = calloc(n3 / 3, sizeof(int32_t));
+  J->off = calloc(n3 / 3 + 1, sizeof(int64_t));
+  if (!J->x || !J->v || !J->ap || !J->a || !J->vt || !J->h || !J->Vt || !J->gam ||
+      !J->eta || !J->f || !J->off) {
+    set_err("out of memory");
+    sphref_destroy(J);
+    return -1;
+  }
+  for (int64_t i = 0; i < n; ++i) {
+    if (feature[i] < 0 || feature[i] >= J->G.nf) { set_err("feature index out of range"); sphref_destroy(J); return -1; }
+    J->f[i] = feature[i];
+    for (int a = 0; a < 3; ++a) J->x[3 * i + a] = a < J->G.dim ? xyz[3 * i + a] : 0.0;
+  }
+  for (int q = 0; q < J->G.nf; ++q) grp_init(&J->g[q]);
+  for (int64_t i = 0; i < n; ++i) J->g[J->f[i]].count++;
+  *out = J;
+  return 0;
+}
+
+void sphref_destroy(sphref_job *J) {
+  if (!J) return;
+  free(J->x); free(J->v); free(J->h); free(J->ap); free(J->a); free(J->vt);
+  free(J->Vt); free(J->gam); free(J->eta); free(J->f); free(J->off); free(J->nb); free(J->rel);
+  free(J);
+}
+
+int32_t sphref_set_state(sphref_job *J, const double *xyz, const double *vel) {
+  for (int64_t i = 0; i < J->n; ++i)
+    for (int a = 0; a < 3; ++a) {
+      if (xyz) J->x[3 * i + a] = a < J->G.dim ? xyz[3 * i + a] : 0.0;
+      if (vel) J->v[3 * i + a] = a < J->G.dim ? vel[3 * i + a] : 0.0;
+    }
+  return 0;
+}
+
+int32_t sphref_get_state(sphref_job *J, double *xyz, double *vel) {
+  if (xyz) memcpy(xyz, J->x, sizeof(double) * 3 * (size_t)J->n);
+  if (vel) memcpy(vel, J->v, sizeof(double) * 3 * (size_t)J->n);
+  return 0;
+}
+
+int32_t sphref_get_field(sphref_job *J, int32_t which, double *out) {
+  size_t n = (size_t)J->n;
+  switch (which) {
+    case SPHREF_F_H: memcpy(out, J->h, sizeof(double) * n); return 0;
+    case SPHREF_F_AP: memcpy(out, J->ap, sizeof(double) * 3 * n); return 0;
+    case SPHREF_F_A: memcpy(out, J->a, sizeof(double) * 3 * n); return 0;
+    case SPHREF_F_VT: memcpy(out, J->Vt, sizeof(double) * n); return 0;
+    case SPHREF_F_GAMMA: memcpy(out, J->gam, sizeof(double) * n); return 0;
+    case SPHREF_F_VMID: memcpy(out, J->vt, sizeof(double) * 3 * n); return 0;
+    default: set_err("unknown field"); return -1;
+  }
+}
+
+/* ------------------------------------------------------------------ */
+/* neighbour lists (Algorithm 1: "construct Verlet neighbor list")       */
+/* ------------------------------------------------------------------ */
+/* relation of j to i (sec. 3.3 interaction hierarchy; reading R12):
+ * 1 same type and index, 2 j bounds i's feature, 0 no interaction. */
+static int relation(const sphref_job *J, int64_t i, int64_t j) {
+  if (J->f[i] == J->f[j]) return 1;
+  return bounds(&J->G, J->f[i], J->f[j]) ? 2 : 0;
+}
+
+/* the pair predicate (reading R11): |x_i - x_j|^2 < 4 max(h_i,h_j)^2, the
+ * squared distance summed over axes in order, no fused operations */
+static int within(const sphref_job *J, int64_t i, int64_t j) {
+  int D = J->G.dim;
+  double s = 0.0;
+  for (int a = 0; a < D; ++a) {
+    double d = J->x[3 * i + a] - J->x[3 * j + a];
+    s = s + d * d;
+  }
+  double m = J->h[i] > J->h[j] ? J->h[i] : J->h[j];
+  return s < 4.0 * (m * m);
+}
+
+static int cmp_i32(const void *a, const void *b) {
+  int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+  return (x > y) - (x < y);
+}
+static int cmp_i32_desc(const void *a, const void *b) { return cmp_i32(b, a); }
+
+/* Lists for every non-singular particle.  A uniform bucket grid of side
+ * 2 max(h) only limits which pairs are tested; the set is exactly the pairs
+ * that pass the predicate and have a relation.  Ids are sorted ascending. */
+static int build_lists(sphref_job *J) {
+  int D = J->G.dim;
+  int64_t n = J->n;
+  double hmax = 0.0, lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+  for (int64_t i = 0; i < n; ++i) if (J->h[i] > hmax) hmax = J->h[i];
+  for (int a = 0; a < D; ++a) { lo[a] = INFINITY; hi[a] = -INFINITY; }
+  for (int64_t i = 0; i < n; ++i)
+    for (int a = 0; a < D; ++a) {
+      double c = J->x[3 * i + a];
+      if (!isfinite(c)) { set_err("non-finite position"); return -1; }
+      if (c < lo[a]) lo[a] = c;
+      if (c > hi[a]) hi[a] = c;
+    }
+  double cs = 2.0 * hmax;
+  if (!(cs > 0)) cs = 1.0;
+  int64_t nc[3] = {1, 1, 1}, ncell = 1;
+  for (int a = 0; a < D; ++a) {
+    nc[a] = (int64_t)floor((hi[a] - lo[a]) / cs) + 1;
+    ncell *= nc[a];
+  }
+  int64_t *cstart = calloc((size_t)ncell + 1, sizeof(int64_t));
+  int64_t *cell = malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+  int64_t *bucket = malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+  int64_t *fill = calloc((size_t)ncell, sizeof(int64_t));
+  if (!cstart || !cell || !bucket || !fill) { set_err("out of memory"); return -1; }
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t c = 0;
+    for (int a = D - 1; a >= 0; --a) {
+      int64_t ci = (int64_t)floor((J->x[3 * i + a] - lo[a]) / cs);
+      if (ci >= nc[a]) ci = nc[a] - 1;
+      c = c * nc[a] + ci;
+    }
+    cell[i] = c;
+    cstart[c + 1]++;
+  }
+  for (int64_t c = 0; c < ncell; ++c) cstart[c + 1] += cstart[c];
+  for (int64_t i = 0; i < n; ++i) bucket[cstart[cell[i]] + fill[cell[i]]++] = i;
+
+  /* count first, then fill */
+  int64_t total = 0;
+  for (int pass = 0; pass < 2; ++pass) {
+    total = 0;
+    for (int64_t i = 0; i < n; ++i) {
+      J->off[i] = total;
+      if (ftype(J, i) == T_SI) continue;
+      int64_t ci[3] = {0, 0, 0};
+      int64_t c = cell[i];
+      for (int a = 0; a < D; ++a) { ci[a] = c % nc[a]; c /= nc[a]; }
+      int64_t begin = total;
+      for (int64_t dz = (D == 3 ? -1 : 0); dz <= (D == 3 ? 1 : 0); ++dz)
+        for (int64_t dy = -1; dy <= 1; ++dy)
+          for (int64_t dx = -1; dx <= 1; ++dx) {
+            int64_t q[3] = {ci[0] + dx, ci[1] + dy, ci[2] + dz};
+            int ok = 1;
+            for (int a = 0; a < D; ++a) if (q[a] < 0 || q[a] >= nc[a]) ok = 0;
+            if (!ok) continue;
+            int64_t cc = 0;
+            for (int a = D - 1; a >= 0; --a) cc = cc * nc[a] + q[a];
+            for (int64_t t = cstart[cc]; t < cstart[cc + 1]; ++t) {
+              int64_t j = bucket[t];
+              if (j == i || !within(J, i, j)) continue;
+              int r = relation(J, i, j);
+              if (!r) continue;
+              if (pass == 1) J->nb[total] = (int32_t)j;
+              total++;
+            }
+          }
+      if (pass == 1)
+        qsort(J->nb + begin, (size_t)(total - begin), sizeof(int32_t),
+              J->P.sum_order ? cmp_i32_desc : cmp_i32);
+    }
+    J->off[n] = total;
+    if (pass == 0 && total > J->cap) {
+      free(J->nb); free(J->rel);
+      J->cap = total + total / 4 + 16;
+      J->nb = malloc(sizeof(int32_t) * (size_t)J->cap);
+      J->rel = malloc(sizeof(int8_t) * (size_t)J->cap);
+      if (!J->nb || !J->rel) { set_err("out of memory"); return -1; }
+    }
+  }
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t t = J->off[i]; t < J->off[i + 1]; ++t) J->rel[t] = (int8_t)relation(J, i, J->nb[t]);
+  free(cstart); free(cell); free(bucket); free(fill);
+  return 0;
+}
+
+static void compute_h(sphref_job *J) {
+  for (int64_t i = 0; i < J->n; ++i) J->h[i] = h_at(&J->G, &J->S, J->x + 3 * i);
+}
+
+int32_t sphref_neighbors(sphref_job *J, int64_t *offsets, int32_t *ids,
+                         int8_t *rel_out, int64_t cap, int64_t *n_pairs) {
+  compute_h(J);
+  if (build_lists(J)) return -1;
+  int64_t total = J->off[J->n];
+  if (n_pairs) *n_pairs = total;
+  if (J->P.sum_order)                       /* report ids ascending regardless */
+    for (int64_t i = 0; i < J->n; ++i) {
+      int64_t b = J->off[i], e = J->off[i + 1];
+      for (int64_t t = 0; t < (e - b) / 2; ++t) {
+        int32_t tmp = J->nb[b + t]; J->nb[b + t] = J->nb[e - 1 - t]; J->nb[e - 1 - t] = tmp;
+        int8_t tr = J->rel[b + t]; J->rel[b + t] = J->rel[e - 1 - t]; J->rel[e - 1 - t] = tr;
+      }
+    }
+  if (offsets) memcpy(offsets, J->off, sizeof(int64_t) * (size_t)(J->n + 1));
+  if (ids || rel_out) {
+    if (cap < total) { set_err("capacity too small"); return -1; }
+    if (ids) memcpy(ids, J->nb, sizeof(int32_t) * (size_t)total);
+    if (rel_out) memcpy(rel_out, J->rel, (size_t)total);
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* control: convergence error, phases, velocity resets (sec. 3.4)        */
+/* ------------------------------------------------------------------ */
+static int is_moving(const grp_t *g) { return g->phase != PH_FROZEN; }
+
+/* damping factor of the current step (Eq. (momentum_equation_new); reading
+ * R20/R21: eps in Phase One, ramped linearly to zero, zero in Phase Two) */
+static double damping(const sphref_params *P, const grp_t *g) {
+  if (g->phase == PH_ONE) return P->eps_damp;
+  if (g->phase == PH_RAMP) return P->eps_damp * (1.0 - (double)g->n_ph / (double)P->ramp_steps);
+  return 0.0;
+}
+
+/* end-of-step control of one group given this step's V-bar (sum of V~ over the
+ * group) and final time step dt.  Sampling and windows follow sec. 3.4.2
+ * (reading R22); the phase logic follows sec. 3.4.3-3.4.4 (readings R19, R21). */
+static void control_end_of_step(const sphref_params *P, grp_t *g, double vbar, double dt) {
+  g->n_ph += 1;
+  if (g->n_ph % P->sample_every == 0) {
+    g->vbar = vbar;
+    g->ring[g->nring++] = vbar;
+    if (g->nring == P->window_samples) {
+      double s = 0.0;
+      for (int q = 0; q < g->nring; ++q) s = s + g->ring[q];
+      g->a_prev = g->a_last;
+      g->a_last = s / (double)g->nring;
+      g->nwin += 1;
+      g->nring = 0;
+    }
+    double et = g->nwin >= 1 ? fabs(vbar - g->a_last) / g->a_last : INFINITY;
+    double ea = g->nwin >= 2 ? fabs(g->a_last - g->a_prev) / g->a_prev : INFINITY;
+    g->esys = et > ea ? et : ea;
+  }
+  if (g->phase == PH_ONE) {
+    if (g->esys < P->tol || g->n_ph >= P->max_phase1_steps) { g->phase = PH_RAMP; g->n_ph = 0; }
+  } else if (g->phase == PH_RAMP) {
+    if (g->n_ph >= P->ramp_steps) { g->phase = PH_TWO; g->n_ph = 0; }
+  } else if (g->phase == PH_TWO) {
+    if (g->n_ph >= P->phase2_steps) g->phase = PH_FROZEN;
+  }
+  if (g->phase == PH_ONE) {
+    g->reset_next = (g->n_ph % P->reset_period == 0) ||
+                    (g->dt_prev > 0.0 && dt < 0.1 * g->dt_prev);
+  } else if (g->phase == PH_RAMP) {
+    int shift = g->n_ph / P->ramp_halving;
+    int period = shift >= 30 ? 1 : P->reset_period >> shift;
+    if (period < 1) period = 1;
+    g->reset_next = g->n_ph % period == 0;
+  } else {
+    g->reset_next = 1;
+  }
+  g->dt_prev = dt;
+}
+
+int32_t sphref_control_replay(const sphref_params *p, int32_t n_steps,
+                              const double *vbar, const double *dt,
+                              int32_t *phase_out, int32_t *reset_out,
+                              double *esys_out) {
+  grp_t g;
+  grp_init(&g);
+  for (int32_t k = 0; k < n_steps; ++k) {
+    if (g.phase != PH_FROZEN) control_end_of_step(p, &g, vbar[k], dt[k]);
+    if (phase_out) phase_out[k] = g.phase;
+    if (reset_out) reset_out[k] = g.reset_next;
+    if (esys_out) esys_out[k] = g.esys;
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* one relaxation step (Algorithm 1; readings R17, R23)                 */
+/* ------------------------------------------------------------------ */
+static double norm3(const double *u) { return sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]); }
+
+/* Eq. (fa_time_step_size) terms of one particle folded into a running min;
+ * r_c = 2h, nu = 0.1 r_c |v|.  Infinite terms (a or v zero) drop out. */
+static double dt_terms(double dt, double h, double amag, double vmag) {
+  double rc = 2.0 * h;
+  if (amag > 0.0) { double t = 0.25 * sqrt(rc / amag); if (t < dt) dt = t; }
+  if (vmag > 0.0) {
+    double t = rc / (40.0 * vmag);
+    if (t < dt) dt = t;
+    double nu = 0.1 * rc * vmag;
+    t = 0.125 * rc * rc / nu;
+    if (t < dt) dt = t;
+  }
+  return dt;
+}
+
+static int one_step(sphref_job *J) {
+  const geo_t *G = &J->G;
+  const sphref_params *P = &J->P;
+  int D = G->dim;
+  int64_t n = J->n;
+
+  /* targets h_i = h_t(x_i^n); lists over x^n */
+  compute_h(J);
+  if (build_lists(J)) return -1;
+
+  /* which particles evolve this step: not singular, group not converged
+   * (Algorithm 1: "if V-bar_{*,k} is not converged") */
+  char *act = malloc((size_t)(n > 0 ? n : 1));
+  if (!act) { set_err("out of memory"); return -1; }
+  for (int64_t i = 0; i < n; ++i) act[i] = ftype(J, i) != T_SI && is_moving(&J->g[J->f[i]]);
+
+  /* reset forces; reset velocities of groups flagged at the previous step */
+  for (int64_t i = 0; i < 3 * n; ++i) { J->ap[i] = 0.0; J->a[i] = 0.0; J->vt[i] = 0.0; }
+  for (int64_t i = 0; i < n; ++i) { J->Vt[i] = 0.0; J->gam[i] = 0.0; J->eta[i] = 0.0; }
+  for (int64_t i = 0; i < n; ++i)
+    if (act[i] && J->g[J->f[i]].reset_next)
+      for (int a = 0; a < 3; ++a) J->v[3 * i + a] = 0.0;
+
+  int64_t inter = 0;
+  /* Shepard term, particle volume, pressure force with the boundary term,
+   * mapped onto the feature (Eqs. (gamma_disc_renormSPH), (particle_volume),
+   * (sph_pressure_force_disc_weighted)) */
+  for (int64_t i = 0; i < n; ++i) {
+    if (!act[i]) continue;
+    int k = G->f[J->f[i]].k;
+    double hi = J->h[i];
+    double hik = hpow(hi, k), hi2k = hik * hik;
+    double S = sphref_W(k, 0.0, hi);          /* self term */
+    double gam = sphref_W(k, 0.0, hi) * hik;
+    double Pi[3] = {0, 0, 0}, B[3] = {0, 0, 0};
+    for (int64_t t = J->off[i]; t < J->off[i + 1]; ++t) {
+      int64_t j = J->nb[t];
+      double dx[3] = {0, 0, 0};
+      for (int a = 0; a < D; ++a) dx[a] = J->x[3 * i + a] - J->x[3 * j + a];
+      double r = norm3(dx);
+      double hj = J->h[j];
+      double hjk = hpow(hj, k), hj2k = hjk * hjk;
+      double hij = 0.5 * (hi + hj);
+      inter++;
+      if (J->rel[t] == 1) {
+        double w = sphref_W(k, r, hi);
+        S = S + w;
+        gam = gam + w * hjk;
+        double c = P->p0 * (hi2k + hj2k) * dWdr_over_r(k, r, hij);
+        for (int a = 0; a < D; ++a) Pi[a] = Pi[a] + c * dx[a];
+      } else {
+        double omega = P->boundary_weighting == 0 ? 1.0 / hj
+                     : P->boundary_weighting == 1 ? hpow(hj, k - 1) : 0.0;
+        double nb[3];
+        bnormal(G, J->f[i], J->f[j], J->x + 3 * j, nb);
+        double c = P->p0 * (hi2k + hj2k) * sphref_W(k, r, hij) * omega;
+        for (int a = 0; a < D; ++a) B[a] = B[a] + c * nb[a];
+      }
+    }
+    double ap[3] = {0, 0, 0};
+    for (int a = 0; a < D; ++a) ap[a] = -((Pi[a] + B[a]) / gam);
+    tproject(G, J->f[i], J->x + 3 * i, ap);
+    for (int a = 0; a < 3; ++a) J->ap[3 * i + a] = ap[a];
+    J->Vt[i] = 1.0 / S;
+    J->gam[i] = gam;
+  }
+
+  /* first time step per group from a^p and v^n */
+  for (int q = 0; q < G->nf; ++q) J->g[q].dt1 = P->dt_max;
+  for (int64_t i = 0; i < n; ++i) {
+    if (!act[i]) continue;
+    grp_t *g = &J->g[J->f[i]];
+    g->dt1 = dt_terms(g->dt1, J->h[i], norm3(J->ap + 3 * i), norm3(J->v + 3 * i));
+  }
+
+  /* mid-point velocity */
+  for (int64_t i = 0; i < n; ++i) {
+    if (!act[i]) continue;
+    double dt1 = J->g[J->f[i]].dt1;
+    for (int a = 0; a < D; ++a) J->vt[3 * i + a] = J->v[3 * i + a] + 0.5 * dt1 * J->ap[3 * i + a];
+  }
+
+  /* viscous force with the mid-point velocity (reading R15: nu_i local) */
+  for (int64_t i = 0; i < n; ++i) {
+    if (!act[i]) continue;
+    int k = G->f[J->f[i]].k;
+    double nu = 0.1 * (2.0 * J->h[i]) * norm3(J->vt + 3 * i);
+    J->eta[i] = nu / hpow(J->h[i], k);         /* eta = rho_t nu, rho_t = h^-k */
+  }
+  for (int64_t i = 0; i < n; ++i) {
+    if (!act[i]) continue;
+    int k = G->f[J->f[i]].k;
+    double hi = J->h[i];
+    double hik = hpow(hi, k), hi2k = hik * hik;
+    double Fv[3] = {0, 0, 0};
+    for (int64_t t = J->off[i]; t < J->off[i + 1]; ++t) {
+      if (J->rel[t] != 1) continue;
+      int64_t j = J->nb[t];
+      double dx[3] = {0, 0, 0};
+      for (int a = 0; a < D; ++a) dx[a] = J->x[3 * i + a] - J->x[3 * j + a];
+      double r = norm3(dx);
+      double hj = J->h[j];
+      double hjk = hpow(hj, k), hj2k = hjk * hjk;
+      double es = J->eta[i] + J->eta[j];
+      double H = es > 0.0 ? 2.0 * J->eta[i] * J->eta[j] / es : 0.0;
+      double c = H * (hi2k + hj2k) * dWdr_over_r(k, r, 0.5 * (hi + hj));
+      for (int a = 0; a < D; ++a) Fv[a] = Fv[a] + c * (J->vt[3 * i + a] - J->vt[3 * j + a]);
+    }
+    tproject(G, J->f[i], J->x + 3 * i, Fv);
+    double eps = damping(P, &J->g[J->f[i]]);
+    for (int a = 0; a < D; ++a)
+      J->a[3 * i + a] = J->ap[3 * i + a] + Fv[a] - eps * J->v[3 * i + a];
+  }
+
+  /* final time step per group from a and v~ */
+  for (int q = 0; q < G->nf; ++q) J->g[q].dt = P->dt_max;
+  for (int64_t i = 0; i < n; ++i) {
+    if (!act[i]) continue;
+    grp_t *g = &J->g[J->f[i]];
+    g->dt = dt_terms(g->dt, J->h[i], norm3(J->a + 3 * i), norm3(J->vt + 3 * i));
+  }
+
+  /* integrate and map onto the feature (reading R17, R18) */
+  for (int64_t i = 0; i < n; ++i) {
+    if (!act[i]) continue;
+    double dt = J->g[J->f[i]].dt;
+    double vh[3] = {0, 0, 0}, xs[3] = {0, 0, 0};
+    for (int a = 0; a < D; ++a) {
+      vh[a] = J->v[3 * i + a] + 0.5 * dt * J->a[3 * i + a];
+      xs[a] = J->x[3 * i + a] + dt * vh[a];
+    }
+    for (int a = 0; a < D; ++a)
+      if (!isfinite(xs[a])) { J->state_error = 1; set_err("non-finite position"); free(act); return -2; }
+    int type = ftype(J, i);
+    if (type == T_V) {
+      if (!inside(G, xs)) {                  /* rejected move: stays, velocity zeroed */
+        for (int a = 0; a < 3; ++a) J->v[3 * i + a] = 0.0;
+        J->escaped++;
+        continue;
+      }
+    } else {
+      pproject(G, J->f[i], xs);
+    }
+    double vn[3] = {0, 0, 0};
+    for (int a = 0; a < D; ++a) vn[a] = vh[a] + 0.5 * dt * J->a[3 * i + a];
+    tproject(G, J->f[i], xs, vn);
+    for (int a = 0; a < D; ++a) { J->x[3 * i + a] = xs[a]; J->v[3 * i + a] = vn[a]; }
+  }
+
+  /* V-bar per group and the control law */
+  double vbar[MAXF];
+  for (int q = 0; q < G->nf; ++q) vbar[q] = 0.0;
+  for (int64_t i = 0; i < n; ++i) if (act[i]) vbar[J->f[i]] = vbar[J->f[i]] + J->Vt[i];
+  for (int q = 0; q < G->nf; ++q) {
+    grp_t *g = &J->g[q];
+    if (G->f[q].type == T_SI || g->count == 0 || !is_moving(g)) continue;
+    control_end_of_step(P, g, vbar[q], g->dt);
+  }
+  J->steps++;
+  J->inter_last = inter;
+  J->inter_total += inter;
+  free(act);
+  return 0;
+}
+
+static int all_frozen(const sphref_job *J) {
+  for (int q = 0; q < J->G.nf; ++q)
+    if (J->G.f[q].type != T_SI && J->g[q].count > 0 && J->g[q].phase != PH_FROZEN) return 0;
+  return 1;
+}
+
+int32_t sphref_step(sphref_job *J, int32_t n_steps) {
+  if (J->state_error) { set_err("job is in an error state"); return -2; }
+  for (int32_t s = 0; s < n_steps; ++s) {
+    if (all_frozen(J)) break;
+    int rc = one_step(J);
+    if (rc) return rc;
+  }
+  return 0;
+}
+
+int32_t sphref_error(sphref_job *J, double *e_sys, int32_t *phase,
+                     int32_t *converged, int64_t *step) {
+  double e = 0.0;
+  int ph = PH_FROZEN, any = 0;
+  for (int q = 0; q < J->G.nf; ++q) {
+    const grp_t *g = &J->g[q];
+    if (J->G.f[q].type == T_SI || g->count == 0) continue;
+    any = 1;
+    if (g->esys > e || isnan(g->esys)) e = g->esys;
+    if (g->phase < ph) ph = g->phase;
+  }
+  if (!any) { e = 0.0; ph = PH_FROZEN; }
+  if (e_sys) *e_sys = e;
+  if (phase) *phase = ph;
+  if (converged) *converged = all_frozen(J);
+  if (step) *step = J->steps;
+  return 0;
+}
+
+int32_t sphref_group_state(sphref_job *J, int32_t f, double *out) {
+  if (f < 0 || f >= J->G.nf) { set_err("bad feature"); return -1; }
+  const grp_t *g = &J->g[f];
+  out[0] = g->phase; out[1] = g->n_ph; out[2] = g->esys; out[3] = g->dt1; out[4] = g->dt;
+  out[5] = g->vbar; out[6] = g->reset_next; out[7] = g->a_last; out[8] = g->a_prev; out[9] = g->nwin;
+  return 0;
+}
+
+int32_t sphref_counters(sphref_job *J, double *out) {
+  out[0] = (double)J->steps;
+  out[1] = (double)J->escaped;
+  out[2] = (double)J->inter_total;
+  out[3] = (double)J->inter_last;
+  return 0;
+}

@@ -1,0 +1,416 @@
+"""Seeded synthetic workloads: geometry, feature-size function, parameters and
+initial particles.
+
+This module is the input generator that both the GPU library and the CPU
+oracle are fed from.  It holds none of the relaxation step's arithmetic: it
+only draws particles.  Following the paper's sec. 3.2 (feature masses
+M_{v,k}, M_{s,k}, M_{c,k} give the particle counts at unit mass) and sec. 3.6
+(initial positions drawn with probability proportional to the target density,
+Mersenne Twister), it
+
+* integrates rho_t = h^-k over every feature of intrinsic dimension k to split
+  the particle budget,
+* scales h by the factor s that makes the integrals add up to the requested
+  count (sum_k M_k / s^k = N), and
+* samples each feature by rejection against rho_t with numpy's MT19937.
+
+The density used for sampling is this module's own copy of the sizing
+formula; it only shapes the input.  Both implementations of the step evaluate
+h_t themselves from the sizing record returned here.
+
+Feature numbering is the convention documented in ``include/sph_mesh.h``.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+# particle / feature types
+SI, CURVE, SURF, VOL = 0, 1, 2, 3
+
+# sizing kinds
+H_CONST, H_LINEAR_FROM_POINT, H_GRADED_TO_HOLES = 0, 1, 2
+
+
+def default_params(**over):
+    """Simulation parameters of the paper (sec. 2.3, 3.4) plus the readings
+    for what it leaves open (ramp, Phase Two length)."""
+    p = dict(
+        p0=1.0,               # EOS constant pressure
+        eps_damp=0.0,         # Phase One damping, suggested range [0, 0.2]
+        tol=5e-6,             # E_sys threshold
+        dt_max=1.0,           # cap when every time-step term is infinite
+        boundary_weighting=0, # 0 rho_t,b A_t,b ; 1 literal A_t,b ; 2 off
+        reset_period=100,     # velocity reset period in Phase One
+        sample_every=20,      # V-bar sampling interval
+        window_samples=10,    # samples per averaging window (200 steps)
+        ramp_steps=140,       # transition: the reset period halves every 20 steps
+        ramp_halving=20,
+        phase2_steps=400,     # Phase Two length, then the group freezes
+        max_phase1_steps=1 << 30,
+        precision=0,          # 0 FP64, 1 FP32 kernel sums / FP64 integration
+    )
+    p.update(over)
+    return p
+
+
+@dataclass
+class Workload:
+    name: str
+    dim: int
+    lo: np.ndarray
+    hi: np.ndarray
+    holes: np.ndarray               # (n_holes, 15)
+    sizing: dict
+    params: dict
+    xyz: np.ndarray                 # (n, 3) float64
+    feature: np.ndarray             # (n,) int32
+    ftype: np.ndarray               # (n_features,) int32 type per feature
+    counts: dict = field(default_factory=dict)
+    scale: float = 1.0
+    steps: int = 0
+
+    @property
+    def n(self):
+        return int(self.xyz.shape[0])
+
+
+# ---------------------------------------------------------------------------
+# feature tables (numbering convention of include/sph_mesh.h)
+# ---------------------------------------------------------------------------
+def feature_types(dim, n_holes):
+    t = [VOL]
+    if dim == 2:
+        t += [CURVE] * 4 + [CURVE] * n_holes + [SI] * 4
+    else:
+        t += [SURF] * 6 + [SURF] * n_holes + [CURVE] * 12 + [SI] * 8
+    return np.asarray(t, np.int32)
+
+
+def _edge3(idx):
+    """3D box edge idx -> (direction axis, (b, sb), (c, sc))"""
+    a, q = divmod(idx, 4)
+    b = 1 if a == 0 else 0
+    c = 1 if a == 2 else 2
+    return a, (b, q & 1), (c, (q >> 1) & 1)
+
+
+def _hole_rec(c, r):
+    rec = np.zeros(15)
+    rec[0:len(c)] = c
+    rec[3:6] = r
+    rec[6:15] = np.eye(3).ravel()
+    return rec
+
+
+# ---------------------------------------------------------------------------
+# the sampling density's own copy of the sizing formula
+# ---------------------------------------------------------------------------
+def _h_field(pts, dim, sizing, holes):
+    kind = sizing["kind"]
+    if kind == H_CONST:
+        return np.full(pts.shape[0], sizing["h0"])
+    if kind == H_LINEAR_FROM_POINT:
+        p = np.asarray(sizing["point"][:dim])
+        return sizing["h0"] + sizing["grad"] * np.linalg.norm(pts[:, :dim] - p, axis=1)
+    d = np.full(pts.shape[0], np.inf)
+    for rec in holes:
+        dd = np.abs(np.linalg.norm(pts[:, :dim] - rec[:dim], axis=1) - rec[3])
+        d = np.minimum(d, dd)
+    d = np.minimum(d, sizing["dcap"])
+    return sizing["h0"] * (1.0 + sizing["grad"] * d)
+
+
+def _inside(pts, dim, lo, hi, holes):
+    ok = np.all((pts[:, :dim] > lo[:dim]) & (pts[:, :dim] < hi[:dim]), axis=1)
+    for rec in holes:
+        ok &= np.sum((pts[:, :dim] - rec[:dim]) ** 2, axis=1) > rec[3] ** 2
+    return ok
+
+
+# ---------------------------------------------------------------------------
+# feature masses (sec. 3.2) by midpoint quadrature at unit scale
+# ---------------------------------------------------------------------------
+def _masses(dim, lo, hi, holes, sizing, res):
+    """Return {feature: integral of h^-k over the feature} for s = 1."""
+    types = feature_types(dim, len(holes))
+    M = {}
+    # volume
+    axes = [lo[a] + (np.arange(res) + 0.5) * (hi[a] - lo[a]) / res for a in range(dim)]
+    cellv = np.prod([(hi[a] - lo[a]) / res for a in range(dim)])
+    if dim == 2:
+        X, Y = np.meshgrid(axes[0], axes[1], indexing="ij")
+        pts = np.stack([X.ravel(), Y.ravel(), np.zeros(X.size)], 1)
+        ins = _inside(pts, dim, lo, hi, holes)
+        M[0] = float(np.sum(_h_field(pts[ins], dim, sizing, holes) ** -2.0) * cellv)
+    else:
+        tot = 0.0
+        for zi in axes[2]:      # slab by slab to bound memory
+            X, Y = np.meshgrid(axes[0], axes[1], indexing="ij")
+            pts = np.stack([X.ravel(), Y.ravel(), np.full(X.size, zi)], 1)
+            ins = _inside(pts, dim, lo, hi, holes)
+            tot += float(np.sum(_h_field(pts[ins], dim, sizing, holes) ** -3.0))
+        M[0] = tot * cellv
+    nseg = res * 4
+    f = 1
+    # box sides: 2D edges (k=1) / 3D faces (k=2)
+    for a in range(dim):
+        for s in range(2):
+            if dim == 2:
+                o = 1 - a
+                t = lo[o] + (np.arange(nseg) + 0.5) * (hi[o] - lo[o]) / nseg
+                pts = np.zeros((nseg, 3))
+                pts[:, a] = hi[a] if s else lo[a]
+                pts[:, o] = t
+                M[f] = float(np.sum(_h_field(pts, dim, sizing, holes) ** -1.0) * (hi[o] - lo[o]) / nseg)
+            else:
+                o1, o2 = [b for b in range(3) if b != a]
+                u = lo[o1] + (np.arange(res) + 0.5) * (hi[o1] - lo[o1]) / res
+                v = lo[o2] + (np.arange(res) + 0.5) * (hi[o2] - lo[o2]) / res
+                U, V = np.meshgrid(u, v, indexing="ij")
+                pts = np.zeros((U.size, 3))
+                pts[:, a] = hi[a] if s else lo[a]
+                pts[:, o1] = U.ravel()
+                pts[:, o2] = V.ravel()
+                da = (hi[o1] - lo[o1]) * (hi[o2] - lo[o2]) / U.size
+                M[f] = float(np.sum(_h_field(pts, dim, sizing, holes) ** -2.0) * da)
+            f += 1
+    # hole boundaries
+    for rec in holes:
+        c, r = rec[:3], rec[3]
+        if dim == 2:
+            th = (np.arange(nseg) + 0.5) * 2 * np.pi / nseg
+            pts = np.stack([c[0] + r * np.cos(th), c[1] + r * np.sin(th), np.zeros(nseg)], 1)
+            M[f] = float(np.sum(_h_field(pts, dim, sizing, holes) ** -1.0) * 2 * np.pi * r / nseg)
+        else:
+            nt = res
+            ct = -1 + (np.arange(nt) + 0.5) * 2.0 / nt          # cos(theta), equal-area bands
+            ph = (np.arange(2 * nt) + 0.5) * np.pi / nt
+            CT, PH = np.meshgrid(ct, ph, indexing="ij")
+            st = np.sqrt(1 - CT ** 2)
+            pts = np.stack([c[0] + r * st * np.cos(PH), c[1] + r * st * np.sin(PH), c[2] + r * CT], -1).reshape(-1, 3)
+            M[f] = float(np.sum(_h_field(pts, dim, sizing, holes) ** -2.0) * 4 * np.pi * r * r / pts.shape[0])
+        f += 1
+    if dim == 3:
+        for e in range(12):
+            a, (b, sb), (c2, sc) = _edge3(e)
+            t = lo[a] + (np.arange(nseg) + 0.5) * (hi[a] - lo[a]) / nseg
+            pts = np.zeros((nseg, 3))
+            pts[:, a] = t
+            pts[:, b] = hi[b] if sb else lo[b]
+            pts[:, c2] = hi[c2] if sc else lo[c2]
+            M[f] = float(np.sum(_h_field(pts, dim, sizing, holes) ** -1.0) * (hi[a] - lo[a]) / nseg)
+            f += 1
+    assert f == len(types) - (1 << dim)
+    return M
+
+
+def _solve_scale(M, types, n_total, dim):
+    """s with sum_f M_f / s^k_f + n_corners = n_total (bisection in log s)."""
+    ncorner = int(np.sum(types == SI))
+    kof = {VOL: dim, SURF: 2, CURVE: 1}
+
+    def total(s):
+        return ncorner + sum(m / s ** kof[int(types[f])] for f, m in M.items())
+
+    lo_s, hi_s = 1e-3, 1e3
+    for _ in range(200):
+        mid = math.sqrt(lo_s * hi_s)
+        if total(mid) > n_total:
+            lo_s = mid
+        else:
+            hi_s = mid
+    return math.sqrt(lo_s * hi_s)
+
+
+def _split_counts(M, types, s, n_total, dim):
+    counts = {}
+    for f, m in M.items():
+        k = dim if types[f] == VOL else (2 if types[f] == SURF else 1)
+        counts[f] = int(round(m / s ** k))
+    ncorner = int(np.sum(types == SI))
+    counts[0] += n_total - ncorner - sum(counts.values())
+    return counts
+
+
+# ---------------------------------------------------------------------------
+# rejection samplers (sec. 3.6: probability proportional to rho_t)
+# ---------------------------------------------------------------------------
+def _sample_rejection(rng, n, propose, dim, sizing, holes, k, hmin, accept_mask=None):
+    out = np.zeros((0, 3))
+    while out.shape[0] < n:
+        m = max(1024, 2 * (n - out.shape[0]))
+        pts = propose(m)
+        if accept_mask is not None:
+            pts = pts[accept_mask(pts)]
+        h = _h_field(pts, dim, sizing, holes)
+        u = rng.random(pts.shape[0])
+        pts = pts[u < (hmin / h) ** k]
+        out = np.concatenate([out, pts], 0)
+    return out[:n]
+
+
+def _build(name, dim, lo, hi, holes, sizing, params, n_total, seed, steps, res):
+    lo = np.asarray(lo, float)
+    hi = np.asarray(hi, float)
+    holes = np.asarray(holes, float).reshape(-1, 15)
+    types = feature_types(dim, len(holes))
+    base = dict(sizing)
+    M = _masses(dim, lo, hi, holes, base, res)
+    s = _solve_scale(M, types, n_total, dim)
+    sizing = dict(base)
+    if sizing["kind"] == H_LINEAR_FROM_POINT:
+        sizing["grad"] = base["grad"] * s
+    sizing["h0"] = base["h0"] * s
+    counts = _split_counts(M, types, s, n_total, dim)
+    rng = np.random.Generator(np.random.MT19937(seed))
+    hmin = _hmin(sizing, dim, lo, hi, holes)
+    xyz, feat = [], []
+
+    def box_prop(m):
+        p = np.zeros((m, 3))
+        p[:, :dim] = lo[:dim] + rng.random((m, dim)) * (hi[:dim] - lo[:dim])
+        return p
+
+    pv = _sample_rejection(rng, counts[0], box_prop, dim, sizing, holes, dim, hmin,
+                           accept_mask=lambda p: _inside(p, dim, lo, hi, holes))
+    xyz.append(pv); feat.append(np.zeros(len(pv), np.int32))
+    f = 1
+    for a in range(dim):
+        for sd in range(2):
+            k = dim - 1
+
+            def side_prop(m, a=a, sd=sd):
+                p = box_prop(m)
+                p[:, a] = hi[a] if sd else lo[a]
+                return p
+
+            p = _sample_rejection(rng, counts[f], side_prop, dim, sizing, holes, k, hmin)
+            xyz.append(p); feat.append(np.full(len(p), f, np.int32))
+            f += 1
+    for rec in holes:
+        c, r = rec[:3], rec[3]
+        k = dim - 1
+
+        def hole_prop(m, c=c, r=r):
+            g = rng.standard_normal((m, dim))
+            g /= np.linalg.norm(g, axis=1, keepdims=True)
+            p = np.zeros((m, 3))
+            p[:, :dim] = c[:dim] + r * g
+            return p
+
+        p = _sample_rejection(rng, counts[f], hole_prop, dim, sizing, holes, k, hmin)
+        xyz.append(p); feat.append(np.full(len(p), f, np.int32))
+        f += 1
+    if dim == 3:
+        for e in range(12):
+            a, (b, sb), (c2, sc) = _edge3(e)
+
+            def edge_prop(m, a=a, b=b, sb=sb, c2=c2, sc=sc):
+                p = np.zeros((m, 3))
+                p[:, a] = lo[a] + rng.random(m) * (hi[a] - lo[a])
+                p[:, b] = hi[b] if sb else lo[b]
+                p[:, c2] = hi[c2] if sc else lo[c2]
+                return p
+
+            p = _sample_rejection(rng, counts[f], edge_prop, dim, sizing, holes, 1, hmin)
+            xyz.append(p); feat.append(np.full(len(p), f, np.int32))
+            f += 1
+    for cbits in range(1 << dim):
+        p = np.zeros((1, 3))
+        for a in range(dim):
+            p[0, a] = hi[a] if (cbits >> a) & 1 else lo[a]
+        xyz.append(p); feat.append(np.full(1, f, np.int32))
+        f += 1
+    xyz = np.ascontiguousarray(np.concatenate(xyz, 0))
+    feat = np.ascontiguousarray(np.concatenate(feat, 0))
+    assert xyz.shape[0] == n_total, (xyz.shape, n_total)
+    return Workload(name=name, dim=dim, lo=lo, hi=hi, holes=holes, sizing=sizing,
+                    params=params, xyz=xyz, feature=feat, ftype=types, counts=counts,
+                    scale=s, steps=steps)
+
+
+def _hmin(sizing, dim, lo, hi, holes):
+    """a lower bound of h over the domain (rejection sampling's envelope):
+    every sizing kind here is h0 plus a non-negative term"""
+    return sizing["h0"]
+
+
+# ---------------------------------------------------------------------------
+# the workloads
+# ---------------------------------------------------------------------------
+def square_lattice(n_side=64, seed=1, jitter=0.25, steps=200, **pover):
+    """2D unit square, constant h = 1/n_side: n_side^2 volume particles on the
+    cell-centred lattice plus U(+-jitter h) per coordinate, 4 edges of
+    n_side-1 curve particles at m/n_side +- U(jitter h) along the edge, and the
+    4 fixed corners (4,352 particles for n_side = 64)."""
+    h = 1.0 / n_side
+    rng = np.random.Generator(np.random.MT19937(seed))
+    ii, jj = np.meshgrid(np.arange(n_side), np.arange(n_side), indexing="ij")
+    pv = np.zeros((n_side * n_side, 3))
+    pv[:, 0] = (ii.ravel() + 0.5) * h
+    pv[:, 1] = (jj.ravel() + 0.5) * h
+    pv[:, :2] += rng.uniform(-jitter * h, jitter * h, size=(n_side * n_side, 2))
+    xyz = [pv]
+    feat = [np.zeros(n_side * n_side, np.int32)]
+    m = np.arange(1, n_side) * h
+    f = 1
+    for a in range(2):
+        for s in range(2):
+            p = np.zeros((n_side - 1, 3))
+            o = 1 - a
+            p[:, a] = 1.0 if s else 0.0
+            p[:, o] = m + rng.uniform(-jitter * h, jitter * h, size=n_side - 1)
+            xyz.append(p); feat.append(np.full(n_side - 1, f, np.int32))
+            f += 1
+    for cbits in range(4):
+        p = np.zeros((1, 3))
+        p[0, 0] = 1.0 if cbits & 1 else 0.0
+        p[0, 1] = 1.0 if cbits & 2 else 0.0
+        xyz.append(p); feat.append(np.full(1, f, np.int32))
+        f += 1
+    xyz = np.ascontiguousarray(np.concatenate(xyz, 0))
+    feat = np.ascontiguousarray(np.concatenate(feat, 0))
+    return Workload(name=f"square{n_side}", dim=2, lo=np.zeros(3), hi=np.array([1.0, 1.0, 0.0]),
+                    holes=np.zeros((0, 15)), sizing=dict(kind=H_CONST, h0=h, grad=0.0, dcap=0.0,
+                                                          point=[0.0, 0.0, 0.0]),
+                    params=default_params(**pover), xyz=xyz, feature=feat,
+                    ftype=feature_types(2, 0), counts={}, scale=1.0, steps=steps)
+
+
+def square_hole(n_total=250_000, seed=2, steps=2000, res=2048, **pover):
+    """2D unit square minus the disc c = (1/2, 1/2), r = 1/4, graded
+    h = s h0 (1 + 4 d), d the distance to the circle, h0 = 1/1024, s solving
+    the mass split for n_total; curve particles on the circle and the edges."""
+    pover.setdefault("max_phase1_steps", 1200)
+    return _build("square_hole", 2, [0, 0, 0], [1, 1, 0], [_hole_rec([0.5, 0.5, 0.0], 0.25)],
+                  dict(kind=H_GRADED_TO_HOLES, h0=1.0 / 1024, grad=4.0, dcap=np.inf,
+                       point=[0.0, 0.0, 0.0]),
+                  default_params(**pover), n_total, seed, steps, res)
+
+
+def cube_ball(n_total=2_000_000, seed=3, steps=1000, res=256, **pover):
+    """3D unit cube minus the ball c = (1/2,1/2,1/2), r = 0.3, graded
+    h = s h0 (1 + 4 d), d the distance to the sphere, h0 = 4.745e-3."""
+    return _build("cube_ball", 3, [0, 0, 0], [1, 1, 1], [_hole_rec([0.5, 0.5, 0.5], 0.3)],
+                  dict(kind=H_GRADED_TO_HOLES, h0=4.745e-3, grad=4.0, dcap=np.inf,
+                       point=[0.0, 0.0, 0.0]),
+                  default_params(**pover), n_total, seed, steps, res)
+
+
+def scaled_hole_2d(n_total, seed, centre=(0.5, 0.5), radius=0.25, grad=4.0, res=512, **pover):
+    """A square-with-hole job of any size (serving stream and small tests)."""
+    return _build("hole2d", 2, [0, 0, 0], [1, 1, 0], [_hole_rec([centre[0], centre[1], 0.0], radius)],
+                  dict(kind=H_GRADED_TO_HOLES, h0=1.0 / 1024, grad=grad, dcap=np.inf,
+                       point=[0.0, 0.0, 0.0]),
+                  default_params(**pover), n_total, seed, 0, res)
+
+
+def scaled_ball_3d(n_total, seed, centre=(0.5, 0.5, 0.5), radius=0.3, grad=4.0, res=96, **pover):
+    """A cube-with-ball job of any size (serving stream and small tests)."""
+    return _build("ball3d", 3, [0, 0, 0], [1, 1, 1], [_hole_rec(list(centre), radius)],
+                  dict(kind=H_GRADED_TO_HOLES, h0=4.745e-3, grad=grad, dcap=np.inf,
+                       point=[0.0, 0.0, 0.0]),
+                  default_params(**pover), n_total, seed, 0, res)
