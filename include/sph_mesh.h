@@ -1,0 +1,218 @@
+/*
+ * sph_mesh.h -- C ABI of the MI355X (gfx950) feature-aware SPH relaxation
+ * library libsphmesh.so.
+ *
+ * The library runs the per-step particle relaxation of Ji, Fu, Hu and Adams,
+ * "A Feature-aware SPH for Isotropic Unstructured Mesh Generation" (arXiv
+ * 2003.01061), Algorithm 1's time loop, entirely in hand-written HIP kernels:
+ * cell hashing and counting sort, cell start tables, the neighbour-list sweep,
+ * the Shepard / pressure / boundary-correction force sweep, the viscous sweep,
+ * integration with feature projection, and the per-feature time step, error
+ * measure and two-phase control.  The host only enqueues work.
+ *
+ * Conventions for every call:
+ *  - Every pointer argument is a HOST pointer unless stated otherwise.
+ *    Inputs are copied during the call; the caller keeps ownership.
+ *  - Outputs go to caller-owned host buffers.
+ *  - Calls return an sph_status; on failure sph_mesh_last_error() returns a
+ *    message (thread-local, valid until the next call on that thread).
+ *  - One handle must not be used from two threads at once; distinct handles
+ *    are independent (each owns its device memory and stream).
+ *  - Particle arrays are row-major n x 3 doubles (the third coordinate is
+ *    ignored in 2D) indexed by the caller's particle id 0..n-1.  The library
+ *    keeps particles in cell order internally and always reports in the
+ *    caller's order.
+ *
+ * Feature numbering (a feature is the paper's (type, index) pair, sec. 3.2;
+ * each feature evolves as one group with its own time step, sec. 3.5):
+ *   2D box [lo,hi]^2 minus n_holes discs:
+ *     0 volume (P_+) | 1..4 box edges x=lo, x=hi, y=lo, y=hi (P_c) |
+ *     5..4+n_holes hole circles (P_c) | then 4 corners (P_si), corner c at
+ *     (bit0 of c ? hi : lo, bit1 of c ? hi : lo).
+ *   3D box [lo,hi]^3 minus n_holes balls:
+ *     0 volume (P_+) | 1..6 faces x=lo, x=hi, y=lo, y=hi, z=lo, z=hi (P_s) |
+ *     7..6+n_holes hole spheres (P_s) | 12 box edges (P_c) | 8 corners (P_si).
+ *     Edge 4a + sb + 2 sc runs along axis a; its fixed coordinates are the
+ *     two other axes b < c, at lo (0) or hi (1) as given by sb and sc.
+ *     Corner c sits at (bit0, bit1, bit2 of c) ? hi : lo per axis.
+ */
+#ifndef SPH_MESH_H
+#define SPH_MESH_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sph_mesh sph_mesh;
+
+typedef enum {
+  SPH_OK = 0,
+  SPH_ERR_INVALID_ARG = 1,   /* bad geometry, sizing, parameters or buffer */
+  SPH_ERR_OUT_OF_MEMORY = 2, /* device allocation failed */
+  SPH_ERR_DEVICE = 3,        /* a HIP call failed */
+  SPH_ERR_STATE = 4,         /* non-finite state or neighbour-list overflow */
+  SPH_ERR_UNSUPPORTED = 5    /* a configuration this build does not handle */
+} sph_status;
+
+enum { SPH_P_SINGULAR = 0, SPH_P_CURVE = 1, SPH_P_SURFACE = 2, SPH_P_VOLUME = 3 };
+enum { SPH_H_CONST = 0, SPH_H_LINEAR_FROM_POINT = 1, SPH_H_GRADED_TO_HOLES = 2 };
+enum { SPH_FP64 = 0, SPH_FP32_MIXED = 1 };
+
+/* Geometry (paper sec. 2.1 / 3.1): the level set phi > 0 is the box minus
+ * the holes.  holes: n_holes x 15 doubles, centre[3], semi_axes[3], rot[9];
+ * this build handles discs / balls (three equal semi-axes; rot ignored).
+ * At most 16 holes; holes must lie inside the box. */
+typedef struct {
+  int32_t dim;               /* 2 or 3 */
+  double lo[3], hi[3];
+  int32_t n_holes;
+  const double *holes;
+} sph_geometry;
+
+/* Target feature size h_t(x) (paper sec. 2.2):
+ *   SPH_H_CONST:             h = h0
+ *   SPH_H_LINEAR_FROM_POINT: h = h0 + grad |x - point|
+ *   SPH_H_GRADED_TO_HOLES:   h = h0 (1 + grad min(d, dcap)), d = distance to
+ *                            the nearest hole boundary.
+ * Evaluated in FP64 with the operation order: squared distances summed over
+ * axes in order, then sqrt; no fused multiply-add. */
+typedef struct {
+  int32_t kind;
+  double h0, grad, dcap;
+  double point[3];
+} sph_sizing;
+
+/* Simulation parameters (paper sec. 2.3, 3.4, 3.5). */
+typedef struct {
+  double p0;                 /* EOS constant pressure P0 (sec. 2.3) */
+  double eps_damp;           /* Phase One damping factor, [0, 0.2] (sec. 3.4.3) */
+  double tol;                /* E_sys threshold, 5e-6 in the paper (sec. 3.4.2) */
+  double dt_max;             /* time-step cap when every term is infinite */
+  int32_t boundary_weighting;/* boundary term weight: 0 rho_t,b A_t,b = 1/h_b,
+                                1 the literal A_t,b = h_b^(k-1), 2 off */
+  int32_t reset_period;      /* Phase One velocity reset period (100) */
+  int32_t sample_every;      /* V-bar sampling interval (20) */
+  int32_t window_samples;    /* samples per averaging window (10), <= 64 */
+  int32_t ramp_steps;        /* transition length between the phases (140) */
+  int32_t ramp_halving;      /* steps between halvings of the reset period (20) */
+  int32_t phase2_steps;      /* Phase Two length before a feature freezes (400) */
+  int32_t max_phase1_steps;  /* forced end of Phase One */
+  int32_t precision;         /* SPH_FP64, or SPH_FP32_MIXED: FP32 kernel sums with
+                                compensated accumulation, FP64 positions,
+                                integration and projection */
+  int32_t max_neighbors;     /* neighbour-list capacity per particle; 0 = 64 in
+                                2D, 160 in 3D */
+  double cell_factor;        /* cell side = 2 h_min cell_factor; 0 = 1.0 */
+  int32_t use_graph;         /* 1: steps replay a captured HIP graph */
+  int32_t debug_fields;      /* 1: keep gamma, V~ and v~ for sph_mesh_field */
+  void *stream;              /* hipStream_t to run on (e.g. PyTorch's current
+                                stream), default priority; NULL = the library
+                                creates its own */
+} sph_params;
+
+/* sph_mesh_create -- Algorithm 1's set-up with the caller's initial particles.
+ * n particles at xyz (n x 3) with feature index feature[i] (numbering above;
+ * the feature fixes the particle type P_si / P_c / P_s / P_+, sec. 3.2).
+ * Copies everything to the device, builds the feature tables and the cell
+ * grid, and returns a handle in *out (library-owned until destroy).
+ * Errors: SPH_ERR_INVALID_ARG for a bad description or a feature index out of
+ * range, SPH_ERR_OUT_OF_MEMORY, SPH_ERR_DEVICE.  *out is NULL on failure. */
+sph_status sph_mesh_create(const sph_geometry *geometry, const sph_sizing *sizing,
+                           const sph_params *params, int64_t n, const double *xyz,
+                           const int32_t *feature, sph_mesh **out);
+
+/* sph_mesh_step -- enqueue n_steps relaxation steps (Algorithm 1's loop body
+ * for every feature that has not converged, all features read x^n) on the
+ * handle's stream and return without waiting.  A step on a converged job does
+ * no work.  Errors that happen on the device are reported by the next
+ * positions / error call. */
+sph_status sph_mesh_step(sph_mesh *m, int32_t n_steps);
+
+/* sph_mesh_positions -- wait for the stream and copy positions (n x 3, caller
+ * order) and, if feature is not NULL, each particle's feature.  With xyz ==
+ * NULL only *n_out is set (size query).  capacity is the particle capacity of
+ * the buffers.  SPH_ERR_STATE if a non-finite position or a list overflow
+ * occurred. */
+sph_status sph_mesh_positions(sph_mesh *m, double *xyz, int32_t *feature,
+                              int64_t capacity, int64_t *n_out);
+
+/* sph_mesh_error -- wait for the stream; report the convergence error E_sys
+ * of sec. 3.4.2 (maximum over moving features; +inf until two averaging
+ * windows exist), the least advanced phase (1 Phase One, 2 transition,
+ * 3 Phase Two, 4 converged), whether every feature has converged, and the
+ * number of steps run.  Any output pointer may be NULL. */
+sph_status sph_mesh_error(sph_mesh *m, double *e_sys, int32_t *phase,
+                          int32_t *converged, int64_t *step);
+
+/* sph_mesh_destroy -- wait for the stream, free everything; NULL-safe. */
+void sph_mesh_destroy(sph_mesh *m);
+
+/* sph_mesh_last_error -- message of the last failure on this thread. */
+const char *sph_mesh_last_error(void);
+
+/* ---- inspection and test entry points --------------------------------- */
+
+/* Replace positions (n x 3) and/or velocities (n x 3), caller order; either
+ * may be NULL.  Waits for the stream. */
+sph_status sph_mesh_set_state(sph_mesh *m, const double *xyz, const double *vel);
+
+/* Copy velocities (n x 3, caller order) after waiting for the stream. */
+sph_status sph_mesh_velocities(sph_mesh *m, double *vel);
+
+/* Neighbour lists N(i) of the current positions (Algorithm 1's "construct
+ * Verlet neighbor list"): j != i with |x_i - x_j|^2 < 4 max(h_i, h_j)^2
+ * (FP64, squared distance summed over axes in order, no fused operations)
+ * and an interaction between the features (same feature: rel 1; j on the
+ * boundary of i's feature and of lower dimension: rel 2).  CSR in caller
+ * order: offsets[n+1], ids ascending per particle, rel per entry (NULL
+ * allowed).  Singular particles have empty lists.  With ids == NULL only
+ * offsets and *n_pairs are written.  cap = capacity of ids / rel. */
+sph_status sph_mesh_neighbors(sph_mesh *m, int64_t *offsets, int32_t *ids,
+                              int8_t *rel, int64_t cap, int64_t *n_pairs);
+
+/* Per-particle quantities of the last step, caller order (needs
+ * debug_fields for 3..5): 0 h (n), 1 pressure acceleration a^p (n x 3),
+ * 2 acceleration a (n x 3), 3 particle volume V~ (n), 4 Shepard gamma (n),
+ * 5 mid-point velocity v~ (n x 3). */
+sph_status sph_mesh_field(sph_mesh *m, int32_t which, double *out);
+
+/* Control state of one feature: out[0..9] = phase, steps in phase, E_sys,
+ * first time step, final time step, last V-bar sample, velocity reset due at
+ * the next step, last window mean, previous window mean, windows seen. */
+sph_status sph_mesh_group_state(sph_mesh *m, int32_t feature, double *out);
+
+/* Counters: out[0] steps, out[1] rejected volume-particle moves, out[2]
+ * interactions (neighbour-list entries of moving particles) summed over all
+ * steps, out[3] interactions of the last step. */
+sph_status sph_mesh_counters(sph_mesh *m, double *out);
+
+/* Run the device control law of one feature over a synthetic series of
+ * per-step V-bar samples and final time steps (no particles), writing per
+ * step the phase after it, whether the velocity is reset at the next step,
+ * and E_sys.  n <= 1,000,000. */
+sph_status sph_mesh_control_replay(const sph_params *params, int32_t n,
+                                   const double *vbar, const double *dt,
+                                   int32_t *phase, int32_t *reset, double *e_sys);
+
+/* Kernel timing with HIP events on the handle's stream.  enable != 0 makes
+ * later steps launch without a graph and bracket every kernel with events;
+ * sph_mesh_kernel_stats waits for the stream and returns, for kernel `kid`
+ * (see sph_mesh_kernel_name), the summed duration in ms and the launch count
+ * since profiling was enabled.  Kernel ids are 0..sph_mesh_kernel_count()-1. */
+sph_status sph_mesh_profile(sph_mesh *m, int32_t enable);
+sph_status sph_mesh_kernel_stats(sph_mesh *m, int32_t kid, double *ms, int64_t *launches);
+int32_t sph_mesh_kernel_count(void);
+const char *sph_mesh_kernel_name(int32_t kid);
+
+/* Wait for the handle's stream. */
+sph_status sph_mesh_sync(sph_mesh *m);
+
+/* Device bytes held by the handle. */
+int64_t sph_mesh_device_bytes(sph_mesh *m);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,277 @@
+"""ctypes binding of libsphmesh.so (include/sph_mesh.h): argument marshalling
+only, every step of the relaxation runs in the library's HIP kernels.
+
+Loading fails loudly when the library has not been built; there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsphmesh.so")
+
+SPH_FP64, SPH_FP32_MIXED = 0, 1
+FIELD_H, FIELD_AP, FIELD_A, FIELD_VT, FIELD_GAMMA, FIELD_VMID = range(6)
+
+
+class Geometry(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("lo", C.c_double * 3), ("hi", C.c_double * 3),
+                ("n_holes", C.c_int32), ("holes", C.POINTER(C.c_double))]
+
+
+class Sizing(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("h0", C.c_double), ("grad", C.c_double),
+                ("dcap", C.c_double), ("point", C.c_double * 3)]
+
+
+class Params(C.Structure):
+    _fields_ = [("p0", C.c_double), ("eps_damp", C.c_double), ("tol", C.c_double),
+                ("dt_max", C.c_double), ("boundary_weighting", C.c_int32),
+                ("reset_period", C.c_int32), ("sample_every", C.c_int32),
+                ("window_samples", C.c_int32), ("ramp_steps", C.c_int32),
+                ("ramp_halving", C.c_int32), ("phase2_steps", C.c_int32),
+                ("max_phase1_steps", C.c_int32), ("precision", C.c_int32),
+                ("max_neighbors", C.c_int32), ("cell_factor", C.c_double),
+                ("use_graph", C.c_int32), ("debug_fields", C.c_int32),
+                ("stream", C.c_void_p)]
+
+
+class SphError(RuntimeError):
+    def __init__(self, fn, status, msg):
+        super().__init__(f"{fn} -> status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+_dp = C.POINTER(C.c_double)
+
+
+def lib():
+    """Load libsphmesh.so; raise if it is missing (no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                              "or python paper_2003_01061_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.sph_mesh_create.argtypes = [C.POINTER(Geometry), C.POINTER(Sizing), C.POINTER(Params),
+                                      C.c_int64, vp, vp, C.POINTER(vp)]
+        L.sph_mesh_step.argtypes = [vp, C.c_int32]
+        L.sph_mesh_positions.argtypes = [vp, vp, vp, C.c_int64, C.POINTER(C.c_int64)]
+        L.sph_mesh_error.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int32),
+                                     C.POINTER(C.c_int32), C.POINTER(C.c_int64)]
+        L.sph_mesh_destroy.argtypes = [vp]
+        L.sph_mesh_destroy.restype = None
+        L.sph_mesh_last_error.restype = C.c_char_p
+        L.sph_mesh_set_state.argtypes = [vp, vp, vp]
+        L.sph_mesh_velocities.argtypes = [vp, vp]
+        L.sph_mesh_neighbors.argtypes = [vp, vp, vp, vp, C.c_int64, C.POINTER(C.c_int64)]
+        L.sph_mesh_field.argtypes = [vp, C.c_int32, vp]
+        L.sph_mesh_group_state.argtypes = [vp, C.c_int32, vp]
+        L.sph_mesh_counters.argtypes = [vp, vp]
+        L.sph_mesh_control_replay.argtypes = [C.POINTER(Params), C.c_int32, vp, vp, vp, vp, vp]
+        L.sph_mesh_profile.argtypes = [vp, C.c_int32]
+        L.sph_mesh_kernel_stats.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+        L.sph_mesh_kernel_count.restype = C.c_int32
+        L.sph_mesh_kernel_name.argtypes = [C.c_int32]
+        L.sph_mesh_kernel_name.restype = C.c_char_p
+        L.sph_mesh_sync.argtypes = [vp]
+        L.sph_mesh_device_bytes.argtypes = [vp]
+        L.sph_mesh_device_bytes.restype = C.c_int64
+        _lib = L
+    return _lib
+
+
+def _check(fn, status):
+    if status != 0:
+        raise SphError(fn, status, lib().sph_mesh_last_error().decode())
+
+
+def make_geometry(dim, lo, hi, holes):
+    holes = np.ascontiguousarray(np.asarray(holes, np.float64).reshape(-1, 15))
+    g = Geometry()
+    g.dim = dim
+    for a in range(3):
+        g.lo[a] = float(lo[a]) if a < len(lo) else 0.0
+        g.hi[a] = float(hi[a]) if a < len(hi) else 0.0
+    g.n_holes = holes.shape[0]
+    g.holes = holes.ctypes.data_as(_dp) if holes.size else None
+    g._keep = holes
+    return g
+
+
+def make_sizing(sz):
+    s = Sizing()
+    s.kind = int(sz["kind"])
+    s.h0 = float(sz["h0"])
+    s.grad = float(sz.get("grad", 0.0))
+    s.dcap = float(sz.get("dcap", np.inf))
+    for a in range(3):
+        s.point[a] = float(sz.get("point", [0, 0, 0])[a])
+    return s
+
+
+def make_params(p, stream=None):
+    q = Params()
+    for name, typ in Params._fields_:
+        if name == "stream":
+            continue
+        setattr(q, name, typ(p.get(name, 0)).value)
+    q.stream = stream
+    return q
+
+
+def current_torch_stream():
+    """The raw hipStream_t of PyTorch's current stream (None if unavailable)."""
+    try:
+        import torch
+        if torch.cuda.is_available():
+            h = torch.cuda.current_stream().cuda_stream
+            return h or None
+    except Exception:
+        pass
+    return None
+
+
+class SphMesh:
+    """One relaxation job on the GPU (libsphmesh.so handle)."""
+
+    def __init__(self, wl, params=None, xyz=None, feature=None, stream=None, **over):
+        L = lib()
+        p = dict(wl.params if params is None else params)
+        p.update(over)
+        self.dim = wl.dim
+        self._geom = make_geometry(wl.dim, wl.lo, wl.hi, wl.holes)
+        self._sizing = make_sizing(wl.sizing)
+        self._params = make_params(p, stream)
+        xyz = np.ascontiguousarray(wl.xyz if xyz is None else xyz, np.float64)
+        feature = np.ascontiguousarray(wl.feature if feature is None else feature, np.int32)
+        self.n = int(xyz.shape[0])
+        h = C.c_void_p()
+        _check("sph_mesh_create", L.sph_mesh_create(C.byref(self._geom), C.byref(self._sizing),
+                                                    C.byref(self._params), self.n,
+                                                    xyz.ctypes.data, feature.ctypes.data,
+                                                    C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().sph_mesh_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def step(self, n=1):
+        _check("sph_mesh_step", lib().sph_mesh_step(self.h, int(n)))
+
+    def sync(self):
+        _check("sph_mesh_sync", lib().sph_mesh_sync(self.h))
+
+    def positions(self, with_feature=False):
+        x = np.zeros((self.n, 3))
+        f = np.zeros(self.n, np.int32) if with_feature else None
+        nout = C.c_int64()
+        _check("sph_mesh_positions", lib().sph_mesh_positions(
+            self.h, x.ctypes.data, None if f is None else f.ctypes.data, self.n, C.byref(nout)))
+        return (x, f) if with_feature else x
+
+    def velocities(self):
+        v = np.zeros((self.n, 3))
+        _check("sph_mesh_velocities", lib().sph_mesh_velocities(self.h, v.ctypes.data))
+        return v
+
+    def state(self):
+        return self.positions(), self.velocities()
+
+    def set_state(self, xyz=None, vel=None):
+        x = None if xyz is None else np.ascontiguousarray(xyz, np.float64)
+        v = None if vel is None else np.ascontiguousarray(vel, np.float64)
+        _check("sph_mesh_set_state", lib().sph_mesh_set_state(
+            self.h, None if x is None else x.ctypes.data, None if v is None else v.ctypes.data))
+
+    def neighbors(self):
+        L = lib()
+        off = np.zeros(self.n + 1, np.int64)
+        npairs = C.c_int64()
+        _check("sph_mesh_neighbors", L.sph_mesh_neighbors(self.h, off.ctypes.data, None, None, 0,
+                                                          C.byref(npairs)))
+        ids = np.zeros(max(npairs.value, 1), np.int32)
+        rel = np.zeros(max(npairs.value, 1), np.int8)
+        _check("sph_mesh_neighbors", L.sph_mesh_neighbors(self.h, off.ctypes.data, ids.ctypes.data,
+                                                          rel.ctypes.data, ids.size,
+                                                          C.byref(npairs)))
+        return off, ids[:npairs.value], rel[:npairs.value]
+
+    def field(self, which):
+        shape = (self.n, 3) if which in (FIELD_AP, FIELD_A, FIELD_VMID) else (self.n,)
+        out = np.zeros(shape)
+        _check("sph_mesh_field", lib().sph_mesh_field(self.h, which, out.ctypes.data))
+        return out
+
+    def error(self):
+        e = C.c_double()
+        ph = C.c_int32()
+        conv = C.c_int32()
+        st = C.c_int64()
+        _check("sph_mesh_error", lib().sph_mesh_error(self.h, C.byref(e), C.byref(ph),
+                                                      C.byref(conv), C.byref(st)))
+        return dict(e_sys=e.value, phase=ph.value, converged=bool(conv.value), step=st.value)
+
+    def group_state(self, f):
+        out = np.zeros(10)
+        _check("sph_mesh_group_state", lib().sph_mesh_group_state(self.h, f, out.ctypes.data))
+        keys = ["phase", "n_ph", "e_sys", "dt1", "dt", "vbar", "reset_next", "a_last", "a_prev",
+                "n_windows"]
+        return dict(zip(keys, out.tolist()))
+
+    def counters(self):
+        out = np.zeros(4)
+        _check("sph_mesh_counters", lib().sph_mesh_counters(self.h, out.ctypes.data))
+        return dict(steps=int(out[0]), escaped=int(out[1]), interactions=int(out[2]),
+                    interactions_last=int(out[3]))
+
+    def profile(self, enable=True):
+        _check("sph_mesh_profile", lib().sph_mesh_profile(self.h, 1 if enable else 0))
+
+    def kernel_stats(self):
+        L = lib()
+        out = {}
+        for k in range(L.sph_mesh_kernel_count()):
+            ms = C.c_double()
+            cnt = C.c_int64()
+            _check("sph_mesh_kernel_stats", L.sph_mesh_kernel_stats(self.h, k, C.byref(ms),
+                                                                    C.byref(cnt)))
+            out[L.sph_mesh_kernel_name(k).decode()] = (ms.value, cnt.value)
+        return out
+
+    def device_bytes(self):
+        return int(lib().sph_mesh_device_bytes(self.h))
+
+
+def control_replay(params, vbar, dt):
+    p = make_params(params)
+    vbar = np.ascontiguousarray(vbar, np.float64)
+    dt = np.ascontiguousarray(dt, np.float64)
+    n = vbar.size
+    ph = np.zeros(n, np.int32)
+    rs = np.zeros(n, np.int32)
+    es = np.zeros(n)
+    _check("sph_mesh_control_replay", lib().sph_mesh_control_replay(
+        C.byref(p), n, vbar.ctypes.data, dt.ctypes.data, ph.ctypes.data, rs.ctypes.data,
+        es.ctypes.data))
+    return ph, rs, es
+
+
+def exported_symbols():
+    """Names the header declares (checked by the CPU test of the ABI)."""
+    return ["sph_mesh_create", "sph_mesh_step", "sph_mesh_positions", "sph_mesh_error",
+            "sph_mesh_destroy", "sph_mesh_last_error", "sph_mesh_set_state", "sph_mesh_velocities",
+            "sph_mesh_neighbors", "sph_mesh_field", "sph_mesh_group_state", "sph_mesh_counters",
+            "sph_mesh_control_replay", "sph_mesh_profile", "sph_mesh_kernel_stats",
+            "sph_mesh_kernel_count", "sph_mesh_kernel_name", "sph_mesh_sync",
+            "sph_mesh_device_bytes"]

@@ -1,0 +1,368 @@
+// sph_device.h -- device-side data layout and math of the feature-aware SPH
+// relaxation step for gfx950 (CDNA4, wave64).
+//
+// Layout in HBM: particles are structure-of-arrays in cell order (x, v, h as
+// FP64 columns, the feature index as one byte, the caller's id as u32).  The
+// neighbour list is ELL, entry e of slot i at nbr[e * n + i], so the 64 lanes
+// of a wave reading entry e touch 256 consecutive bytes.  The top bit of an
+// entry marks a boundary neighbour (a lower-dimensional feature bounding the
+// particle's own, paper sec. 3.3), the low 31 bits are the slot.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sph {
+
+constexpr int MAXF = 64;        // features per job
+constexpr int MAXH = 16;        // holes per job
+constexpr int MAXRING = 64;     // samples per averaging window
+constexpr int BLOCK = 256;
+
+enum : int { T_SI = 0, T_C = 1, T_S = 2, T_V = 3 };
+enum : int { K_VOL = 0, K_BOXSIDE = 1, K_HOLE = 2, K_EDGE3 = 3, K_CORNER = 4 };
+enum : int { PH_ONE = 1, PH_RAMP = 2, PH_TWO = 3, PH_FROZEN = 4 };
+
+// one feature: the paper's (type, index) pair and what its geometry is
+struct Feat {
+  int8_t type, k, kind, axis, side, fax0, fsd0, fax1, fsd1, hole, bits, pad[5];
+};
+
+// outward normal n_b of feature fi's boundary at a particle of feature fb
+// (paper sec. 3.3): mode 0 no relation, 1 the constant vector n, 2 the unit
+// vector from the particle to the centre of hole `hole` (out of the domain)
+struct BNorm {
+  int32_t mode, hole;
+  double n[3];
+};
+
+struct Geom {
+  int32_t dim, nf, nh, hkind;
+  double lo[3], hi[3];
+  double hc[MAXH][3];
+  double hr[MAXH];
+  double h0, grad, dcap, hpt[3];
+};
+
+// uniform cell grid over the box; per-particle search radius
+// R_i = min(rfac h_i, rmax) (rfac from the Lipschitz bound of h_t)
+struct Grid {
+  int32_t nc[3];
+  uint32_t ncell;
+  double lo[3], inv_c[3];
+  double rfac, rmax;
+};
+
+struct Ctl {
+  double tol, eps_damp, dt_max;
+  int32_t reset_period, sample_every, window_samples, ramp_steps, ramp_halving,
+      phase2_steps, max_phase1_steps, pad;
+};
+
+// per-feature group: inputs of the coming step, accumulators of the running
+// step (order independent: min of non-negative double bit patterns, integer
+// fixed-point sums), and the control state of sec. 3.4
+struct Group {
+  int32_t active, reset_now;
+  double eps;
+  unsigned long long dt1_bits, dt_bits, vsum;
+  int32_t phase, n_ph, nring, nwin, count, tracked, reset_next, pad;
+  double vscale, dt_prev, dt1, dt, esys, vbar, a_last, a_prev;
+  double ring[MAXRING];
+};
+
+struct Status {
+  unsigned long long escaped, inter_total, inter_last, inter_step, steps;
+  unsigned int nan_flag, nan_oid, overflow, overflow_max;
+  int32_t converged, pad;
+};
+
+struct Parts {
+  double *x[3];
+  double *v[3];
+  double *h;
+  uint8_t *f;
+  uint32_t *oid;
+};
+
+// ---------------------------------------------------------------------------
+// exact FP64 pieces shared by the neighbour predicate and the sizing function
+// ---------------------------------------------------------------------------
+
+// h_t(x) of the sizing record: squared distances summed over axes in order,
+// sqrt, no fused multiply-add, so that it is bit-reproducible.
+template <int D>
+__device__ __forceinline__ double h_target(const Geom &g, const double *p) {
+#pragma clang fp contract(off)
+  if (g.hkind == 0) return g.h0;
+  if (g.hkind == 1) {
+    double s = 0.0;
+    for (int a = 0; a < D; ++a) {
+      double d = p[a] - g.hpt[a];
+      s = s + d * d;
+    }
+    return g.h0 + g.grad * __builtin_sqrt(s);
+  }
+  double dmin = __builtin_inf();
+  for (int q = 0; q < g.nh; ++q) {
+    double s = 0.0;
+    for (int a = 0; a < D; ++a) {
+      double d = p[a] - g.hc[q][a];
+      s = s + d * d;
+    }
+    double d = __builtin_fabs(__builtin_sqrt(s) - g.hr[q]);
+    if (d < dmin) dmin = d;
+  }
+  if (g.dcap < dmin) dmin = g.dcap;
+  return g.h0 * (1.0 + g.grad * dmin);
+}
+
+// |x_i - x_j|^2 < 4 max(h_i, h_j)^2 evaluated exactly as specified
+template <int D>
+__device__ __forceinline__ bool within(const double *xi, double xj0, double xj1, double xj2,
+                                       double hi, double hj) {
+#pragma clang fp contract(off)
+  double d = xi[0] - xj0;
+  double s = d * d;
+  d = xi[1] - xj1;
+  s = s + d * d;
+  if (D == 3) {
+    d = xi[2] - xj2;
+    s = s + d * d;
+  }
+  double m = hi > hj ? hi : hj;
+  return s < 4.0 * (m * m);
+}
+
+__device__ __forceinline__ int cell_coord(const Grid &G, int a, double p) {
+  double t = __builtin_floor((p - G.lo[a]) * G.inv_c[a]);
+  t = t >= 0.0 ? t : 0.0;   // also maps NaN to cell 0
+  double top = (double)(G.nc[a] - 1);
+  t = t > top ? top : t;
+  return (int)t;
+}
+
+// ---------------------------------------------------------------------------
+// Wendland C2 kernel with support 2h in intrinsic dimension k (1, 2, 3):
+// W = alpha_k h^-k w(q), w = (1-q/2)^4 (1+2q) (k = 2, 3) or (1-q/2)^3 (1+3q/2)
+// (k = 1); (dW/dr)/r = alpha_k h^-(k+2) w'(q)/q with w'(q)/q = -5 (1-q/2)^3 or
+// -3 (1-q/2)^2, finite at r = 0.
+// ---------------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ R kalpha(int k) {
+  return k == 1 ? R(0.625) : (k == 2 ? R(0.55704230082163367519) : R(0.41778172561622525639));
+}
+template <typename R>
+__device__ __forceinline__ R wshape(int k, R q) {
+  if (!(q < R(2))) return R(0);
+  R t = R(1) - R(0.5) * q;
+  R t2 = t * t;
+  return k == 1 ? t2 * t * (R(1) + R(1.5) * q) : t2 * t2 * (R(1) + R(2) * q);
+}
+template <typename R>
+__device__ __forceinline__ R dwq(int k, R q) {
+  if (!(q < R(2))) return R(0);
+  R t = R(1) - R(0.5) * q;
+  return k == 1 ? R(-3) * t * t : R(-5) * t * t * t;
+}
+template <typename R>
+__device__ __forceinline__ R powk(R h, int k) {
+  return k == 1 ? h : (k == 2 ? h * h : h * h * h);
+}
+
+// fast reciprocal / square root per precision
+__device__ __forceinline__ double rcp_(double x) { return 1.0 / x; }
+__device__ __forceinline__ float rcp_(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double sqrt_(double x) { return __builtin_sqrt(x); }
+__device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
+
+__device__ __forceinline__ double abs_(double x) { return __builtin_fabs(x); }
+__device__ __forceinline__ float abs_(float x) { return __builtin_fabsf(x); }
+
+// compensated (Neumaier) accumulator for FP32 sums; plain sum for FP64
+template <typename R>
+struct Acc {
+  R s, c;
+  __device__ __forceinline__ void init(R v) { s = v; c = R(0); }
+  __device__ __forceinline__ void add(R v) {
+    R t = s + v;
+    const bool sb = abs_(s) >= abs_(v);
+    R big = sb ? s : v;
+    R small = sb ? v : s;
+    c += (big - t) + small;
+    s = t;
+  }
+  __device__ __forceinline__ R get() const { return s + c; }
+};
+template <>
+struct Acc<double> {
+  double s;
+  __device__ __forceinline__ void init(double v) { s = v; }
+  __device__ __forceinline__ void add(double v) { s += v; }
+  __device__ __forceinline__ double get() const { return s; }
+};
+
+// ---------------------------------------------------------------------------
+// feature geometry: tangent projection and closest-point projection
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double sgn_side(int s) { return s ? 1.0 : -1.0; }
+
+// u <- T_i u: identity on the volume, drop the normal part on a surface, keep
+// the tangent part on a curve, zero on a singular point
+template <int D>
+__device__ __forceinline__ void tangent(const Geom &g, const Feat &F, const double *x, double *u) {
+  switch (F.kind) {
+    case K_VOL: return;
+    case K_BOXSIDE: u[F.axis] = 0.0; return;
+    case K_EDGE3: {
+      double keep = u[F.axis];
+      u[0] = u[1] = u[2] = 0.0;
+      u[F.axis] = keep;
+      return;
+    }
+    case K_HOLE: {
+      const double *c = g.hc[F.hole];
+      if (D == 2) {
+        double t0 = -(x[1] - c[1]), t1 = x[0] - c[0];
+        double il = 1.0 / __builtin_sqrt(t0 * t0 + t1 * t1);
+        t0 *= il;
+        t1 *= il;
+        double ut = u[0] * t0 + u[1] * t1;
+        u[0] = ut * t0;
+        u[1] = ut * t1;
+      } else {
+        double m0 = x[0] - c[0], m1 = x[1] - c[1], m2 = x[2] - c[2];
+        double il = 1.0 / __builtin_sqrt(m0 * m0 + m1 * m1 + m2 * m2);
+        m0 *= il;
+        m1 *= il;
+        m2 *= il;
+        double un = u[0] * m0 + u[1] * m1 + u[2] * m2;
+        u[0] -= un * m0;
+        u[1] -= un * m1;
+        u[2] -= un * m2;
+      }
+      return;
+    }
+    default: u[0] = u[1] = u[2] = 0.0; return;
+  }
+}
+
+__device__ __forceinline__ double clamp_(double v, double lo, double hi) {
+  return v < lo ? lo : (v > hi ? hi : v);
+}
+
+// closest point of feature F to x (in place)
+template <int D>
+__device__ __forceinline__ void project(const Geom &g, const Feat &F, double *x) {
+  switch (F.kind) {
+    case K_BOXSIDE:
+      for (int a = 0; a < D; ++a) x[a] = clamp_(x[a], g.lo[a], g.hi[a]);
+      x[F.axis] = F.side ? g.hi[F.axis] : g.lo[F.axis];
+      return;
+    case K_EDGE3:
+      x[F.axis] = clamp_(x[F.axis], g.lo[F.axis], g.hi[F.axis]);
+      x[F.fax0] = F.fsd0 ? g.hi[F.fax0] : g.lo[F.fax0];
+      x[F.fax1] = F.fsd1 ? g.hi[F.fax1] : g.lo[F.fax1];
+      return;
+    case K_HOLE: {
+      const double *c = g.hc[F.hole];
+      double d[3] = {0.0, 0.0, 0.0}, s = 0.0;
+      for (int a = 0; a < D; ++a) {
+        d[a] = x[a] - c[a];
+        s += d[a] * d[a];
+      }
+      double r = __builtin_sqrt(s);
+      for (int a = 0; a < D; ++a) x[a] = c[a] + g.hr[F.hole] * (d[a] / r);
+      return;
+    }
+    case K_CORNER:
+      for (int a = 0; a < D; ++a) x[a] = ((F.bits >> a) & 1) ? g.hi[a] : g.lo[a];
+      return;
+    default: return;
+  }
+}
+
+// phi(x) > 0: strictly inside the box, strictly outside every hole
+template <int D>
+__device__ __forceinline__ bool inside(const Geom &g, const double *x) {
+#pragma clang fp contract(off)
+  for (int a = 0; a < D; ++a)
+    if (!(x[a] > g.lo[a] && x[a] < g.hi[a])) return false;
+  for (int q = 0; q < g.nh; ++q) {
+    double s = 0.0;
+    for (int a = 0; a < D; ++a) {
+      double d = x[a] - g.hc[q][a];
+      s = s + d * d;
+    }
+    double r = g.hr[q];
+    if (!(s > r * r)) return false;
+  }
+  return true;
+}
+
+__device__ __forceinline__ unsigned long long dbits(double v) {
+  return (unsigned long long)__double_as_longlong(v);
+}
+__device__ __forceinline__ double bitsd(unsigned long long b) {
+  return __longlong_as_double((long long)b);
+}
+
+// ---------------------------------------------------------------------------
+// the control law of one feature (sec. 3.4): V-bar sampling every
+// sample_every steps into windows of window_samples, E_t against the last
+// window mean, E_avg between the last two window means, E_sys = max of both;
+// Phase One -> transition when E_sys < tol (or after max_phase1_steps) ->
+// Phase Two -> frozen; velocity resets: every reset_period steps and after a
+// tenfold time-step drop in Phase One, a halving period in the transition,
+// every step in Phase Two.
+// ---------------------------------------------------------------------------
+__device__ inline void control_law(const Ctl &P, Group &G, double vbar, double dt) {
+  G.n_ph += 1;
+  if (G.n_ph % P.sample_every == 0) {
+    G.vbar = vbar;
+    G.ring[G.nring] = vbar;
+    G.nring += 1;
+    if (G.nring == P.window_samples) {
+      double s = 0.0;
+      for (int q = 0; q < G.nring; ++q) s = s + G.ring[q];
+      G.a_prev = G.a_last;
+      G.a_last = s / (double)G.nring;
+      G.nwin += 1;
+      G.nring = 0;
+    }
+    double et = G.nwin >= 1 ? __builtin_fabs(vbar - G.a_last) / G.a_last : __builtin_inf();
+    double ea = G.nwin >= 2 ? __builtin_fabs(G.a_last - G.a_prev) / G.a_prev : __builtin_inf();
+    G.esys = et > ea ? et : ea;
+  }
+  if (G.phase == PH_ONE) {
+    if (G.esys < P.tol || G.n_ph >= P.max_phase1_steps) {
+      G.phase = PH_RAMP;
+      G.n_ph = 0;
+    }
+  } else if (G.phase == PH_RAMP) {
+    if (G.n_ph >= P.ramp_steps) {
+      G.phase = PH_TWO;
+      G.n_ph = 0;
+    }
+  } else if (G.phase == PH_TWO) {
+    if (G.n_ph >= P.phase2_steps) G.phase = PH_FROZEN;
+  }
+  if (G.phase == PH_ONE) {
+    G.reset_next = (G.n_ph % P.reset_period == 0) || (G.dt_prev > 0.0 && dt < 0.1 * G.dt_prev);
+  } else if (G.phase == PH_RAMP) {
+    int shift = G.n_ph / P.ramp_halving;
+    int period = shift >= 30 ? 1 : (P.reset_period >> shift);
+    if (period < 1) period = 1;
+    G.reset_next = (G.n_ph % period) == 0;
+  } else {
+    G.reset_next = 1;
+  }
+  G.dt_prev = dt;
+}
+
+__device__ inline double damping(const Ctl &P, const Group &G) {
+  if (G.phase == PH_ONE) return P.eps_damp;
+  if (G.phase == PH_RAMP) return P.eps_damp * (1.0 - (double)G.n_ph / (double)P.ramp_steps);
+  return 0.0;
+}
+
+}  // namespace sph

@@ -1,0 +1,183 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Bars: neighbour lists and h bit-exact; positions after K steps within 1e-12
+of the domain size for the FP64 path and 1e-5 for the FP32-mixed path;
+control law identical.  Every case is seeded and synthetic (see
+paper_2003_01061_amd.workload).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2003_01061_amd import binding
+from paper_2003_01061_amd import workload as wk
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12     # FP64 path, relative to the domain extent (1.0)
+TOL32 = 1e-5      # FP32-mixed path
+
+CASES = {
+    "square64": lambda: wk.square_lattice(),
+    "hole2d_20011": lambda: wk.scaled_hole_2d(20011, seed=21, res=512),
+    "ball3d_30011": lambda: wk.scaled_ball_3d(30011, seed=22, res=96),
+}
+KSTEPS = {"square64": 200, "hole2d_20011": 60, "ball3d_30011": 25}
+
+_wl_cache = {}
+
+
+def case(name):
+    if name not in _wl_cache:
+        _wl_cache[name] = CASES[name]()
+    return _wl_cache[name]
+
+
+def domain(wl):
+    return float(np.max(wl.hi[:wl.dim] - wl.lo[:wl.dim]))
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu(gpu):
+    return gpu
+
+
+# ---------------------------------------------------------------------------
+def test_control_law_matches_oracle():
+    rng = np.random.default_rng(7)
+    series = []
+    n = 1500
+    series.append((wk.default_params(), np.ones(n), np.full(n, 0.01)))
+    v = np.ones(n); v[200:400] = 1.001
+    series.append((wk.default_params(), v, np.full(n, 0.01)))
+    dt = np.full(n, 0.01); dt[50] = 0.0009; dt[700] = 1e-5
+    series.append((wk.default_params(max_phase1_steps=250), np.linspace(1, 2, n), dt))
+    series.append((wk.default_params(), 1 + 1e-7 * rng.standard_normal(n), rng.uniform(1e-3, 1e-2, n)))
+    for p, vb, d in series:
+        a = oracle.control_replay(p, vb, d)
+        b = binding.control_replay(p, vb, d)
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_h_and_neighbor_lists_bit_exact(name):
+    wl = case(name)
+    ref = oracle.RefJob(wl)
+    off_r, ids_r, rel_r = ref.neighbors()
+    gpu = binding.SphMesh(wl)
+    off_g, ids_g, rel_g = gpu.neighbors()
+    assert np.array_equal(gpu.field(binding.FIELD_H), ref.field(oracle.F_H))
+    assert np.array_equal(off_g, off_r)
+    assert np.array_equal(ids_g, ids_r)
+    assert np.array_equal(rel_g, rel_r)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_first_step_fields(name):
+    wl = case(name)
+    ref = oracle.RefJob(wl)
+    ref.step(1)
+    gpu = binding.SphMesh(wl, debug_fields=1)
+    gpu.step(1)
+    pairs = [(binding.FIELD_AP, oracle.F_AP), (binding.FIELD_A, oracle.F_A),
+             (binding.FIELD_VT, oracle.F_VT), (binding.FIELD_GAMMA, oracle.F_GAMMA),
+             (binding.FIELD_VMID, oracle.F_VMID)]
+    for fg, fr in pairs:
+        g = gpu.field(fg)
+        r = ref.field(fr)
+        scale = np.abs(r).max()
+        assert scale > 0
+        assert np.abs(g - r).max() <= 1e-12 * scale, (fg, np.abs(g - r).max() / scale)
+    for f in range(len(wl.ftype)):
+        gs, rs = gpu.group_state(f), ref.group_state(f)
+        if wl.ftype[f] == wk.SI or not np.any(wl.feature == f):
+            continue
+        assert abs(gs["dt1"] - rs["dt1"]) <= 1e-12 * rs["dt1"]
+        assert abs(gs["dt"] - rs["dt"]) <= 1e-12 * rs["dt"]
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_positions_after_k_steps_fp64(name):
+    wl = case(name)
+    K = KSTEPS[name]
+    ref = oracle.RefJob(wl)
+    ref.step(K)
+    gpu = binding.SphMesh(wl, use_graph=1)
+    gpu.step(K)
+    xr, vr = ref.state()
+    xg, vg = gpu.state()
+    err = np.abs(xg - xr).max() / domain(wl)
+    assert err <= TOL64, err
+    assert gpu.counters()["interactions"] == ref.counters()["interactions"]
+    assert gpu.counters()["escaped"] == ref.counters()["escaped"]
+    assert gpu.error()["step"] == K
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_positions_after_k_steps_fp32_mixed(name):
+    wl = case(name)
+    K = KSTEPS[name]
+    ref = oracle.RefJob(wl)
+    ref.step(K)
+    gpu = binding.SphMesh(wl, precision=binding.SPH_FP32_MIXED, use_graph=1)
+    gpu.step(K)
+    err = np.abs(gpu.positions() - ref.state()[0]).max() / domain(wl)
+    assert err <= TOL32, err
+
+
+def test_graph_replay_equals_eager_and_is_deterministic():
+    wl = case("hole2d_20011")
+    runs = []
+    for graph in (0, 1, 1):
+        g = binding.SphMesh(wl, use_graph=graph)
+        g.step(7)          # odd count: one eager step, then graph pairs
+        g.step(6)
+        runs.append(g.positions())
+    assert np.array_equal(runs[0], runs[1])
+    assert np.array_equal(runs[1], runs[2])
+
+
+def test_edge_cases():
+    # no particles
+    wl = wk.square_lattice(n_side=4)
+    wl.xyz = np.zeros((0, 3))
+    wl.feature = np.zeros(0, np.int32)
+    g = binding.SphMesh(wl)
+    g.step(3)
+    assert g.positions().shape == (0, 3)
+    # corners only: nothing moves, the job is converged from the start
+    wl = wk.square_lattice(n_side=4)
+    keep = wl.feature >= 5
+    wl.xyz, wl.feature = wl.xyz[keep].copy(), wl.feature[keep].copy()
+    g = binding.SphMesh(wl)
+    g.step(5)
+    assert np.array_equal(g.positions(), wl.xyz)
+    assert g.error()["converged"]
+    # a handful of particles: one per feature group, ragged tail
+    wl = wk.square_lattice(n_side=6, seed=3)
+    ref = oracle.RefJob(wl)
+    ref.step(30)
+    g = binding.SphMesh(wl)
+    g.step(30)
+    assert np.abs(g.positions() - ref.state()[0]).max() <= TOL64
+
+
+def test_full_size_square_hole_250k():
+    """The benchmark workload at full size: bit-exact lists, 5 steps in FP64
+    and FP32-mixed, in the launch configuration the benchmark times."""
+    wl = wk.square_hole()
+    ref = oracle.RefJob(wl)
+    off_r, ids_r, rel_r = ref.neighbors()
+    g64 = binding.SphMesh(wl, use_graph=1)
+    off_g, ids_g, rel_g = g64.neighbors()
+    assert np.array_equal(off_g, off_r) and np.array_equal(ids_g, ids_r)
+    assert np.array_equal(rel_g, rel_r)
+    K = 6
+    ref.step(K)
+    g64.step(K)
+    g32 = binding.SphMesh(wl, precision=binding.SPH_FP32_MIXED, use_graph=1)
+    g32.step(K)
+    xr = ref.state()[0]
+    assert np.abs(g64.positions() - xr).max() <= TOL64
+    assert np.abs(g32.positions() - xr).max() <= TOL32
