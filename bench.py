@@ -1,0 +1,209 @@
+"""Benchmark: particle-neighbour interactions/s of the feature-aware SPH
+relaxation step on one MI355X.
+
+Workload (default): the 2D unit square minus the disc r = 1/4, 250,000
+particles, graded h = s h0 (1 + 4 d), h0 = 1/1024, seeded random init, 2,000
+steps through both phases (Phase One capped at 1,200 steps), run once with
+FP32 kernel sums + FP64 integration (the reported value) and once in plain
+FP64.  A step is one pass of the whole hot path: hashing, sort, cell table,
+neighbour list, both force sweeps, integration with projection and control.
+The timed region starts with the particles resident in HBM and ends after
+the last step; creation and the host copy of the result are outside it.
+
+interactions = neighbour-list entries of every moving particle, once per step.
+
+Prints one JSON line (see the design doc for the roofline bytes and the CPU
+baseline sample).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def kernel_bytes(name, wl, n_active, inter, real_bytes):
+    """Algorithmic HBM bytes of one launch: every particle column read or
+    written once, the neighbour list read or written once; gathers of
+    neighbour data are cache traffic and not counted."""
+    D = wl.dim
+    N = wl.n
+    x = 8 * D
+    if name == "neighbors":
+        return N * (x + 8 + 1) + N * 4 + inter * 4 + N * 4
+    if name == "sweep_a":
+        return n_active * (x + x + 8 + 1 + 4) + inter * 4 + n_active * D * real_bytes
+    if name == "sweep_b":
+        return n_active * (x + x + 8 + 1 + 4 + D * real_bytes) + inter * 4 + n_active * D * real_bytes
+    if name == "integrate":
+        return n_active * (1 + x + x + D * real_bytes) + n_active * (x + x)
+    if name == "gather":
+        return N * 4 + 2 * N * (x + x + 8 + 1 + 4)
+    if name == "hash_count":
+        return N * (x + 8 + 4 + 4)
+    return None
+
+
+def run_timed(wl, precision, steps, warmup, graph=True):
+    from paper_2003_01061_amd import binding
+    import torch
+    if warmup:
+        w = binding.SphMesh(wl, precision=precision, use_graph=int(graph))
+        w.step(warmup)
+        w.sync()
+        w.close()
+    j = binding.SphMesh(wl, precision=precision, use_graph=int(graph))
+    j.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    j.step(steps)
+    j.sync()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    c = j.counters()
+    e = j.error()
+    x = j.positions()
+    j.close()
+    return dict(seconds=t1 - t0, interactions=c["interactions"], escaped=c["escaped"],
+                steps=c["steps"], e_sys=e["e_sys"], phase=e["phase"], converged=e["converged"],
+                positions=x)
+
+
+def profile_kernels(wl, precision, steps):
+    """Per-kernel durations from HIP events recorded on the library's stream."""
+    from paper_2003_01061_amd import binding
+    j = binding.SphMesh(wl, precision=precision, use_graph=0)
+    j.profile(True)
+    j.step(steps)
+    stats = j.kernel_stats()
+    c = j.counters()
+    j.close()
+    return stats, c
+
+
+def quality(wl, x):
+    """Proxy of converged mesh quality: nearest-neighbour distance / h_t."""
+    from scipy.spatial import cKDTree
+    from paper_2003_01061_amd.workload import _h_field
+    pts = x[:, :wl.dim]
+    d, _ = cKDTree(pts).query(pts, k=2)
+    h = _h_field(x, wl.dim, wl.sizing, wl.holes)
+    r = d[:, 1] / h
+    return dict(nn_over_h_mean=float(r.mean()), nn_over_h_p1=float(np.percentile(r, 1)),
+                nn_over_h_min=float(r.min()))
+
+
+def cpu_baseline(wl, budget_s):
+    import oracle
+    j = oracle.RefJob(wl)
+    t0 = time.perf_counter()
+    steps = 0
+    while True:
+        j.step(1)
+        steps += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    t = time.perf_counter() - t0
+    c = j.counters()
+    return dict(value=c["interactions"] / t, unit="interactions/s", cores=1, kind="oracle",
+                sample=f"first {steps} steps of the same workload, single-threaded FP64 oracle, "
+                       f"{t:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--profile-steps", type=int, default=200)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--n", type=int, default=250_000)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
+              "(the design of a multi-GPU decomposition is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    from paper_2003_01061_amd import binding
+    from paper_2003_01061_amd import workload as wk
+
+    wl = wk.square_hole(n_total=args.n)
+    print(f"[bench] workload square_hole n={wl.n} scale={wl.scale:.4f}", file=sys.stderr, flush=True)
+    r32 = run_timed(wl, binding.SPH_FP32_MIXED, args.steps, args.warmup)
+    print(f"[bench] fp32-mixed {r32['seconds']:.3f}s", file=sys.stderr, flush=True)
+    r64 = None
+    if not args.no_fp64:
+        r64 = run_timed(wl, binding.SPH_FP64, args.steps, args.warmup)
+        print(f"[bench] fp64 {r64['seconds']:.3f}s", file=sys.stderr, flush=True)
+    value = r32["interactions"] / r32["seconds"]
+
+    stats, pc = profile_kernels(wl, binding.SPH_FP32_MIXED, args.profile_steps)
+    per = {k: (ms / cnt if cnt else 0.0, cnt) for k, (ms, cnt) in stats.items()}
+    dom = max((k for k in stats if kernel_bytes(k, wl, 1, 1, 4) is not None),
+              key=lambda k: stats[k][0])
+    n_active = int(np.sum(wl.ftype[wl.feature] != wk.SI))
+    inter_step = pc["interactions"] / max(pc["steps"], 1)
+    byts = kernel_bytes(dom, wl, n_active, inter_step, 4)
+    avg_s = per[dom][0] * 1e-3
+    achieved = byts / avg_s / 1e9
+    print(f"[bench] profile: " + ", ".join(f"{k}={v[0]*1e3:.1f}us" for k, v in per.items()),
+          file=sys.stderr, flush=True)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(wl, args.cpu_seconds)
+
+    out = {
+        "metric": "particle-neighbour interactions/s per step (FP32 vs FP64) + p50/p99 job latency",
+        "value": value,
+        "unit": "interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r32["seconds"] / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "square_hole_2d", "n_particles": wl.n, "h0": 1.0 / 1024,
+                   "h_scale": round(wl.scale, 6), "grad": 4.0, "hole_radius": 0.25,
+                   "steps": args.steps, "precision": "fp32 sums + fp64 integration",
+                   "parallelism": "single GPU"},
+        "fp64": None if r64 is None else {
+            "value": r64["interactions"] / r64["seconds"],
+            "ms_per_step": r64["seconds"] / args.steps * 1e3,
+            "e_sys": r64["e_sys"], "phase": r64["phase"],
+            "max_abs_position_diff_vs_fp32": float(np.abs(r64["positions"] - r32["positions"]).max()),
+        },
+        "convergence": {"e_sys": r32["e_sys"], "phase": r32["phase"],
+                        "converged": r32["converged"], "escaped": r32["escaped"]},
+        "quality": {"fp32": quality(wl, r32["positions"]),
+                    "fp64": None if r64 is None else quality(wl, r64["positions"])},
+        "latency_p50_p99_s": None,
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "avg_launch_us": per[dom][0] * 1e3, "bytes_per_launch": byts,
+                     "launches": per[dom][1]},
+        "kernel_avg_us": {k: round(v[0] * 1e3, 2) for k, v in per.items()},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

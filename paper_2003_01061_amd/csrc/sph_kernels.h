@@ -28,9 +28,22 @@ __device__ __forceinline__ unsigned long long umin64(unsigned long long a, unsig
   return a < b ? a : b;
 }
 
-__device__ __forceinline__ void group_commit(bool valid, int g, unsigned long long vmin,
-                                             unsigned long long vadd, unsigned long long *min_base,
-                                             unsigned long long *add_base, size_t stride) {
+// Per-group reduction of one block: every wave reduces each distinct group
+// among its valid lanes with xor shuffles, one lane folds the result into the
+// block's LDS slot with an LDS atomic, and the block writes one partial per
+// group.  Device-wide same-address atomics are avoided on purpose: with
+// thousands of waves they serialise.
+__device__ __forceinline__ void block_group_reduce(bool valid, int g, unsigned long long vmin,
+                                                   unsigned long long vadd,
+                                                   unsigned long long *s_min,
+                                                   unsigned long long *s_sum, int nf,
+                                                   unsigned long long *pmin,
+                                                   unsigned long long *psum) {
+  for (int t = threadIdx.x; t < nf; t += blockDim.x) {
+    s_min[t] = ~0ull;
+    s_sum[t] = 0ull;
+  }
+  __syncthreads();
   unsigned long long mask = __ballot(valid);
   const int lane = __lane_id();
   while (mask) {
@@ -45,10 +58,54 @@ __device__ __forceinline__ void group_commit(bool valid, int g, unsigned long lo
       sm += __shfl_xor(sm, o);
     }
     if (lane == leader) {
-      if (min_base) atomicMin((unsigned long long *)((char *)min_base + stride * gl), mn);
-      if (add_base) atomicAdd((unsigned long long *)((char *)add_base + stride * gl), sm);
+      atomicMin(&s_min[gl], mn);
+      if (psum) atomicAdd(&s_sum[gl], sm);
     }
     mask &= ~mm;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < nf; t += blockDim.x) {
+    pmin[(size_t)blockIdx.x * nf + t] = s_min[t];
+    if (psum) psum[(size_t)blockIdx.x * nf + t] = s_sum[t];
+  }
+}
+
+// one block per group: fold the per-block partials of group blockIdx.x;
+// which = 0 -> dt_1 and the V~ sum, which = 1 -> dt.  The time step is the
+// minimum of the particle terms and the cap dt_max.
+__global__ __launch_bounds__(BLOCK) void k_group_reduce(const unsigned long long *__restrict__ pmin,
+                                                        const unsigned long long *__restrict__ psum,
+                                                        int nblk, int nf, double dt_max, Group *grp,
+                                                        int which) {
+  __shared__ unsigned long long smn[BLOCK / 64], ssm[BLOCK / 64];
+  const int g = blockIdx.x;
+  unsigned long long mn = ~0ull, sm = 0ull;
+  for (int b = threadIdx.x; b < nblk; b += BLOCK) {
+    mn = umin64(mn, pmin[(size_t)b * nf + g]);
+    if (psum) sm += psum[(size_t)b * nf + g];
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    mn = umin64(mn, __shfl_xor(mn, o));
+    sm += __shfl_xor(sm, o);
+  }
+  const int w = threadIdx.x >> 6;
+  if (__lane_id() == 0) {
+    smn[w] = mn;
+    ssm[w] = sm;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 1; q < BLOCK / 64; ++q) {
+      mn = umin64(mn, smn[q]);
+      sm += ssm[q];
+    }
+    mn = umin64(mn, dbits(dt_max));
+    if (which == 0) {
+      grp[g].dt1_bits = mn;
+      grp[g].vsum = sm;
+    } else {
+      grp[g].dt_bits = mn;
+    }
   }
 }
 
@@ -222,7 +279,9 @@ __global__ __launch_bounds__(BLOCK) void k_neighbors(Geom g, Grid G, Parts s, in
                                                      const Group *__restrict__ grp, int all,
                                                      uint32_t *__restrict__ nbr,
                                                      uint32_t *__restrict__ nnb, int cap,
-                                                     Status *st, int count_inter) {
+                                                     Status *st,
+                                                     unsigned long long *__restrict__ pcount) {
+  __shared__ unsigned long long s_cnt[BLOCK / 64];
   int i = blockIdx.x * BLOCK + threadIdx.x;
   unsigned long long mine = 0;
   if (i < n) {
@@ -264,9 +323,15 @@ __global__ __launch_bounds__(BLOCK) void k_neighbors(Geom g, Grid G, Parts s, in
     nnb[i] = count;
     mine = count;
   }
-  if (count_inter) {
+  if (pcount) {
     unsigned long long tot = wave_sum_u64(mine);
-    if (__lane_id() == 0 && tot) atomicAdd(&st->inter_step, tot);
+    if (__lane_id() == 0) s_cnt[threadIdx.x >> 6] = tot;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      unsigned long long b = 0;
+      for (int w = 0; w < BLOCK / 64; ++w) b += s_cnt[w];
+      pcount[blockIdx.x] = b;
+    }
   }
 }
 
@@ -282,7 +347,10 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_a(Geom g, double p0, int bw, Pa
                                                    const BNorm *__restrict__ bn, Group *grp,
                                                    R *__restrict__ ap0, R *__restrict__ ap1,
                                                    R *__restrict__ ap2, double *__restrict__ dbg_gam,
-                                                   double *__restrict__ dbg_vt) {
+                                                   double *__restrict__ dbg_vt,
+                                                   unsigned long long *__restrict__ pmin,
+                                                   unsigned long long *__restrict__ psum) {
+  __shared__ unsigned long long s_min[MAXF], s_sum[MAXF];
   int i = blockIdx.x * BLOCK + threadIdx.x;
   bool act = false;
   int fi = 0;
@@ -385,9 +453,15 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_a(Geom g, double p0, int bw, Pa
       }
       dtb = dbits(dt);
       vfix = (unsigned long long)__builtin_llrint(vt * grp[fi].vscale);
+    } else {
+      ap0[i] = R(0);
+      ap1[i] = R(0);
+      if (D == 3) ap2[i] = R(0);
+      if (dbg_gam) dbg_gam[i] = 0.0;
+      if (dbg_vt) dbg_vt[i] = 0.0;
     }
   }
-  group_commit(act, fi, dtb, vfix, &grp[0].dt1_bits, &grp[0].vsum, sizeof(Group));
+  block_group_reduce(act, fi, dtb, vfix, s_min, s_sum, g.nf, pmin, psum);
 }
 
 // ---------------------------------------------------------------------------
@@ -404,7 +478,9 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_b(Geom g, Parts s, int n,
                                                    R *__restrict__ a1, R *__restrict__ a2,
                                                    double *__restrict__ dbg_vm0,
                                                    double *__restrict__ dbg_vm1,
-                                                   double *__restrict__ dbg_vm2) {
+                                                   double *__restrict__ dbg_vm2,
+                                                   unsigned long long *__restrict__ pmin) {
+  __shared__ unsigned long long s_min[MAXF], s_sum[MAXF];
   int i = blockIdx.x * BLOCK + threadIdx.x;
   bool act = false;
   int fi = 0;
@@ -484,9 +560,18 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_b(Geom g, Parts s, int n,
         dt = t < dt ? t : dt;
       }
       dtb = dbits(dt);
+    } else {
+      a0[i] = R(0);
+      a1[i] = R(0);
+      if (D == 3) a2[i] = R(0);
+      if (dbg_vm0) {
+        dbg_vm0[i] = 0.0;
+        dbg_vm1[i] = 0.0;
+        if (D == 3) dbg_vm2[i] = 0.0;
+      }
     }
   }
-  group_commit(act, fi, dtb, 0ull, &grp[0].dt_bits, nullptr, sizeof(Group));
+  block_group_reduce(act, fi, dtb, 0ull, s_min, s_sum, g.nf, pmin, nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -498,7 +583,9 @@ __global__ __launch_bounds__(BLOCK) void k_integrate(Geom g, Parts s, int n,
                                                      const Group *__restrict__ grp,
                                                      const R *__restrict__ a0,
                                                      const R *__restrict__ a1,
-                                                     const R *__restrict__ a2, Status *st) {
+                                                     const R *__restrict__ a2, Status *st,
+                                                     unsigned long long *__restrict__ pesc) {
+  __shared__ unsigned long long s_esc[BLOCK / 64];
   int i = blockIdx.x * BLOCK + threadIdx.x;
   bool escaped = false;
   if (i < n) {
@@ -548,16 +635,37 @@ __global__ __launch_bounds__(BLOCK) void k_integrate(Geom g, Parts s, int n,
     }
   }
   unsigned long long m = __ballot(escaped);
-  if (__lane_id() == 0 && m) atomicAdd(&st->escaped, (unsigned long long)__popcll(m));
+  if (__lane_id() == 0) s_esc[threadIdx.x >> 6] = (unsigned long long)__popcll(m);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long b = 0;
+    for (int w = 0; w < BLOCK / 64; ++w) b += s_esc[w];
+    pesc[blockIdx.x] = b;
+  }
 }
 
 // ---------------------------------------------------------------------------
 // control of every feature; prepares the next step (one block)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void k_control(Ctl P, Group *grp, int nf, Status *st) {
+__global__ __launch_bounds__(BLOCK) void k_control(Ctl P, Group *grp, int nf, Status *st,
+                                                   const unsigned long long *__restrict__ pcount,
+                                                   const unsigned long long *__restrict__ pesc,
+                                                   int nblk) {
   __shared__ int moving;
+  __shared__ unsigned long long s_c[BLOCK / 64], s_e[BLOCK / 64];
   const int q = threadIdx.x;
   if (q == 0) moving = 0;
+  unsigned long long c = 0, e = 0;
+  for (int b = q; b < nblk; b += BLOCK) {
+    c += pcount[b];
+    e += pesc[b];
+  }
+  c = wave_sum_u64(c);
+  e = wave_sum_u64(e);
+  if (__lane_id() == 0) {
+    s_c[q >> 6] = c;
+    s_e[q >> 6] = e;
+  }
   __syncthreads();
   if (q < nf) {
     Group &G = grp[q];
@@ -571,17 +679,19 @@ __global__ __launch_bounds__(64) void k_control(Ctl P, Group *grp, int nf, Statu
     G.active = G.tracked && G.phase != PH_FROZEN;
     G.reset_now = G.reset_next;
     G.eps = damping(P, G);
-    G.dt1_bits = dbits(P.dt_max);
-    G.dt_bits = dbits(P.dt_max);
-    G.vsum = 0ull;
     if (G.active) atomicOr(&moving, 1);
   }
   __syncthreads();
   if (q == 0) {
+    unsigned long long ct = 0, et = 0;
+    for (int w = 0; w < BLOCK / 64; ++w) {
+      ct += s_c[w];
+      et += s_e[w];
+    }
     st->steps += 1ull;
-    st->inter_last = st->inter_step;
-    st->inter_total += st->inter_step;
-    st->inter_step = 0ull;
+    st->inter_last = ct;
+    st->inter_total += ct;
+    st->escaped += et;
     st->converged = moving ? 0 : 1;
   }
 }

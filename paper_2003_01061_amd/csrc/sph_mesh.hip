@@ -45,11 +45,12 @@ sph_status fail(sph_status st, const char *fmt, ...) {
 
 enum KernelId {
   KID_HASH = 0, KID_SCAN_LOCAL, KID_SCAN_TOP, KID_SCAN_ADD, KID_SCATTER, KID_CELLSORT,
-  KID_GATHER, KID_NEIGHBORS, KID_SWEEP_A, KID_SWEEP_B, KID_INTEGRATE, KID_CONTROL, KID_COUNT
+  KID_GATHER, KID_NEIGHBORS, KID_SWEEP_A, KID_REDUCE_A, KID_SWEEP_B, KID_REDUCE_B, KID_INTEGRATE,
+  KID_CONTROL, KID_COUNT
 };
 const char *kKernelNames[KID_COUNT] = {
-    "hash_count", "scan_local", "scan_top", "scan_add", "scatter", "cellsort",
-    "gather", "neighbors", "sweep_a", "sweep_b", "integrate", "control"};
+    "hash_count", "scan_local", "scan_top", "scan_add", "scatter", "cellsort", "gather",
+    "neighbors", "sweep_a", "reduce_a", "sweep_b", "reduce_b", "integrate", "control"};
 
 // ---------------------------------------------------------------------------
 // features of a box-minus-holes geometry (numbering of sph_mesh.h)
@@ -184,6 +185,8 @@ struct sph_mesh {
   Group *d_grp = nullptr;
   Status *d_st = nullptr;
   uint32_t nscan_tiles = 0;
+  int nblk = 0;                                 // particle blocks of one launch
+  unsigned long long *pmin = nullptr, *psum = nullptr, *pcount = nullptr, *pesc = nullptr;
   // graph of two steps
   hipGraphExec_t gexec = nullptr;
   // profiling
@@ -256,7 +259,8 @@ struct sph_mesh {
     cur = 1 - cur;
     HIPCHK(launch(KID_NEIGHBORS, k_neighbors<DD>, blocks(n), BLOCK, geom, grid, P[cur], n,
                   (const uint32_t *)cstart, (const int8_t *)d_rel, (const Feat *)d_feat,
-                  (const Group *)d_grp, all_lists ? 1 : 0, nbr, nnb, cap, d_st, count_inter ? 1 : 0));
+                  (const Group *)d_grp, all_lists ? 1 : 0, nbr, nnb, cap, d_st,
+                  count_inter ? pcount : (unsigned long long *)nullptr));
     return SPH_OK;
   }
 
@@ -267,15 +271,22 @@ struct sph_mesh {
     R *a_c[3] = {(R *)acc_ptr(0), (R *)acc_ptr(1), (R *)acc_ptr(2)};
     HIPCHK(launch(KID_SWEEP_A, k_sweep_a<DD, R>, blocks(n), BLOCK, geom, p0, bw, s, n,
                   (const uint32_t *)nbr, (const uint32_t *)nnb, (const Feat *)d_feat,
-                  (const BNorm *)d_bn, d_grp, a_p[0], a_p[1], a_p[2], dbg_gam, dbg_vt));
+                  (const BNorm *)d_bn, d_grp, a_p[0], a_p[1], a_p[2], dbg_gam, dbg_vt, pmin, psum));
+    HIPCHK(launch(KID_REDUCE_A, k_group_reduce, (unsigned)nf, BLOCK,
+                  (const unsigned long long *)pmin, (const unsigned long long *)psum, nblk, nf,
+                  ctl.dt_max, d_grp, 0));
     HIPCHK(launch(KID_SWEEP_B, k_sweep_b<DD, R>, blocks(n), BLOCK, geom, s, n, (const uint32_t *)nbr,
                   (const uint32_t *)nnb, (const Feat *)d_feat, d_grp, (const R *)a_p[0],
                   (const R *)a_p[1], (const R *)a_p[2], a_c[0], a_c[1], a_c[2], dbg_vm[0], dbg_vm[1],
-                  dbg_vm[2]));
+                  dbg_vm[2], pmin));
+    HIPCHK(launch(KID_REDUCE_B, k_group_reduce, (unsigned)nf, BLOCK,
+                  (const unsigned long long *)pmin, (const unsigned long long *)nullptr, nblk, nf,
+                  ctl.dt_max, d_grp, 1));
     HIPCHK(launch(KID_INTEGRATE, k_integrate<DD, R>, blocks(n), BLOCK, geom, s, n,
                   (const Feat *)d_feat, (const Group *)d_grp, (const R *)a_c[0], (const R *)a_c[1],
-                  (const R *)a_c[2], d_st));
-    HIPCHK(launch(KID_CONTROL, k_control, 1u, 64u, ctl, d_grp, nf, d_st));
+                  (const R *)a_c[2], d_st, pesc));
+    HIPCHK(launch(KID_CONTROL, k_control, 1u, BLOCK, ctl, d_grp, nf, d_st,
+                  (const unsigned long long *)pcount, (const unsigned long long *)pesc, nblk));
     return SPH_OK;
   }
 
@@ -554,7 +565,12 @@ extern "C" sph_status sph_mesh_create(const sph_geometry *g, const sph_sizing *s
   M->d_rel = dalloc<int8_t>((size_t)nf * nf, ow, by);
   M->d_grp = dalloc<Group>(nf, ow, by);
   M->d_st = dalloc<Status>(1, ow, by);
-  ok = ok && M->cell && M->rank && M->psrc && M->pkey && M->cnt && M->cstart && M->aux &&
+  M->nblk = (int)((N + BLOCK - 1) / BLOCK);
+  M->pmin = dalloc<unsigned long long>((size_t)std::max(M->nblk, 1) * nf, ow, by);
+  M->psum = dalloc<unsigned long long>((size_t)std::max(M->nblk, 1) * nf, ow, by);
+  M->pcount = dalloc<unsigned long long>(std::max(M->nblk, 1), ow, by);
+  M->pesc = dalloc<unsigned long long>(std::max(M->nblk, 1), ow, by);
+  ok = ok && M->pmin && M->psum && M->pcount && M->pesc && M->cell && M->rank && M->psrc && M->pkey && M->cnt && M->cstart && M->aux &&
        M->total && M->nbr && M->nnb && M->d_feat && M->d_bn && M->d_rel && M->d_grp && M->d_st;
   if (!ok) {
     delete M;
