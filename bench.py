@@ -32,24 +32,23 @@ HBM_PEAK_GBS = 8000.0
 
 
 def kernel_bytes(name, wl, n_active, inter, real_bytes):
-    """Algorithmic HBM bytes of one launch: every particle column read or
-    written once, the neighbour list read or written once; gathers of
-    neighbour data are cache traffic and not counted."""
-    D = wl.dim
+    """Algorithmic HBM bytes of one launch: every particle record or column
+    read or written once, the neighbour list written or read once; gathers of
+    neighbour records are cache traffic and not counted."""
     N = wl.n
-    x = 8 * D
-    if name == "neighbors":
-        return N * (x + 8 + 1) + N * 4 + inter * 4 + N * 4
-    if name == "sweep_a":
-        return n_active * (x + x + 8 + 1 + 4) + inter * 4 + n_active * D * real_bytes
+    r4 = 4 * real_bytes                       # {ax, ay, az, 0} record
+    if name == "nbr_forces":
+        return N * 33 + n_active * (32 + 4 + r4) + inter * 4
+    if name == "nbr_lists":
+        return N * 33 + N * 4 + inter * 4
     if name == "sweep_b":
-        return n_active * (x + x + 8 + 1 + 4 + D * real_bytes) + inter * 4 + n_active * D * real_bytes
-    if name == "integrate":
-        return n_active * (1 + x + x + D * real_bytes) + n_active * (x + x)
-    if name == "gather":
-        return N * 4 + 2 * N * (x + x + 8 + 1 + 4)
-    if name == "hash_count":
-        return N * (x + 8 + 4 + 4)
+        return n_active * (32 + 32 + r4 + 1 + 4 + r4) + inter * 4
+    if name == "integrate_hash":
+        return N * (64 + 1 + 8) + n_active * (64 + r4)
+    if name == "rank_gather":
+        return N * 158
+    if name == "scatter":
+        return N * 24
     return None
 
 

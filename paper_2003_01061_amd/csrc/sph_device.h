@@ -1,12 +1,15 @@
 // sph_device.h -- device-side data layout and math of the feature-aware SPH
 // relaxation step for gfx950 (CDNA4, wave64).
 //
-// Layout in HBM: particles are structure-of-arrays in cell order (x, v, h as
-// FP64 columns, the feature index as one byte, the caller's id as u32).  The
-// neighbour list is ELL, entry e of slot i at nbr[e * n + i], so the 64 lanes
-// of a wave reading entry e touch 256 consecutive bytes.  The top bit of an
-// entry marks a boundary neighbour (a lower-dimensional feature bounding the
-// particle's own, paper sec. 3.3), the low 31 bits are the slot.
+// Layout in HBM: particles sit in cell order as packed 32-byte records, one
+// array of {x, y, z, h} (FP64, z = 0 in 2D) and one of {vx, vy, vz, 0}
+// (FP64), so a neighbour gather touches one 32-byte sector per record; the
+// feature index is one byte and the caller's id a u32 column.  Accelerations
+// are {ax, ay, az, 0} records in the sweep precision.  The neighbour list is
+// ELL, entry e of slot i at nbr[e * n + i], so the 64 lanes of a wave reading
+// entry e touch 256 consecutive bytes.  The top bit of an entry marks a
+// boundary neighbour (a lower-dimensional feature bounding the particle's
+// own, paper sec. 3.3), the low 31 bits are the slot.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -17,6 +20,15 @@ constexpr int MAXF = 64;        // features per job
 constexpr int MAXH = 16;        // holes per job
 constexpr int MAXRING = 64;     // samples per averaging window
 constexpr int BLOCK = 256;
+
+// tuning knobs (compile time): records loaded together per neighbour batch,
+// and whether blocks are remapped so that each XCD gets a contiguous range
+#ifndef SPH_NBATCH
+#define SPH_NBATCH 4
+#endif
+#ifndef SPH_XCD_REMAP
+#define SPH_XCD_REMAP 1
+#endif
 
 enum : int { T_SI = 0, T_C = 1, T_S = 2, T_V = 3 };
 enum : int { K_VOL = 0, K_BOXSIDE = 1, K_HOLE = 2, K_EDGE3 = 3, K_CORNER = 4 };
@@ -73,15 +85,26 @@ struct Group {
 struct Status {
   unsigned long long escaped, inter_total, inter_last, inter_step, steps;
   unsigned int nan_flag, nan_oid, overflow, overflow_max;
-  int32_t converged, pad;
+  int32_t converged;
+  unsigned int scan_fail;     // a scan tile gave up waiting (never expected)
 };
 
 struct Parts {
-  double *x[3];
-  double *v[3];
-  double *h;
+  double4 *xh;      // x, y, z, h
+  double4 *v;       // vx, vy, vz, 0
   uint8_t *f;
   uint32_t *oid;
+};
+
+template <typename R>
+struct Vec4;
+template <>
+struct Vec4<float> {
+  using T = float4;
+};
+template <>
+struct Vec4<double> {
+  using T = double4;
 };
 
 // ---------------------------------------------------------------------------
@@ -118,19 +141,30 @@ __device__ __forceinline__ double h_target(const Geom &g, const double *p) {
 
 // |x_i - x_j|^2 < 4 max(h_i, h_j)^2 evaluated exactly as specified
 template <int D>
-__device__ __forceinline__ bool within(const double *xi, double xj0, double xj1, double xj2,
-                                       double hi, double hj) {
+__device__ __forceinline__ bool within(const double4 &a, const double4 &b) {
 #pragma clang fp contract(off)
-  double d = xi[0] - xj0;
+  double d = a.x - b.x;
   double s = d * d;
-  d = xi[1] - xj1;
+  d = a.y - b.y;
   s = s + d * d;
   if (D == 3) {
-    d = xi[2] - xj2;
+    d = a.z - b.z;
     s = s + d * d;
   }
-  double m = hi > hj ? hi : hj;
+  double m = a.w > b.w ? a.w : b.w;
   return s < 4.0 * (m * m);
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs; map them so that
+// each XCD (and its L2) works on one contiguous stretch of the cell-ordered
+// particles.  gridDim.x is a multiple of 8.
+__device__ __forceinline__ int xcd_block() {
+#if SPH_XCD_REMAP
+  const int per = (int)(gridDim.x >> 3);
+  return (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+#else
+  return (int)blockIdx.x;
+#endif
 }
 
 __device__ __forceinline__ int cell_coord(const Grid &G, int a, double p) {

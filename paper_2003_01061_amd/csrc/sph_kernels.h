@@ -1,31 +1,35 @@
 // sph_kernels.h -- the gfx950 kernels of one relaxation step.
 //
-// Per step (Algorithm 1's loop body, every feature at once, all reading x^n):
-//   k_hash_count   h_i = h_t(x_i), cell of x_i, rank inside the cell (atomic)
-//   k_scan_*       exclusive scan of the cell counts -> cell start table
-//   k_scatter      slot of every particle in cell order
-//   k_cellsort     order inside a cell by caller id (canonical, history free)
-//   k_gather       permute the particle columns into the new order
-//   k_neighbors    ELL neighbour list: exact FP64 predicate + feature relation
-//   k_sweep_a      Shepard gamma, V~, pressure force with the boundary term,
-//                  tangent projection -> a^p; group min of dt_1, sum of V~
-//   k_sweep_b      mid-point velocity on the fly, viscous force -> a;
-//                  group min of dt
-//   k_integrate    v_{n+1/2}, x_{n+1}, projection / rejection, v_{n+1}
-//   k_control      E_sys, phases, resets, damping of every feature (1 block)
+// Per step (Algorithm 1's loop body, every feature at once, all reading x^n);
+// h_i = h_t(x_i), the cell of x_i and its rank inside the cell are already
+// known from the previous step's integration (or the set-up hash):
+//   k_scan           single-pass exclusive scan of the cell counts (decoupled
+//                    look-back) -> cell start table
+//   k_scatter        position of every particle in cell order
+//   k_rank_gather    order inside a cell by caller id (canonical, history
+//                    free) and permute the particle records into it
+//   k_nbr_forces     ELL neighbour list (exact FP64 predicate + feature
+//                    relation) fused with the Shepard gamma, V~, pressure
+//                    force with the boundary term and its tangent projection
+//                    -> a^p; per-block minima of dt_1 and sums of V~
+//   k_group_reduce   fold per-block partials per feature (dt_1, V~ sum)
+//   k_sweep_b        mid-point velocity on the fly, viscous force -> a
+//   k_group_reduce   fold per-block minima of dt
+//   k_integrate_hash v_{n+1/2}, x_{n+1}, projection / rejection, v_{n+1},
+//                    then h, cell and rank of every particle for the next step
+//   k_control        E_sys, phases, resets, damping of every feature (1 block)
 #pragma once
 #include "sph_device.h"
 
 namespace sph {
 
-// ---------------------------------------------------------------------------
-// wave-level per-group reductions: lanes of one wave usually share a group;
-// each distinct group among the valid lanes is reduced with xor shuffles and
-// committed by one lane with a device atomic (min of non-negative double bit
-// patterns and integer sums are exact and order independent).
-// ---------------------------------------------------------------------------
 __device__ __forceinline__ unsigned long long umin64(unsigned long long a, unsigned long long b) {
   return a < b ? a : b;
+}
+
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
 }
 
 // Per-group reduction of one block: every wave reduces each distinct group
@@ -70,6 +74,18 @@ __device__ __forceinline__ void block_group_reduce(bool valid, int g, unsigned l
   }
 }
 
+__device__ __forceinline__ void block_count(unsigned long long v, unsigned long long *s_cnt,
+                                            unsigned long long *out) {
+  unsigned long long tot = wave_sum_u64(v);
+  if (__lane_id() == 0) s_cnt[threadIdx.x >> 6] = tot;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long b = 0;
+    for (int w = 0; w < BLOCK / 64; ++w) b += s_cnt[w];
+    out[blockIdx.x] = b;
+  }
+}
+
 // one block per group: fold the per-block partials of group blockIdx.x;
 // which = 0 -> dt_1 and the V~ sum, which = 1 -> dt.  The time step is the
 // minimum of the particle terms and the cap dt_max.
@@ -109,29 +125,60 @@ __global__ __launch_bounds__(BLOCK) void k_group_reduce(const unsigned long long
   }
 }
 
-__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
-}
-
 // ---------------------------------------------------------------------------
 // cell hashing and counting sort
 // ---------------------------------------------------------------------------
 template <int D>
-__global__ __launch_bounds__(BLOCK) void k_hash_count(Geom g, Grid G, Parts s, int n,
-                                                      uint32_t *__restrict__ cell,
-                                                      uint32_t *__restrict__ rank,
-                                                      uint32_t *__restrict__ cnt) {
-  int i = blockIdx.x * BLOCK + threadIdx.x;
-  if (i >= n) return;
-  double p[3] = {s.x[0][i], s.x[1][i], D == 3 ? s.x[2][i] : 0.0};
-  s.h[i] = h_target<D>(g, p);
+__device__ __forceinline__ void hash_one(const Geom &g, const Grid &G, double4 &xh, uint32_t &cell) {
+  double p[3] = {xh.x, xh.y, xh.z};
+  xh.w = h_target<D>(g, p);
   int c0 = cell_coord(G, 0, p[0]);
   int c1 = cell_coord(G, 1, p[1]);
   int c2 = D == 3 ? cell_coord(G, 2, p[2]) : 0;
-  uint32_t c = ((uint32_t)c2 * (uint32_t)G.nc[1] + (uint32_t)c1) * (uint32_t)G.nc[0] + (uint32_t)c0;
-  cell[i] = c;
-  rank[i] = atomicAdd(&cnt[c], 1u);
+  cell = ((uint32_t)c2 * (uint32_t)G.nc[1] + (uint32_t)c1) * (uint32_t)G.nc[0] + (uint32_t)c0;
+}
+
+// Rank of a particle inside its cell.  Lanes of a wave that hold the same
+// cell in consecutive lanes form a run (particles are in cell order, and most
+// stay in their cell from one step to the next); the run's first lane
+// reserves the whole run with one atomic and the others take consecutive
+// ranks, so a wave issues one atomic per distinct run instead of one per
+// particle.  Valid lanes are a prefix of the wave.  Ranks only need to be
+// distinct: k_rank_gather puts each cell in caller-id order afterwards.
+__device__ __forceinline__ uint32_t rank_in_cell(uint32_t c, bool valid, uint32_t *cnt) {
+  const int lane = __lane_id();
+  const uint32_t prev = __shfl_up(c, 1);
+  const bool head = valid && (lane == 0 || prev != c);
+  const unsigned long long heads = __ballot(head);
+  const int nvalid = __popcll(__ballot(valid));
+  const unsigned long long below_eq = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+  const unsigned long long above = heads & ~below_eq;
+  const int next = above ? __ffsll((long long)above) - 1 : 64;
+  uint32_t base = 0;
+  if (head) base = atomicAdd(&cnt[c], (uint32_t)((next < nvalid ? next : nvalid) - lane));
+  const unsigned long long mine = heads & below_eq;
+  const int my_head = mine ? 63 - __clzll((long long)mine) : 0;
+  return __shfl(base, my_head) + (uint32_t)(lane - my_head);
+}
+
+// h, cell and rank inside the cell of every particle (set-up and test paths;
+// a step gets them from k_integrate_hash)
+template <int D>
+__global__ __launch_bounds__(BLOCK) void k_hash(Geom g, Grid G, Parts s, int n,
+                                                uint32_t *__restrict__ cell,
+                                                uint32_t *__restrict__ rank,
+                                                uint32_t *__restrict__ cnt) {
+  const int i = blockIdx.x * BLOCK + threadIdx.x;
+  const bool valid = i < n;
+  uint32_t c = 0;
+  if (valid) {
+    double4 xh = s.xh[i];
+    hash_one<D>(g, G, xh, c);
+    s.xh[i] = xh;
+    cell[i] = c;
+  }
+  const uint32_t r = rank_in_cell(c, valid, cnt);
+  if (valid) rank[i] = r;
 }
 
 constexpr int SCAN_PER = 16;
@@ -157,12 +204,25 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *l
   return pre + x - v;
 }
 
-// out[i] = exclusive prefix of in[] inside its tile; aux[tile] = tile total
-__global__ __launch_bounds__(BLOCK) void k_scan_local(const uint32_t *__restrict__ in,
-                                                      uint32_t *__restrict__ out,
-                                                      uint32_t *__restrict__ aux, uint32_t n) {
+// Single-pass exclusive scan (decoupled look-back).  Tiles take ids from a
+// ticket in dispatch order, so a tile only ever waits for tiles that have
+// already started; each tile publishes {flag, value} in one 64-bit word:
+// flag 1 = tile aggregate, flag 2 = inclusive prefix.  status[] and the
+// ticket are cleared by k_scatter, which runs after the scan has finished.
+__global__ __launch_bounds__(BLOCK) void k_scan(const uint32_t *__restrict__ in,
+                                                uint32_t *__restrict__ out, uint32_t n,
+                                                unsigned long long *status, uint32_t *ticket,
+                                                uint32_t ntiles, Status *st) {
   __shared__ uint32_t lds[BLOCK / 64];
-  size_t base = (size_t)blockIdx.x * SCAN_TILE + (size_t)threadIdx.x * SCAN_PER;
+  __shared__ uint32_t s_tile, s_prefix;
+  if (threadIdx.x == 0) s_tile = atomicAdd(ticket, 1u);
+  __syncthreads();
+  const uint32_t tile = s_tile;
+  if (tile >= ntiles) {            // stale ticket: report, never wait
+    if (threadIdx.x == 0) atomicExch(&st->scan_fail, 1u);
+    return;
+  }
+  const size_t base = (size_t)tile * SCAN_TILE + (size_t)threadIdx.x * SCAN_PER;
   uint32_t v[SCAN_PER];
   uint32_t sum = 0;
 #pragma unroll
@@ -173,46 +233,59 @@ __global__ __launch_bounds__(BLOCK) void k_scan_local(const uint32_t *__restrict
   }
   uint32_t tot;
   uint32_t ex = block_exclusive_scan(sum, lds, tot);
+  if (threadIdx.x < 64) {
+    // publish the tile aggregate, then look back with the whole wave: lane l
+    // reads tile (base - l); tiles before 0 count as an inclusive prefix 0.
+    // Predecessors took their tickets earlier and publish without waiting on
+    // later tiles, so the loop ends; the spin bound only turns a broken
+    // invariant into an error instead of a hang.
+    const int lane = threadIdx.x;
+    if (lane == 0)
+      __hip_atomic_store(&status[tile], ((tile == 0 ? 2ull : 1ull) << 32) | tot, __ATOMIC_RELEASE,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t prefix = 0;
+    int base = (int)tile - 1;
+    unsigned spins = 0;
+    while (base >= 0) {
+      const int p = base - lane;
+      unsigned long long w = p >= 0 ? __hip_atomic_load(&status[p], __ATOMIC_ACQUIRE,
+                                                         __HIP_MEMORY_SCOPE_AGENT)
+                                    : (2ull << 32);
+      const unsigned flag = (unsigned)(w >> 32);
+      const unsigned long long m2 = __ballot(flag == 2u);
+      const unsigned long long m0 = __ballot(flag == 0u);
+      const int first2 = m2 ? __ffsll((long long)m2) - 1 : 64;
+      const unsigned long long upto = first2 >= 63 ? ~0ull : ((2ull << first2) - 1ull);
+      if (m0 & upto) {
+        if (++spins > (1u << 22)) {
+          if (lane == 0) atomicExch(&st->scan_fail, 1u);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+        continue;
+      }
+      unsigned long long part = lane <= first2 ? (unsigned long long)(uint32_t)w : 0ull;
+      part = wave_sum_u64(part);
+      prefix += (uint32_t)part;
+      if (first2 < 64) break;
+      base -= 64;
+    }
+    if (lane == 0) {
+      if (tile != 0)
+        __hip_atomic_store(&status[tile], (2ull << 32) | (uint32_t)(prefix + tot), __ATOMIC_RELEASE,
+                           __HIP_MEMORY_SCOPE_AGENT);
+      s_prefix = prefix;
+      if ((size_t)(tile + 1) * SCAN_TILE >= n) out[n] = prefix + tot;
+    }
+  }
+  __syncthreads();
+  ex += s_prefix;
 #pragma unroll
   for (int k = 0; k < SCAN_PER; ++k) {
     size_t idx = base + k;
     if (idx < n) out[idx] = ex;
     ex += v[k];
   }
-  if (threadIdx.x == 0) aux[blockIdx.x] = tot;
-}
-
-// one block: exclusive scan of the tile totals in place (m <= SCAN_TILE)
-__global__ __launch_bounds__(BLOCK) void k_scan_top(uint32_t *__restrict__ aux, uint32_t m,
-                                                    uint32_t *__restrict__ total_out) {
-  __shared__ uint32_t lds[BLOCK / 64];
-  size_t base = (size_t)threadIdx.x * SCAN_PER;
-  uint32_t v[SCAN_PER];
-  uint32_t sum = 0;
-#pragma unroll
-  for (int k = 0; k < SCAN_PER; ++k) {
-    size_t idx = base + k;
-    v[k] = idx < m ? aux[idx] : 0u;
-    sum += v[k];
-  }
-  uint32_t tot;
-  uint32_t ex = block_exclusive_scan(sum, lds, tot);
-#pragma unroll
-  for (int k = 0; k < SCAN_PER; ++k) {
-    size_t idx = base + k;
-    if (idx < m) aux[idx] = ex;
-    ex += v[k];
-  }
-  if (threadIdx.x == 0) *total_out = tot;
-}
-
-// out[i] += aux[tile of i]; out[n] = grand total
-__global__ __launch_bounds__(BLOCK) void k_scan_add(uint32_t *__restrict__ out,
-                                                    const uint32_t *__restrict__ aux, uint32_t n,
-                                                    const uint32_t *__restrict__ total) {
-  size_t i = (size_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (i < n) out[i] += aux[i / SCAN_TILE];
-  if (i == 0) out[n] = *total;
 }
 
 __global__ __launch_bounds__(BLOCK) void k_scatter(int n, const uint32_t *__restrict__ cell,
@@ -220,8 +293,12 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(int n, const uint32_t *__rest
                                                    const uint32_t *__restrict__ cstart,
                                                    const uint32_t *__restrict__ oid,
                                                    uint32_t *__restrict__ psrc,
-                                                   uint32_t *__restrict__ pkey) {
-  int i = blockIdx.x * BLOCK + threadIdx.x;
+                                                   uint32_t *__restrict__ pkey,
+                                                   unsigned long long *__restrict__ status,
+                                                   uint32_t ntiles, uint32_t *__restrict__ ticket) {
+  const int i = blockIdx.x * BLOCK + threadIdx.x;
+  for (uint32_t t = (uint32_t)i; t < ntiles; t += gridDim.x * BLOCK) status[t] = 0ull;
+  if (i == 0) *ticket = 0u;
   if (i >= n) return;
   uint32_t pos = cstart[cell[i]] + rank[i];
   if (pos >= (uint32_t)n) return;   // counts are consistent by construction
@@ -229,147 +306,77 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(int n, const uint32_t *__rest
   pkey[pos] = oid[i];
 }
 
-// insertion sort of one cell's entries by caller id; clears the cell count
-__global__ __launch_bounds__(BLOCK) void k_cellsort(uint32_t ncell, const uint32_t *__restrict__ cstart,
-                                                    uint32_t *__restrict__ pkey,
-                                                    uint32_t *__restrict__ psrc,
-                                                    uint32_t *__restrict__ cnt) {
-  uint32_t c = blockIdx.x * BLOCK + threadIdx.x;
-  if (c >= ncell) return;
-  uint32_t b = cstart[c], e = cstart[c + 1];
-  cnt[c] = 0u;
-  for (uint32_t i = b + 1; i < e; ++i) {
-    uint32_t key = pkey[i], src = psrc[i];
-    uint32_t j = i;
-    while (j > b && pkey[j - 1] > key) {
-      pkey[j] = pkey[j - 1];
-      psrc[j] = psrc[j - 1];
-      --j;
-    }
-    pkey[j] = key;
-    psrc[j] = src;
-  }
-}
-
-template <int D>
-__global__ __launch_bounds__(BLOCK) void k_gather(int n, const uint32_t *__restrict__ psrc, Parts a,
-                                                  Parts b) {
-  int k = blockIdx.x * BLOCK + threadIdx.x;
-  if (k >= n) return;
-  uint32_t s = psrc[k];
-  if (s >= (uint32_t)n) return;
-#pragma unroll
-  for (int d = 0; d < D; ++d) {
-    b.x[d][k] = a.x[d][s];
-    b.v[d][k] = a.v[d][s];
-  }
-  b.h[k] = a.h[s];
-  b.f[k] = a.f[s];
-  b.oid[k] = a.oid[s];
+// Entry u of a cell (filled in atomic order) finds its rank among the cell's
+// caller ids and copies its particle to that slot; the first entry of a cell
+// clears the cell's count for the next hash.
+__global__ __launch_bounds__(BLOCK) void k_rank_gather(int n, const uint32_t *__restrict__ psrc,
+                                                       const uint32_t *__restrict__ pkey,
+                                                       const uint32_t *__restrict__ cell,
+                                                       const uint32_t *__restrict__ cstart,
+                                                       uint32_t *__restrict__ cnt, Parts a,
+                                                       Parts b) {
+  const int u = blockIdx.x * BLOCK + threadIdx.x;
+  if (u >= n) return;
+  const uint32_t src = psrc[u];
+  if (src >= (uint32_t)n) return;
+  const uint32_t c = cell[src];
+  const uint32_t lo = cstart[c], hi = cstart[c + 1];
+  const uint32_t key = pkey[u];
+  uint32_t r = 0;
+  for (uint32_t v = lo; v < hi; ++v) r += pkey[v] < key ? 1u : 0u;
+  if ((uint32_t)u == lo) cnt[c] = 0u;
+  const uint32_t dst = lo + r;
+  if (dst >= (uint32_t)n) return;
+  b.xh[dst] = a.xh[src];
+  b.v[dst] = a.v[src];
+  b.f[dst] = a.f[src];
+  b.oid[dst] = key;
 }
 
 // ---------------------------------------------------------------------------
-// neighbour list (Algorithm 1 "construct Verlet neighbor list")
+// neighbour list (Algorithm 1 "construct Verlet neighbor list") fused with
+// the Shepard term, particle volume and pressure force with the
+// feature-boundary correction (Eqs. (gamma_disc_renormSPH),
+// (particle_volume), (sph_pressure_force_disc_weighted)), mapped onto the
+// feature.  FORCES = false builds the lists only (test entry point).
 // ---------------------------------------------------------------------------
-template <int D>
-__global__ __launch_bounds__(BLOCK) void k_neighbors(Geom g, Grid G, Parts s, int n,
-                                                     const uint32_t *__restrict__ cstart,
-                                                     const int8_t *__restrict__ rel,
-                                                     const Feat *__restrict__ feat,
-                                                     const Group *__restrict__ grp, int all,
-                                                     uint32_t *__restrict__ nbr,
-                                                     uint32_t *__restrict__ nnb, int cap,
-                                                     Status *st,
-                                                     unsigned long long *__restrict__ pcount) {
-  __shared__ unsigned long long s_cnt[BLOCK / 64];
-  int i = blockIdx.x * BLOCK + threadIdx.x;
-  unsigned long long mine = 0;
-  if (i < n) {
-    int fi = s.f[i];
-    bool want = feat[fi].type != T_SI && (all || grp[fi].active);
-    uint32_t count = 0;
-    if (want) {
-      double xi[3] = {s.x[0][i], s.x[1][i], D == 3 ? s.x[2][i] : 0.0};
-      double hi = s.h[i];
-      double R = G.rfac * hi;
-      R = R < G.rmax ? R : G.rmax;
-      int lo_c[3] = {0, 0, 0}, hi_c[3] = {0, 0, 0};
-#pragma unroll
-      for (int a = 0; a < D; ++a) {
-        lo_c[a] = cell_coord(G, a, xi[a] - R);
-        hi_c[a] = cell_coord(G, a, xi[a] + R);
-      }
-      const int8_t *relrow = rel + fi * g.nf;
-      for (int cz = lo_c[2]; cz <= hi_c[2]; ++cz)
-        for (int cy = lo_c[1]; cy <= hi_c[1]; ++cy) {
-          uint32_t row = ((uint32_t)cz * (uint32_t)G.nc[1] + (uint32_t)cy) * (uint32_t)G.nc[0];
-          uint32_t jb = cstart[row + lo_c[0]], je = cstart[row + hi_c[0] + 1];
-          for (uint32_t j = jb; j < je; ++j) {
-            if ((int)j == i) continue;
-            double xj2 = D == 3 ? s.x[2][j] : 0.0;
-            if (!within<D>(xi, s.x[0][j], s.x[1][j], xj2, hi, s.h[j])) continue;
-            int r = relrow[s.f[j]];
-            if (!r) continue;
-            if ((int)count < cap) nbr[(size_t)count * n + i] = j | (r == 2 ? 0x80000000u : 0u);
-            ++count;
-          }
-        }
-      if ((int)count > cap) {
-        atomicMax(&st->overflow_max, count);
-        atomicExch(&st->overflow, 1u);
-        count = cap;
-      }
-    }
-    nnb[i] = count;
-    mine = count;
-  }
-  if (pcount) {
-    unsigned long long tot = wave_sum_u64(mine);
-    if (__lane_id() == 0) s_cnt[threadIdx.x >> 6] = tot;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      unsigned long long b = 0;
-      for (int w = 0; w < BLOCK / 64; ++w) b += s_cnt[w];
-      pcount[blockIdx.x] = b;
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// sweep A: Shepard term, particle volume, pressure force with the
-// feature-boundary correction, mapped onto the feature
-// ---------------------------------------------------------------------------
-template <int D, typename R>
-__global__ __launch_bounds__(BLOCK) void k_sweep_a(Geom g, double p0, int bw, Parts s, int n,
-                                                   const uint32_t *__restrict__ nbr,
-                                                   const uint32_t *__restrict__ nnb,
-                                                   const Feat *__restrict__ feat,
-                                                   const BNorm *__restrict__ bn, Group *grp,
-                                                   R *__restrict__ ap0, R *__restrict__ ap1,
-                                                   R *__restrict__ ap2, double *__restrict__ dbg_gam,
-                                                   double *__restrict__ dbg_vt,
-                                                   unsigned long long *__restrict__ pmin,
-                                                   unsigned long long *__restrict__ psum) {
-  __shared__ unsigned long long s_min[MAXF], s_sum[MAXF];
-  int i = blockIdx.x * BLOCK + threadIdx.x;
+template <int D, typename R, bool FORCES>
+__global__ __launch_bounds__(BLOCK) void k_nbr_forces(
+    Geom g, Grid G, double p0, int bw, Parts s, int n, const uint32_t *__restrict__ cstart,
+    const unsigned long long *__restrict__ bmask, const Feat *__restrict__ feat,
+    const BNorm *__restrict__ bn,
+    const Group *__restrict__ grp, int all, uint32_t *__restrict__ nbr, uint32_t *__restrict__ nnb,
+    int cap, Status *st, typename Vec4<R>::T *__restrict__ ap, double *__restrict__ dbg_gam,
+    double *__restrict__ dbg_vt, unsigned long long *__restrict__ pmin,
+    unsigned long long *__restrict__ psum, unsigned long long *__restrict__ pcount) {
+  using R4 = typename Vec4<R>::T;
+  __shared__ unsigned long long s_min[MAXF], s_sum[MAXF], s_cnt[BLOCK / 64];
+  const int i = xcd_block() * BLOCK + threadIdx.x;
   bool act = false;
   int fi = 0;
-  unsigned long long dtb = ~0ull, vfix = 0ull;
+  unsigned long long dtb = ~0ull, vfix = 0ull, mine = 0ull;
   if (i < n) {
     fi = s.f[i];
     const Feat F = feat[fi];
-    act = F.type != T_SI && grp[fi].active;
-    if (act) {
+    const bool moving = F.type != T_SI && grp[fi].active;
+    const bool want = F.type != T_SI && (all || grp[fi].active);
+    act = FORCES && moving;
+    uint32_t count = 0;
+    if (want) {
+      const double4 xi = s.xh[i];
       const int k = F.k;
-      double xi[3] = {s.x[0][i], s.x[1][i], D == 3 ? s.x[2][i] : 0.0};
-      double vi[3] = {s.v[0][i], s.v[1][i], D == 3 ? s.v[2][i] : 0.0};
-      if (grp[fi].reset_now) {
-        vi[0] = vi[1] = vi[2] = 0.0;
-#pragma unroll
-        for (int a = 0; a < D; ++a) s.v[a][i] = 0.0;
+      double vi[3] = {0.0, 0.0, 0.0};
+      if (act) {
+        const double4 v4 = s.v[i];
+        if (grp[fi].reset_now) {
+          s.v[i] = make_double4(0.0, 0.0, 0.0, 0.0);
+        } else {
+          vi[0] = v4.x;
+          vi[1] = v4.y;
+          vi[2] = v4.z;
+        }
       }
-      const double hid = s.h[i];
-      const R hi = (R)hid;
+      const R hi = (R)xi.w;
       const R ihi = rcp_(hi);
       const R alpha = kalpha<R>(k);
       const R hik = powk(hi, k), hi2k = hik * hik;
@@ -384,84 +391,135 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_a(Geom g, double p0, int bw, Pa
         Pi[a].init(R(0));
         B[a].init(R(0));
       }
-      const uint32_t cnt = nnb[i];
-      for (uint32_t e = 0; e < cnt; ++e) {
-        const uint32_t u = nbr[(size_t)e * n + i];
-        const uint32_t j = u & 0x7fffffffu;
-        R dx[3];
-        dx[0] = (R)(xi[0] - s.x[0][j]);
-        dx[1] = (R)(xi[1] - s.x[1][j]);
-        dx[2] = D == 3 ? (R)(xi[2] - s.x[2][j]) : R(0);
-        const R r = sqrt_(dx[0] * dx[0] + dx[1] * dx[1] + dx[2] * dx[2]);
-        const R hj = (R)s.h[j];
-        const R hjk = powk(hj, k), hj2k = hjk * hjk;
-        const R ihij = rcp_(R(0.5) * (hi + hj));
-        const R qij = r * ihij;
-        if (!(u >> 31)) {
-          const R w = alpha * wshape(k, r * ihi) * ihik;           // W(r, h_i)
-          S.add(w);
-          gam.add(w * hjk);
-          const R ih2 = ihij * ihij;
-          const R ihk2 = k == 1 ? ih2 * ihij : (k == 2 ? ih2 * ih2 : ih2 * ih2 * ihij);
-          const R c = P0 * (hi2k + hj2k) * alpha * dwq(k, qij) * ihk2;   // (dW/dr)/r at h_ij
+      double Rs = G.rfac * xi.w;
+      Rs = Rs < G.rmax ? Rs : G.rmax;
+      const double pc[3] = {xi.x, xi.y, xi.z};
+      int lo_c[3] = {0, 0, 0}, hi_c[3] = {0, 0, 0};
 #pragma unroll
-          for (int a = 0; a < D; ++a) Pi[a].add(c * dx[a]);
-        } else {
-          const int fb = s.f[j];
-          const BNorm N = bn[fi * g.nf + fb];
-          double nv[3];
-          if (N.mode == 2) {
-            const double *cc = g.hc[N.hole];
-            double d0 = cc[0] - s.x[0][j], d1 = cc[1] - s.x[1][j];
-            double d2 = D == 3 ? cc[2] - s.x[2][j] : 0.0;
-            double il = 1.0 / __builtin_sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-            nv[0] = d0 * il;
-            nv[1] = d1 * il;
-            nv[2] = d2 * il;
-          } else {
-            nv[0] = N.n[0];
-            nv[1] = N.n[1];
-            nv[2] = N.n[2];
+      for (int a = 0; a < D; ++a) {
+        lo_c[a] = cell_coord(G, a, pc[a] - Rs);
+        hi_c[a] = cell_coord(G, a, pc[a] + Rs);
+      }
+      // features that bound fi (bit f set); a candidate of fi's own feature
+      // interacts as "same", one of a bounding feature as "boundary"
+      const unsigned long long bm = bmask[fi];
+      constexpr int NB = SPH_NBATCH;   // candidates whose records are loaded together
+      for (int cz = lo_c[2]; cz <= hi_c[2]; ++cz)
+        for (int cy = lo_c[1]; cy <= hi_c[1]; ++cy) {
+          const uint32_t row = ((uint32_t)cz * (uint32_t)G.nc[1] + (uint32_t)cy) * (uint32_t)G.nc[0];
+          const uint32_t jb = cstart[row + lo_c[0]], je = cstart[row + hi_c[0] + 1];
+          for (uint32_t j0 = jb; j0 < je; j0 += NB) {
+            double4 xr[NB];
+            int fr[NB];
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+              const uint32_t j = j0 + q < je ? j0 + q : je - 1;
+              xr[q] = s.xh[j];
+              fr[q] = s.f[j];
+            }
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+              const uint32_t j = j0 + q;
+              if (j >= je || (int)j == i) continue;
+              const double4 xj = xr[q];
+              if (!within<D>(xi, xj)) continue;
+              const int fj = fr[q];
+              const int r = fj == fi ? 1 : (int)((bm >> fj) & 1ull) * 2;
+              if (!r) continue;
+              if ((int)count < cap) nbr[(size_t)count * n + i] = j | (r == 2 ? 0x80000000u : 0u);
+              ++count;
+              if (FORCES && act) {
+                const R dx0 = (R)(xi.x - xj.x), dx1 = (R)(xi.y - xj.y);
+                const R dx2 = D == 3 ? (R)(xi.z - xj.z) : R(0);
+                const R rr = sqrt_(dx0 * dx0 + dx1 * dx1 + dx2 * dx2);
+                const R hj = (R)xj.w;
+                const R hjk = powk(hj, k), hj2k = hjk * hjk;
+                const R ihij = rcp_(R(0.5) * (hi + hj));
+                const R qij = rr * ihij;
+                if (r == 1) {
+                  const R w = alpha * wshape(k, rr * ihi) * ihik;   // W(r, h_i)
+                  S.add(w);
+                  gam.add(w * hjk);
+                  const R ih2 = ihij * ihij;
+                  const R ihk2 = k == 1 ? ih2 * ihij : (k == 2 ? ih2 * ih2 : ih2 * ih2 * ihij);
+                  const R c = P0 * (hi2k + hj2k) * alpha * dwq(k, qij) * ihk2;   // (dW/dr)/r, h_ij
+                  Pi[0].add(c * dx0);
+                  Pi[1].add(c * dx1);
+                  if (D == 3) Pi[2].add(c * dx2);
+                } else {
+                  const BNorm N = bn[fi * g.nf + fj];
+                  double nv[3];
+                  if (N.mode == 2) {
+                    const double *cc = g.hc[N.hole];
+                    const double d0 = cc[0] - xj.x, d1 = cc[1] - xj.y;
+                    const double d2 = D == 3 ? cc[2] - xj.z : 0.0;
+                    const double il = 1.0 / __builtin_sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+                    nv[0] = d0 * il;
+                    nv[1] = d1 * il;
+                    nv[2] = d2 * il;
+                  } else {
+                    nv[0] = N.n[0];
+                    nv[1] = N.n[1];
+                    nv[2] = N.n[2];
+                  }
+                  const R om = bw == 0 ? rcp_(hj) : (bw == 1 ? powk(hj, k) * rcp_(hj) : R(0));
+                  const R w = alpha * wshape(k, qij) * powk(ihij, k);    // W(r, h_ib)
+                  const R c = P0 * (hi2k + hj2k) * w * om;
+                  B[0].add(c * (R)nv[0]);
+                  B[1].add(c * (R)nv[1]);
+                  if (D == 3) B[2].add(c * (R)nv[2]);
+                }
+              }
+            }
           }
-          const R om = bw == 0 ? rcp_(hj) : (bw == 1 ? powk(hj, k) * rcp_(hj) : R(0));
-          const R w = alpha * wshape(k, qij) * powk(ihij, k);      // W(r, h_ib)
-          const R c = P0 * (hi2k + hj2k) * w * om;
-#pragma unroll
-          for (int a = 0; a < D; ++a) B[a].add(c * (R)nv[a]);
         }
+      if ((int)count > cap) {
+        atomicMax(&st->overflow_max, count);
+        atomicExch(&st->overflow, 1u);
+        count = cap;
       }
-      const double gm = (double)gam.get();
-      double ap[3] = {0.0, 0.0, 0.0};
+      if (FORCES && act) {
+        const double gm = (double)gam.get();
+        double a3[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-      for (int a = 0; a < D; ++a) ap[a] = -(((double)Pi[a].get() + (double)B[a].get()) / gm);
-      tangent<D>(g, F, xi, ap);
-      ap0[i] = (R)ap[0];
-      ap1[i] = (R)ap[1];
-      if (D == 3) ap2[i] = (R)ap[2];
-      const double vt = 1.0 / (double)S.get();
-      if (dbg_gam) dbg_gam[i] = gm;
-      if (dbg_vt) dbg_vt[i] = vt;
-      // Eq. (fa_time_step_size) terms from a^p and v^n
-      const double rc = 2.0 * hid;
-      double dt = __builtin_inf();
-      double am = __builtin_sqrt(ap[0] * ap[0] + ap[1] * ap[1] + ap[2] * ap[2]);
-      if (am > 0.0) dt = 0.25 * __builtin_sqrt(rc / am);
-      double vm = __builtin_sqrt(vi[0] * vi[0] + vi[1] * vi[1] + vi[2] * vi[2]);
-      if (vm > 0.0) {
-        double t = rc / (40.0 * vm);
-        dt = t < dt ? t : dt;
+        for (int a = 0; a < D; ++a) a3[a] = -(((double)Pi[a].get() + (double)B[a].get()) / gm);
+        double xa[3] = {xi.x, xi.y, xi.z};
+        tangent<D>(g, F, xa, a3);
+        R4 o;
+        o.x = (R)a3[0];
+        o.y = (R)a3[1];
+        o.z = (R)a3[2];
+        o.w = R(0);
+        ap[i] = o;
+        const double vt = 1.0 / (double)S.get();
+        if (dbg_gam) dbg_gam[i] = gm;
+        if (dbg_vt) dbg_vt[i] = vt;
+        // Eq. (fa_time_step_size) terms from a^p and v^n
+        const double rc = 2.0 * xi.w;
+        double dt = __builtin_inf();
+        const double am = __builtin_sqrt(a3[0] * a3[0] + a3[1] * a3[1] + a3[2] * a3[2]);
+        if (am > 0.0) dt = 0.25 * __builtin_sqrt(rc / am);
+        const double vm = __builtin_sqrt(vi[0] * vi[0] + vi[1] * vi[1] + vi[2] * vi[2]);
+        if (vm > 0.0) {
+          const double t = rc / (40.0 * vm);
+          dt = t < dt ? t : dt;
+        }
+        dtb = dbits(dt);
+        vfix = (unsigned long long)__builtin_llrint(vt * grp[fi].vscale);
       }
-      dtb = dbits(dt);
-      vfix = (unsigned long long)__builtin_llrint(vt * grp[fi].vscale);
-    } else {
-      ap0[i] = R(0);
-      ap1[i] = R(0);
-      if (D == 3) ap2[i] = R(0);
+    }
+    if (FORCES && !act) {
+      R4 z;
+      z.x = z.y = z.z = z.w = R(0);
+      ap[i] = z;
       if (dbg_gam) dbg_gam[i] = 0.0;
       if (dbg_vt) dbg_vt[i] = 0.0;
     }
+    nnb[i] = count;
+    mine = count;
   }
-  block_group_reduce(act, fi, dtb, vfix, s_min, s_sum, g.nf, pmin, psum);
+  if (FORCES) block_group_reduce(act, fi, dtb, vfix, s_min, s_sum, g.nf, pmin, psum);
+  if (pcount) block_count(mine, s_cnt, pcount);
 }
 
 // ---------------------------------------------------------------------------
@@ -471,17 +529,15 @@ template <int D, typename R>
 __global__ __launch_bounds__(BLOCK) void k_sweep_b(Geom g, Parts s, int n,
                                                    const uint32_t *__restrict__ nbr,
                                                    const uint32_t *__restrict__ nnb,
-                                                   const Feat *__restrict__ feat, Group *grp,
-                                                   const R *__restrict__ ap0,
-                                                   const R *__restrict__ ap1,
-                                                   const R *__restrict__ ap2, R *__restrict__ a0,
-                                                   R *__restrict__ a1, R *__restrict__ a2,
-                                                   double *__restrict__ dbg_vm0,
-                                                   double *__restrict__ dbg_vm1,
-                                                   double *__restrict__ dbg_vm2,
+                                                   const Feat *__restrict__ feat,
+                                                   const Group *__restrict__ grp,
+                                                   const typename Vec4<R>::T *__restrict__ ap,
+                                                   typename Vec4<R>::T *__restrict__ acc,
+                                                   double4 *__restrict__ dbg_vm,
                                                    unsigned long long *__restrict__ pmin) {
+  using R4 = typename Vec4<R>::T;
   __shared__ unsigned long long s_min[MAXF], s_sum[MAXF];
-  int i = blockIdx.x * BLOCK + threadIdx.x;
+  const int i = xcd_block() * BLOCK + threadIdx.x;
   bool act = false;
   int fi = 0;
   unsigned long long dtb = ~0ull;
@@ -493,147 +549,156 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_b(Geom g, Parts s, int n,
       const int k = F.k;
       const double dt1 = bitsd(grp[fi].dt1_bits);
       const double half = 0.5 * dt1;
-      double xi[3] = {s.x[0][i], s.x[1][i], D == 3 ? s.x[2][i] : 0.0};
-      double vi[3] = {s.v[0][i], s.v[1][i], D == 3 ? s.v[2][i] : 0.0};
-      double api[3] = {(double)ap0[i], (double)ap1[i], D == 3 ? (double)ap2[i] : 0.0};
+      const double4 xi = s.xh[i];
+      const double4 v4 = s.v[i];
+      const R4 api4 = ap[i];
+      const double vi[3] = {v4.x, v4.y, v4.z};
+      const double api[3] = {(double)api4.x, (double)api4.y, (double)api4.z};
       double vti[3];
 #pragma unroll
       for (int a = 0; a < 3; ++a) vti[a] = vi[a] + half * api[a];
       const double vmi = __builtin_sqrt(vti[0] * vti[0] + vti[1] * vti[1] + vti[2] * vti[2]);
-      const double hid = s.h[i];
+      const double hid = xi.w;
       const R hi = (R)hid;
       const R alpha = kalpha<R>(k);
       const R hik = powk(hi, k), hi2k = hik * hik;
-      const R etai = (R)(0.2 * hid * vmi) * rcp_(hik);            // eta = rho_t nu, nu = 0.1 r_c |v~|
+      const R etai = (R)(0.2 * hid * vmi) * rcp_(hik);   // eta = rho_t nu, nu = 0.1 r_c |v~|
       const R vtiR[3] = {(R)vti[0], (R)vti[1], (R)vti[2]};
       const R halfR = (R)half;
       Acc<R> Fv[3];
 #pragma unroll
       for (int a = 0; a < 3; ++a) Fv[a].init(R(0));
       const uint32_t cnt = nnb[i];
-      for (uint32_t e = 0; e < cnt; ++e) {
-        const uint32_t u = nbr[(size_t)e * n + i];
-        if (u >> 31) continue;
-        const uint32_t j = u;
-        R dx[3];
-        dx[0] = (R)(xi[0] - s.x[0][j]);
-        dx[1] = (R)(xi[1] - s.x[1][j]);
-        dx[2] = D == 3 ? (R)(xi[2] - s.x[2][j]) : R(0);
-        const R r = sqrt_(dx[0] * dx[0] + dx[1] * dx[1] + dx[2] * dx[2]);
-        const R hj = (R)s.h[j];
-        const R hjk = powk(hj, k), hj2k = hjk * hjk;
-        R vtj[3];
-        vtj[0] = (R)s.v[0][j] + halfR * ap0[j];
-        vtj[1] = (R)s.v[1][j] + halfR * ap1[j];
-        vtj[2] = D == 3 ? (R)s.v[2][j] + halfR * ap2[j] : R(0);
-        const R vmj = sqrt_(vtj[0] * vtj[0] + vtj[1] * vtj[1] + vtj[2] * vtj[2]);
-        const R etaj = R(0.2) * hj * vmj * rcp_(hjk);
-        const R es = etai + etaj;
-        const R H = es > R(0) ? R(2) * etai * etaj * rcp_(es) : R(0);
-        const R ihij = rcp_(R(0.5) * (hi + hj));
-        const R ih2 = ihij * ihij;
-        const R ihk2 = k == 1 ? ih2 * ihij : (k == 2 ? ih2 * ih2 : ih2 * ih2 * ihij);
-        const R c = H * (hi2k + hj2k) * alpha * dwq(k, r * ihij) * ihk2;
+      constexpr int NB = SPH_NBATCH;   // neighbours whose records are loaded together
+      for (uint32_t e0 = 0; e0 < cnt; e0 += NB) {
+        uint32_t u[NB];
 #pragma unroll
-        for (int a = 0; a < D; ++a) Fv[a].add(c * (vtiR[a] - vtj[a]));
+        for (int q = 0; q < NB; ++q)
+          u[q] = e0 + q < cnt ? nbr[(size_t)(e0 + q) * n + i] : 0x80000000u;
+        double4 xr[NB], vr[NB];
+        R4 ar[NB];
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+          const uint32_t j = u[q] & 0x7fffffffu;   // boundary entries fetch a valid slot, unused
+          xr[q] = s.xh[j];
+          vr[q] = s.v[j];
+          ar[q] = ap[j];
+        }
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+          if (u[q] >> 31) continue;
+          const double4 xj = xr[q];
+          const double4 vj = vr[q];
+          const R4 apj = ar[q];
+          const R dx0 = (R)(xi.x - xj.x), dx1 = (R)(xi.y - xj.y);
+          const R dx2 = D == 3 ? (R)(xi.z - xj.z) : R(0);
+          const R rr = sqrt_(dx0 * dx0 + dx1 * dx1 + dx2 * dx2);
+          const R hj = (R)xj.w;
+          const R hjk = powk(hj, k), hj2k = hjk * hjk;
+          R vtj[3];
+          vtj[0] = (R)vj.x + halfR * apj.x;
+          vtj[1] = (R)vj.y + halfR * apj.y;
+          vtj[2] = D == 3 ? (R)vj.z + halfR * apj.z : R(0);
+          const R vmj = sqrt_(vtj[0] * vtj[0] + vtj[1] * vtj[1] + vtj[2] * vtj[2]);
+          const R etaj = R(0.2) * hj * vmj * rcp_(hjk);
+          const R es = etai + etaj;
+          const R H = es > R(0) ? R(2) * etai * etaj * rcp_(es) : R(0);
+          const R ihij = rcp_(R(0.5) * (hi + hj));
+          const R ih2 = ihij * ihij;
+          const R ihk2 = k == 1 ? ih2 * ihij : (k == 2 ? ih2 * ih2 : ih2 * ih2 * ihij);
+          const R c = H * (hi2k + hj2k) * alpha * dwq(k, rr * ihij) * ihk2;
+#pragma unroll
+          for (int a = 0; a < D; ++a) Fv[a].add(c * (vtiR[a] - vtj[a]));
+        }
       }
       double fv[3] = {(double)Fv[0].get(), (double)Fv[1].get(), D == 3 ? (double)Fv[2].get() : 0.0};
-      tangent<D>(g, F, xi, fv);
+      double xa[3] = {xi.x, xi.y, xi.z};
+      tangent<D>(g, F, xa, fv);
       const double eps = grp[fi].eps;
-      double acc[3];
+      double a3[3];
 #pragma unroll
-      for (int a = 0; a < 3; ++a) acc[a] = api[a] + fv[a] - eps * vi[a];
-      a0[i] = (R)acc[0];
-      a1[i] = (R)acc[1];
-      if (D == 3) a2[i] = (R)acc[2];
-      if (dbg_vm0) {
-        dbg_vm0[i] = vti[0];
-        dbg_vm1[i] = vti[1];
-        if (D == 3) dbg_vm2[i] = vti[2];
-      }
+      for (int a = 0; a < 3; ++a) a3[a] = api[a] + fv[a] - eps * vi[a];
+      R4 o;
+      o.x = (R)a3[0];
+      o.y = (R)a3[1];
+      o.z = (R)a3[2];
+      o.w = R(0);
+      acc[i] = o;
+      if (dbg_vm) dbg_vm[i] = make_double4(vti[0], vti[1], vti[2], 0.0);
       const double rc = 2.0 * hid;
       double dt = __builtin_inf();
-      const double am = __builtin_sqrt(acc[0] * acc[0] + acc[1] * acc[1] + acc[2] * acc[2]);
+      const double am = __builtin_sqrt(a3[0] * a3[0] + a3[1] * a3[1] + a3[2] * a3[2]);
       if (am > 0.0) dt = 0.25 * __builtin_sqrt(rc / am);
       if (vmi > 0.0) {
-        double t = rc / (40.0 * vmi);
+        const double t = rc / (40.0 * vmi);
         dt = t < dt ? t : dt;
       }
       dtb = dbits(dt);
     } else {
-      a0[i] = R(0);
-      a1[i] = R(0);
-      if (D == 3) a2[i] = R(0);
-      if (dbg_vm0) {
-        dbg_vm0[i] = 0.0;
-        dbg_vm1[i] = 0.0;
-        if (D == 3) dbg_vm2[i] = 0.0;
-      }
+      R4 z;
+      z.x = z.y = z.z = z.w = R(0);
+      acc[i] = z;
+      if (dbg_vm) dbg_vm[i] = make_double4(0.0, 0.0, 0.0, 0.0);
     }
   }
   block_group_reduce(act, fi, dtb, 0ull, s_min, s_sum, g.nf, pmin, nullptr);
 }
 
 // ---------------------------------------------------------------------------
-// integration with feature projection (FP64 in every precision mode)
+// integration with feature projection (FP64 in every precision mode), then
+// h, cell and rank of every particle for the next step's sort
 // ---------------------------------------------------------------------------
 template <int D, typename R>
-__global__ __launch_bounds__(BLOCK) void k_integrate(Geom g, Parts s, int n,
-                                                     const Feat *__restrict__ feat,
-                                                     const Group *__restrict__ grp,
-                                                     const R *__restrict__ a0,
-                                                     const R *__restrict__ a1,
-                                                     const R *__restrict__ a2, Status *st,
-                                                     unsigned long long *__restrict__ pesc) {
+__global__ __launch_bounds__(BLOCK) void k_integrate_hash(
+    Geom g, Grid G, Parts s, int n, const Feat *__restrict__ feat, const Group *__restrict__ grp,
+    const typename Vec4<R>::T *__restrict__ acc, Status *st, unsigned long long *__restrict__ pesc,
+    uint32_t *__restrict__ cell, uint32_t *__restrict__ rank, uint32_t *__restrict__ cnt) {
   __shared__ unsigned long long s_esc[BLOCK / 64];
-  int i = blockIdx.x * BLOCK + threadIdx.x;
+  const int i = blockIdx.x * BLOCK + threadIdx.x;
   bool escaped = false;
+  uint32_t cc = 0;
   if (i < n) {
     const int fi = s.f[i];
     const Feat F = feat[fi];
+    double4 xh = s.xh[i];
     if (F.type != T_SI && grp[fi].active) {
       const double dt = bitsd(grp[fi].dt_bits);
-      double acc[3] = {(double)a0[i], (double)a1[i], D == 3 ? (double)a2[i] : 0.0};
-      double x[3] = {s.x[0][i], s.x[1][i], D == 3 ? s.x[2][i] : 0.0};
-      double v[3] = {s.v[0][i], s.v[1][i], D == 3 ? s.v[2][i] : 0.0};
-      double vh[3], xs[3] = {0.0, 0.0, 0.0};
+      const auto a4 = acc[i];
+      const double4 v4 = s.v[i];
+      const double a3[3] = {(double)a4.x, (double)a4.y, (double)a4.z};
+      const double x[3] = {xh.x, xh.y, xh.z};
+      const double v[3] = {v4.x, v4.y, v4.z};
+      double vh[3] = {0.0, 0.0, 0.0}, xs[3] = {0.0, 0.0, 0.0};
       bool finite = true;
 #pragma unroll
       for (int a = 0; a < D; ++a) {
-        vh[a] = v[a] + 0.5 * dt * acc[a];
+        vh[a] = v[a] + 0.5 * dt * a3[a];
         xs[a] = x[a] + dt * vh[a];
         finite = finite && __builtin_isfinite(xs[a]);
       }
       if (!finite) {
         if (atomicExch(&st->nan_flag, 1u) == 0u) st->nan_oid = s.oid[i];
-      } else if (F.kind == K_VOL) {
-        if (!inside<D>(g, xs)) {
-          escaped = true;
-#pragma unroll
-          for (int a = 0; a < D; ++a) s.v[a][i] = 0.0;
-        } else {
-          double vn[3];
-#pragma unroll
-          for (int a = 0; a < D; ++a) {
-            vn[a] = vh[a] + 0.5 * dt * acc[a];
-            s.x[a][i] = xs[a];
-            s.v[a][i] = vn[a];
-          }
-        }
+      } else if (F.kind == K_VOL && !inside<D>(g, xs)) {
+        escaped = true;                                   // rejected move: stay, stop
+        s.v[i] = make_double4(0.0, 0.0, 0.0, 0.0);
       } else {
-        project<D>(g, F, xs);
+        if (F.kind != K_VOL) project<D>(g, F, xs);
         double vn[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-        for (int a = 0; a < D; ++a) vn[a] = vh[a] + 0.5 * dt * acc[a];
-        tangent<D>(g, F, xs, vn);
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-          s.x[a][i] = xs[a];
-          s.v[a][i] = vn[a];
-        }
+        for (int a = 0; a < D; ++a) vn[a] = vh[a] + 0.5 * dt * a3[a];
+        if (F.kind != K_VOL) tangent<D>(g, F, xs, vn);
+        xh.x = xs[0];
+        xh.y = xs[1];
+        if (D == 3) xh.z = xs[2];
+        s.v[i] = make_double4(vn[0], vn[1], D == 3 ? vn[2] : 0.0, 0.0);
       }
     }
+    hash_one<D>(g, G, xh, cc);
+    s.xh[i] = xh;
+    cell[i] = cc;
   }
+  const uint32_t r = rank_in_cell(cc, i < n, cnt);
+  if (i < n) rank[i] = r;
   unsigned long long m = __ballot(escaped);
   if (__lane_id() == 0) s_esc[threadIdx.x >> 6] = (unsigned long long)__popcll(m);
   __syncthreads();
@@ -649,17 +714,16 @@ __global__ __launch_bounds__(BLOCK) void k_integrate(Geom g, Parts s, int n,
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(BLOCK) void k_control(Ctl P, Group *grp, int nf, Status *st,
                                                    const unsigned long long *__restrict__ pcount,
+                                                   int ncount,
                                                    const unsigned long long *__restrict__ pesc,
-                                                   int nblk) {
+                                                   int nesc) {
   __shared__ int moving;
   __shared__ unsigned long long s_c[BLOCK / 64], s_e[BLOCK / 64];
   const int q = threadIdx.x;
   if (q == 0) moving = 0;
   unsigned long long c = 0, e = 0;
-  for (int b = q; b < nblk; b += BLOCK) {
-    c += pcount[b];
-    e += pesc[b];
-  }
+  for (int b = q; b < ncount; b += BLOCK) c += pcount[b];
+  for (int b = q; b < nesc; b += BLOCK) e += pesc[b];
   c = wave_sum_u64(c);
   e = wave_sum_u64(e);
   if (__lane_id() == 0) {
@@ -668,18 +732,18 @@ __global__ __launch_bounds__(BLOCK) void k_control(Ctl P, Group *grp, int nf, St
   }
   __syncthreads();
   if (q < nf) {
-    Group &G = grp[q];
-    if (G.tracked && G.phase != PH_FROZEN) {
-      const double dt1 = bitsd(G.dt1_bits), dt = bitsd(G.dt_bits);
-      const double vbar = (double)G.vsum / G.vscale;
-      G.dt1 = dt1;
-      G.dt = dt;
-      control_law(P, G, vbar, dt);
+    Group &Gq = grp[q];
+    if (Gq.tracked && Gq.phase != PH_FROZEN) {
+      const double dt1 = bitsd(Gq.dt1_bits), dt = bitsd(Gq.dt_bits);
+      const double vbar = (double)Gq.vsum / Gq.vscale;
+      Gq.dt1 = dt1;
+      Gq.dt = dt;
+      control_law(P, Gq, vbar, dt);
     }
-    G.active = G.tracked && G.phase != PH_FROZEN;
-    G.reset_now = G.reset_next;
-    G.eps = damping(P, G);
-    if (G.active) atomicOr(&moving, 1);
+    Gq.active = Gq.tracked && Gq.phase != PH_FROZEN;
+    Gq.reset_now = Gq.reset_next;
+    Gq.eps = damping(P, Gq);
+    if (Gq.active) atomicOr(&moving, 1);
   }
   __syncthreads();
   if (q == 0) {

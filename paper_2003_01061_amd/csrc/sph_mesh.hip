@@ -44,13 +44,12 @@ sph_status fail(sph_status st, const char *fmt, ...) {
   } while (0)
 
 enum KernelId {
-  KID_HASH = 0, KID_SCAN_LOCAL, KID_SCAN_TOP, KID_SCAN_ADD, KID_SCATTER, KID_CELLSORT,
-  KID_GATHER, KID_NEIGHBORS, KID_SWEEP_A, KID_REDUCE_A, KID_SWEEP_B, KID_REDUCE_B, KID_INTEGRATE,
-  KID_CONTROL, KID_COUNT
+  KID_SCAN = 0, KID_SCATTER, KID_RANK_GATHER, KID_NBR_FORCES, KID_REDUCE_A, KID_SWEEP_B,
+  KID_REDUCE_B, KID_INTEGRATE_HASH, KID_CONTROL, KID_HASH, KID_NBR_LISTS, KID_COUNT
 };
 const char *kKernelNames[KID_COUNT] = {
-    "hash_count", "scan_local", "scan_top", "scan_add", "scatter", "cellsort", "gather",
-    "neighbors", "sweep_a", "reduce_a", "sweep_b", "reduce_b", "integrate", "control"};
+    "scan", "scatter", "rank_gather", "nbr_forces", "reduce_a", "sweep_b", "reduce_b",
+    "integrate_hash", "control", "hash", "nbr_lists"};
 
 // ---------------------------------------------------------------------------
 // features of a box-minus-holes geometry (numbering of sph_mesh.h)
@@ -175,17 +174,21 @@ struct sph_mesh {
   Parts P[2]{};
   int cur = 0;
   uint32_t *cell = nullptr, *rank = nullptr, *psrc = nullptr, *pkey = nullptr;
-  uint32_t *cnt = nullptr, *cstart = nullptr, *aux = nullptr, *total = nullptr;
+  uint32_t *cnt = nullptr, *cstart = nullptr, *ticket = nullptr;
+  unsigned long long *scan_status = nullptr;
   uint32_t *nbr = nullptr, *nnb = nullptr;
-  void *ap[3] = {nullptr, nullptr, nullptr}, *acc[3] = {nullptr, nullptr, nullptr};
-  double *dbg_gam = nullptr, *dbg_vt = nullptr, *dbg_vm[3] = {nullptr, nullptr, nullptr};
+  void *ap = nullptr, *acc = nullptr;              // {ax, ay, az, 0} in the sweep precision
+  double *dbg_gam = nullptr, *dbg_vt = nullptr;
+  double4 *dbg_vm = nullptr;
   Feat *d_feat = nullptr;
   BNorm *d_bn = nullptr;
   int8_t *d_rel = nullptr;
+  unsigned long long *d_bmask = nullptr;   // per feature: bit f set if feature f bounds it
   Group *d_grp = nullptr;
   Status *d_st = nullptr;
   uint32_t nscan_tiles = 0;
   int nblk = 0;                                 // particle blocks of one launch
+  int nblk8 = 0;                                // rounded up to the 8 XCDs
   unsigned long long *pmin = nullptr, *psum = nullptr, *pcount = nullptr, *pesc = nullptr;
   // graph of two steps
   hipGraphExec_t gexec = nullptr;
@@ -237,68 +240,72 @@ struct sph_mesh {
 
   unsigned blocks(size_t count) const { return (unsigned)((count + BLOCK - 1) / BLOCK); }
 
-  void *ap_ptr(int a) const { return ap[a] ? ap[a] : ap[0]; }
-  void *acc_ptr(int a) const { return acc[a] ? acc[a] : acc[0]; }
+  template <int DD>
+  sph_status enqueue_hash() {
+    HIPCHK(launch(KID_HASH, k_hash<DD>, blocks(n), BLOCK, geom, grid, P[cur], n, cell, rank, cnt));
+    return SPH_OK;
+  }
+
+  // counting sort of the current particles into (cell, caller id) order;
+  // needs cell / rank / cnt of the current buffer, leaves cnt cleared
+  sph_status enqueue_sort() {
+    HIPCHK(launch(KID_SCAN, k_scan, nscan_tiles, BLOCK, (const uint32_t *)cnt, cstart, grid.ncell,
+                  scan_status, ticket, nscan_tiles, d_st));
+    HIPCHK(launch(KID_SCATTER, k_scatter, blocks(n), BLOCK, n, (const uint32_t *)cell,
+                  (const uint32_t *)rank, (const uint32_t *)cstart, (const uint32_t *)P[cur].oid,
+                  psrc, pkey, scan_status, nscan_tiles, ticket));
+    HIPCHK(launch(KID_RANK_GATHER, k_rank_gather, blocks(n), BLOCK, n, (const uint32_t *)psrc,
+                  (const uint32_t *)pkey, (const uint32_t *)cell, (const uint32_t *)cstart, cnt,
+                  P[cur], P[1 - cur]));
+    cur = 1 - cur;
+    return SPH_OK;
+  }
 
   template <int DD>
-  sph_status enqueue_rebuild(bool all_lists, bool count_inter) {
-    Parts &src = P[cur];
-    Parts &dst = P[1 - cur];
-    HIPCHK(launch(KID_HASH, k_hash_count<DD>, blocks(n), BLOCK, geom, grid, src, n, cell, rank, cnt));
-    HIPCHK(launch(KID_SCAN_LOCAL, k_scan_local, nscan_tiles, BLOCK, (const uint32_t *)cnt, cstart,
-                  aux, grid.ncell));
-    HIPCHK(launch(KID_SCAN_TOP, k_scan_top, 1u, BLOCK, aux, nscan_tiles, total));
-    HIPCHK(launch(KID_SCAN_ADD, k_scan_add, blocks(grid.ncell), BLOCK, cstart, (const uint32_t *)aux,
-                  grid.ncell, (const uint32_t *)total));
-    HIPCHK(launch(KID_SCATTER, k_scatter, blocks(n), BLOCK, n, (const uint32_t *)cell,
-                  (const uint32_t *)rank, (const uint32_t *)cstart, (const uint32_t *)src.oid, psrc,
-                  pkey));
-    HIPCHK(launch(KID_CELLSORT, k_cellsort, blocks(grid.ncell), BLOCK, grid.ncell,
-                  (const uint32_t *)cstart, pkey, psrc, cnt));
-    HIPCHK(launch(KID_GATHER, k_gather<DD>, blocks(n), BLOCK, n, (const uint32_t *)psrc, src, dst));
-    cur = 1 - cur;
-    HIPCHK(launch(KID_NEIGHBORS, k_neighbors<DD>, blocks(n), BLOCK, geom, grid, P[cur], n,
-                  (const uint32_t *)cstart, (const int8_t *)d_rel, (const Feat *)d_feat,
-                  (const Group *)d_grp, all_lists ? 1 : 0, nbr, nnb, cap, d_st,
-                  count_inter ? pcount : (unsigned long long *)nullptr));
+  sph_status enqueue_lists_only() {
+    HIPCHK(launch(KID_NBR_LISTS, k_nbr_forces<DD, double, false>, (unsigned)nblk8, BLOCK, geom,
+                  grid, p0, bw, P[cur], n, (const uint32_t *)cstart, (const unsigned long long *)d_bmask,
+                  (const Feat *)d_feat, (const BNorm *)d_bn, (const Group *)d_grp, 1, nbr, nnb, cap,
+                  d_st, (double4 *)nullptr, (double *)nullptr, (double *)nullptr,
+                  (unsigned long long *)nullptr, (unsigned long long *)nullptr,
+                  (unsigned long long *)nullptr));
     return SPH_OK;
   }
 
   template <int DD, typename R>
   sph_status enqueue_forces() {
+    using R4 = typename Vec4<R>::T;
     Parts &s = P[cur];
-    R *a_p[3] = {(R *)ap_ptr(0), (R *)ap_ptr(1), (R *)ap_ptr(2)};
-    R *a_c[3] = {(R *)acc_ptr(0), (R *)acc_ptr(1), (R *)acc_ptr(2)};
-    HIPCHK(launch(KID_SWEEP_A, k_sweep_a<DD, R>, blocks(n), BLOCK, geom, p0, bw, s, n,
-                  (const uint32_t *)nbr, (const uint32_t *)nnb, (const Feat *)d_feat,
-                  (const BNorm *)d_bn, d_grp, a_p[0], a_p[1], a_p[2], dbg_gam, dbg_vt, pmin, psum));
+    HIPCHK(launch(KID_NBR_FORCES, k_nbr_forces<DD, R, true>, (unsigned)nblk8, BLOCK, geom, grid, p0,
+                  bw, s, n, (const uint32_t *)cstart, (const unsigned long long *)d_bmask,
+                  (const Feat *)d_feat,
+                  (const BNorm *)d_bn, (const Group *)d_grp, 0, nbr, nnb, cap, d_st, (R4 *)ap,
+                  dbg_gam, dbg_vt, pmin, psum, pcount));
     HIPCHK(launch(KID_REDUCE_A, k_group_reduce, (unsigned)nf, BLOCK,
-                  (const unsigned long long *)pmin, (const unsigned long long *)psum, nblk, nf,
+                  (const unsigned long long *)pmin, (const unsigned long long *)psum, nblk8, nf,
                   ctl.dt_max, d_grp, 0));
-    HIPCHK(launch(KID_SWEEP_B, k_sweep_b<DD, R>, blocks(n), BLOCK, geom, s, n, (const uint32_t *)nbr,
-                  (const uint32_t *)nnb, (const Feat *)d_feat, d_grp, (const R *)a_p[0],
-                  (const R *)a_p[1], (const R *)a_p[2], a_c[0], a_c[1], a_c[2], dbg_vm[0], dbg_vm[1],
-                  dbg_vm[2], pmin));
+    HIPCHK(launch(KID_SWEEP_B, k_sweep_b<DD, R>, (unsigned)nblk8, BLOCK, geom, s, n,
+                  (const uint32_t *)nbr, (const uint32_t *)nnb, (const Feat *)d_feat,
+                  (const Group *)d_grp, (const R4 *)ap, (R4 *)acc, dbg_vm, pmin));
     HIPCHK(launch(KID_REDUCE_B, k_group_reduce, (unsigned)nf, BLOCK,
-                  (const unsigned long long *)pmin, (const unsigned long long *)nullptr, nblk, nf,
+                  (const unsigned long long *)pmin, (const unsigned long long *)nullptr, nblk8, nf,
                   ctl.dt_max, d_grp, 1));
-    HIPCHK(launch(KID_INTEGRATE, k_integrate<DD, R>, blocks(n), BLOCK, geom, s, n,
-                  (const Feat *)d_feat, (const Group *)d_grp, (const R *)a_c[0], (const R *)a_c[1],
-                  (const R *)a_c[2], d_st, pesc));
+    HIPCHK(launch(KID_INTEGRATE_HASH, k_integrate_hash<DD, R>, blocks(n), BLOCK, geom, grid, s, n,
+                  (const Feat *)d_feat, (const Group *)d_grp, (const R4 *)acc, d_st, pesc, cell,
+                  rank, cnt));
     HIPCHK(launch(KID_CONTROL, k_control, 1u, BLOCK, ctl, d_grp, nf, d_st,
-                  (const unsigned long long *)pcount, (const unsigned long long *)pesc, nblk));
+                  (const unsigned long long *)pcount, nblk8, (const unsigned long long *)pesc,
+                  nblk));
     return SPH_OK;
   }
 
   sph_status enqueue_step() {
-    sph_status st;
-    if (D == 2) {
-      if ((st = enqueue_rebuild<2>(false, true))) return st;
-      return prec == SPH_FP64 ? enqueue_forces<2, double>() : enqueue_forces<2, float>();
-    }
-    if ((st = enqueue_rebuild<3>(false, true))) return st;
+    if (sph_status st = enqueue_sort()) return st;
+    if (D == 2) return prec == SPH_FP64 ? enqueue_forces<2, double>() : enqueue_forces<2, float>();
     return prec == SPH_FP64 ? enqueue_forces<3, double>() : enqueue_forces<3, float>();
   }
+
+  sph_status hash_now() { return D == 2 ? enqueue_hash<2>() : enqueue_hash<3>(); }
 
   sph_status build_graph() {
     if (gexec) return SPH_OK;
@@ -327,6 +334,7 @@ struct sph_mesh {
     Status s{};
     HIPCHK(hipMemcpy(&s, d_st, sizeof s, hipMemcpyDeviceToHost));
     if (s.nan_flag) return fail(SPH_ERR_STATE, "non-finite position of particle %u", s.nan_oid);
+    if (s.scan_fail) return fail(SPH_ERR_DEVICE, "cell-count scan lost a tile");
     if (s.overflow)
       return fail(SPH_ERR_STATE, "neighbour list overflow: %u neighbours > capacity %d "
                                  "(raise max_neighbors)", s.overflow_max, cap);
@@ -498,10 +506,6 @@ extern "C" sph_status sph_mesh_create(const sph_geometry *g, const sph_sizing *s
   Gr.rmax = 2.0 * hmax * (1.0 + 1e-9);
   Gr.rfac = 2.0 * lip < 0.9 ? 2.0 * (1.0 + 1e-9) / (1.0 - 2.0 * lip) : 1e300;
   M->nscan_tiles = (Gr.ncell + SCAN_TILE - 1) / SCAN_TILE;
-  if (M->nscan_tiles > (uint32_t)SCAN_TILE) {
-    delete M;
-    return fail(SPH_ERR_UNSUPPORTED, "cell grid too large");
-  }
 
   // stream
   if (p->stream) {
@@ -520,19 +524,11 @@ extern "C" sph_status sph_mesh_create(const sph_geometry *g, const sph_sizing *s
   const size_t N = (size_t)n;
   bool ok = true;
   for (int b = 0; b < 2; ++b) {
-    for (int a = 0; a < 3; ++a) {
-      M->P[b].x[a] = a < D ? dalloc<double>(N, ow, by) : nullptr;
-      M->P[b].v[a] = a < D ? dalloc<double>(N, ow, by) : nullptr;
-      if (a < D) ok = ok && M->P[b].x[a] && M->P[b].v[a];
-    }
-    if (D == 2) {
-      M->P[b].x[2] = M->P[b].x[0];   // never dereferenced in 2D kernels
-      M->P[b].v[2] = M->P[b].v[0];
-    }
-    M->P[b].h = dalloc<double>(N, ow, by);
+    M->P[b].xh = dalloc<double4>(N, ow, by);
+    M->P[b].v = dalloc<double4>(N, ow, by);
     M->P[b].f = dalloc<uint8_t>(N, ow, by);
     M->P[b].oid = dalloc<uint32_t>(N, ow, by);
-    ok = ok && M->P[b].h && M->P[b].f && M->P[b].oid;
+    ok = ok && M->P[b].xh && M->P[b].v && M->P[b].f && M->P[b].oid;
   }
   M->cell = dalloc<uint32_t>(N, ow, by);
   M->rank = dalloc<uint32_t>(N, ow, by);
@@ -540,38 +536,34 @@ extern "C" sph_status sph_mesh_create(const sph_geometry *g, const sph_sizing *s
   M->pkey = dalloc<uint32_t>(N, ow, by);
   M->cnt = dalloc<uint32_t>(Gr.ncell, ow, by);
   M->cstart = dalloc<uint32_t>((size_t)Gr.ncell + 1, ow, by);
-  M->aux = dalloc<uint32_t>(M->nscan_tiles + 1, ow, by);
-  M->total = dalloc<uint32_t>(1, ow, by);
+  M->scan_status = dalloc<unsigned long long>(M->nscan_tiles, ow, by);
+  M->ticket = dalloc<uint32_t>(1, ow, by);
   M->nbr = dalloc<uint32_t>(N * (size_t)M->cap, ow, by);
   M->nnb = dalloc<uint32_t>(N, ow, by);
-  const size_t rsz = M->prec == SPH_FP64 ? 8 : 4;
-  for (int a = 0; a < D; ++a) {
-    M->ap[a] = dalloc<char>(N * rsz, ow, by);
-    M->acc[a] = dalloc<char>(N * rsz, ow, by);
-    ok = ok && M->ap[a] && M->acc[a];
-  }
+  const size_t r4 = M->prec == SPH_FP64 ? sizeof(double4) : sizeof(float4);
+  M->ap = dalloc<char>(N * r4, ow, by);
+  M->acc = dalloc<char>(N * r4, ow, by);
+  ok = ok && M->ap && M->acc;
   if (M->debug) {
     M->dbg_gam = dalloc<double>(N, ow, by);
     M->dbg_vt = dalloc<double>(N, ow, by);
-    for (int a = 0; a < D; ++a) {
-      M->dbg_vm[a] = dalloc<double>(N, ow, by);
-      ok = ok && M->dbg_vm[a];
-    }
-    if (D == 2) M->dbg_vm[2] = M->dbg_vm[0];
-    ok = ok && M->dbg_gam && M->dbg_vt;
+    M->dbg_vm = dalloc<double4>(N, ow, by);
+    ok = ok && M->dbg_gam && M->dbg_vt && M->dbg_vm;
   }
   M->d_feat = dalloc<Feat>(nf, ow, by);
   M->d_bn = dalloc<BNorm>((size_t)nf * nf, ow, by);
   M->d_rel = dalloc<int8_t>((size_t)nf * nf, ow, by);
+  M->d_bmask = dalloc<unsigned long long>(nf, ow, by);
   M->d_grp = dalloc<Group>(nf, ow, by);
   M->d_st = dalloc<Status>(1, ow, by);
   M->nblk = (int)((N + BLOCK - 1) / BLOCK);
-  M->pmin = dalloc<unsigned long long>((size_t)std::max(M->nblk, 1) * nf, ow, by);
-  M->psum = dalloc<unsigned long long>((size_t)std::max(M->nblk, 1) * nf, ow, by);
-  M->pcount = dalloc<unsigned long long>(std::max(M->nblk, 1), ow, by);
+  M->nblk8 = (M->nblk + 7) / 8 * 8;
+  M->pmin = dalloc<unsigned long long>((size_t)std::max(M->nblk8, 1) * nf, ow, by);
+  M->psum = dalloc<unsigned long long>((size_t)std::max(M->nblk8, 1) * nf, ow, by);
+  M->pcount = dalloc<unsigned long long>(std::max(M->nblk8, 1), ow, by);
   M->pesc = dalloc<unsigned long long>(std::max(M->nblk, 1), ow, by);
-  ok = ok && M->pmin && M->psum && M->pcount && M->pesc && M->cell && M->rank && M->psrc && M->pkey && M->cnt && M->cstart && M->aux &&
-       M->total && M->nbr && M->nnb && M->d_feat && M->d_bn && M->d_rel && M->d_grp && M->d_st;
+  ok = ok && M->pmin && M->psum && M->pcount && M->pesc && M->cell && M->rank && M->psrc && M->pkey && M->cnt && M->cstart &&
+       M->scan_status && M->ticket && M->nbr && M->nnb && M->d_feat && M->d_bn && M->d_rel && M->d_bmask && M->d_grp && M->d_st;
   if (!ok) {
     delete M;
     return fail(SPH_ERR_OUT_OF_MEMORY, "device allocation of %zu bytes failed", by);
@@ -581,6 +573,7 @@ extern "C" sph_status sph_mesh_create(const sph_geometry *g, const sph_sizing *s
   std::vector<Feat> hf(nf);
   std::vector<BNorm> hb((size_t)nf * nf);
   std::vector<int8_t> hr((size_t)nf * nf, 0);
+  std::vector<unsigned long long> hm(nf, 0ull);
   for (int i = 0; i < nf; ++i) {
     const HFeat &F = feats[i];
     Feat d{};
@@ -599,6 +592,7 @@ extern "C" sph_status sph_mesh_create(const sph_geometry *g, const sph_sizing *s
     for (int j = 0; j < nf; ++j) {
       hb[(size_t)i * nf + j] = boundary_normal(D, F, feats[j]);
       hr[(size_t)i * nf + j] = i == j ? 1 : (on_boundary_of(F, feats[j]) ? 2 : 0);
+      if (i != j && on_boundary_of(F, feats[j])) hm[i] |= 1ull << j;
     }
   }
   std::vector<int64_t> counts(nf, 0);
@@ -624,33 +618,45 @@ extern "C" sph_status sph_mesh_create(const sph_geometry *g, const sph_sizing *s
     int e = 62 - (int)std::ceil(std::log2(bound * 2.0));
     Q.vscale = std::ldexp(1.0, std::min(e, 1000));
   }
-  // particle columns: caller order, caller ids
-  std::vector<double> col(N);
+  // particle records: caller order, caller ids
+  std::vector<double4> xh(N);
   std::vector<uint32_t> oid(N);
   std::vector<uint8_t> f8(N);
-  hipError_t e = hipSuccess;
-  for (int a = 0; a < D && e == hipSuccess; ++a) {
-    for (size_t i = 0; i < N; ++i) col[i] = xyz[3 * i + a];
-    e = hipMemcpy(M->P[0].x[a], col.data(), N * 8, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemset(M->P[0].v[a], 0, N * 8);
-  }
   for (size_t i = 0; i < N; ++i) {
+    xh[i] = make_double4(xyz[3 * i], xyz[3 * i + 1], D == 3 ? xyz[3 * i + 2] : 0.0, 0.0);
     oid[i] = (uint32_t)i;
     f8[i] = (uint8_t)feature[i];
   }
-  if (e == hipSuccess) e = hipMemcpy(M->P[0].oid, oid.data(), N * 4, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(M->P[0].f, f8.data(), N, hipMemcpyHostToDevice);
+  hipError_t e = hipSuccess;
+  if (N) e = hipMemcpy(M->P[0].xh, xh.data(), N * sizeof(double4), hipMemcpyHostToDevice);
+  if (e == hipSuccess && N) e = hipMemset(M->P[0].v, 0, N * sizeof(double4));
+  if (e == hipSuccess && N) e = hipMemcpy(M->P[0].oid, oid.data(), N * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess && N) e = hipMemcpy(M->P[0].f, f8.data(), N, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(M->d_feat, hf.data(), sizeof(Feat) * nf, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(M->d_bn, hb.data(), sizeof(BNorm) * nf * nf, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(M->d_rel, hr.data(), (size_t)nf * nf, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(M->d_bmask, hm.data(), 8 * nf, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(M->d_grp, hg.data(), sizeof(Group) * nf, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(M->d_st, 0, sizeof(Status));
   if (e == hipSuccess) e = hipMemset(M->cnt, 0, sizeof(uint32_t) * Gr.ncell);
+  if (e == hipSuccess)
+    e = hipMemset(M->scan_status, 0, sizeof(unsigned long long) * std::max(M->nscan_tiles, 1u));
+  if (e == hipSuccess) e = hipMemset(M->ticket, 0, sizeof(uint32_t));
   if (e == hipSuccess) e = hipMemset(M->nnb, 0, sizeof(uint32_t) * std::max<size_t>(N, 1));
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     delete M;
     return fail(SPH_ERR_DEVICE, "initial upload failed: %s", hipGetErrorString(e));
+  }
+  if (N) {
+    if (sph_status st = M->hash_now()) {
+      delete M;
+      return st;
+    }
+    if ((e = hipStreamSynchronize(M->stream)) != hipSuccess) {
+      delete M;
+      return fail(SPH_ERR_DEVICE, "initial hash failed: %s", hipGetErrorString(e));
+    }
   }
   *out = M;
   return SPH_OK;
@@ -706,10 +712,13 @@ extern "C" sph_status sph_mesh_positions(sph_mesh *m, double *xyz, int32_t *feat
   std::vector<uint32_t> oid;
   HIPCHK(pull(oid, s.oid, m->n));
   if (xyz) {
-    std::vector<double> col;
-    for (int a = 0; a < 3; ++a) {
-      if (a < m->D) HIPCHK(pull(col, s.x[a], m->n));
-      for (int i = 0; i < m->n; ++i) xyz[3 * (size_t)oid[i] + a] = a < m->D ? col[i] : 0.0;
+    std::vector<double4> xh;
+    HIPCHK(pull(xh, s.xh, m->n));
+    for (int i = 0; i < m->n; ++i) {
+      double *o = xyz + 3 * (size_t)oid[i];
+      o[0] = xh[i].x;
+      o[1] = xh[i].y;
+      o[2] = m->D == 3 ? xh[i].z : 0.0;
     }
   }
   if (feature) {
@@ -726,10 +735,13 @@ extern "C" sph_status sph_mesh_velocities(sph_mesh *m, double *vel) {
   const Parts &s = m->P[m->cur];
   std::vector<uint32_t> oid;
   HIPCHK(pull(oid, s.oid, m->n));
-  std::vector<double> col;
-  for (int a = 0; a < 3; ++a) {
-    if (a < m->D) HIPCHK(pull(col, s.v[a], m->n));
-    for (int i = 0; i < m->n; ++i) vel[3 * (size_t)oid[i] + a] = a < m->D ? col[i] : 0.0;
+  std::vector<double4> v;
+  HIPCHK(pull(v, s.v, m->n));
+  for (int i = 0; i < m->n; ++i) {
+    double *o = vel + 3 * (size_t)oid[i];
+    o[0] = v[i].x;
+    o[1] = v[i].y;
+    o[2] = m->D == 3 ? v[i].z : 0.0;
   }
   return SPH_OK;
 }
@@ -737,19 +749,29 @@ extern "C" sph_status sph_mesh_velocities(sph_mesh *m, double *vel) {
 extern "C" sph_status sph_mesh_set_state(sph_mesh *m, const double *xyz, const double *vel) {
   if (!m) return fail(SPH_ERR_INVALID_ARG, "null handle");
   HIPCHK(hipStreamSynchronize(m->stream));
+  if (m->n == 0) return SPH_OK;
   const Parts &s = m->P[m->cur];
   std::vector<uint32_t> oid;
   HIPCHK(pull(oid, s.oid, m->n));
-  std::vector<double> col(m->n);
-  for (int a = 0; a < m->D; ++a) {
-    if (xyz) {
-      for (int i = 0; i < m->n; ++i) col[i] = xyz[3 * (size_t)oid[i] + a];
-      HIPCHK(hipMemcpy(s.x[a], col.data(), col.size() * 8, hipMemcpyHostToDevice));
+  if (xyz) {
+    std::vector<double4> xh(m->n);
+    for (int i = 0; i < m->n; ++i) {
+      const double *p = xyz + 3 * (size_t)oid[i];
+      xh[i] = make_double4(p[0], p[1], m->D == 3 ? p[2] : 0.0, 0.0);
     }
-    if (vel) {
-      for (int i = 0; i < m->n; ++i) col[i] = vel[3 * (size_t)oid[i] + a];
-      HIPCHK(hipMemcpy(s.v[a], col.data(), col.size() * 8, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(s.xh, xh.data(), xh.size() * sizeof(double4), hipMemcpyHostToDevice));
+    // new positions: new h, cells and ranks
+    HIPCHK(hipMemset(m->cnt, 0, sizeof(uint32_t) * m->grid.ncell));
+    if (sph_status st = m->hash_now()) return st;
+    HIPCHK(hipStreamSynchronize(m->stream));
+  }
+  if (vel) {
+    std::vector<double4> v(m->n);
+    for (int i = 0; i < m->n; ++i) {
+      const double *p = vel + 3 * (size_t)oid[i];
+      v[i] = make_double4(p[0], p[1], m->D == 3 ? p[2] : 0.0, 0.0);
     }
+    HIPCHK(hipMemcpy(s.v, v.data(), v.size() * sizeof(double4), hipMemcpyHostToDevice));
   }
   return SPH_OK;
 }
@@ -758,11 +780,20 @@ extern "C" sph_status sph_mesh_neighbors(sph_mesh *m, int64_t *offsets, int32_t 
                                          int64_t cap, int64_t *n_pairs) {
   if (!m || !offsets) return fail(SPH_ERR_INVALID_ARG, "null argument");
   HIPCHK(hipStreamSynchronize(m->stream));
-  sph_status st = m->D == 2 ? m->enqueue_rebuild<2>(true, false) : m->enqueue_rebuild<3>(true, false);
+  const int n = m->n;
+  if (n == 0) {
+    offsets[0] = 0;
+    if (n_pairs) *n_pairs = 0;
+    return SPH_OK;
+  }
+  // sort into cell order, build the lists, then re-hash so that the next
+  // step starts from consistent cell counts
+  sph_status st = m->enqueue_sort();
+  if (!st) st = m->D == 2 ? m->enqueue_lists_only<2>() : m->enqueue_lists_only<3>();
+  if (!st) st = m->hash_now();
   if (st) return st;
   HIPCHK(hipStreamSynchronize(m->stream));
   if ((st = m->check_status())) return st;
-  const int n = m->n;
   const Parts &s = m->P[m->cur];
   std::vector<uint32_t> oid, nnb, nbr;
   HIPCHK(pull(oid, s.oid, n));
@@ -803,30 +834,41 @@ extern "C" sph_status sph_mesh_field(sph_mesh *m, int32_t which, double *out) {
   std::vector<uint32_t> oid;
   HIPCHK(pull(oid, s.oid, n));
   std::vector<double> col;
-  auto pull_real = [&](const void *d) -> hipError_t {
-    if (m->prec == SPH_FP64) return pull(col, d, n);
-    std::vector<float> f;
-    hipError_t e = pull(f, d, n);
-    col.assign(f.begin(), f.end());
-    return e;
+  auto scatter1 = [&]() {
+    for (int i = 0; i < n; ++i) out[oid[i]] = col[i];
   };
-  auto scatter1 = [&]() { for (int i = 0; i < n; ++i) out[oid[i]] = col[i]; };
-  auto scatter3 = [&](int a) { for (int i = 0; i < n; ++i) out[3 * (size_t)oid[i] + a] = col[i]; };
+  auto scatter4 = [&](const std::vector<double4> &v) {
+    for (int i = 0; i < n; ++i) {
+      double *o = out + 3 * (size_t)oid[i];
+      o[0] = v[i].x;
+      o[1] = v[i].y;
+      o[2] = m->D == 3 ? v[i].z : 0.0;
+    }
+  };
+  std::vector<double4> v4;
   switch (which) {
-    case 0: HIPCHK(pull(col, s.h, n)); scatter1(); break;
+    case 0: {
+      HIPCHK(pull(v4, s.xh, n));
+      col.resize(n);
+      for (int i = 0; i < n; ++i) col[i] = v4[i].w;
+      scatter1();
+      break;
+    }
     case 3: HIPCHK(pull(col, m->dbg_vt, n)); scatter1(); break;
     case 4: HIPCHK(pull(col, m->dbg_gam, n)); scatter1(); break;
-    default:
-      for (int a = 0; a < 3; ++a) {
-        if (a < m->D) {
-          if (which == 1) HIPCHK(pull_real(m->ap[a]));
-          else if (which == 2) HIPCHK(pull_real(m->acc[a]));
-          else HIPCHK(pull(col, m->dbg_vm[a], n));
-        } else {
-          col.assign(n, 0.0);
-        }
-        scatter3(a);
+    case 5: HIPCHK(pull(v4, m->dbg_vm, n)); scatter4(v4); break;
+    default: {
+      const void *src = which == 1 ? m->ap : m->acc;
+      if (m->prec == SPH_FP64) {
+        HIPCHK(pull(v4, src, n));
+      } else {
+        std::vector<float4> f4;
+        HIPCHK(pull(f4, src, n));
+        v4.resize(n);
+        for (int i = 0; i < n; ++i) v4[i] = make_double4(f4[i].x, f4[i].y, f4[i].z, f4[i].w);
       }
+      scatter4(v4);
+    }
   }
   return SPH_OK;
 }

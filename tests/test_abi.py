@@ -33,7 +33,7 @@ def test_kernel_names_need_no_gpu():
     from paper_2003_01061_amd import binding
     L = binding.lib()
     names = [L.sph_mesh_kernel_name(k).decode() for k in range(L.sph_mesh_kernel_count())]
-    assert "sweep_a" in names and "neighbors" in names
+    assert "nbr_forces" in names and "sweep_b" in names
 
 
 def test_invalid_arguments_fail_before_touching_the_gpu():
