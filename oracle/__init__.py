@@ -77,6 +77,8 @@ def lib():
         L.sphref_control_replay.argtypes = [C.POINTER(Params), C.c_int32, _dp, _dp,
                                             np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS"),
                                             np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS"), _dp]
+        L.sphref_sample.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                    C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]
         L.sphref_last_error.restype = C.c_char_p
         _lib = L
     return _lib
@@ -187,6 +189,24 @@ class RefJob:
                               ids.size, C.byref(npairs)):
             raise RuntimeError(_err())
         return off, ids[:npairs.value], rel[:npairs.value]
+
+    def sample(self, idx, cap_per=256):
+        """Brute-force lists and sweep-A quantities of the particles idx at
+        the current positions (any job size)."""
+        idx = np.ascontiguousarray(idx, np.int64)
+        m = idx.size
+        cap = cap_per * max(m, 1)
+        off = np.zeros(m + 1, np.int64)
+        ids = np.zeros(cap, np.int32)
+        rel = np.zeros(cap, np.int8)
+        ap = np.zeros((m, 3))
+        vt = np.zeros(m)
+        gam = np.zeros(m)
+        if lib().sphref_sample(self.h, m, idx.ctypes.data, off.ctypes.data, ids.ctypes.data,
+                               rel.ctypes.data, cap, ap.ctypes.data, vt.ctypes.data,
+                               gam.ctypes.data):
+            raise RuntimeError(_err())
+        return off, ids[:off[-1]], rel[:off[-1]], ap, vt, gam
 
     def error(self):
         e = C.c_double()

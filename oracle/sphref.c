@@ -675,10 +675,94 @@ int32_t sphref_control_replay(const sphref_params *p, int32_t n_steps,
   return 0;
 }
 
+static double norm3(const double *u) { return sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]); }
+
+/* Shepard term, particle volume, pressure force with the boundary term,
+ * mapped onto the feature (Eqs. (gamma_disc_renormSPH), (particle_volume),
+ * (sph_pressure_force_disc_weighted)) of particle i over its list nb / rel */
+static void sweep_a_particle(const sphref_job *J, int64_t i, const int32_t *nbl, const int8_t *rel,
+                             int64_t cnt, double *ap_out, double *Vt_out, double *gam_out) {
+  const geo_t *G = &J->G;
+  const sphref_params *P = &J->P;
+  int D = G->dim;
+  int k = G->f[J->f[i]].k;
+  double hi = J->h[i];
+  double hik = hpow(hi, k), hi2k = hik * hik;
+  double S = sphref_W(k, 0.0, hi);          /* self term */
+  double gam = sphref_W(k, 0.0, hi) * hik;
+  double Pi[3] = {0, 0, 0}, B[3] = {0, 0, 0};
+  for (int64_t t = 0; t < cnt; ++t) {
+    int64_t j = nbl[t];
+    double dx[3] = {0, 0, 0};
+    for (int a = 0; a < D; ++a) dx[a] = J->x[3 * i + a] - J->x[3 * j + a];
+    double r = norm3(dx);
+    double hj = J->h[j];
+    double hjk = hpow(hj, k), hj2k = hjk * hjk;
+    double hij = 0.5 * (hi + hj);
+    if (rel[t] == 1) {
+      double w = sphref_W(k, r, hi);
+      S = S + w;
+      gam = gam + w * hjk;
+      double c = P->p0 * (hi2k + hj2k) * dWdr_over_r(k, r, hij);
+      for (int a = 0; a < D; ++a) Pi[a] = Pi[a] + c * dx[a];
+    } else {
+      double omega = P->boundary_weighting == 0 ? 1.0 / hj
+                   : P->boundary_weighting == 1 ? hpow(hj, k - 1) : 0.0;
+      double nb[3];
+      bnormal(G, J->f[i], J->f[j], J->x + 3 * j, nb);
+      double c = P->p0 * (hi2k + hj2k) * sphref_W(k, r, hij) * omega;
+      for (int a = 0; a < D; ++a) B[a] = B[a] + c * nb[a];
+    }
+  }
+  double ap[3] = {0, 0, 0};
+  for (int a = 0; a < D; ++a) ap[a] = -((Pi[a] + B[a]) / gam);
+  tproject(G, J->f[i], J->x + 3 * i, ap);
+  for (int a = 0; a < 3; ++a) ap_out[a] = ap[a];
+  *Vt_out = 1.0 / S;
+  *gam_out = gam;
+}
+
+/* Neighbour list of a single particle by brute force over all particles,
+ * ids ascending (same predicate and relation as build_lists). */
+static int64_t brute_list(const sphref_job *J, int64_t i, int32_t *ids, int8_t *rel, int64_t cap) {
+  int64_t c = 0;
+  if (ftype(J, i) == T_SI) return 0;
+  for (int64_t j = 0; j < J->n; ++j) {
+    if (j == i || !within(J, i, j)) continue;
+    int r = relation(J, i, j);
+    if (!r) continue;
+    if (c < cap) { ids[c] = (int32_t)j; rel[c] = (int8_t)r; }
+    c++;
+  }
+  return c;
+}
+
+int32_t sphref_sample(sphref_job *J, int32_t m, const int64_t *idx, int64_t *offsets,
+                      int32_t *ids, int8_t *rel, int64_t cap, double *ap, double *vt,
+                      double *gam) {
+  compute_h(J);
+  int64_t total = 0;
+  offsets[0] = 0;
+  for (int32_t s = 0; s < m; ++s) {
+    int64_t i = idx[s];
+    if (i < 0 || i >= J->n) { set_err("sample index out of range"); return -1; }
+    int64_t c = brute_list(J, i, ids + total, rel + total, cap - total);
+    if (total + c > cap) { set_err("capacity too small"); return -1; }
+    if (ftype(J, i) != T_SI)
+      sweep_a_particle(J, i, ids + total, rel + total, c, ap + 3 * s, vt + s, gam + s);
+    else {
+      ap[3 * s] = ap[3 * s + 1] = ap[3 * s + 2] = 0.0;
+      vt[s] = gam[s] = 0.0;
+    }
+    total += c;
+    offsets[s + 1] = total;
+  }
+  return 0;
+}
+
 /* ------------------------------------------------------------------ */
 /* one relaxation step (Algorithm 1; readings R17, R23)                 */
 /* ------------------------------------------------------------------ */
-static double norm3(const double *u) { return sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]); }
 
 /* Eq. (fa_time_step_size) terms of one particle folded into a running min;
  * r_c = 2h, nu = 0.1 r_c |v|.  Infinite terms (a or v zero) drop out. */
@@ -719,47 +803,12 @@ static int one_step(sphref_job *J) {
       for (int a = 0; a < 3; ++a) J->v[3 * i + a] = 0.0;
 
   int64_t inter = 0;
-  /* Shepard term, particle volume, pressure force with the boundary term,
-   * mapped onto the feature (Eqs. (gamma_disc_renormSPH), (particle_volume),
-   * (sph_pressure_force_disc_weighted)) */
   for (int64_t i = 0; i < n; ++i) {
     if (!act[i]) continue;
-    int k = G->f[J->f[i]].k;
-    double hi = J->h[i];
-    double hik = hpow(hi, k), hi2k = hik * hik;
-    double S = sphref_W(k, 0.0, hi);          /* self term */
-    double gam = sphref_W(k, 0.0, hi) * hik;
-    double Pi[3] = {0, 0, 0}, B[3] = {0, 0, 0};
-    for (int64_t t = J->off[i]; t < J->off[i + 1]; ++t) {
-      int64_t j = J->nb[t];
-      double dx[3] = {0, 0, 0};
-      for (int a = 0; a < D; ++a) dx[a] = J->x[3 * i + a] - J->x[3 * j + a];
-      double r = norm3(dx);
-      double hj = J->h[j];
-      double hjk = hpow(hj, k), hj2k = hjk * hjk;
-      double hij = 0.5 * (hi + hj);
-      inter++;
-      if (J->rel[t] == 1) {
-        double w = sphref_W(k, r, hi);
-        S = S + w;
-        gam = gam + w * hjk;
-        double c = P->p0 * (hi2k + hj2k) * dWdr_over_r(k, r, hij);
-        for (int a = 0; a < D; ++a) Pi[a] = Pi[a] + c * dx[a];
-      } else {
-        double omega = P->boundary_weighting == 0 ? 1.0 / hj
-                     : P->boundary_weighting == 1 ? hpow(hj, k - 1) : 0.0;
-        double nb[3];
-        bnormal(G, J->f[i], J->f[j], J->x + 3 * j, nb);
-        double c = P->p0 * (hi2k + hj2k) * sphref_W(k, r, hij) * omega;
-        for (int a = 0; a < D; ++a) B[a] = B[a] + c * nb[a];
-      }
-    }
-    double ap[3] = {0, 0, 0};
-    for (int a = 0; a < D; ++a) ap[a] = -((Pi[a] + B[a]) / gam);
-    tproject(G, J->f[i], J->x + 3 * i, ap);
-    for (int a = 0; a < 3; ++a) J->ap[3 * i + a] = ap[a];
-    J->Vt[i] = 1.0 / S;
-    J->gam[i] = gam;
+    int64_t cnt = J->off[i + 1] - J->off[i];
+    inter += cnt;
+    sweep_a_particle(J, i, J->nb + J->off[i], J->rel + J->off[i], cnt, J->ap + 3 * i, &J->Vt[i],
+                     &J->gam[i]);
   }
 
   /* first time step per group from a^p and v^n */

@@ -112,6 +112,13 @@ int32_t sphref_get_field(sphref_job *j, int32_t which, double *out);
  * through n_pairs; fails (-1) when cap is too small (n_pairs still set). */
 int32_t sphref_neighbors(sphref_job *j, int64_t *offsets, int32_t *ids,
                          int8_t *rel_out, int64_t cap, int64_t *n_pairs);
+/* Sampled check at any size: for the m particles idx[] of the current
+ * positions, the neighbour list by brute force over all particles (CSR over
+ * the sample, ids ascending) and the sweep-A quantities over it: pressure
+ * acceleration a^p (m x 3), particle volume V~ (m), Shepard gamma (m). */
+int32_t sphref_sample(sphref_job *j, int32_t m, const int64_t *idx, int64_t *offsets,
+                      int32_t *ids, int8_t *rel, int64_t cap, double *ap, double *vt,
+                      double *gam);
 int32_t sphref_error(sphref_job *j, double *e_sys, int32_t *phase,
                      int32_t *converged, int64_t *step);
 /* per-feature control state: out[0..9] = phase, n_phase, E_sys, dt1, dt,

@@ -26,6 +26,7 @@ constexpr int BLOCK = 256;
 #ifndef SPH_NBATCH
 #define SPH_NBATCH 4
 #endif
+static_assert(SPH_NBATCH >= 1 && SPH_NBATCH <= 8, "records are padded by 8");
 #ifndef SPH_XCD_REMAP
 #define SPH_XCD_REMAP 1
 #endif
@@ -60,7 +61,7 @@ struct Geom {
 struct Grid {
   int32_t nc[3];
   uint32_t ncell;
-  double lo[3], inv_c[3];
+  double lo[3], inv_c[3], c[3];
   double rfac, rmax;
 };
 
@@ -201,6 +202,29 @@ __device__ __forceinline__ R dwq(int k, R q) {
 template <typename R>
 __device__ __forceinline__ R powk(R h, int k) {
   return k == 1 ? h : (k == 2 ? h * h : h * h * h);
+}
+
+// the same with the intrinsic dimension K known at compile time
+template <int K, typename R>
+__device__ __forceinline__ constexpr R kalphaK() {
+  return K == 1 ? R(0.625) : (K == 2 ? R(0.55704230082163367519) : R(0.41778172561622525639));
+}
+template <int K, typename R>
+__device__ __forceinline__ R wshapeK(R q) {   // w(q), caller guarantees q < 2 or clamps t
+  R t = R(1) - R(0.5) * q;
+  t = t > R(0) ? t : R(0);
+  const R t2 = t * t;
+  return K == 1 ? t2 * t * (R(1) + R(1.5) * q) : t2 * t2 * (R(1) + R(2) * q);
+}
+template <int K, typename R>
+__device__ __forceinline__ R dwqK(R q) {      // w'(q)/q
+  R t = R(1) - R(0.5) * q;
+  t = t > R(0) ? t : R(0);
+  return K == 1 ? R(-3) * t * t : R(-5) * t * t * t;
+}
+template <int K, typename R>
+__device__ __forceinline__ R powK(R h) {
+  return K == 1 ? h : (K == 2 ? h * h : h * h * h);
 }
 
 // fast reciprocal / square root per precision

@@ -334,19 +334,102 @@ __global__ __launch_bounds__(BLOCK) void k_rank_gather(int n, const uint32_t *__
 }
 
 // ---------------------------------------------------------------------------
-// neighbour list (Algorithm 1 "construct Verlet neighbor list") fused with
-// the Shepard term, particle volume and pressure force with the
-// feature-boundary correction (Eqs. (gamma_disc_renormSPH),
-// (particle_volume), (sph_pressure_force_disc_weighted)), mapped onto the
-// feature.  FORCES = false builds the lists only (test entry point).
+// Pair sums of sweep A (Eqs. (gamma_disc_renormSPH), (particle_volume),
+// (sph_pressure_force_disc_weighted)) of particle i of intrinsic dimension K
+// over its neighbour list.  Pair terms are evaluated in R; sums accumulate in
+// FP64 (for R = float this is the compensated accumulation: a few dozen FP32
+// terms add exactly in a 53-bit accumulator).
+// ---------------------------------------------------------------------------
+template <int D, int K, typename R>
+__device__ __forceinline__ void sweep_a_sums(const Geom &g, const Parts &s,
+                                             const BNorm *__restrict__ bn, int bw, double p0,
+                                             const uint32_t *__restrict__ nbr, int n, int i,
+                                             uint32_t cnt, const double4 &xi, int fi, double &S,
+                                             double &gam, double Pi[3], double B[3]) {
+  const R hi = (R)xi.w;
+  const R ihi = rcp_(hi);
+  constexpr R alpha = kalphaK<K, R>();
+  const R hik = powK<K>(hi), hi2k = hik * hik;
+  const R ihik = powK<K>(ihi);
+  const R P0 = (R)p0;
+  const R wself = alpha * ihik;
+  S = (double)wself;
+  gam = (double)(wself * hik);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) Pi[a] = B[a] = 0.0;
+  constexpr int NB = SPH_NBATCH;
+  for (uint32_t e0 = 0; e0 < cnt; e0 += NB) {
+    uint32_t u[NB];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) u[q] = e0 + q < cnt ? nbr[(size_t)(e0 + q) * n + i] : 0u;
+    double4 xr[NB];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) xr[q] = s.xh[u[q] & 0x7fffffffu];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      if (e0 + q >= cnt) break;
+      const double4 xj = xr[q];
+      const R dx0 = (R)(xi.x - xj.x), dx1 = (R)(xi.y - xj.y);
+      const R dx2 = D == 3 ? (R)(xi.z - xj.z) : R(0);
+      const R rr = sqrt_(dx0 * dx0 + dx1 * dx1 + dx2 * dx2);
+      const R hj = (R)xj.w;
+      const R hjk = powK<K>(hj);
+      const R hsum = hi2k + hjk * hjk;
+      const R ihij = rcp_(R(0.5) * (hi + hj));
+      const R qij = rr * ihij;
+      if (!(u[q] >> 31)) {
+        const R w = alpha * wshapeK<K>(rr * ihi) * ihik;           // W(r, h_i)
+        S += (double)w;
+        gam += (double)(w * hjk);
+        const R ih2 = ihij * ihij;
+        const R ihk2 = K == 1 ? ih2 * ihij : (K == 2 ? ih2 * ih2 : ih2 * ih2 * ihij);
+        const R c = P0 * hsum * alpha * dwqK<K>(qij) * ihk2;       // (dW/dr)/r at h_ij
+        Pi[0] += (double)(c * dx0);
+        Pi[1] += (double)(c * dx1);
+        if (D == 3) Pi[2] += (double)(c * dx2);
+      } else {
+        const int fj = s.f[u[q] & 0x7fffffffu];
+        const BNorm N = bn[fi * g.nf + fj];
+        double nv[3];
+        if (N.mode == 2) {
+          const double *cc = g.hc[N.hole];
+          const double d0 = cc[0] - xj.x, d1 = cc[1] - xj.y, d2 = D == 3 ? cc[2] - xj.z : 0.0;
+          const double il = 1.0 / __builtin_sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+          nv[0] = d0 * il;
+          nv[1] = d1 * il;
+          nv[2] = d2 * il;
+        } else {
+          nv[0] = N.n[0];
+          nv[1] = N.n[1];
+          nv[2] = N.n[2];
+        }
+        const R om = bw == 0 ? rcp_(hj) : (bw == 1 ? powK<K>(hj) * rcp_(hj) : R(0));
+        const R w = alpha * wshapeK<K>(qij) * powK<K>(ihij);          // W(r, h_ib)
+        const double c = (double)(P0 * hsum * w * om);
+        B[0] += c * nv[0];
+        B[1] += c * nv[1];
+        if (D == 3) B[2] += c * nv[2];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// neighbour list (Algorithm 1 "construct Verlet neighbor list") and, in the
+// same launch, sweep A over it; FORCES = false builds the lists only (test
+// entry point).  The candidate scan covers, for every cell row within R_i of
+// x_i, only the cells under the chord of the disc (sphere) of radius R_i, so
+// no neighbour is skipped and fewer non-neighbours are tested.  The pair sums
+// then run over the list just written, so the force math executes once per
+// neighbour instead of once per candidate.
 // ---------------------------------------------------------------------------
 template <int D, typename R, bool FORCES>
 __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
     Geom g, Grid G, double p0, int bw, Parts s, int n, const uint32_t *__restrict__ cstart,
     const unsigned long long *__restrict__ bmask, const Feat *__restrict__ feat,
-    const BNorm *__restrict__ bn,
-    const Group *__restrict__ grp, int all, uint32_t *__restrict__ nbr, uint32_t *__restrict__ nnb,
-    int cap, Status *st, typename Vec4<R>::T *__restrict__ ap, double *__restrict__ dbg_gam,
+    const BNorm *__restrict__ bn, const Group *__restrict__ grp, int all,
+    uint32_t *__restrict__ nbr, uint32_t *__restrict__ nnb, int cap, Status *st,
+    typename Vec4<R>::T *__restrict__ ap, double *__restrict__ dbg_gam,
     double *__restrict__ dbg_vt, unsigned long long *__restrict__ pmin,
     unsigned long long *__restrict__ psum, unsigned long long *__restrict__ pcount) {
   using R4 = typename Vec4<R>::T;
@@ -362,153 +445,111 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
     const bool want = F.type != T_SI && (all || grp[fi].active);
     act = FORCES && moving;
     uint32_t count = 0;
+    const double4 xi = s.xh[i];
     if (want) {
-      const double4 xi = s.xh[i];
-      const int k = F.k;
-      double vi[3] = {0.0, 0.0, 0.0};
-      if (act) {
-        const double4 v4 = s.v[i];
-        if (grp[fi].reset_now) {
-          s.v[i] = make_double4(0.0, 0.0, 0.0, 0.0);
-        } else {
-          vi[0] = v4.x;
-          vi[1] = v4.y;
-          vi[2] = v4.z;
-        }
-      }
-      const R hi = (R)xi.w;
-      const R ihi = rcp_(hi);
-      const R alpha = kalpha<R>(k);
-      const R hik = powk(hi, k), hi2k = hik * hik;
-      const R ihik = powk(ihi, k);
-      const R wself = alpha * ihik;
-      const R P0 = (R)p0;
-      Acc<R> S, gam, Pi[3], B[3];
-      S.init(wself);
-      gam.init(wself * hik);
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        Pi[a].init(R(0));
-        B[a].init(R(0));
-      }
       double Rs = G.rfac * xi.w;
       Rs = Rs < G.rmax ? Rs : G.rmax;
+      const double R2 = Rs * Rs;
       const double pc[3] = {xi.x, xi.y, xi.z};
       int lo_c[3] = {0, 0, 0}, hi_c[3] = {0, 0, 0};
 #pragma unroll
-      for (int a = 0; a < D; ++a) {
+      for (int a = 1; a < D; ++a) {
         lo_c[a] = cell_coord(G, a, pc[a] - Rs);
         hi_c[a] = cell_coord(G, a, pc[a] + Rs);
       }
       // features that bound fi (bit f set); a candidate of fi's own feature
       // interacts as "same", one of a bounding feature as "boundary"
       const unsigned long long bm = bmask[fi];
-      constexpr int NB = SPH_NBATCH;   // candidates whose records are loaded together
-      for (int cz = lo_c[2]; cz <= hi_c[2]; ++cz)
+      constexpr int NB = SPH_NBATCH;   // candidate records loaded together
+      for (int cz = lo_c[2]; cz <= hi_c[2]; ++cz) {
+        double dz2 = 0.0;
+        if (D == 3) {
+          const double z0 = G.lo[2] + cz * G.c[2];
+          double dz = z0 - pc[2] > pc[2] - (z0 + G.c[2]) ? z0 - pc[2] : pc[2] - (z0 + G.c[2]);
+          dz = dz - 1e-7 * G.c[2];
+          dz = dz > 0.0 ? dz : 0.0;
+          dz2 = dz * dz;
+        }
         for (int cy = lo_c[1]; cy <= hi_c[1]; ++cy) {
+          const double y0 = G.lo[1] + cy * G.c[1];
+          double dy = y0 - pc[1] > pc[1] - (y0 + G.c[1]) ? y0 - pc[1] : pc[1] - (y0 + G.c[1]);
+          dy = dy - 1e-7 * G.c[1];
+          dy = dy > 0.0 ? dy : 0.0;
+          const double w2 = R2 - dy * dy - dz2;
+          if (w2 < 0.0) continue;
+          const double wx = __builtin_sqrt(w2) * (1.0 + 1e-9) + 1e-7 * G.c[0];
+          const int cx0 = cell_coord(G, 0, pc[0] - wx), cx1 = cell_coord(G, 0, pc[0] + wx);
           const uint32_t row = ((uint32_t)cz * (uint32_t)G.nc[1] + (uint32_t)cy) * (uint32_t)G.nc[0];
-          const uint32_t jb = cstart[row + lo_c[0]], je = cstart[row + hi_c[0] + 1];
+          const uint32_t jb = cstart[row + cx0], je = cstart[row + cx1 + 1];
           for (uint32_t j0 = jb; j0 < je; j0 += NB) {
             double4 xr[NB];
             int fr[NB];
 #pragma unroll
-            for (int q = 0; q < NB; ++q) {
-              const uint32_t j = j0 + q < je ? j0 + q : je - 1;
-              xr[q] = s.xh[j];
-              fr[q] = s.f[j];
+            for (int q = 0; q < NB; ++q) {   // records are padded by NB past n
+              xr[q] = s.xh[j0 + q];
+              fr[q] = s.f[j0 + q];
             }
 #pragma unroll
             for (int q = 0; q < NB; ++q) {
               const uint32_t j = j0 + q;
-              if (j >= je || (int)j == i) continue;
-              const double4 xj = xr[q];
-              if (!within<D>(xi, xj)) continue;
+              if (j >= je) break;
+              if ((int)j == i || !within<D>(xi, xr[q])) continue;
               const int fj = fr[q];
               const int r = fj == fi ? 1 : (int)((bm >> fj) & 1ull) * 2;
               if (!r) continue;
               if ((int)count < cap) nbr[(size_t)count * n + i] = j | (r == 2 ? 0x80000000u : 0u);
               ++count;
-              if (FORCES && act) {
-                const R dx0 = (R)(xi.x - xj.x), dx1 = (R)(xi.y - xj.y);
-                const R dx2 = D == 3 ? (R)(xi.z - xj.z) : R(0);
-                const R rr = sqrt_(dx0 * dx0 + dx1 * dx1 + dx2 * dx2);
-                const R hj = (R)xj.w;
-                const R hjk = powk(hj, k), hj2k = hjk * hjk;
-                const R ihij = rcp_(R(0.5) * (hi + hj));
-                const R qij = rr * ihij;
-                if (r == 1) {
-                  const R w = alpha * wshape(k, rr * ihi) * ihik;   // W(r, h_i)
-                  S.add(w);
-                  gam.add(w * hjk);
-                  const R ih2 = ihij * ihij;
-                  const R ihk2 = k == 1 ? ih2 * ihij : (k == 2 ? ih2 * ih2 : ih2 * ih2 * ihij);
-                  const R c = P0 * (hi2k + hj2k) * alpha * dwq(k, qij) * ihk2;   // (dW/dr)/r, h_ij
-                  Pi[0].add(c * dx0);
-                  Pi[1].add(c * dx1);
-                  if (D == 3) Pi[2].add(c * dx2);
-                } else {
-                  const BNorm N = bn[fi * g.nf + fj];
-                  double nv[3];
-                  if (N.mode == 2) {
-                    const double *cc = g.hc[N.hole];
-                    const double d0 = cc[0] - xj.x, d1 = cc[1] - xj.y;
-                    const double d2 = D == 3 ? cc[2] - xj.z : 0.0;
-                    const double il = 1.0 / __builtin_sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-                    nv[0] = d0 * il;
-                    nv[1] = d1 * il;
-                    nv[2] = d2 * il;
-                  } else {
-                    nv[0] = N.n[0];
-                    nv[1] = N.n[1];
-                    nv[2] = N.n[2];
-                  }
-                  const R om = bw == 0 ? rcp_(hj) : (bw == 1 ? powk(hj, k) * rcp_(hj) : R(0));
-                  const R w = alpha * wshape(k, qij) * powk(ihij, k);    // W(r, h_ib)
-                  const R c = P0 * (hi2k + hj2k) * w * om;
-                  B[0].add(c * (R)nv[0]);
-                  B[1].add(c * (R)nv[1]);
-                  if (D == 3) B[2].add(c * (R)nv[2]);
-                }
-              }
             }
           }
         }
+      }
       if ((int)count > cap) {
         atomicMax(&st->overflow_max, count);
         atomicExch(&st->overflow, 1u);
         count = cap;
       }
-      if (FORCES && act) {
-        const double gm = (double)gam.get();
-        double a3[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-        for (int a = 0; a < D; ++a) a3[a] = -(((double)Pi[a].get() + (double)B[a].get()) / gm);
-        double xa[3] = {xi.x, xi.y, xi.z};
-        tangent<D>(g, F, xa, a3);
-        R4 o;
-        o.x = (R)a3[0];
-        o.y = (R)a3[1];
-        o.z = (R)a3[2];
-        o.w = R(0);
-        ap[i] = o;
-        const double vt = 1.0 / (double)S.get();
-        if (dbg_gam) dbg_gam[i] = gm;
-        if (dbg_vt) dbg_vt[i] = vt;
-        // Eq. (fa_time_step_size) terms from a^p and v^n
-        const double rc = 2.0 * xi.w;
-        double dt = __builtin_inf();
-        const double am = __builtin_sqrt(a3[0] * a3[0] + a3[1] * a3[1] + a3[2] * a3[2]);
-        if (am > 0.0) dt = 0.25 * __builtin_sqrt(rc / am);
-        const double vm = __builtin_sqrt(vi[0] * vi[0] + vi[1] * vi[1] + vi[2] * vi[2]);
-        if (vm > 0.0) {
-          const double t = rc / (40.0 * vm);
-          dt = t < dt ? t : dt;
-        }
-        dtb = dbits(dt);
-        vfix = (unsigned long long)__builtin_llrint(vt * grp[fi].vscale);
-      }
     }
-    if (FORCES && !act) {
+    if (FORCES && act) {
+      const int k = F.k;
+      double4 v4 = s.v[i];
+      if (grp[fi].reset_now) {
+        v4 = make_double4(0.0, 0.0, 0.0, 0.0);
+        s.v[i] = v4;
+      }
+      double S, gam, Pi[3], B[3];
+      if (k == D)
+        sweep_a_sums<D, D, R>(g, s, bn, bw, p0, nbr, n, i, count, xi, fi, S, gam, Pi, B);
+      else if (k == D - 1)
+        sweep_a_sums<D, D - 1, R>(g, s, bn, bw, p0, nbr, n, i, count, xi, fi, S, gam, Pi, B);
+      else
+        sweep_a_sums<D, 1, R>(g, s, bn, bw, p0, nbr, n, i, count, xi, fi, S, gam, Pi, B);
+      double a3[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+      for (int a = 0; a < D; ++a) a3[a] = -((Pi[a] + B[a]) / gam);
+      double xa[3] = {xi.x, xi.y, xi.z};
+      tangent<D>(g, F, xa, a3);
+      R4 o;
+      o.x = (R)a3[0];
+      o.y = (R)a3[1];
+      o.z = (R)a3[2];
+      o.w = R(0);
+      ap[i] = o;
+      const double vt = 1.0 / S;
+      if (dbg_gam) dbg_gam[i] = gam;
+      if (dbg_vt) dbg_vt[i] = vt;
+      // Eq. (fa_time_step_size) terms from a^p and v^n
+      const double rc = 2.0 * xi.w;
+      double dt = __builtin_inf();
+      const double am = __builtin_sqrt(a3[0] * a3[0] + a3[1] * a3[1] + a3[2] * a3[2]);
+      if (am > 0.0) dt = 0.25 * __builtin_sqrt(rc / am);
+      const double vm = __builtin_sqrt(v4.x * v4.x + v4.y * v4.y + v4.z * v4.z);
+      if (vm > 0.0) {
+        const double t = rc / (40.0 * vm);
+        dt = t < dt ? t : dt;
+      }
+      dtb = dbits(dt);
+      vfix = (unsigned long long)__builtin_llrint(vt * grp[fi].vscale);
+    } else if (FORCES) {
       R4 z;
       z.x = z.y = z.z = z.w = R(0);
       ap[i] = z;
@@ -520,6 +561,68 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
   }
   if (FORCES) block_group_reduce(act, fi, dtb, vfix, s_min, s_sum, g.nf, pmin, psum);
   if (pcount) block_count(mine, s_cnt, pcount);
+}
+
+// ---------------------------------------------------------------------------
+// sweep B pair sums: viscous force of Eq. (momentum_equation_discretized)
+// with eta = rho_t nu, nu = 0.1 r_c |v~| (Eq. (viscosity_coefficient)), the
+// mid-point velocities v~_j = v_j + dt_1/2 a^p_j formed on the fly
+// ---------------------------------------------------------------------------
+template <int D, int K, typename R>
+__device__ __forceinline__ void sweep_b_sums(const Parts &s, const typename Vec4<R>::T *__restrict__ ap,
+                                             const uint32_t *__restrict__ nbr, int n, int i,
+                                             uint32_t cnt, const double4 &xi, const double vti[3],
+                                             double vmi, double half, double Fv[3]) {
+  using R4 = typename Vec4<R>::T;
+  const R hi = (R)xi.w;
+  constexpr R alpha = kalphaK<K, R>();
+  const R hik = powK<K>(hi), hi2k = hik * hik;
+  const R etai = (R)(0.2 * xi.w * vmi) * rcp_(hik);
+  const R vtiR[3] = {(R)vti[0], (R)vti[1], (R)vti[2]};
+  const R halfR = (R)half;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) Fv[a] = 0.0;
+  constexpr int NB = SPH_NBATCH;
+  for (uint32_t e0 = 0; e0 < cnt; e0 += NB) {
+    uint32_t u[NB];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) u[q] = e0 + q < cnt ? nbr[(size_t)(e0 + q) * n + i] : 0x80000000u;
+    double4 xr[NB], vr[NB];
+    R4 ar[NB];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const uint32_t j = u[q] & 0x7fffffffu;   // boundary entries fetch a valid slot, unused
+      xr[q] = s.xh[j];
+      vr[q] = s.v[j];
+      ar[q] = ap[j];
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      if (u[q] >> 31) continue;
+      const double4 xj = xr[q];
+      const double4 vj = vr[q];
+      const R4 apj = ar[q];
+      const R dx0 = (R)(xi.x - xj.x), dx1 = (R)(xi.y - xj.y);
+      const R dx2 = D == 3 ? (R)(xi.z - xj.z) : R(0);
+      const R rr = sqrt_(dx0 * dx0 + dx1 * dx1 + dx2 * dx2);
+      const R hj = (R)xj.w;
+      const R hjk = powK<K>(hj);
+      R vtj[3];
+      vtj[0] = (R)vj.x + halfR * apj.x;
+      vtj[1] = (R)vj.y + halfR * apj.y;
+      vtj[2] = D == 3 ? (R)vj.z + halfR * apj.z : R(0);
+      const R vmj = sqrt_(vtj[0] * vtj[0] + vtj[1] * vtj[1] + vtj[2] * vtj[2]);
+      const R etaj = R(0.2) * hj * vmj * rcp_(hjk);
+      const R es = etai + etaj;
+      const R H = es > R(0) ? R(2) * etai * etaj * rcp_(es) : R(0);
+      const R ihij = rcp_(R(0.5) * (hi + hj));
+      const R ih2 = ihij * ihij;
+      const R ihk2 = K == 1 ? ih2 * ihij : (K == 2 ? ih2 * ih2 : ih2 * ih2 * ihij);
+      const R c = H * (hi2k + hjk * hjk) * alpha * dwqK<K>(rr * ihij) * ihk2;
+#pragma unroll
+      for (int a = 0; a < D; ++a) Fv[a] += (double)(c * (vtiR[a] - vtj[a]));
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -558,60 +661,14 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_b(Geom g, Parts s, int n,
 #pragma unroll
       for (int a = 0; a < 3; ++a) vti[a] = vi[a] + half * api[a];
       const double vmi = __builtin_sqrt(vti[0] * vti[0] + vti[1] * vti[1] + vti[2] * vti[2]);
-      const double hid = xi.w;
-      const R hi = (R)hid;
-      const R alpha = kalpha<R>(k);
-      const R hik = powk(hi, k), hi2k = hik * hik;
-      const R etai = (R)(0.2 * hid * vmi) * rcp_(hik);   // eta = rho_t nu, nu = 0.1 r_c |v~|
-      const R vtiR[3] = {(R)vti[0], (R)vti[1], (R)vti[2]};
-      const R halfR = (R)half;
-      Acc<R> Fv[3];
-#pragma unroll
-      for (int a = 0; a < 3; ++a) Fv[a].init(R(0));
       const uint32_t cnt = nnb[i];
-      constexpr int NB = SPH_NBATCH;   // neighbours whose records are loaded together
-      for (uint32_t e0 = 0; e0 < cnt; e0 += NB) {
-        uint32_t u[NB];
-#pragma unroll
-        for (int q = 0; q < NB; ++q)
-          u[q] = e0 + q < cnt ? nbr[(size_t)(e0 + q) * n + i] : 0x80000000u;
-        double4 xr[NB], vr[NB];
-        R4 ar[NB];
-#pragma unroll
-        for (int q = 0; q < NB; ++q) {
-          const uint32_t j = u[q] & 0x7fffffffu;   // boundary entries fetch a valid slot, unused
-          xr[q] = s.xh[j];
-          vr[q] = s.v[j];
-          ar[q] = ap[j];
-        }
-#pragma unroll
-        for (int q = 0; q < NB; ++q) {
-          if (u[q] >> 31) continue;
-          const double4 xj = xr[q];
-          const double4 vj = vr[q];
-          const R4 apj = ar[q];
-          const R dx0 = (R)(xi.x - xj.x), dx1 = (R)(xi.y - xj.y);
-          const R dx2 = D == 3 ? (R)(xi.z - xj.z) : R(0);
-          const R rr = sqrt_(dx0 * dx0 + dx1 * dx1 + dx2 * dx2);
-          const R hj = (R)xj.w;
-          const R hjk = powk(hj, k), hj2k = hjk * hjk;
-          R vtj[3];
-          vtj[0] = (R)vj.x + halfR * apj.x;
-          vtj[1] = (R)vj.y + halfR * apj.y;
-          vtj[2] = D == 3 ? (R)vj.z + halfR * apj.z : R(0);
-          const R vmj = sqrt_(vtj[0] * vtj[0] + vtj[1] * vtj[1] + vtj[2] * vtj[2]);
-          const R etaj = R(0.2) * hj * vmj * rcp_(hjk);
-          const R es = etai + etaj;
-          const R H = es > R(0) ? R(2) * etai * etaj * rcp_(es) : R(0);
-          const R ihij = rcp_(R(0.5) * (hi + hj));
-          const R ih2 = ihij * ihij;
-          const R ihk2 = k == 1 ? ih2 * ihij : (k == 2 ? ih2 * ih2 : ih2 * ih2 * ihij);
-          const R c = H * (hi2k + hj2k) * alpha * dwq(k, rr * ihij) * ihk2;
-#pragma unroll
-          for (int a = 0; a < D; ++a) Fv[a].add(c * (vtiR[a] - vtj[a]));
-        }
-      }
-      double fv[3] = {(double)Fv[0].get(), (double)Fv[1].get(), D == 3 ? (double)Fv[2].get() : 0.0};
+      double fv[3];
+      if (k == D)
+        sweep_b_sums<D, D, R>(s, ap, nbr, n, i, cnt, xi, vti, vmi, half, fv);
+      else if (k == D - 1)
+        sweep_b_sums<D, D - 1, R>(s, ap, nbr, n, i, cnt, xi, vti, vmi, half, fv);
+      else
+        sweep_b_sums<D, 1, R>(s, ap, nbr, n, i, cnt, xi, vti, vmi, half, fv);
       double xa[3] = {xi.x, xi.y, xi.z};
       tangent<D>(g, F, xa, fv);
       const double eps = grp[fi].eps;
@@ -625,7 +682,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_b(Geom g, Parts s, int n,
       o.w = R(0);
       acc[i] = o;
       if (dbg_vm) dbg_vm[i] = make_double4(vti[0], vti[1], vti[2], 0.0);
-      const double rc = 2.0 * hid;
+      const double rc = 2.0 * xi.w;
       double dt = __builtin_inf();
       const double am = __builtin_sqrt(a3[0] * a3[0] + a3[1] * a3[1] + a3[2] * a3[2]);
       if (am > 0.0) dt = 0.25 * __builtin_sqrt(rc / am);

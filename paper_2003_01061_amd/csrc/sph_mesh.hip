@@ -497,9 +497,11 @@ extern "C" sph_status sph_mesh_create(const sph_geometry *g, const sph_sizing *s
     if (a < D) {
       Gr.nc[a] = (int)std::max(1.0, std::floor((g->hi[a] - g->lo[a]) / side));
       Gr.inv_c[a] = Gr.nc[a] / (g->hi[a] - g->lo[a]);
+      Gr.c[a] = (g->hi[a] - g->lo[a]) / Gr.nc[a];
     } else {
       Gr.nc[a] = 1;
       Gr.inv_c[a] = 0.0;
+      Gr.c[a] = 0.0;
     }
     Gr.ncell *= (uint32_t)Gr.nc[a];
   }
@@ -523,10 +525,12 @@ extern "C" sph_status sph_mesh_create(const sph_geometry *g, const sph_sizing *s
   size_t &by = M->bytes;
   const size_t N = (size_t)n;
   bool ok = true;
+  // records are padded past n so that batched candidate loads need no clamp
+  const size_t NPAD = N + 8;
   for (int b = 0; b < 2; ++b) {
-    M->P[b].xh = dalloc<double4>(N, ow, by);
-    M->P[b].v = dalloc<double4>(N, ow, by);
-    M->P[b].f = dalloc<uint8_t>(N, ow, by);
+    M->P[b].xh = dalloc<double4>(NPAD, ow, by);
+    M->P[b].v = dalloc<double4>(NPAD, ow, by);
+    M->P[b].f = dalloc<uint8_t>(NPAD, ow, by);
     M->P[b].oid = dalloc<uint32_t>(N, ow, by);
     ok = ok && M->P[b].xh && M->P[b].v && M->P[b].f && M->P[b].oid;
   }

@@ -181,3 +181,39 @@ def test_full_size_square_hole_250k():
     xr = ref.state()[0]
     assert np.abs(g64.positions() - xr).max() <= TOL64
     assert np.abs(g32.positions() - xr).max() <= TOL32
+
+
+def _sample_indices(wl, n_random, seed):
+    rng = np.random.default_rng(seed)
+    idx = [rng.choice(wl.n, n_random, replace=False)]
+    for f in range(len(wl.ftype)):          # a few from every feature
+        members = np.nonzero(wl.feature == f)[0]
+        if len(members):
+            idx.append(rng.choice(members, min(4, len(members)), replace=False))
+    return np.unique(np.concatenate(idx))
+
+
+@pytest.mark.parametrize("precision,tol", [(binding.SPH_FP64, 1e-12),
+                                           (binding.SPH_FP32_MIXED, 1e-5)])
+def test_full_size_cube_ball_2m_sampled(precision, tol):
+    """The 3D workload at full size (2,000,000 particles): neighbour lists of
+    sampled particles bit-exact, and their first-step a^p, V~ and gamma,
+    against the oracle computing each sampled particle by brute force."""
+    wl = _wl_cache.get("cube_ball") or _wl_cache.setdefault("cube_ball", wk.cube_ball())
+    ref = oracle.RefJob(wl)
+    idx = _sample_indices(wl, 400, seed=5)
+    so, si, sr, ap_r, vt_r, gam_r = ref.sample(idx)
+    g = binding.SphMesh(wl, precision=precision, use_graph=1, debug_fields=1)
+    off, ids, rel = g.neighbors()
+    for s_, i in enumerate(idx):
+        assert np.array_equal(ids[off[i]:off[i + 1]], si[so[s_]:so[s_ + 1]]), i
+        assert np.array_equal(rel[off[i]:off[i + 1]], sr[so[s_]:so[s_ + 1]]), i
+    g.step(1)
+    moving = wl.ftype[wl.feature[idx]] != wk.SI
+    for field, ref_v in ((binding.FIELD_AP, ap_r), (binding.FIELD_VT, vt_r),
+                         (binding.FIELD_GAMMA, gam_r)):
+        got = g.field(field)[idx][moving]
+        want = ref_v[moving]
+        scale = np.abs(want).max()
+        assert np.abs(got - want).max() <= tol * scale, (field, np.abs(got - want).max() / scale)
+    assert g.counters()["steps"] == 1
