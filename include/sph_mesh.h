@@ -50,7 +50,7 @@ typedef struct sph_mesh sph_mesh;
 typedef enum {
   SPH_OK = 0,
   SPH_ERR_INVALID_ARG = 1,   /* bad geometry, sizing, parameters or buffer */
-  SPH_ERR_OUT_OF_MEMORY = 2, /* device allocation failed */
+  SPH_ERR_OUT_OF_MEMORY = 2, /* device allocation failed, or a batch is full */
   SPH_ERR_DEVICE = 3,        /* a HIP call failed */
   SPH_ERR_STATE = 4,         /* non-finite state or neighbour-list overflow */
   SPH_ERR_UNSUPPORTED = 5    /* a configuration this build does not handle */
@@ -208,6 +208,71 @@ const char *sph_mesh_kernel_name(int32_t kid);
 
 /* Wait for the handle's stream. */
 sph_status sph_mesh_sync(sph_mesh *m);
+
+/* ---- batches: many jobs advanced by the same launches ------------------ */
+/* A batch keeps several jobs resident on one GPU and advances all of them
+ * with one sequence of kernel launches per step (one captured graph), so
+ * small jobs share the launch cost.  Every job keeps its own geometry,
+ * sizing, parameters, time steps and control state (sec. 3.4-3.5 per job);
+ * jobs never interact, and a job's result is bit-identical alone or in any
+ * mix.  Jobs can be added and removed between steps (continuous batching).
+ * The sph_mesh_* calls above are a batch holding one job. */
+typedef struct sph_batch sph_batch;
+
+typedef struct {
+  int32_t dim;               /* 2 or 3, shared by every job of the batch */
+  int32_t precision;         /* SPH_FP64 or SPH_FP32_MIXED, shared */
+  int64_t max_particles;     /* capacity: particles of all resident jobs */
+  int64_t max_cells;         /* capacity: cells of all resident jobs' grids */
+  int32_t max_jobs;          /* resident jobs, 1..64 */
+  int32_t max_neighbors;     /* 0 = 64 in 2D, 160 in 3D */
+  int32_t use_graph;         /* 1: steps replay a captured graph of two steps */
+  int32_t debug_fields;      /* keep gamma, V~, v~ (single-job inspection) */
+  void *stream;              /* hipStream_t; NULL = the batch creates its own */
+} sph_batch_params;
+
+/* Device bytes a batch with these capacities allocates (admission control);
+ * -1 on invalid parameters. */
+int64_t sph_batch_footprint(const sph_batch_params *bp);
+
+/* Cells of the grid a job would use in a batch (its cell_factor and sizing),
+ * or -1 if the description is invalid. */
+int64_t sph_job_cells(const sph_geometry *geometry, const sph_sizing *sizing,
+                      const sph_params *params);
+
+/* Allocate an empty batch.  SPH_ERR_OUT_OF_MEMORY if the capacities do not
+ * fit; *out is NULL on failure. */
+sph_status sph_batch_create(const sph_batch_params *bp, sph_batch **out);
+
+/* Add a job (same arguments as sph_mesh_create; the batch's dimension,
+ * precision, neighbour capacity, graph, debug and stream settings apply, the
+ * job's own ones are ignored).  Waits for the stream.  *job receives the
+ * job's slot id.  SPH_ERR_OUT_OF_MEMORY when the batch has no room for its
+ * particles, cells or slot (the batch is unchanged). */
+sph_status sph_batch_add(sph_batch *b, const sph_geometry *geometry, const sph_sizing *sizing,
+                         const sph_params *params, int64_t n, const double *xyz,
+                         const int32_t *feature, int32_t *job);
+
+/* Remove a job and compact the others.  Waits for the stream. */
+sph_status sph_batch_remove(sph_batch *b, int32_t job);
+
+/* Enqueue n_steps steps of every resident job that has not converged. */
+sph_status sph_batch_step(sph_batch *b, int32_t n_steps);
+
+/* One synchronisation, then per job slot 0..cap-1: resident (live), converged,
+ * and steps run.  Any output may be NULL. */
+sph_status sph_batch_status(sph_batch *b, int32_t *live, int32_t *converged, int64_t *steps,
+                            int32_t cap);
+
+/* Per-job results (same meaning as the sph_mesh_* calls). */
+sph_status sph_batch_positions(sph_batch *b, int32_t job, double *xyz, int32_t *feature,
+                               int64_t capacity, int64_t *n_out);
+sph_status sph_batch_error(sph_batch *b, int32_t job, double *e_sys, int32_t *phase,
+                           int32_t *converged, int64_t *step);
+sph_status sph_batch_counters(sph_batch *b, int32_t job, double *out);
+
+/* Wait for the batch's stream, free everything; NULL-safe. */
+void sph_batch_destroy(sph_batch *b);
 
 /* Device bytes held by the handle. */
 int64_t sph_mesh_device_bytes(sph_mesh *m);

@@ -40,6 +40,12 @@ class Params(C.Structure):
                 ("stream", C.c_void_p)]
 
 
+class BatchParams(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("precision", C.c_int32), ("max_particles", C.c_int64),
+                ("max_cells", C.c_int64), ("max_jobs", C.c_int32), ("max_neighbors", C.c_int32),
+                ("use_graph", C.c_int32), ("debug_fields", C.c_int32), ("stream", C.c_void_p)]
+
+
 class SphError(RuntimeError):
     def __init__(self, fn, status, msg):
         super().__init__(f"{fn} -> status {status}: {msg}")
@@ -83,6 +89,23 @@ def lib():
         L.sph_mesh_sync.argtypes = [vp]
         L.sph_mesh_device_bytes.argtypes = [vp]
         L.sph_mesh_device_bytes.restype = C.c_int64
+        bpp = C.POINTER(BatchParams)
+        L.sph_batch_footprint.argtypes = [bpp]
+        L.sph_batch_footprint.restype = C.c_int64
+        L.sph_job_cells.argtypes = [C.POINTER(Geometry), C.POINTER(Sizing), C.POINTER(Params)]
+        L.sph_job_cells.restype = C.c_int64
+        L.sph_batch_create.argtypes = [bpp, C.POINTER(vp)]
+        L.sph_batch_add.argtypes = [vp, C.POINTER(Geometry), C.POINTER(Sizing), C.POINTER(Params),
+                                    C.c_int64, vp, vp, C.POINTER(C.c_int32)]
+        L.sph_batch_remove.argtypes = [vp, C.c_int32]
+        L.sph_batch_step.argtypes = [vp, C.c_int32]
+        L.sph_batch_status.argtypes = [vp, vp, vp, vp, C.c_int32]
+        L.sph_batch_positions.argtypes = [vp, C.c_int32, vp, vp, C.c_int64, C.POINTER(C.c_int64)]
+        L.sph_batch_error.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int32),
+                                      C.POINTER(C.c_int32), C.POINTER(C.c_int64)]
+        L.sph_batch_counters.argtypes = [vp, C.c_int32, vp]
+        L.sph_batch_destroy.argtypes = [vp]
+        L.sph_batch_destroy.restype = None
         _lib = L
     return _lib
 
@@ -253,6 +276,113 @@ class SphMesh:
         return int(lib().sph_mesh_device_bytes(self.h))
 
 
+class JobSpec:
+    """Marshalled description of one job (geometry, sizing, parameters,
+    particles) for sph_batch_add / sph_job_cells."""
+
+    def __init__(self, wl, params=None, xyz=None, feature=None, **over):
+        p = dict(wl.params if params is None else params)
+        p.update(over)
+        self.dim = wl.dim
+        self.geom = make_geometry(wl.dim, wl.lo, wl.hi, wl.holes)
+        self.sizing = make_sizing(wl.sizing)
+        self.params = make_params(p)
+        self.xyz = np.ascontiguousarray(wl.xyz if xyz is None else xyz, np.float64)
+        self.feature = np.ascontiguousarray(wl.feature if feature is None else feature, np.int32)
+        self.n = int(self.xyz.shape[0])
+
+    def cells(self):
+        return int(lib().sph_job_cells(C.byref(self.geom), C.byref(self.sizing),
+                                       C.byref(self.params)))
+
+
+def batch_params(dim, precision=SPH_FP64, max_particles=0, max_cells=1, max_jobs=1,
+                 max_neighbors=0, use_graph=1, debug_fields=0, stream=None):
+    bp = BatchParams()
+    bp.dim, bp.precision = dim, precision
+    bp.max_particles, bp.max_cells, bp.max_jobs = max_particles, max_cells, max_jobs
+    bp.max_neighbors, bp.use_graph, bp.debug_fields = max_neighbors, use_graph, debug_fields
+    bp.stream = stream
+    return bp
+
+
+def batch_footprint(**kw):
+    """Device bytes of a batch with these capacities (-1 if invalid)."""
+    bp = batch_params(**kw)
+    return int(lib().sph_batch_footprint(C.byref(bp)))
+
+
+class SphBatch:
+    """Many relaxation jobs sharing one set of device arrays and one launch
+    sequence per step (libsphmesh.so batch handle)."""
+
+    def __init__(self, dim, precision=SPH_FP64, max_particles=0, max_cells=1, max_jobs=1,
+                 max_neighbors=0, use_graph=1, stream=None):
+        self.bp = batch_params(dim, precision, max_particles, max_cells, max_jobs,
+                               max_neighbors, use_graph, 0, stream)
+        self.max_jobs = max_jobs
+        h = C.c_void_p()
+        _check("sph_batch_create", lib().sph_batch_create(C.byref(self.bp), C.byref(h)))
+        self.h = h
+        self.n_of = {}
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().sph_batch_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def add(self, spec):
+        j = C.c_int32()
+        _check("sph_batch_add", lib().sph_batch_add(
+            self.h, C.byref(spec.geom), C.byref(spec.sizing), C.byref(spec.params), spec.n,
+            spec.xyz.ctypes.data, spec.feature.ctypes.data, C.byref(j)))
+        self.n_of[j.value] = spec.n
+        return j.value
+
+    def remove(self, job):
+        _check("sph_batch_remove", lib().sph_batch_remove(self.h, int(job)))
+        self.n_of.pop(int(job), None)
+
+    def step(self, n=1):
+        _check("sph_batch_step", lib().sph_batch_step(self.h, int(n)))
+
+    def status(self):
+        m = self.max_jobs
+        live = np.zeros(m, np.int32)
+        conv = np.zeros(m, np.int32)
+        steps = np.zeros(m, np.int64)
+        _check("sph_batch_status", lib().sph_batch_status(
+            self.h, live.ctypes.data, conv.ctypes.data, steps.ctypes.data, m))
+        return live.astype(bool), conv.astype(bool), steps
+
+    def positions(self, job, with_feature=False):
+        n = self.n_of[job]
+        x = np.zeros((n, 3))
+        f = np.zeros(n, np.int32) if with_feature else None
+        nout = C.c_int64()
+        _check("sph_batch_positions", lib().sph_batch_positions(
+            self.h, int(job), x.ctypes.data, None if f is None else f.ctypes.data, n,
+            C.byref(nout)))
+        return (x, f) if with_feature else x
+
+    def error(self, job):
+        e = C.c_double()
+        ph = C.c_int32()
+        conv = C.c_int32()
+        st = C.c_int64()
+        _check("sph_batch_error", lib().sph_batch_error(self.h, int(job), C.byref(e),
+                                                        C.byref(ph), C.byref(conv), C.byref(st)))
+        return dict(e_sys=e.value, phase=ph.value, converged=bool(conv.value), step=st.value)
+
+    def counters(self, job):
+        out = np.zeros(4)
+        _check("sph_batch_counters", lib().sph_batch_counters(self.h, int(job), out.ctypes.data))
+        return dict(steps=int(out[0]), escaped=int(out[1]), interactions=int(out[2]),
+                    interactions_last=int(out[3]))
+
+
 def control_replay(params, vbar, dt):
     p = make_params(params)
     vbar = np.ascontiguousarray(vbar, np.float64)
@@ -274,4 +404,6 @@ def exported_symbols():
             "sph_mesh_neighbors", "sph_mesh_field", "sph_mesh_group_state", "sph_mesh_counters",
             "sph_mesh_control_replay", "sph_mesh_profile", "sph_mesh_kernel_stats",
             "sph_mesh_kernel_count", "sph_mesh_kernel_name", "sph_mesh_sync",
-            "sph_mesh_device_bytes"]
+            "sph_mesh_device_bytes", "sph_batch_footprint", "sph_job_cells", "sph_batch_create",
+            "sph_batch_add", "sph_batch_remove", "sph_batch_step", "sph_batch_status",
+            "sph_batch_positions", "sph_batch_error", "sph_batch_counters", "sph_batch_destroy"]

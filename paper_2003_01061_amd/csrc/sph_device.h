@@ -16,10 +16,12 @@
 
 namespace sph {
 
-constexpr int MAXF = 64;        // features per job
+constexpr int MAXF = 64;        // features per job; a job's features own ids [64 s, 64 s + nf)
+constexpr int MAXJ = 64;        // jobs per batch
 constexpr int MAXH = 16;        // holes per job
 constexpr int MAXRING = 64;     // samples per averaging window
 constexpr int BLOCK = 256;
+constexpr int NSTRIPE = 64;     // copies of each atomic accumulator (spreads contention)
 
 // tuning knobs (compile time): records loaded together per neighbour batch,
 // and whether blocks are remapped so that each XCD gets a contiguous range
@@ -56,11 +58,12 @@ struct Geom {
   double h0, grad, dcap, hpt[3];
 };
 
-// uniform cell grid over the box; per-particle search radius
+// uniform cell grid over a job's box; its cells own the global cell ids
+// [cbase, cbase + ncell) of the batch; per-particle search radius
 // R_i = min(rfac h_i, rmax) (rfac from the Lipschitz bound of h_t)
 struct Grid {
   int32_t nc[3];
-  uint32_t ncell;
+  uint32_t ncell, cbase;
   double lo[3], inv_c[3], c[3];
   double rfac, rmax;
 };
@@ -83,18 +86,42 @@ struct Group {
   double ring[MAXRING];
 };
 
-struct Status {
-  unsigned long long escaped, inter_total, inter_last, inter_step, steps;
+// per-job counters and error flags
+struct JobStat {
+  unsigned long long escaped, inter_total, inter_last, steps;
   unsigned int nan_flag, nan_oid, overflow, overflow_max;
-  int32_t converged;
-  unsigned int scan_fail;     // a scan tile gave up waiting (never expected)
+  int32_t converged, live;
+};
+
+struct JobDev {
+  Geom g;
+  Grid G;
+  Ctl ctl;
+  double p0;
+  int32_t bw, nf, live, pad;
 };
 
 struct Parts {
   double4 *xh;      // x, y, z, h
   double4 *v;       // vx, vy, vz, 0
-  uint8_t *f;
-  uint32_t *oid;
+  uint16_t *f;      // global feature id = 64 * job slot + local feature
+  uint32_t *oid;    // caller's id inside the job
+};
+
+// tables and accumulators shared by every kernel of a batch
+struct Batch {
+  const JobDev *jobs;                 // [MAXJ]
+  const Feat *feat;                   // [MAXJ * MAXF]
+  const unsigned long long *bmask;    // [MAXJ * MAXF] bit l: local feature l bounds this one
+  const BNorm *bn;                    // [MAXJ * MAXF][MAXF]
+  Group *grp;                         // [MAXJ * MAXF]
+  JobStat *st;                        // [MAXJ]
+  unsigned int *gflags;               // [0] a scan tile gave up waiting (never expected)
+  unsigned long long *smin, *ssum;    // [MAXJ * MAXF][NSTRIPE] group minima / sums
+  unsigned long long *scnt, *sesc;    // [MAXJ][NSTRIPE] interactions / rejected moves
+  int n, cap;
+  uint32_t ncell, ntiles;
+  int njobs;                          // job slots in use: [0, njobs)
 };
 
 template <typename R>

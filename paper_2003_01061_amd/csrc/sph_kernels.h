@@ -11,13 +11,17 @@
 //   k_nbr_forces     ELL neighbour list (exact FP64 predicate + feature
 //                    relation) fused with the Shepard gamma, V~, pressure
 //                    force with the boundary term and its tangent projection
-//                    -> a^p; per-block minima of dt_1 and sums of V~
-//   k_group_reduce   fold per-block partials per feature (dt_1, V~ sum)
+//                    -> a^p; striped minima of dt_1 and sums of V~
+//   k_group_reduce   fold the striped accumulators per feature (dt_1, V~ sum)
 //   k_sweep_b        mid-point velocity on the fly, viscous force -> a
-//   k_group_reduce   fold per-block minima of dt
+//   k_group_reduce   fold the striped minima of dt
 //   k_integrate_hash v_{n+1/2}, x_{n+1}, projection / rejection, v_{n+1},
 //                    then h, cell and rank of every particle for the next step
 //   k_control        E_sys, phases, resets, damping of every feature (1 block)
+// A launch covers every job of a batch: particles carry a global feature id
+// (64 per job slot), every kernel reads its particle's job record, and a
+// job's cells occupy their own range of the batch's cell ids, so jobs never
+// interact and each job's result is the same alone or in any mix.
 #pragma once
 #include "sph_device.h"
 
@@ -32,29 +36,24 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
   return v;
 }
 
-// Per-group reduction of one block: every wave reduces each distinct group
-// among its valid lanes with xor shuffles, one lane folds the result into the
-// block's LDS slot with an LDS atomic, and the block writes one partial per
-// group.  Device-wide same-address atomics are avoided on purpose: with
-// thousands of waves they serialise.
-__device__ __forceinline__ void block_group_reduce(bool valid, int g, unsigned long long vmin,
-                                                   unsigned long long vadd,
-                                                   unsigned long long *s_min,
-                                                   unsigned long long *s_sum, int nf,
-                                                   unsigned long long *pmin,
-                                                   unsigned long long *psum) {
-  for (int t = threadIdx.x; t < nf; t += blockDim.x) {
-    s_min[t] = ~0ull;
-    s_sum[t] = 0ull;
-  }
-  __syncthreads();
+// Per-key reduction of one wave: each distinct key (a feature, or a job)
+// among the valid lanes is reduced with xor shuffles and committed by one lane
+// with a device atomic into one of NSTRIPE copies of the accumulator (chosen
+// by wave), so no address sees more than a few dozen atomics per launch.
+// Minima of non-negative double bit patterns and integer sums are exact and
+// order independent, so the result does not depend on scheduling or on which
+// other jobs share the launch.
+__device__ __forceinline__ void wave_commit(bool valid, int key, unsigned long long vmin,
+                                            unsigned long long vadd, unsigned long long *smin,
+                                            unsigned long long *ssum) {
+  const int stripe = (int)((blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6)) & (NSTRIPE - 1));
   unsigned long long mask = __ballot(valid);
   const int lane = __lane_id();
   while (mask) {
-    int leader = __ffsll((long long)mask) - 1;
-    int gl = __shfl(g, leader);
-    bool mine = valid && g == gl;
-    unsigned long long mm = __ballot(mine);
+    const int leader = __ffsll((long long)mask) - 1;
+    const int kl = __shfl(key, leader);
+    const bool mine = valid && key == kl;
+    const unsigned long long mm = __ballot(mine);
     unsigned long long mn = mine ? vmin : ~0ull;
     unsigned long long sm = mine ? vadd : 0ull;
     for (int o = 32; o > 0; o >>= 1) {
@@ -62,66 +61,39 @@ __device__ __forceinline__ void block_group_reduce(bool valid, int g, unsigned l
       sm += __shfl_xor(sm, o);
     }
     if (lane == leader) {
-      atomicMin(&s_min[gl], mn);
-      if (psum) atomicAdd(&s_sum[gl], sm);
+      if (smin) atomicMin(&smin[(size_t)kl * NSTRIPE + stripe], mn);
+      if (ssum && sm) atomicAdd(&ssum[(size_t)kl * NSTRIPE + stripe], sm);
     }
     mask &= ~mm;
   }
-  __syncthreads();
-  for (int t = threadIdx.x; t < nf; t += blockDim.x) {
-    pmin[(size_t)blockIdx.x * nf + t] = s_min[t];
-    if (psum) psum[(size_t)blockIdx.x * nf + t] = s_sum[t];
-  }
 }
 
-__device__ __forceinline__ void block_count(unsigned long long v, unsigned long long *s_cnt,
-                                            unsigned long long *out) {
-  unsigned long long tot = wave_sum_u64(v);
-  if (__lane_id() == 0) s_cnt[threadIdx.x >> 6] = tot;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned long long b = 0;
-    for (int w = 0; w < BLOCK / 64; ++w) b += s_cnt[w];
-    out[blockIdx.x] = b;
-  }
-}
-
-// one block per group: fold the per-block partials of group blockIdx.x;
-// which = 0 -> dt_1 and the V~ sum, which = 1 -> dt.  The time step is the
-// minimum of the particle terms and the cap dt_max.
-__global__ __launch_bounds__(BLOCK) void k_group_reduce(const unsigned long long *__restrict__ pmin,
-                                                        const unsigned long long *__restrict__ psum,
-                                                        int nblk, int nf, double dt_max, Group *grp,
-                                                        int which) {
-  __shared__ unsigned long long smn[BLOCK / 64], ssm[BLOCK / 64];
-  const int g = blockIdx.x;
+// one thread per feature slot: fold the stripes of every tracked feature and
+// reset them; which = 0 -> dt_1 and the V~ sum, which = 1 -> dt.  The time
+// step is the minimum of the particle terms and the job's cap dt_max.
+__global__ __launch_bounds__(BLOCK) void k_group_reduce(Batch B, int which) {
+  const int q = blockIdx.x * BLOCK + threadIdx.x;
+  if (q >= B.njobs * MAXF) return;
+  Group &G = B.grp[q];
+  if (!G.tracked) return;
+  unsigned long long *mp = B.smin + (size_t)q * NSTRIPE;
+  unsigned long long *sp = B.ssum + (size_t)q * NSTRIPE;
   unsigned long long mn = ~0ull, sm = 0ull;
-  for (int b = threadIdx.x; b < nblk; b += BLOCK) {
-    mn = umin64(mn, pmin[(size_t)b * nf + g]);
-    if (psum) sm += psum[(size_t)b * nf + g];
-  }
-  for (int o = 32; o > 0; o >>= 1) {
-    mn = umin64(mn, __shfl_xor(mn, o));
-    sm += __shfl_xor(sm, o);
-  }
-  const int w = threadIdx.x >> 6;
-  if (__lane_id() == 0) {
-    smn[w] = mn;
-    ssm[w] = sm;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int q = 1; q < BLOCK / 64; ++q) {
-      mn = umin64(mn, smn[q]);
-      sm += ssm[q];
-    }
-    mn = umin64(mn, dbits(dt_max));
+#pragma unroll 8
+  for (int t = 0; t < NSTRIPE; ++t) {
+    mn = umin64(mn, mp[t]);
+    mp[t] = ~0ull;
     if (which == 0) {
-      grp[g].dt1_bits = mn;
-      grp[g].vsum = sm;
-    } else {
-      grp[g].dt_bits = mn;
+      sm += sp[t];
+      sp[t] = 0ull;
     }
+  }
+  mn = umin64(mn, dbits(B.jobs[q / MAXF].ctl.dt_max));
+  if (which == 0) {
+    G.dt1_bits = mn;
+    G.vsum = sm;
+  } else {
+    G.dt_bits = mn;
   }
 }
 
@@ -135,7 +107,7 @@ __device__ __forceinline__ void hash_one(const Geom &g, const Grid &G, double4 &
   int c0 = cell_coord(G, 0, p[0]);
   int c1 = cell_coord(G, 1, p[1]);
   int c2 = D == 3 ? cell_coord(G, 2, p[2]) : 0;
-  cell = ((uint32_t)c2 * (uint32_t)G.nc[1] + (uint32_t)c1) * (uint32_t)G.nc[0] + (uint32_t)c0;
+  cell = G.cbase + ((uint32_t)c2 * (uint32_t)G.nc[1] + (uint32_t)c1) * (uint32_t)G.nc[0] + (uint32_t)c0;
 }
 
 // Rank of a particle inside its cell.  Lanes of a wave that hold the same
@@ -161,19 +133,20 @@ __device__ __forceinline__ uint32_t rank_in_cell(uint32_t c, bool valid, uint32_
   return __shfl(base, my_head) + (uint32_t)(lane - my_head);
 }
 
-// h, cell and rank inside the cell of every particle (set-up and test paths;
-// a step gets them from k_integrate_hash)
+// h, cell and rank inside the cell of the particles [i0, i1) (set-up and
+// test paths; a step gets them from k_integrate_hash)
 template <int D>
-__global__ __launch_bounds__(BLOCK) void k_hash(Geom g, Grid G, Parts s, int n,
+__global__ __launch_bounds__(BLOCK) void k_hash(Batch B, Parts s, int i0, int i1,
                                                 uint32_t *__restrict__ cell,
                                                 uint32_t *__restrict__ rank,
                                                 uint32_t *__restrict__ cnt) {
-  const int i = blockIdx.x * BLOCK + threadIdx.x;
-  const bool valid = i < n;
+  const int i = i0 + (int)(blockIdx.x * BLOCK + threadIdx.x);
+  const bool valid = i < i1;
   uint32_t c = 0;
   if (valid) {
+    const JobDev &J = B.jobs[s.f[i] / MAXF];
     double4 xh = s.xh[i];
-    hash_one<D>(g, G, xh, c);
+    hash_one<D>(J.g, J.G, xh, c);
     s.xh[i] = xh;
     cell[i] = c;
   }
@@ -212,14 +185,14 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *l
 __global__ __launch_bounds__(BLOCK) void k_scan(const uint32_t *__restrict__ in,
                                                 uint32_t *__restrict__ out, uint32_t n,
                                                 unsigned long long *status, uint32_t *ticket,
-                                                uint32_t ntiles, Status *st) {
+                                                uint32_t ntiles, unsigned int *gflags) {
   __shared__ uint32_t lds[BLOCK / 64];
   __shared__ uint32_t s_tile, s_prefix;
   if (threadIdx.x == 0) s_tile = atomicAdd(ticket, 1u);
   __syncthreads();
   const uint32_t tile = s_tile;
   if (tile >= ntiles) {            // stale ticket: report, never wait
-    if (threadIdx.x == 0) atomicExch(&st->scan_fail, 1u);
+    if (threadIdx.x == 0) atomicExch(&gflags[0], 1u);
     return;
   }
   const size_t base = (size_t)tile * SCAN_TILE + (size_t)threadIdx.x * SCAN_PER;
@@ -258,7 +231,7 @@ __global__ __launch_bounds__(BLOCK) void k_scan(const uint32_t *__restrict__ in,
       const unsigned long long upto = first2 >= 63 ? ~0ull : ((2ull << first2) - 1ull);
       if (m0 & upto) {
         if (++spins > (1u << 22)) {
-          if (lane == 0) atomicExch(&st->scan_fail, 1u);
+          if (lane == 0) atomicExch(&gflags[0], 1u);
           break;
         }
         __builtin_amdgcn_s_sleep(1);
@@ -342,7 +315,7 @@ __global__ __launch_bounds__(BLOCK) void k_rank_gather(int n, const uint32_t *__
 // ---------------------------------------------------------------------------
 template <int D, int K, typename R>
 __device__ __forceinline__ void sweep_a_sums(const Geom &g, const Parts &s,
-                                             const BNorm *__restrict__ bn, int bw, double p0,
+                                             const BNorm *__restrict__ bnrow, int bw, double p0,
                                              const uint32_t *__restrict__ nbr, int n, int i,
                                              uint32_t cnt, const double4 &xi, int fi, double &S,
                                              double &gam, double Pi[3], double B[3]) {
@@ -389,7 +362,7 @@ __device__ __forceinline__ void sweep_a_sums(const Geom &g, const Parts &s,
         if (D == 3) Pi[2] += (double)(c * dx2);
       } else {
         const int fj = s.f[u[q] & 0x7fffffffu];
-        const BNorm N = bn[fi * g.nf + fj];
+        const BNorm N = bnrow[fj & (MAXF - 1)];
         double nv[3];
         if (N.mode == 2) {
           const double *cc = g.hc[N.hole];
@@ -421,32 +394,32 @@ __device__ __forceinline__ void sweep_a_sums(const Geom &g, const Parts &s,
 // x_i, only the cells under the chord of the disc (sphere) of radius R_i, so
 // no neighbour is skipped and fewer non-neighbours are tested.  The pair sums
 // then run over the list just written, so the force math executes once per
-// neighbour instead of once per candidate.
+// neighbour instead of once per candidate.  Every particle reads its own
+// job's geometry and grid; cells of different jobs never meet.
 // ---------------------------------------------------------------------------
 template <int D, typename R, bool FORCES>
 __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
-    Geom g, Grid G, double p0, int bw, Parts s, int n, const uint32_t *__restrict__ cstart,
-    const unsigned long long *__restrict__ bmask, const Feat *__restrict__ feat,
-    const BNorm *__restrict__ bn, const Group *__restrict__ grp, int all,
-    uint32_t *__restrict__ nbr, uint32_t *__restrict__ nnb, int cap, Status *st,
-    typename Vec4<R>::T *__restrict__ ap, double *__restrict__ dbg_gam,
-    double *__restrict__ dbg_vt, unsigned long long *__restrict__ pmin,
-    unsigned long long *__restrict__ psum, unsigned long long *__restrict__ pcount) {
+    Batch B, Parts s, const uint32_t *__restrict__ cstart, int all, uint32_t *__restrict__ nbr,
+    uint32_t *__restrict__ nnb, typename Vec4<R>::T *__restrict__ ap,
+    double *__restrict__ dbg_gam, double *__restrict__ dbg_vt) {
   using R4 = typename Vec4<R>::T;
-  __shared__ unsigned long long s_min[MAXF], s_sum[MAXF], s_cnt[BLOCK / 64];
+  const int n = B.n;
   const int i = xcd_block() * BLOCK + threadIdx.x;
   bool act = false;
-  int fi = 0;
+  int fi = 0, job = 0;
   unsigned long long dtb = ~0ull, vfix = 0ull, mine = 0ull;
   if (i < n) {
     fi = s.f[i];
-    const Feat F = feat[fi];
-    const bool moving = F.type != T_SI && grp[fi].active;
-    const bool want = F.type != T_SI && (all || grp[fi].active);
+    job = fi / MAXF;
+    const JobDev &J = B.jobs[job];
+    const Feat F = B.feat[fi];
+    const bool moving = F.type != T_SI && B.grp[fi].active;
+    const bool want = F.type != T_SI && (all || B.grp[fi].active);
     act = FORCES && moving;
     uint32_t count = 0;
     const double4 xi = s.xh[i];
     if (want) {
+      const Grid &G = J.G;
       double Rs = G.rfac * xi.w;
       Rs = Rs < G.rmax ? Rs : G.rmax;
       const double R2 = Rs * Rs;
@@ -457,9 +430,11 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
         lo_c[a] = cell_coord(G, a, pc[a] - Rs);
         hi_c[a] = cell_coord(G, a, pc[a] + Rs);
       }
-      // features that bound fi (bit f set); a candidate of fi's own feature
-      // interacts as "same", one of a bounding feature as "boundary"
-      const unsigned long long bm = bmask[fi];
+      // features that bound fi (bit = local feature id); a candidate of fi's
+      // own feature interacts as "same", one of a bounding feature of the same
+      // job as "boundary"
+      const unsigned long long bm = B.bmask[fi];
+      const int jbase = job * MAXF;
       constexpr int NB = SPH_NBATCH;   // candidate records loaded together
       for (int cz = lo_c[2]; cz <= hi_c[2]; ++cz) {
         double dz2 = 0.0;
@@ -479,13 +454,14 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
           if (w2 < 0.0) continue;
           const double wx = __builtin_sqrt(w2) * (1.0 + 1e-9) + 1e-7 * G.c[0];
           const int cx0 = cell_coord(G, 0, pc[0] - wx), cx1 = cell_coord(G, 0, pc[0] + wx);
-          const uint32_t row = ((uint32_t)cz * (uint32_t)G.nc[1] + (uint32_t)cy) * (uint32_t)G.nc[0];
+          const uint32_t row =
+              G.cbase + ((uint32_t)cz * (uint32_t)G.nc[1] + (uint32_t)cy) * (uint32_t)G.nc[0];
           const uint32_t jb = cstart[row + cx0], je = cstart[row + cx1 + 1];
           for (uint32_t j0 = jb; j0 < je; j0 += NB) {
             double4 xr[NB];
             int fr[NB];
 #pragma unroll
-            for (int q = 0; q < NB; ++q) {   // records are padded by NB past n
+            for (int q = 0; q < NB; ++q) {   // records are padded by 8 past the capacity
               xr[q] = s.xh[j0 + q];
               fr[q] = s.f[j0 + q];
             }
@@ -495,39 +471,41 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
               if (j >= je) break;
               if ((int)j == i || !within<D>(xi, xr[q])) continue;
               const int fj = fr[q];
-              const int r = fj == fi ? 1 : (int)((bm >> fj) & 1ull) * 2;
+              const int lj = fj - jbase;
+              const int r = fj == fi ? 1 : ((unsigned)lj < (unsigned)MAXF ? (int)((bm >> lj) & 1ull) * 2 : 0);
               if (!r) continue;
-              if ((int)count < cap) nbr[(size_t)count * n + i] = j | (r == 2 ? 0x80000000u : 0u);
+              if ((int)count < B.cap) nbr[(size_t)count * n + i] = j | (r == 2 ? 0x80000000u : 0u);
               ++count;
             }
           }
         }
       }
-      if ((int)count > cap) {
-        atomicMax(&st->overflow_max, count);
-        atomicExch(&st->overflow, 1u);
-        count = cap;
+      if ((int)count > B.cap) {
+        atomicMax(&B.st[job].overflow_max, count);
+        atomicExch(&B.st[job].overflow, 1u);
+        count = B.cap;
       }
     }
     if (FORCES && act) {
       const int k = F.k;
       double4 v4 = s.v[i];
-      if (grp[fi].reset_now) {
+      if (B.grp[fi].reset_now) {
         v4 = make_double4(0.0, 0.0, 0.0, 0.0);
         s.v[i] = v4;
       }
-      double S, gam, Pi[3], B[3];
+      const BNorm *bnrow = B.bn + (size_t)fi * MAXF;
+      double S, gam, Pi[3], B3[3];
       if (k == D)
-        sweep_a_sums<D, D, R>(g, s, bn, bw, p0, nbr, n, i, count, xi, fi, S, gam, Pi, B);
+        sweep_a_sums<D, D, R>(J.g, s, bnrow, J.bw, J.p0, nbr, n, i, count, xi, fi, S, gam, Pi, B3);
       else if (k == D - 1)
-        sweep_a_sums<D, D - 1, R>(g, s, bn, bw, p0, nbr, n, i, count, xi, fi, S, gam, Pi, B);
+        sweep_a_sums<D, D - 1, R>(J.g, s, bnrow, J.bw, J.p0, nbr, n, i, count, xi, fi, S, gam, Pi, B3);
       else
-        sweep_a_sums<D, 1, R>(g, s, bn, bw, p0, nbr, n, i, count, xi, fi, S, gam, Pi, B);
+        sweep_a_sums<D, 1, R>(J.g, s, bnrow, J.bw, J.p0, nbr, n, i, count, xi, fi, S, gam, Pi, B3);
       double a3[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-      for (int a = 0; a < D; ++a) a3[a] = -((Pi[a] + B[a]) / gam);
+      for (int a = 0; a < D; ++a) a3[a] = -((Pi[a] + B3[a]) / gam);
       double xa[3] = {xi.x, xi.y, xi.z};
-      tangent<D>(g, F, xa, a3);
+      tangent<D>(J.g, F, xa, a3);
       R4 o;
       o.x = (R)a3[0];
       o.y = (R)a3[1];
@@ -548,7 +526,7 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
         dt = t < dt ? t : dt;
       }
       dtb = dbits(dt);
-      vfix = (unsigned long long)__builtin_llrint(vt * grp[fi].vscale);
+      vfix = (unsigned long long)__builtin_llrint(vt * B.grp[fi].vscale);
     } else if (FORCES) {
       R4 z;
       z.x = z.y = z.z = z.w = R(0);
@@ -559,8 +537,10 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
     nnb[i] = count;
     mine = count;
   }
-  if (FORCES) block_group_reduce(act, fi, dtb, vfix, s_min, s_sum, g.nf, pmin, psum);
-  if (pcount) block_count(mine, s_cnt, pcount);
+  if (FORCES) {
+    wave_commit(act, fi, dtb, vfix, B.smin, B.ssum);
+    wave_commit(i < n && mine != 0ull, job, 0ull, mine, nullptr, B.scnt);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -629,28 +609,26 @@ __device__ __forceinline__ void sweep_b_sums(const Parts &s, const typename Vec4
 // sweep B: mid-point velocity, viscous force, damping
 // ---------------------------------------------------------------------------
 template <int D, typename R>
-__global__ __launch_bounds__(BLOCK) void k_sweep_b(Geom g, Parts s, int n,
+__global__ __launch_bounds__(BLOCK) void k_sweep_b(Batch B, Parts s,
                                                    const uint32_t *__restrict__ nbr,
                                                    const uint32_t *__restrict__ nnb,
-                                                   const Feat *__restrict__ feat,
-                                                   const Group *__restrict__ grp,
                                                    const typename Vec4<R>::T *__restrict__ ap,
                                                    typename Vec4<R>::T *__restrict__ acc,
-                                                   double4 *__restrict__ dbg_vm,
-                                                   unsigned long long *__restrict__ pmin) {
+                                                   double4 *__restrict__ dbg_vm) {
   using R4 = typename Vec4<R>::T;
-  __shared__ unsigned long long s_min[MAXF], s_sum[MAXF];
+  const int n = B.n;
   const int i = xcd_block() * BLOCK + threadIdx.x;
   bool act = false;
   int fi = 0;
   unsigned long long dtb = ~0ull;
   if (i < n) {
     fi = s.f[i];
-    const Feat F = feat[fi];
-    act = F.type != T_SI && grp[fi].active;
+    const Feat F = B.feat[fi];
+    act = F.type != T_SI && B.grp[fi].active;
     if (act) {
+      const JobDev &J = B.jobs[fi / MAXF];
       const int k = F.k;
-      const double dt1 = bitsd(grp[fi].dt1_bits);
+      const double dt1 = bitsd(B.grp[fi].dt1_bits);
       const double half = 0.5 * dt1;
       const double4 xi = s.xh[i];
       const double4 v4 = s.v[i];
@@ -670,8 +648,8 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_b(Geom g, Parts s, int n,
       else
         sweep_b_sums<D, 1, R>(s, ap, nbr, n, i, cnt, xi, vti, vmi, half, fv);
       double xa[3] = {xi.x, xi.y, xi.z};
-      tangent<D>(g, F, xa, fv);
-      const double eps = grp[fi].eps;
+      tangent<D>(J.g, F, xa, fv);
+      const double eps = B.grp[fi].eps;
       double a3[3];
 #pragma unroll
       for (int a = 0; a < 3; ++a) a3[a] = api[a] + fv[a] - eps * vi[a];
@@ -698,7 +676,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_b(Geom g, Parts s, int n,
       if (dbg_vm) dbg_vm[i] = make_double4(0.0, 0.0, 0.0, 0.0);
     }
   }
-  block_group_reduce(act, fi, dtb, 0ull, s_min, s_sum, g.nf, pmin, nullptr);
+  wave_commit(act, fi, dtb, 0ull, B.smin, nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -707,19 +685,21 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_b(Geom g, Parts s, int n,
 // ---------------------------------------------------------------------------
 template <int D, typename R>
 __global__ __launch_bounds__(BLOCK) void k_integrate_hash(
-    Geom g, Grid G, Parts s, int n, const Feat *__restrict__ feat, const Group *__restrict__ grp,
-    const typename Vec4<R>::T *__restrict__ acc, Status *st, unsigned long long *__restrict__ pesc,
-    uint32_t *__restrict__ cell, uint32_t *__restrict__ rank, uint32_t *__restrict__ cnt) {
-  __shared__ unsigned long long s_esc[BLOCK / 64];
+    Batch B, Parts s, const typename Vec4<R>::T *__restrict__ acc, uint32_t *__restrict__ cell,
+    uint32_t *__restrict__ rank, uint32_t *__restrict__ cnt) {
+  const int n = B.n;
   const int i = blockIdx.x * BLOCK + threadIdx.x;
   bool escaped = false;
+  int job = 0;
   uint32_t cc = 0;
   if (i < n) {
     const int fi = s.f[i];
-    const Feat F = feat[fi];
+    job = fi / MAXF;
+    const JobDev &J = B.jobs[job];
+    const Feat F = B.feat[fi];
     double4 xh = s.xh[i];
-    if (F.type != T_SI && grp[fi].active) {
-      const double dt = bitsd(grp[fi].dt_bits);
+    if (F.type != T_SI && B.grp[fi].active) {
+      const double dt = bitsd(B.grp[fi].dt_bits);
       const auto a4 = acc[i];
       const double4 v4 = s.v[i];
       const double a3[3] = {(double)a4.x, (double)a4.y, (double)a4.z};
@@ -734,89 +714,77 @@ __global__ __launch_bounds__(BLOCK) void k_integrate_hash(
         finite = finite && __builtin_isfinite(xs[a]);
       }
       if (!finite) {
-        if (atomicExch(&st->nan_flag, 1u) == 0u) st->nan_oid = s.oid[i];
-      } else if (F.kind == K_VOL && !inside<D>(g, xs)) {
+        if (atomicExch(&B.st[job].nan_flag, 1u) == 0u) B.st[job].nan_oid = s.oid[i];
+      } else if (F.kind == K_VOL && !inside<D>(J.g, xs)) {
         escaped = true;                                   // rejected move: stay, stop
         s.v[i] = make_double4(0.0, 0.0, 0.0, 0.0);
       } else {
-        if (F.kind != K_VOL) project<D>(g, F, xs);
+        if (F.kind != K_VOL) project<D>(J.g, F, xs);
         double vn[3] = {0.0, 0.0, 0.0};
 #pragma unroll
         for (int a = 0; a < D; ++a) vn[a] = vh[a] + 0.5 * dt * a3[a];
-        if (F.kind != K_VOL) tangent<D>(g, F, xs, vn);
+        if (F.kind != K_VOL) tangent<D>(J.g, F, xs, vn);
         xh.x = xs[0];
         xh.y = xs[1];
         if (D == 3) xh.z = xs[2];
         s.v[i] = make_double4(vn[0], vn[1], D == 3 ? vn[2] : 0.0, 0.0);
       }
     }
-    hash_one<D>(g, G, xh, cc);
+    hash_one<D>(J.g, J.G, xh, cc);
     s.xh[i] = xh;
     cell[i] = cc;
   }
   const uint32_t r = rank_in_cell(cc, i < n, cnt);
   if (i < n) rank[i] = r;
-  unsigned long long m = __ballot(escaped);
-  if (__lane_id() == 0) s_esc[threadIdx.x >> 6] = (unsigned long long)__popcll(m);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned long long b = 0;
-    for (int w = 0; w < BLOCK / 64; ++w) b += s_esc[w];
-    pesc[blockIdx.x] = b;
-  }
+  wave_commit(escaped, job, 0ull, 1ull, nullptr, B.sesc);
 }
 
 // ---------------------------------------------------------------------------
-// control of every feature; prepares the next step (one block)
+// control of every feature of every job; prepares the next step (one block)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(BLOCK) void k_control(Ctl P, Group *grp, int nf, Status *st,
-                                                   const unsigned long long *__restrict__ pcount,
-                                                   int ncount,
-                                                   const unsigned long long *__restrict__ pesc,
-                                                   int nesc) {
-  __shared__ int moving;
-  __shared__ unsigned long long s_c[BLOCK / 64], s_e[BLOCK / 64];
-  const int q = threadIdx.x;
-  if (q == 0) moving = 0;
-  unsigned long long c = 0, e = 0;
-  for (int b = q; b < ncount; b += BLOCK) c += pcount[b];
-  for (int b = q; b < nesc; b += BLOCK) e += pesc[b];
-  c = wave_sum_u64(c);
-  e = wave_sum_u64(e);
-  if (__lane_id() == 0) {
-    s_c[q >> 6] = c;
-    s_e[q >> 6] = e;
-  }
+constexpr int CTL_BLOCK = 1024;
+
+__global__ __launch_bounds__(CTL_BLOCK) void k_control(Batch B) {
+  __shared__ int moving[MAXJ];
+  for (int j = threadIdx.x; j < MAXJ; j += CTL_BLOCK) moving[j] = 0;
   __syncthreads();
-  if (q < nf) {
-    Group &Gq = grp[q];
-    if (Gq.tracked && Gq.phase != PH_FROZEN) {
+  for (int q = threadIdx.x; q < B.njobs * MAXF; q += CTL_BLOCK) {
+    Group &Gq = B.grp[q];
+    if (!Gq.tracked) continue;
+    const Ctl &P = B.jobs[q / MAXF].ctl;
+    if (Gq.phase != PH_FROZEN) {
       const double dt1 = bitsd(Gq.dt1_bits), dt = bitsd(Gq.dt_bits);
       const double vbar = (double)Gq.vsum / Gq.vscale;
       Gq.dt1 = dt1;
       Gq.dt = dt;
       control_law(P, Gq, vbar, dt);
     }
-    Gq.active = Gq.tracked && Gq.phase != PH_FROZEN;
+    Gq.active = Gq.phase != PH_FROZEN;
     Gq.reset_now = Gq.reset_next;
     Gq.eps = damping(P, Gq);
-    if (Gq.active) atomicOr(&moving, 1);
+    if (Gq.active) atomicOr(&moving[q / MAXF], 1);
   }
   __syncthreads();
-  if (q == 0) {
-    unsigned long long ct = 0, et = 0;
-    for (int w = 0; w < BLOCK / 64; ++w) {
-      ct += s_c[w];
-      et += s_e[w];
+  for (int j = threadIdx.x; j < B.njobs; j += CTL_BLOCK) {
+    JobStat &S = B.st[j];
+    unsigned long long c = 0, e = 0;
+    unsigned long long *cp = B.scnt + (size_t)j * NSTRIPE, *ep = B.sesc + (size_t)j * NSTRIPE;
+    for (int t = 0; t < NSTRIPE; ++t) {
+      c += cp[t];
+      e += ep[t];
+      cp[t] = 0ull;
+      ep[t] = 0ull;
     }
-    st->steps += 1ull;
-    st->inter_last = ct;
-    st->inter_total += ct;
-    st->escaped += et;
-    st->converged = moving ? 0 : 1;
+    if (!S.live) continue;
+    if (!S.converged) S.steps += 1ull;     // a converged job stops counting
+    S.inter_last = c;
+    S.inter_total += c;
+    S.escaped += e;
+    S.converged = moving[j] ? 0 : 1;
   }
 }
 
+// ---------------------------------------------------------------------------
 // the control law alone over a synthetic series (test entry point)
 __global__ void k_control_replay(Ctl P, int n, const double *__restrict__ vbar,
                                  const double *__restrict__ dt, int32_t *__restrict__ phase,

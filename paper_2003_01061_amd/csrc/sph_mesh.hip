@@ -1,11 +1,16 @@
 // sph_mesh.hip -- host runtime and C ABI of libsphmesh.so (include/sph_mesh.h).
 //
-// One handle = one relaxation job: device-resident particle columns (double
-// buffered for the per-step counting sort), the cell grid, the ELL neighbour
-// list, the per-feature group table and a status block.  sph_mesh_step only
-// enqueues kernels (optionally as a replayed HIP graph of two steps, so the
-// double-buffer parity is the same at every replay); control decisions are
-// taken on the device, and the host reads state back only when asked.
+// A batch holds any number of relaxation jobs (up to 64) in one set of
+// device arrays: particle columns double buffered for the per-step counting
+// sort, one cell table in which every job owns a contiguous range of cells,
+// one ELL neighbour list, and per-job tables of features, feature groups and
+// counters.  A step is one launch sequence over all resident particles,
+// whatever job they belong to, so small jobs share the chip instead of each
+// filling a fraction of it.  sph_batch_step only enqueues kernels
+// (optionally as a replayed HIP graph of two steps, so the double-buffer
+// parity is the same at every replay); control decisions are taken on the
+// device, and the host reads state back only when asked.  The single-job
+// handle sph_mesh is a batch holding one job.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -158,193 +163,7 @@ T *dalloc(size_t count, std::vector<void *> &owned, size_t &bytes) {
 
 }  // namespace
 
-struct sph_mesh {
-  int D = 2, n = 0, nf = 0, prec = SPH_FP64, cap = 64, bw = 0;
-  double p0 = 1.0;
-  Geom geom{};
-  Grid grid{};
-  Ctl ctl{};
-  std::vector<HFeat> feats;
-  hipStream_t stream = nullptr;
-  bool own_stream = false;
-  bool use_graph = false, debug = false;
-  // device memory
-  std::vector<void *> owned;
-  size_t bytes = 0;
-  Parts P[2]{};
-  int cur = 0;
-  uint32_t *cell = nullptr, *rank = nullptr, *psrc = nullptr, *pkey = nullptr;
-  uint32_t *cnt = nullptr, *cstart = nullptr, *ticket = nullptr;
-  unsigned long long *scan_status = nullptr;
-  uint32_t *nbr = nullptr, *nnb = nullptr;
-  void *ap = nullptr, *acc = nullptr;              // {ax, ay, az, 0} in the sweep precision
-  double *dbg_gam = nullptr, *dbg_vt = nullptr;
-  double4 *dbg_vm = nullptr;
-  Feat *d_feat = nullptr;
-  BNorm *d_bn = nullptr;
-  int8_t *d_rel = nullptr;
-  unsigned long long *d_bmask = nullptr;   // per feature: bit f set if feature f bounds it
-  Group *d_grp = nullptr;
-  Status *d_st = nullptr;
-  uint32_t nscan_tiles = 0;
-  int nblk = 0;                                 // particle blocks of one launch
-  int nblk8 = 0;                                // rounded up to the 8 XCDs
-  unsigned long long *pmin = nullptr, *psum = nullptr, *pcount = nullptr, *pesc = nullptr;
-  // graph of two steps
-  hipGraphExec_t gexec = nullptr;
-  // profiling
-  bool profiling = false;
-  struct Ev { int kid; hipEvent_t a, b; };
-  std::vector<Ev> ev_live;
-  std::vector<hipEvent_t> ev_pool;
-  double kms[KID_COUNT] = {};
-  long long kcount[KID_COUNT] = {};
 
-  ~sph_mesh() {
-    if (stream) (void)hipStreamSynchronize(stream);
-    if (gexec) (void)hipGraphExecDestroy(gexec);
-    for (auto &e : ev_live) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
-    for (auto e : ev_pool) (void)hipEventDestroy(e);
-    for (void *p : owned) (void)hipFree(p);
-    if (own_stream && stream) (void)hipStreamDestroy(stream);
-  }
-
-  hipEvent_t get_event() {
-    if (!ev_pool.empty()) {
-      hipEvent_t e = ev_pool.back();
-      ev_pool.pop_back();
-      return e;
-    }
-    hipEvent_t e = nullptr;
-    (void)hipEventCreate(&e);
-    return e;
-  }
-
-  template <typename K, typename... A>
-  hipError_t launch(int kid, K kern, unsigned grid, unsigned block, A... args) {
-    if (grid == 0) return hipSuccess;
-    hipEvent_t a = nullptr, b = nullptr;
-    if (profiling) {
-      a = get_event();
-      (void)hipEventRecord(a, stream);
-    }
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, stream, args...);
-    hipError_t e = hipGetLastError();
-    if (profiling) {
-      b = get_event();
-      (void)hipEventRecord(b, stream);
-      ev_live.push_back({kid, a, b});
-    }
-    return e;
-  }
-
-  unsigned blocks(size_t count) const { return (unsigned)((count + BLOCK - 1) / BLOCK); }
-
-  template <int DD>
-  sph_status enqueue_hash() {
-    HIPCHK(launch(KID_HASH, k_hash<DD>, blocks(n), BLOCK, geom, grid, P[cur], n, cell, rank, cnt));
-    return SPH_OK;
-  }
-
-  // counting sort of the current particles into (cell, caller id) order;
-  // needs cell / rank / cnt of the current buffer, leaves cnt cleared
-  sph_status enqueue_sort() {
-    HIPCHK(launch(KID_SCAN, k_scan, nscan_tiles, BLOCK, (const uint32_t *)cnt, cstart, grid.ncell,
-                  scan_status, ticket, nscan_tiles, d_st));
-    HIPCHK(launch(KID_SCATTER, k_scatter, blocks(n), BLOCK, n, (const uint32_t *)cell,
-                  (const uint32_t *)rank, (const uint32_t *)cstart, (const uint32_t *)P[cur].oid,
-                  psrc, pkey, scan_status, nscan_tiles, ticket));
-    HIPCHK(launch(KID_RANK_GATHER, k_rank_gather, blocks(n), BLOCK, n, (const uint32_t *)psrc,
-                  (const uint32_t *)pkey, (const uint32_t *)cell, (const uint32_t *)cstart, cnt,
-                  P[cur], P[1 - cur]));
-    cur = 1 - cur;
-    return SPH_OK;
-  }
-
-  template <int DD>
-  sph_status enqueue_lists_only() {
-    HIPCHK(launch(KID_NBR_LISTS, k_nbr_forces<DD, double, false>, (unsigned)nblk8, BLOCK, geom,
-                  grid, p0, bw, P[cur], n, (const uint32_t *)cstart, (const unsigned long long *)d_bmask,
-                  (const Feat *)d_feat, (const BNorm *)d_bn, (const Group *)d_grp, 1, nbr, nnb, cap,
-                  d_st, (double4 *)nullptr, (double *)nullptr, (double *)nullptr,
-                  (unsigned long long *)nullptr, (unsigned long long *)nullptr,
-                  (unsigned long long *)nullptr));
-    return SPH_OK;
-  }
-
-  template <int DD, typename R>
-  sph_status enqueue_forces() {
-    using R4 = typename Vec4<R>::T;
-    Parts &s = P[cur];
-    HIPCHK(launch(KID_NBR_FORCES, k_nbr_forces<DD, R, true>, (unsigned)nblk8, BLOCK, geom, grid, p0,
-                  bw, s, n, (const uint32_t *)cstart, (const unsigned long long *)d_bmask,
-                  (const Feat *)d_feat,
-                  (const BNorm *)d_bn, (const Group *)d_grp, 0, nbr, nnb, cap, d_st, (R4 *)ap,
-                  dbg_gam, dbg_vt, pmin, psum, pcount));
-    HIPCHK(launch(KID_REDUCE_A, k_group_reduce, (unsigned)nf, BLOCK,
-                  (const unsigned long long *)pmin, (const unsigned long long *)psum, nblk8, nf,
-                  ctl.dt_max, d_grp, 0));
-    HIPCHK(launch(KID_SWEEP_B, k_sweep_b<DD, R>, (unsigned)nblk8, BLOCK, geom, s, n,
-                  (const uint32_t *)nbr, (const uint32_t *)nnb, (const Feat *)d_feat,
-                  (const Group *)d_grp, (const R4 *)ap, (R4 *)acc, dbg_vm, pmin));
-    HIPCHK(launch(KID_REDUCE_B, k_group_reduce, (unsigned)nf, BLOCK,
-                  (const unsigned long long *)pmin, (const unsigned long long *)nullptr, nblk8, nf,
-                  ctl.dt_max, d_grp, 1));
-    HIPCHK(launch(KID_INTEGRATE_HASH, k_integrate_hash<DD, R>, blocks(n), BLOCK, geom, grid, s, n,
-                  (const Feat *)d_feat, (const Group *)d_grp, (const R4 *)acc, d_st, pesc, cell,
-                  rank, cnt));
-    HIPCHK(launch(KID_CONTROL, k_control, 1u, BLOCK, ctl, d_grp, nf, d_st,
-                  (const unsigned long long *)pcount, nblk8, (const unsigned long long *)pesc,
-                  nblk));
-    return SPH_OK;
-  }
-
-  sph_status enqueue_step() {
-    if (sph_status st = enqueue_sort()) return st;
-    if (D == 2) return prec == SPH_FP64 ? enqueue_forces<2, double>() : enqueue_forces<2, float>();
-    return prec == SPH_FP64 ? enqueue_forces<3, double>() : enqueue_forces<3, float>();
-  }
-
-  sph_status hash_now() { return D == 2 ? enqueue_hash<2>() : enqueue_hash<3>(); }
-
-  sph_status build_graph() {
-    if (gexec) return SPH_OK;
-    const int saved = cur;
-    hipGraph_t graph = nullptr;
-    HIPCHK(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
-    sph_status st = enqueue_step();
-    if (!st) st = enqueue_step();
-    hipError_t e = hipStreamEndCapture(stream, &graph);
-    cur = saved;
-    if (st) {
-      if (graph) (void)hipGraphDestroy(graph);
-      return st;
-    }
-    if (e != hipSuccess) return fail(SPH_ERR_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
-    e = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(graph);
-    if (e != hipSuccess) {
-      gexec = nullptr;
-      return fail(SPH_ERR_DEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
-    }
-    return SPH_OK;
-  }
-
-  sph_status check_status() {
-    Status s{};
-    HIPCHK(hipMemcpy(&s, d_st, sizeof s, hipMemcpyDeviceToHost));
-    if (s.nan_flag) return fail(SPH_ERR_STATE, "non-finite position of particle %u", s.nan_oid);
-    if (s.scan_fail) return fail(SPH_ERR_DEVICE, "cell-count scan lost a tile");
-    if (s.overflow)
-      return fail(SPH_ERR_STATE, "neighbour list overflow: %u neighbours > capacity %d "
-                                 "(raise max_neighbors)", s.overflow_max, cap);
-    return SPH_OK;
-  }
-};
-
-// ---------------------------------------------------------------------------
-// creation
-// ---------------------------------------------------------------------------
 static sph_status validate(const sph_geometry *g, const sph_sizing *s, const sph_params *p) {
   if (!g || !s || !p) return fail(SPH_ERR_INVALID_ARG, "null geometry, sizing or params");
   if (g->dim != 2 && g->dim != 3) return fail(SPH_ERR_INVALID_ARG, "dim must be 2 or 3");
@@ -421,38 +240,306 @@ static void sizing_bounds(const sph_geometry *g, const sph_sizing *s, double &hm
   lip = s->h0 * s->grad;
 }
 
-extern "C" sph_status sph_mesh_create(const sph_geometry *g, const sph_sizing *s,
-                                      const sph_params *p, int64_t n, const double *xyz,
-                                      const int32_t *feature, sph_mesh **out) {
-  if (!out) return fail(SPH_ERR_INVALID_ARG, "out is NULL");
-  *out = nullptr;
-  if (sph_status st = validate(g, s, p)) return st;
-  if (n < 0 || n > 0x7fffffff || (n > 0 && (!xyz || !feature)))
-    return fail(SPH_ERR_INVALID_ARG, "bad particle count or NULL particle arrays");
-  const int D = g->dim;
-  auto feats = make_features(D, g->n_holes);
-  const int nf = (int)feats.size();
-  if (nf > MAXF) return fail(SPH_ERR_UNSUPPORTED, "too many features (%d > %d)", nf, MAXF);
-  for (int64_t i = 0; i < n; ++i)
-    if (feature[i] < 0 || feature[i] >= nf)
-      return fail(SPH_ERR_INVALID_ARG, "particle %lld: feature %d out of range [0, %d)",
-                  (long long)i, feature[i], nf);
 
-  auto *M = new sph_mesh();
-  M->D = D;
-  M->n = (int)n;
-  M->nf = nf;
-  M->feats = feats;
-  M->prec = p->precision;
-  M->cap = p->max_neighbors ? p->max_neighbors : (D == 2 ? 64 : 160);
-  M->bw = p->boundary_weighting;
-  M->p0 = p->p0;
-  M->use_graph = p->use_graph != 0;
-  M->debug = p->debug_fields != 0;
-  // geometry + sizing record
-  Geom &G = M->geom;
+
+// copy a device column (slot order) to a host vector
+template <typename T>
+static hipError_t pull(std::vector<T> &h, const void *d, size_t count) {
+  h.resize(count);
+  if (!count) return hipSuccess;
+  return hipMemcpy(h.data(), d, count * sizeof(T), hipMemcpyDeviceToHost);
+}
+
+// ---------------------------------------------------------------------------
+// a batch: resident jobs sharing one set of device arrays and one launch
+// sequence per step
+// ---------------------------------------------------------------------------
+struct HostJob {
+  bool live = false;
+  int n = 0;
+  uint32_t ncell = 0, cbase = 0;
+  int nf = 0;
+  std::vector<HFeat> feats;
+  JobDev dev{};
+};
+
+struct sph_batch {
+  int D = 2, prec = SPH_FP64, cap = 64;
+  bool use_graph = false, debug = false;
+  int ncap = 0, jcap = 0;
+  uint32_t ccap = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::vector<void *> owned;
+  size_t bytes = 0;
+  Parts P[2]{};
+  int cur = 0;
+  uint32_t *cell = nullptr, *rank = nullptr, *psrc = nullptr, *pkey = nullptr;
+  uint32_t *cnt = nullptr, *cstart = nullptr, *ticket = nullptr;
+  unsigned long long *scan_status = nullptr;
+  uint32_t *nbr = nullptr, *nnb = nullptr;
+  void *ap = nullptr, *acc = nullptr;              // {ax, ay, az, 0} in the sweep precision
+  double *dbg_gam = nullptr, *dbg_vt = nullptr;
+  double4 *dbg_vm = nullptr;
+  JobDev *d_jobs = nullptr;
+  Feat *d_feat = nullptr;
+  unsigned long long *d_bmask = nullptr;
+  BNorm *d_bn = nullptr;
+  Group *d_grp = nullptr;
+  JobStat *d_st = nullptr;
+  unsigned int *d_gflags = nullptr;
+  unsigned long long *smin = nullptr, *ssum = nullptr, *scnt = nullptr, *sesc = nullptr;
+  std::vector<HostJob> jobs;
+  int n = 0, njobs = 0;
+  uint32_t ncell = 0;
+  hipGraphExec_t gexec = nullptr;
+  // profiling
+  bool profiling = false;
+  struct Ev {
+    int kid;
+    hipEvent_t a, b;
+  };
+  std::vector<Ev> ev_live;
+  std::vector<hipEvent_t> ev_pool;
+  double kms[KID_COUNT] = {};
+  long long kcount[KID_COUNT] = {};
+
+  ~sph_batch() {
+    if (stream) (void)hipStreamSynchronize(stream);
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    for (auto &e : ev_live) {
+      (void)hipEventDestroy(e.a);
+      (void)hipEventDestroy(e.b);
+    }
+    for (auto e : ev_pool) (void)hipEventDestroy(e);
+    for (void *p : owned) (void)hipFree(p);
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
+  }
+
+  Batch dev() const {
+    Batch B;
+    B.jobs = d_jobs;
+    B.feat = d_feat;
+    B.bmask = d_bmask;
+    B.bn = d_bn;
+    B.grp = d_grp;
+    B.st = d_st;
+    B.gflags = d_gflags;
+    B.smin = smin;
+    B.ssum = ssum;
+    B.scnt = scnt;
+    B.sesc = sesc;
+    B.n = n;
+    B.cap = cap;
+    B.ncell = ncell;
+    B.ntiles = ntiles();
+    B.njobs = njobs;
+    return B;
+  }
+  uint32_t ntiles() const { return (ncell + SCAN_TILE - 1) / SCAN_TILE; }
+  unsigned blocks(size_t count) const { return (unsigned)((count + BLOCK - 1) / BLOCK); }
+  unsigned blocks8(size_t count) const { return (blocks(count) + 7u) / 8u * 8u; }
+
+  void invalidate_graph() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    gexec = nullptr;
+  }
+
+  hipEvent_t get_event() {
+    if (!ev_pool.empty()) {
+      hipEvent_t e = ev_pool.back();
+      ev_pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+  }
+
+  template <typename K, typename... A>
+  hipError_t launch(int kid, K kern, unsigned grid, unsigned block, A... args) {
+    if (grid == 0) return hipSuccess;
+    hipEvent_t a = nullptr, b = nullptr;
+    if (profiling) {
+      a = get_event();
+      (void)hipEventRecord(a, stream);
+    }
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, stream, args...);
+    hipError_t e = hipGetLastError();
+    if (profiling) {
+      b = get_event();
+      (void)hipEventRecord(b, stream);
+      ev_live.push_back({kid, a, b});
+    }
+    return e;
+  }
+
+  sph_status hash_range(int i0, int i1) {
+    if (i1 <= i0) return SPH_OK;
+    if (D == 2)
+      HIPCHK(launch(KID_HASH, k_hash<2>, blocks(i1 - i0), BLOCK, dev(), P[cur], i0, i1, cell, rank, cnt));
+    else
+      HIPCHK(launch(KID_HASH, k_hash<3>, blocks(i1 - i0), BLOCK, dev(), P[cur], i0, i1, cell, rank, cnt));
+    return SPH_OK;
+  }
+
+  // counting sort of the current particles into (cell, caller id) order;
+  // needs cell / rank / cnt of the current buffer, leaves cnt cleared
+  sph_status enqueue_sort() {
+    const Batch B = dev();
+    HIPCHK(launch(KID_SCAN, k_scan, B.ntiles, BLOCK, (const uint32_t *)cnt, cstart, ncell,
+                  scan_status, ticket, B.ntiles, d_gflags));
+    HIPCHK(launch(KID_SCATTER, k_scatter, blocks(n), BLOCK, n, (const uint32_t *)cell,
+                  (const uint32_t *)rank, (const uint32_t *)cstart, (const uint32_t *)P[cur].oid,
+                  psrc, pkey, scan_status, B.ntiles, ticket));
+    HIPCHK(launch(KID_RANK_GATHER, k_rank_gather, blocks(n), BLOCK, n, (const uint32_t *)psrc,
+                  (const uint32_t *)pkey, (const uint32_t *)cell, (const uint32_t *)cstart, cnt,
+                  P[cur], P[1 - cur]));
+    cur = 1 - cur;
+    return SPH_OK;
+  }
+
+  template <int DD>
+  sph_status enqueue_lists_only() {
+    HIPCHK(launch(KID_NBR_LISTS, k_nbr_forces<DD, double, false>, blocks8(n), BLOCK, dev(), P[cur],
+                  (const uint32_t *)cstart, 1, nbr, nnb, (double4 *)nullptr, (double *)nullptr,
+                  (double *)nullptr));
+    return SPH_OK;
+  }
+
+  template <int DD, typename R>
+  sph_status enqueue_forces() {
+    using R4 = typename Vec4<R>::T;
+    const Batch B = dev();
+    const Parts &s = P[cur];
+    const unsigned gslots = (unsigned)((njobs * MAXF + BLOCK - 1) / BLOCK);
+    HIPCHK(launch(KID_NBR_FORCES, k_nbr_forces<DD, R, true>, blocks8(n), BLOCK, B, s,
+                  (const uint32_t *)cstart, 0, nbr, nnb, (R4 *)ap, dbg_gam, dbg_vt));
+    HIPCHK(launch(KID_REDUCE_A, k_group_reduce, gslots, BLOCK, B, 0));
+    HIPCHK(launch(KID_SWEEP_B, k_sweep_b<DD, R>, blocks8(n), BLOCK, B, s, (const uint32_t *)nbr,
+                  (const uint32_t *)nnb, (const R4 *)ap, (R4 *)acc, dbg_vm));
+    HIPCHK(launch(KID_REDUCE_B, k_group_reduce, gslots, BLOCK, B, 1));
+    HIPCHK(launch(KID_INTEGRATE_HASH, k_integrate_hash<DD, R>, blocks(n), BLOCK, B, s,
+                  (const R4 *)acc, cell, rank, cnt));
+    HIPCHK(launch(KID_CONTROL, k_control, 1u, (unsigned)CTL_BLOCK, B));
+    return SPH_OK;
+  }
+
+  sph_status enqueue_step() {
+    if (n == 0) return SPH_OK;
+    if (sph_status st = enqueue_sort()) return st;
+    if (D == 2) return prec == SPH_FP64 ? enqueue_forces<2, double>() : enqueue_forces<2, float>();
+    return prec == SPH_FP64 ? enqueue_forces<3, double>() : enqueue_forces<3, float>();
+  }
+
+  sph_status build_graph() {
+    if (gexec) return SPH_OK;
+    const int saved = cur;
+    hipGraph_t graph = nullptr;
+    HIPCHK(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+    sph_status st = enqueue_step();
+    if (!st) st = enqueue_step();
+    hipError_t e = hipStreamEndCapture(stream, &graph);
+    cur = saved;
+    if (st) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return st;
+    }
+    if (e != hipSuccess) return fail(SPH_ERR_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      gexec = nullptr;
+      return fail(SPH_ERR_DEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
+    }
+    return SPH_OK;
+  }
+
+  sph_status step(int n_steps) {
+    int left = n_steps;
+    if (n == 0) return SPH_OK;
+    if (use_graph && !profiling) {
+      if (left > 0 && cur != 0) {   // graphs are captured at parity 0
+        if (sph_status st = enqueue_step()) return st;
+        --left;
+      }
+      if (left >= 2) {
+        if (sph_status st = build_graph()) return st;
+        for (; left >= 2; left -= 2) HIPCHK(hipGraphLaunch(gexec, stream));
+      }
+    }
+    for (; left > 0; --left)
+      if (sph_status st = enqueue_step()) return st;
+    return SPH_OK;
+  }
+
+  // first slot of job j in the particle order (jobs are ordered by cell base)
+  int job_first(int j) const {
+    int first = 0;
+    for (int k = 0; k < njobs; ++k)
+      if (jobs[k].live && k != j && jobs[k].cbase < jobs[j].cbase) first += jobs[k].n;
+    return first;
+  }
+
+  sph_status check_job(int j) {
+    JobStat s{};
+    unsigned int gf = 0;
+    HIPCHK(hipMemcpy(&s, d_st + j, sizeof s, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(&gf, d_gflags, sizeof gf, hipMemcpyDeviceToHost));
+    if (gf) return fail(SPH_ERR_DEVICE, "cell-count scan lost a tile");
+    if (s.nan_flag) return fail(SPH_ERR_STATE, "non-finite position of particle %u", s.nan_oid);
+    if (s.overflow)
+      return fail(SPH_ERR_STATE, "neighbour list overflow: %u neighbours > capacity %d "
+                                 "(raise max_neighbors)", s.overflow_max, cap);
+    return SPH_OK;
+  }
+
+  bool valid_job(int j) const { return j >= 0 && j < njobs && jobs[j].live; }
+};
+
+// ---------------------------------------------------------------------------
+// job description -> host job record
+// ---------------------------------------------------------------------------
+static void grid_of(const sph_geometry *g, const sph_sizing *s, const sph_params *p, Grid &Gr) {
+  const int D = g->dim;
+  double hmin, hmax, lip;
+  sizing_bounds(g, s, hmin, hmax, lip);
+  const double cf = p->cell_factor > 0 ? p->cell_factor : 1.0;
+  double side = 2.0 * hmin * cf;
+  for (;;) {
+    double cells = 1.0;
+    for (int a = 0; a < D; ++a) cells *= std::max(1.0, std::floor((g->hi[a] - g->lo[a]) / side));
+    if (cells <= 16.0 * 1024 * 1024) break;
+    side *= 1.25;
+  }
+  std::memset(&Gr, 0, sizeof Gr);
+  Gr.ncell = 1;
+  for (int a = 0; a < 3; ++a) {
+    Gr.lo[a] = g->lo[a];
+    if (a < D) {
+      Gr.nc[a] = (int)std::max(1.0, std::floor((g->hi[a] - g->lo[a]) / side));
+      Gr.inv_c[a] = Gr.nc[a] / (g->hi[a] - g->lo[a]);
+      Gr.c[a] = (g->hi[a] - g->lo[a]) / Gr.nc[a];
+    } else {
+      Gr.nc[a] = 1;
+    }
+    Gr.ncell *= (uint32_t)Gr.nc[a];
+  }
+  Gr.rmax = 2.0 * hmax * (1.0 + 1e-9);
+  Gr.rfac = 2.0 * lip < 0.9 ? 2.0 * (1.0 + 1e-9) / (1.0 - 2.0 * lip) : 1e300;
+}
+
+static void fill_job(HostJob &J, const sph_geometry *g, const sph_sizing *s, const sph_params *p,
+                     uint32_t cbase, int n) {
+  const int D = g->dim;
+  J.feats = make_features(D, g->n_holes);
+  J.nf = (int)J.feats.size();
+  J.n = n;
+  JobDev &d = J.dev;
+  std::memset(&d, 0, sizeof d);
+  Geom &G = d.g;
   G.dim = D;
-  G.nf = nf;
+  G.nf = J.nf;
   G.nh = g->n_holes;
   G.hkind = s->kind;
   for (int a = 0; a < 3; ++a) {
@@ -467,8 +554,11 @@ extern "C" sph_status sph_mesh_create(const sph_geometry *g, const sph_sizing *s
   G.h0 = s->h0;
   G.grad = s->grad;
   G.dcap = s->dcap;
-  // control
-  Ctl &C = M->ctl;
+  grid_of(g, s, p, d.G);
+  d.G.cbase = cbase;
+  J.ncell = d.G.ncell;
+  J.cbase = cbase;
+  Ctl &C = d.ctl;
   C.tol = p->tol;
   C.eps_damp = p->eps_damp;
   C.dt_max = p->dt_max;
@@ -479,107 +569,194 @@ extern "C" sph_status sph_mesh_create(const sph_geometry *g, const sph_sizing *s
   C.ramp_halving = p->ramp_halving;
   C.phase2_steps = p->phase2_steps;
   C.max_phase1_steps = p->max_phase1_steps;
-  // cell grid: side 2 h_min cell_factor; search radius from the Lipschitz bound
-  double hmin, hmax, lip;
-  sizing_bounds(g, s, hmin, hmax, lip);
-  Grid &Gr = M->grid;
-  const double cf = p->cell_factor > 0 ? p->cell_factor : 1.0;
-  double side = 2.0 * hmin * cf;
-  for (;;) {
-    double cells = 1.0;
-    for (int a = 0; a < D; ++a) cells *= std::max(1.0, std::floor((g->hi[a] - g->lo[a]) / side));
-    if (cells <= 16.0 * 1024 * 1024) break;
-    side *= 1.25;
-  }
-  Gr.ncell = 1;
-  for (int a = 0; a < 3; ++a) {
-    Gr.lo[a] = g->lo[a];
-    if (a < D) {
-      Gr.nc[a] = (int)std::max(1.0, std::floor((g->hi[a] - g->lo[a]) / side));
-      Gr.inv_c[a] = Gr.nc[a] / (g->hi[a] - g->lo[a]);
-      Gr.c[a] = (g->hi[a] - g->lo[a]) / Gr.nc[a];
-    } else {
-      Gr.nc[a] = 1;
-      Gr.inv_c[a] = 0.0;
-      Gr.c[a] = 0.0;
-    }
-    Gr.ncell *= (uint32_t)Gr.nc[a];
-  }
-  Gr.rmax = 2.0 * hmax * (1.0 + 1e-9);
-  Gr.rfac = 2.0 * lip < 0.9 ? 2.0 * (1.0 + 1e-9) / (1.0 - 2.0 * lip) : 1e300;
-  M->nscan_tiles = (Gr.ncell + SCAN_TILE - 1) / SCAN_TILE;
+  d.p0 = p->p0;
+  d.bw = p->boundary_weighting;
+  d.nf = J.nf;
+  d.live = 1;
+}
 
-  // stream
-  if (p->stream) {
-    M->stream = (hipStream_t)p->stream;
+static int64_t default_cap(int D) { return D == 2 ? 64 : 160; }
+
+// particle arrays of a job: count, non-NULL arrays, finite coordinates,
+// feature ids of the geometry
+static sph_status check_particles(const sph_geometry *g, int64_t n, const double *xyz,
+                                  const int32_t *feature) {
+  if (n < 0 || n > 0x7ffffff0ll || (n > 0 && (!xyz || !feature)))
+    return fail(SPH_ERR_INVALID_ARG, "bad particle count or NULL particle arrays");
+  const int nf = (int)make_features(g->dim, g->n_holes).size();
+  if (nf > MAXF) return fail(SPH_ERR_UNSUPPORTED, "too many features (%d > %d)", nf, MAXF);
+  for (int64_t i = 0; i < n; ++i) {
+    if (feature[i] < 0 || feature[i] >= nf)
+      return fail(SPH_ERR_INVALID_ARG, "particle %lld: feature %d out of range [0, %d)",
+                  (long long)i, feature[i], nf);
+    for (int a = 0; a < g->dim; ++a)
+      if (!std::isfinite(xyz[3 * i + a]))
+        return fail(SPH_ERR_INVALID_ARG, "particle %lld: non-finite coordinate", (long long)i);
+  }
+  return SPH_OK;
+}
+
+extern "C" int64_t sph_batch_footprint(const sph_batch_params *bp) {
+  if (!bp || (bp->dim != 2 && bp->dim != 3) || bp->max_particles < 0 || bp->max_cells < 1 ||
+      bp->max_jobs < 1 || bp->max_jobs > MAXJ || bp->max_neighbors < 0)
+    return -1;
+  const int64_t N = bp->max_particles + 8, C = bp->max_cells;
+  const int64_t cap = bp->max_neighbors ? bp->max_neighbors : default_cap(bp->dim);
+  const int64_t r4 = bp->precision == SPH_FP64 ? 32 : 16;
+  int64_t b = 2 * N * (32 + 32 + 2 + 4);             // particle records, double buffered
+  b += 4 * N * 4;                                     // cell, rank, psrc, pkey
+  b += C * 4 + (C + 1) * 4 + ((C + SCAN_TILE - 1) / SCAN_TILE) * 8;
+  b += N * cap * 4 + N * 4;                           // neighbour list + counts
+  b += 2 * N * r4;                                    // a^p, a
+  if (bp->debug_fields) b += N * (8 + 8 + 32);
+  const int64_t slots = (int64_t)bp->max_jobs * MAXF;
+  b += bp->max_jobs * (int64_t)sizeof(JobDev) + slots * (int64_t)(sizeof(Feat) + 8 + sizeof(Group)) +
+       slots * MAXF * (int64_t)sizeof(BNorm) + bp->max_jobs * (int64_t)sizeof(JobStat);
+  b += 2 * slots * NSTRIPE * 8 + 2 * (int64_t)bp->max_jobs * NSTRIPE * 8;
+  return b;
+}
+
+extern "C" int64_t sph_job_cells(const sph_geometry *g, const sph_sizing *s, const sph_params *p) {
+  if (validate(g, s, p)) return -1;
+  Grid Gr;
+  grid_of(g, s, p, Gr);
+  return (int64_t)Gr.ncell;
+}
+
+extern "C" sph_status sph_batch_create(const sph_batch_params *bp, sph_batch **out) {
+  if (!out) return fail(SPH_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (sph_batch_footprint(bp) < 0) return fail(SPH_ERR_INVALID_ARG, "bad batch parameters");
+  if (bp->precision != SPH_FP64 && bp->precision != SPH_FP32_MIXED)
+    return fail(SPH_ERR_INVALID_ARG, "precision must be SPH_FP64 or SPH_FP32_MIXED");
+  if (bp->max_particles > 0x7ffffff0ll || bp->max_cells > 0x7ffffff0ll)
+    return fail(SPH_ERR_UNSUPPORTED, "capacity above 2^31");
+  if (bp->max_neighbors > 4096) return fail(SPH_ERR_INVALID_ARG, "max_neighbors above 4096");
+  auto *B = new sph_batch();
+  B->D = bp->dim;
+  B->prec = bp->precision;
+  B->cap = bp->max_neighbors ? bp->max_neighbors : (int)default_cap(bp->dim);
+  B->use_graph = bp->use_graph != 0;
+  B->debug = bp->debug_fields != 0;
+  B->ncap = (int)bp->max_particles;
+  B->ccap = (uint32_t)bp->max_cells;
+  B->jcap = bp->max_jobs;
+  B->jobs.resize(B->jcap);
+  if (bp->stream) {
+    B->stream = (hipStream_t)bp->stream;
   } else {
-    if (hipStreamCreateWithFlags(&M->stream, hipStreamNonBlocking) != hipSuccess) {
-      delete M;
+    if (hipStreamCreateWithFlags(&B->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete B;
       return fail(SPH_ERR_DEVICE, "hipStreamCreate failed");
     }
-    M->own_stream = true;
+    B->own_stream = true;
   }
-
-  // device memory
-  auto &ow = M->owned;
-  size_t &by = M->bytes;
-  const size_t N = (size_t)n;
+  auto &ow = B->owned;
+  size_t &by = B->bytes;
+  const size_t N = (size_t)B->ncap, NPAD = N + 8, C = B->ccap;
+  const size_t tiles = (C + SCAN_TILE - 1) / SCAN_TILE;
+  const size_t slots = (size_t)B->jcap * MAXF;
   bool ok = true;
-  // records are padded past n so that batched candidate loads need no clamp
-  const size_t NPAD = N + 8;
-  for (int b = 0; b < 2; ++b) {
-    M->P[b].xh = dalloc<double4>(NPAD, ow, by);
-    M->P[b].v = dalloc<double4>(NPAD, ow, by);
-    M->P[b].f = dalloc<uint8_t>(NPAD, ow, by);
-    M->P[b].oid = dalloc<uint32_t>(N, ow, by);
-    ok = ok && M->P[b].xh && M->P[b].v && M->P[b].f && M->P[b].oid;
+  for (int b = 0; b < 2; ++b) {   // records padded past capacity: unclamped batched loads
+    B->P[b].xh = dalloc<double4>(NPAD, ow, by);
+    B->P[b].v = dalloc<double4>(NPAD, ow, by);
+    B->P[b].f = dalloc<uint16_t>(NPAD, ow, by);
+    B->P[b].oid = dalloc<uint32_t>(NPAD, ow, by);
+    ok = ok && B->P[b].xh && B->P[b].v && B->P[b].f && B->P[b].oid;
   }
-  M->cell = dalloc<uint32_t>(N, ow, by);
-  M->rank = dalloc<uint32_t>(N, ow, by);
-  M->psrc = dalloc<uint32_t>(N, ow, by);
-  M->pkey = dalloc<uint32_t>(N, ow, by);
-  M->cnt = dalloc<uint32_t>(Gr.ncell, ow, by);
-  M->cstart = dalloc<uint32_t>((size_t)Gr.ncell + 1, ow, by);
-  M->scan_status = dalloc<unsigned long long>(M->nscan_tiles, ow, by);
-  M->ticket = dalloc<uint32_t>(1, ow, by);
-  M->nbr = dalloc<uint32_t>(N * (size_t)M->cap, ow, by);
-  M->nnb = dalloc<uint32_t>(N, ow, by);
-  const size_t r4 = M->prec == SPH_FP64 ? sizeof(double4) : sizeof(float4);
-  M->ap = dalloc<char>(N * r4, ow, by);
-  M->acc = dalloc<char>(N * r4, ow, by);
-  ok = ok && M->ap && M->acc;
-  if (M->debug) {
-    M->dbg_gam = dalloc<double>(N, ow, by);
-    M->dbg_vt = dalloc<double>(N, ow, by);
-    M->dbg_vm = dalloc<double4>(N, ow, by);
-    ok = ok && M->dbg_gam && M->dbg_vt && M->dbg_vm;
+  B->cell = dalloc<uint32_t>(N, ow, by);
+  B->rank = dalloc<uint32_t>(N, ow, by);
+  B->psrc = dalloc<uint32_t>(N, ow, by);
+  B->pkey = dalloc<uint32_t>(N, ow, by);
+  B->cnt = dalloc<uint32_t>(C, ow, by);
+  B->cstart = dalloc<uint32_t>(C + 1, ow, by);
+  B->scan_status = dalloc<unsigned long long>(tiles, ow, by);
+  B->ticket = dalloc<uint32_t>(1, ow, by);
+  B->nbr = dalloc<uint32_t>(N * (size_t)B->cap, ow, by);
+  B->nnb = dalloc<uint32_t>(N, ow, by);
+  const size_t r4 = B->prec == SPH_FP64 ? sizeof(double4) : sizeof(float4);
+  B->ap = dalloc<char>(N * r4, ow, by);
+  B->acc = dalloc<char>(N * r4, ow, by);
+  if (B->debug) {
+    B->dbg_gam = dalloc<double>(N, ow, by);
+    B->dbg_vt = dalloc<double>(N, ow, by);
+    B->dbg_vm = dalloc<double4>(N, ow, by);
+    ok = ok && B->dbg_gam && B->dbg_vt && B->dbg_vm;
   }
-  M->d_feat = dalloc<Feat>(nf, ow, by);
-  M->d_bn = dalloc<BNorm>((size_t)nf * nf, ow, by);
-  M->d_rel = dalloc<int8_t>((size_t)nf * nf, ow, by);
-  M->d_bmask = dalloc<unsigned long long>(nf, ow, by);
-  M->d_grp = dalloc<Group>(nf, ow, by);
-  M->d_st = dalloc<Status>(1, ow, by);
-  M->nblk = (int)((N + BLOCK - 1) / BLOCK);
-  M->nblk8 = (M->nblk + 7) / 8 * 8;
-  M->pmin = dalloc<unsigned long long>((size_t)std::max(M->nblk8, 1) * nf, ow, by);
-  M->psum = dalloc<unsigned long long>((size_t)std::max(M->nblk8, 1) * nf, ow, by);
-  M->pcount = dalloc<unsigned long long>(std::max(M->nblk8, 1), ow, by);
-  M->pesc = dalloc<unsigned long long>(std::max(M->nblk, 1), ow, by);
-  ok = ok && M->pmin && M->psum && M->pcount && M->pesc && M->cell && M->rank && M->psrc && M->pkey && M->cnt && M->cstart &&
-       M->scan_status && M->ticket && M->nbr && M->nnb && M->d_feat && M->d_bn && M->d_rel && M->d_bmask && M->d_grp && M->d_st;
+  B->d_jobs = dalloc<JobDev>(B->jcap, ow, by);
+  B->d_feat = dalloc<Feat>(slots, ow, by);
+  B->d_bmask = dalloc<unsigned long long>(slots, ow, by);
+  B->d_bn = dalloc<BNorm>(slots * MAXF, ow, by);
+  B->d_grp = dalloc<Group>(slots, ow, by);
+  B->d_st = dalloc<JobStat>(B->jcap, ow, by);
+  B->d_gflags = dalloc<unsigned int>(4, ow, by);
+  B->smin = dalloc<unsigned long long>(slots * NSTRIPE, ow, by);
+  B->ssum = dalloc<unsigned long long>(slots * NSTRIPE, ow, by);
+  B->scnt = dalloc<unsigned long long>((size_t)B->jcap * NSTRIPE, ow, by);
+  B->sesc = dalloc<unsigned long long>((size_t)B->jcap * NSTRIPE, ow, by);
+  ok = ok && B->cell && B->rank && B->psrc && B->pkey && B->cnt && B->cstart && B->scan_status &&
+       B->ticket && B->nbr && B->nnb && B->ap && B->acc && B->d_jobs && B->d_feat && B->d_bmask &&
+       B->d_bn && B->d_grp && B->d_st && B->d_gflags && B->smin && B->ssum && B->scnt && B->sesc;
   if (!ok) {
-    delete M;
+    delete B;
     return fail(SPH_ERR_OUT_OF_MEMORY, "device allocation of %zu bytes failed", by);
   }
+  hipError_t e = hipMemset(B->cnt, 0, sizeof(uint32_t) * C);
+  if (e == hipSuccess) e = hipMemset(B->scan_status, 0, 8 * std::max<size_t>(tiles, 1));
+  if (e == hipSuccess) e = hipMemset(B->ticket, 0, 4);
+  if (e == hipSuccess) e = hipMemset(B->nnb, 0, 4 * std::max<size_t>(N, 1));
+  if (e == hipSuccess) e = hipMemset(B->d_grp, 0, sizeof(Group) * slots);
+  if (e == hipSuccess) e = hipMemset(B->d_st, 0, sizeof(JobStat) * B->jcap);
+  if (e == hipSuccess) e = hipMemset(B->d_gflags, 0, 16);
+  if (e == hipSuccess) e = hipMemset(B->smin, 0xff, 8 * slots * NSTRIPE);   // minimum identity
+  if (e == hipSuccess) e = hipMemset(B->ssum, 0, 8 * slots * NSTRIPE);
+  if (e == hipSuccess) e = hipMemset(B->scnt, 0, 8 * (size_t)B->jcap * NSTRIPE);
+  if (e == hipSuccess) e = hipMemset(B->sesc, 0, 8 * (size_t)B->jcap * NSTRIPE);
+  if (e == hipSuccess) e = hipMemset(B->P[0].f, 0, 2 * NPAD);
+  if (e == hipSuccess) e = hipMemset(B->P[1].f, 0, 2 * NPAD);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    delete B;
+    return fail(SPH_ERR_DEVICE, "batch initialisation failed: %s", hipGetErrorString(e));
+  }
+  *out = B;
+  return SPH_OK;
+}
 
-  // host-side tables
-  std::vector<Feat> hf(nf);
-  std::vector<BNorm> hb((size_t)nf * nf);
-  std::vector<int8_t> hr((size_t)nf * nf, 0);
-  std::vector<unsigned long long> hm(nf, 0ull);
+extern "C" void sph_batch_destroy(sph_batch *b) { delete b; }
+
+extern "C" sph_status sph_batch_add(sph_batch *b, const sph_geometry *g, const sph_sizing *s,
+                                    const sph_params *p, int64_t n, const double *xyz,
+                                    const int32_t *feature, int32_t *job) {
+  if (!b) return fail(SPH_ERR_INVALID_ARG, "null batch");
+  if (sph_status st = validate(g, s, p)) return st;
+  if (g->dim != b->D) return fail(SPH_ERR_INVALID_ARG, "job dimension %d != batch dimension %d",
+                                  g->dim, b->D);
+  if (sph_status st = check_particles(g, n, xyz, feature)) return st;
+  const int nf = (int)make_features(g->dim, g->n_holes).size();
+  int slot = -1;
+  for (int j = 0; j < b->jcap; ++j)
+    if (!b->jobs[j].live) {
+      slot = j;
+      break;
+    }
+  if (slot < 0) return fail(SPH_ERR_OUT_OF_MEMORY, "no free job slot (max_jobs %d)", b->jcap);
+  HostJob J;
+  fill_job(J, g, s, p, b->ncell, (int)n);
+  if ((int64_t)b->n + n > b->ncap)
+    return fail(SPH_ERR_OUT_OF_MEMORY, "particle capacity %d exceeded", b->ncap);
+  if ((uint64_t)b->ncell + J.ncell > b->ccap)
+    return fail(SPH_ERR_OUT_OF_MEMORY, "cell capacity %u exceeded (job needs %u)", b->ccap, J.ncell);
+  HIPCHK(hipStreamSynchronize(b->stream));
+  const int D = b->D;
+  // tables of the job's feature slots
+  std::vector<Feat> hf(MAXF);
+  std::vector<unsigned long long> hm(MAXF, 0ull);
+  std::vector<BNorm> hb((size_t)MAXF * MAXF);
+  std::memset(hf.data(), 0, sizeof(Feat) * MAXF);
+  std::memset(hb.data(), 0, sizeof(BNorm) * MAXF * MAXF);
   for (int i = 0; i < nf; ++i) {
-    const HFeat &F = feats[i];
+    const HFeat &F = J.feats[i];
     Feat d{};
     d.type = (int8_t)F.type;
     d.k = (int8_t)F.k;
@@ -594,18 +771,20 @@ extern "C" sph_status sph_mesh_create(const sph_geometry *g, const sph_sizing *s
     d.bits = (int8_t)F.bits;
     hf[i] = d;
     for (int j = 0; j < nf; ++j) {
-      hb[(size_t)i * nf + j] = boundary_normal(D, F, feats[j]);
-      hr[(size_t)i * nf + j] = i == j ? 1 : (on_boundary_of(F, feats[j]) ? 2 : 0);
-      if (i != j && on_boundary_of(F, feats[j])) hm[i] |= 1ull << j;
+      hb[(size_t)i * MAXF + j] = boundary_normal(D, F, J.feats[j]);
+      if (i != j && on_boundary_of(F, J.feats[j])) hm[i] |= 1ull << j;
     }
   }
   std::vector<int64_t> counts(nf, 0);
   for (int64_t i = 0; i < n; ++i) counts[feature[i]]++;
-  std::vector<Group> hg(nf);
-  for (int q = 0; q < nf; ++q) {
+  double hmin, hmax, lip;
+  sizing_bounds(g, s, hmin, hmax, lip);
+  std::vector<Group> hg(MAXF);
+  for (int q = 0; q < MAXF; ++q) {
     Group &Q = hg[q];
     std::memset(&Q, 0, sizeof Q);
-    Q.tracked = feats[q].type != T_SI && counts[q] > 0;
+    if (q >= nf) continue;
+    Q.tracked = J.feats[q].type != T_SI && counts[q] > 0;
     Q.active = Q.tracked;
     Q.phase = PH_ONE;
     Q.count = (int32_t)counts[q];
@@ -615,52 +794,230 @@ extern "C" sph_status sph_mesh_create(const sph_geometry *g, const sph_sizing *s
     std::memcpy(&Q.dt1_bits, &db, 8);
     std::memcpy(&Q.dt_bits, &db, 8);
     // fixed-point scale of the V~ sum: V~_i <= h^k / alpha_k, keep the
-    // group total below 2^62
-    const int k = feats[q].k;
+    // feature's total below 2^62
+    const int k = J.feats[q].k;
     const double alpha = k == 1 ? 0.625 : (k == 2 ? 7.0 / (4.0 * M_PI) : 21.0 / (16.0 * M_PI));
     double bound = (double)std::max<int64_t>(counts[q], 1) * std::pow(hmax, k) / alpha;
-    int e = 62 - (int)std::ceil(std::log2(bound * 2.0));
-    Q.vscale = std::ldexp(1.0, std::min(e, 1000));
+    int ex = 62 - (int)std::ceil(std::log2(bound * 2.0));
+    Q.vscale = std::ldexp(1.0, std::min(ex, 1000));
   }
-  // particle records: caller order, caller ids
+  // particle records appended after the resident jobs (their cells follow
+  // every resident cell, so the order stays sorted by cell)
+  const size_t N = (size_t)n;
   std::vector<double4> xh(N);
   std::vector<uint32_t> oid(N);
-  std::vector<uint8_t> f8(N);
+  std::vector<uint16_t> f16(N);
   for (size_t i = 0; i < N; ++i) {
     xh[i] = make_double4(xyz[3 * i], xyz[3 * i + 1], D == 3 ? xyz[3 * i + 2] : 0.0, 0.0);
     oid[i] = (uint32_t)i;
-    f8[i] = (uint8_t)feature[i];
+    f16[i] = (uint16_t)(slot * MAXF + feature[i]);
   }
+  const Parts &P = b->P[b->cur];
+  const size_t o = (size_t)b->n;
+  JobStat js{};
+  js.live = 1;
   hipError_t e = hipSuccess;
-  if (N) e = hipMemcpy(M->P[0].xh, xh.data(), N * sizeof(double4), hipMemcpyHostToDevice);
-  if (e == hipSuccess && N) e = hipMemset(M->P[0].v, 0, N * sizeof(double4));
-  if (e == hipSuccess && N) e = hipMemcpy(M->P[0].oid, oid.data(), N * 4, hipMemcpyHostToDevice);
-  if (e == hipSuccess && N) e = hipMemcpy(M->P[0].f, f8.data(), N, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(M->d_feat, hf.data(), sizeof(Feat) * nf, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(M->d_bn, hb.data(), sizeof(BNorm) * nf * nf, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(M->d_rel, hr.data(), (size_t)nf * nf, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(M->d_bmask, hm.data(), 8 * nf, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(M->d_grp, hg.data(), sizeof(Group) * nf, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemset(M->d_st, 0, sizeof(Status));
-  if (e == hipSuccess) e = hipMemset(M->cnt, 0, sizeof(uint32_t) * Gr.ncell);
+  if (N) e = hipMemcpy(P.xh + o, xh.data(), N * sizeof(double4), hipMemcpyHostToDevice);
+  if (e == hipSuccess && N) e = hipMemset(P.v + o, 0, N * sizeof(double4));
+  if (e == hipSuccess && N) e = hipMemcpy(P.oid + o, oid.data(), N * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess && N) e = hipMemcpy(P.f + o, f16.data(), N * 2, hipMemcpyHostToDevice);
   if (e == hipSuccess)
-    e = hipMemset(M->scan_status, 0, sizeof(unsigned long long) * std::max(M->nscan_tiles, 1u));
-  if (e == hipSuccess) e = hipMemset(M->ticket, 0, sizeof(uint32_t));
-  if (e == hipSuccess) e = hipMemset(M->nnb, 0, sizeof(uint32_t) * std::max<size_t>(N, 1));
-  if (e == hipSuccess) e = hipDeviceSynchronize();
-  if (e != hipSuccess) {
-    delete M;
-    return fail(SPH_ERR_DEVICE, "initial upload failed: %s", hipGetErrorString(e));
+    e = hipMemcpy(b->d_feat + slot * MAXF, hf.data(), sizeof(Feat) * MAXF, hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(b->d_bmask + slot * MAXF, hm.data(), 8 * MAXF, hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(b->d_bn + (size_t)slot * MAXF * MAXF, hb.data(), sizeof(BNorm) * MAXF * MAXF,
+                  hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(b->d_grp + slot * MAXF, hg.data(), sizeof(Group) * MAXF, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(b->d_jobs + slot, &J.dev, sizeof(JobDev), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(b->d_st + slot, &js, sizeof js, hipMemcpyHostToDevice);
+  if (e == hipSuccess && J.ncell) e = hipMemset(b->cnt + b->ncell, 0, 4 * (size_t)J.ncell);
+  if (e != hipSuccess) return fail(SPH_ERR_DEVICE, "job upload failed: %s", hipGetErrorString(e));
+  J.live = true;
+  b->jobs[slot] = J;
+  const int i0 = b->n;
+  b->n += (int)n;
+  b->ncell += J.ncell;
+  b->njobs = std::max(b->njobs, slot + 1);
+  b->invalidate_graph();
+  if (sph_status st = b->hash_range(i0, b->n)) return st;
+  HIPCHK(hipStreamSynchronize(b->stream));
+  if (job) *job = slot;
+  return SPH_OK;
+}
+
+extern "C" sph_status sph_batch_remove(sph_batch *b, int32_t job) {
+  if (!b || !b->valid_job(job)) return fail(SPH_ERR_INVALID_ARG, "no such job");
+  HIPCHK(hipStreamSynchronize(b->stream));
+  // surviving jobs in their current (cell base) order, copied contiguously
+  std::vector<int> order;
+  for (int j = 0; j < b->njobs; ++j)
+    if (b->jobs[j].live && j != job) order.push_back(j);
+  std::sort(order.begin(), order.end(),
+            [&](int x, int y) { return b->jobs[x].cbase < b->jobs[y].cbase; });
+  const Parts &src = b->P[b->cur], &dst = b->P[1 - b->cur];
+  size_t off = 0;
+  uint32_t cb = 0;
+  for (int j : order) {
+    HostJob &J = b->jobs[j];
+    const size_t first = (size_t)b->job_first(j), m = (size_t)J.n;
+    if (m) {
+      HIPCHK(hipMemcpyAsync(dst.xh + off, src.xh + first, m * sizeof(double4), hipMemcpyDeviceToDevice, b->stream));
+      HIPCHK(hipMemcpyAsync(dst.v + off, src.v + first, m * sizeof(double4), hipMemcpyDeviceToDevice, b->stream));
+      HIPCHK(hipMemcpyAsync(dst.f + off, src.f + first, m * 2, hipMemcpyDeviceToDevice, b->stream));
+      HIPCHK(hipMemcpyAsync(dst.oid + off, src.oid + first, m * 4, hipMemcpyDeviceToDevice, b->stream));
+    }
+    off += m;
   }
-  if (N) {
-    if (sph_status st = M->hash_now()) {
-      delete M;
-      return st;
+  // new cell bases
+  for (int j : order) {
+    HostJob &J = b->jobs[j];
+    J.cbase = cb;
+    J.dev.G.cbase = cb;
+    cb += J.ncell;
+    HIPCHK(hipMemcpyAsync(b->d_jobs + j, &J.dev, sizeof(JobDev), hipMemcpyHostToDevice, b->stream));
+  }
+  HostJob &R = b->jobs[job];
+  R.live = false;
+  R.dev.live = 0;
+  HIPCHK(hipMemsetAsync(b->d_grp + job * MAXF, 0, sizeof(Group) * MAXF, b->stream));
+  HIPCHK(hipMemsetAsync(b->d_st + job, 0, sizeof(JobStat), b->stream));
+  HIPCHK(hipMemcpyAsync(b->d_jobs + job, &R.dev, sizeof(JobDev), hipMemcpyHostToDevice, b->stream));
+  HIPCHK(hipMemsetAsync(b->cnt, 0, 4 * (size_t)std::max(b->ncell, 1u), b->stream));
+  HIPCHK(hipStreamSynchronize(b->stream));
+  b->cur = 1 - b->cur;
+  b->n = (int)off;
+  b->ncell = cb;
+  while (b->njobs > 0 && !b->jobs[b->njobs - 1].live) b->njobs--;
+  b->invalidate_graph();
+  if (sph_status st = b->hash_range(0, b->n)) return st;
+  HIPCHK(hipStreamSynchronize(b->stream));
+  return SPH_OK;
+}
+
+extern "C" sph_status sph_batch_step(sph_batch *b, int32_t n_steps) {
+  if (!b || n_steps < 0) return fail(SPH_ERR_INVALID_ARG, "bad batch or step count");
+  return b->step(n_steps);
+}
+
+extern "C" sph_status sph_batch_status(sph_batch *b, int32_t *live, int32_t *converged,
+                                       int64_t *steps, int32_t cap) {
+  if (!b) return fail(SPH_ERR_INVALID_ARG, "null batch");
+  HIPCHK(hipStreamSynchronize(b->stream));
+  std::vector<JobStat> st(b->jcap);
+  HIPCHK(hipMemcpy(st.data(), b->d_st, sizeof(JobStat) * b->jcap, hipMemcpyDeviceToHost));
+  for (int j = 0; j < cap; ++j) {
+    const bool ok = j < b->jcap && b->jobs[j].live;
+    if (live) live[j] = ok;
+    if (converged) converged[j] = ok ? st[j].converged : 0;
+    if (steps) steps[j] = ok ? (int64_t)st[j].steps : 0;
+  }
+  return SPH_OK;
+}
+
+extern "C" sph_status sph_batch_positions(sph_batch *b, int32_t job, double *xyz, int32_t *feature,
+                                          int64_t capacity, int64_t *n_out) {
+  if (!b || !b->valid_job(job)) return fail(SPH_ERR_INVALID_ARG, "no such job");
+  const HostJob &J = b->jobs[job];
+  if (n_out) *n_out = J.n;
+  if (!xyz && !feature) return SPH_OK;
+  if (capacity < J.n) return fail(SPH_ERR_INVALID_ARG, "capacity %lld < %d particles",
+                                  (long long)capacity, J.n);
+  HIPCHK(hipStreamSynchronize(b->stream));
+  if (sph_status st = b->check_job(job)) return st;
+  const Parts &s = b->P[b->cur];
+  const size_t first = (size_t)b->job_first(job);
+  std::vector<uint32_t> oid;
+  HIPCHK(pull(oid, s.oid + first, J.n));
+  if (xyz) {
+    std::vector<double4> xh;
+    HIPCHK(pull(xh, s.xh + first, J.n));
+    for (int i = 0; i < J.n; ++i) {
+      double *o = xyz + 3 * (size_t)oid[i];
+      o[0] = xh[i].x;
+      o[1] = xh[i].y;
+      o[2] = b->D == 3 ? xh[i].z : 0.0;
     }
-    if ((e = hipStreamSynchronize(M->stream)) != hipSuccess) {
-      delete M;
-      return fail(SPH_ERR_DEVICE, "initial hash failed: %s", hipGetErrorString(e));
-    }
+  }
+  if (feature) {
+    std::vector<uint16_t> f;
+    HIPCHK(pull(f, s.f + first, J.n));
+    for (int i = 0; i < J.n; ++i) feature[oid[i]] = f[i] % MAXF;
+  }
+  return SPH_OK;
+}
+
+extern "C" sph_status sph_batch_error(sph_batch *b, int32_t job, double *e_sys, int32_t *phase,
+                                      int32_t *converged, int64_t *step) {
+  if (!b || !b->valid_job(job)) return fail(SPH_ERR_INVALID_ARG, "no such job");
+  HIPCHK(hipStreamSynchronize(b->stream));
+  if (sph_status st = b->check_job(job)) return st;
+  std::vector<Group> G(MAXF);
+  HIPCHK(hipMemcpy(G.data(), b->d_grp + job * MAXF, sizeof(Group) * MAXF, hipMemcpyDeviceToHost));
+  JobStat S;
+  HIPCHK(hipMemcpy(&S, b->d_st + job, sizeof S, hipMemcpyDeviceToHost));
+  double e = 0.0;
+  int ph = PH_FROZEN, conv = 1;
+  for (const Group &q : G) {
+    if (!q.tracked) continue;
+    if (q.esys > e || std::isnan(q.esys)) e = q.esys;
+    ph = std::min(ph, (int)q.phase);
+    if (q.phase != PH_FROZEN) conv = 0;
+  }
+  if (e_sys) *e_sys = e;
+  if (phase) *phase = ph;
+  if (converged) *converged = conv;
+  if (step) *step = (int64_t)S.steps;
+  return SPH_OK;
+}
+
+extern "C" sph_status sph_batch_counters(sph_batch *b, int32_t job, double *out) {
+  if (!b || !out || !b->valid_job(job)) return fail(SPH_ERR_INVALID_ARG, "bad argument");
+  HIPCHK(hipStreamSynchronize(b->stream));
+  JobStat S;
+  HIPCHK(hipMemcpy(&S, b->d_st + job, sizeof S, hipMemcpyDeviceToHost));
+  out[0] = (double)S.steps;
+  out[1] = (double)S.escaped;
+  out[2] = (double)S.inter_total;
+  out[3] = (double)S.inter_last;
+  return SPH_OK;
+}
+
+// ---------------------------------------------------------------------------
+// the single-job API: a batch holding one job (slot 0)
+// ---------------------------------------------------------------------------
+struct sph_mesh {
+  sph_batch *b = nullptr;
+  int job = 0;
+  ~sph_mesh() { delete b; }
+};
+
+extern "C" sph_status sph_mesh_create(const sph_geometry *g, const sph_sizing *s,
+                                      const sph_params *p, int64_t n, const double *xyz,
+                                      const int32_t *feature, sph_mesh **out) {
+  if (!out) return fail(SPH_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (sph_status st = validate(g, s, p)) return st;
+  if (sph_status st = check_particles(g, n, xyz, feature)) return st;
+  sph_batch_params bp{};
+  bp.dim = g->dim;
+  bp.precision = p->precision;
+  bp.max_particles = std::max<int64_t>(n, 1);
+  bp.max_cells = sph_job_cells(g, s, p);
+  bp.max_jobs = 1;
+  bp.max_neighbors = p->max_neighbors;
+  bp.use_graph = p->use_graph;
+  bp.debug_fields = p->debug_fields;
+  bp.stream = p->stream;
+  auto *M = new sph_mesh();
+  if (sph_status st = sph_batch_create(&bp, &M->b)) {
+    delete M;
+    return st;
+  }
+  if (sph_status st = sph_batch_add(M->b, g, s, p, n, xyz, feature, &M->job)) {
+    delete M;
+    return st;
   }
   *out = M;
   return SPH_OK;
@@ -672,108 +1029,75 @@ extern "C" const char *sph_mesh_last_error(void) { return g_err.c_str(); }
 
 extern "C" sph_status sph_mesh_step(sph_mesh *m, int32_t n_steps) {
   if (!m || n_steps < 0) return fail(SPH_ERR_INVALID_ARG, "bad handle or step count");
-  if (m->n == 0) return SPH_OK;
-  int left = n_steps;
-  if (m->use_graph && !m->profiling) {
-    if (left > 0 && m->cur != 0) {   // graphs are captured at parity 0
-      if (sph_status st = m->enqueue_step()) return st;
-      --left;
-    }
-    if (left >= 2) {
-      if (sph_status st = m->build_graph()) return st;
-      for (; left >= 2; left -= 2) HIPCHK(hipGraphLaunch(m->gexec, m->stream));
-    }
-  }
-  for (; left > 0; --left)
-    if (sph_status st = m->enqueue_step()) return st;
-  return SPH_OK;
+  return m->b->step(n_steps);
 }
 
 extern "C" sph_status sph_mesh_sync(sph_mesh *m) {
   if (!m) return fail(SPH_ERR_INVALID_ARG, "null handle");
-  HIPCHK(hipStreamSynchronize(m->stream));
+  HIPCHK(hipStreamSynchronize(m->b->stream));
   return SPH_OK;
-}
-
-// copy a device column (slot order) to a host vector
-template <typename T>
-static hipError_t pull(std::vector<T> &h, const void *d, size_t count) {
-  h.resize(count);
-  if (!count) return hipSuccess;
-  return hipMemcpy(h.data(), d, count * sizeof(T), hipMemcpyDeviceToHost);
 }
 
 extern "C" sph_status sph_mesh_positions(sph_mesh *m, double *xyz, int32_t *feature,
                                          int64_t capacity, int64_t *n_out) {
   if (!m) return fail(SPH_ERR_INVALID_ARG, "null handle");
-  if (n_out) *n_out = m->n;
-  if (!xyz && !feature) return SPH_OK;
-  if (capacity < m->n) return fail(SPH_ERR_INVALID_ARG, "capacity %lld < %d particles",
-                                   (long long)capacity, m->n);
-  HIPCHK(hipStreamSynchronize(m->stream));
-  if (sph_status st = m->check_status()) return st;
-  const Parts &s = m->P[m->cur];
-  std::vector<uint32_t> oid;
-  HIPCHK(pull(oid, s.oid, m->n));
-  if (xyz) {
-    std::vector<double4> xh;
-    HIPCHK(pull(xh, s.xh, m->n));
-    for (int i = 0; i < m->n; ++i) {
-      double *o = xyz + 3 * (size_t)oid[i];
-      o[0] = xh[i].x;
-      o[1] = xh[i].y;
-      o[2] = m->D == 3 ? xh[i].z : 0.0;
-    }
-  }
-  if (feature) {
-    std::vector<uint8_t> f;
-    HIPCHK(pull(f, s.f, m->n));
-    for (int i = 0; i < m->n; ++i) feature[oid[i]] = f[i];
-  }
-  return SPH_OK;
+  return sph_batch_positions(m->b, m->job, xyz, feature, capacity, n_out);
+}
+
+extern "C" sph_status sph_mesh_error(sph_mesh *m, double *e_sys, int32_t *phase, int32_t *converged,
+                                     int64_t *step) {
+  if (!m) return fail(SPH_ERR_INVALID_ARG, "null handle");
+  return sph_batch_error(m->b, m->job, e_sys, phase, converged, step);
+}
+
+extern "C" sph_status sph_mesh_counters(sph_mesh *m, double *out) {
+  if (!m) return fail(SPH_ERR_INVALID_ARG, "null handle");
+  return sph_batch_counters(m->b, m->job, out);
 }
 
 extern "C" sph_status sph_mesh_velocities(sph_mesh *m, double *vel) {
   if (!m || !vel) return fail(SPH_ERR_INVALID_ARG, "null argument");
-  HIPCHK(hipStreamSynchronize(m->stream));
-  const Parts &s = m->P[m->cur];
+  sph_batch *b = m->b;
+  HIPCHK(hipStreamSynchronize(b->stream));
+  const Parts &s = b->P[b->cur];
   std::vector<uint32_t> oid;
-  HIPCHK(pull(oid, s.oid, m->n));
+  HIPCHK(pull(oid, s.oid, b->n));
   std::vector<double4> v;
-  HIPCHK(pull(v, s.v, m->n));
-  for (int i = 0; i < m->n; ++i) {
+  HIPCHK(pull(v, s.v, b->n));
+  for (int i = 0; i < b->n; ++i) {
     double *o = vel + 3 * (size_t)oid[i];
     o[0] = v[i].x;
     o[1] = v[i].y;
-    o[2] = m->D == 3 ? v[i].z : 0.0;
+    o[2] = b->D == 3 ? v[i].z : 0.0;
   }
   return SPH_OK;
 }
 
 extern "C" sph_status sph_mesh_set_state(sph_mesh *m, const double *xyz, const double *vel) {
   if (!m) return fail(SPH_ERR_INVALID_ARG, "null handle");
-  HIPCHK(hipStreamSynchronize(m->stream));
-  if (m->n == 0) return SPH_OK;
-  const Parts &s = m->P[m->cur];
+  sph_batch *b = m->b;
+  HIPCHK(hipStreamSynchronize(b->stream));
+  if (b->n == 0) return SPH_OK;
+  const Parts &s = b->P[b->cur];
   std::vector<uint32_t> oid;
-  HIPCHK(pull(oid, s.oid, m->n));
+  HIPCHK(pull(oid, s.oid, b->n));
   if (xyz) {
-    std::vector<double4> xh(m->n);
-    for (int i = 0; i < m->n; ++i) {
+    std::vector<double4> xh(b->n);
+    for (int i = 0; i < b->n; ++i) {
       const double *p = xyz + 3 * (size_t)oid[i];
-      xh[i] = make_double4(p[0], p[1], m->D == 3 ? p[2] : 0.0, 0.0);
+      xh[i] = make_double4(p[0], p[1], b->D == 3 ? p[2] : 0.0, 0.0);
     }
     HIPCHK(hipMemcpy(s.xh, xh.data(), xh.size() * sizeof(double4), hipMemcpyHostToDevice));
     // new positions: new h, cells and ranks
-    HIPCHK(hipMemset(m->cnt, 0, sizeof(uint32_t) * m->grid.ncell));
-    if (sph_status st = m->hash_now()) return st;
-    HIPCHK(hipStreamSynchronize(m->stream));
+    HIPCHK(hipMemset(b->cnt, 0, sizeof(uint32_t) * b->ncell));
+    if (sph_status st = b->hash_range(0, b->n)) return st;
+    HIPCHK(hipStreamSynchronize(b->stream));
   }
   if (vel) {
-    std::vector<double4> v(m->n);
-    for (int i = 0; i < m->n; ++i) {
+    std::vector<double4> v(b->n);
+    for (int i = 0; i < b->n; ++i) {
       const double *p = vel + 3 * (size_t)oid[i];
-      v[i] = make_double4(p[0], p[1], m->D == 3 ? p[2] : 0.0, 0.0);
+      v[i] = make_double4(p[0], p[1], b->D == 3 ? p[2] : 0.0, 0.0);
     }
     HIPCHK(hipMemcpy(s.v, v.data(), v.size() * sizeof(double4), hipMemcpyHostToDevice));
   }
@@ -783,8 +1107,9 @@ extern "C" sph_status sph_mesh_set_state(sph_mesh *m, const double *xyz, const d
 extern "C" sph_status sph_mesh_neighbors(sph_mesh *m, int64_t *offsets, int32_t *ids, int8_t *rel,
                                          int64_t cap, int64_t *n_pairs) {
   if (!m || !offsets) return fail(SPH_ERR_INVALID_ARG, "null argument");
-  HIPCHK(hipStreamSynchronize(m->stream));
-  const int n = m->n;
+  sph_batch *b = m->b;
+  HIPCHK(hipStreamSynchronize(b->stream));
+  const int n = b->n;
   if (n == 0) {
     offsets[0] = 0;
     if (n_pairs) *n_pairs = 0;
@@ -792,17 +1117,18 @@ extern "C" sph_status sph_mesh_neighbors(sph_mesh *m, int64_t *offsets, int32_t 
   }
   // sort into cell order, build the lists, then re-hash so that the next
   // step starts from consistent cell counts
-  sph_status st = m->enqueue_sort();
-  if (!st) st = m->D == 2 ? m->enqueue_lists_only<2>() : m->enqueue_lists_only<3>();
-  if (!st) st = m->hash_now();
+  b->invalidate_graph();
+  sph_status st = b->enqueue_sort();
+  if (!st) st = b->D == 2 ? b->enqueue_lists_only<2>() : b->enqueue_lists_only<3>();
+  if (!st) st = b->hash_range(0, n);
   if (st) return st;
-  HIPCHK(hipStreamSynchronize(m->stream));
-  if ((st = m->check_status())) return st;
-  const Parts &s = m->P[m->cur];
+  HIPCHK(hipStreamSynchronize(b->stream));
+  if ((st = b->check_job(m->job))) return st;
+  const Parts &s = b->P[b->cur];
   std::vector<uint32_t> oid, nnb, nbr;
   HIPCHK(pull(oid, s.oid, n));
-  HIPCHK(pull(nnb, m->nnb, n));
-  HIPCHK(pull(nbr, m->nbr, (size_t)n * m->cap));
+  HIPCHK(pull(nnb, b->nnb, n));
+  HIPCHK(pull(nbr, b->nbr, (size_t)n * b->cap));
   std::vector<int64_t> cnt(n + 1, 0);
   for (int i = 0; i < n; ++i) cnt[oid[i] + 1] = nnb[i];
   for (int i = 0; i < n; ++i) cnt[i + 1] += cnt[i];
@@ -830,11 +1156,12 @@ extern "C" sph_status sph_mesh_neighbors(sph_mesh *m, int64_t *offsets, int32_t 
 
 extern "C" sph_status sph_mesh_field(sph_mesh *m, int32_t which, double *out) {
   if (!m || !out) return fail(SPH_ERR_INVALID_ARG, "null argument");
+  sph_batch *b = m->b;
   if (which < 0 || which > 5) return fail(SPH_ERR_INVALID_ARG, "unknown field %d", which);
-  if (which >= 3 && !m->debug) return fail(SPH_ERR_INVALID_ARG, "field %d needs debug_fields", which);
-  HIPCHK(hipStreamSynchronize(m->stream));
-  const int n = m->n;
-  const Parts &s = m->P[m->cur];
+  if (which >= 3 && !b->debug) return fail(SPH_ERR_INVALID_ARG, "field %d needs debug_fields", which);
+  HIPCHK(hipStreamSynchronize(b->stream));
+  const int n = b->n;
+  const Parts &s = b->P[b->cur];
   std::vector<uint32_t> oid;
   HIPCHK(pull(oid, s.oid, n));
   std::vector<double> col;
@@ -846,7 +1173,7 @@ extern "C" sph_status sph_mesh_field(sph_mesh *m, int32_t which, double *out) {
       double *o = out + 3 * (size_t)oid[i];
       o[0] = v[i].x;
       o[1] = v[i].y;
-      o[2] = m->D == 3 ? v[i].z : 0.0;
+      o[2] = b->D == 3 ? v[i].z : 0.0;
     }
   };
   std::vector<double4> v4;
@@ -858,12 +1185,12 @@ extern "C" sph_status sph_mesh_field(sph_mesh *m, int32_t which, double *out) {
       scatter1();
       break;
     }
-    case 3: HIPCHK(pull(col, m->dbg_vt, n)); scatter1(); break;
-    case 4: HIPCHK(pull(col, m->dbg_gam, n)); scatter1(); break;
-    case 5: HIPCHK(pull(v4, m->dbg_vm, n)); scatter4(v4); break;
+    case 3: HIPCHK(pull(col, b->dbg_vt, n)); scatter1(); break;
+    case 4: HIPCHK(pull(col, b->dbg_gam, n)); scatter1(); break;
+    case 5: HIPCHK(pull(v4, b->dbg_vm, n)); scatter4(v4); break;
     default: {
-      const void *src = which == 1 ? m->ap : m->acc;
-      if (m->prec == SPH_FP64) {
+      const void *src = which == 1 ? b->ap : b->acc;
+      if (b->prec == SPH_FP64) {
         HIPCHK(pull(v4, src, n));
       } else {
         std::vector<float4> f4;
@@ -878,49 +1205,57 @@ extern "C" sph_status sph_mesh_field(sph_mesh *m, int32_t which, double *out) {
 }
 
 extern "C" sph_status sph_mesh_group_state(sph_mesh *m, int32_t f, double *out) {
-  if (!m || !out || f < 0 || f >= m->nf) return fail(SPH_ERR_INVALID_ARG, "bad argument");
-  HIPCHK(hipStreamSynchronize(m->stream));
+  if (!m || !out || f < 0 || f >= MAXF) return fail(SPH_ERR_INVALID_ARG, "bad argument");
+  sph_batch *b = m->b;
+  HIPCHK(hipStreamSynchronize(b->stream));
   Group G;
-  HIPCHK(hipMemcpy(&G, m->d_grp + f, sizeof G, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(&G, b->d_grp + m->job * MAXF + f, sizeof G, hipMemcpyDeviceToHost));
   out[0] = G.phase; out[1] = G.n_ph; out[2] = G.esys; out[3] = G.dt1; out[4] = G.dt;
   out[5] = G.vbar; out[6] = G.reset_next; out[7] = G.a_last; out[8] = G.a_prev; out[9] = G.nwin;
   return SPH_OK;
 }
 
-extern "C" sph_status sph_mesh_error(sph_mesh *m, double *e_sys, int32_t *phase, int32_t *converged,
-                                     int64_t *step) {
+extern "C" int64_t sph_mesh_device_bytes(sph_mesh *m) { return m ? (int64_t)m->b->bytes : 0; }
+
+extern "C" sph_status sph_mesh_profile(sph_mesh *m, int32_t enable) {
   if (!m) return fail(SPH_ERR_INVALID_ARG, "null handle");
-  HIPCHK(hipStreamSynchronize(m->stream));
-  if (sph_status st = m->check_status()) return st;
-  std::vector<Group> G(m->nf);
-  HIPCHK(hipMemcpy(G.data(), m->d_grp, sizeof(Group) * m->nf, hipMemcpyDeviceToHost));
-  Status S;
-  HIPCHK(hipMemcpy(&S, m->d_st, sizeof S, hipMemcpyDeviceToHost));
-  double e = 0.0;
-  int ph = PH_FROZEN, conv = 1;
-  for (const Group &q : G) {
-    if (!q.tracked) continue;
-    if (q.esys > e || std::isnan(q.esys)) e = q.esys;
-    ph = std::min(ph, (int)q.phase);
-    if (q.phase != PH_FROZEN) conv = 0;
+  sph_batch *b = m->b;
+  HIPCHK(hipStreamSynchronize(b->stream));
+  for (auto &e : b->ev_live) {
+    b->ev_pool.push_back(e.a);
+    b->ev_pool.push_back(e.b);
   }
-  if (e_sys) *e_sys = e;
-  if (phase) *phase = ph;
-  if (converged) *converged = conv;
-  if (step) *step = (int64_t)S.steps;
+  b->ev_live.clear();
+  for (int k = 0; k < KID_COUNT; ++k) {
+    b->kms[k] = 0.0;
+    b->kcount[k] = 0;
+  }
+  b->profiling = enable != 0;
   return SPH_OK;
 }
 
-extern "C" sph_status sph_mesh_counters(sph_mesh *m, double *out) {
-  if (!m || !out) return fail(SPH_ERR_INVALID_ARG, "null argument");
-  HIPCHK(hipStreamSynchronize(m->stream));
-  Status S;
-  HIPCHK(hipMemcpy(&S, m->d_st, sizeof S, hipMemcpyDeviceToHost));
-  out[0] = (double)S.steps;
-  out[1] = (double)S.escaped;
-  out[2] = (double)S.inter_total;
-  out[3] = (double)S.inter_last;
+extern "C" sph_status sph_mesh_kernel_stats(sph_mesh *m, int32_t kid, double *ms, int64_t *launches) {
+  if (!m || kid < 0 || kid >= KID_COUNT) return fail(SPH_ERR_INVALID_ARG, "bad argument");
+  sph_batch *b = m->b;
+  HIPCHK(hipStreamSynchronize(b->stream));
+  for (auto &e : b->ev_live) {
+    float t = 0.f;
+    HIPCHK(hipEventElapsedTime(&t, e.a, e.b));
+    b->kms[e.kid] += t;
+    b->kcount[e.kid] += 1;
+    b->ev_pool.push_back(e.a);
+    b->ev_pool.push_back(e.b);
+  }
+  b->ev_live.clear();
+  if (ms) *ms = b->kms[kid];
+  if (launches) *launches = b->kcount[kid];
   return SPH_OK;
+}
+
+extern "C" int32_t sph_mesh_kernel_count(void) { return KID_COUNT; }
+
+extern "C" const char *sph_mesh_kernel_name(int32_t kid) {
+  return kid >= 0 && kid < KID_COUNT ? kKernelNames[kid] : "";
 }
 
 extern "C" sph_status sph_mesh_control_replay(const sph_params *p, int32_t n, const double *vbar,
@@ -974,44 +1309,3 @@ extern "C" sph_status sph_mesh_control_replay(const sph_params *p, int32_t n, co
   if (e != hipSuccess) return fail(SPH_ERR_DEVICE, "control replay: %s", hipGetErrorString(e));
   return SPH_OK;
 }
-
-extern "C" sph_status sph_mesh_profile(sph_mesh *m, int32_t enable) {
-  if (!m) return fail(SPH_ERR_INVALID_ARG, "null handle");
-  HIPCHK(hipStreamSynchronize(m->stream));
-  for (auto &e : m->ev_live) {
-    m->ev_pool.push_back(e.a);
-    m->ev_pool.push_back(e.b);
-  }
-  m->ev_live.clear();
-  for (int k = 0; k < KID_COUNT; ++k) {
-    m->kms[k] = 0.0;
-    m->kcount[k] = 0;
-  }
-  m->profiling = enable != 0;
-  return SPH_OK;
-}
-
-extern "C" sph_status sph_mesh_kernel_stats(sph_mesh *m, int32_t kid, double *ms, int64_t *launches) {
-  if (!m || kid < 0 || kid >= KID_COUNT) return fail(SPH_ERR_INVALID_ARG, "bad argument");
-  HIPCHK(hipStreamSynchronize(m->stream));
-  for (auto &e : m->ev_live) {
-    float t = 0.f;
-    HIPCHK(hipEventElapsedTime(&t, e.a, e.b));
-    m->kms[e.kid] += t;
-    m->kcount[e.kid] += 1;
-    m->ev_pool.push_back(e.a);
-    m->ev_pool.push_back(e.b);
-  }
-  m->ev_live.clear();
-  if (ms) *ms = m->kms[kid];
-  if (launches) *launches = m->kcount[kid];
-  return SPH_OK;
-}
-
-extern "C" int32_t sph_mesh_kernel_count(void) { return KID_COUNT; }
-
-extern "C" const char *sph_mesh_kernel_name(int32_t kid) {
-  return kid >= 0 && kid < KID_COUNT ? kKernelNames[kid] : "";
-}
-
-extern "C" int64_t sph_mesh_device_bytes(sph_mesh *m) { return m ? (int64_t)m->bytes : 0; }

@@ -12,7 +12,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def declared_functions():
     text = open(os.path.join(ROOT, "include", "sph_mesh.h")).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(sph_mesh_\w+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(sph_(?:mesh|batch|job)_\w+)\s*\(", text)))
 
 
 def test_header_declares_the_four_calls():
@@ -56,3 +56,25 @@ def test_struct_layout_matches_header():
     from paper_2003_01061_amd import binding
     assert ctypes.sizeof(binding.Geometry) == 4 + 4 + 48 + 8 + 8   # padded
     assert ctypes.sizeof(binding.Sizing) == 8 + 24 + 24
+
+
+def test_batch_footprint_and_job_cells_are_host_logic():
+    """Admission figures come from the host alone: the footprint grows with
+    every capacity, rejects nonsense, and a job's cell count follows its
+    cell side 2 h_min * cell_factor."""
+    from paper_2003_01061_amd import binding
+    from paper_2003_01061_amd import workload as wk
+    base = dict(dim=2, max_particles=100_000, max_cells=50_000, max_jobs=8)
+    f0 = binding.batch_footprint(**base)
+    assert f0 > 0
+    for key, val in (("max_particles", 200_000), ("max_cells", 100_000), ("max_jobs", 16),
+                     ("max_neighbors", 128)):
+        assert binding.batch_footprint(**dict(base, **{key: val})) > f0, key
+    assert binding.batch_footprint(**dict(base, precision=binding.SPH_FP32_MIXED)) < f0
+    assert binding.batch_footprint(**dict(base, max_jobs=65)) == -1
+    assert binding.batch_footprint(**dict(base, dim=4)) == -1
+    wl = wk.square_lattice(n_side=64)
+    assert binding.JobSpec(wl).cells() == 32 * 32          # side 2/64 on the unit square
+    assert binding.JobSpec(wl, cell_factor=0.5).cells() == 64 * 64
+    bad = dict(wl.params, window_samples=0)
+    assert binding.JobSpec(wl, params=bad).cells() == -1

@@ -1,0 +1,135 @@
+"""Batched execution: many jobs resident in one batch, stepped by one launch
+sequence.  A job's trajectory must not depend on what else shares the
+batch: every per-particle result reads only its own job's particles, the
+neighbour order is the canonical (cell, caller id) order inside the job's own
+cell range, and the per-feature reductions (a minimum on bit patterns and a
+fixed-point sum) are exact whatever the order.  So a job run in a mix is
+compared bit for bit with the same job run alone."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2003_01061_amd import binding
+from paper_2003_01061_amd import workload as wk
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu(gpu):
+    return gpu
+
+
+def alone(wl, steps, precision):
+    g = binding.SphMesh(wl, precision=precision, use_graph=1)
+    g.step(steps)
+    return g.positions(), g.error(), g.counters()
+
+
+def jobs_2d():
+    return [wk.scaled_hole_2d(3001, seed=31), wk.square_lattice(n_side=32, seed=5),
+            wk.scaled_hole_2d(12007, seed=32, centre=(0.45, 0.55), radius=0.2),
+            wk.scaled_hole_2d(777, seed=33)]
+
+
+def capacity(wls):
+    specs = [binding.JobSpec(w) for w in wls]
+    return specs, sum(s.n for s in specs), sum(s.cells() for s in specs)
+
+
+@pytest.mark.parametrize("precision", [binding.SPH_FP64, binding.SPH_FP32_MIXED])
+def test_job_in_a_mix_is_bit_identical_to_the_job_alone(precision):
+    wls = jobs_2d()
+    specs, npart, ncell = capacity(wls)
+    b = binding.SphBatch(2, precision, max_particles=npart, max_cells=ncell, max_jobs=4)
+    A = b.add(specs[0])
+    B = b.add(specs[1])
+    b.step(10)
+    C = b.add(specs[2])              # joins while A and B are mid-run
+    b.step(15)                       # odd split: eager step + graph pairs
+    xa = b.positions(A)
+    ea, ca = b.error(A), b.counters(A)
+    b.remove(A)                      # compaction moves B and C
+    D = b.add(specs[3])              # reuses a free slot
+    b.step(5)
+    got = {"A": (xa, ea, ca, 25, 0), "B": (b.positions(B), b.error(B), b.counters(B), 30, 1),
+           "C": (b.positions(C), b.error(C), b.counters(C), 20, 2),
+           "D": (b.positions(D), b.error(D), b.counters(D), 5, 3)}
+    live, conv, steps = b.status()
+    assert live[B] and live[C] and live[D]
+    assert D == A                    # the freed slot is reused
+    assert steps[B] == 30 and steps[C] == 20 and steps[D] == 5
+    for name, (x, e, c, k, w) in got.items():
+        xr, er, cr = alone(wls[w], k, precision)
+        assert np.array_equal(x, xr), name
+        assert e == er, name
+        assert c == cr, name
+        assert e["step"] == k or e["converged"], name
+
+
+def test_mix_against_oracle():
+    """Two jobs in one batch, each against its own oracle run."""
+    wls = [wk.scaled_hole_2d(2003, seed=41), wk.scaled_hole_2d(5003, seed=42, grad=2.0)]
+    specs, npart, ncell = capacity(wls)
+    b = binding.SphBatch(2, binding.SPH_FP64, max_particles=npart, max_cells=ncell, max_jobs=2)
+    ids = [b.add(s) for s in specs]
+    b.step(40)
+    for j, wl in zip(ids, wls):
+        ref = oracle.RefJob(wl)
+        ref.step(40)
+        assert np.abs(b.positions(j) - ref.state()[0]).max() <= 1e-12
+        assert b.counters(j)["interactions"] == ref.counters()["interactions"]
+
+
+def test_3d_mix_is_bit_identical():
+    wls = [wk.scaled_ball_3d(6007, seed=51, res=48), wk.scaled_ball_3d(9001, seed=52, res=48,
+                                                                     radius=0.25)]
+    specs, npart, ncell = capacity(wls)
+    b = binding.SphBatch(3, binding.SPH_FP32_MIXED, max_particles=npart, max_cells=ncell,
+                         max_jobs=3)
+    ids = [b.add(s) for s in specs]
+    b.step(12)
+    for j, wl in zip(ids, wls):
+        xr, er, cr = alone(wl, 12, binding.SPH_FP32_MIXED)
+        assert np.array_equal(b.positions(j), xr)
+        assert b.counters(j) == cr
+
+
+def test_full_batch_refuses_and_stays_usable():
+    wls = jobs_2d()[:2]
+    specs, npart, ncell = capacity(wls)
+    b = binding.SphBatch(2, binding.SPH_FP64, max_particles=npart, max_cells=ncell, max_jobs=2)
+    j0 = b.add(specs[0])
+    with pytest.raises(binding.SphError) as e:     # particles do not fit next to job 0 twice
+        b.add(binding.JobSpec(wk.scaled_hole_2d(npart, seed=9)))
+    assert e.value.status == 2
+    j1 = b.add(specs[1])
+    with pytest.raises(binding.SphError) as e:     # no free slot
+        b.add(specs[0])
+    assert e.value.status == 2
+    b.step(8)
+    xr, _, _ = alone(wls[0], 8, binding.SPH_FP64)
+    assert np.array_equal(b.positions(j0), xr)
+    xr, _, _ = alone(wls[1], 8, binding.SPH_FP64)
+    assert np.array_equal(b.positions(j1), xr)
+
+
+def test_converged_job_stops_counting_and_stays_put():
+    """A job whose every feature froze reports converged and its step count
+    stops, while the other job keeps moving."""
+    quick = wk.square_lattice(n_side=16, seed=7, max_phase1_steps=30, phase2_steps=20,
+                              ramp_steps=20)
+    slow = wk.scaled_hole_2d(3001, seed=31)
+    specs, npart, ncell = capacity([quick, slow])
+    b = binding.SphBatch(2, binding.SPH_FP64, max_particles=npart, max_cells=ncell, max_jobs=2)
+    q, s = b.add(specs[0]), b.add(specs[1])
+    b.step(120)
+    live, conv, steps = b.status()
+    assert conv[q] and not conv[s]
+    assert steps[s] == 120 and steps[q] == 70
+    x = b.positions(q)
+    b.step(6)
+    assert np.array_equal(b.positions(q), x)
+    ref = oracle.RefJob(quick)
+    ref.step(int(steps[q]))
+    assert np.abs(x - ref.state()[0]).max() <= 1e-12
