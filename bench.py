@@ -118,6 +118,62 @@ def cpu_baseline(wl, budget_s):
                        f"{t:.1f} s")
 
 
+def _build_job(desc):
+    from paper_2003_01061_amd import workload as wk
+    return wk.build_job(desc)
+
+
+def serving(args):
+    """The serving stream: n_jobs requests of both dimensions, N log-uniform in
+    [1e3, 5e5], FP32 sums + FP64 integration, full two-phase schedule.  First
+    all requests at t = 0 (closed loop): its completion rate is the saturation
+    rate.  Then Poisson arrivals at the given fractions of that rate."""
+    import multiprocessing as mp
+    from paper_2003_01061_amd import binding, serve
+    from paper_2003_01061_amd import workload as wk
+    descs = wk.serving_stream(args.serve_jobs, seed=4)
+    t0 = time.perf_counter()
+    order = sorted(descs, key=lambda d: -d.n)
+    with mp.get_context("spawn").Pool(min(8, os.cpu_count() or 1)) as pool:
+        built = pool.map(_build_job, order, chunksize=1)
+    wl_of = {d.idx: w for d, w in zip(order, built)}
+    specs = {d.idx: binding.JobSpec(wl_of[d.idx]) for d in descs}
+    print(f"[bench] serving stream: {len(descs)} jobs, "
+          f"{sum(d.n for d in descs)} particles, built in {time.perf_counter() - t0:.1f}s",
+          file=sys.stderr, flush=True)
+    srv = serve.Server(pool_bytes=int(args.serve_pool_gib * (1 << 30)), slots=args.serve_slots,
+                       precision=binding.SPH_FP32_MIXED, chunk=args.serve_chunk)
+
+    def one(rate):
+        t = wk.poisson_arrivals(len(descs), rate, seed=4)
+        reqs = [serve.Request(d.idx, d.dim, d.n, float(t[q]), specs[d.idx])
+                for q, d in enumerate(descs)]
+        srv.stats = serve.ServeStats()
+        done = [0]
+
+        def progress(r):
+            done[0] += 1
+            if done[0] % 32 == 0:
+                print(f"[bench] serving: {done[0]} jobs done", file=sys.stderr, flush=True)
+
+        res = srv.run(reqs, progress=progress)
+        out = serve.summarize(res, srv.stats)
+        out["arrival_rate_per_s"] = None if not np.isfinite(rate) else rate
+        print(f"[bench] serving rate={rate:.3g}/s: " + json.dumps(out), file=sys.stderr, flush=True)
+        return out
+
+    closed = one(float("inf"))
+    sat = closed["jobs_per_s"]
+    runs = {"closed_loop": closed}
+    for f in args.serve_rates:
+        runs[f"poisson_{f:g}x"] = one(f * sat)
+    return dict(jobs=len(descs), particles=int(sum(d.n for d in descs)),
+                jobs_2d=sum(d.dim == 2 for d in descs), pool_bytes=srv.footprint_bytes(),
+                slots=args.serve_slots, chunk_steps=args.serve_chunk,
+                capacity_particles={str(k): v for k, v in srv.cap_particles.items()},
+                saturation_jobs_per_s=sat, runs=runs)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -128,6 +184,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--n", type=int, default=250_000)
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-jobs", type=int, default=256)
+    ap.add_argument("--serve-rates", type=float, nargs="*", default=[0.9])
+    ap.add_argument("--serve-pool-gib", type=float, default=8.0)
+    ap.add_argument("--serve-slots", type=int, default=32)
+    ap.add_argument("--serve-chunk", type=int, default=20)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
@@ -162,6 +224,12 @@ def main():
     print(f"[bench] profile: " + ", ".join(f"{k}={v[0]*1e3:.1f}us" for k, v in per.items()),
           file=sys.stderr, flush=True)
 
+    srv = None if args.no_serve else serving(args)
+    lat = None
+    if srv is not None:
+        key = next((k for k in srv["runs"] if k.startswith("poisson")), "closed_loop")
+        lat = [srv["runs"][key]["latency_p50_s"], srv["runs"][key]["latency_p99_s"]]
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(wl, args.cpu_seconds)
@@ -193,7 +261,8 @@ def main():
                         "converged": r32["converged"], "escaped": r32["escaped"]},
         "quality": {"fp32": quality(wl, r32["positions"]),
                     "fp64": None if r64 is None else quality(wl, r64["positions"])},
-        "latency_p50_p99_s": None,
+        "latency_p50_p99_s": lat,
+        "serving": srv,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "avg_launch_us": per[dom][0] * 1e3, "bytes_per_launch": byts,

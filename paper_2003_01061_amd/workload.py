@@ -414,3 +414,61 @@ def scaled_ball_3d(n_total, seed, centre=(0.5, 0.5, 0.5), radius=0.3, grad=4.0, 
                   dict(kind=H_GRADED_TO_HOLES, h0=4.745e-3, grad=grad, dcap=np.inf,
                        point=[0.0, 0.0, 0.0]),
                   default_params(**pover), n_total, seed, 0, res)
+
+
+# ---------------------------------------------------------------------------
+# the serving stream: many jobs of both dimensions and a wide size range
+# ---------------------------------------------------------------------------
+@dataclass
+class JobDesc:
+    """One meshing request of the serving stream: enough to build its
+    Workload (build_job) without holding the particles."""
+    idx: int
+    dim: int
+    n: int
+    centre: tuple
+    radius: float
+    grad: float
+    seed: int
+    pover: dict = field(default_factory=dict)
+
+
+def serving_stream(n_jobs=256, seed=4, n_min=1_000, n_max=500_000, **pover):
+    """Seeded request stream: dimension 2 or 3 with probability 1/2, N log-uniform
+    in [n_min, n_max]; 2D jobs are squares with a disc hole (centre U[0.35,0.65]^2,
+    r U[0.1,0.3]), 3D jobs cubes with a ball hole (centre U[0.4,0.6]^3, r
+    U[0.15,0.35]); h = h0 (1 + g d) with g U[1,8] and h0 solved from N.  The
+    schedule is the full two-phase one with Phase One capped at 1,200 steps."""
+    rng = np.random.Generator(np.random.MT19937(seed))
+    pover.setdefault("max_phase1_steps", 1200)
+    out = []
+    for q in range(n_jobs):
+        dim = 2 if rng.random() < 0.5 else 3
+        n = int(math.floor(math.exp(rng.uniform(math.log(n_min), math.log(n_max)))))
+        if dim == 2:
+            c = tuple(rng.uniform(0.35, 0.65, 2).tolist())
+            r = float(rng.uniform(0.1, 0.3))
+        else:
+            c = tuple(rng.uniform(0.4, 0.6, 3).tolist())
+            r = float(rng.uniform(0.15, 0.35))
+        g = float(rng.uniform(1.0, 8.0))
+        out.append(JobDesc(q, dim, n, c, r, g, int(rng.integers(1, 2**31 - 1)), dict(pover)))
+    return out
+
+
+def build_job(d: JobDesc) -> Workload:
+    """Particles of one request (seeded by the request)."""
+    if d.dim == 2:
+        return scaled_hole_2d(d.n, d.seed, centre=d.centre, radius=d.radius, grad=d.grad,
+                              res=512, **d.pover)
+    return scaled_ball_3d(d.n, d.seed, centre=d.centre, radius=d.radius, grad=d.grad, res=96,
+                          **d.pover)
+
+
+def poisson_arrivals(n, rate, seed=4):
+    """Arrival times (s) of a Poisson process of the given rate (1/s); all at 0
+    when rate is infinite."""
+    if not np.isfinite(rate):
+        return np.zeros(n)
+    rng = np.random.Generator(np.random.MT19937(seed + 1000))
+    return np.cumsum(rng.exponential(1.0 / rate, n))
