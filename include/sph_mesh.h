@@ -105,6 +105,9 @@ typedef struct {
   int32_t max_neighbors;     /* neighbour-list capacity per particle; 0 = 64 in
                                 2D, 160 in 3D */
   double cell_factor;        /* cell side = 2 h_min cell_factor; 0 = 1.0 */
+  int32_t scan_tile;         /* candidate records tested per pass of the
+                                neighbour scan: 2, 4 or 8; 0 = 4.  Results do
+                                not depend on it (autotuning knob) */
   int32_t use_graph;         /* 1: steps replay a captured HIP graph */
   int32_t debug_fields;      /* 1: keep gamma, V~ and v~ for sph_mesh_field */
   void *stream;              /* hipStream_t to run on (e.g. PyTorch's current
@@ -226,6 +229,7 @@ typedef struct {
   int64_t max_cells;         /* capacity: cells of all resident jobs' grids */
   int32_t max_jobs;          /* resident jobs, 1..64 */
   int32_t max_neighbors;     /* 0 = 64 in 2D, 160 in 3D */
+  int32_t scan_tile;         /* 2, 4 or 8 (0 = 4), as in sph_params */
   int32_t use_graph;         /* 1: steps replay a captured graph of two steps */
   int32_t debug_fields;      /* keep gamma, V~, v~ (single-job inspection) */
   void *stream;              /* hipStream_t; NULL = the batch creates its own */

@@ -36,14 +36,14 @@ class Params(C.Structure):
                 ("ramp_halving", C.c_int32), ("phase2_steps", C.c_int32),
                 ("max_phase1_steps", C.c_int32), ("precision", C.c_int32),
                 ("max_neighbors", C.c_int32), ("cell_factor", C.c_double),
-                ("use_graph", C.c_int32), ("debug_fields", C.c_int32),
+                ("scan_tile", C.c_int32), ("use_graph", C.c_int32), ("debug_fields", C.c_int32),
                 ("stream", C.c_void_p)]
 
 
 class BatchParams(C.Structure):
     _fields_ = [("dim", C.c_int32), ("precision", C.c_int32), ("max_particles", C.c_int64),
                 ("max_cells", C.c_int64), ("max_jobs", C.c_int32), ("max_neighbors", C.c_int32),
-                ("use_graph", C.c_int32), ("debug_fields", C.c_int32), ("stream", C.c_void_p)]
+                ("scan_tile", C.c_int32), ("use_graph", C.c_int32), ("debug_fields", C.c_int32), ("stream", C.c_void_p)]
 
 
 class SphError(RuntimeError):
@@ -297,11 +297,12 @@ class JobSpec:
 
 
 def batch_params(dim, precision=SPH_FP64, max_particles=0, max_cells=1, max_jobs=1,
-                 max_neighbors=0, use_graph=1, debug_fields=0, stream=None):
+                 max_neighbors=0, use_graph=1, debug_fields=0, stream=None, scan_tile=0):
     bp = BatchParams()
     bp.dim, bp.precision = dim, precision
     bp.max_particles, bp.max_cells, bp.max_jobs = max_particles, max_cells, max_jobs
     bp.max_neighbors, bp.use_graph, bp.debug_fields = max_neighbors, use_graph, debug_fields
+    bp.scan_tile = scan_tile
     bp.stream = stream
     return bp
 
@@ -317,9 +318,9 @@ class SphBatch:
     sequence per step (libsphmesh.so batch handle)."""
 
     def __init__(self, dim, precision=SPH_FP64, max_particles=0, max_cells=1, max_jobs=1,
-                 max_neighbors=0, use_graph=1, stream=None):
+                 max_neighbors=0, use_graph=1, stream=None, scan_tile=0):
         self.bp = batch_params(dim, precision, max_particles, max_cells, max_jobs,
-                               max_neighbors, use_graph, 0, stream)
+                               max_neighbors, use_graph, 0, stream, scan_tile)
         self.max_jobs = max_jobs
         h = C.c_void_p()
         _check("sph_batch_create", lib().sph_batch_create(C.byref(self.bp), C.byref(h)))

@@ -179,8 +179,26 @@ __device__ __forceinline__ bool within(const double4 &a, const double4 &b) {
     d = a.z - b.z;
     s = s + d * d;
   }
-  double m = a.w > b.w ? a.w : b.w;
+  const double m = __builtin_fmax(a.w, b.w);   // h > 0 and finite
   return s < 4.0 * (m * m);
+}
+
+// The same predicate with A4 = 4.0 * (h_a * h_a) precomputed: 4 max(h_a, h_b)^2
+// is the larger of 4 h_a^2 and 4 h_b^2 (squaring and scaling by 4 are
+// monotone, and both sides round the same products), so s < 4 max(.)^2 holds
+// exactly when s is below either.
+template <int D>
+__device__ __forceinline__ bool within_a4(const double4 &a, double A4, const double4 &b) {
+#pragma clang fp contract(off)
+  double d = a.x - b.x;
+  double s = d * d;
+  d = a.y - b.y;
+  s = s + d * d;
+  if (D == 3) {
+    d = a.z - b.z;
+    s = s + d * d;
+  }
+  return (s < A4) | (s < 4.0 * (b.w * b.w));
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs; map them so that

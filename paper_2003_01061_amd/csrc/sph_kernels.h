@@ -68,32 +68,39 @@ __device__ __forceinline__ void wave_commit(bool valid, int key, unsigned long l
   }
 }
 
-// one thread per feature slot: fold the stripes of every tracked feature and
-// reset them; which = 0 -> dt_1 and the V~ sum, which = 1 -> dt.  The time
-// step is the minimum of the particle terms and the job's cap dt_max.
+// read a striped accumulator word (filled by the previous launch) and reset it
+__device__ __forceinline__ unsigned long long take(unsigned long long *p, unsigned long long reset) {
+  const unsigned long long v = *p;
+  *p = reset;
+  return v;
+}
+
+static_assert(NSTRIPE == 64, "one stripe per lane");
+
+// One wave per feature slot folds its NSTRIPE stripes (a lane each, one
+// memory round trip) and resets them; which = 0 -> dt_1 and the V~ sum,
+// which = 1 -> dt.  The time step is the minimum of the particle terms and
+// the job's dt_max.
 __global__ __launch_bounds__(BLOCK) void k_group_reduce(Batch B, int which) {
-  const int q = blockIdx.x * BLOCK + threadIdx.x;
-  if (q >= B.njobs * MAXF) return;
-  Group &G = B.grp[q];
-  if (!G.tracked) return;
-  unsigned long long *mp = B.smin + (size_t)q * NSTRIPE;
-  unsigned long long *sp = B.ssum + (size_t)q * NSTRIPE;
-  unsigned long long mn = ~0ull, sm = 0ull;
-#pragma unroll 8
-  for (int t = 0; t < NSTRIPE; ++t) {
-    mn = umin64(mn, mp[t]);
-    mp[t] = ~0ull;
-    if (which == 0) {
-      sm += sp[t];
-      sp[t] = 0ull;
+  const int lane = __lane_id();
+  const int q = (int)(blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6));
+  if (q < B.njobs * MAXF && B.grp[q].tracked) {   // uniform per wave
+    Group &G = B.grp[q];
+    unsigned long long mn = take(B.smin + (size_t)q * NSTRIPE + lane, ~0ull);
+    unsigned long long sm = which == 0 ? take(B.ssum + (size_t)q * NSTRIPE + lane, 0ull) : 0ull;
+    for (int o = 32; o > 0; o >>= 1) {
+      mn = umin64(mn, __shfl_xor(mn, o));
+      sm += __shfl_xor(sm, o);
     }
-  }
-  mn = umin64(mn, dbits(B.jobs[q / MAXF].ctl.dt_max));
-  if (which == 0) {
-    G.dt1_bits = mn;
-    G.vsum = sm;
-  } else {
-    G.dt_bits = mn;
+    if (lane == 0) {
+      mn = umin64(mn, dbits(B.jobs[q / MAXF].ctl.dt_max));
+      if (which == 0) {
+        G.dt1_bits = mn;
+        G.vsum = sm;
+      } else {
+        G.dt_bits = mn;
+      }
+    }
   }
 }
 
@@ -397,7 +404,7 @@ __device__ __forceinline__ void sweep_a_sums(const Geom &g, const Parts &s,
 // neighbour instead of once per candidate.  Every particle reads its own
 // job's geometry and grid; cells of different jobs never meet.
 // ---------------------------------------------------------------------------
-template <int D, typename R, bool FORCES>
+template <int D, typename R, bool FORCES, int NB>
 __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
     Batch B, Parts s, const uint32_t *__restrict__ cstart, int all, uint32_t *__restrict__ nbr,
     uint32_t *__restrict__ nnb, typename Vec4<R>::T *__restrict__ ap,
@@ -430,52 +437,78 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
         lo_c[a] = cell_coord(G, a, pc[a] - Rs);
         hi_c[a] = cell_coord(G, a, pc[a] + Rs);
       }
+      // grid values the row loop needs, kept in registers
+      const double c0 = G.c[0], inv0 = G.inv_c[0], lo1 = G.lo[1], c1 = G.c[1];
+      const double lo2 = D == 3 ? G.lo[2] : 0.0, c2 = D == 3 ? G.c[2] : 0.0;
+      const uint32_t nc0 = (uint32_t)G.nc[0], nc1 = (uint32_t)G.nc[1], cbase = G.cbase;
+      const double u0 = (pc[0] - G.lo[0]) * inv0;     // x of i in cell units
+      const double top0 = (double)(G.nc[0] - 1);
       // features that bound fi (bit = local feature id); a candidate of fi's
       // own feature interacts as "same", one of a bounding feature of the same
-      // job as "boundary"
-      const unsigned long long bm = B.bmask[fi];
-      const int jbase = job * MAXF;
-      constexpr int NB = SPH_NBATCH;   // candidate records loaded together
+      // job as "boundary".  The scan only visits cells of i's own job, so a
+      // candidate's feature slot is in i's job range and its local id is its
+      // low 6 bits.
+      const unsigned long long accept = B.bmask[fi] | (1ull << (fi & (MAXF - 1)));
+      const double A4 = 4.0 * (xi.w * xi.w);
+      static_assert(NB >= 1 && NB <= 8, "records are padded by 8");
+      uint32_t *wp = nbr + i;            // next list slot of i (ELL: stride n)
       for (int cz = lo_c[2]; cz <= hi_c[2]; ++cz) {
         double dz2 = 0.0;
         if (D == 3) {
-          const double z0 = G.lo[2] + cz * G.c[2];
-          double dz = z0 - pc[2] > pc[2] - (z0 + G.c[2]) ? z0 - pc[2] : pc[2] - (z0 + G.c[2]);
-          dz = dz - 1e-7 * G.c[2];
+          const double z0 = lo2 + cz * c2;
+          double dz = z0 - pc[2] > pc[2] - (z0 + c2) ? z0 - pc[2] : pc[2] - (z0 + c2);
+          dz = dz - 1e-7 * c2;
           dz = dz > 0.0 ? dz : 0.0;
           dz2 = dz * dz;
         }
         for (int cy = lo_c[1]; cy <= hi_c[1]; ++cy) {
-          const double y0 = G.lo[1] + cy * G.c[1];
-          double dy = y0 - pc[1] > pc[1] - (y0 + G.c[1]) ? y0 - pc[1] : pc[1] - (y0 + G.c[1]);
-          dy = dy - 1e-7 * G.c[1];
+          const double y0 = lo1 + cy * c1;
+          double dy = y0 - pc[1] > pc[1] - (y0 + c1) ? y0 - pc[1] : pc[1] - (y0 + c1);
+          dy = dy - 1e-7 * c1;
           dy = dy > 0.0 ? dy : 0.0;
           const double w2 = R2 - dy * dy - dz2;
           if (w2 < 0.0) continue;
-          const double wx = __builtin_sqrt(w2) * (1.0 + 1e-9) + 1e-7 * G.c[0];
-          const int cx0 = cell_coord(G, 0, pc[0] - wx), cx1 = cell_coord(G, 0, pc[0] + wx);
-          const uint32_t row =
-              G.cbase + ((uint32_t)cz * (uint32_t)G.nc[1] + (uint32_t)cy) * (uint32_t)G.nc[0];
-          const uint32_t jb = cstart[row + cx0], je = cstart[row + cx1 + 1];
+          // half chord of the row; the FP32 square root (error < 2e-7
+          // relative) is covered by the 1e-6 relative widening
+          const double wx = (double)sqrt_((float)w2) * (1.0 + 1e-6) + 1e-7 * c0;
+          const double wu = wx * inv0;
+          double t0 = __builtin_floor(u0 - wu), t1 = __builtin_floor(u0 + wu);
+          t0 = t0 >= 0.0 ? t0 : 0.0;   // also maps NaN to cell 0
+          t1 = t1 >= 0.0 ? t1 : 0.0;
+          t0 = t0 < top0 ? t0 : top0;
+          t1 = t1 < top0 ? t1 : top0;
+          const uint32_t row = cbase + ((uint32_t)cz * nc1 + (uint32_t)cy) * nc0;
+          const uint32_t jb = cstart[row + (uint32_t)t0], je = cstart[row + (uint32_t)t1 + 1];
+          // NB candidates per pass: records loaded together (the arrays are
+          // padded by 8 past the capacity), the predicate evaluated for all of
+          // them without early exits, then the hits appended in order
           for (uint32_t j0 = jb; j0 < je; j0 += NB) {
+            const double4 *rp = s.xh + j0;
+            const uint16_t *fp = s.f + j0;
             double4 xr[NB];
-            int fr[NB];
+            uint32_t fr[NB];
 #pragma unroll
-            for (int q = 0; q < NB; ++q) {   // records are padded by 8 past the capacity
-              xr[q] = s.xh[j0 + q];
-              fr[q] = s.f[j0 + q];
+            for (int q = 0; q < NB; ++q) {
+              xr[q] = rp[q];
+              fr[q] = fp[q];
             }
+            uint32_t tag[NB];
 #pragma unroll
             for (int q = 0; q < NB; ++q) {
               const uint32_t j = j0 + q;
-              if (j >= je) break;
-              if ((int)j == i || !within<D>(xi, xr[q])) continue;
-              const int fj = fr[q];
-              const int lj = fj - jbase;
-              const int r = fj == fi ? 1 : ((unsigned)lj < (unsigned)MAXF ? (int)((bm >> lj) & 1ull) * 2 : 0);
-              if (!r) continue;
-              if ((int)count < B.cap) nbr[(size_t)count * n + i] = j | (r == 2 ? 0x80000000u : 0u);
-              ++count;
+              const bool rel = (accept >> (fr[q] & (MAXF - 1))) & 1ull;
+              const bool hit = rel & (j < je) & (j != (uint32_t)i) & within_a4<D>(xi, A4, xr[q]);
+              tag[q] = hit ? (j | (fr[q] == (uint32_t)fi ? 0u : 0x80000000u)) : 0xffffffffu;
+            }
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+              if (tag[q] != 0xffffffffu) {
+                if ((int)count < B.cap) {
+                  *wp = tag[q];
+                  wp += n;
+                }
+                ++count;
+              }
             }
           }
         }
@@ -680,6 +713,48 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_b(Batch B, Parts s,
 }
 
 // ---------------------------------------------------------------------------
+// control of every feature of every job; prepares the next step (one block)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(BLOCK) void k_control(Batch B) {
+  __shared__ int moving[MAXJ];
+  for (int j = threadIdx.x; j < MAXJ; j += BLOCK) moving[j] = 0;
+  __syncthreads();
+  for (int q = threadIdx.x; q < B.njobs * MAXF; q += BLOCK) {
+    Group &Gq = B.grp[q];
+    if (!Gq.tracked) continue;
+    const Ctl &P = B.jobs[q / MAXF].ctl;
+    if (Gq.phase != PH_FROZEN) {
+      const double dt1 = bitsd(Gq.dt1_bits), dt = bitsd(Gq.dt_bits);
+      const double vbar = (double)Gq.vsum / Gq.vscale;
+      Gq.dt1 = dt1;
+      Gq.dt = dt;
+      control_law(P, Gq, vbar, dt);
+    }
+    Gq.active = Gq.phase != PH_FROZEN;
+    Gq.reset_now = Gq.reset_next;
+    Gq.eps = damping(P, Gq);
+    if (Gq.active) atomicOr(&moving[q / MAXF], 1);
+  }
+  __syncthreads();
+  // per job: fold the interaction and escape stripes (a wave per job)
+  const int lane = __lane_id();
+  for (int j = threadIdx.x >> 6; j < B.njobs; j += BLOCK / 64) {
+    unsigned long long c = take(B.scnt + (size_t)j * NSTRIPE + lane, 0ull);
+    unsigned long long e = take(B.sesc + (size_t)j * NSTRIPE + lane, 0ull);
+    c = wave_sum_u64(c);
+    e = wave_sum_u64(e);
+    JobStat &S = B.st[j];
+    if (lane == 0 && S.live) {
+      if (!S.converged) S.steps += 1ull;     // a converged job stops counting
+      S.inter_last = c;
+      S.inter_total += c;
+      S.escaped += e;
+      S.converged = moving[j] ? 0 : 1;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // integration with feature projection (FP64 in every precision mode), then
 // h, cell and rank of every particle for the next step's sort
 // ---------------------------------------------------------------------------
@@ -737,51 +812,6 @@ __global__ __launch_bounds__(BLOCK) void k_integrate_hash(
   const uint32_t r = rank_in_cell(cc, i < n, cnt);
   if (i < n) rank[i] = r;
   wave_commit(escaped, job, 0ull, 1ull, nullptr, B.sesc);
-}
-
-// ---------------------------------------------------------------------------
-// control of every feature of every job; prepares the next step (one block)
-// ---------------------------------------------------------------------------
-constexpr int CTL_BLOCK = 1024;
-
-__global__ __launch_bounds__(CTL_BLOCK) void k_control(Batch B) {
-  __shared__ int moving[MAXJ];
-  for (int j = threadIdx.x; j < MAXJ; j += CTL_BLOCK) moving[j] = 0;
-  __syncthreads();
-  for (int q = threadIdx.x; q < B.njobs * MAXF; q += CTL_BLOCK) {
-    Group &Gq = B.grp[q];
-    if (!Gq.tracked) continue;
-    const Ctl &P = B.jobs[q / MAXF].ctl;
-    if (Gq.phase != PH_FROZEN) {
-      const double dt1 = bitsd(Gq.dt1_bits), dt = bitsd(Gq.dt_bits);
-      const double vbar = (double)Gq.vsum / Gq.vscale;
-      Gq.dt1 = dt1;
-      Gq.dt = dt;
-      control_law(P, Gq, vbar, dt);
-    }
-    Gq.active = Gq.phase != PH_FROZEN;
-    Gq.reset_now = Gq.reset_next;
-    Gq.eps = damping(P, Gq);
-    if (Gq.active) atomicOr(&moving[q / MAXF], 1);
-  }
-  __syncthreads();
-  for (int j = threadIdx.x; j < B.njobs; j += CTL_BLOCK) {
-    JobStat &S = B.st[j];
-    unsigned long long c = 0, e = 0;
-    unsigned long long *cp = B.scnt + (size_t)j * NSTRIPE, *ep = B.sesc + (size_t)j * NSTRIPE;
-    for (int t = 0; t < NSTRIPE; ++t) {
-      c += cp[t];
-      e += ep[t];
-      cp[t] = 0ull;
-      ep[t] = 0ull;
-    }
-    if (!S.live) continue;
-    if (!S.converged) S.steps += 1ull;     // a converged job stops counting
-    S.inter_last = c;
-    S.inter_total += c;
-    S.escaped += e;
-    S.converged = moving[j] ? 0 : 1;
-  }
 }
 
 // ---------------------------------------------------------------------------

@@ -199,6 +199,10 @@ static sph_status validate(const sph_geometry *g, const sph_sizing *s, const sph
     return fail(SPH_ERR_INVALID_ARG, "precision must be SPH_FP64 or SPH_FP32_MIXED");
   if (p->max_neighbors < 0 || p->max_neighbors > 4096)
     return fail(SPH_ERR_INVALID_ARG, "max_neighbors must be in [0, 4096]");
+  if (p->scan_tile != 0 && p->scan_tile != 2 && p->scan_tile != 4 && p->scan_tile != 8)
+    return fail(SPH_ERR_INVALID_ARG, "scan_tile must be 0, 2, 4 or 8");
+  if (!(p->cell_factor >= 0.0) || p->cell_factor > 16.0)
+    return fail(SPH_ERR_INVALID_ARG, "cell_factor must be in [0, 16]");
   return SPH_OK;
 }
 
@@ -264,7 +268,7 @@ struct HostJob {
 };
 
 struct sph_batch {
-  int D = 2, prec = SPH_FP64, cap = 64;
+  int D = 2, prec = SPH_FP64, cap = 64, tile = 4;
   bool use_graph = false, debug = false;
   int ncap = 0, jcap = 0;
   uint32_t ccap = 0;
@@ -401,10 +405,23 @@ struct sph_batch {
 
   template <int DD>
   sph_status enqueue_lists_only() {
-    HIPCHK(launch(KID_NBR_LISTS, k_nbr_forces<DD, double, false>, blocks8(n), BLOCK, dev(), P[cur],
-                  (const uint32_t *)cstart, 1, nbr, nnb, (double4 *)nullptr, (double *)nullptr,
-                  (double *)nullptr));
+    HIPCHK(launch(KID_NBR_LISTS, k_nbr_forces<DD, double, false, 4>, blocks8(n), BLOCK, dev(),
+                  P[cur], (const uint32_t *)cstart, 1, nbr, nnb, (double4 *)nullptr,
+                  (double *)nullptr, (double *)nullptr));
     return SPH_OK;
+  }
+
+  // the neighbour + sweep A kernel for the batch's scan tile
+  template <int DD, typename R>
+  hipError_t launch_nbr_forces(const Batch &B, const Parts &s) {
+    using R4 = typename Vec4<R>::T;
+    auto go = [&](auto kern) {
+      return launch(KID_NBR_FORCES, kern, blocks8(n), BLOCK, B, s, (const uint32_t *)cstart, 0,
+                    nbr, nnb, (R4 *)ap, dbg_gam, dbg_vt);
+    };
+    if (tile == 2) return go(k_nbr_forces<DD, R, true, 2>);
+    if (tile == 8) return go(k_nbr_forces<DD, R, true, 8>);
+    return go(k_nbr_forces<DD, R, true, 4>);
   }
 
   template <int DD, typename R>
@@ -412,16 +429,15 @@ struct sph_batch {
     using R4 = typename Vec4<R>::T;
     const Batch B = dev();
     const Parts &s = P[cur];
-    const unsigned gslots = (unsigned)((njobs * MAXF + BLOCK - 1) / BLOCK);
-    HIPCHK(launch(KID_NBR_FORCES, k_nbr_forces<DD, R, true>, blocks8(n), BLOCK, B, s,
-                  (const uint32_t *)cstart, 0, nbr, nnb, (R4 *)ap, dbg_gam, dbg_vt));
+    const unsigned gslots = (unsigned)((njobs * MAXF + BLOCK / 64 - 1) / (BLOCK / 64));
+    HIPCHK((launch_nbr_forces<DD, R>(B, s)));
     HIPCHK(launch(KID_REDUCE_A, k_group_reduce, gslots, BLOCK, B, 0));
     HIPCHK(launch(KID_SWEEP_B, k_sweep_b<DD, R>, blocks8(n), BLOCK, B, s, (const uint32_t *)nbr,
                   (const uint32_t *)nnb, (const R4 *)ap, (R4 *)acc, dbg_vm));
     HIPCHK(launch(KID_REDUCE_B, k_group_reduce, gslots, BLOCK, B, 1));
     HIPCHK(launch(KID_INTEGRATE_HASH, k_integrate_hash<DD, R>, blocks(n), BLOCK, B, s,
                   (const R4 *)acc, cell, rank, cnt));
-    HIPCHK(launch(KID_CONTROL, k_control, 1u, (unsigned)CTL_BLOCK, B));
+    HIPCHK(launch(KID_CONTROL, k_control, 1u, BLOCK, B));
     return SPH_OK;
   }
 
@@ -632,10 +648,13 @@ extern "C" sph_status sph_batch_create(const sph_batch_params *bp, sph_batch **o
   if (bp->max_particles > 0x7ffffff0ll || bp->max_cells > 0x7ffffff0ll)
     return fail(SPH_ERR_UNSUPPORTED, "capacity above 2^31");
   if (bp->max_neighbors > 4096) return fail(SPH_ERR_INVALID_ARG, "max_neighbors above 4096");
+  if (bp->scan_tile != 0 && bp->scan_tile != 2 && bp->scan_tile != 4 && bp->scan_tile != 8)
+    return fail(SPH_ERR_INVALID_ARG, "scan_tile must be 0, 2, 4 or 8");
   auto *B = new sph_batch();
   B->D = bp->dim;
   B->prec = bp->precision;
   B->cap = bp->max_neighbors ? bp->max_neighbors : (int)default_cap(bp->dim);
+  B->tile = bp->scan_tile ? bp->scan_tile : 4;
   B->use_graph = bp->use_graph != 0;
   B->debug = bp->debug_fields != 0;
   B->ncap = (int)bp->max_particles;
@@ -1007,6 +1026,7 @@ extern "C" sph_status sph_mesh_create(const sph_geometry *g, const sph_sizing *s
   bp.max_cells = sph_job_cells(g, s, p);
   bp.max_jobs = 1;
   bp.max_neighbors = p->max_neighbors;
+  bp.scan_tile = p->scan_tile;
   bp.use_graph = p->use_graph;
   bp.debug_fields = p->debug_fields;
   bp.stream = p->stream;
