@@ -52,15 +52,16 @@ def kernel_bytes(name, wl, n_active, inter, real_bytes):
     return None
 
 
-def run_timed(wl, precision, steps, warmup, graph=True):
+def run_timed(wl, precision, steps, warmup, graph=True, cfg=None):
     from paper_2003_01061_amd import binding
     import torch
+    cfg = cfg or {}
     if warmup:
-        w = binding.SphMesh(wl, precision=precision, use_graph=int(graph))
+        w = binding.SphMesh(wl, precision=precision, use_graph=int(graph), **cfg)
         w.step(warmup)
         w.sync()
         w.close()
-    j = binding.SphMesh(wl, precision=precision, use_graph=int(graph))
+    j = binding.SphMesh(wl, precision=precision, use_graph=int(graph), **cfg)
     j.sync()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -77,10 +78,10 @@ def run_timed(wl, precision, steps, warmup, graph=True):
                 positions=x)
 
 
-def profile_kernels(wl, precision, steps):
+def profile_kernels(wl, precision, steps, cfg=None):
     """Per-kernel durations from HIP events recorded on the library's stream."""
     from paper_2003_01061_amd import binding
-    j = binding.SphMesh(wl, precision=precision, use_graph=0)
+    j = binding.SphMesh(wl, precision=precision, use_graph=0, **(cfg or {}))
     j.profile(True)
     j.step(steps)
     stats = j.kernel_stats()
@@ -141,8 +142,23 @@ def serving(args):
     print(f"[bench] serving stream: {len(descs)} jobs, "
           f"{sum(d.n for d in descs)} particles, built in {time.perf_counter() - t0:.1f}s",
           file=sys.stderr, flush=True)
+    # autotune per dimension on the median-size request of that dimension
+    from paper_2003_01061_amd import autotune
+    configs, tuning = {}, {}
+    if not args.no_tune:
+        for d in (2, 3):
+            ds = sorted((x for x in descs if x.dim == d), key=lambda x: x.n)
+            if not ds:
+                continue
+            med = ds[len(ds) // 2]
+            r = autotune.tune([specs[med.idx]], d, binding.SPH_FP32_MIXED, steps=10, warmup=2,
+                              max_neighbors=192 if d == 3 else 64)
+            configs[d] = r.best
+            tuning[str(d)] = dict(job_particles=med.n, best=r.best,
+                                  speedup_over_default=r.speedup_over_default())
+        print(f"[bench] serving tuned: {json.dumps(tuning)}", file=sys.stderr, flush=True)
     srv = serve.Server(pool_bytes=int(args.serve_pool_gib * (1 << 30)), slots=args.serve_slots,
-                       precision=binding.SPH_FP32_MIXED, chunk=args.serve_chunk)
+                       precision=binding.SPH_FP32_MIXED, chunk=args.serve_chunk, configs=configs)
 
     def one(rate):
         t = wk.poisson_arrivals(len(descs), rate, seed=4)
@@ -171,7 +187,7 @@ def serving(args):
                 jobs_2d=sum(d.dim == 2 for d in descs), pool_bytes=srv.footprint_bytes(),
                 slots=args.serve_slots, chunk_steps=args.serve_chunk,
                 capacity_particles={str(k): v for k, v in srv.cap_particles.items()},
-                saturation_jobs_per_s=sat, runs=runs)
+                saturation_jobs_per_s=sat, autotune=tuning, runs=runs)
 
 
 def main():
@@ -185,6 +201,11 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--n", type=int, default=250_000)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--pmc-pass", choices=["step", "copy"], default=None,
+                    help="counter-collection pass for rocprofv3 --pmc: 'step' runs --steps "
+                         "eagerly launched FP32-mixed steps of the workload (default tuning), "
+                         "'copy' one 256 MiB device copy (counter calibration); prints no JSON")
     ap.add_argument("--serve-jobs", type=int, default=256)
     ap.add_argument("--serve-rates", type=float, nargs="*", default=[0.9])
     ap.add_argument("--serve-pool-gib", type=float, default=8.0)
@@ -202,17 +223,42 @@ def main():
     from paper_2003_01061_amd import binding
     from paper_2003_01061_amd import workload as wk
 
+    if args.pmc_pass == "copy":
+        a = torch.ones(1 << 25, dtype=torch.float64, device="cuda")   # 256 MiB
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(f"[bench] copy pass: {a.numel() * 8} bytes read, {b.numel() * 8} written",
+              file=sys.stderr, flush=True)
+        return
     wl = wk.square_hole(n_total=args.n)
+    if args.pmc_pass == "step":
+        j = binding.SphMesh(wl, precision=binding.SPH_FP32_MIXED, use_graph=0)
+        j.step(args.steps)
+        j.sync()
+        c = j.counters()
+        print(f"[bench] step pass: {args.steps} steps, {c['interactions']} interactions",
+              file=sys.stderr, flush=True)
+        return
     print(f"[bench] workload square_hole n={wl.n} scale={wl.scale:.4f}", file=sys.stderr, flush=True)
-    r32 = run_timed(wl, binding.SPH_FP32_MIXED, args.steps, args.warmup)
+    cfg, tuned = {}, None
+    if not args.no_tune:
+        from paper_2003_01061_amd import autotune
+        t = autotune.tune([binding.JobSpec(wl)], 2, binding.SPH_FP32_MIXED, steps=20, warmup=4)
+        cfg = t.best
+        tuned = dict(best=t.best, speedup_over_default=t.speedup_over_default(), table=t.table)
+        print(f"[bench] tuned {json.dumps(t.best)} ({t.speedup_over_default():.3f}x over default)",
+              file=sys.stderr, flush=True)
+    r32 = run_timed(wl, binding.SPH_FP32_MIXED, args.steps, args.warmup, cfg=cfg)
     print(f"[bench] fp32-mixed {r32['seconds']:.3f}s", file=sys.stderr, flush=True)
     r64 = None
     if not args.no_fp64:
-        r64 = run_timed(wl, binding.SPH_FP64, args.steps, args.warmup)
+        r64 = run_timed(wl, binding.SPH_FP64, args.steps, args.warmup, cfg=cfg)
         print(f"[bench] fp64 {r64['seconds']:.3f}s", file=sys.stderr, flush=True)
     value = r32["interactions"] / r32["seconds"]
 
-    stats, pc = profile_kernels(wl, binding.SPH_FP32_MIXED, args.profile_steps)
+    stats, pc = profile_kernels(wl, binding.SPH_FP32_MIXED, args.profile_steps, cfg)
     per = {k: (ms / cnt if cnt else 0.0, cnt) for k, (ms, cnt) in stats.items()}
     dom = max((k for k in stats if kernel_bytes(k, wl, 1, 1, 4) is not None),
               key=lambda k: stats[k][0])
@@ -250,7 +296,8 @@ def main():
         "config": {"workload": "square_hole_2d", "n_particles": wl.n, "h0": 1.0 / 1024,
                    "h_scale": round(wl.scale, 6), "grad": 4.0, "hole_radius": 0.25,
                    "steps": args.steps, "precision": "fp32 sums + fp64 integration",
-                   "parallelism": "single GPU"},
+                   "parallelism": "single GPU", "tuned": cfg},
+        "autotune": tuned,
         "fp64": None if r64 is None else {
             "value": r64["interactions"] / r64["seconds"],
             "ms_per_step": r64["seconds"] / args.steps * 1e3,

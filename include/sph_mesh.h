@@ -275,6 +275,9 @@ sph_status sph_batch_error(sph_batch *b, int32_t job, double *e_sys, int32_t *ph
                            int32_t *converged, int64_t *step);
 sph_status sph_batch_counters(sph_batch *b, int32_t job, double *out);
 
+/* Wait until every step enqueued on the batch's stream has finished. */
+sph_status sph_batch_sync(sph_batch *b);
+
 /* Wait for the batch's stream, free everything; NULL-safe. */
 void sph_batch_destroy(sph_batch *b);
 

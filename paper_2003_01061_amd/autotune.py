@@ -1,0 +1,99 @@
+"""Autotuner of the batched relaxation step.
+
+The knobs are the ones that change speed but not the method:
+
+* ``cell_factor`` -- cell side 2 h_min * cell_factor (per job).  Smaller cells
+  follow the support disc (sphere) more tightly, so fewer candidates fail the
+  predicate, but every particle visits more cell rows.  Changing it changes
+  the canonical (cell, caller id) order of a neighbour list, hence the
+  rounding of the force sums, never the list itself.
+* ``scan_tile`` -- candidate records the neighbour scan loads and tests per
+  pass (2, 4 or 8; per batch).  Results are bit-identical for every value.
+
+The workgroup size is fixed at 256 (the kernels' occupancy is bounded by
+their registers, and the per-wave accumulator stripes assume it) and the
+list format is ELL, so neither is searched.
+
+``tune`` times every configuration of the grid on a trial batch holding the
+given jobs (the graph-replayed step, after warm-up steps) and returns the
+fastest; ties keep the earlier (default-first) entry.  The timing source is
+injectable so that the selection logic is testable without a GPU.
+"""
+from __future__ import annotations
+
+import ctypes
+import time
+from dataclasses import dataclass, field
+from typing import Callable, Optional, Sequence
+
+DEFAULT = {"cell_factor": 1.0, "scan_tile": 4}
+CELL_FACTORS = (1.0, 0.75, 1.25)
+SCAN_TILES = (4, 2, 8)
+
+
+@dataclass
+class TuneResult:
+    dim: int
+    precision: int
+    n_particles: int
+    best: dict
+    table: list = field(default_factory=list)   # one entry per configuration
+
+    def speedup_over_default(self):
+        base = next(r["ms_per_step"] for r in self.table
+                    if r["cell_factor"] == DEFAULT["cell_factor"]
+                    and r["scan_tile"] == DEFAULT["scan_tile"])
+        return base / min(r["ms_per_step"] for r in self.table)
+
+
+def with_cell_factor(spec, cf):
+    """A copy of a binding.JobSpec whose parameters use cell side factor cf
+    (the particle arrays are shared)."""
+    from . import binding
+    out = binding.JobSpec.__new__(binding.JobSpec)
+    out.__dict__.update(spec.__dict__)
+    out.params = binding.Params.from_buffer_copy(spec.params)
+    out.params.cell_factor = float(cf)
+    return out
+
+
+def _time_config(specs, dim, precision, cf, tile, steps, warmup, max_neighbors):
+    from . import binding
+    sp = [with_cell_factor(s, cf) for s in specs]
+    b = binding.SphBatch(dim, precision, max_particles=sum(s.n for s in sp),
+                         max_cells=sum(s.cells() for s in sp), max_jobs=len(sp),
+                         max_neighbors=max_neighbors, use_graph=1, scan_tile=tile)
+    try:
+        for s in sp:
+            b.add(s)
+        b.step(warmup)
+        b.sync()
+        t0 = time.perf_counter()
+        b.step(steps)
+        b.sync()
+        return (time.perf_counter() - t0) / steps * 1e3
+    finally:
+        b.close()
+
+
+def tune(specs: Sequence, dim: int, precision: int, cell_factors=CELL_FACTORS,
+         scan_tiles=SCAN_TILES, steps=20, warmup=4, max_neighbors=0,
+         measure: Optional[Callable] = None) -> TuneResult:
+    """Time every (cell_factor, scan_tile) pair on a batch of ``specs`` and
+    return the fastest.  ``measure(cf, tile) -> ms per step`` replaces the
+    GPU timing when given."""
+    if not specs:
+        raise ValueError("tune needs at least one job")
+    if measure is None:
+        def measure(cf, tile):
+            return _time_config(specs, dim, precision, cf, tile, steps, warmup, max_neighbors)
+    grid = [(cf, t) for cf in cell_factors for t in scan_tiles]
+    if (DEFAULT["cell_factor"], DEFAULT["scan_tile"]) not in grid:
+        grid.insert(0, (DEFAULT["cell_factor"], DEFAULT["scan_tile"]))
+    table = []
+    for cf, t in grid:
+        table.append({"cell_factor": cf, "scan_tile": t, "ms_per_step": float(measure(cf, t))})
+    best = min(table, key=lambda r: r["ms_per_step"])   # first minimum wins ties
+    return TuneResult(dim, precision, int(sum(s.n for s in specs)),
+                      {"cell_factor": best["cell_factor"], "scan_tile": best["scan_tile"]},
+                      table)

@@ -99,6 +99,7 @@ def lib():
                                     C.c_int64, vp, vp, C.POINTER(C.c_int32)]
         L.sph_batch_remove.argtypes = [vp, C.c_int32]
         L.sph_batch_step.argtypes = [vp, C.c_int32]
+        L.sph_batch_sync.argtypes = [vp]
         L.sph_batch_status.argtypes = [vp, vp, vp, vp, C.c_int32]
         L.sph_batch_positions.argtypes = [vp, C.c_int32, vp, vp, C.c_int64, C.POINTER(C.c_int64)]
         L.sph_batch_error.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int32),
@@ -349,6 +350,9 @@ class SphBatch:
     def step(self, n=1):
         _check("sph_batch_step", lib().sph_batch_step(self.h, int(n)))
 
+    def sync(self):
+        _check("sph_batch_sync", lib().sph_batch_sync(self.h))
+
     def status(self):
         m = self.max_jobs
         live = np.zeros(m, np.int32)
@@ -407,4 +411,5 @@ def exported_symbols():
             "sph_mesh_kernel_count", "sph_mesh_kernel_name", "sph_mesh_sync",
             "sph_mesh_device_bytes", "sph_batch_footprint", "sph_job_cells", "sph_batch_create",
             "sph_batch_add", "sph_batch_remove", "sph_batch_step", "sph_batch_status",
-            "sph_batch_positions", "sph_batch_error", "sph_batch_counters", "sph_batch_destroy"]
+            "sph_batch_positions", "sph_batch_error", "sph_batch_counters", "sph_batch_destroy",
+            "sph_batch_sync"]

@@ -920,6 +920,12 @@ extern "C" sph_status sph_batch_step(sph_batch *b, int32_t n_steps) {
   return b->step(n_steps);
 }
 
+extern "C" sph_status sph_batch_sync(sph_batch *b) {
+  if (!b) return fail(SPH_ERR_INVALID_ARG, "null batch");
+  HIPCHK(hipStreamSynchronize(b->stream));
+  return SPH_OK;
+}
+
 extern "C" sph_status sph_batch_status(sph_batch *b, int32_t *live, int32_t *converged,
                                        int64_t *steps, int32_t cap) {
   if (!b) return fail(SPH_ERR_INVALID_ARG, "null batch");

@@ -83,7 +83,7 @@ class Server:
                  batch_factory: Optional[Callable] = None,
                  footprint: Optional[Callable] = None,
                  clock=time.perf_counter, sleep=time.sleep, keep_positions=False,
-                 max_job_steps=1 << 20):
+                 max_job_steps=1 << 20, configs=None):
         if precision is None or batch_factory is None or footprint is None:
             from . import binding
             precision = binding.SPH_FP32_MIXED if precision is None else precision
@@ -97,6 +97,8 @@ class Server:
         self.clock, self.sleep = clock, sleep
         self.keep_positions = keep_positions
         self.max_job_steps = int(max_job_steps)   # a job not converged by then is retired as an error
+        # autotuned settings per dimension: {"cell_factor": .., "scan_tile": ..}
+        self.configs = {d: dict(c) for d, c in (configs or {}).items()}
         self.max_neighbors = dict(max_neighbors or {2: 64, 3: 192})
         share = dict(share or {2: 0.5, 3: 0.5})
         ratio = dict(cells_per_particle or {2: 4.0, 3: 2.0})
@@ -120,7 +122,8 @@ class Server:
             self.bytes[d] = fp(p)
             self.batches[d] = batch_factory(d, precision, max_particles=p,
                                             max_cells=self.cap_cells[d], max_jobs=self.slots,
-                                            max_neighbors=self.max_neighbors[d])
+                                            max_neighbors=self.max_neighbors[d],
+                                            scan_tile=self.configs.get(d, {}).get("scan_tile", 0))
         self.stats = ServeStats()
 
     def footprint_bytes(self):
@@ -137,6 +140,18 @@ class Server:
         finished = 0
         nxt = 0
         cells_of = {}
+        spec_of = {}
+
+        def spec(r):
+            # the request's job with its dimension's tuned cell size
+            if r.idx not in spec_of:
+                cf = self.configs.get(r.dim, {}).get("cell_factor")
+                if cf is None:
+                    spec_of[r.idx] = r.spec
+                else:
+                    from .autotune import with_cell_factor
+                    spec_of[r.idx] = with_cell_factor(r.spec, cf)
+            return spec_of[r.idx]
         t0 = self.clock()
         st = self.stats
         st.max_particles = {2: 0, 3: 0}
@@ -155,7 +170,7 @@ class Server:
                 while q:
                     r = q[0]
                     if r.idx not in cells_of:
-                        cells_of[r.idx] = int(r.spec.cells())
+                        cells_of[r.idx] = int(spec(r).cells())
                     cells = cells_of[r.idx]
                     if (cells < 0 or r.n > self.cap_particles[d] or cells > self.cap_cells[d]):
                         q.popleft()
@@ -173,7 +188,7 @@ class Server:
                         break
                     q.popleft()
                     try:
-                        job = self.batches[d].add(r.spec)
+                        job = self.batches[d].add(spec(r))
                     except Exception as e:       # refused by the library: report, go on
                         res = results[r.idx]
                         res.status, res.message, res.done = "error", str(e), now()

@@ -1,0 +1,28 @@
+"""Selection logic of the autotuner with an injected timing (no GPU)."""
+import pytest
+
+from paper_2003_01061_amd import autotune
+
+
+class Spec:
+    n = 1000
+
+
+def test_picks_the_fastest_configuration():
+    times = {(1.0, 4): 3.0, (0.75, 2): 2.0, (1.25, 8): 2.5}
+    r = autotune.tune([Spec()], 2, 1, measure=lambda cf, t: times.get((cf, t), 9.0))
+    assert r.best == {"cell_factor": 0.75, "scan_tile": 2}
+    assert len(r.table) == len(autotune.CELL_FACTORS) * len(autotune.SCAN_TILES)
+    assert r.speedup_over_default() == pytest.approx(1.5)
+
+
+def test_ties_keep_the_default_and_the_grid_always_holds_it():
+    r = autotune.tune([Spec()], 3, 1, cell_factors=(0.5, 0.75), scan_tiles=(2,),
+                      measure=lambda cf, t: 1.0)
+    assert r.table[0]["cell_factor"] == 1.0 and r.table[0]["scan_tile"] == 4
+    assert r.best == autotune.DEFAULT
+
+
+def test_needs_a_job():
+    with pytest.raises(ValueError):
+        autotune.tune([], 2, 1, measure=lambda cf, t: 1.0)

@@ -32,7 +32,8 @@ class FakeBatch:
     proportion to the resident particles (the clock is shared)."""
     instances = []
 
-    def __init__(self, dim, precision, max_particles, max_cells, max_jobs, max_neighbors):
+    def __init__(self, dim, precision, max_particles, max_cells, max_jobs, max_neighbors,
+                 scan_tile=0):
         self.dim, self.cap_p, self.cap_c, self.cap_j = dim, max_particles, max_cells, max_jobs
         self.jobs = {}
         self.log = []
@@ -76,7 +77,7 @@ class FakeBatch:
 CLOCK = FakeClock()
 
 
-def footprint(dim, precision, max_particles, max_cells, max_jobs, max_neighbors):
+def footprint(dim, precision, max_particles, max_cells, max_jobs, max_neighbors, scan_tile=0):
     return 1000 + 100 * max_particles + 8 * max_cells + 64 * max_jobs
 
 
