@@ -20,6 +20,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import re
 import sys
 import time
 
@@ -29,6 +30,32 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# VALU issue peak in wave64 instructions/s: 256 CUs x 4 SIMDs, a wave64 VALU
+# instruction occupies a 16-lane SIMD for 4 cycles, 2.4 GHz
+VALU_PEAK_WAVE_INSTS = 256 * 4 * 2.4e9 / 4
+COUNTERS_MD = os.path.join(ROOT, "profiles", "nbr_forces_square_hole_250k_counters.md")
+KERNEL_SOURCES = ("paper_2003_01061_amd/csrc/sph_device.h", "paper_2003_01061_amd/csrc/sph_kernels.h")
+
+
+def profiled_counters(cfg):
+    """Counter figures of the dominant kernel from the committed rocprofv3
+    summary, or None when the kernel sources changed since they were taken or
+    the benchmark runs another configuration."""
+    import hashlib
+    try:
+        text = open(COUNTERS_MD).read()
+    except OSError:
+        return None
+    kv = dict(re.findall(r"^(\w+): (.+)$", text, flags=re.M))
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    want = "cell_factor={} scan_tile={}".format(float(cfg.get("cell_factor", 1.0)),
+                                                int(cfg.get("scan_tile", 4)))
+    if kv.get("kernel_source_sha256") != h.hexdigest() or kv.get("config") != want:
+        return None
+    return dict(traffic=float(kv["traffic_bytes_per_launch"]),
+                valu=float(kv["valu_insts_per_launch"]), waves=float(kv["waves_per_launch"]))
 
 
 def kernel_bytes(name, wl, n_active, inter, real_bytes):
@@ -267,6 +294,7 @@ def main():
     byts = kernel_bytes(dom, wl, n_active, inter_step, 4)
     avg_s = per[dom][0] * 1e-3
     achieved = byts / avg_s / 1e9
+    ctr = profiled_counters(cfg) if dom == "nbr_forces" else None
     print(f"[bench] profile: " + ", ".join(f"{k}={v[0]*1e3:.1f}us" for k, v in per.items()),
           file=sys.stderr, flush=True)
 
@@ -311,7 +339,10 @@ def main():
         "latency_p50_p99_s": lat,
         "serving": srv,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None if ctr is None else ctr["traffic"],
+                     "traffic_frac": None if ctr is None else ctr["traffic"] / avg_s / 1e9 / HBM_PEAK_GBS,
+                     "valu_issue_frac": None if ctr is None else ctr["valu"] / avg_s / VALU_PEAK_WAVE_INSTS,
                      "avg_launch_us": per[dom][0] * 1e3, "bytes_per_launch": byts,
                      "launches": per[dom][1]},
         "kernel_avg_us": {k: round(v[0] * 1e3, 2) for k, v in per.items()},

@@ -78,10 +78,11 @@ def _time_config(specs, dim, precision, cf, tile, steps, warmup, max_neighbors):
 
 def tune(specs: Sequence, dim: int, precision: int, cell_factors=CELL_FACTORS,
          scan_tiles=SCAN_TILES, steps=20, warmup=4, max_neighbors=0,
-         measure: Optional[Callable] = None) -> TuneResult:
+         measure: Optional[Callable] = None, min_gain=0.02) -> TuneResult:
     """Time every (cell_factor, scan_tile) pair on a batch of ``specs`` and
-    return the fastest.  ``measure(cf, tile) -> ms per step`` replaces the
-    GPU timing when given."""
+    return the fastest; the default stays unless another configuration is
+    faster by more than ``min_gain`` (timing noise must not flip the choice).
+    ``measure(cf, tile) -> ms per step`` replaces the GPU timing when given."""
     if not specs:
         raise ValueError("tune needs at least one job")
     if measure is None:
@@ -94,6 +95,9 @@ def tune(specs: Sequence, dim: int, precision: int, cell_factors=CELL_FACTORS,
     for cf, t in grid:
         table.append({"cell_factor": cf, "scan_tile": t, "ms_per_step": float(measure(cf, t))})
     best = min(table, key=lambda r: r["ms_per_step"])   # first minimum wins ties
+    default = table[grid.index((DEFAULT["cell_factor"], DEFAULT["scan_tile"]))]
+    if best["ms_per_step"] * (1.0 + min_gain) > default["ms_per_step"]:
+        best = default
     return TuneResult(dim, precision, int(sum(s.n for s in specs)),
                       {"cell_factor": best["cell_factor"], "scan_tile": best["scan_tile"]},
                       table)

@@ -12,6 +12,7 @@
 // device, and the host reads state back only when asked.  The single-job
 // handle sph_mesh is a batch holding one job.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <algorithm>
 #include <cstdarg>
@@ -363,18 +364,16 @@ struct sph_batch {
   template <typename K, typename... A>
   hipError_t launch(int kid, K kern, unsigned grid, unsigned block, A... args) {
     if (grid == 0) return hipSuccess;
-    hipEvent_t a = nullptr, b = nullptr;
-    if (profiling) {
-      a = get_event();
-      (void)hipEventRecord(a, stream);
+    if (!profiling) {
+      hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, stream, args...);
+      return hipGetLastError();
     }
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, stream, args...);
+    // profiling: the start and stop events are recorded by the dispatch
+    // itself, so their interval is the kernel's execution alone
+    hipEvent_t a = get_event(), b = get_event();
+    hipExtLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, stream, a, b, 0, args...);
     hipError_t e = hipGetLastError();
-    if (profiling) {
-      b = get_event();
-      (void)hipEventRecord(b, stream);
-      ev_live.push_back({kid, a, b});
-    }
+    ev_live.push_back({kid, a, b});
     return e;
   }
 

@@ -26,3 +26,11 @@ def test_ties_keep_the_default_and_the_grid_always_holds_it():
 def test_needs_a_job():
     with pytest.raises(ValueError):
         autotune.tune([], 2, 1, measure=lambda cf, t: 1.0)
+
+
+def test_a_gain_within_the_noise_keeps_the_default():
+    times = {(1.0, 4): 1.00, (0.75, 2): 0.99}
+    r = autotune.tune([Spec()], 2, 1, measure=lambda cf, t: times.get((cf, t), 9.0))
+    assert r.best == autotune.DEFAULT
+    r = autotune.tune([Spec()], 2, 1, measure=lambda cf, t: times.get((cf, t), 9.0), min_gain=0.0)
+    assert r.best == {"cell_factor": 0.75, "scan_tile": 2}
