@@ -229,9 +229,10 @@ def main():
     ap.add_argument("--n", type=int, default=250_000)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
-    ap.add_argument("--pmc-pass", choices=["step", "copy"], default=None,
+    ap.add_argument("--pmc-pass", choices=["step", "step3d", "copy"], default=None,
                     help="counter-collection pass for rocprofv3 --pmc: 'step' runs --steps "
                          "eagerly launched FP32-mixed steps of the workload (default tuning), "
+                         "'step3d' the same on the 2M-particle cube minus a ball, "
                          "'copy' one 256 MiB device copy (counter calibration); prints no JSON")
     ap.add_argument("--serve-jobs", type=int, default=256)
     ap.add_argument("--serve-rates", type=float, nargs="*", default=[0.9])
@@ -258,6 +259,13 @@ def main():
         torch.cuda.synchronize()
         print(f"[bench] copy pass: {a.numel() * 8} bytes read, {b.numel() * 8} written",
               file=sys.stderr, flush=True)
+        return
+    if args.pmc_pass == "step3d":
+        wl3 = wk.cube_ball()
+        j = binding.SphMesh(wl3, precision=binding.SPH_FP32_MIXED, use_graph=0)
+        j.step(args.steps)
+        j.sync()
+        print(f"[bench] step3d pass: {args.steps} steps", file=sys.stderr, flush=True)
         return
     wl = wk.square_hole(n_total=args.n)
     if args.pmc_pass == "step":

@@ -102,8 +102,8 @@ typedef struct {
   int32_t precision;         /* SPH_FP64, or SPH_FP32_MIXED: FP32 kernel sums with
                                 compensated accumulation, FP64 positions,
                                 integration and projection */
-  int32_t max_neighbors;     /* neighbour-list capacity per particle; 0 = 64 in
-                                2D, 160 in 3D */
+  int32_t max_neighbors;     /* neighbour-list capacity per particle, rounded up
+                                to a multiple of 8; 0 = 64 in 2D, 160 in 3D */
   double cell_factor;        /* cell side = 2 h_min cell_factor; 0 = 1.0 */
   int32_t scan_tile;         /* candidate records tested per pass of the
                                 neighbour scan: 2, 4 or 8; 0 = 4.  Results do

@@ -4,18 +4,20 @@
 // Layout in HBM: particles sit in cell order as packed 32-byte records, one
 // array of {x, y, z, h} (FP64, z = 0 in 2D) and one of {vx, vy, vz, 0}
 // (FP64), so a neighbour gather touches one 32-byte sector per record; the
-// feature index is one byte and the caller's id a u32 column.  Accelerations
+// feature index is a u16 and the caller's id a u32 column.  Accelerations
 // are {ax, ay, az, 0} records in the sweep precision.  The neighbour list is
-// ELL, entry e of slot i at nbr[e * n + i], so the 64 lanes of a wave reading
-// entry e touch 256 consecutive bytes.  The top bit of an entry marks a
-// boundary neighbour (a lower-dimensional feature bounding the particle's
-// own, paper sec. 3.3), the low 31 bits are the slot.
+// blocked ELL: entries 8b .. 8b+7 of slot i form one 32-byte block at words
+// [(b * n + i) * 8, +8), so a lane appends whole 32-byte sectors and the 64
+// lanes of a wave reading block b touch 2 KB of consecutive memory.  The top
+// bit of an entry marks a boundary neighbour (a lower-dimensional feature
+// bounding the particle's own, paper sec. 3.3), the low 31 bits are the slot.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace sph {
 
+constexpr int LB = 8;           // neighbour-list entries per block (32 bytes)
 constexpr int MAXF = 64;        // features per job; a job's features own ids [64 s, 64 s + nf)
 constexpr int MAXJ = 64;        // jobs per batch
 constexpr int MAXH = 16;        // holes per job

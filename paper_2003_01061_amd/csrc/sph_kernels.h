@@ -338,57 +338,65 @@ __device__ __forceinline__ void sweep_a_sums(const Geom &g, const Parts &s,
 #pragma unroll
   for (int a = 0; a < 3; ++a) Pi[a] = B[a] = 0.0;
   constexpr int NB = SPH_NBATCH;
-  for (uint32_t e0 = 0; e0 < cnt; e0 += NB) {
-    uint32_t u[NB];
+  static_assert(LB % NB == 0, "record batches tile a list block");
+  const uint4 *blk = reinterpret_cast<const uint4 *>(nbr) + (size_t)i * (LB / 4);
+  for (uint32_t b0 = 0; b0 < cnt; b0 += LB, blk += (size_t)n * (LB / 4)) {
+    const uint4 w0 = blk[0], w1 = blk[1];
+    const uint32_t ub[LB] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
 #pragma unroll
-    for (int q = 0; q < NB; ++q) u[q] = e0 + q < cnt ? nbr[(size_t)(e0 + q) * n + i] : 0u;
-    double4 xr[NB];
+    for (int hb = 0; hb < LB; hb += NB) {
+      const uint32_t e0 = b0 + hb;
+      uint32_t u[NB];
 #pragma unroll
-    for (int q = 0; q < NB; ++q) xr[q] = s.xh[u[q] & 0x7fffffffu];
+      for (int q = 0; q < NB; ++q) u[q] = e0 + q < cnt ? ub[hb + q] : 0u;
+      double4 xr[NB];
 #pragma unroll
-    for (int q = 0; q < NB; ++q) {
-      if (e0 + q >= cnt) break;
-      const double4 xj = xr[q];
-      const R dx0 = (R)(xi.x - xj.x), dx1 = (R)(xi.y - xj.y);
-      const R dx2 = D == 3 ? (R)(xi.z - xj.z) : R(0);
-      const R rr = sqrt_(dx0 * dx0 + dx1 * dx1 + dx2 * dx2);
-      const R hj = (R)xj.w;
-      const R hjk = powK<K>(hj);
-      const R hsum = hi2k + hjk * hjk;
-      const R ihij = rcp_(R(0.5) * (hi + hj));
-      const R qij = rr * ihij;
-      if (!(u[q] >> 31)) {
-        const R w = alpha * wshapeK<K>(rr * ihi) * ihik;           // W(r, h_i)
-        S += (double)w;
-        gam += (double)(w * hjk);
-        const R ih2 = ihij * ihij;
-        const R ihk2 = K == 1 ? ih2 * ihij : (K == 2 ? ih2 * ih2 : ih2 * ih2 * ihij);
-        const R c = P0 * hsum * alpha * dwqK<K>(qij) * ihk2;       // (dW/dr)/r at h_ij
-        Pi[0] += (double)(c * dx0);
-        Pi[1] += (double)(c * dx1);
-        if (D == 3) Pi[2] += (double)(c * dx2);
-      } else {
-        const int fj = s.f[u[q] & 0x7fffffffu];
-        const BNorm N = bnrow[fj & (MAXF - 1)];
-        double nv[3];
-        if (N.mode == 2) {
-          const double *cc = g.hc[N.hole];
-          const double d0 = cc[0] - xj.x, d1 = cc[1] - xj.y, d2 = D == 3 ? cc[2] - xj.z : 0.0;
-          const double il = 1.0 / __builtin_sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-          nv[0] = d0 * il;
-          nv[1] = d1 * il;
-          nv[2] = d2 * il;
+      for (int q = 0; q < NB; ++q) xr[q] = s.xh[u[q] & 0x7fffffffu];
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        if (e0 + q >= cnt) break;
+        const double4 xj = xr[q];
+        const R dx0 = (R)(xi.x - xj.x), dx1 = (R)(xi.y - xj.y);
+        const R dx2 = D == 3 ? (R)(xi.z - xj.z) : R(0);
+        const R rr = sqrt_(dx0 * dx0 + dx1 * dx1 + dx2 * dx2);
+        const R hj = (R)xj.w;
+        const R hjk = powK<K>(hj);
+        const R hsum = hi2k + hjk * hjk;
+        const R ihij = rcp_(R(0.5) * (hi + hj));
+        const R qij = rr * ihij;
+        if (!(u[q] >> 31)) {
+          const R w = alpha * wshapeK<K>(rr * ihi) * ihik;           // W(r, h_i)
+          S += (double)w;
+          gam += (double)(w * hjk);
+          const R ih2 = ihij * ihij;
+          const R ihk2 = K == 1 ? ih2 * ihij : (K == 2 ? ih2 * ih2 : ih2 * ih2 * ihij);
+          const R c = P0 * hsum * alpha * dwqK<K>(qij) * ihk2;       // (dW/dr)/r at h_ij
+          Pi[0] += (double)(c * dx0);
+          Pi[1] += (double)(c * dx1);
+          if (D == 3) Pi[2] += (double)(c * dx2);
         } else {
-          nv[0] = N.n[0];
-          nv[1] = N.n[1];
-          nv[2] = N.n[2];
+          const int fj = s.f[u[q] & 0x7fffffffu];
+          const BNorm N = bnrow[fj & (MAXF - 1)];
+          double nv[3];
+          if (N.mode == 2) {
+            const double *cc = g.hc[N.hole];
+            const double d0 = cc[0] - xj.x, d1 = cc[1] - xj.y, d2 = D == 3 ? cc[2] - xj.z : 0.0;
+            const double il = 1.0 / __builtin_sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+            nv[0] = d0 * il;
+            nv[1] = d1 * il;
+            nv[2] = d2 * il;
+          } else {
+            nv[0] = N.n[0];
+            nv[1] = N.n[1];
+            nv[2] = N.n[2];
+          }
+          const R om = bw == 0 ? rcp_(hj) : (bw == 1 ? powK<K>(hj) * rcp_(hj) : R(0));
+          const R w = alpha * wshapeK<K>(qij) * powK<K>(ihij);          // W(r, h_ib)
+          const double c = (double)(P0 * hsum * w * om);
+          B[0] += c * nv[0];
+          B[1] += c * nv[1];
+          if (D == 3) B[2] += c * nv[2];
         }
-        const R om = bw == 0 ? rcp_(hj) : (bw == 1 ? powK<K>(hj) * rcp_(hj) : R(0));
-        const R w = alpha * wshapeK<K>(qij) * powK<K>(ihij);          // W(r, h_ib)
-        const double c = (double)(P0 * hsum * w * om);
-        B[0] += c * nv[0];
-        B[1] += c * nv[1];
-        if (D == 3) B[2] += c * nv[2];
       }
     }
   }
@@ -451,7 +459,14 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
       const unsigned long long accept = B.bmask[fi] | (1ull << (fi & (MAXF - 1)));
       const double A4 = 4.0 * (xi.w * xi.w);
       static_assert(NB >= 1 && NB <= 8, "records are padded by 8");
-      uint32_t *wp = nbr + i;            // next list slot of i (ELL: stride n)
+      // hits collect in a register block of LB entries, stored as one
+      // 32-byte sector when full (and once more, partly filled, at the end)
+      uint4 *wp = reinterpret_cast<uint4 *>(nbr) + (size_t)i * (LB / 4);
+      const uint32_t wstep = (uint32_t)n * (LB / 4);
+      const uint32_t nblk = (uint32_t)B.cap / LB;   // blocks of capacity
+      uint32_t lbuf[LB];
+#pragma unroll
+      for (int q = 0; q < LB; ++q) lbuf[q] = 0u;
       for (int cz = lo_c[2]; cz <= hi_c[2]; ++cz) {
         double dz2 = 0.0;
         if (D == 3) {
@@ -503,15 +518,23 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
 #pragma unroll
             for (int q = 0; q < NB; ++q) {
               if (tag[q] != 0xffffffffu) {
-                if ((int)count < B.cap) {
-                  *wp = tag[q];
-                  wp += n;
-                }
+                const uint32_t k = count % LB;
+#pragma unroll
+                for (int t = 0; t < LB; ++t) lbuf[t] = (uint32_t)t == k ? tag[q] : lbuf[t];
                 ++count;
+                if (k == LB - 1 && count / LB <= nblk) {
+                  wp[0] = make_uint4(lbuf[0], lbuf[1], lbuf[2], lbuf[3]);
+                  wp[1] = make_uint4(lbuf[4], lbuf[5], lbuf[6], lbuf[7]);
+                  wp += wstep;
+                }
               }
             }
           }
         }
+      }
+      if (count % LB != 0 && count / LB < nblk) {   // the last, partly filled block
+        wp[0] = make_uint4(lbuf[0], lbuf[1], lbuf[2], lbuf[3]);
+        wp[1] = make_uint4(lbuf[4], lbuf[5], lbuf[6], lbuf[7]);
       }
       if ((int)count > B.cap) {
         atomicMax(&B.st[job].overflow_max, count);
@@ -596,44 +619,52 @@ __device__ __forceinline__ void sweep_b_sums(const Parts &s, const typename Vec4
 #pragma unroll
   for (int a = 0; a < 3; ++a) Fv[a] = 0.0;
   constexpr int NB = SPH_NBATCH;
-  for (uint32_t e0 = 0; e0 < cnt; e0 += NB) {
-    uint32_t u[NB];
+  static_assert(LB % NB == 0, "record batches tile a list block");
+  const uint4 *blk = reinterpret_cast<const uint4 *>(nbr) + (size_t)i * (LB / 4);
+  for (uint32_t b0 = 0; b0 < cnt; b0 += LB, blk += (size_t)n * (LB / 4)) {
+    const uint4 w0 = blk[0], w1 = blk[1];
+    const uint32_t ub[LB] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
 #pragma unroll
-    for (int q = 0; q < NB; ++q) u[q] = e0 + q < cnt ? nbr[(size_t)(e0 + q) * n + i] : 0x80000000u;
-    double4 xr[NB], vr[NB];
-    R4 ar[NB];
+    for (int hb = 0; hb < LB; hb += NB) {
+      const uint32_t e0 = b0 + hb;
+      uint32_t u[NB];
 #pragma unroll
-    for (int q = 0; q < NB; ++q) {
-      const uint32_t j = u[q] & 0x7fffffffu;   // boundary entries fetch a valid slot, unused
-      xr[q] = s.xh[j];
-      vr[q] = s.v[j];
-      ar[q] = ap[j];
-    }
+      for (int q = 0; q < NB; ++q) u[q] = e0 + q < cnt ? ub[hb + q] : 0x80000000u;
+      double4 xr[NB], vr[NB];
+      R4 ar[NB];
 #pragma unroll
-    for (int q = 0; q < NB; ++q) {
-      if (u[q] >> 31) continue;
-      const double4 xj = xr[q];
-      const double4 vj = vr[q];
-      const R4 apj = ar[q];
-      const R dx0 = (R)(xi.x - xj.x), dx1 = (R)(xi.y - xj.y);
-      const R dx2 = D == 3 ? (R)(xi.z - xj.z) : R(0);
-      const R rr = sqrt_(dx0 * dx0 + dx1 * dx1 + dx2 * dx2);
-      const R hj = (R)xj.w;
-      const R hjk = powK<K>(hj);
-      R vtj[3];
-      vtj[0] = (R)vj.x + halfR * apj.x;
-      vtj[1] = (R)vj.y + halfR * apj.y;
-      vtj[2] = D == 3 ? (R)vj.z + halfR * apj.z : R(0);
-      const R vmj = sqrt_(vtj[0] * vtj[0] + vtj[1] * vtj[1] + vtj[2] * vtj[2]);
-      const R etaj = R(0.2) * hj * vmj * rcp_(hjk);
-      const R es = etai + etaj;
-      const R H = es > R(0) ? R(2) * etai * etaj * rcp_(es) : R(0);
-      const R ihij = rcp_(R(0.5) * (hi + hj));
-      const R ih2 = ihij * ihij;
-      const R ihk2 = K == 1 ? ih2 * ihij : (K == 2 ? ih2 * ih2 : ih2 * ih2 * ihij);
-      const R c = H * (hi2k + hjk * hjk) * alpha * dwqK<K>(rr * ihij) * ihk2;
+      for (int q = 0; q < NB; ++q) {
+        const uint32_t j = u[q] & 0x7fffffffu;   // boundary entries fetch a valid slot, unused
+        xr[q] = s.xh[j];
+        vr[q] = s.v[j];
+        ar[q] = ap[j];
+      }
 #pragma unroll
-      for (int a = 0; a < D; ++a) Fv[a] += (double)(c * (vtiR[a] - vtj[a]));
+      for (int q = 0; q < NB; ++q) {
+        if (u[q] >> 31) continue;
+        const double4 xj = xr[q];
+        const double4 vj = vr[q];
+        const R4 apj = ar[q];
+        const R dx0 = (R)(xi.x - xj.x), dx1 = (R)(xi.y - xj.y);
+        const R dx2 = D == 3 ? (R)(xi.z - xj.z) : R(0);
+        const R rr = sqrt_(dx0 * dx0 + dx1 * dx1 + dx2 * dx2);
+        const R hj = (R)xj.w;
+        const R hjk = powK<K>(hj);
+        R vtj[3];
+        vtj[0] = (R)vj.x + halfR * apj.x;
+        vtj[1] = (R)vj.y + halfR * apj.y;
+        vtj[2] = D == 3 ? (R)vj.z + halfR * apj.z : R(0);
+        const R vmj = sqrt_(vtj[0] * vtj[0] + vtj[1] * vtj[1] + vtj[2] * vtj[2]);
+        const R etaj = R(0.2) * hj * vmj * rcp_(hjk);
+        const R es = etai + etaj;
+        const R H = es > R(0) ? R(2) * etai * etaj * rcp_(es) : R(0);
+        const R ihij = rcp_(R(0.5) * (hi + hj));
+        const R ih2 = ihij * ihij;
+        const R ihk2 = K == 1 ? ih2 * ihij : (K == 2 ? ih2 * ih2 : ih2 * ih2 * ihij);
+        const R c = H * (hi2k + hjk * hjk) * alpha * dwqK<K>(rr * ihij) * ihk2;
+#pragma unroll
+        for (int a = 0; a < D; ++a) Fv[a] += (double)(c * (vtiR[a] - vtj[a]));
+      }
     }
   }
 }

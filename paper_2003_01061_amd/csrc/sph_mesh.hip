@@ -616,7 +616,7 @@ extern "C" int64_t sph_batch_footprint(const sph_batch_params *bp) {
       bp->max_jobs < 1 || bp->max_jobs > MAXJ || bp->max_neighbors < 0)
     return -1;
   const int64_t N = bp->max_particles + 8, C = bp->max_cells;
-  const int64_t cap = bp->max_neighbors ? bp->max_neighbors : default_cap(bp->dim);
+  const int64_t cap = (bp->max_neighbors ? bp->max_neighbors + LB - 1 : default_cap(bp->dim)) / LB * LB;
   const int64_t r4 = bp->precision == SPH_FP64 ? 32 : 16;
   int64_t b = 2 * N * (32 + 32 + 2 + 4);             // particle records, double buffered
   b += 4 * N * 4;                                     // cell, rank, psrc, pkey
@@ -652,7 +652,8 @@ extern "C" sph_status sph_batch_create(const sph_batch_params *bp, sph_batch **o
   auto *B = new sph_batch();
   B->D = bp->dim;
   B->prec = bp->precision;
-  B->cap = bp->max_neighbors ? bp->max_neighbors : (int)default_cap(bp->dim);
+  // capacity in whole list blocks
+  B->cap = (bp->max_neighbors ? (bp->max_neighbors + LB - 1) / LB * LB : (int)default_cap(bp->dim));
   B->tile = bp->scan_tile ? bp->scan_tile : 4;
   B->use_graph = bp->use_graph != 0;
   B->debug = bp->debug_fields != 0;
@@ -1166,7 +1167,7 @@ extern "C" sph_status sph_mesh_neighbors(sph_mesh *m, int64_t *offsets, int32_t 
   for (int i = 0; i < n; ++i) {
     tmp.clear();
     for (uint32_t e = 0; e < nnb[i]; ++e) {
-      uint32_t u = nbr[(size_t)e * n + i];
+      uint32_t u = nbr[((size_t)(e / LB) * n + i) * LB + e % LB];
       tmp.push_back({oid[u & 0x7fffffffu], (int8_t)((u >> 31) ? 2 : 1)});
     }
     std::sort(tmp.begin(), tmp.end());
