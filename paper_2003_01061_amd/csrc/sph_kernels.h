@@ -151,10 +151,12 @@ __global__ __launch_bounds__(BLOCK) void k_hash(Batch B, Parts s, int i0, int i1
   const bool valid = i < i1;
   uint32_t c = 0;
   if (valid) {
-    const JobDev &J = B.jobs[s.f[i] / MAXF];
+    const uint32_t f = s.f[i];
+    const JobDev &J = B.jobs[f / MAXF];
     double4 xh = s.xh[i];
     hash_one<D>(J.g, J.G, xh, c);
     s.xh[i] = xh;
+    s.xf[i] = scan_record<D>(xh, f);
     cell[i] = c;
   }
   const uint32_t r = rank_in_cell(c, valid, cnt);
@@ -289,6 +291,7 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(int n, const uint32_t *__rest
 // Entry u of a cell (filled in atomic order) finds its rank among the cell's
 // caller ids and copies its particle to that slot; the first entry of a cell
 // clears the cell's count for the next hash.
+template <int D>
 __global__ __launch_bounds__(BLOCK) void k_rank_gather(int n, const uint32_t *__restrict__ psrc,
                                                        const uint32_t *__restrict__ pkey,
                                                        const uint32_t *__restrict__ cell,
@@ -307,10 +310,13 @@ __global__ __launch_bounds__(BLOCK) void k_rank_gather(int n, const uint32_t *__
   if ((uint32_t)u == lo) cnt[c] = 0u;
   const uint32_t dst = lo + r;
   if (dst >= (uint32_t)n) return;
-  b.xh[dst] = a.xh[src];
+  const double4 xh = a.xh[src];
+  const uint32_t f = a.f[src];
+  b.xh[dst] = xh;
   b.v[dst] = a.v[src];
-  b.f[dst] = a.f[src];
+  b.f[dst] = (uint16_t)f;
   b.oid[dst] = key;
+  b.xf[dst] = scan_record<D>(xh, f);
 }
 
 // ---------------------------------------------------------------------------
@@ -458,6 +464,31 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
       // low 6 bits.
       const unsigned long long accept = B.bmask[fi] | (1ull << (fi & (MAXF - 1)));
       const double A4 = 4.0 * (xi.w * xi.w);
+      // Candidates are classified in FP32 from the scan records; only those
+      // whose distance is within a thin band around the support radius are
+      // decided by the exact FP64 predicate.  Bound: a coordinate of a
+      // candidate the scan visits is at most Xb in magnitude (the job's box,
+      // or |x_i| + 2 R_i + 2 cells), so each rounded coordinate is off by at
+      // most 2^-24 Xb and an FP32 distance by at most M = sqrt(D) 2^-23 Xb
+      // plus a relative 1e-6; the band of relative half-width 2e-6 around
+      // 2 max(h_i, h_j), widened by M, covers every such error, so the
+      // classification always equals the FP64 predicate.
+      const float4 xif = scan_record<D>(xi, (uint32_t)fi);
+      const float hif = D == 2 ? xif.z : xif.w;
+      float Mf;
+      {
+        double xb = 0.0, cm = c0 > c1 ? c0 : c1;
+        if (D == 3) cm = cm > c2 ? cm : c2;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          const double l = __builtin_fabs(J.g.lo[a]), h = __builtin_fabs(J.g.hi[a]);
+          double m = l > h ? l : h;
+          const double own = __builtin_fabs(pc[a]) + 2.0 * Rs + 2.0 * cm;
+          m = m > own ? m : own;
+          xb = xb > m ? xb : m;
+        }
+        Mf = (float)((D == 3 ? 1.7320508075688772 : 1.4142135623730951) * 0x1p-23 * xb * 1.01);
+      }
       static_assert(NB >= 1 && NB <= 8, "records are padded by 8");
       // hits collect in a register block of LB entries, stored as one
       // 32-byte sector when full (and once more, partly filled, at the end)
@@ -498,21 +529,32 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
           // padded by 8 past the capacity), the predicate evaluated for all of
           // them without early exits, then the hits appended in order
           for (uint32_t j0 = jb; j0 < je; j0 += NB) {
-            const double4 *rp = s.xh + j0;
+            const float4 *rp = s.xf + j0;
             const uint16_t *fp = s.f + j0;
-            double4 xr[NB];
+            float4 xr[NB];
             uint32_t fr[NB];
 #pragma unroll
             for (int q = 0; q < NB; ++q) {
               xr[q] = rp[q];
-              fr[q] = fp[q];
+              fr[q] = D == 2 ? __float_as_uint(xr[q].w) : (uint32_t)fp[q];
             }
             uint32_t tag[NB];
 #pragma unroll
             for (int q = 0; q < NB; ++q) {
               const uint32_t j = j0 + q;
               const bool rel = (accept >> (fr[q] & (MAXF - 1))) & 1ull;
-              const bool hit = rel & (j < je) & (j != (uint32_t)i) & within_a4<D>(xi, A4, xr[q]);
+              const bool cand = rel & (j < je) & (j != (uint32_t)i);
+              const float dx = xif.x - xr[q].x, dy = xif.y - xr[q].y;
+              const float dz = D == 3 ? xif.z - xr[q].z : 0.0f;
+              const float d2 = dx * dx + dy * dy + dz * dz;
+              const float hj = D == 2 ? xr[q].z : xr[q].w;
+              const float H = 2.0f * (hif > hj ? hif : hj);
+              float tin = H * (1.0f - 2e-6f) - Mf;
+              tin = tin > 0.0f ? tin * tin : -1.0f;
+              const float tout = (H * (1.0f + 2e-6f) + Mf) * (H * (1.0f + 2e-6f) + Mf);
+              bool hit = cand & (d2 < tin);
+              if (cand & !(d2 < tin) & !(d2 > tout))   // near the support radius: exact test
+                hit = within_a4<D>(xi, A4, s.xh[j]);
               tag[q] = hit ? (j | (fr[q] == (uint32_t)fi ? 0u : 0x80000000u)) : 0xffffffffu;
             }
 #pragma unroll
@@ -838,6 +880,7 @@ __global__ __launch_bounds__(BLOCK) void k_integrate_hash(
     }
     hash_one<D>(J.g, J.G, xh, cc);
     s.xh[i] = xh;
+    s.xf[i] = scan_record<D>(xh, (uint32_t)fi);
     cell[i] = cc;
   }
   const uint32_t r = rank_in_cell(cc, i < n, cnt);

@@ -395,9 +395,14 @@ struct sph_batch {
     HIPCHK(launch(KID_SCATTER, k_scatter, blocks(n), BLOCK, n, (const uint32_t *)cell,
                   (const uint32_t *)rank, (const uint32_t *)cstart, (const uint32_t *)P[cur].oid,
                   psrc, pkey, scan_status, B.ntiles, ticket));
-    HIPCHK(launch(KID_RANK_GATHER, k_rank_gather, blocks(n), BLOCK, n, (const uint32_t *)psrc,
-                  (const uint32_t *)pkey, (const uint32_t *)cell, (const uint32_t *)cstart, cnt,
-                  P[cur], P[1 - cur]));
+    if (D == 2)
+      HIPCHK(launch(KID_RANK_GATHER, k_rank_gather<2>, blocks(n), BLOCK, n, (const uint32_t *)psrc,
+                    (const uint32_t *)pkey, (const uint32_t *)cell, (const uint32_t *)cstart, cnt,
+                    P[cur], P[1 - cur]));
+    else
+      HIPCHK(launch(KID_RANK_GATHER, k_rank_gather<3>, blocks(n), BLOCK, n, (const uint32_t *)psrc,
+                    (const uint32_t *)pkey, (const uint32_t *)cell, (const uint32_t *)cstart, cnt,
+                    P[cur], P[1 - cur]));
     cur = 1 - cur;
     return SPH_OK;
   }
@@ -604,9 +609,13 @@ static sph_status check_particles(const sph_geometry *g, int64_t n, const double
     if (feature[i] < 0 || feature[i] >= nf)
       return fail(SPH_ERR_INVALID_ARG, "particle %lld: feature %d out of range [0, %d)",
                   (long long)i, feature[i], nf);
-    for (int a = 0; a < g->dim; ++a)
-      if (!std::isfinite(xyz[3 * i + a]))
+    for (int a = 0; a < g->dim; ++a) {
+      const double x = xyz[3 * i + a], slack = 1e-9 * (g->hi[a] - g->lo[a]);
+      if (!std::isfinite(x))
         return fail(SPH_ERR_INVALID_ARG, "particle %lld: non-finite coordinate", (long long)i);
+      if (x < g->lo[a] - slack || x > g->hi[a] + slack)
+        return fail(SPH_ERR_INVALID_ARG, "particle %lld lies outside the box", (long long)i);
+    }
   }
   return SPH_OK;
 }
@@ -618,7 +627,7 @@ extern "C" int64_t sph_batch_footprint(const sph_batch_params *bp) {
   const int64_t N = bp->max_particles + 8, C = bp->max_cells;
   const int64_t cap = (bp->max_neighbors ? bp->max_neighbors + LB - 1 : default_cap(bp->dim)) / LB * LB;
   const int64_t r4 = bp->precision == SPH_FP64 ? 32 : 16;
-  int64_t b = 2 * N * (32 + 32 + 2 + 4);             // particle records, double buffered
+  int64_t b = 2 * N * (32 + 32 + 2 + 4 + 16);        // particle records, double buffered
   b += 4 * N * 4;                                     // cell, rank, psrc, pkey
   b += C * 4 + (C + 1) * 4 + ((C + SCAN_TILE - 1) / SCAN_TILE) * 8;
   b += N * cap * 4 + N * 4;                           // neighbour list + counts
@@ -681,7 +690,8 @@ extern "C" sph_status sph_batch_create(const sph_batch_params *bp, sph_batch **o
     B->P[b].v = dalloc<double4>(NPAD, ow, by);
     B->P[b].f = dalloc<uint16_t>(NPAD, ow, by);
     B->P[b].oid = dalloc<uint32_t>(NPAD, ow, by);
-    ok = ok && B->P[b].xh && B->P[b].v && B->P[b].f && B->P[b].oid;
+    B->P[b].xf = dalloc<float4>(NPAD, ow, by);
+    ok = ok && B->P[b].xh && B->P[b].v && B->P[b].f && B->P[b].oid && B->P[b].xf;
   }
   B->cell = dalloc<uint32_t>(N, ow, by);
   B->rank = dalloc<uint32_t>(N, ow, by);
@@ -733,6 +743,8 @@ extern "C" sph_status sph_batch_create(const sph_batch_params *bp, sph_batch **o
   if (e == hipSuccess) e = hipMemset(B->sesc, 0, 8 * (size_t)B->jcap * NSTRIPE);
   if (e == hipSuccess) e = hipMemset(B->P[0].f, 0, 2 * NPAD);
   if (e == hipSuccess) e = hipMemset(B->P[1].f, 0, 2 * NPAD);
+  if (e == hipSuccess) e = hipMemset(B->P[0].xf, 0, sizeof(float4) * NPAD);
+  if (e == hipSuccess) e = hipMemset(B->P[1].xf, 0, sizeof(float4) * NPAD);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     delete B;
