@@ -642,12 +642,48 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
 }
 
 // ---------------------------------------------------------------------------
+// mid-point velocity of every moving particle, once: v~ = v + dt_1/2 a^p
+// (Eq. momentum_equation_discretized's v~) and eta = 0.2 h |v~| / h^k
+// (Eq. viscosity_coefficient), in the sweep precision, so that sweep B
+// gathers one 16-byte (FP32) record per neighbour instead of v and a^p
+// ---------------------------------------------------------------------------
+template <int D, typename R>
+__global__ __launch_bounds__(BLOCK) void k_midpoint(Batch B, Parts s,
+                                                    const typename Vec4<R>::T *__restrict__ ap,
+                                                    typename Vec4<R>::T *__restrict__ mid) {
+  using R4 = typename Vec4<R>::T;
+  const int i = blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= B.n) return;
+  const int fi = s.f[i];
+  const Feat F = B.feat[fi];
+  R4 o;
+  o.x = o.y = o.z = o.w = R(0);
+  if (F.type != T_SI && B.grp[fi].active) {
+    const R halfR = (R)(0.5 * bitsd(B.grp[fi].dt1_bits));
+    const double4 v = s.v[i];
+    const R4 a = ap[i];
+    o.x = (R)v.x + halfR * a.x;
+    o.y = (R)v.y + halfR * a.y;
+    o.z = D == 3 ? (R)v.z + halfR * a.z : R(0);
+    const R vm = sqrt_(o.x * o.x + o.y * o.y + o.z * o.z);
+    const R h = (R)s.xh[i].w;
+    const R hk = F.k == 1 ? powK<1>(h) : (F.k == 2 ? powK<2>(h) : powK<3>(h));
+    o.w = R(0.2) * h * vm * rcp_(hk);
+  }
+  mid[i] = o;
+}
+
+// ---------------------------------------------------------------------------
 // sweep B pair sums: viscous force of Eq. (momentum_equation_discretized)
 // with eta = rho_t nu, nu = 0.1 r_c |v~| (Eq. (viscosity_coefficient)), the
 // mid-point velocities v~_j = v_j + dt_1/2 a^p_j formed on the fly
 // ---------------------------------------------------------------------------
-template <int D, int K, typename R>
+// MID: neighbours' v~ and eta come from their mid-point records (3D);
+// otherwise they are formed here from v and a^p (2D, where the extra pass
+// costs more than the smaller gather saves)
+template <int D, int K, typename R, bool MID>
 __device__ __forceinline__ void sweep_b_sums(const Parts &s, const typename Vec4<R>::T *__restrict__ ap,
+                                             const typename Vec4<R>::T *__restrict__ mid,
                                              const uint32_t *__restrict__ nbr, int n, int i,
                                              uint32_t cnt, const double4 &xi, const double vti[3],
                                              double vmi, double half, double Fv[3]) {
@@ -673,31 +709,41 @@ __device__ __forceinline__ void sweep_b_sums(const Parts &s, const typename Vec4
 #pragma unroll
       for (int q = 0; q < NB; ++q) u[q] = e0 + q < cnt ? ub[hb + q] : 0x80000000u;
       double4 xr[NB], vr[NB];
-      R4 ar[NB];
+      R4 mr[NB];
 #pragma unroll
       for (int q = 0; q < NB; ++q) {
         const uint32_t j = u[q] & 0x7fffffffu;   // boundary entries fetch a valid slot, unused
         xr[q] = s.xh[j];
-        vr[q] = s.v[j];
-        ar[q] = ap[j];
+        if (MID) {
+          mr[q] = mid[j];
+        } else {
+          vr[q] = s.v[j];
+          mr[q] = ap[j];
+        }
       }
 #pragma unroll
       for (int q = 0; q < NB; ++q) {
         if (u[q] >> 31) continue;
         const double4 xj = xr[q];
-        const double4 vj = vr[q];
-        const R4 apj = ar[q];
         const R dx0 = (R)(xi.x - xj.x), dx1 = (R)(xi.y - xj.y);
         const R dx2 = D == 3 ? (R)(xi.z - xj.z) : R(0);
         const R rr = sqrt_(dx0 * dx0 + dx1 * dx1 + dx2 * dx2);
         const R hj = (R)xj.w;
         const R hjk = powK<K>(hj);
-        R vtj[3];
-        vtj[0] = (R)vj.x + halfR * apj.x;
-        vtj[1] = (R)vj.y + halfR * apj.y;
-        vtj[2] = D == 3 ? (R)vj.z + halfR * apj.z : R(0);
-        const R vmj = sqrt_(vtj[0] * vtj[0] + vtj[1] * vtj[1] + vtj[2] * vtj[2]);
-        const R etaj = R(0.2) * hj * vmj * rcp_(hjk);
+        R vtj[3], etaj;
+        if (MID) {
+          vtj[0] = mr[q].x;
+          vtj[1] = mr[q].y;
+          vtj[2] = D == 3 ? mr[q].z : R(0);
+          etaj = mr[q].w;
+        } else {
+          const R4 apj = mr[q];
+          vtj[0] = (R)vr[q].x + halfR * apj.x;
+          vtj[1] = (R)vr[q].y + halfR * apj.y;
+          vtj[2] = D == 3 ? (R)vr[q].z + halfR * apj.z : R(0);
+          const R vmj = sqrt_(vtj[0] * vtj[0] + vtj[1] * vtj[1] + vtj[2] * vtj[2]);
+          etaj = R(0.2) * hj * vmj * rcp_(hjk);
+        }
         const R es = etai + etaj;
         const R H = es > R(0) ? R(2) * etai * etaj * rcp_(es) : R(0);
         const R ihij = rcp_(R(0.5) * (hi + hj));
@@ -719,6 +765,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_b(Batch B, Parts s,
                                                    const uint32_t *__restrict__ nbr,
                                                    const uint32_t *__restrict__ nnb,
                                                    const typename Vec4<R>::T *__restrict__ ap,
+                                                   const typename Vec4<R>::T *__restrict__ mid,
                                                    typename Vec4<R>::T *__restrict__ acc,
                                                    double4 *__restrict__ dbg_vm) {
   using R4 = typename Vec4<R>::T;
@@ -748,11 +795,11 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_b(Batch B, Parts s,
       const uint32_t cnt = nnb[i];
       double fv[3];
       if (k == D)
-        sweep_b_sums<D, D, R>(s, ap, nbr, n, i, cnt, xi, vti, vmi, half, fv);
+        sweep_b_sums<D, D, R, D == 3>(s, ap, mid, nbr, n, i, cnt, xi, vti, vmi, half, fv);
       else if (k == D - 1)
-        sweep_b_sums<D, D - 1, R>(s, ap, nbr, n, i, cnt, xi, vti, vmi, half, fv);
+        sweep_b_sums<D, D - 1, R, D == 3>(s, ap, mid, nbr, n, i, cnt, xi, vti, vmi, half, fv);
       else
-        sweep_b_sums<D, 1, R>(s, ap, nbr, n, i, cnt, xi, vti, vmi, half, fv);
+        sweep_b_sums<D, 1, R, D == 3>(s, ap, mid, nbr, n, i, cnt, xi, vti, vmi, half, fv);
       double xa[3] = {xi.x, xi.y, xi.z};
       tangent<D>(J.g, F, xa, fv);
       const double eps = B.grp[fi].eps;

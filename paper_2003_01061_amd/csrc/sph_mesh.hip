@@ -50,12 +50,12 @@ sph_status fail(sph_status st, const char *fmt, ...) {
   } while (0)
 
 enum KernelId {
-  KID_SCAN = 0, KID_SCATTER, KID_RANK_GATHER, KID_NBR_FORCES, KID_REDUCE_A, KID_SWEEP_B,
-  KID_REDUCE_B, KID_INTEGRATE_HASH, KID_CONTROL, KID_HASH, KID_NBR_LISTS, KID_COUNT
+  KID_SCAN = 0, KID_SCATTER, KID_RANK_GATHER, KID_NBR_FORCES, KID_REDUCE_A, KID_MIDPOINT,
+  KID_SWEEP_B, KID_REDUCE_B, KID_INTEGRATE_HASH, KID_CONTROL, KID_HASH, KID_NBR_LISTS, KID_COUNT
 };
 const char *kKernelNames[KID_COUNT] = {
-    "scan", "scatter", "rank_gather", "nbr_forces", "reduce_a", "sweep_b", "reduce_b",
-    "integrate_hash", "control", "hash", "nbr_lists"};
+    "scan", "scatter", "rank_gather", "nbr_forces", "reduce_a", "midpoint", "sweep_b",
+    "reduce_b", "integrate_hash", "control", "hash", "nbr_lists"};
 
 // ---------------------------------------------------------------------------
 // features of a box-minus-holes geometry (numbering of sph_mesh.h)
@@ -283,7 +283,7 @@ struct sph_batch {
   uint32_t *cnt = nullptr, *cstart = nullptr, *ticket = nullptr;
   unsigned long long *scan_status = nullptr;
   uint32_t *nbr = nullptr, *nnb = nullptr;
-  void *ap = nullptr, *acc = nullptr;              // {ax, ay, az, 0} in the sweep precision
+  void *ap = nullptr, *acc = nullptr, *mid = nullptr;              // {ax, ay, az, 0} in the sweep precision
   double *dbg_gam = nullptr, *dbg_vt = nullptr;
   double4 *dbg_vm = nullptr;
   JobDev *d_jobs = nullptr;
@@ -436,8 +436,11 @@ struct sph_batch {
     const unsigned gslots = (unsigned)((njobs * MAXF + BLOCK / 64 - 1) / (BLOCK / 64));
     HIPCHK((launch_nbr_forces<DD, R>(B, s)));
     HIPCHK(launch(KID_REDUCE_A, k_group_reduce, gslots, BLOCK, B, 0));
+    if (DD == 3)   // 3D sweep B gathers precomputed mid-point records
+      HIPCHK(launch(KID_MIDPOINT, k_midpoint<DD, R>, blocks(n), BLOCK, B, s, (const R4 *)ap,
+                    (R4 *)mid));
     HIPCHK(launch(KID_SWEEP_B, k_sweep_b<DD, R>, blocks8(n), BLOCK, B, s, (const uint32_t *)nbr,
-                  (const uint32_t *)nnb, (const R4 *)ap, (R4 *)acc, dbg_vm));
+                  (const uint32_t *)nnb, (const R4 *)ap, (const R4 *)mid, (R4 *)acc, dbg_vm));
     HIPCHK(launch(KID_REDUCE_B, k_group_reduce, gslots, BLOCK, B, 1));
     HIPCHK(launch(KID_INTEGRATE_HASH, k_integrate_hash<DD, R>, blocks(n), BLOCK, B, s,
                   (const R4 *)acc, cell, rank, cnt));
@@ -631,7 +634,7 @@ extern "C" int64_t sph_batch_footprint(const sph_batch_params *bp) {
   b += 4 * N * 4;                                     // cell, rank, psrc, pkey
   b += C * 4 + (C + 1) * 4 + ((C + SCAN_TILE - 1) / SCAN_TILE) * 8;
   b += N * cap * 4 + N * 4;                           // neighbour list + counts
-  b += 2 * N * r4;                                    // a^p, a
+  b += (bp->dim == 3 ? 3 : 2) * N * r4;               // a^p, a (and 3D mid-point records)
   if (bp->debug_fields) b += N * (8 + 8 + 32);
   const int64_t slots = (int64_t)bp->max_jobs * MAXF;
   b += bp->max_jobs * (int64_t)sizeof(JobDev) + slots * (int64_t)(sizeof(Feat) + 8 + sizeof(Group)) +
@@ -706,6 +709,7 @@ extern "C" sph_status sph_batch_create(const sph_batch_params *bp, sph_batch **o
   const size_t r4 = B->prec == SPH_FP64 ? sizeof(double4) : sizeof(float4);
   B->ap = dalloc<char>(N * r4, ow, by);
   B->acc = dalloc<char>(N * r4, ow, by);
+  if (B->D == 3) B->mid = dalloc<char>(N * r4, ow, by);   // mid-point records (3D sweep B)
   if (B->debug) {
     B->dbg_gam = dalloc<double>(N, ow, by);
     B->dbg_vt = dalloc<double>(N, ow, by);
@@ -724,7 +728,7 @@ extern "C" sph_status sph_batch_create(const sph_batch_params *bp, sph_batch **o
   B->scnt = dalloc<unsigned long long>((size_t)B->jcap * NSTRIPE, ow, by);
   B->sesc = dalloc<unsigned long long>((size_t)B->jcap * NSTRIPE, ow, by);
   ok = ok && B->cell && B->rank && B->psrc && B->pkey && B->cnt && B->cstart && B->scan_status &&
-       B->ticket && B->nbr && B->nnb && B->ap && B->acc && B->d_jobs && B->d_feat && B->d_bmask &&
+       B->ticket && B->nbr && B->nnb && B->ap && B->acc && (B->mid || B->D == 2) && B->d_jobs && B->d_feat && B->d_bmask &&
        B->d_bn && B->d_grp && B->d_st && B->d_gflags && B->smin && B->ssum && B->scnt && B->sesc;
   if (!ok) {
     delete B;
