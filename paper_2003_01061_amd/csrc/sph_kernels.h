@@ -189,14 +189,22 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *l
 // Single-pass exclusive scan (decoupled look-back).  Tiles take ids from a
 // ticket in dispatch order, so a tile only ever waits for tiles that have
 // already started; each tile publishes {flag, value} in one 64-bit word:
-// flag 1 = tile aggregate, flag 2 = inclusive prefix.  status[] and the
-// ticket are cleared by k_scatter, which runs after the scan has finished.
+// flag 1 = tile aggregate, flag 2 = inclusive prefix.  Flag and value travel
+// in the same atomic word and nothing else is communicated between tiles, so
+// relaxed device-scope atomics suffice (a release would write back the L2 of
+// the XCD on every tile).  A tile's counts are loaded coalesced and
+// transposed through LDS so that each thread scans SCAN_PER consecutive
+// cells.  status[] and the ticket are cleared by k_scatter, which runs after
+// the scan has finished.
 __global__ __launch_bounds__(BLOCK) void k_scan(const uint32_t *__restrict__ in,
                                                 uint32_t *__restrict__ out, uint32_t n,
                                                 unsigned long long *status, uint32_t *ticket,
                                                 uint32_t ntiles, unsigned int *gflags) {
   __shared__ uint32_t lds[BLOCK / 64];
   __shared__ uint32_t s_tile, s_prefix;
+  // tile in LDS, one padding word per SCAN_PER so that the per-thread reads
+  // of SCAN_PER consecutive words hit distinct banks
+  __shared__ uint32_t tbuf[SCAN_TILE + SCAN_TILE / SCAN_PER];
   if (threadIdx.x == 0) s_tile = atomicAdd(ticket, 1u);
   __syncthreads();
   const uint32_t tile = s_tile;
@@ -204,13 +212,19 @@ __global__ __launch_bounds__(BLOCK) void k_scan(const uint32_t *__restrict__ in,
     if (threadIdx.x == 0) atomicExch(&gflags[0], 1u);
     return;
   }
-  const size_t base = (size_t)tile * SCAN_TILE + (size_t)threadIdx.x * SCAN_PER;
+  const size_t tbase = (size_t)tile * SCAN_TILE;
+#pragma unroll
+  for (int k = 0; k < SCAN_PER; ++k) {
+    const uint32_t t = (uint32_t)k * BLOCK + threadIdx.x;
+    const size_t idx = tbase + t;
+    tbuf[t + t / SCAN_PER] = idx < n ? in[idx] : 0u;
+  }
+  __syncthreads();
   uint32_t v[SCAN_PER];
   uint32_t sum = 0;
 #pragma unroll
   for (int k = 0; k < SCAN_PER; ++k) {
-    size_t idx = base + k;
-    v[k] = idx < n ? in[idx] : 0u;
+    v[k] = tbuf[threadIdx.x * (SCAN_PER + 1) + k];
     sum += v[k];
   }
   uint32_t tot;
@@ -223,14 +237,14 @@ __global__ __launch_bounds__(BLOCK) void k_scan(const uint32_t *__restrict__ in,
     // invariant into an error instead of a hang.
     const int lane = threadIdx.x;
     if (lane == 0)
-      __hip_atomic_store(&status[tile], ((tile == 0 ? 2ull : 1ull) << 32) | tot, __ATOMIC_RELEASE,
+      __hip_atomic_store(&status[tile], ((tile == 0 ? 2ull : 1ull) << 32) | tot, __ATOMIC_RELAXED,
                          __HIP_MEMORY_SCOPE_AGENT);
     uint32_t prefix = 0;
     int base = (int)tile - 1;
     unsigned spins = 0;
     while (base >= 0) {
       const int p = base - lane;
-      unsigned long long w = p >= 0 ? __hip_atomic_load(&status[p], __ATOMIC_ACQUIRE,
+      unsigned long long w = p >= 0 ? __hip_atomic_load(&status[p], __ATOMIC_RELAXED,
                                                          __HIP_MEMORY_SCOPE_AGENT)
                                     : (2ull << 32);
       const unsigned flag = (unsigned)(w >> 32);
@@ -254,7 +268,7 @@ __global__ __launch_bounds__(BLOCK) void k_scan(const uint32_t *__restrict__ in,
     }
     if (lane == 0) {
       if (tile != 0)
-        __hip_atomic_store(&status[tile], (2ull << 32) | (uint32_t)(prefix + tot), __ATOMIC_RELEASE,
+        __hip_atomic_store(&status[tile], (2ull << 32) | (uint32_t)(prefix + tot), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
       s_prefix = prefix;
       if ((size_t)(tile + 1) * SCAN_TILE >= n) out[n] = prefix + tot;
@@ -263,10 +277,16 @@ __global__ __launch_bounds__(BLOCK) void k_scan(const uint32_t *__restrict__ in,
   __syncthreads();
   ex += s_prefix;
 #pragma unroll
-  for (int k = 0; k < SCAN_PER; ++k) {
-    size_t idx = base + k;
-    if (idx < n) out[idx] = ex;
+  for (int k = 0; k < SCAN_PER; ++k) {   // back through LDS for coalesced stores
+    tbuf[threadIdx.x * (SCAN_PER + 1) + k] = ex;
     ex += v[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < SCAN_PER; ++k) {
+    const uint32_t t = (uint32_t)k * BLOCK + threadIdx.x;
+    const size_t idx = tbase + t;
+    if (idx < n) out[idx] = tbuf[t + t / SCAN_PER];
   }
 }
 
