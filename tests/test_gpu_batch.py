@@ -133,3 +133,46 @@ def test_converged_job_stops_counting_and_stays_put():
     ref = oracle.RefJob(quick)
     ref.step(int(steps[q]))
     assert np.abs(x - ref.state()[0]).max() <= 1e-12
+
+
+def test_sixty_four_tiny_jobs_and_an_emptied_batch():
+    """The slot maximum: 64 jobs of ~60 particles in one batch; a sample of
+    them equals the same jobs alone; emptying the batch and refilling it
+    works."""
+    wls = [wk.square_lattice(n_side=6, seed=100 + q) for q in range(64)]
+    specs, npart, ncell = capacity(wls)
+    b = binding.SphBatch(2, binding.SPH_FP64, max_particles=npart, max_cells=ncell, max_jobs=64)
+    ids = [b.add(s) for s in specs]
+    assert sorted(ids) == list(range(64))
+    b.step(12)
+    for q in (0, 17, 63):
+        xr, er, cr = alone(wls[q], 12, binding.SPH_FP64)
+        assert np.array_equal(b.positions(ids[q]), xr)
+        assert b.counters(ids[q]) == cr
+    for j in ids:
+        b.remove(j)
+    live, _, _ = b.status()
+    assert not live.any()
+    b.step(3)                                     # nothing resident: a no-op
+    j = b.add(specs[5])
+    b.step(12)
+    xr, _, _ = alone(wls[5], 12, binding.SPH_FP64)
+    assert np.array_equal(b.positions(j), xr)
+
+
+def test_job_without_particles():
+    """A job with no particles is resident, converged from the first step,
+    and does not disturb its neighbour in the batch."""
+    empty = wk.square_lattice(n_side=8, seed=4)
+    empty.xyz = np.zeros((0, 3))
+    empty.feature = np.zeros(0, np.int32)
+    other = wk.scaled_hole_2d(3001, seed=31)
+    specs, npart, ncell = capacity([empty, other])
+    b = binding.SphBatch(2, binding.SPH_FP64, max_particles=npart, max_cells=ncell, max_jobs=2)
+    je, jo = b.add(specs[0]), b.add(specs[1])
+    b.step(10)
+    live, conv, steps = b.status()
+    assert live[je] and conv[je] and steps[je] <= 1
+    assert b.positions(je).shape == (0, 3)
+    xr, _, _ = alone(other, 10, binding.SPH_FP64)
+    assert np.array_equal(b.positions(jo), xr)
