@@ -109,14 +109,16 @@ struct Parts {
   uint16_t *f;      // global feature id = 64 * job slot + local feature
   uint32_t *oid;    // caller's id inside the job
   float4 *xf;       // the neighbour scan's FP32 record: {x, y, h, feature bits} in
-                    // 2D, {x, y, z, h} in 3D; always the rounding of xh (and f)
+                    // 2D; {x, y, z, h'} in 3D, h' = h rounded to FP32 with its 6
+                    // low mantissa bits replaced by the job-local feature id
 };
 
 // FP32 scan record of a particle (the rounding of its FP64 record)
 template <int D>
 __device__ __forceinline__ float4 scan_record(const double4 &xh, uint32_t f) {
   if (D == 2) return make_float4((float)xh.x, (float)xh.y, (float)xh.w, __uint_as_float(f));
-  return make_float4((float)xh.x, (float)xh.y, (float)xh.z, (float)xh.w);
+  const uint32_t hb = (__float_as_uint((float)xh.w) & ~(uint32_t)(MAXF - 1)) | (f & (MAXF - 1));
+  return make_float4((float)xh.x, (float)xh.y, (float)xh.z, __uint_as_float(hb));
 }
 
 // tables and accumulators shared by every kernel of a batch

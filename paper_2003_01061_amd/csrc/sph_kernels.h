@@ -492,7 +492,9 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
       // most 2^-24 Xb and an FP32 distance by at most M = sqrt(D) 2^-23 Xb
       // plus a relative 1e-6; the band of relative half-width 2e-6 around
       // 2 max(h_i, h_j), widened by M, covers every such error, so the
-      // classification always equals the FP64 predicate.
+      // classification always equals the FP64 predicate.  In 3D the
+      // candidate's h carries the feature id in its 6 low mantissa bits
+      // (relative error below 2^-17), so the band there is 2e-5 wide.
       const float4 xif = scan_record<D>(xi, (uint32_t)fi);
       const float hif = D == 2 ? xif.z : xif.w;
       float Mf;
@@ -550,13 +552,12 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
           // them without early exits, then the hits appended in order
           for (uint32_t j0 = jb; j0 < je; j0 += NB) {
             const float4 *rp = s.xf + j0;
-            const uint16_t *fp = s.f + j0;
             float4 xr[NB];
-            uint32_t fr[NB];
+            uint32_t fr[NB];   // job-local feature id of the candidate
 #pragma unroll
             for (int q = 0; q < NB; ++q) {
               xr[q] = rp[q];
-              fr[q] = D == 2 ? __float_as_uint(xr[q].w) : (uint32_t)fp[q];
+              fr[q] = __float_as_uint(xr[q].w) & (MAXF - 1);
             }
             uint32_t tag[NB];
 #pragma unroll
@@ -569,13 +570,15 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
               const float d2 = dx * dx + dy * dy + dz * dz;
               const float hj = D == 2 ? xr[q].z : xr[q].w;
               const float H = 2.0f * (hif > hj ? hif : hj);
-              float tin = H * (1.0f - 2e-6f) - Mf;
+              constexpr float band = D == 2 ? 2e-6f : 2e-5f;
+              float tin = H * (1.0f - band) - Mf;
               tin = tin > 0.0f ? tin * tin : -1.0f;
-              const float tout = (H * (1.0f + 2e-6f) + Mf) * (H * (1.0f + 2e-6f) + Mf);
+              const float tout = (H * (1.0f + band) + Mf) * (H * (1.0f + band) + Mf);
               bool hit = cand & (d2 < tin);
               if (cand & !(d2 < tin) & !(d2 > tout))   // near the support radius: exact test
                 hit = within_a4<D>(xi, A4, s.xh[j]);
-              tag[q] = hit ? (j | (fr[q] == (uint32_t)fi ? 0u : 0x80000000u)) : 0xffffffffu;
+              tag[q] = hit ? (j | (fr[q] == (uint32_t)(fi & (MAXF - 1)) ? 0u : 0x80000000u))
+                           : 0xffffffffu;
             }
 #pragma unroll
             for (int q = 0; q < NB; ++q) {
