@@ -46,16 +46,18 @@ def profiled_counters(cfg):
         text = open(COUNTERS_MD).read()
     except OSError:
         return None
-    kv = dict(re.findall(r"^(\w+): (.+)$", text, flags=re.M))
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         h.update(open(os.path.join(ROOT, f), "rb").read())
     want = "cell_factor={} scan_tile={}".format(float(cfg.get("cell_factor", 1.0)),
                                                 int(cfg.get("scan_tile", 4)))
-    if kv.get("kernel_source_sha256") != h.hexdigest() or kv.get("config") != want:
-        return None
-    return dict(traffic=float(kv["traffic_bytes_per_launch"]),
-                valu=float(kv["valu_insts_per_launch"]), waves=float(kv["waves_per_launch"]))
+    # one fenced block of "key: value" lines per profiled configuration
+    for block in re.findall(r"```\n(kernel: .*?)```", text, flags=re.S):
+        kv = dict(re.findall(r"^(\w+): (.+)$", block, flags=re.M))
+        if kv.get("kernel_source_sha256") == h.hexdigest() and kv.get("config") == want:
+            return dict(traffic=float(kv["traffic_bytes_per_launch"]),
+                        valu=float(kv["valu_insts_per_launch"]), waves=float(kv["waves_per_launch"]))
+    return None
 
 
 def kernel_bytes(name, wl, n_active, inter, real_bytes):
@@ -229,6 +231,8 @@ def main():
     ap.add_argument("--n", type=int, default=250_000)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--pmc-cell-factor", type=float, default=1.0,
+                    help="cell factor of the 'step' counter pass (scan tile 4)")
     ap.add_argument("--pmc-pass", choices=["step", "step3d", "copy"], default=None,
                     help="counter-collection pass for rocprofv3 --pmc: 'step' runs --steps "
                          "eagerly launched FP32-mixed steps of the workload (default tuning), "
@@ -269,7 +273,8 @@ def main():
         return
     wl = wk.square_hole(n_total=args.n)
     if args.pmc_pass == "step":
-        j = binding.SphMesh(wl, precision=binding.SPH_FP32_MIXED, use_graph=0)
+        j = binding.SphMesh(wl, precision=binding.SPH_FP32_MIXED, use_graph=0,
+                            cell_factor=args.pmc_cell_factor)
         j.step(args.steps)
         j.sync()
         c = j.counters()
