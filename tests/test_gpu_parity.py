@@ -181,6 +181,23 @@ def test_full_size_square_hole_250k():
     xr = ref.state()[0]
     assert np.abs(g64.positions() - xr).max() <= TOL64
     assert np.abs(g32.positions() - xr).max() <= TOL32
+    # the other configurations the benchmark's tuner may pick
+    for cfg in ({"cell_factor": 0.75, "scan_tile": 2}, {"cell_factor": 1.25, "scan_tile": 8}):
+        g = binding.SphMesh(wl, precision=binding.SPH_FP32_MIXED, use_graph=1, **cfg)
+        g.step(K)
+        assert np.abs(g.positions() - xr).max() <= TOL32, cfg
+
+
+def test_neighbor_list_overflow_is_reported_not_truncated():
+    """A capacity below the largest list: the step runs, the particle count
+    that did not fit is reported, and reading results fails with
+    SPH_ERR_STATE instead of returning a result from truncated lists."""
+    wl = wk.scaled_hole_2d(4001, seed=71)
+    g = binding.SphMesh(wl, max_neighbors=8)
+    g.step(1)
+    with pytest.raises(binding.SphError) as e:
+        g.positions()
+    assert e.value.status == 4 and "overflow" in str(e.value)
 
 
 def _sample_indices(wl, n_random, seed):
