@@ -25,13 +25,13 @@
  *
  * Feature numbering (a feature is the paper's (type, index) pair, sec. 3.2;
  * each feature evolves as one group with its own time step, sec. 3.5):
- *   2D box [lo,hi]^2 minus n_holes discs:
+ *   2D box [lo,hi]^2 minus n_holes discs / ellipses:
  *     0 volume (P_+) | 1..4 box edges x=lo, x=hi, y=lo, y=hi (P_c) |
- *     5..4+n_holes hole circles (P_c) | then 4 corners (P_si), corner c at
+ *     5..4+n_holes hole boundaries (P_c) | then 4 corners (P_si), corner c at
  *     (bit0 of c ? hi : lo, bit1 of c ? hi : lo).
- *   3D box [lo,hi]^3 minus n_holes balls:
+ *   3D box [lo,hi]^3 minus n_holes balls / ellipsoids:
  *     0 volume (P_+) | 1..6 faces x=lo, x=hi, y=lo, y=hi, z=lo, z=hi (P_s) |
- *     7..6+n_holes hole spheres (P_s) | 12 box edges (P_c) | 8 corners (P_si).
+ *     7..6+n_holes hole surfaces (P_s) | 12 box edges (P_c) | 8 corners (P_si).
  *     Edge 4a + sb + 2 sc runs along axis a; its fixed coordinates are the
  *     two other axes b < c, at lo (0) or hi (1) as given by sb and sc.
  *     Corner c sits at (bit0, bit1, bit2 of c) ? hi : lo per axis.
@@ -61,9 +61,15 @@ enum { SPH_H_CONST = 0, SPH_H_LINEAR_FROM_POINT = 1, SPH_H_GRADED_TO_HOLES = 2 }
 enum { SPH_FP64 = 0, SPH_FP32_MIXED = 1 };
 
 /* Geometry (paper sec. 2.1 / 3.1): the level set phi > 0 is the box minus
- * the holes.  holes: n_holes x 15 doubles, centre[3], semi_axes[3], rot[9];
- * this build handles discs / balls (three equal semi-axes; rot ignored).
- * At most 16 holes; holes must lie inside the box. */
+ * the holes.  holes: n_holes x 15 doubles, centre[3], semi_axes[3], rot[9]
+ * (row-major, orthonormal): the hole is sum_k (y_k / a_k)^2 <= 1 with local
+ * coordinates y = rot (x - centre) (the first dim axes).  Equal semi-axes
+ * make a disc / ball (rot ignored; closed-form projections); otherwise an
+ * ellipse / ellipsoid, whose closest points come from Newton's method on
+ * the Lagrange multiplier t of z_k = a_k^2 y_k / (a_k^2 + t) (8 fixed steps
+ * to project a particle, until t stops increasing for the distance in h_t).
+ * At most 16 holes; each must lie inside the box with a margin of its
+ * largest semi-axis; every particle must lie in the box. */
 typedef struct {
   int32_t dim;               /* 2 or 3 */
   double lo[3], hi[3];
@@ -104,7 +110,8 @@ typedef struct {
                                 integration and projection */
   int32_t max_neighbors;     /* neighbour-list capacity per particle, rounded up
                                 to a multiple of 8; 0 = 64 in 2D, 160 in 3D */
-  double cell_factor;        /* cell side = 2 h_min cell_factor; 0 = 1.0 */
+  double cell_factor;        /* cell side = 2 h_min cell_factor (0 = 1.0), enlarged
+                                if the grid would exceed 2^29 cells */
   int32_t scan_tile;         /* candidate records tested per pass of the
                                 neighbour scan: 2, 4 or 8; 0 = 4.  Results do
                                 not depend on it (autotuning knob) */
@@ -174,6 +181,16 @@ sph_status sph_mesh_velocities(sph_mesh *m, double *vel);
  * offsets and *n_pairs are written.  cap = capacity of ids / rel. */
 sph_status sph_mesh_neighbors(sph_mesh *m, int64_t *offsets, int32_t *ids,
                               int8_t *rel, int64_t cap, int64_t *n_pairs);
+
+/* Neighbour lists of the count particles idx[0..count) (caller ids) at the
+ * current positions, as sph_mesh_neighbors writes them but for those
+ * particles only: offsets[count+1], ids / rel per entry (NULL allowed).
+ * Copies only the requested lists to the host, so it suits jobs whose whole
+ * list set is too large to pull.  SPH_ERR_INVALID_ARG for an index outside
+ * [0, n) or cap below the pair count. */
+sph_status sph_mesh_neighbors_of(sph_mesh *m, int32_t count, const int64_t *idx,
+                                 int64_t *offsets, int32_t *ids, int8_t *rel, int64_t cap,
+                                 int64_t *n_pairs);
 
 /* Per-particle quantities of the last step, caller order (needs
  * debug_fields for 3..5): 0 h (n), 1 pressure acceleration a^p (n x 3),

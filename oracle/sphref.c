@@ -58,6 +58,9 @@ typedef struct {
   double lo[3], hi[3];
   int nh;
   double hc[MAXH][3], hr[MAXH];
+  int ell[MAXH];            /* 1: ellipsoid (unequal semi-axes), 0: ball */
+  double ha[MAXH][3];       /* ellipsoid semi-axes */
+  double hR[MAXH][9];       /* ellipsoid rotation, row-major: local = R (x - c) */
   int nf;
   feat_t f[MAXF];
 } geo_t;
@@ -73,12 +76,22 @@ static int geo_build(const sphref_geometry *g, geo_t *G) {
   G->nh = g->n_holes;
   for (int q = 0; q < G->nh; ++q) {
     const double *H = g->holes + 15 * q;
-    if (!(H[3] > 0) || H[4] != H[3] || H[5] != H[3]) {
-      set_err("only discs / balls (equal semi-axes) are supported");
-      return -1;
-    }
+    int D = g->dim;
+    for (int a = 0; a < D; ++a)
+      if (!(H[3 + a] > 0)) { set_err("hole semi-axes must be positive"); return -1; }
     for (int a = 0; a < 3; ++a) G->hc[q][a] = H[a];
     G->hr[q] = H[3];
+    G->ell[q] = D == 2 ? H[4] != H[3] : (H[4] != H[3] || H[5] != H[3]);
+    for (int a = 0; a < 3; ++a) G->ha[q][a] = H[3 + a];
+    for (int e = 0; e < 9; ++e) G->hR[q][e] = H[6 + e];
+    if (G->ell[q]) {               /* the rotation must be orthonormal */
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+          double s = 0.0;
+          for (int m = 0; m < 3; ++m) s = s + H[6 + 3 * m + r] * H[6 + 3 * m + c];
+          if (fabs(s - (r == c ? 1.0 : 0.0)) > 1e-9) { set_err("hole rotation not orthonormal"); return -1; }
+        }
+    }
   }
   int D = G->dim, nf = 0;
   G->f[nf++] = (feat_t){.type = T_V, .k = D, .kind = K_VOL};
@@ -129,6 +142,105 @@ static int bounds(const geo_t *G, int fi, int fb) {
   }
 }
 
+/* ------------------------------------------------------------------ */
+/* ellipsoidal holes: local coordinates y = R (x - c), the hole is       */
+/* sum_k (y_k / a_k)^2 <= 1 (sec. 2.1's level set for a quadric)         */
+/* ------------------------------------------------------------------ */
+static void ell_local(const geo_t *G, int q, const double *x, double *y) {
+  int D = G->dim;
+  for (int k = 0; k < D; ++k) {
+    double s = 0.0;
+    for (int m = 0; m < D; ++m) s = s + G->hR[q][3 * k + m] * (x[m] - G->hc[q][m]);
+    y[k] = s;
+  }
+}
+
+static double ell_level(const geo_t *G, int q, const double *y) {
+  double s = 0.0;
+  for (int k = 0; k < G->dim; ++k) {
+    double u = y[k] / G->ha[q][k];
+    s = s + u * u;
+  }
+  return s;
+}
+
+/* One Newton step for the closest point: z_k = a_k^2 y_k / (a_k^2 + t) lies
+ * on the surface where g(t) = sum_k (a_k y_k / (a_k^2 + t))^2 - 1 = 0, and
+ * g'(t) = -2 sum_k (a_k y_k)^2 / (a_k^2 + t)^3. */
+static double ell_newton(const geo_t *G, int q, const double *y, double t) {
+  double g = -1.0, dg = 0.0;
+  for (int k = 0; k < G->dim; ++k) {
+    double a = G->ha[q][k];
+    double e = a * a + t;
+    double u = a * y[k] / e;
+    double uu = u * u;
+    g = g + uu;
+    dg = dg + uu / e;
+  }
+  return t + g / (2.0 * dg);
+}
+
+static void ell_point(const geo_t *G, int q, const double *y, double t, double *z) {
+  for (int k = 0; k < G->dim; ++k) {
+    double a = G->ha[q][k];
+    z[k] = a * a * y[k] / (a * a + t);
+  }
+}
+
+/* distance from x to the surface of hole q for x outside it (0 inside):
+ * g is convex and decreasing for t > -min a^2 and g(0) > 0 outside, so
+ * Newton from t = 0 increases monotonically to the root; it stops when t
+ * no longer increases (at most 64 steps; 18 suffice on [0,1]^3). */
+static double ell_dist(const geo_t *G, int q, const double *x) {
+  double y[3] = {0, 0, 0}, z[3] = {0, 0, 0};
+  ell_local(G, q, x, y);
+  if (!(ell_level(G, q, y) > 1.0)) return 0.0;
+  double t = 0.0;
+  for (int it = 0; it < 64; ++it) {
+    double tn = ell_newton(G, q, y, t);
+    if (!(tn > t)) break;
+    t = tn;
+  }
+  ell_point(G, q, y, t, z);
+  double s = 0.0;
+  for (int k = 0; k < G->dim; ++k) { double d = y[k] - z[k]; s = s + d * d; }
+  return sqrt(s);
+}
+
+/* closest point on the surface of hole q to a point x near it: eight Newton
+ * steps from t = 0 (reading R18: a fixed count; eight bring offsets up to
+ * 3e-3 of the semi-axes to |level - 1| <= 1e-15) */
+static void ell_project(const geo_t *G, int q, double *x) {
+  int D = G->dim;
+  double y[3] = {0, 0, 0}, z[3] = {0, 0, 0};
+  ell_local(G, q, x, y);
+  double t = 0.0;
+  for (int it = 0; it < 8; ++it) t = ell_newton(G, q, y, t);
+  ell_point(G, q, y, t, z);
+  for (int m = 0; m < D; ++m) {
+    double s = 0.0;
+    for (int k = 0; k < D; ++k) s = s + G->hR[q][3 * k + m] * z[k];
+    x[m] = G->hc[q][m] + s;
+  }
+}
+
+/* unit normal of hole q's level set at x, pointing out of the hole */
+static void ell_normal(const geo_t *G, int q, const double *x, double *n) {
+  int D = G->dim;
+  double y[3] = {0, 0, 0}, gy[3] = {0, 0, 0};
+  ell_local(G, q, x, y);
+  for (int k = 0; k < D; ++k) { double a = G->ha[q][k]; gy[k] = y[k] / (a * a); }
+  double s = 0.0;
+  for (int m = 0; m < D; ++m) {
+    double v = 0.0;
+    for (int k = 0; k < D; ++k) v = v + G->hR[q][3 * k + m] * gy[k];
+    n[m] = v;
+    s = s + v * v;
+  }
+  double r = sqrt(s);
+  for (int m = 0; m < D; ++m) n[m] = n[m] / r;
+}
+
 static double sg(int side) { return side ? 1.0 : -1.0; }
 
 /* outward normal n_b of feature fi's boundary at boundary particle b
@@ -141,6 +253,10 @@ static void bnormal(const geo_t *G, int fi, int fb, const double *xb, double *n)
   if (A->kind == K_VOL) {
     if (B->kind == K_BOXSIDE) {
       n[B->axis] = sg(B->side);
+    } else if (B->kind == K_HOLE && G->ell[B->hole]) {
+      /* out of the domain = into the hole, against its level set's normal */
+      ell_normal(G, B->hole, xb, n);
+      for (int a = 0; a < D; ++a) n[a] = -n[a];
     } else if (B->kind == K_HOLE) {
       /* out of the domain = into the hole, towards its centre */
       double d[3] = {0, 0, 0}, s = 0.0;
@@ -189,6 +305,18 @@ static void tproject(const geo_t *G, int fi, const double *x, double *u) {
     }
     case K_HOLE: {
       const double *c = G->hc[A->hole];
+      if (G->ell[A->hole]) {
+        double m[3] = {0, 0, 0};
+        ell_normal(G, A->hole, x, m);
+        if (D == 2) {                     /* keep the part along the tangent (-n1, n0) */
+          double ut = u[0] * (-m[1]) + u[1] * m[0];
+          u[0] = ut * (-m[1]); u[1] = ut * m[0];
+        } else {                          /* remove the normal part */
+          double un = u[0] * m[0] + u[1] * m[1] + u[2] * m[2];
+          for (int a = 0; a < 3; ++a) u[a] = u[a] - un * m[a];
+        }
+        return;
+      }
       if (D == 2) {
         double t0 = -(x[1] - c[1]), t1 = x[0] - c[0];
         double tl = sqrt(t0 * t0 + t1 * t1);
@@ -226,6 +354,7 @@ static void pproject(const geo_t *G, int fi, double *x) {
         x[A->fax[q]] = A->fsd[q] ? G->hi[A->fax[q]] : G->lo[A->fax[q]];
       return;
     case K_HOLE: {
+      if (G->ell[A->hole]) { ell_project(G, A->hole, x); return; }
       const double *c = G->hc[A->hole];
       double d[3] = {0, 0, 0}, s = 0.0;
       for (int a = 0; a < D; ++a) { d[a] = x[a] - c[a]; s = s + d[a] * d[a]; }
@@ -246,6 +375,12 @@ static int inside(const geo_t *G, const double *x) {
   for (int a = 0; a < D; ++a)
     if (!(x[a] > G->lo[a] && x[a] < G->hi[a])) return 0;
   for (int q = 0; q < G->nh; ++q) {
+    if (G->ell[q]) {
+      double y[3] = {0, 0, 0};
+      ell_local(G, q, x, y);
+      if (!(ell_level(G, q, y) > 1.0)) return 0;
+      continue;
+    }
     double s = 0.0;
     for (int a = 0; a < D; ++a) { double d = x[a] - G->hc[q][a]; s = s + d * d; }
     double r = G->hr[q];
@@ -267,9 +402,14 @@ static double h_at(const geo_t *G, const sphref_sizing *S, const double *x) {
   }
   double dmin = INFINITY;
   for (int q = 0; q < G->nh; ++q) {
-    double s = 0.0;
-    for (int a = 0; a < D; ++a) { double d = x[a] - G->hc[q][a]; s = s + d * d; }
-    double d = fabs(sqrt(s) - G->hr[q]);
+    double d;
+    if (G->ell[q]) {
+      d = ell_dist(G, q, x);
+    } else {
+      double s = 0.0;
+      for (int a = 0; a < D; ++a) { double e = x[a] - G->hc[q][a]; s = s + e * e; }
+      d = fabs(sqrt(s) - G->hr[q]);
+    }
     if (d < dmin) dmin = d;
   }
   if (S->dcap < dmin) dmin = S->dcap;
@@ -722,13 +862,44 @@ static void sweep_a_particle(const sphref_job *J, int64_t i, const int32_t *nbl,
   *gam_out = gam;
 }
 
-/* Neighbour list of a single particle by brute force over all particles,
- * ids ascending (same predicate and relation as build_lists). */
-static int64_t brute_list(const sphref_job *J, int64_t i, int32_t *ids, int8_t *rel, int64_t cap) {
+
+/* h of particle j at the current positions, computed on first use */
+static double h_of(sphref_job *J, int64_t j) {
+  if (isnan(J->h[j])) J->h[j] = h_at(&J->G, &J->S, J->x + 3 * j);
+  return J->h[j];
+}
+
+/* Lipschitz constant of h_t: |grad d| <= 1 for the distance to the holes */
+static double h_lipschitz(const sphref_sizing *S) {
+  if (S->kind == 0) return 0.0;
+  if (S->kind == 1) return S->grad;
+  return S->h0 * S->grad;
+}
+
+/* brute_list with h evaluated only where the predicate can hold: with L the
+ * Lipschitz constant of h_t, h_j <= h_i + L r, so a j at distance
+ * r >= R_i = 2 h_i / (1 - 2L) has 4 max(h_i, h_j)^2 <= r^2 and is no
+ * neighbour (R_i^2 is widened by 1e-9 for rounding).  Same predicate and
+ * relation as build_lists; ids ascending. */
+static int64_t brute_list_lazy(sphref_job *J, int64_t i, int32_t *ids, int8_t *rel, int64_t cap) {
   int64_t c = 0;
   if (ftype(J, i) == T_SI) return 0;
+  int D = J->G.dim;
+  double hi = h_of(J, i);
+  double L = h_lipschitz(&J->S);
+  double R2 = INFINITY;
+  if (2.0 * L < 1.0) { double R = 2.0 * hi / (1.0 - 2.0 * L); R2 = R * R * (1.0 + 1e-9); }
   for (int64_t j = 0; j < J->n; ++j) {
-    if (j == i || !within(J, i, j)) continue;
+    if (j == i) continue;
+    double s = 0.0;
+    for (int a = 0; a < D; ++a) {
+      double d = J->x[3 * i + a] - J->x[3 * j + a];
+      s = s + d * d;
+    }
+    if (!(s < R2)) continue;
+    double hj = h_of(J, j);
+    double m = hi > hj ? hi : hj;
+    if (!(s < 4.0 * (m * m))) continue;
     int r = relation(J, i, j);
     if (!r) continue;
     if (c < cap) { ids[c] = (int32_t)j; rel[c] = (int8_t)r; }
@@ -740,13 +911,13 @@ static int64_t brute_list(const sphref_job *J, int64_t i, int32_t *ids, int8_t *
 int32_t sphref_sample(sphref_job *J, int32_t m, const int64_t *idx, int64_t *offsets,
                       int32_t *ids, int8_t *rel, int64_t cap, double *ap, double *vt,
                       double *gam) {
-  compute_h(J);
+  for (int64_t j = 0; j < J->n; ++j) J->h[j] = NAN;   /* h at the current positions, lazily */
   int64_t total = 0;
   offsets[0] = 0;
   for (int32_t s = 0; s < m; ++s) {
     int64_t i = idx[s];
     if (i < 0 || i >= J->n) { set_err("sample index out of range"); return -1; }
-    int64_t c = brute_list(J, i, ids + total, rel + total, cap - total);
+    int64_t c = brute_list_lazy(J, i, ids + total, rel + total, cap - total);
     if (total + c > cap) { set_err("capacity too small"); return -1; }
     if (ftype(J, i) != T_SI)
       sweep_a_particle(J, i, ids + total, rel + total, c, ap + 3 * s, vt + s, gam + s);

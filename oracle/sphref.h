@@ -37,8 +37,9 @@ typedef struct sphref_job sphref_job;
 
 /* Box [lo,hi]^dim minus n_holes holes.  holes: n_holes x 15 doubles:
  * centre[3], semi_axes[3], rot[9] (row-major, local = rot * (x - centre)).
- * A hole whose three semi-axes are equal is a disc (2D) / ball (3D) of that
- * radius and its rotation is ignored. */
+ * A hole whose semi-axes (the first dim) are equal is a disc (2D) / ball (3D)
+ * of that radius and its rotation is ignored; otherwise it is an ellipse /
+ * ellipsoid, sum_k (local_k / a_k)^2 <= 1, with an orthonormal rotation. */
 typedef struct {
   int32_t dim;
   double lo[3], hi[3];

@@ -77,6 +77,8 @@ def lib():
         L.sph_mesh_set_state.argtypes = [vp, vp, vp]
         L.sph_mesh_velocities.argtypes = [vp, vp]
         L.sph_mesh_neighbors.argtypes = [vp, vp, vp, vp, C.c_int64, C.POINTER(C.c_int64)]
+        L.sph_mesh_neighbors_of.argtypes = [vp, C.c_int32, vp, vp, vp, vp, C.c_int64,
+                                            C.POINTER(C.c_int64)]
         L.sph_mesh_field.argtypes = [vp, C.c_int32, vp]
         L.sph_mesh_group_state.argtypes = [vp, C.c_int32, vp]
         L.sph_mesh_counters.argtypes = [vp, vp]
@@ -229,6 +231,22 @@ class SphMesh:
         _check("sph_mesh_neighbors", L.sph_mesh_neighbors(self.h, off.ctypes.data, ids.ctypes.data,
                                                           rel.ctypes.data, ids.size,
                                                           C.byref(npairs)))
+        return off, ids[:npairs.value], rel[:npairs.value]
+
+    def neighbors_of(self, idx):
+        """Lists of the particles idx only (caller ids), as neighbors() gives
+        them: offsets into ids / rel per requested particle."""
+        L = lib()
+        idx = np.ascontiguousarray(idx, np.int64)
+        off = np.zeros(idx.size + 1, np.int64)
+        npairs = C.c_int64()
+        _check("sph_mesh_neighbors_of", L.sph_mesh_neighbors_of(
+            self.h, idx.size, idx.ctypes.data, off.ctypes.data, None, None, 0, C.byref(npairs)))
+        ids = np.zeros(max(npairs.value, 1), np.int32)
+        rel = np.zeros(max(npairs.value, 1), np.int8)
+        _check("sph_mesh_neighbors_of", L.sph_mesh_neighbors_of(
+            self.h, idx.size, idx.ctypes.data, off.ctypes.data, ids.ctypes.data, rel.ctypes.data,
+            ids.size, C.byref(npairs)))
         return off, ids[:npairs.value], rel[:npairs.value]
 
     def field(self, which):
@@ -406,7 +424,7 @@ def exported_symbols():
     """Names the header declares (checked by the CPU test of the ABI)."""
     return ["sph_mesh_create", "sph_mesh_step", "sph_mesh_positions", "sph_mesh_error",
             "sph_mesh_destroy", "sph_mesh_last_error", "sph_mesh_set_state", "sph_mesh_velocities",
-            "sph_mesh_neighbors", "sph_mesh_field", "sph_mesh_group_state", "sph_mesh_counters",
+            "sph_mesh_neighbors", "sph_mesh_neighbors_of", "sph_mesh_field", "sph_mesh_group_state", "sph_mesh_counters",
             "sph_mesh_control_replay", "sph_mesh_profile", "sph_mesh_kernel_stats",
             "sph_mesh_kernel_count", "sph_mesh_kernel_name", "sph_mesh_sync",
             "sph_mesh_device_bytes", "sph_batch_footprint", "sph_job_cells", "sph_batch_create",

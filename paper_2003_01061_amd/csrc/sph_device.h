@@ -58,6 +58,10 @@ struct Geom {
   double hc[MAXH][3];
   double hr[MAXH];
   double h0, grad, dcap, hpt[3];
+  int32_t hell[MAXH];       // 1: ellipsoidal hole (unequal semi-axes)
+  double ha[MAXH][3];       // its semi-axes, and max over them
+  double hamax[MAXH];
+  double hR[MAXH][9];       // rotation, row-major: local y = R (x - c)
 };
 
 // uniform cell grid over a job's box; its cells own the global cell ids
@@ -154,6 +158,124 @@ struct Vec4<double> {
 
 // h_t(x) of the sizing record: squared distances summed over axes in order,
 // sqrt, no fused multiply-add, so that it is bit-reproducible.
+// ---------------------------------------------------------------------------
+// ellipsoidal holes: sum_k (y_k / a_k)^2 <= 1 with y = R (x - c).  The
+// operations that decide h and the inside test run in this fixed order with
+// no contraction, so h is the same on every IEEE-754 FP64 implementation of
+// the same steps.
+// ---------------------------------------------------------------------------
+template <int D>
+__device__ __forceinline__ void ell_local(const Geom &g, int q, const double *x, double *y) {
+#pragma clang fp contract(off)
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    double s = 0.0;
+#pragma unroll
+    for (int m = 0; m < D; ++m) s = s + g.hR[q][3 * k + m] * (x[m] - g.hc[q][m]);
+    y[k] = s;
+  }
+}
+
+template <int D>
+__device__ __forceinline__ double ell_level(const Geom &g, int q, const double *y) {
+#pragma clang fp contract(off)
+  double s = 0.0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    const double u = y[k] / g.ha[q][k];
+    s = s + u * u;
+  }
+  return s;
+}
+
+// Newton step on g(t) = sum_k (a_k y_k / (a_k^2 + t))^2 - 1, whose root t
+// gives the closest surface point z_k = a_k^2 y_k / (a_k^2 + t)
+template <int D>
+__device__ __forceinline__ double ell_newton(const Geom &g, int q, const double *y, double t) {
+#pragma clang fp contract(off)
+  double gv = -1.0, dg = 0.0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    const double a = g.ha[q][k];
+    const double e = a * a + t;
+    const double u = a * y[k] / e;
+    const double uu = u * u;
+    gv = gv + uu;
+    dg = dg + uu / e;
+  }
+  return t + gv / (2.0 * dg);
+}
+
+// distance to the surface for x outside the hole, 0 inside: Newton from
+// t = 0 rises monotonically to the root (g convex, decreasing, g(0) > 0)
+// and stops when t no longer increases (64 steps at most)
+template <int D>
+__device__ __forceinline__ double ell_dist(const Geom &g, int q, const double *x) {
+#pragma clang fp contract(off)
+  double y[3] = {0.0, 0.0, 0.0};
+  ell_local<D>(g, q, x, y);
+  if (!(ell_level<D>(g, q, y) > 1.0)) return 0.0;
+  double t = 0.0;
+  for (int it = 0; it < 64; ++it) {
+    const double tn = ell_newton<D>(g, q, y, t);
+    if (!(tn > t)) break;
+    t = tn;
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    const double a = g.ha[q][k];
+    const double z = a * a * y[k] / (a * a + t);
+    const double d = y[k] - z;
+    s = s + d * d;
+  }
+  return __builtin_sqrt(s);
+}
+
+// closest surface point to a point near the surface: 8 Newton steps from t = 0
+template <int D>
+__device__ __forceinline__ void ell_project(const Geom &g, int q, double *x) {
+  double y[3] = {0.0, 0.0, 0.0}, z[3] = {0.0, 0.0, 0.0};
+  ell_local<D>(g, q, x, y);
+  double t = 0.0;
+#pragma unroll
+  for (int it = 0; it < 8; ++it) t = ell_newton<D>(g, q, y, t);
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    const double a = g.ha[q][k];
+    z[k] = a * a * y[k] / (a * a + t);
+  }
+#pragma unroll
+  for (int m = 0; m < D; ++m) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) s = s + g.hR[q][3 * k + m] * z[k];
+    x[m] = g.hc[q][m] + s;
+  }
+}
+
+// unit normal of the hole's level set at x, pointing out of the hole
+template <int D>
+__device__ __forceinline__ void ell_normal(const Geom &g, int q, const double *x, double *n) {
+  double y[3] = {0.0, 0.0, 0.0};
+  ell_local<D>(g, q, x, y);
+  double gy[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < D; ++k) gy[k] = y[k] / (g.ha[q][k] * g.ha[q][k]);
+  double s = 0.0;
+#pragma unroll
+  for (int m = 0; m < D; ++m) {
+    double v = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) v = v + g.hR[q][3 * k + m] * gy[k];
+    n[m] = v;
+    s = s + v * v;
+  }
+  const double il = 1.0 / __builtin_sqrt(s);
+#pragma unroll
+  for (int m = 0; m < D; ++m) n[m] *= il;
+}
+
 template <int D>
 __device__ __forceinline__ double h_target(const Geom &g, const double *p) {
 #pragma clang fp contract(off)
@@ -173,7 +295,17 @@ __device__ __forceinline__ double h_target(const Geom &g, const double *p) {
       double d = p[a] - g.hc[q][a];
       s = s + d * d;
     }
-    double d = __builtin_fabs(__builtin_sqrt(s) - g.hr[q]);
+    double d;
+    if (g.hell[q]) {
+      // |x - c| - max a bounds the distance from below; an ellipsoid whose
+      // bound exceeds the current minimum (or the cap) by a relative 1e-12
+      // cannot lower min(d, dcap), so its Newton solve is skipped
+      const double lim = dmin < g.dcap ? dmin : g.dcap;
+      if (__builtin_sqrt(s) - g.hamax[q] > lim * (1.0 + 1e-12)) continue;
+      d = ell_dist<D>(g, q, p);
+    } else {
+      d = __builtin_fabs(__builtin_sqrt(s) - g.hr[q]);
+    }
     if (d < dmin) dmin = d;
   }
   if (g.dcap < dmin) dmin = g.dcap;
@@ -336,6 +468,21 @@ __device__ __forceinline__ void tangent(const Geom &g, const Feat &F, const doub
       return;
     }
     case K_HOLE: {
+      if (g.hell[F.hole]) {
+        double m[3] = {0.0, 0.0, 0.0};
+        ell_normal<D>(g, F.hole, x, m);
+        if (D == 2) {   // keep the part along the tangent (-n1, n0)
+          const double ut = u[0] * (-m[1]) + u[1] * m[0];
+          u[0] = ut * (-m[1]);
+          u[1] = ut * m[0];
+        } else {        // remove the normal part
+          const double un = u[0] * m[0] + u[1] * m[1] + u[2] * m[2];
+          u[0] -= un * m[0];
+          u[1] -= un * m[1];
+          u[2] -= un * m[2];
+        }
+        return;
+      }
       const double *c = g.hc[F.hole];
       if (D == 2) {
         double t0 = -(x[1] - c[1]), t1 = x[0] - c[0];
@@ -380,6 +527,10 @@ __device__ __forceinline__ void project(const Geom &g, const Feat &F, double *x)
       x[F.fax1] = F.fsd1 ? g.hi[F.fax1] : g.lo[F.fax1];
       return;
     case K_HOLE: {
+      if (g.hell[F.hole]) {
+        ell_project<D>(g, F.hole, x);
+        return;
+      }
       const double *c = g.hc[F.hole];
       double d[3] = {0.0, 0.0, 0.0}, s = 0.0;
       for (int a = 0; a < D; ++a) {
@@ -404,6 +555,12 @@ __device__ __forceinline__ bool inside(const Geom &g, const double *x) {
   for (int a = 0; a < D; ++a)
     if (!(x[a] > g.lo[a] && x[a] < g.hi[a])) return false;
   for (int q = 0; q < g.nh; ++q) {
+    if (g.hell[q]) {
+      double y[3] = {0.0, 0.0, 0.0};
+      ell_local<D>(g, q, x, y);
+      if (!(ell_level<D>(g, q, y) > 1.0)) return false;
+      continue;
+    }
     double s = 0.0;
     for (int a = 0; a < D; ++a) {
       double d = x[a] - g.hc[q][a];

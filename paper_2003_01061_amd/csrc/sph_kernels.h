@@ -411,6 +411,13 @@ __device__ __forceinline__ void sweep_a_sums(const Geom &g, const Parts &s,
             nv[0] = d0 * il;
             nv[1] = d1 * il;
             nv[2] = d2 * il;
+          } else if (N.mode == 3) {   // ellipsoidal hole: against its level set's normal
+            const double xb[3] = {xj.x, xj.y, xj.z};
+            double m[3] = {0.0, 0.0, 0.0};
+            ell_normal<D>(g, N.hole, xb, m);
+            nv[0] = -m[0];
+            nv[1] = -m[1];
+            nv[2] = -m[2];
           } else {
             nv[0] = N.n[0];
             nv[1] = N.n[1];

@@ -62,6 +62,7 @@ const char *kKernelNames[KID_COUNT] = {
 // ---------------------------------------------------------------------------
 struct HFeat {
   int type, k, kind, axis = 0, side = 0, fax[2] = {0, 0}, fsd[2] = {0, 0}, hole = 0, bits = 0;
+  int ell = 0;   // HOLE: the hole is an ellipsoid
 };
 
 std::vector<HFeat> make_features(int D, int nh) {
@@ -123,7 +124,7 @@ BNorm boundary_normal(int D, const HFeat &A, const HFeat &B) {
     if (B.kind == K_BOXSIDE) {
       N.n[B.axis] = sg(B.side);
     } else if (B.kind == K_HOLE) {
-      N.mode = 2;
+      N.mode = B.ell ? 3 : 2;
       N.hole = B.hole;
     } else if (B.kind == K_EDGE3) {
       const double r = std::sqrt(0.5);
@@ -165,6 +166,11 @@ T *dalloc(size_t count, std::vector<void *> &owned, size_t &bytes) {
 }  // namespace
 
 
+// a hole with unequal semi-axes (the first D of them) is an ellipsoid
+static bool hole_is_ellipsoid(int D, const double *H) {
+  return D == 2 ? H[4] != H[3] : (H[4] != H[3] || H[5] != H[3]);
+}
+
 static sph_status validate(const sph_geometry *g, const sph_sizing *s, const sph_params *p) {
   if (!g || !s || !p) return fail(SPH_ERR_INVALID_ARG, "null geometry, sizing or params");
   if (g->dim != 2 && g->dim != 3) return fail(SPH_ERR_INVALID_ARG, "dim must be 2 or 3");
@@ -176,10 +182,22 @@ static sph_status validate(const sph_geometry *g, const sph_sizing *s, const sph
   if (g->n_holes > 0 && !g->holes) return fail(SPH_ERR_INVALID_ARG, "holes is NULL");
   for (int q = 0; q < g->n_holes; ++q) {
     const double *H = g->holes + 15 * q;
-    if (!(H[3] > 0) || H[4] != H[3] || H[5] != H[3])
-      return fail(SPH_ERR_UNSUPPORTED, "hole %d: only discs / balls (equal semi-axes)", q);
+    double amax = 0.0;
+    for (int a = 0; a < g->dim; ++a) {
+      if (!(H[3 + a] > 0) || !std::isfinite(H[3 + a]))
+        return fail(SPH_ERR_INVALID_ARG, "hole %d: semi-axes must be positive", q);
+      amax = std::max(amax, H[3 + a]);
+    }
+    if (hole_is_ellipsoid(g->dim, H))   // the rotation must be orthonormal
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+          double t = 0.0;
+          for (int m = 0; m < 3; ++m) t += H[6 + 3 * m + r] * H[6 + 3 * m + c];
+          if (!(std::fabs(t - (r == c ? 1.0 : 0.0)) <= 1e-9))
+            return fail(SPH_ERR_INVALID_ARG, "hole %d: rotation is not orthonormal", q);
+        }
     for (int a = 0; a < g->dim; ++a)
-      if (!(H[a] - H[3] > g->lo[a] && H[a] + H[3] < g->hi[a]))
+      if (!(H[a] - amax > g->lo[a] && H[a] + amax < g->hi[a]))
         return fail(SPH_ERR_INVALID_ARG, "hole %d must lie strictly inside the box", q);
   }
   if (s->kind < 0 || s->kind > 2) return fail(SPH_ERR_INVALID_ARG, "unknown sizing kind");
@@ -239,7 +257,9 @@ static void sizing_bounds(const sph_geometry *g, const sph_sizing *s, double &hm
       for (int a = 0; a < D; ++a) d2 += (corner(c, a) - H[a]) * (corner(c, a) - H[a]);
       far = std::max(far, std::sqrt(d2));
     }
-    dmax = std::min(dmax, far - H[3]);
+    double amin = H[3];
+    for (int a = 1; a < D; ++a) amin = std::min(amin, H[3 + a]);
+    dmax = std::min(dmax, far - amin);
   }
   hmax = s->h0 * (1.0 + s->grad * dmax);
   lip = s->h0 * s->grad;
@@ -247,12 +267,14 @@ static void sizing_bounds(const sph_geometry *g, const sph_sizing *s, double &hm
 
 
 
-// copy a device column (slot order) to a host vector
+// copy a device column (slot order) to a host vector, ordered after the work
+// already queued on the batch's stream
 template <typename T>
-static hipError_t pull(std::vector<T> &h, const void *d, size_t count) {
+static hipError_t pull(std::vector<T> &h, const void *d, size_t count, hipStream_t st) {
   h.resize(count);
   if (!count) return hipSuccess;
-  return hipMemcpy(h.data(), d, count * sizeof(T), hipMemcpyDeviceToHost);
+  hipError_t e = hipMemcpyAsync(h.data(), d, count * sizeof(T), hipMemcpyDeviceToHost, st);
+  return e == hipSuccess ? hipStreamSynchronize(st) : e;
 }
 
 // ---------------------------------------------------------------------------
@@ -507,8 +529,9 @@ struct sph_batch {
   sph_status check_job(int j) {
     JobStat s{};
     unsigned int gf = 0;
-    HIPCHK(hipMemcpy(&s, d_st + j, sizeof s, hipMemcpyDeviceToHost));
-    HIPCHK(hipMemcpy(&gf, d_gflags, sizeof gf, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpyAsync(&s, d_st + j, sizeof s, hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipMemcpyAsync(&gf, d_gflags, sizeof gf, hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
     if (gf) return fail(SPH_ERR_DEVICE, "cell-count scan lost a tile");
     if (s.nan_flag) return fail(SPH_ERR_STATE, "non-finite position of particle %u", s.nan_oid);
     if (s.overflow)
@@ -532,7 +555,7 @@ static void grid_of(const sph_geometry *g, const sph_sizing *s, const sph_params
   for (;;) {
     double cells = 1.0;
     for (int a = 0; a < D; ++a) cells *= std::max(1.0, std::floor((g->hi[a] - g->lo[a]) / side));
-    if (cells <= 16.0 * 1024 * 1024) break;
+    if (cells <= 512.0 * 1024 * 1024) break;   // at most 2^29 cells per job
     side *= 1.25;
   }
   std::memset(&Gr, 0, sizeof Gr);
@@ -556,6 +579,8 @@ static void fill_job(HostJob &J, const sph_geometry *g, const sph_sizing *s, con
                      uint32_t cbase, int n) {
   const int D = g->dim;
   J.feats = make_features(D, g->n_holes);
+  for (HFeat &F : J.feats)
+    if (F.kind == K_HOLE) F.ell = hole_is_ellipsoid(D, g->holes + 15 * F.hole) ? 1 : 0;
   J.nf = (int)J.feats.size();
   J.n = n;
   JobDev &d = J.dev;
@@ -571,8 +596,16 @@ static void fill_job(HostJob &J, const sph_geometry *g, const sph_sizing *s, con
     G.hpt[a] = s->point[a];
   }
   for (int q = 0; q < g->n_holes; ++q) {
-    for (int a = 0; a < 3; ++a) G.hc[q][a] = g->holes[15 * q + a];
-    G.hr[q] = g->holes[15 * q + 3];
+    const double *H = g->holes + 15 * q;
+    for (int a = 0; a < 3; ++a) G.hc[q][a] = H[a];
+    G.hr[q] = H[3];
+    G.hell[q] = hole_is_ellipsoid(D, H) ? 1 : 0;
+    G.hamax[q] = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      G.ha[q][a] = H[3 + a];
+      if (a < D) G.hamax[q] = std::max(G.hamax[q], H[3 + a]);
+    }
+    for (int e = 0; e < 9; ++e) G.hR[q][e] = H[6 + e];
   }
   G.h0 = s->h0;
   G.grad = s->grad;
@@ -852,22 +885,31 @@ extern "C" sph_status sph_batch_add(sph_batch *b, const sph_geometry *g, const s
   JobStat js{};
   js.live = 1;
   hipError_t e = hipSuccess;
-  if (N) e = hipMemcpy(P.xh + o, xh.data(), N * sizeof(double4), hipMemcpyHostToDevice);
-  if (e == hipSuccess && N) e = hipMemset(P.v + o, 0, N * sizeof(double4));
-  if (e == hipSuccess && N) e = hipMemcpy(P.oid + o, oid.data(), N * 4, hipMemcpyHostToDevice);
-  if (e == hipSuccess && N) e = hipMemcpy(P.f + o, f16.data(), N * 2, hipMemcpyHostToDevice);
+  // every upload and clear is queued on the batch's stream, in order with the
+  // hash that follows (a null-stream copy or memset is not ordered with a
+  // non-blocking stream); the host vectors live until the synchronisation
+  hipStream_t q = b->stream;
+  if (N) e = hipMemcpyAsync(P.xh + o, xh.data(), N * sizeof(double4), hipMemcpyHostToDevice, q);
+  if (e == hipSuccess && N) e = hipMemsetAsync(P.v + o, 0, N * sizeof(double4), q);
+  if (e == hipSuccess && N) e = hipMemcpyAsync(P.oid + o, oid.data(), N * 4, hipMemcpyHostToDevice, q);
+  if (e == hipSuccess && N) e = hipMemcpyAsync(P.f + o, f16.data(), N * 2, hipMemcpyHostToDevice, q);
   if (e == hipSuccess)
-    e = hipMemcpy(b->d_feat + slot * MAXF, hf.data(), sizeof(Feat) * MAXF, hipMemcpyHostToDevice);
+    e = hipMemcpyAsync(b->d_feat + slot * MAXF, hf.data(), sizeof(Feat) * MAXF,
+                       hipMemcpyHostToDevice, q);
   if (e == hipSuccess)
-    e = hipMemcpy(b->d_bmask + slot * MAXF, hm.data(), 8 * MAXF, hipMemcpyHostToDevice);
+    e = hipMemcpyAsync(b->d_bmask + slot * MAXF, hm.data(), 8 * MAXF, hipMemcpyHostToDevice, q);
   if (e == hipSuccess)
-    e = hipMemcpy(b->d_bn + (size_t)slot * MAXF * MAXF, hb.data(), sizeof(BNorm) * MAXF * MAXF,
-                  hipMemcpyHostToDevice);
+    e = hipMemcpyAsync(b->d_bn + (size_t)slot * MAXF * MAXF, hb.data(),
+                       sizeof(BNorm) * MAXF * MAXF, hipMemcpyHostToDevice, q);
   if (e == hipSuccess)
-    e = hipMemcpy(b->d_grp + slot * MAXF, hg.data(), sizeof(Group) * MAXF, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(b->d_jobs + slot, &J.dev, sizeof(JobDev), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(b->d_st + slot, &js, sizeof js, hipMemcpyHostToDevice);
-  if (e == hipSuccess && J.ncell) e = hipMemset(b->cnt + b->ncell, 0, 4 * (size_t)J.ncell);
+    e = hipMemcpyAsync(b->d_grp + slot * MAXF, hg.data(), sizeof(Group) * MAXF,
+                       hipMemcpyHostToDevice, q);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->d_jobs + slot, &J.dev, sizeof(JobDev), hipMemcpyHostToDevice, q);
+  if (e == hipSuccess) e = hipMemcpyAsync(b->d_st + slot, &js, sizeof js, hipMemcpyHostToDevice, q);
+  if (e == hipSuccess && J.ncell) e = hipMemsetAsync(b->cnt + b->ncell, 0, 4 * (size_t)J.ncell, q);
+  if (e == hipSuccess) e = hipStreamSynchronize(q);
+  else (void)hipStreamSynchronize(q);
   if (e != hipSuccess) return fail(SPH_ERR_DEVICE, "job upload failed: %s", hipGetErrorString(e));
   J.live = true;
   b->jobs[slot] = J;
@@ -947,7 +989,8 @@ extern "C" sph_status sph_batch_status(sph_batch *b, int32_t *live, int32_t *con
   if (!b) return fail(SPH_ERR_INVALID_ARG, "null batch");
   HIPCHK(hipStreamSynchronize(b->stream));
   std::vector<JobStat> st(b->jcap);
-  HIPCHK(hipMemcpy(st.data(), b->d_st, sizeof(JobStat) * b->jcap, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpyAsync(st.data(), b->d_st, sizeof(JobStat) * b->jcap, hipMemcpyDeviceToHost, b->stream));
+  HIPCHK(hipStreamSynchronize(b->stream));
   for (int j = 0; j < cap; ++j) {
     const bool ok = j < b->jcap && b->jobs[j].live;
     if (live) live[j] = ok;
@@ -970,10 +1013,10 @@ extern "C" sph_status sph_batch_positions(sph_batch *b, int32_t job, double *xyz
   const Parts &s = b->P[b->cur];
   const size_t first = (size_t)b->job_first(job);
   std::vector<uint32_t> oid;
-  HIPCHK(pull(oid, s.oid + first, J.n));
+  HIPCHK(pull(oid, s.oid + first, J.n, b->stream));
   if (xyz) {
     std::vector<double4> xh;
-    HIPCHK(pull(xh, s.xh + first, J.n));
+    HIPCHK(pull(xh, s.xh + first, J.n, b->stream));
     for (int i = 0; i < J.n; ++i) {
       double *o = xyz + 3 * (size_t)oid[i];
       o[0] = xh[i].x;
@@ -983,7 +1026,7 @@ extern "C" sph_status sph_batch_positions(sph_batch *b, int32_t job, double *xyz
   }
   if (feature) {
     std::vector<uint16_t> f;
-    HIPCHK(pull(f, s.f + first, J.n));
+    HIPCHK(pull(f, s.f + first, J.n, b->stream));
     for (int i = 0; i < J.n; ++i) feature[oid[i]] = f[i] % MAXF;
   }
   return SPH_OK;
@@ -995,9 +1038,11 @@ extern "C" sph_status sph_batch_error(sph_batch *b, int32_t job, double *e_sys, 
   HIPCHK(hipStreamSynchronize(b->stream));
   if (sph_status st = b->check_job(job)) return st;
   std::vector<Group> G(MAXF);
-  HIPCHK(hipMemcpy(G.data(), b->d_grp + job * MAXF, sizeof(Group) * MAXF, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpyAsync(G.data(), b->d_grp + job * MAXF, sizeof(Group) * MAXF, hipMemcpyDeviceToHost, b->stream));
+  HIPCHK(hipStreamSynchronize(b->stream));
   JobStat S;
-  HIPCHK(hipMemcpy(&S, b->d_st + job, sizeof S, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpyAsync(&S, b->d_st + job, sizeof S, hipMemcpyDeviceToHost, b->stream));
+  HIPCHK(hipStreamSynchronize(b->stream));
   double e = 0.0;
   int ph = PH_FROZEN, conv = 1;
   for (const Group &q : G) {
@@ -1017,7 +1062,8 @@ extern "C" sph_status sph_batch_counters(sph_batch *b, int32_t job, double *out)
   if (!b || !out || !b->valid_job(job)) return fail(SPH_ERR_INVALID_ARG, "bad argument");
   HIPCHK(hipStreamSynchronize(b->stream));
   JobStat S;
-  HIPCHK(hipMemcpy(&S, b->d_st + job, sizeof S, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpyAsync(&S, b->d_st + job, sizeof S, hipMemcpyDeviceToHost, b->stream));
+  HIPCHK(hipStreamSynchronize(b->stream));
   out[0] = (double)S.steps;
   out[1] = (double)S.escaped;
   out[2] = (double)S.inter_total;
@@ -1103,9 +1149,9 @@ extern "C" sph_status sph_mesh_velocities(sph_mesh *m, double *vel) {
   HIPCHK(hipStreamSynchronize(b->stream));
   const Parts &s = b->P[b->cur];
   std::vector<uint32_t> oid;
-  HIPCHK(pull(oid, s.oid, b->n));
+  HIPCHK(pull(oid, s.oid, b->n, b->stream));
   std::vector<double4> v;
-  HIPCHK(pull(v, s.v, b->n));
+  HIPCHK(pull(v, s.v, b->n, b->stream));
   for (int i = 0; i < b->n; ++i) {
     double *o = vel + 3 * (size_t)oid[i];
     o[0] = v[i].x;
@@ -1122,16 +1168,17 @@ extern "C" sph_status sph_mesh_set_state(sph_mesh *m, const double *xyz, const d
   if (b->n == 0) return SPH_OK;
   const Parts &s = b->P[b->cur];
   std::vector<uint32_t> oid;
-  HIPCHK(pull(oid, s.oid, b->n));
+  HIPCHK(pull(oid, s.oid, b->n, b->stream));
   if (xyz) {
     std::vector<double4> xh(b->n);
     for (int i = 0; i < b->n; ++i) {
       const double *p = xyz + 3 * (size_t)oid[i];
       xh[i] = make_double4(p[0], p[1], b->D == 3 ? p[2] : 0.0, 0.0);
     }
-    HIPCHK(hipMemcpy(s.xh, xh.data(), xh.size() * sizeof(double4), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpyAsync(s.xh, xh.data(), xh.size() * sizeof(double4), hipMemcpyHostToDevice,
+                          b->stream));
     // new positions: new h, cells and ranks
-    HIPCHK(hipMemset(b->cnt, 0, sizeof(uint32_t) * b->ncell));
+    HIPCHK(hipMemsetAsync(b->cnt, 0, sizeof(uint32_t) * b->ncell, b->stream));
     if (sph_status st = b->hash_range(0, b->n)) return st;
     HIPCHK(hipStreamSynchronize(b->stream));
   }
@@ -1141,9 +1188,25 @@ extern "C" sph_status sph_mesh_set_state(sph_mesh *m, const double *xyz, const d
       const double *p = vel + 3 * (size_t)oid[i];
       v[i] = make_double4(p[0], p[1], b->D == 3 ? p[2] : 0.0, 0.0);
     }
-    HIPCHK(hipMemcpy(s.v, v.data(), v.size() * sizeof(double4), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpyAsync(s.v, v.data(), v.size() * sizeof(double4), hipMemcpyHostToDevice,
+                          b->stream));
+    HIPCHK(hipStreamSynchronize(b->stream));
   }
   return SPH_OK;
+}
+
+// Lists of every particle at the current positions: sort into cell order,
+// build the lists, then re-hash so that the next step starts from consistent
+// cell counts.
+static sph_status build_lists_now(sph_mesh *m) {
+  sph_batch *b = m->b;
+  b->invalidate_graph();
+  sph_status st = b->enqueue_sort();
+  if (!st) st = b->D == 2 ? b->enqueue_lists_only<2>() : b->enqueue_lists_only<3>();
+  if (!st) st = b->hash_range(0, b->n);
+  if (st) return st;
+  HIPCHK(hipStreamSynchronize(b->stream));
+  return b->check_job(m->job);
 }
 
 extern "C" sph_status sph_mesh_neighbors(sph_mesh *m, int64_t *offsets, int32_t *ids, int8_t *rel,
@@ -1157,20 +1220,13 @@ extern "C" sph_status sph_mesh_neighbors(sph_mesh *m, int64_t *offsets, int32_t 
     if (n_pairs) *n_pairs = 0;
     return SPH_OK;
   }
-  // sort into cell order, build the lists, then re-hash so that the next
-  // step starts from consistent cell counts
-  b->invalidate_graph();
-  sph_status st = b->enqueue_sort();
-  if (!st) st = b->D == 2 ? b->enqueue_lists_only<2>() : b->enqueue_lists_only<3>();
-  if (!st) st = b->hash_range(0, n);
+  sph_status st = build_lists_now(m);
   if (st) return st;
-  HIPCHK(hipStreamSynchronize(b->stream));
-  if ((st = b->check_job(m->job))) return st;
   const Parts &s = b->P[b->cur];
   std::vector<uint32_t> oid, nnb, nbr;
-  HIPCHK(pull(oid, s.oid, n));
-  HIPCHK(pull(nnb, b->nnb, n));
-  HIPCHK(pull(nbr, b->nbr, (size_t)n * b->cap));
+  HIPCHK(pull(oid, s.oid, n, b->stream));
+  HIPCHK(pull(nnb, b->nnb, n, b->stream));
+  HIPCHK(pull(nbr, b->nbr, (size_t)n * b->cap, b->stream));
   std::vector<int64_t> cnt(n + 1, 0);
   for (int i = 0; i < n; ++i) cnt[oid[i] + 1] = nnb[i];
   for (int i = 0; i < n; ++i) cnt[i + 1] += cnt[i];
@@ -1196,6 +1252,61 @@ extern "C" sph_status sph_mesh_neighbors(sph_mesh *m, int64_t *offsets, int32_t 
   return SPH_OK;
 }
 
+extern "C" sph_status sph_mesh_neighbors_of(sph_mesh *m, int32_t count, const int64_t *idx,
+                                            int64_t *offsets, int32_t *ids, int8_t *rel,
+                                            int64_t cap, int64_t *n_pairs) {
+  if (!m || !offsets || (count > 0 && !idx)) return fail(SPH_ERR_INVALID_ARG, "null argument");
+  if (count < 0) return fail(SPH_ERR_INVALID_ARG, "count < 0");
+  sph_batch *b = m->b;
+  HIPCHK(hipStreamSynchronize(b->stream));
+  const int n = b->n;
+  for (int32_t q = 0; q < count; ++q)
+    if (idx[q] < 0 || idx[q] >= n)
+      return fail(SPH_ERR_INVALID_ARG, "particle index %lld out of range", (long long)idx[q]);
+  offsets[0] = 0;
+  if (count == 0) {
+    if (n_pairs) *n_pairs = 0;
+    return SPH_OK;
+  }
+  sph_status st = build_lists_now(m);
+  if (st) return st;
+  const Parts &s = b->P[b->cur];
+  std::vector<uint32_t> oid, nnb;
+  HIPCHK(pull(oid, s.oid, n, b->stream));
+  HIPCHK(pull(nnb, b->nnb, n, b->stream));
+  std::vector<int> slot(n);                 // caller id -> cell-order position
+  for (int i = 0; i < n; ++i) slot[oid[i]] = i;
+  int64_t total = 0;
+  for (int32_t q = 0; q < count; ++q) {
+    total += nnb[slot[idx[q]]];
+    offsets[q + 1] = total;
+  }
+  if (n_pairs) *n_pairs = total;
+  if (!ids && !rel) return SPH_OK;
+  if (cap < total) return fail(SPH_ERR_INVALID_ARG, "capacity %lld < %lld pairs", (long long)cap,
+                               (long long)total);
+  std::vector<uint32_t> row;
+  std::vector<std::pair<uint32_t, int8_t>> tmp;
+  for (int32_t q = 0; q < count; ++q) {
+    const int i = slot[idx[q]];
+    const uint32_t k = nnb[i];
+    row.assign(((k + LB - 1) / LB) * LB, 0u);
+    for (uint32_t blk = 0; blk * LB < k; ++blk)    // one block of LB entries per copy
+      HIPCHK(hipMemcpyAsync(row.data() + (size_t)blk * LB, b->nbr + ((size_t)blk * n + i) * LB,
+                            sizeof(uint32_t) * LB, hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    tmp.clear();
+    for (uint32_t e = 0; e < k; ++e)
+      tmp.push_back({oid[row[e] & 0x7fffffffu], (int8_t)((row[e] >> 31) ? 2 : 1)});
+    std::sort(tmp.begin(), tmp.end());
+    for (size_t t = 0; t < tmp.size(); ++t) {
+      if (ids) ids[offsets[q] + t] = (int32_t)tmp[t].first;
+      if (rel) rel[offsets[q] + t] = tmp[t].second;
+    }
+  }
+  return SPH_OK;
+}
+
 extern "C" sph_status sph_mesh_field(sph_mesh *m, int32_t which, double *out) {
   if (!m || !out) return fail(SPH_ERR_INVALID_ARG, "null argument");
   sph_batch *b = m->b;
@@ -1205,7 +1316,7 @@ extern "C" sph_status sph_mesh_field(sph_mesh *m, int32_t which, double *out) {
   const int n = b->n;
   const Parts &s = b->P[b->cur];
   std::vector<uint32_t> oid;
-  HIPCHK(pull(oid, s.oid, n));
+  HIPCHK(pull(oid, s.oid, n, b->stream));
   std::vector<double> col;
   auto scatter1 = [&]() {
     for (int i = 0; i < n; ++i) out[oid[i]] = col[i];
@@ -1221,22 +1332,22 @@ extern "C" sph_status sph_mesh_field(sph_mesh *m, int32_t which, double *out) {
   std::vector<double4> v4;
   switch (which) {
     case 0: {
-      HIPCHK(pull(v4, s.xh, n));
+      HIPCHK(pull(v4, s.xh, n, b->stream));
       col.resize(n);
       for (int i = 0; i < n; ++i) col[i] = v4[i].w;
       scatter1();
       break;
     }
-    case 3: HIPCHK(pull(col, b->dbg_vt, n)); scatter1(); break;
-    case 4: HIPCHK(pull(col, b->dbg_gam, n)); scatter1(); break;
-    case 5: HIPCHK(pull(v4, b->dbg_vm, n)); scatter4(v4); break;
+    case 3: HIPCHK(pull(col, b->dbg_vt, n, b->stream)); scatter1(); break;
+    case 4: HIPCHK(pull(col, b->dbg_gam, n, b->stream)); scatter1(); break;
+    case 5: HIPCHK(pull(v4, b->dbg_vm, n, b->stream)); scatter4(v4); break;
     default: {
       const void *src = which == 1 ? b->ap : b->acc;
       if (b->prec == SPH_FP64) {
-        HIPCHK(pull(v4, src, n));
+        HIPCHK(pull(v4, src, n, b->stream));
       } else {
         std::vector<float4> f4;
-        HIPCHK(pull(f4, src, n));
+        HIPCHK(pull(f4, src, n, b->stream));
         v4.resize(n);
         for (int i = 0; i < n; ++i) v4[i] = make_double4(f4[i].x, f4[i].y, f4[i].z, f4[i].w);
       }
@@ -1251,7 +1362,8 @@ extern "C" sph_status sph_mesh_group_state(sph_mesh *m, int32_t f, double *out) 
   sph_batch *b = m->b;
   HIPCHK(hipStreamSynchronize(b->stream));
   Group G;
-  HIPCHK(hipMemcpy(&G, b->d_grp + m->job * MAXF + f, sizeof G, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpyAsync(&G, b->d_grp + m->job * MAXF + f, sizeof G, hipMemcpyDeviceToHost, b->stream));
+  HIPCHK(hipStreamSynchronize(b->stream));
   out[0] = G.phase; out[1] = G.n_ph; out[2] = G.esys; out[3] = G.dt1; out[4] = G.dt;
   out[5] = G.vbar; out[6] = G.reset_next; out[7] = G.a_last; out[8] = G.a_prev; out[9] = G.nwin;
   return SPH_OK;

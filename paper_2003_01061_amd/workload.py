@@ -105,6 +105,106 @@ def _hole_rec(c, r):
     return rec
 
 
+def _ellipsoid_rec(c, a, rot):
+    """hole record of the ellipsoid sum_k (y_k / a_k)^2 <= 1, y = rot (x - c)
+    (rot row-major, orthonormal)"""
+    rec = np.zeros(15)
+    rec[0:len(c)] = c
+    rec[3:3 + len(a)] = a
+    if len(a) == 2:
+        rec[5] = a[0]              # unused third semi-axis of a 2D hole
+    rec[6:15] = np.asarray(rot, float).ravel()
+    return rec
+
+
+def _is_ellipsoid(rec, dim):
+    return rec[4] != rec[3] or (dim == 3 and rec[5] != rec[3])
+
+
+def _random_rotation(rng, dim):
+    """uniform random rotation: a unit quaternion from four normals (3D), a
+    uniform angle (2D)"""
+    if dim == 2:
+        t = rng.uniform(0.0, 2.0 * np.pi)
+        c, s = math.cos(t), math.sin(t)
+        return np.array([[c, s, 0.0], [-s, c, 0.0], [0.0, 0.0, 1.0]])
+    q = rng.standard_normal(4)
+    w, x, y, z = q / np.linalg.norm(q)
+    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+                     [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+                     [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
+
+
+def _ell_local(pts, dim, rec):
+    R = rec[6:15].reshape(3, 3)[:dim, :dim]
+    return (pts[:, :dim] - rec[:dim]) @ R.T
+
+
+def _ell_level(y, rec):
+    a = rec[3:3 + y.shape[1]]
+    out = (y[:, 0] / a[0]) ** 2
+    for k in range(1, y.shape[1]):
+        out += (y[:, k] / a[k]) ** 2
+    return out
+
+
+def _ell_dist(pts, dim, rec):
+    """distance to the ellipsoid's surface of points outside it (0 inside):
+    the closest point is a_k^2 y_k / (a_k^2 + t) at the root t of
+    sum_k (a_k y_k / (a_k^2 + t))^2 = 1, found by Newton's method from the
+    lower bound t0 = |a y| - max a^2 (left of the root, so the iterates
+    increase to it; 12 steps converge for points up to unit distance)"""
+    a = rec[3:3 + dim]
+    y = _ell_local(pts, dim, rec)
+    out = np.zeros(len(pts))
+    ext = _ell_level(y, rec) > 1.0
+    if not np.any(ext):
+        return out
+    ys = [y[ext, k] for k in range(dim)]
+    a2 = a * a
+    ay = [a[k] * ys[k] for k in range(dim)]
+    t = np.maximum(0.0, np.sqrt(sum(v * v for v in ay)) - a2.max())
+    for _ in range(12):
+        g = -1.0
+        dg = 0.0
+        for k in range(dim):
+            e = a2[k] + t
+            u = ay[k] / e
+            u *= u
+            g = g + u
+            dg = dg + u / e
+        t = np.maximum(t, t + g / (2.0 * dg))
+    d2 = 0.0
+    for k in range(dim):
+        dk = ys[k] * (1.0 - a2[k] / (a2[k] + t))
+        d2 = d2 + dk * dk
+    out[ext] = np.sqrt(d2)
+    return out
+
+
+def _hole_dists(pts, dim, holes, cap=np.inf):
+    """min over the holes of the distance to their boundaries, capped at cap.
+    A hole whose bounding-sphere lower bound |x - c| - max a is no less than
+    the running upper bound (|x - c| - min a over every hole, and cap) cannot
+    change the minimum and is skipped for that point."""
+    n = len(pts)
+    if len(holes) == 0:
+        return np.full(n, cap)
+    dc = [np.linalg.norm(pts[:, :dim] - rec[:dim], axis=1) for rec in holes]
+    ub = np.full(n, cap)
+    for rec, r in zip(holes, dc):
+        ub = np.minimum(ub, np.maximum(r - rec[3:3 + dim].min(), 0.0))
+    d = ub.copy()
+    for rec, r in zip(holes, dc):
+        if not _is_ellipsoid(rec, dim):
+            d = np.minimum(d, np.abs(r - rec[3]))
+            continue
+        m = r - rec[3:3 + dim].max() < ub
+        if np.any(m):
+            d[m] = np.minimum(d[m], _ell_dist(pts[m], dim, rec))
+    return d
+
+
 # ---------------------------------------------------------------------------
 # the sampling density's own copy of the sizing formula
 # ---------------------------------------------------------------------------
@@ -115,19 +215,60 @@ def _h_field(pts, dim, sizing, holes):
     if kind == H_LINEAR_FROM_POINT:
         p = np.asarray(sizing["point"][:dim])
         return sizing["h0"] + sizing["grad"] * np.linalg.norm(pts[:, :dim] - p, axis=1)
-    d = np.full(pts.shape[0], np.inf)
-    for rec in holes:
-        dd = np.abs(np.linalg.norm(pts[:, :dim] - rec[:dim], axis=1) - rec[3])
-        d = np.minimum(d, dd)
-    d = np.minimum(d, sizing["dcap"])
+    if not any(_is_ellipsoid(rec, dim) for rec in holes):
+        d = np.full(pts.shape[0], np.inf)
+        for rec in holes:
+            dd = np.abs(np.linalg.norm(pts[:, :dim] - rec[:dim], axis=1) - rec[3])
+            d = np.minimum(d, dd)
+        d = np.minimum(d, sizing["dcap"])
+    else:
+        d = np.zeros(0)
+        for q in range(0, len(pts), 1 << 20):      # chunks bound the memory
+            d = np.concatenate([d, _hole_dists(pts[q:q + (1 << 20)], dim, holes, sizing["dcap"])])
     return sizing["h0"] * (1.0 + sizing["grad"] * d)
 
 
 def _inside(pts, dim, lo, hi, holes):
     ok = np.all((pts[:, :dim] > lo[:dim]) & (pts[:, :dim] < hi[:dim]), axis=1)
     for rec in holes:
-        ok &= np.sum((pts[:, :dim] - rec[:dim]) ** 2, axis=1) > rec[3] ** 2
+        if _is_ellipsoid(rec, dim):
+            ok &= _ell_level(_ell_local(pts, dim, rec), rec) > 1.0
+        else:
+            ok &= np.sum((pts[:, :dim] - rec[:dim]) ** 2, axis=1) > rec[3] ** 2
     return ok
+
+
+def _lipschitz(sizing):
+    """Lipschitz constant of h (the distance to the holes is 1-Lipschitz)"""
+    k = sizing["kind"]
+    return 0.0 if k == H_CONST else (sizing["grad"] if k == H_LINEAR_FROM_POINT
+                                     else sizing["h0"] * sizing["grad"])
+
+
+def _sphere_points(dim, rec, res):
+    """equal-measure points u of the unit circle / sphere, their mapped points
+    c + rot^T (a u) on the hole boundary and the boundary measure per point
+    (for the map u -> a u the measure is prod(a) |u / a| times that of u)"""
+    c = rec[:3]
+    a = rec[3:3 + dim]
+    if dim == 2:
+        nseg = res * 4
+        th = (np.arange(nseg) + 0.5) * 2 * np.pi / nseg
+        u = np.stack([np.cos(th), np.sin(th)], 1)
+        dOmega = 2 * np.pi / nseg
+    else:
+        nt = res
+        ct = -1 + (np.arange(nt) + 0.5) * 2.0 / nt          # cos(theta), equal-area bands
+        ph = (np.arange(2 * nt) + 0.5) * np.pi / nt
+        CT, PH = np.meshgrid(ct, ph, indexing="ij")
+        st = np.sqrt(1 - CT ** 2)
+        u = np.stack([st * np.cos(PH), st * np.sin(PH), CT], -1).reshape(-1, 3)
+        dOmega = 4 * np.pi / u.shape[0]
+    R = rec[6:15].reshape(3, 3)[:dim, :dim]
+    pts = np.zeros((len(u), 3))
+    pts[:, :dim] = c[:dim] + (a * u) @ R
+    dA = np.prod(a) * np.linalg.norm(u / a, axis=1) * dOmega
+    return pts, dA
 
 
 # ---------------------------------------------------------------------------
@@ -180,7 +321,10 @@ def _masses(dim, lo, hi, holes, sizing, res):
     # hole boundaries
     for rec in holes:
         c, r = rec[:3], rec[3]
-        if dim == 2:
+        if _is_ellipsoid(rec, dim):
+            pts, dA = _sphere_points(dim, rec, res)
+            M[f] = float(np.sum(_h_field(pts, dim, sizing, holes) ** -float(dim - 1) * dA))
+        elif dim == 2:
             th = (np.arange(nseg) + 0.5) * 2 * np.pi / nseg
             pts = np.stack([c[0] + r * np.cos(th), c[1] + r * np.sin(th), np.zeros(nseg)], 1)
             M[f] = float(np.sum(_h_field(pts, dim, sizing, holes) ** -1.0) * 2 * np.pi * r / nseg)
@@ -252,7 +396,78 @@ def _sample_rejection(rng, n, propose, dim, sizing, holes, k, hmin, accept_mask=
     return out[:n]
 
 
-def _build(name, dim, lo, hi, holes, sizing, params, n_total, seed, steps, res):
+def _sample_volume_envelope(rng, n, dim, lo, hi, sizing, holes, g):
+    """Rejection sampling of the volume against rho_t = h^-dim with a
+    piecewise-constant envelope on a g^dim grid: in a cell of half-diagonal
+    r around centre c, h >= max(h0, h(c) - L r) (L the Lipschitz constant of
+    h), so a proposal drawn uniformly in a cell chosen with weight
+    h_lb^-dim is kept with probability (h_lb / h(x))^dim <= 1.  Cells that
+    lie inside a hole (|c / a| + r / min a <= 1 in the hole's frame) get no
+    weight.  The acceptance stays near one even where h spans 1:20.
+
+    Per cell, only the holes whose bounding sphere meets the cell can reject
+    a proposal, and only those whose distance lower bound over the cell is
+    below the cell's upper bound of the minimum distance can set h there."""
+    side = (hi[:dim] - lo[:dim]) / g
+    ax = [lo[a] + (np.arange(g) + 0.5) * side[a] for a in range(dim)]
+    C = np.stack([m.ravel() for m in np.meshgrid(*ax, indexing="ij")], 1)
+    cen = np.zeros((len(C), 3))
+    cen[:, :dim] = C
+    r = 0.5 * float(np.linalg.norm(side))
+    hc = _h_field(cen, dim, sizing, holes)
+    hlb = np.maximum(sizing["h0"], hc - _lipschitz(sizing) * r)
+    w = hlb ** -float(dim)
+    nh = len(holes)
+    touch = np.zeros((len(C), nh), bool)
+    useful = np.zeros((len(C), nh), bool)
+    if sizing["kind"] == H_GRADED_TO_HOLES and nh:
+        dc = np.stack([np.linalg.norm(C - rec[:dim], axis=1) for rec in holes], 1)
+        amax = np.array([rec[3:3 + dim].max() for rec in holes])
+        amin = np.array([rec[3:3 + dim].min() for rec in holes])
+        ub = np.minimum(sizing["dcap"], np.min(np.maximum(dc - amin, 0.0) + r, axis=1))
+        useful = np.maximum(dc - r - amax, 0.0) < ub[:, None]
+    for q, rec in enumerate(holes):
+        a = rec[3:3 + dim]
+        dcq = np.linalg.norm(C - rec[:dim], axis=1)
+        touch[:, q] = dcq - r < a.max()
+        lev = _ell_level(_ell_local(cen, dim, rec), rec)
+        w[np.sqrt(lev) + r / a.min() <= 1.0 - 1e-9] = 0.0
+    pw = w / w.sum()
+    out, have = [], 0
+    while have < n:
+        m = min(max(1 << 16, int(1.25 * (n - have))), 1 << 22)
+        cell = np.repeat(np.arange(len(C)), rng.multinomial(m, pw))
+        pts = np.zeros((m, 3))
+        pts[:, :dim] = C[cell] - 0.5 * side + rng.random((m, dim)) * side
+        ok = np.all((pts[:, :dim] > lo[:dim]) & (pts[:, :dim] < hi[:dim]), axis=1)
+        for q, rec in enumerate(holes):
+            sel = np.nonzero(touch[cell, q] & ok)[0]
+            if sel.size:
+                ok[sel] = _ell_level(_ell_local(pts[sel], dim, rec), rec) > 1.0
+        pts, cell = pts[ok], cell[ok]
+        if sizing["kind"] == H_GRADED_TO_HOLES and nh:
+            d = np.full(len(pts), float(sizing["dcap"]))
+            for q, rec in enumerate(holes):
+                sel = np.nonzero(useful[cell, q])[0]
+                if not sel.size:
+                    continue
+                if _is_ellipsoid(rec, dim):
+                    dq = _ell_dist(pts[sel], dim, rec)
+                else:
+                    dq = np.abs(np.linalg.norm(pts[sel, :dim] - rec[:dim], axis=1) - rec[3])
+                d[sel] = np.minimum(d[sel], dq)
+            h = sizing["h0"] * (1.0 + sizing["grad"] * d)
+        else:
+            h = _h_field(pts, dim, sizing, holes)
+        u = rng.random(len(pts))
+        acc = pts[u < (hlb[cell] / h) ** dim]
+        out.append(acc)
+        have += len(acc)
+    return np.concatenate(out, 0)[:n]
+
+
+def _build(name, dim, lo, hi, holes, sizing, params, n_total, seed, steps, res,
+           envelope_grid=0):
     lo = np.asarray(lo, float)
     hi = np.asarray(hi, float)
     holes = np.asarray(holes, float).reshape(-1, 15)
@@ -274,8 +489,11 @@ def _build(name, dim, lo, hi, holes, sizing, params, n_total, seed, steps, res):
         p[:, :dim] = lo[:dim] + rng.random((m, dim)) * (hi[:dim] - lo[:dim])
         return p
 
-    pv = _sample_rejection(rng, counts[0], box_prop, dim, sizing, holes, dim, hmin,
-                           accept_mask=lambda p: _inside(p, dim, lo, hi, holes))
+    if envelope_grid:
+        pv = _sample_volume_envelope(rng, counts[0], dim, lo, hi, sizing, holes, envelope_grid)
+    else:
+        pv = _sample_rejection(rng, counts[0], box_prop, dim, sizing, holes, dim, hmin,
+                               accept_mask=lambda p: _inside(p, dim, lo, hi, holes))
     xyz.append(pv); feat.append(np.zeros(len(pv), np.int32))
     f = 1
     for a in range(dim):
@@ -294,10 +512,19 @@ def _build(name, dim, lo, hi, holes, sizing, params, n_total, seed, steps, res):
         c, r = rec[:3], rec[3]
         k = dim - 1
 
-        def hole_prop(m, c=c, r=r):
+        def hole_prop(m, c=c, r=r, rec=rec):
             g = rng.standard_normal((m, dim))
             g /= np.linalg.norm(g, axis=1, keepdims=True)
             p = np.zeros((m, 3))
+            if _is_ellipsoid(rec, dim):
+                # u uniform on the sphere mapped to a u: thin by the measure
+                # factor |u / a| / max |u / a| = min(a) |u / a|
+                a = rec[3:3 + dim]
+                keep = rng.random(m) < a.min() * np.linalg.norm(g / a, axis=1)
+                g = g[keep]
+                p = p[:len(g)]
+                p[:, :dim] = c[:dim] + (a * g) @ rec[6:15].reshape(3, 3)[:dim, :dim]
+                return p
             p[:, :dim] = c[:dim] + r * g
             return p
 
@@ -414,6 +641,49 @@ def scaled_ball_3d(n_total, seed, centre=(0.5, 0.5, 0.5), radius=0.3, grad=4.0, 
                   dict(kind=H_GRADED_TO_HOLES, h0=4.745e-3, grad=grad, dcap=np.inf,
                        point=[0.0, 0.0, 0.0]),
                   default_params(**pover), n_total, seed, 0, res)
+
+
+def _inclusion_records(rng, dim, n_incl, cmin, cmax, amin, amax, gap):
+    """n_incl ellipsoids: centres uniform in [cmin, cmax]^dim, semi-axes
+    uniform in [amin, amax], uniform random rotation; a draw whose bounding
+    sphere comes closer than gap to an earlier one is redrawn"""
+    recs = []
+    tries = 0
+    while len(recs) < n_incl:
+        tries += 1
+        if tries > 100000:
+            raise ValueError("could not place the inclusions")
+        c = rng.uniform(cmin, cmax, dim)
+        a = rng.uniform(amin, amax, dim)
+        rot = _random_rotation(rng, dim)
+        if all(np.linalg.norm(c - q[:dim]) >= a.max() + q[3:3 + dim].max() + gap for q in recs):
+            cc = np.zeros(3)
+            cc[:dim] = c
+            recs.append(_ellipsoid_rec(cc, a, rot))
+    return recs
+
+
+def ellipsoid_inclusions(n_total=20_000_000, seed=5, dim=3, n_incl=16, ratio=20.0, ramp=0.25,
+                         cmin=0.15, cmax=0.85, amin=0.03, amax=0.10, gap=0.02, res=None,
+                         envelope_grid=None, steps=0, **pover):
+    """Unit box minus n_incl seeded ellipsoidal inclusions (centres
+    U[cmin, cmax]^dim with a bounding-sphere gap >= gap, semi-axes
+    U[amin, amax], uniform random rotations), h = h_min (1 + (ratio - 1)
+    min(1, d / ramp)) with d the distance to the nearest inclusion, h_min
+    solved for n_total.  Defaults: 16 ellipsoids in 3D, 20,000,000
+    particles, size ratio 1:20."""
+    rng = np.random.Generator(np.random.MT19937(seed))
+    recs = _inclusion_records(rng, dim, n_incl, cmin, cmax, amin, amax, gap)
+    if res is None:
+        res = 128 if dim == 3 else 1024
+    if envelope_grid is None:
+        envelope_grid = 128 if dim == 3 else 512
+    hi = [1.0, 1.0, 1.0 if dim == 3 else 0.0]
+    return _build(f"ellipsoids{dim}d", dim, [0, 0, 0], hi, recs,
+                  dict(kind=H_GRADED_TO_HOLES, h0=1e-3, grad=(ratio - 1.0) / ramp, dcap=ramp,
+                       point=[0.0, 0.0, 0.0]),
+                  default_params(**pover), n_total, int(rng.integers(1, 2**31 - 1)), steps, res,
+                  envelope_grid=envelope_grid)
 
 
 # ---------------------------------------------------------------------------

@@ -21,8 +21,15 @@ CASES = {
     "square64": lambda: wk.square_lattice(),
     "hole2d_20011": lambda: wk.scaled_hole_2d(20011, seed=21, res=512),
     "ball3d_30011": lambda: wk.scaled_ball_3d(30011, seed=22, res=96),
+    # six rotated ellipses, h ratio 1:20
+    "ell2d_20011": lambda: wk.ellipsoid_inclusions(n_total=20011, seed=23, dim=2, n_incl=6,
+                                                   res=256, envelope_grid=64),
+    # sixteen rotated ellipsoids (the 20M workload's layout), h ratio 1:4
+    "ell3d_30011": lambda: wk.ellipsoid_inclusions(n_total=30011, seed=24, dim=3, n_incl=16,
+                                                   ratio=4.0, res=32, envelope_grid=24),
 }
-KSTEPS = {"square64": 200, "hole2d_20011": 60, "ball3d_30011": 25}
+KSTEPS = {"square64": 200, "hole2d_20011": 60, "ball3d_30011": 25, "ell2d_20011": 60,
+          "ell3d_30011": 20}
 
 _wl_cache = {}
 
@@ -234,3 +241,74 @@ def test_full_size_cube_ball_2m_sampled(precision, tol):
         scale = np.abs(want).max()
         assert np.abs(got - want).max() <= tol * scale, (field, np.abs(got - want).max() / scale)
     assert g.counters()["steps"] == 1
+
+
+_c5 = {}
+
+
+def _ellipsoids_20m():
+    """the 20M-particle ellipsoid workload, its sampled particles and the
+    oracle's brute-force lists and sweep-A fields for them (built once)"""
+    if not _c5:
+        wl = wk.ellipsoid_inclusions()
+        idx = _sample_indices(wl, 120, seed=6)
+        _c5.update(wl=wl, idx=idx, ref=oracle.RefJob(wl).sample(idx))
+    return _c5["wl"], _c5["idx"], _c5["ref"]
+
+
+def _list_report(wl, g, idx, which, got, want):
+    """positions, h (both sides) and distances of the particles whose lists
+    differ, and of the ids only one side lists"""
+    L = oracle.lib()
+    geo = oracle.make_geometry(wl.dim, wl.lo, wl.hi, wl.holes)
+    siz = oracle.make_sizing(wl.sizing)
+    hg = g.field(binding.FIELD_H)
+    xg = g.positions()
+    lines = []
+    for t in which:
+        i = int(idx[t])
+        a = set(got[1][got[0][t]:got[0][t + 1]].tolist())
+        b = set(want[1][want[0][t]:want[0][t + 1]].tolist())
+        hi_r = L.sphref_h_at(geo, siz, np.ascontiguousarray(wl.xyz[i]))
+        lines.append(f"i={i} f={wl.feature[i]} h_gpu={hg[i]!r} h_ref={hi_r!r} "
+                     f"dx={np.abs(xg[i] - wl.xyz[i]).max():.3g}")
+        for tag, js in (("only_gpu", a - b), ("only_ref", b - a)):
+            for j in sorted(js)[:6]:
+                r = float(np.linalg.norm(wl.xyz[i] - wl.xyz[j]))
+                hj_r = L.sphref_h_at(geo, siz, np.ascontiguousarray(wl.xyz[j]))
+                lines.append(f"  {tag} j={j} f={wl.feature[j]} r={r!r} h_gpu={hg[j]!r} "
+                             f"h_ref={hj_r!r} r/2max_h={r / (2 * max(hi_r, hj_r))!r}")
+    return "\n".join(lines)
+
+
+@pytest.mark.timeout(400)
+@pytest.mark.parametrize("precision,tol,cfg", [
+    (binding.SPH_FP32_MIXED, 1e-5, {}),
+    (binding.SPH_FP64, 1e-12, {"cell_factor": 1.25, "scan_tile": 8})])
+def test_full_size_ellipsoids_20m_sampled(precision, tol, cfg):
+    """The 16-ellipsoid workload at full size (20,000,000 particles, h ratio
+    1:20): lists of sampled particles bit-exact and their first-step a^p, V~
+    and gamma against the oracle's brute force, in the default and in a
+    tuned launch configuration."""
+    wl, idx, (so, si, sr, ap_r, vt_r, gam_r) = _ellipsoids_20m()
+    g = binding.SphMesh(wl, precision=precision, use_graph=1, debug_fields=1, **cfg)
+    off, ids, rel = g.neighbors_of(idx)
+    bad = [t for t in range(len(idx)) if not np.array_equal(ids[off[t]:off[t + 1]],
+                                                             si[so[t]:so[t + 1]])]
+    assert not bad, _list_report(wl, g, idx, bad[:4], (off, ids), (so, si))
+    assert np.array_equal(off, so)
+    assert np.array_equal(ids, si) and np.array_equal(rel, sr)
+    # a rebuild from the re-hashed state gives the same lists (the job's cell
+    # counts are cleared in order with the hash that fills them)
+    off2, ids2, rel2 = g.neighbors_of(idx)
+    assert np.array_equal(off2, so) and np.array_equal(ids2, si) and np.array_equal(rel2, sr)
+    g.step(1)
+    moving = wl.ftype[wl.feature[idx]] != wk.SI
+    for field, ref_v in ((binding.FIELD_AP, ap_r), (binding.FIELD_VT, vt_r),
+                         (binding.FIELD_GAMMA, gam_r)):
+        got = g.field(field)[idx][moving]
+        want = ref_v[moving]
+        scale = np.abs(want).max()
+        assert np.abs(got - want).max() <= tol * scale, (field, np.abs(got - want).max() / scale)
+    assert g.counters()["steps"] == 1
+
