@@ -115,6 +115,12 @@ typedef struct {
   int32_t scan_tile;         /* candidate records tested per pass of the
                                 neighbour scan: 2, 4 or 8; 0 = 4.  Results do
                                 not depend on it (autotuning knob) */
+  int32_t cell_levels;       /* cell grids per band of h: level l holds the
+                                particles with h_min 2^l <= h < h_min 2^(l+1)
+                                on cells of side 2 h_min 2^l cell_factor.
+                                0 = one level per factor 2 when h_max > 4 h_min
+                                (else 1), 1 = a single grid, k <= 6 = at most
+                                k levels.  Lists do not depend on it */
   int32_t use_graph;         /* 1: steps replay a captured HIP graph */
   int32_t debug_fields;      /* 1: keep gamma, V~ and v~ for sph_mesh_field */
   void *stream;              /* hipStream_t to run on (e.g. PyTorch's current

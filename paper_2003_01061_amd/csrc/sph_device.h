@@ -67,11 +67,22 @@ struct Geom {
 // uniform cell grid over a job's box; its cells own the global cell ids
 // [cbase, cbase + ncell) of the batch; per-particle search radius
 // R_i = min(rfac h_i, rmax) (rfac from the Lipschitz bound of h_t)
+// A job's cells: nlev uniform grids over its box, one per band of h
+// (level l holds the particles with hthr[l] <= h < hthr[l+1], cell side
+// ~ 2 hthr[l] cell_factor), laid end to end from cbase (level l from
+// cbase + lbase[l]).  One level is the plain uniform grid.
+constexpr int MAXLEV = 6;
 struct Grid {
-  int32_t nc[3];
+  int32_t nlev;
   uint32_t ncell, cbase;
-  double lo[3], inv_c[3], c[3];
-  double rfac, rmax;
+  uint32_t lbase[MAXLEV];
+  int32_t nc[MAXLEV][3];
+  double lo[3];
+  double inv_c[MAXLEV][3], c[MAXLEV][3];
+  double hthr[MAXLEV];   // lower h bound of level l (hthr[0] = 0)
+  double hcap[MAXLEV];   // h of a level-l particle is below hcap[l] (the last: <= h_max)
+  double cmax;           // largest cell side over the levels
+  double rfac, rmax, lip;
 };
 
 struct Ctl {
@@ -358,12 +369,19 @@ __device__ __forceinline__ int xcd_block() {
 #endif
 }
 
-__device__ __forceinline__ int cell_coord(const Grid &G, int a, double p) {
-  double t = __builtin_floor((p - G.lo[a]) * G.inv_c[a]);
+__device__ __forceinline__ int cell_coord(const Grid &G, int l, int a, double p) {
+  double t = __builtin_floor((p - G.lo[a]) * G.inv_c[l][a]);
   t = t >= 0.0 ? t : 0.0;   // also maps NaN to cell 0
-  double top = (double)(G.nc[a] - 1);
+  double top = (double)(G.nc[l][a] - 1);
   t = t > top ? top : t;
   return (int)t;
+}
+
+// cell level of smoothing length h (thresholds ascending; NaN -> level 0)
+__device__ __forceinline__ int h_level(const Grid &G, double h) {
+  int l = 0;
+  for (int q = 1; q < G.nlev; ++q) l += h >= G.hthr[q] ? 1 : 0;
+  return l;
 }
 
 // ---------------------------------------------------------------------------

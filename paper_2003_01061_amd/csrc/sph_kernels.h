@@ -111,10 +111,12 @@ template <int D>
 __device__ __forceinline__ void hash_one(const Geom &g, const Grid &G, double4 &xh, uint32_t &cell) {
   double p[3] = {xh.x, xh.y, xh.z};
   xh.w = h_target<D>(g, p);
-  int c0 = cell_coord(G, 0, p[0]);
-  int c1 = cell_coord(G, 1, p[1]);
-  int c2 = D == 3 ? cell_coord(G, 2, p[2]) : 0;
-  cell = G.cbase + ((uint32_t)c2 * (uint32_t)G.nc[1] + (uint32_t)c1) * (uint32_t)G.nc[0] + (uint32_t)c0;
+  const int l = h_level(G, xh.w);
+  int c0 = cell_coord(G, l, 0, p[0]);
+  int c1 = cell_coord(G, l, 1, p[1]);
+  int c2 = D == 3 ? cell_coord(G, l, 2, p[2]) : 0;
+  cell = G.cbase + G.lbase[l] +
+         ((uint32_t)c2 * (uint32_t)G.nc[l][1] + (uint32_t)c1) * (uint32_t)G.nc[l][0] + (uint32_t)c0;
 }
 
 // Rank of a particle inside its cell.  Lanes of a wave that hold the same
@@ -470,20 +472,15 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
       const Grid &G = J.G;
       double Rs = G.rfac * xi.w;
       Rs = Rs < G.rmax ? Rs : G.rmax;
-      const double R2 = Rs * Rs;
       const double pc[3] = {xi.x, xi.y, xi.z};
-      int lo_c[3] = {0, 0, 0}, hi_c[3] = {0, 0, 0};
-#pragma unroll
-      for (int a = 1; a < D; ++a) {
-        lo_c[a] = cell_coord(G, a, pc[a] - Rs);
-        hi_c[a] = cell_coord(G, a, pc[a] + Rs);
+      // cell levels that can hold a neighbour: h is L-Lipschitz, so a
+      // neighbour (r < R_i) has |h_j - h_i| <= L R_i (widened for rounding)
+      int lv0 = 0, lv1 = G.nlev - 1;
+      if (G.nlev > 1) {
+        const double dh = G.lip * Rs * (1.0 + 1e-9);
+        lv0 = h_level(G, (xi.w - dh) * (1.0 - 1e-12));
+        lv1 = h_level(G, (xi.w + dh) * (1.0 + 1e-12));
       }
-      // grid values the row loop needs, kept in registers
-      const double c0 = G.c[0], inv0 = G.inv_c[0], lo1 = G.lo[1], c1 = G.c[1];
-      const double lo2 = D == 3 ? G.lo[2] : 0.0, c2 = D == 3 ? G.c[2] : 0.0;
-      const uint32_t nc0 = (uint32_t)G.nc[0], nc1 = (uint32_t)G.nc[1], cbase = G.cbase;
-      const double u0 = (pc[0] - G.lo[0]) * inv0;     // x of i in cell units
-      const double top0 = (double)(G.nc[0] - 1);
       // features that bound fi (bit = local feature id); a candidate of fi's
       // own feature interacts as "same", one of a bounding feature of the same
       // job as "boundary".  The scan only visits cells of i's own job, so a
@@ -506,8 +503,8 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
       const float hif = D == 2 ? xif.z : xif.w;
       float Mf;
       {
-        double xb = 0.0, cm = c0 > c1 ? c0 : c1;
-        if (D == 3) cm = cm > c2 ? cm : c2;
+        double xb = 0.0;
+        const double cm = G.cmax;
 #pragma unroll
         for (int a = 0; a < D; ++a) {
           const double l = __builtin_fabs(J.g.lo[a]), h = __builtin_fabs(J.g.hi[a]);
@@ -527,77 +524,97 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
       uint32_t lbuf[LB];
 #pragma unroll
       for (int q = 0; q < LB; ++q) lbuf[q] = 0u;
-      for (int cz = lo_c[2]; cz <= hi_c[2]; ++cz) {
-        double dz2 = 0.0;
-        if (D == 3) {
-          const double z0 = lo2 + cz * c2;
-          double dz = z0 - pc[2] > pc[2] - (z0 + c2) ? z0 - pc[2] : pc[2] - (z0 + c2);
-          dz = dz - 1e-7 * c2;
-          dz = dz > 0.0 ? dz : 0.0;
-          dz2 = dz * dz;
+      for (int lv = lv0; lv <= lv1; ++lv) {
+        // a level-lv candidate has h_j < hcap[lv], so none beyond
+        // 2 max(h_i, hcap[lv]) is a neighbour
+        double Rl = 2.0 * (xi.w > G.hcap[lv] ? xi.w : G.hcap[lv]) * (1.0 + 1e-9);
+        Rl = Rl < Rs ? Rl : Rs;
+        const double R2 = Rl * Rl;
+        int lo_c[3] = {0, 0, 0}, hi_c[3] = {0, 0, 0};
+#pragma unroll
+        for (int a = 1; a < D; ++a) {
+          lo_c[a] = cell_coord(G, lv, a, pc[a] - Rl);
+          hi_c[a] = cell_coord(G, lv, a, pc[a] + Rl);
         }
-        for (int cy = lo_c[1]; cy <= hi_c[1]; ++cy) {
-          const double y0 = lo1 + cy * c1;
-          double dy = y0 - pc[1] > pc[1] - (y0 + c1) ? y0 - pc[1] : pc[1] - (y0 + c1);
-          dy = dy - 1e-7 * c1;
-          dy = dy > 0.0 ? dy : 0.0;
-          const double w2 = R2 - dy * dy - dz2;
-          if (w2 < 0.0) continue;
-          // half chord of the row; the FP32 square root (error < 2e-7
-          // relative) is covered by the 1e-6 relative widening
-          const double wx = (double)sqrt_((float)w2) * (1.0 + 1e-6) + 1e-7 * c0;
-          const double wu = wx * inv0;
-          double t0 = __builtin_floor(u0 - wu), t1 = __builtin_floor(u0 + wu);
-          t0 = t0 >= 0.0 ? t0 : 0.0;   // also maps NaN to cell 0
-          t1 = t1 >= 0.0 ? t1 : 0.0;
-          t0 = t0 < top0 ? t0 : top0;
-          t1 = t1 < top0 ? t1 : top0;
-          const uint32_t row = cbase + ((uint32_t)cz * nc1 + (uint32_t)cy) * nc0;
-          const uint32_t jb = cstart[row + (uint32_t)t0], je = cstart[row + (uint32_t)t1 + 1];
-          // NB candidates per pass: records loaded together (the arrays are
-          // padded by 8 past the capacity), the predicate evaluated for all of
-          // them without early exits, then the hits appended in order
-          for (uint32_t j0 = jb; j0 < je; j0 += NB) {
-            const float4 *rp = s.xf + j0;
-            float4 xr[NB];
-            uint32_t fr[NB];   // job-local feature id of the candidate
-#pragma unroll
-            for (int q = 0; q < NB; ++q) {
-              xr[q] = rp[q];
-              fr[q] = __float_as_uint(xr[q].w) & (MAXF - 1);
-            }
-            uint32_t tag[NB];
-#pragma unroll
-            for (int q = 0; q < NB; ++q) {
-              const uint32_t j = j0 + q;
-              const bool rel = (accept >> (fr[q] & (MAXF - 1))) & 1ull;
-              const bool cand = rel & (j < je) & (j != (uint32_t)i);
-              const float dx = xif.x - xr[q].x, dy = xif.y - xr[q].y;
-              const float dz = D == 3 ? xif.z - xr[q].z : 0.0f;
-              const float d2 = dx * dx + dy * dy + dz * dz;
-              const float hj = D == 2 ? xr[q].z : xr[q].w;
-              const float H = 2.0f * (hif > hj ? hif : hj);
-              constexpr float band = D == 2 ? 2e-6f : 2e-5f;
-              float tin = H * (1.0f - band) - Mf;
-              tin = tin > 0.0f ? tin * tin : -1.0f;
-              const float tout = (H * (1.0f + band) + Mf) * (H * (1.0f + band) + Mf);
-              bool hit = cand & (d2 < tin);
-              if (cand & !(d2 < tin) & !(d2 > tout))   // near the support radius: exact test
-                hit = within_a4<D>(xi, A4, s.xh[j]);
-              tag[q] = hit ? (j | (fr[q] == (uint32_t)(fi & (MAXF - 1)) ? 0u : 0x80000000u))
-                           : 0xffffffffu;
-            }
-#pragma unroll
-            for (int q = 0; q < NB; ++q) {
-              if (tag[q] != 0xffffffffu) {
-                const uint32_t k = count % LB;
-#pragma unroll
-                for (int t = 0; t < LB; ++t) lbuf[t] = (uint32_t)t == k ? tag[q] : lbuf[t];
-                ++count;
-                if (k == LB - 1 && count / LB <= nblk) {
-                  wp[0] = make_uint4(lbuf[0], lbuf[1], lbuf[2], lbuf[3]);
-                  wp[1] = make_uint4(lbuf[4], lbuf[5], lbuf[6], lbuf[7]);
-                  wp += wstep;
+        // grid values the row loop needs, kept in registers
+        const double c0 = G.c[lv][0], inv0 = G.inv_c[lv][0], lo1 = G.lo[1], c1 = G.c[lv][1];
+        const double lo2 = D == 3 ? G.lo[2] : 0.0, c2 = D == 3 ? G.c[lv][2] : 0.0;
+        const uint32_t nc0 = (uint32_t)G.nc[lv][0], nc1 = (uint32_t)G.nc[lv][1];
+        const uint32_t cbase = G.cbase + G.lbase[lv];
+        const double u0 = (pc[0] - G.lo[0]) * inv0;     // x of i in cell units
+        const double top0 = (double)(G.nc[lv][0] - 1);
+        for (int cz = lo_c[2]; cz <= hi_c[2]; ++cz) {
+          double dz2 = 0.0;
+          if (D == 3) {
+            const double z0 = lo2 + cz * c2;
+            double dz = z0 - pc[2] > pc[2] - (z0 + c2) ? z0 - pc[2] : pc[2] - (z0 + c2);
+            dz = dz - 1e-7 * c2;
+            dz = dz > 0.0 ? dz : 0.0;
+            dz2 = dz * dz;
+          }
+          for (int cy = lo_c[1]; cy <= hi_c[1]; ++cy) {
+            const double y0 = lo1 + cy * c1;
+            double dy = y0 - pc[1] > pc[1] - (y0 + c1) ? y0 - pc[1] : pc[1] - (y0 + c1);
+            dy = dy - 1e-7 * c1;
+            dy = dy > 0.0 ? dy : 0.0;
+            const double w2 = R2 - dy * dy - dz2;
+            if (w2 < 0.0) continue;
+            // half chord of the row; the FP32 square root (error < 2e-7
+            // relative) is covered by the 1e-6 relative widening
+            const double wx = (double)sqrt_((float)w2) * (1.0 + 1e-6) + 1e-7 * c0;
+            const double wu = wx * inv0;
+            double t0 = __builtin_floor(u0 - wu), t1 = __builtin_floor(u0 + wu);
+            t0 = t0 >= 0.0 ? t0 : 0.0;   // also maps NaN to cell 0
+            t1 = t1 >= 0.0 ? t1 : 0.0;
+            t0 = t0 < top0 ? t0 : top0;
+            t1 = t1 < top0 ? t1 : top0;
+            const uint32_t row = cbase + ((uint32_t)cz * nc1 + (uint32_t)cy) * nc0;
+            const uint32_t jb = cstart[row + (uint32_t)t0], je = cstart[row + (uint32_t)t1 + 1];
+            // NB candidates per pass: records loaded together (the arrays are
+            // padded by 8 past the capacity), the predicate evaluated for all of
+            // them without early exits, then the hits appended in order
+            for (uint32_t j0 = jb; j0 < je; j0 += NB) {
+              const float4 *rp = s.xf + j0;
+              float4 xr[NB];
+              uint32_t fr[NB];   // job-local feature id of the candidate
+  #pragma unroll
+              for (int q = 0; q < NB; ++q) {
+                xr[q] = rp[q];
+                fr[q] = __float_as_uint(xr[q].w) & (MAXF - 1);
+              }
+              uint32_t tag[NB];
+  #pragma unroll
+              for (int q = 0; q < NB; ++q) {
+                const uint32_t j = j0 + q;
+                const bool rel = (accept >> (fr[q] & (MAXF - 1))) & 1ull;
+                const bool cand = rel & (j < je) & (j != (uint32_t)i);
+                const float dx = xif.x - xr[q].x, dy = xif.y - xr[q].y;
+                const float dz = D == 3 ? xif.z - xr[q].z : 0.0f;
+                const float d2 = dx * dx + dy * dy + dz * dz;
+                const float hj = D == 2 ? xr[q].z : xr[q].w;
+                const float H = 2.0f * (hif > hj ? hif : hj);
+                constexpr float band = D == 2 ? 2e-6f : 2e-5f;
+                float tin = H * (1.0f - band) - Mf;
+                tin = tin > 0.0f ? tin * tin : -1.0f;
+                const float tout = (H * (1.0f + band) + Mf) * (H * (1.0f + band) + Mf);
+                bool hit = cand & (d2 < tin);
+                if (cand & !(d2 < tin) & !(d2 > tout))   // near the support radius: exact test
+                  hit = within_a4<D>(xi, A4, s.xh[j]);
+                tag[q] = hit ? (j | (fr[q] == (uint32_t)(fi & (MAXF - 1)) ? 0u : 0x80000000u))
+                             : 0xffffffffu;
+              }
+  #pragma unroll
+              for (int q = 0; q < NB; ++q) {
+                if (tag[q] != 0xffffffffu) {
+                  const uint32_t k = count % LB;
+  #pragma unroll
+                  for (int t = 0; t < LB; ++t) lbuf[t] = (uint32_t)t == k ? tag[q] : lbuf[t];
+                  ++count;
+                  if (k == LB - 1 && count / LB <= nblk) {
+                    wp[0] = make_uint4(lbuf[0], lbuf[1], lbuf[2], lbuf[3]);
+                    wp[1] = make_uint4(lbuf[4], lbuf[5], lbuf[6], lbuf[7]);
+                    wp += wstep;
+                  }
                 }
               }
             }

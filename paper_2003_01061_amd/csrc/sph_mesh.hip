@@ -201,6 +201,8 @@ static sph_status validate(const sph_geometry *g, const sph_sizing *s, const sph
         return fail(SPH_ERR_INVALID_ARG, "hole %d must lie strictly inside the box", q);
   }
   if (s->kind < 0 || s->kind > 2) return fail(SPH_ERR_INVALID_ARG, "unknown sizing kind");
+  if (p->cell_levels < 0 || p->cell_levels > MAXLEV)
+    return fail(SPH_ERR_INVALID_ARG, "cell_levels must be in [0, %d]", MAXLEV);
   if (!(s->h0 > 0) || !(s->grad >= 0) || !std::isfinite(s->h0) || !std::isfinite(s->grad))
     return fail(SPH_ERR_INVALID_ARG, "sizing needs h0 > 0 and grad >= 0");
   if (s->kind == 2 && g->n_holes == 0 && !std::isfinite(s->dcap))
@@ -546,33 +548,62 @@ struct sph_batch {
 // ---------------------------------------------------------------------------
 // job description -> host job record
 // ---------------------------------------------------------------------------
+// Number of cell levels of a job: one per factor 2 of h when h spans more
+// than a factor 4 (cell_levels = 0), capped by cell_levels and MAXLEV.
+static int level_count(double hmin, double hmax, int want) {
+  if (want == 1 || !(hmax > 4.0 * hmin)) return 1;
+  int nl = (int)std::ceil(std::log2(hmax / hmin));
+  return std::max(1, std::min(nl, want > 0 ? want : MAXLEV));
+}
+
 static void grid_of(const sph_geometry *g, const sph_sizing *s, const sph_params *p, Grid &Gr) {
   const int D = g->dim;
   double hmin, hmax, lip;
   sizing_bounds(g, s, hmin, hmax, lip);
   const double cf = p->cell_factor > 0 ? p->cell_factor : 1.0;
-  double side = 2.0 * hmin * cf;
+  const int nlev = level_count(hmin, hmax, p->cell_levels);
+  // level l: h in [hmin 2^l, hmin 2^(l+1)), cell side 2 hmin 2^l cell_factor
+  double scale = 1.0;
+  auto cells_at = [&](int l, int a) {
+    const double side = 2.0 * std::ldexp(hmin, l) * cf * scale;
+    return std::max(1.0, std::floor((g->hi[a] - g->lo[a]) / side));
+  };
   for (;;) {
-    double cells = 1.0;
-    for (int a = 0; a < D; ++a) cells *= std::max(1.0, std::floor((g->hi[a] - g->lo[a]) / side));
+    double cells = 0.0;
+    for (int l = 0; l < nlev; ++l) {
+      double c = 1.0;
+      for (int a = 0; a < D; ++a) c *= cells_at(l, a);
+      cells += c;
+    }
     if (cells <= 512.0 * 1024 * 1024) break;   // at most 2^29 cells per job
-    side *= 1.25;
+    scale *= 1.25;
   }
   std::memset(&Gr, 0, sizeof Gr);
-  Gr.ncell = 1;
-  for (int a = 0; a < 3; ++a) {
-    Gr.lo[a] = g->lo[a];
-    if (a < D) {
-      Gr.nc[a] = (int)std::max(1.0, std::floor((g->hi[a] - g->lo[a]) / side));
-      Gr.inv_c[a] = Gr.nc[a] / (g->hi[a] - g->lo[a]);
-      Gr.c[a] = (g->hi[a] - g->lo[a]) / Gr.nc[a];
-    } else {
-      Gr.nc[a] = 1;
+  Gr.nlev = nlev;
+  for (int a = 0; a < 3; ++a) Gr.lo[a] = g->lo[a];
+  uint32_t total = 0;
+  for (int l = 0; l < nlev; ++l) {
+    Gr.lbase[l] = total;
+    uint32_t nl = 1;
+    for (int a = 0; a < 3; ++a) {
+      if (a < D) {
+        Gr.nc[l][a] = (int)cells_at(l, a);
+        Gr.inv_c[l][a] = Gr.nc[l][a] / (g->hi[a] - g->lo[a]);
+        Gr.c[l][a] = (g->hi[a] - g->lo[a]) / Gr.nc[l][a];
+        Gr.cmax = std::max(Gr.cmax, Gr.c[l][a]);
+      } else {
+        Gr.nc[l][a] = 1;
+      }
+      nl *= (uint32_t)Gr.nc[l][a];
     }
-    Gr.ncell *= (uint32_t)Gr.nc[a];
+    total += nl;
+    Gr.hthr[l] = l == 0 ? 0.0 : std::ldexp(hmin, l);
+    Gr.hcap[l] = l + 1 < nlev ? std::ldexp(hmin, l + 1) : hmax;
   }
+  Gr.ncell = total;
   Gr.rmax = 2.0 * hmax * (1.0 + 1e-9);
   Gr.rfac = 2.0 * lip < 0.9 ? 2.0 * (1.0 + 1e-9) / (1.0 - 2.0 * lip) : 1e300;
+  Gr.lip = lip;
 }
 
 static void fill_job(HostJob &J, const sph_geometry *g, const sph_sizing *s, const sph_params *p,

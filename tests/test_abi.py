@@ -78,3 +78,25 @@ def test_batch_footprint_and_job_cells_are_host_logic():
     assert binding.JobSpec(wl, cell_factor=0.5).cells() == 64 * 64
     bad = dict(wl.params, window_samples=0)
     assert binding.JobSpec(wl, params=bad).cells() == -1
+
+
+def test_cell_levels_follow_the_range_of_h():
+    """A job whose h spans more than a factor 4 gets one cell grid per factor
+    2 of h (level l on cells of side 2 h_min 2^l); cell_levels = 1 keeps a
+    single grid and k caps the count.  Host logic, no GPU."""
+    from paper_2003_01061_amd import binding
+    from paper_2003_01061_amd import workload as wk
+    wl = wk.ellipsoid_inclusions(n_total=20011, seed=23, dim=2, n_incl=6, res=128,
+                                 envelope_grid=32)
+    hmin = wl.sizing["h0"]
+    hmax = hmin * (1 + wl.sizing["grad"] * wl.sizing["dcap"])        # ratio 20: 5 levels
+    side = [2 * hmin * 2 ** l for l in range(5)]
+    per = [int(1.0 // s) ** 2 for s in side]
+    assert binding.JobSpec(wl, cell_levels=1).cells() == per[0]
+    assert binding.JobSpec(wl).cells() == sum(per)
+    assert binding.JobSpec(wl, cell_levels=3).cells() == sum(per[:3])
+    assert binding.JobSpec(wl, cell_levels=7).cells() == -1
+    assert hmax / hmin > 16
+    # h within a factor 4: one grid whatever the setting
+    sq = wk.square_hole(n_total=20000, res=128)
+    assert binding.JobSpec(sq).cells() == binding.JobSpec(sq, cell_levels=1).cells()
