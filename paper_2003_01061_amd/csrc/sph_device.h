@@ -147,9 +147,12 @@ struct Batch {
   unsigned int *gflags;               // [0] a scan tile gave up waiting (never expected)
   unsigned long long *smin, *ssum;    // [MAXJ * MAXF][NSTRIPE] group minima / sums
   unsigned long long *scnt, *sesc;    // [MAXJ][NSTRIPE] interactions / rejected moves
+  double4 *enrm;                      // [n] cell order: for a particle on a hole's
+                                      // boundary, the normal out of the domain (k_rank_gather)
   int n, cap;
   uint32_t ncell, ntiles;
   int njobs;                          // job slots in use: [0, njobs)
+  int has_hole;                       // some resident job has a hole
 };
 
 template <typename R>

@@ -7,7 +7,8 @@
 //                    look-back) -> cell start table
 //   k_scatter        position of every particle in cell order
 //   k_rank_gather    order inside a cell by caller id (canonical, history
-//                    free) and permute the particle records into it
+//                    free), permute the particle records into it, and store
+//                    the boundary normals of particles on holes
 //   k_nbr_forces     ELL neighbour list (exact FP64 predicate + feature
 //                    relation) fused with the Shepard gamma, V~, pressure
 //                    force with the boundary term and its tangent projection
@@ -314,7 +315,7 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(int n, const uint32_t *__rest
 // caller ids and copies its particle to that slot; the first entry of a cell
 // clears the cell's count for the next hash.
 template <int D>
-__global__ __launch_bounds__(BLOCK) void k_rank_gather(int n, const uint32_t *__restrict__ psrc,
+__global__ __launch_bounds__(BLOCK) void k_rank_gather(Batch B, int n, const uint32_t *__restrict__ psrc,
                                                        const uint32_t *__restrict__ pkey,
                                                        const uint32_t *__restrict__ cell,
                                                        const uint32_t *__restrict__ cstart,
@@ -339,6 +340,29 @@ __global__ __launch_bounds__(BLOCK) void k_rank_gather(int n, const uint32_t *__
   b.f[dst] = (uint16_t)f;
   b.oid[dst] = key;
   b.xf[dst] = scan_record<D>(xh, f);
+  // the normal out of the domain of a particle on a hole's boundary, for the
+  // sweep that follows (computed there, it would hold registers inside the
+  // neighbour loop): towards the centre of a disc or ball, against the level
+  // set's gradient for an ellipse or ellipsoid
+  if (B.has_hole) {
+    const Feat F = B.feat[f];
+    if (F.kind == K_HOLE) {
+      const Geom &g = B.jobs[f / MAXF].g;
+      double4 e;
+      if (g.hell[F.hole]) {
+        const double x[3] = {xh.x, xh.y, xh.z};
+        double m[3] = {0.0, 0.0, 0.0};
+        ell_normal<D>(g, F.hole, x, m);
+        e = make_double4(-m[0], -m[1], -m[2], 0.0);
+      } else {
+        const double *cc = g.hc[F.hole];
+        const double d0 = cc[0] - xh.x, d1 = cc[1] - xh.y, d2 = D == 3 ? cc[2] - xh.z : 0.0;
+        const double il = 1.0 / __builtin_sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+        e = make_double4(d0 * il, d1 * il, d2 * il, 0.0);
+      }
+      B.enrm[dst] = e;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -350,6 +374,7 @@ __global__ __launch_bounds__(BLOCK) void k_rank_gather(int n, const uint32_t *__
 // ---------------------------------------------------------------------------
 template <int D, int K, typename R>
 __device__ __forceinline__ void sweep_a_sums(const Geom &g, const Parts &s,
+                                             const double4 *__restrict__ enrm,
                                              const BNorm *__restrict__ bnrow, int bw, double p0,
                                              const uint32_t *__restrict__ nbr, int n, int i,
                                              uint32_t cnt, const double4 &xi, int fi, double &S,
@@ -406,20 +431,11 @@ __device__ __forceinline__ void sweep_a_sums(const Geom &g, const Parts &s,
           const int fj = s.f[u[q] & 0x7fffffffu];
           const BNorm N = bnrow[fj & (MAXF - 1)];
           double nv[3];
-          if (N.mode == 2) {
-            const double *cc = g.hc[N.hole];
-            const double d0 = cc[0] - xj.x, d1 = cc[1] - xj.y, d2 = D == 3 ? cc[2] - xj.z : 0.0;
-            const double il = 1.0 / __builtin_sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-            nv[0] = d0 * il;
-            nv[1] = d1 * il;
-            nv[2] = d2 * il;
-          } else if (N.mode == 3) {   // ellipsoidal hole: against its level set's normal
-            const double xb[3] = {xj.x, xj.y, xj.z};
-            double m[3] = {0.0, 0.0, 0.0};
-            ell_normal<D>(g, N.hole, xb, m);
-            nv[0] = -m[0];
-            nv[1] = -m[1];
-            nv[2] = -m[2];
+          if (N.mode >= 2) {   // a hole's boundary: the normal k_rank_gather stored
+            const double4 e = enrm[u[q] & 0x7fffffffu];
+            nv[0] = e.x;
+            nv[1] = e.y;
+            nv[2] = e.z;
           } else {
             nv[0] = N.n[0];
             nv[1] = N.n[1];
@@ -641,11 +657,11 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
       const BNorm *bnrow = B.bn + (size_t)fi * MAXF;
       double S, gam, Pi[3], B3[3];
       if (k == D)
-        sweep_a_sums<D, D, R>(J.g, s, bnrow, J.bw, J.p0, nbr, n, i, count, xi, fi, S, gam, Pi, B3);
+        sweep_a_sums<D, D, R>(J.g, s, B.enrm, bnrow, J.bw, J.p0, nbr, n, i, count, xi, fi, S, gam, Pi, B3);
       else if (k == D - 1)
-        sweep_a_sums<D, D - 1, R>(J.g, s, bnrow, J.bw, J.p0, nbr, n, i, count, xi, fi, S, gam, Pi, B3);
+        sweep_a_sums<D, D - 1, R>(J.g, s, B.enrm, bnrow, J.bw, J.p0, nbr, n, i, count, xi, fi, S, gam, Pi, B3);
       else
-        sweep_a_sums<D, 1, R>(J.g, s, bnrow, J.bw, J.p0, nbr, n, i, count, xi, fi, S, gam, Pi, B3);
+        sweep_a_sums<D, 1, R>(J.g, s, B.enrm, bnrow, J.bw, J.p0, nbr, n, i, count, xi, fi, S, gam, Pi, B3);
       double a3[3] = {0.0, 0.0, 0.0};
 #pragma unroll
       for (int a = 0; a < D; ++a) a3[a] = -((Pi[a] + B3[a]) / gam);

@@ -308,6 +308,7 @@ struct sph_batch {
   unsigned long long *scan_status = nullptr;
   uint32_t *nbr = nullptr, *nnb = nullptr;
   void *ap = nullptr, *acc = nullptr, *mid = nullptr;              // {ax, ay, az, 0} in the sweep precision
+  double4 *enrm = nullptr;   // boundary normals of particles on holes (cell order)
   double *dbg_gam = nullptr, *dbg_vt = nullptr;
   double4 *dbg_vm = nullptr;
   JobDev *d_jobs = nullptr;
@@ -363,6 +364,11 @@ struct sph_batch {
     B.ncell = ncell;
     B.ntiles = ntiles();
     B.njobs = njobs;
+    B.enrm = enrm;
+    B.has_hole = 0;
+    for (int j = 0; j < njobs; ++j)
+      if (jobs[j].live)
+        for (const HFeat &F : jobs[j].feats) B.has_hole |= F.kind == K_HOLE;
     return B;
   }
   uint32_t ntiles() const { return (ncell + SCAN_TILE - 1) / SCAN_TILE; }
@@ -420,11 +426,11 @@ struct sph_batch {
                   (const uint32_t *)rank, (const uint32_t *)cstart, (const uint32_t *)P[cur].oid,
                   psrc, pkey, scan_status, B.ntiles, ticket));
     if (D == 2)
-      HIPCHK(launch(KID_RANK_GATHER, k_rank_gather<2>, blocks(n), BLOCK, n, (const uint32_t *)psrc,
+      HIPCHK(launch(KID_RANK_GATHER, k_rank_gather<2>, blocks(n), BLOCK, B, n, (const uint32_t *)psrc,
                     (const uint32_t *)pkey, (const uint32_t *)cell, (const uint32_t *)cstart, cnt,
                     P[cur], P[1 - cur]));
     else
-      HIPCHK(launch(KID_RANK_GATHER, k_rank_gather<3>, blocks(n), BLOCK, n, (const uint32_t *)psrc,
+      HIPCHK(launch(KID_RANK_GATHER, k_rank_gather<3>, blocks(n), BLOCK, B, n, (const uint32_t *)psrc,
                     (const uint32_t *)pkey, (const uint32_t *)cell, (const uint32_t *)cstart, cnt,
                     P[cur], P[1 - cur]));
     cur = 1 - cur;
@@ -699,6 +705,7 @@ extern "C" int64_t sph_batch_footprint(const sph_batch_params *bp) {
   b += C * 4 + (C + 1) * 4 + ((C + SCAN_TILE - 1) / SCAN_TILE) * 8;
   b += N * cap * 4 + N * 4;                           // neighbour list + counts
   b += (bp->dim == 3 ? 3 : 2) * N * r4;               // a^p, a (and 3D mid-point records)
+  b += N * 32;                                        // normals of particles on holes
   if (bp->debug_fields) b += N * (8 + 8 + 32);
   const int64_t slots = (int64_t)bp->max_jobs * MAXF;
   b += bp->max_jobs * (int64_t)sizeof(JobDev) + slots * (int64_t)(sizeof(Feat) + 8 + sizeof(Group)) +
@@ -774,6 +781,7 @@ extern "C" sph_status sph_batch_create(const sph_batch_params *bp, sph_batch **o
   B->ap = dalloc<char>(N * r4, ow, by);
   B->acc = dalloc<char>(N * r4, ow, by);
   if (B->D == 3) B->mid = dalloc<char>(N * r4, ow, by);   // mid-point records (3D sweep B)
+  B->enrm = dalloc<double4>(N, ow, by);
   if (B->debug) {
     B->dbg_gam = dalloc<double>(N, ow, by);
     B->dbg_vt = dalloc<double>(N, ow, by);
@@ -792,7 +800,7 @@ extern "C" sph_status sph_batch_create(const sph_batch_params *bp, sph_batch **o
   B->scnt = dalloc<unsigned long long>((size_t)B->jcap * NSTRIPE, ow, by);
   B->sesc = dalloc<unsigned long long>((size_t)B->jcap * NSTRIPE, ow, by);
   ok = ok && B->cell && B->rank && B->psrc && B->pkey && B->cnt && B->cstart && B->scan_status &&
-       B->ticket && B->nbr && B->nnb && B->ap && B->acc && (B->mid || B->D == 2) && B->d_jobs && B->d_feat && B->d_bmask &&
+       B->ticket && B->nbr && B->nnb && B->ap && B->acc && (B->mid || B->D == 2) && B->enrm && B->d_jobs && B->d_feat && B->d_bmask &&
        B->d_bn && B->d_grp && B->d_st && B->d_gflags && B->smin && B->ssum && B->scnt && B->sesc;
   if (!ok) {
     delete B;
