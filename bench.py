@@ -12,8 +12,8 @@ the last step; creation and the host copy of the result are outside it.
 
 interactions = neighbour-list entries of every moving particle, once per step.
 
-Prints one JSON line (see the design doc for the roofline bytes and the CPU
-baseline sample).
+Prints one JSON line, with the roofline of the dominant kernel and the CPU
+oracle baseline on a bounded sample.
 """
 from __future__ import annotations
 
@@ -125,14 +125,17 @@ def profile_kernels(wl, precision, steps, cfg=None):
 
 
 def quality(wl, x):
-    """Proxy of converged mesh quality: nearest-neighbour distance / h_t."""
+    """Converged mesh quality: the Delaunay mesh of the final positions with
+    the paper's triangle measures, and nearest-neighbour distance / h_t."""
     from scipy.spatial import cKDTree
+    from paper_2003_01061_amd import quality as mq
     from paper_2003_01061_amd.workload import _h_field
     pts = x[:, :wl.dim]
     d, _ = cKDTree(pts).query(pts, k=2)
     h = _h_field(x, wl.dim, wl.sizing, wl.holes)
     r = d[:, 1] / h
-    return dict(nn_over_h_mean=float(r.mean()), nn_over_h_p1=float(np.percentile(r, 1)),
+    return dict(mesh=mq.mesh_quality(x, wl.dim, wl.lo, wl.hi, wl.holes),
+                nn_over_h_mean=float(r.mean()), nn_over_h_p1=float(np.percentile(r, 1)),
                 nn_over_h_min=float(r.min()))
 
 
@@ -199,11 +202,14 @@ def ellipsoid_run(args):
     byts = kernel_bytes("nbr_forces", wl, n_active, inter_step, 4)
     avg_s = per["nbr_forces"][0] * 1e-3
     from scipy.spatial import cKDTree
+    from paper_2003_01061_amd import quality as mq
     from paper_2003_01061_amd.workload import _h_field
     rng = np.random.default_rng(0)
     q = rng.choice(wl.n, 200_000, replace=False)
     d, _ = cKDTree(x).query(x[q], k=2)
     r = d[:, 1] / _h_field(x[q], 3, wl.sizing, wl.holes)
+    region = ([0.45, 0.45, 0.45], [0.55, 0.55, 0.55])
+    mesh = mq.mesh_quality(x, 3, wl.lo, wl.hi, wl.holes, region=region)
     out = {
         "metric": "particle-neighbour interactions/s per step, run to the converged mesh",
         "value": c["interactions"] / sec, "unit": "interactions/s", "n_gpus": 1,
@@ -216,7 +222,8 @@ def ellipsoid_run(args):
         "autotune": tuned,
         "escaped": c["escaped"],
         "quality_sample": {"particles": int(len(q)), "nn_over_h_mean": float(r.mean()),
-                           "nn_over_h_p1": float(np.percentile(r, 1))},
+                           "nn_over_h_p1": float(np.percentile(r, 1)),
+                           "mesh_region": region, "mesh": mesh},
         "roofline": {"bound": "hbm", "kernel": "nbr_forces", "achieved": byts / avg_s / 1e9,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": byts / avg_s / 1e9 / HBM_PEAK_GBS,
                      "traffic": None, "avg_launch_us": avg_s * 1e6, "bytes_per_launch": byts},
@@ -250,7 +257,7 @@ def serving(args):
           file=sys.stderr, flush=True)
     # autotune per dimension on the median-size request of that dimension
     from paper_2003_01061_amd import autotune
-    configs, tuning = {}, {}
+    tuned, tuning = {}, {}
     if not args.no_tune:
         for d in (2, 3):
             ds = sorted((x for x in descs if x.dim == d), key=lambda x: x.n)
@@ -259,12 +266,12 @@ def serving(args):
             med = ds[len(ds) // 2]
             r = autotune.tune([specs[med.idx]], d, binding.SPH_FP32_MIXED, steps=10, warmup=2,
                               max_neighbors=192 if d == 3 else 64)
-            configs[d] = r.best
+            tuned[d] = r.best
             tuning[str(d)] = dict(job_particles=med.n, best=r.best,
                                   speedup_over_default=r.speedup_over_default())
         print(f"[bench] serving tuned: {json.dumps(tuning)}", file=sys.stderr, flush=True)
     srv = serve.Server(pool_bytes=int(args.serve_pool_gib * (1 << 30)), slots=args.serve_slots,
-                       precision=binding.SPH_FP32_MIXED, chunk=args.serve_chunk, configs=configs)
+                       precision=binding.SPH_FP32_MIXED, chunk=args.serve_chunk, tuned=tuned)
 
     def one(rate):
         t = wk.poisson_arrivals(len(descs), rate, seed=4)
@@ -328,7 +335,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
-              "(the design of a multi-GPU decomposition is described in DESIGN.md)", file=sys.stderr)
+              "(a multi-GPU decomposition is designed but not built)", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -83,7 +83,7 @@ class Server:
                  batch_factory: Optional[Callable] = None,
                  footprint: Optional[Callable] = None,
                  clock=time.perf_counter, sleep=time.sleep, keep_positions=False,
-                 max_job_steps=1 << 20, configs=None):
+                 max_job_steps=1 << 20, tuned=None):
         if precision is None or batch_factory is None or footprint is None:
             from . import binding
             precision = binding.SPH_FP32_MIXED if precision is None else precision
@@ -98,7 +98,7 @@ class Server:
         self.keep_positions = keep_positions
         self.max_job_steps = int(max_job_steps)   # a job not converged by then is retired as an error
         # autotuned settings per dimension: {"cell_factor": .., "scan_tile": ..}
-        self.configs = {d: dict(c) for d, c in (configs or {}).items()}
+        self.tuned = {d: dict(c) for d, c in (tuned or {}).items()}
         self.max_neighbors = dict(max_neighbors or {2: 64, 3: 192})
         share = dict(share or {2: 0.5, 3: 0.5})
         ratio = dict(cells_per_particle or {2: 4.0, 3: 2.0})
@@ -123,7 +123,7 @@ class Server:
             self.batches[d] = batch_factory(d, precision, max_particles=p,
                                             max_cells=self.cap_cells[d], max_jobs=self.slots,
                                             max_neighbors=self.max_neighbors[d],
-                                            scan_tile=self.configs.get(d, {}).get("scan_tile", 0))
+                                            scan_tile=self.tuned.get(d, {}).get("scan_tile", 0))
         self.stats = ServeStats()
 
     def footprint_bytes(self):
@@ -145,7 +145,7 @@ class Server:
         def spec(r):
             # the request's job with its dimension's tuned cell size
             if r.idx not in spec_of:
-                cf = self.configs.get(r.dim, {}).get("cell_factor")
+                cf = self.tuned.get(r.dim, {}).get("cell_factor")
                 if cf is None:
                     spec_of[r.idx] = r.spec
                 else:
