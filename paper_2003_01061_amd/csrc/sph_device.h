@@ -131,8 +131,10 @@ struct Parts {
 // FP32 scan record of a particle (the rounding of its FP64 record)
 template <int D>
 __device__ __forceinline__ float4 scan_record(const double4 &xh, uint32_t f) {
-  if (D == 2) return make_float4((float)xh.x, (float)xh.y, (float)xh.w, __uint_as_float(f));
-  const uint32_t hb = (__float_as_uint((float)xh.w) & ~(uint32_t)(MAXF - 1)) | (f & (MAXF - 1));
+  // the support radius 2h (scaling by 2 commutes with the rounding)
+  if (D == 2) return make_float4((float)xh.x, (float)xh.y, (float)(2.0 * xh.w), __uint_as_float(f));
+  const uint32_t hb =
+      (__float_as_uint((float)(2.0 * xh.w)) & ~(uint32_t)(MAXF - 1)) | (f & (MAXF - 1));
   return make_float4((float)xh.x, (float)xh.y, (float)xh.z, __uint_as_float(hb));
 }
 

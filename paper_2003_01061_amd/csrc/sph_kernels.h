@@ -504,19 +504,21 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
       // low 6 bits.
       const unsigned long long accept = B.bmask[fi] | (1ull << (fi & (MAXF - 1)));
       const double A4 = 4.0 * (xi.w * xi.w);
-      // Candidates are classified in FP32 from the scan records; only those
-      // whose distance is within a thin band around the support radius are
-      // decided by the exact FP64 predicate.  Bound: a coordinate of a
-      // candidate the scan visits is at most Xb in magnitude (the job's box,
-      // or |x_i| + 2 R_i + 2 cells), so each rounded coordinate is off by at
-      // most 2^-24 Xb and an FP32 distance by at most M = sqrt(D) 2^-23 Xb
-      // plus a relative 1e-6; the band of relative half-width 2e-6 around
-      // 2 max(h_i, h_j), widened by M, covers every such error, so the
+      // Candidates are classified in FP32 from the scan records (which hold
+      // the support radius 2h); only those whose distance is within a thin
+      // band around H = 2 max(h_i, h_j) are decided by the exact FP64
+      // predicate.  Bound: a coordinate of a candidate the scan visits is at
+      // most Xb in magnitude (the job's box, or |x_i| + 2 R_i + 2 cells), so
+      // each rounded coordinate is off by at most 2^-24 Xb and an FP32
+      // distance by at most M = sqrt(D) 2^-23 Xb plus a relative 1e-6.  As H
+      // is at least 2 h0 (the sizing's smallest h), M is at most a relative
+      // M / (2 h0) of H, so the band of relative half-width
+      // w = 2e-6 + M / (2 h0) around H covers every such error and the
       // classification always equals the FP64 predicate.  In 3D the
-      // candidate's h carries the feature id in its 6 low mantissa bits
-      // (relative error below 2^-17), so the band there is 2e-5 wide.
+      // candidate's radius carries the feature id in its 6 low mantissa bits
+      // (relative error below 2^-17), so the base width there is 2e-5.
       const float4 xif = scan_record<D>(xi, (uint32_t)fi);
-      const float hif = D == 2 ? xif.z : xif.w;
+      const float Hif = D == 2 ? xif.z : xif.w;
       float Mf;
       {
         double xb = 0.0;
@@ -531,15 +533,26 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
         }
         Mf = (float)((D == 3 ? 1.7320508075688772 : 1.4142135623730951) * 0x1p-23 * xb * 1.01);
       }
+      // squared band limits: a certain neighbour below H^2 cin, a certain
+      // non-neighbour above H^2 cout
+      float cin, cout;
+      {
+        const double w = (D == 2 ? 2e-6 : 2e-5) + (double)Mf / (2.0 * J.g.h0);
+        cin = w < 1.0 ? (float)((1.0 - w) * (1.0 - w)) : -1.0f;
+        cout = (float)((1.0 + w) * (1.0 + w));
+      }
       static_assert(NB >= 1 && NB <= 8, "records are padded by 8");
-      // hits collect in a register block of LB entries, stored as one
-      // 32-byte sector when full (and once more, partly filled, at the end)
+      // hits collect in the thread's own column of an LDS ring of LB entries
+      // (entry-major, so the lanes of a wave hit distinct banks whatever
+      // their fill), stored as one 32-byte sector when full (and once more,
+      // partly filled, at the end).  One LDS write per hit replaces a
+      // select over LB registers, which every lane would execute whenever
+      // any lane of the wave hits.
+      static_assert(LB == 8, "the ring is flushed as two 16-byte stores");
+      __shared__ uint32_t ring[LB][BLOCK];
       uint4 *wp = reinterpret_cast<uint4 *>(nbr) + (size_t)i * (LB / 4);
       const uint32_t wstep = (uint32_t)n * (LB / 4);
       const uint32_t nblk = (uint32_t)B.cap / LB;   // blocks of capacity
-      uint32_t lbuf[LB];
-#pragma unroll
-      for (int q = 0; q < LB; ++q) lbuf[q] = 0u;
       for (int lv = lv0; lv <= lv1; ++lv) {
         // a level-lv candidate has h_j < hcap[lv], so none beyond
         // 2 max(h_i, hcap[lv]) is a neighbour
@@ -607,12 +620,10 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
                 const float dx = xif.x - xr[q].x, dy = xif.y - xr[q].y;
                 const float dz = D == 3 ? xif.z - xr[q].z : 0.0f;
                 const float d2 = dx * dx + dy * dy + dz * dz;
-                const float hj = D == 2 ? xr[q].z : xr[q].w;
-                const float H = 2.0f * (hif > hj ? hif : hj);
-                constexpr float band = D == 2 ? 2e-6f : 2e-5f;
-                float tin = H * (1.0f - band) - Mf;
-                tin = tin > 0.0f ? tin * tin : -1.0f;
-                const float tout = (H * (1.0f + band) + Mf) * (H * (1.0f + band) + Mf);
+                const float Hj = D == 2 ? xr[q].z : xr[q].w;
+                const float H = __builtin_fmaxf(Hif, Hj);
+                const float H2 = H * H;
+                const float tin = H2 * cin, tout = H2 * cout;
                 bool hit = cand & (d2 < tin);
                 if (cand & !(d2 < tin) & !(d2 > tout))   // near the support radius: exact test
                   hit = within_a4<D>(xi, A4, s.xh[j]);
@@ -623,12 +634,13 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
               for (int q = 0; q < NB; ++q) {
                 if (tag[q] != 0xffffffffu) {
                   const uint32_t k = count % LB;
-  #pragma unroll
-                  for (int t = 0; t < LB; ++t) lbuf[t] = (uint32_t)t == k ? tag[q] : lbuf[t];
+                  ring[k][threadIdx.x] = tag[q];
                   ++count;
                   if (k == LB - 1 && count / LB <= nblk) {
-                    wp[0] = make_uint4(lbuf[0], lbuf[1], lbuf[2], lbuf[3]);
-                    wp[1] = make_uint4(lbuf[4], lbuf[5], lbuf[6], lbuf[7]);
+                    wp[0] = make_uint4(ring[0][threadIdx.x], ring[1][threadIdx.x],
+                                       ring[2][threadIdx.x], ring[3][threadIdx.x]);
+                    wp[1] = make_uint4(ring[4][threadIdx.x], ring[5][threadIdx.x],
+                                       ring[6][threadIdx.x], ring[7][threadIdx.x]);
                     wp += wstep;
                   }
                 }
@@ -638,8 +650,10 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
         }
       }
       if (count % LB != 0 && count / LB < nblk) {   // the last, partly filled block
-        wp[0] = make_uint4(lbuf[0], lbuf[1], lbuf[2], lbuf[3]);
-        wp[1] = make_uint4(lbuf[4], lbuf[5], lbuf[6], lbuf[7]);
+        wp[0] = make_uint4(ring[0][threadIdx.x], ring[1][threadIdx.x], ring[2][threadIdx.x],
+                           ring[3][threadIdx.x]);
+        wp[1] = make_uint4(ring[4][threadIdx.x], ring[5][threadIdx.x], ring[6][threadIdx.x],
+                           ring[7][threadIdx.x]);
       }
       if ((int)count > B.cap) {
         atomicMax(&B.st[job].overflow_max, count);
