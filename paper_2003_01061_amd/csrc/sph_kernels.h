@@ -681,11 +681,13 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
       for (int a = 0; a < D; ++a) a3[a] = -((Pi[a] + B3[a]) / gam);
       double xa[3] = {xi.x, xi.y, xi.z};
       tangent<D>(J.g, F, xa, a3);
+      // in 2D the record's free slots carry v^n (after any reset) in the
+      // sweep precision, so sweep B gathers one record per neighbour less
       R4 o;
       o.x = (R)a3[0];
       o.y = (R)a3[1];
-      o.z = (R)a3[2];
-      o.w = R(0);
+      o.z = D == 2 ? (R)v4.x : (R)a3[2];
+      o.w = D == 2 ? (R)v4.y : R(0);
       ap[i] = o;
       const double vt = 1.0 / S;
       if (dbg_gam) dbg_gam[i] = gam;
@@ -756,8 +758,8 @@ __global__ __launch_bounds__(BLOCK) void k_midpoint(Batch B, Parts s,
 // mid-point velocities v~_j = v_j + dt_1/2 a^p_j formed on the fly
 // ---------------------------------------------------------------------------
 // MID: neighbours' v~ and eta come from their mid-point records (3D);
-// otherwise they are formed here from v and a^p (2D, where the extra pass
-// costs more than the smaller gather saves)
+// otherwise they are formed here from the a^p record, which in 2D also holds
+// v (an extra pass for mid-point records costs more than it saves in 2D)
 template <int D, int K, typename R, bool MID>
 __device__ __forceinline__ void sweep_b_sums(const Parts &s, const typename Vec4<R>::T *__restrict__ ap,
                                              const typename Vec4<R>::T *__restrict__ mid,
@@ -785,18 +787,13 @@ __device__ __forceinline__ void sweep_b_sums(const Parts &s, const typename Vec4
       uint32_t u[NB];
 #pragma unroll
       for (int q = 0; q < NB; ++q) u[q] = e0 + q < cnt ? ub[hb + q] : 0x80000000u;
-      double4 xr[NB], vr[NB];
+      double4 xr[NB];
       R4 mr[NB];
 #pragma unroll
       for (int q = 0; q < NB; ++q) {
         const uint32_t j = u[q] & 0x7fffffffu;   // boundary entries fetch a valid slot, unused
         xr[q] = s.xh[j];
-        if (MID) {
-          mr[q] = mid[j];
-        } else {
-          vr[q] = s.v[j];
-          mr[q] = ap[j];
-        }
+        mr[q] = MID ? mid[j] : ap[j];
       }
 #pragma unroll
       for (int q = 0; q < NB; ++q) {
@@ -813,11 +810,12 @@ __device__ __forceinline__ void sweep_b_sums(const Parts &s, const typename Vec4
           vtj[1] = mr[q].y;
           vtj[2] = D == 3 ? mr[q].z : R(0);
           etaj = mr[q].w;
-        } else {
+        } else {   // 2D: {a^p_x, a^p_y, v_x, v_y} in the sweep precision
+          static_assert(MID || D == 2, "the a^p record carries v only in 2D");
           const R4 apj = mr[q];
-          vtj[0] = (R)vr[q].x + halfR * apj.x;
-          vtj[1] = (R)vr[q].y + halfR * apj.y;
-          vtj[2] = D == 3 ? (R)vr[q].z + halfR * apj.z : R(0);
+          vtj[0] = apj.z + halfR * apj.x;
+          vtj[1] = apj.w + halfR * apj.y;
+          vtj[2] = R(0);
           const R vmj = sqrt_(vtj[0] * vtj[0] + vtj[1] * vtj[1] + vtj[2] * vtj[2]);
           etaj = R(0.2) * hj * vmj * rcp_(hjk);
         }
@@ -864,7 +862,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_b(Batch B, Parts s,
       const double4 v4 = s.v[i];
       const R4 api4 = ap[i];
       const double vi[3] = {v4.x, v4.y, v4.z};
-      const double api[3] = {(double)api4.x, (double)api4.y, (double)api4.z};
+      const double api[3] = {(double)api4.x, (double)api4.y, D == 3 ? (double)api4.z : 0.0};
       double vti[3];
 #pragma unroll
       for (int a = 0; a < 3; ++a) vti[a] = vi[a] + half * api[a];
