@@ -188,14 +188,24 @@ static void ell_point(const geo_t *G, int q, const double *y, double t, double *
 }
 
 /* distance from x to the surface of hole q for x outside it (0 inside):
- * g is convex and decreasing for t > -min a^2 and g(0) > 0 outside, so
- * Newton from t = 0 increases monotonically to the root; it stops when t
- * no longer increases (at most 64 steps; 18 suffice on [0,1]^3). */
+ * g is convex and decreasing for t > -min a^2, so Newton from any point left
+ * of the root increases monotonically to it.  g(t) >= |a y|^2 / (max a^2 + t)^2 - 1,
+ * so t0 = |a y| - max a^2 (or 0 if negative; g(0) > 0 outside) lies left of
+ * the root.  Newton starts there and stops when t no longer increases (at
+ * most 64 steps; 11 suffice on [0,1]^3). */
 static double ell_dist(const geo_t *G, int q, const double *x) {
   double y[3] = {0, 0, 0}, z[3] = {0, 0, 0};
   ell_local(G, q, x, y);
   if (!(ell_level(G, q, y) > 1.0)) return 0.0;
-  double t = 0.0;
+  double s0 = 0.0, amax2 = 0.0;
+  for (int k = 0; k < G->dim; ++k) {
+    double a = G->ha[q][k];
+    double ay = a * y[k];
+    s0 = s0 + ay * ay;
+    if (a * a > amax2) amax2 = a * a;
+  }
+  double t = sqrt(s0) - amax2;
+  if (!(t > 0.0)) t = 0.0;
   for (int it = 0; it < 64; ++it) {
     double tn = ell_newton(G, q, y, t);
     if (!(tn > t)) break;

@@ -60,7 +60,7 @@ struct Geom {
   double h0, grad, dcap, hpt[3];
   int32_t hell[MAXH];       // 1: ellipsoidal hole (unequal semi-axes)
   double ha[MAXH][3];       // its semi-axes, and max over them
-  double hamax[MAXH];
+  double hamax[MAXH], hamin[MAXH];   // largest / smallest semi-axis of an ellipsoid
   double hR[MAXH][9];       // rotation, row-major: local y = R (x - c)
 };
 
@@ -222,8 +222,9 @@ __device__ __forceinline__ double ell_newton(const Geom &g, int q, const double 
   return t + gv / (2.0 * dg);
 }
 
-// distance to the surface for x outside the hole, 0 inside: Newton from
-// t = 0 rises monotonically to the root (g convex, decreasing, g(0) > 0)
+// distance to the surface for x outside the hole, 0 inside: g is convex and
+// decreasing, and g(t) >= |a y|^2 / (max a^2 + t)^2 - 1, so Newton from
+// t0 = max(0, |a y| - max a^2) (left of the root) rises monotonically to it
 // and stops when t no longer increases (64 steps at most)
 template <int D>
 __device__ __forceinline__ double ell_dist(const Geom &g, int q, const double *x) {
@@ -231,7 +232,16 @@ __device__ __forceinline__ double ell_dist(const Geom &g, int q, const double *x
   double y[3] = {0.0, 0.0, 0.0};
   ell_local<D>(g, q, x, y);
   if (!(ell_level<D>(g, q, y) > 1.0)) return 0.0;
-  double t = 0.0;
+  double s0 = 0.0, amax2 = 0.0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    const double a = g.ha[q][k];
+    const double ay = a * y[k];
+    s0 = s0 + ay * ay;
+    amax2 = a * a > amax2 ? a * a : amax2;
+  }
+  double t = __builtin_sqrt(s0) - amax2;
+  t = t > 0.0 ? t : 0.0;
   for (int it = 0; it < 64; ++it) {
     const double tn = ell_newton<D>(g, q, y, t);
     if (!(tn > t)) break;
@@ -292,6 +302,18 @@ __device__ __forceinline__ void ell_normal(const Geom &g, int q, const double *x
   for (int m = 0; m < D; ++m) n[m] *= il;
 }
 
+// |x - c_q| in FP32 (for bounds that only prune)
+template <int D>
+__device__ __forceinline__ float center_dist32(const Geom &g, int q, const double *p) {
+  float s = 0.0f;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    const float e = (float)(p[a] - g.hc[q][a]);
+    s += e * e;
+  }
+  return __builtin_sqrtf(s);
+}
+
 template <int D>
 __device__ __forceinline__ double h_target(const Geom &g, const double *p) {
 #pragma clang fp contract(off)
@@ -304,22 +326,36 @@ __device__ __forceinline__ double h_target(const Geom &g, const double *p) {
     }
     return g.h0 + g.grad * __builtin_sqrt(s);
   }
+  // |x - c| - min a bounds an ellipsoid's distance from above (its inscribed
+  // ball) and |x - c| - max a from below.  An ellipsoid whose lower bound
+  // exceeds the smallest upper bound (or the cap) by a relative 1e-12 cannot
+  // lower min(d, dcap), so its Newton solve is skipped; the result is the
+  // same as with every ellipsoid solved.
+  // The bounds only prune, so |x - c| is taken in FP32 (relative error below
+  // 1e-6) and widened by a relative 1e-5 in the safe direction.
+  double ub = g.dcap;
+  for (int q = 0; q < g.nh; ++q) {
+    if (!g.hell[q]) continue;
+    const double r = (double)center_dist32<D>(g, q, p) * (1.0 + 1e-5);
+    double u = r - g.hamin[q];
+    u = u > 0.0 ? u : 0.0;
+    ub = u < ub ? u : ub;
+  }
   double dmin = __builtin_inf();
   for (int q = 0; q < g.nh; ++q) {
-    double s = 0.0;
-    for (int a = 0; a < D; ++a) {
-      double d = p[a] - g.hc[q][a];
-      s = s + d * d;
-    }
     double d;
     if (g.hell[q]) {
-      // |x - c| - max a bounds the distance from below; an ellipsoid whose
-      // bound exceeds the current minimum (or the cap) by a relative 1e-12
-      // cannot lower min(d, dcap), so its Newton solve is skipped
-      const double lim = dmin < g.dcap ? dmin : g.dcap;
-      if (__builtin_sqrt(s) - g.hamax[q] > lim * (1.0 + 1e-12)) continue;
+      double lim = dmin < g.dcap ? dmin : g.dcap;
+      lim = ub < lim ? ub : lim;
+      const double r = (double)center_dist32<D>(g, q, p) * (1.0 - 1e-5);
+      if (r - g.hamax[q] > lim * (1.0 + 1e-12)) continue;
       d = ell_dist<D>(g, q, p);
     } else {
+      double s = 0.0;
+      for (int a = 0; a < D; ++a) {
+        double e = p[a] - g.hc[q][a];
+        s = s + e * e;
+      }
       d = __builtin_fabs(__builtin_sqrt(s) - g.hr[q]);
     }
     if (d < dmin) dmin = d;
@@ -578,16 +614,20 @@ __device__ __forceinline__ bool inside(const Geom &g, const double *x) {
   for (int a = 0; a < D; ++a)
     if (!(x[a] > g.lo[a] && x[a] < g.hi[a])) return false;
   for (int q = 0; q < g.nh; ++q) {
-    if (g.hell[q]) {
-      double y[3] = {0.0, 0.0, 0.0};
-      ell_local<D>(g, q, x, y);
-      if (!(ell_level<D>(g, q, y) > 1.0)) return false;
-      continue;
-    }
     double s = 0.0;
     for (int a = 0; a < D; ++a) {
       double d = x[a] - g.hc[q][a];
       s = s + d * d;
+    }
+    if (g.hell[q]) {
+      // beyond the ellipsoid's bounding ball (with a relative 1e-12 to
+      // spare) its level exceeds 1 whatever the rounding: no quadric needed
+      const double am = g.hamax[q];
+      if (s > am * am * (1.0 + 1e-12)) continue;
+      double y[3] = {0.0, 0.0, 0.0};
+      ell_local<D>(g, q, x, y);
+      if (!(ell_level<D>(g, q, y) > 1.0)) return false;
+      continue;
     }
     double r = g.hr[q];
     if (!(s > r * r)) return false;

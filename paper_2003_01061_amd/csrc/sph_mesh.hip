@@ -638,9 +638,11 @@ static void fill_job(HostJob &J, const sph_geometry *g, const sph_sizing *s, con
     G.hr[q] = H[3];
     G.hell[q] = hole_is_ellipsoid(D, H) ? 1 : 0;
     G.hamax[q] = 0.0;
+    G.hamin[q] = H[3];
     for (int a = 0; a < 3; ++a) {
       G.ha[q][a] = H[3 + a];
       if (a < D) G.hamax[q] = std::max(G.hamax[q], H[3 + a]);
+      if (a < D) G.hamin[q] = std::min(G.hamin[q], H[3 + a]);
     }
     for (int e = 0; e < 9; ++e) G.hR[q][e] = H[6 + e];
   }
