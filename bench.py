@@ -232,6 +232,62 @@ def ellipsoid_run(args):
     print(json.dumps(out))
 
 
+# the paper's tables for its square and cube (sec. 4.1 Table "Square", sec. 4.5
+# Table "Cube", rows of the proposed method; its own hardware and meshing)
+PAPER_VALIDATION = {
+    "paper_square": dict(G_avg=0.95, G_min=0.67, theta_max=94.85, theta_min=40.11,
+                         theta_min_avg=56.23, n_theta_below_30=0, n_elements=4828,
+                         runtime_s=5.07, n_iter=1600),
+    "paper_cube": dict(theta_min=23.07, theta_max=146.74, gamma_min=0.27, gamma_avg=0.92,
+                       theta_min_avg=56.88, slivers={"10": 0, "20": 0, "30": 28, "40": 1913},
+                       n_elements=367839, runtime_s=1437.3, n_iter=7000),
+}
+
+
+def validation_run(args):
+    """The paper's square and cube run through both phases to convergence in
+    FP32-mixed: the step at which every feature has left Phase One, the
+    converged step, the wall time and the mesh quality, beside the paper's
+    table values (context: other hardware, other meshing)."""
+    import torch
+    from paper_2003_01061_amd import binding
+    from paper_2003_01061_amd import quality as mq
+    from paper_2003_01061_amd import workload as wk
+    out = {}
+    for name, make in (("paper_square", wk.paper_square), ("paper_cube", wk.paper_cube)):
+        # E_sys plateaus near 1e-3 in Phase One under these readings, above
+        # the paper's 5e-6, so Phase One ends at the step cap used elsewhere
+        wl = make(max_phase1_steps=1200)
+        j = binding.SphMesh(wl, precision=binding.SPH_FP32_MIXED, use_graph=1)
+        j.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        steps, phase_two = 0, None
+        while steps < args.max_steps:
+            j.step(20)
+            steps += 20
+            e = j.error()
+            if phase_two is None and e["phase"] >= 2:
+                phase_two = steps
+            if e["converged"]:
+                break
+        j.sync()
+        sec = time.perf_counter() - t0
+        c, e = j.counters(), j.error()
+        x = j.positions()
+        j.close()
+        out[name] = dict(particles=wl.n, h_scale=wl.scale, phase_one_ended_by_step=phase_two,
+                         phase_one_cap=1200,
+                         converged=e["converged"], steps=int(c["steps"]), seconds=sec,
+                         interactions_per_s=c["interactions"] / sec, e_sys=e["e_sys"],
+                         mesh=mq.mesh_quality(x, wl.dim, wl.lo, wl.hi, wl.holes),
+                         paper=PAPER_VALIDATION[name])
+        print(f"[bench] {name}: {json.dumps(out[name])}", file=sys.stderr, flush=True)
+    print(json.dumps({"metric": "steps and time to the converged mesh, mesh quality",
+                      "data": "synthetic", "precision": "fp32 sums + fp64 integration",
+                      "cases": out}))
+
+
 def _build_job(desc):
     from paper_2003_01061_amd import workload as wk
     return wk.build_job(desc)
@@ -322,9 +378,11 @@ def main():
                          "eagerly launched FP32-mixed steps of the workload (default tuning), "
                          "'step3d' the same on the 2M-particle cube minus a ball, "
                          "'copy' one 256 MiB device copy (counter calibration); prints no JSON")
-    ap.add_argument("--workload", choices=["square_hole", "ellipsoids"], default="square_hole",
-                    help="ellipsoids: the 20M-particle inclusion workload run to convergence "
-                         "(its own JSON line; not the headline)")
+    ap.add_argument("--workload", choices=["square_hole", "ellipsoids", "validation"],
+                    default="square_hole",
+                    help="ellipsoids: the 20M-particle inclusion workload run to convergence; "
+                         "validation: the paper's square and cube run to convergence "
+                         "(each its own JSON line; not the headline)")
     ap.add_argument("--max-steps", type=int, default=3000,
                     help="step cap of the ellipsoid run")
     ap.add_argument("--serve-jobs", type=int, default=256)
@@ -355,6 +413,9 @@ def main():
         return
     if args.workload == "ellipsoids":
         ellipsoid_run(args)
+        return
+    if args.workload == "validation":
+        validation_run(args)
         return
     if args.pmc_pass == "step3d":
         wl3 = wk.cube_ball()

@@ -686,6 +686,28 @@ def ellipsoid_inclusions(n_total=20_000_000, seed=5, dim=3, n_incl=16, ratio=20.
                   envelope_grid=envelope_grid)
 
 
+def paper_square(n_total=2524, seed=6, res=512, **pover):
+    """Sec. 4.1's square: [0,100]^2, h_t = h_min + (h_max - h_min) |x - (100, 100)|
+    / (100 sqrt 2), h_min = 0.244, h_max = 4.88, 2,524 particles (h scaled by
+    the mass split's s)."""
+    hmin, hmax = 0.244, 4.88
+    return _build("paper_square", 2, [0, 0, 0], [100, 100, 0], np.zeros((0, 15)),
+                  dict(kind=H_LINEAR_FROM_POINT, h0=hmin, grad=(hmax - hmin) / (100 * math.sqrt(2)),
+                       dcap=np.inf, point=[100.0, 100.0, 0.0]),
+                  default_params(**pover), n_total, seed, 0, res)
+
+
+def paper_cube(n_total=66038, seed=7, res=96, **pover):
+    """Sec. 4.5's cube: [0,100]^3, h_t = h_min + (h_max - h_min) |x - (100, 100, 100)|
+    / (100 sqrt 3), h_min = 0.488, h_max = 4.88, 66,038 particles (h scaled by
+    the mass split's s)."""
+    hmin, hmax = 0.488, 4.88
+    return _build("paper_cube", 3, [0, 0, 0], [100, 100, 100], np.zeros((0, 15)),
+                  dict(kind=H_LINEAR_FROM_POINT, h0=hmin, grad=(hmax - hmin) / (100 * math.sqrt(3)),
+                       dcap=np.inf, point=[100.0, 100.0, 100.0]),
+                  default_params(**pover), n_total, seed, 0, res, envelope_grid=64)
+
+
 # ---------------------------------------------------------------------------
 # the serving stream: many jobs of both dimensions and a wide size range
 # ---------------------------------------------------------------------------

@@ -27,9 +27,13 @@ CASES = {
     # sixteen rotated ellipsoids (the 20M workload's layout), h ratio 1:4
     "ell3d_30011": lambda: wk.ellipsoid_inclusions(n_total=30011, seed=24, dim=3, n_incl=16,
                                                    ratio=4.0, res=32, envelope_grid=24),
+    # the paper's validation square and cube (sec. 4.1, 4.5): [0,100]^D, h
+    # linear from a corner, ratio 1:20 / 1:10
+    "paper_square": lambda: wk.paper_square(),
+    "paper_cube": lambda: wk.paper_cube(),
 }
 KSTEPS = {"square64": 200, "hole2d_20011": 60, "ball3d_30011": 25, "ell2d_20011": 60,
-          "ell3d_30011": 20}
+          "ell3d_30011": 20, "paper_square": 150, "paper_cube": 6}
 
 _wl_cache = {}
 
