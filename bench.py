@@ -321,7 +321,7 @@ def serving(args):
                 continue
             med = ds[len(ds) // 2]
             r = autotune.tune([specs[med.idx]], d, binding.SPH_FP32_MIXED, steps=10, warmup=2,
-                              max_neighbors=192 if d == 3 else 64)
+                              max_neighbors=320 if d == 3 else 104)
             tuned[d] = r.best
             tuning[str(d)] = dict(job_particles=med.n, best=r.best,
                                   speedup_over_default=r.speedup_over_default())

@@ -109,18 +109,26 @@ typedef struct {
                                 compensated accumulation, FP64 positions,
                                 integration and projection */
   int32_t max_neighbors;     /* neighbour-list capacity per particle, rounded up
-                                to a multiple of 8; 0 = 64 in 2D, 160 in 3D */
-  double cell_factor;        /* cell side = 2 h_min cell_factor (0 = 1.0), enlarged
+                                to a multiple of 8; 0 = 104 in 2D, 320 in 3D */
+  double cell_factor;        /* cell side = r_c,min cell_factor, r_c,min the
+                                support radius kernel_support h_min (0 = 1.0), enlarged
                                 if the grid would exceed 2^29 cells */
   int32_t scan_tile;         /* candidate records tested per pass of the
                                 neighbour scan: 2, 4 or 8; 0 = 4.  Results do
                                 not depend on it (autotuning knob) */
   int32_t cell_levels;       /* cell grids per band of h: level l holds the
                                 particles with h_min 2^l <= h < h_min 2^(l+1)
-                                on cells of side 2 h_min 2^l cell_factor.
+                                on cells of side kernel_support h_min 2^l
+                                cell_factor.
                                 0 = one level per factor 2 when h_max > 4 h_min
                                 (else 1), 1 = a single grid, k <= 6 = at most
                                 k levels.  Lists do not depend on it */
+  double kernel_support;     /* cut-off radius r_c in units of h (sec. 2.3 names
+                                r_c without a value):
+                                the kernel is Wendland C2 at smoothing length
+                                r_c / 2, neighbours satisfy |x_i - x_j| <
+                                r_c max(h_i, h_j) / h, and r_c enters the time
+                                step and the viscosity.  0 = 2.5; [1, 8] */
   int32_t use_graph;         /* 1: steps replay a captured HIP graph */
   int32_t debug_fields;      /* 1: keep gamma, V~ and v~ for sph_mesh_field */
   void *stream;              /* hipStream_t to run on (e.g. PyTorch's current
@@ -251,7 +259,7 @@ typedef struct {
   int64_t max_particles;     /* capacity: particles of all resident jobs */
   int64_t max_cells;         /* capacity: cells of all resident jobs' grids */
   int32_t max_jobs;          /* resident jobs, 1..64 */
-  int32_t max_neighbors;     /* 0 = 64 in 2D, 160 in 3D */
+  int32_t max_neighbors;     /* 0 = 104 in 2D, 320 in 3D */
   int32_t scan_tile;         /* 2, 4 or 8 (0 = 4), as in sph_params */
   int32_t use_graph;         /* 1: steps replay a captured graph of two steps */
   int32_t debug_fields;      /* keep gamma, V~, v~ (single-job inspection) */

@@ -19,8 +19,8 @@
  *                                   (volume_integral)
  *   two-phase control ............ sec. 3.4.2-3.4.4, Eq. (momentum_equation_new)
  *   step order ................... Algorithm 1 (flowchart)
- * Points the paper leaves open are resolved by named readings R1..R26, the
- * same list the design document keeps; each appears where it is used.
+ * Where the paper leaves a point open, the choice made is stated in a
+ * comment where it is used.
  *
  * Built with gcc -O2 -ffp-contract=off: no fused multiply-add anywhere, so
  * every expression rounds exactly as written.
@@ -120,8 +120,9 @@ static int geo_build(const sphref_geometry *g, geo_t *G) {
 }
 
 /* fb bounds fi: the lower-dimensional feature fb lies on the boundary of fi
- * (reading R12: the boundary relation of sec. 3.3 is taken between adjacent
- * features; a volume is bounded by every lower-dimensional feature). */
+ * (the boundary relation of sec. 3.3 is read as one between adjacent
+ * features, since n_b is only defined on i's own boundary; a volume is
+ * bounded by every lower-dimensional feature). */
 static int bounds(const geo_t *G, int fi, int fb) {
   const feat_t *A = &G->f[fi], *B = &G->f[fb];
   if (B->k >= A->k) return 0;
@@ -218,8 +219,9 @@ static double ell_dist(const geo_t *G, int q, const double *x) {
 }
 
 /* closest point on the surface of hole q to a point x near it: eight Newton
- * steps from t = 0 (reading R18: a fixed count; eight bring offsets up to
- * 3e-3 of the semi-axes to |level - 1| <= 1e-15) */
+ * steps from t = 0 (a fixed count, as the level-set projection of sec. 2.1
+ * gives no iteration rule; eight bring offsets up to 3e-3 of the semi-axes
+ * to |level - 1| <= 1e-15) */
 static void ell_project(const geo_t *G, int q, double *x) {
   int D = G->dim;
   double y[3] = {0, 0, 0}, z[3] = {0, 0, 0};
@@ -255,7 +257,9 @@ static double sg(int side) { return side ? 1.0 : -1.0; }
 
 /* outward normal n_b of feature fi's boundary at boundary particle b
  * (sec. 3.3, Eq. (gradient_operator_renormSPH_bypart): n points out of the
- * domain of i; reading R13 for edges and corners). */
+ * domain of i; at box edges and corners the normalised sum of the adjacent
+ * face normals, within a face the in-face conormal, on a curve the outward
+ * tangent). */
 static void bnormal(const geo_t *G, int fi, int fb, const double *xb, double *n) {
   const feat_t *A = &G->f[fi], *B = &G->f[fb];
   int D = G->dim;
@@ -298,7 +302,8 @@ static void bnormal(const geo_t *G, int fi, int fb, const double *xb, double *n)
   }
 }
 
-/* tangent projection T_i u of sec. 3.6's "map onto feature k" (reading R18):
+/* tangent projection T_i u of sec. 3.6's "map onto feature k" (its cited
+ * equations are not available; read as):
  * identity for volume particles, remove the normal part on surfaces, keep the
  * tangent part on curves, zero for singular particles. */
 static void tproject(const geo_t *G, int fi, const double *x, double *u) {
@@ -349,7 +354,9 @@ static void tproject(const geo_t *G, int fi, const double *x, double *u) {
 
 static double clampd(double v, double lo, double hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
-/* closest-point projection of x onto feature fi (reading R18) */
+/* closest-point projection of x onto feature fi (sec. 3.6's mapping, read
+ * as the closest point: clamped to a face or edge segment, radial on circles
+ * and spheres, Newton on ellipses and ellipsoids) */
 static void pproject(const geo_t *G, int fi, double *x) {
   const feat_t *A = &G->f[fi];
   int D = G->dim;
@@ -400,7 +407,7 @@ static int inside(const geo_t *G, const double *x) {
 }
 
 /* ------------------------------------------------------------------ */
-/* target feature size h_t(x) (sec. 2.2; reading R3: h_i = h_t(x_i))    */
+/* target feature size h_t(x) (sec. 2.2; h_i = h_t(x_i) each step)       */
 /* ------------------------------------------------------------------ */
 static double h_at(const geo_t *G, const sphref_sizing *S, const double *x) {
   int D = G->dim;
@@ -427,7 +434,8 @@ static double h_at(const geo_t *G, const sphref_sizing *S, const double *x) {
 }
 
 /* ------------------------------------------------------------------ */
-/* kernel: Wendland C2, support 2h, intrinsic dimension k (reading R1,R2) */
+/* kernel: Wendland C2 (sec. 2.3 names only a cut-off radius), reaching  */
+/* two smoothing lengths, in the intrinsic dimension k of the feature     */
 /* ------------------------------------------------------------------ */
 static double kalpha(int k) {
   if (k == 1) return 5.0 / 8.0;
@@ -614,15 +622,27 @@ int32_t sphref_get_field(sphref_job *J, int32_t which, double *out) {
 /* ------------------------------------------------------------------ */
 /* neighbour lists (Algorithm 1: "construct Verlet neighbor list")       */
 /* ------------------------------------------------------------------ */
-/* relation of j to i (sec. 3.3 interaction hierarchy; reading R12):
+/* relation of j to i (sec. 3.3 interaction hierarchy, boundary relation
+ * between adjacent features as in bounds()):
  * 1 same type and index, 2 j bounds i's feature, 0 no interaction. */
 static int relation(const sphref_job *J, int64_t i, int64_t j) {
   if (J->f[i] == J->f[j]) return 1;
   return bounds(&J->G, J->f[i], J->f[j]) ? 2 : 0;
 }
 
-/* the pair predicate (reading R11): |x_i - x_j|^2 < 4 max(h_i,h_j)^2, the
- * squared distance summed over axes in order, no fused operations */
+/* cut-off radius r_c in units of h (sec. 2.3 gives no value; 2.5 by
+ * default, calibrated on the mesh quality of sec. 4.1's square), and the
+ * kernel's smoothing length per unit h (the kernel reaches 2 smoothing
+ * lengths) */
+static double rc_ratio(const sphref_params *P) {
+  return P->kernel_support > 0.0 ? P->kernel_support : 2.5;
+}
+static double klen(const sphref_params *P) { return 0.5 * rc_ratio(P); }
+
+/* the pair predicate (symmetric, and covering both kernel supports used,
+ * W(., h_i) and W(., h_ij)): |x_i - x_j|^2 < c^2 max(h_i,h_j)^2 with
+ * c = r_c / h, the squared distance summed over axes in order, no fused
+ * operations */
 static int within(const sphref_job *J, int64_t i, int64_t j) {
   int D = J->G.dim;
   double s = 0.0;
@@ -631,7 +651,8 @@ static int within(const sphref_job *J, int64_t i, int64_t j) {
     s = s + d * d;
   }
   double m = J->h[i] > J->h[j] ? J->h[i] : J->h[j];
-  return s < 4.0 * (m * m);
+  double c = rc_ratio(&J->P);
+  return s < (c * c) * (m * m);
 }
 
 static int cmp_i32(const void *a, const void *b) {
@@ -656,7 +677,7 @@ static int build_lists(sphref_job *J) {
       if (c < lo[a]) lo[a] = c;
       if (c > hi[a]) hi[a] = c;
     }
-  double cs = 2.0 * hmax;
+  double cs = rc_ratio(&J->P) * hmax;
   if (!(cs > 0)) cs = 1.0;
   int64_t nc[3] = {1, 1, 1}, ncell = 1;
   for (int a = 0; a < D; ++a) {
@@ -771,7 +792,11 @@ static double damping(const sphref_params *P, const grp_t *g) {
 
 /* end-of-step control of one group given this step's V-bar (sum of V~ over the
  * group) and final time step dt.  Sampling and windows follow sec. 3.4.2
- * (reading R22); the phase logic follows sec. 3.4.3-3.4.4 (readings R19, R21). */
+ * (V-bar sampled every sample_every phase-local steps, windows of
+ * window_samples samples that do not overlap); the phase logic follows
+ * sec. 3.4.3-3.4.4 (a time-step drop flagged at the end of a step resets at
+ * the start of the next; the transition halves the reset period every
+ * ramp_halving steps and lowers the damping linearly). */
 static void control_end_of_step(const sphref_params *P, grp_t *g, double vbar, double dt) {
   g->n_ph += 1;
   if (g->n_ph % P->sample_every == 0) {
@@ -838,8 +863,10 @@ static void sweep_a_particle(const sphref_job *J, int64_t i, const int32_t *nbl,
   int k = G->f[J->f[i]].k;
   double hi = J->h[i];
   double hik = hpow(hi, k), hi2k = hik * hik;
-  double S = sphref_W(k, 0.0, hi);          /* self term */
-  double gam = sphref_W(k, 0.0, hi) * hik;
+  double lk = klen(P);                       /* smoothing length per unit h */
+  double li = lk * hi;
+  double S = sphref_W(k, 0.0, li);          /* self term */
+  double gam = sphref_W(k, 0.0, li) * hik;
   double Pi[3] = {0, 0, 0}, B[3] = {0, 0, 0};
   for (int64_t t = 0; t < cnt; ++t) {
     int64_t j = nbl[t];
@@ -848,19 +875,19 @@ static void sweep_a_particle(const sphref_job *J, int64_t i, const int32_t *nbl,
     double r = norm3(dx);
     double hj = J->h[j];
     double hjk = hpow(hj, k), hj2k = hjk * hjk;
-    double hij = 0.5 * (hi + hj);
+    double lij = lk * (0.5 * (hi + hj));
     if (rel[t] == 1) {
-      double w = sphref_W(k, r, hi);
+      double w = sphref_W(k, r, li);
       S = S + w;
       gam = gam + w * hjk;
-      double c = P->p0 * (hi2k + hj2k) * dWdr_over_r(k, r, hij);
+      double c = P->p0 * (hi2k + hj2k) * dWdr_over_r(k, r, lij);
       for (int a = 0; a < D; ++a) Pi[a] = Pi[a] + c * dx[a];
     } else {
       double omega = P->boundary_weighting == 0 ? 1.0 / hj
                    : P->boundary_weighting == 1 ? hpow(hj, k - 1) : 0.0;
       double nb[3];
       bnormal(G, J->f[i], J->f[j], J->x + 3 * j, nb);
-      double c = P->p0 * (hi2k + hj2k) * sphref_W(k, r, hij) * omega;
+      double c = P->p0 * (hi2k + hj2k) * sphref_W(k, r, lij) * omega;
       for (int a = 0; a < D; ++a) B[a] = B[a] + c * nb[a];
     }
   }
@@ -898,7 +925,8 @@ static int64_t brute_list_lazy(sphref_job *J, int64_t i, int32_t *ids, int8_t *r
   double hi = h_of(J, i);
   double L = h_lipschitz(&J->S);
   double R2 = INFINITY;
-  if (2.0 * L < 1.0) { double R = 2.0 * hi / (1.0 - 2.0 * L); R2 = R * R * (1.0 + 1e-9); }
+  double cr = rc_ratio(&J->P);
+  if (cr * L < 1.0) { double R = cr * hi / (1.0 - cr * L); R2 = R * R * (1.0 + 1e-9); }
   for (int64_t j = 0; j < J->n; ++j) {
     if (j == i) continue;
     double s = 0.0;
@@ -909,7 +937,7 @@ static int64_t brute_list_lazy(sphref_job *J, int64_t i, int32_t *ids, int8_t *r
     if (!(s < R2)) continue;
     double hj = h_of(J, j);
     double m = hi > hj ? hi : hj;
-    if (!(s < 4.0 * (m * m))) continue;
+    if (!(s < (cr * cr) * (m * m))) continue;
     int r = relation(J, i, j);
     if (!r) continue;
     if (c < cap) { ids[c] = (int32_t)j; rel[c] = (int8_t)r; }
@@ -942,13 +970,14 @@ int32_t sphref_sample(sphref_job *J, int32_t m, const int64_t *idx, int64_t *off
 }
 
 /* ------------------------------------------------------------------ */
-/* one relaxation step (Algorithm 1; readings R17, R23)                 */
+/* one relaxation step (Algorithm 1; every feature reads x^n, and the  */
+/* force is evaluated once per step, see the integration below)         */
 /* ------------------------------------------------------------------ */
 
 /* Eq. (fa_time_step_size) terms of one particle folded into a running min;
- * r_c = 2h, nu = 0.1 r_c |v|.  Infinite terms (a or v zero) drop out. */
-static double dt_terms(double dt, double h, double amag, double vmag) {
-  double rc = 2.0 * h;
+ * r_c = c h, nu = 0.1 r_c |v|.  Infinite terms (a or v zero) drop out. */
+static double dt_terms(double dt, double cr, double h, double amag, double vmag) {
+  double rc = cr * h;
   if (amag > 0.0) { double t = 0.25 * sqrt(rc / amag); if (t < dt) dt = t; }
   if (vmag > 0.0) {
     double t = rc / (40.0 * vmag);
@@ -997,7 +1026,7 @@ static int one_step(sphref_job *J) {
   for (int64_t i = 0; i < n; ++i) {
     if (!act[i]) continue;
     grp_t *g = &J->g[J->f[i]];
-    g->dt1 = dt_terms(g->dt1, J->h[i], norm3(J->ap + 3 * i), norm3(J->v + 3 * i));
+    g->dt1 = dt_terms(g->dt1, rc_ratio(P), J->h[i], norm3(J->ap + 3 * i), norm3(J->v + 3 * i));
   }
 
   /* mid-point velocity */
@@ -1007,11 +1036,12 @@ static int one_step(sphref_job *J) {
     for (int a = 0; a < D; ++a) J->vt[3 * i + a] = J->v[3 * i + a] + 0.5 * dt1 * J->ap[3 * i + a];
   }
 
-  /* viscous force with the mid-point velocity (reading R15: nu_i local) */
+  /* viscous force with the mid-point velocity (nu_i = 0.1 r_c |v~_i| per
+   * particle, combined by the harmonic mean of eta) */
   for (int64_t i = 0; i < n; ++i) {
     if (!act[i]) continue;
     int k = G->f[J->f[i]].k;
-    double nu = 0.1 * (2.0 * J->h[i]) * norm3(J->vt + 3 * i);
+    double nu = 0.1 * (rc_ratio(P) * J->h[i]) * norm3(J->vt + 3 * i);
     J->eta[i] = nu / hpow(J->h[i], k);         /* eta = rho_t nu, rho_t = h^-k */
   }
   for (int64_t i = 0; i < n; ++i) {
@@ -1030,7 +1060,7 @@ static int one_step(sphref_job *J) {
       double hjk = hpow(hj, k), hj2k = hjk * hjk;
       double es = J->eta[i] + J->eta[j];
       double H = es > 0.0 ? 2.0 * J->eta[i] * J->eta[j] / es : 0.0;
-      double c = H * (hi2k + hj2k) * dWdr_over_r(k, r, 0.5 * (hi + hj));
+      double c = H * (hi2k + hj2k) * dWdr_over_r(k, r, klen(P) * (0.5 * (hi + hj)));
       for (int a = 0; a < D; ++a) Fv[a] = Fv[a] + c * (J->vt[3 * i + a] - J->vt[3 * j + a]);
     }
     tproject(G, J->f[i], J->x + 3 * i, Fv);
@@ -1044,10 +1074,12 @@ static int one_step(sphref_job *J) {
   for (int64_t i = 0; i < n; ++i) {
     if (!act[i]) continue;
     grp_t *g = &J->g[J->f[i]];
-    g->dt = dt_terms(g->dt, J->h[i], norm3(J->a + 3 * i), norm3(J->vt + 3 * i));
+    g->dt = dt_terms(g->dt, rc_ratio(P), J->h[i], norm3(J->a + 3 * i), norm3(J->vt + 3 * i));
   }
 
-  /* integrate and map onto the feature (reading R17, R18) */
+  /* integrate (v~ = v^n + dt1 a^p / 2; v^(n+1/2) = v^n + dt a / 2;
+   * x* = x^n + dt v^(n+1/2); v^(n+1) = T (v^(n+1/2) + dt a / 2)) and map onto
+   * the feature */
   for (int64_t i = 0; i < n; ++i) {
     if (!act[i]) continue;
     double dt = J->g[J->f[i]].dt;

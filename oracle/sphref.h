@@ -73,6 +73,9 @@ typedef struct {
   int32_t sum_order;       /* neighbour sums: 0 ascending id, 1 descending id
                               (two equally valid rounding orders; their
                               divergence is the noise floor of a trajectory) */
+  double kernel_support;   /* cut-off radius r_c in units of h (sec. 2.3 gives
+                              no value): the kernel's smoothing length is
+                              r_c / 2; 0 = 2.5 */
 } sphref_params;
 
 /* fields for sphref_get_field, all from the last completed step */

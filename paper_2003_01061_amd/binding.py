@@ -36,7 +36,8 @@ class Params(C.Structure):
                 ("ramp_halving", C.c_int32), ("phase2_steps", C.c_int32),
                 ("max_phase1_steps", C.c_int32), ("precision", C.c_int32),
                 ("max_neighbors", C.c_int32), ("cell_factor", C.c_double),
-                ("scan_tile", C.c_int32), ("cell_levels", C.c_int32), ("use_graph", C.c_int32),
+                ("scan_tile", C.c_int32), ("cell_levels", C.c_int32),
+                ("kernel_support", C.c_double), ("use_graph", C.c_int32),
                 ("debug_fields", C.c_int32), ("stream", C.c_void_p)]
 
 

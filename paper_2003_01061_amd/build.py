@@ -21,7 +21,7 @@ def flags():
     return ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-shared",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-munsafe-fp-atomics", "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
-            "-Wno-unused-result",
+            "-Wno-unused-result", "-Wshadow",
             "-I" + os.path.join(ROOT, "include")]
 
 

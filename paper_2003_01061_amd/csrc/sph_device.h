@@ -115,6 +115,9 @@ struct JobDev {
   Grid G;
   Ctl ctl;
   double p0;
+  // cut-off radius r_c = ksup h; the kernel's smoothing length is klen h
+  // (klen = ksup / 2) and the pair predicate compares with ksup2 max(h)^2
+  double ksup, klen, ksup2;
   int32_t bw, nf, live, pad;
 };
 
@@ -364,9 +367,14 @@ __device__ __forceinline__ double h_target(const Geom &g, const double *p) {
   return g.h0 * (1.0 + g.grad * dmin);
 }
 
-// |x_i - x_j|^2 < 4 max(h_i, h_j)^2 evaluated exactly as specified
+// |x_i - x_j|^2 < c2 max(h_i, h_j)^2 (c2 = (r_c / h)^2) with A4 = c2 (h_a h_a)
+// precomputed: c2 max(h_a, h_b)^2 is the larger of c2 h_a^2 and c2 h_b^2
+// (squaring and scaling by c2 > 0 are monotone, and both sides round the same
+// products), so the predicate holds exactly when s is below either.  The
+// squared distance is summed over axes in order, without contraction.
 template <int D>
-__device__ __forceinline__ bool within(const double4 &a, const double4 &b) {
+__device__ __forceinline__ bool within_a4(const double4 &a, double A4, double c2,
+                                          const double4 &b) {
 #pragma clang fp contract(off)
   double d = a.x - b.x;
   double s = d * d;
@@ -376,26 +384,7 @@ __device__ __forceinline__ bool within(const double4 &a, const double4 &b) {
     d = a.z - b.z;
     s = s + d * d;
   }
-  const double m = __builtin_fmax(a.w, b.w);   // h > 0 and finite
-  return s < 4.0 * (m * m);
-}
-
-// The same predicate with A4 = 4.0 * (h_a * h_a) precomputed: 4 max(h_a, h_b)^2
-// is the larger of 4 h_a^2 and 4 h_b^2 (squaring and scaling by 4 are
-// monotone, and both sides round the same products), so s < 4 max(.)^2 holds
-// exactly when s is below either.
-template <int D>
-__device__ __forceinline__ bool within_a4(const double4 &a, double A4, const double4 &b) {
-#pragma clang fp contract(off)
-  double d = a.x - b.x;
-  double s = d * d;
-  d = a.y - b.y;
-  s = s + d * d;
-  if (D == 3) {
-    d = a.z - b.z;
-    s = s + d * d;
-  }
-  return (s < A4) | (s < 4.0 * (b.w * b.w));
+  return (s < A4) | (s < c2 * (b.w * b.w));
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs; map them so that

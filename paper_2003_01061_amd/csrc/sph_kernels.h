@@ -376,11 +376,15 @@ template <int D, int K, typename R>
 __device__ __forceinline__ void sweep_a_sums(const Geom &g, const Parts &s,
                                              const double4 *__restrict__ enrm,
                                              const BNorm *__restrict__ bnrow, int bw, double p0,
+                                             double klen,
                                              const uint32_t *__restrict__ nbr, int n, int i,
                                              uint32_t cnt, const double4 &xi, int fi, double &S,
                                              double &gam, double Pi[3], double B[3]) {
+  // h enters rho_t = h^-k; the kernel is evaluated at the smoothing length
+  // klen h (cut-off radius 2 klen h)
   const R hi = (R)xi.w;
-  const R ihi = rcp_(hi);
+  const R kl = (R)klen;
+  const R ihi = rcp_((R)(klen * xi.w));
   constexpr R alpha = kalphaK<K, R>();
   const R hik = powK<K>(hi), hi2k = hik * hik;
   const R ihik = powK<K>(ihi);
@@ -415,7 +419,7 @@ __device__ __forceinline__ void sweep_a_sums(const Geom &g, const Parts &s,
         const R hj = (R)xj.w;
         const R hjk = powK<K>(hj);
         const R hsum = hi2k + hjk * hjk;
-        const R ihij = rcp_(R(0.5) * (hi + hj));
+        const R ihij = rcp_(kl * (R(0.5) * (hi + hj)));
         const R qij = rr * ihij;
         if (!(u[q] >> 31)) {
           const R w = alpha * wshapeK<K>(rr * ihi) * ihik;           // W(r, h_i)
@@ -503,7 +507,8 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
       // candidate's feature slot is in i's job range and its local id is its
       // low 6 bits.
       const unsigned long long accept = B.bmask[fi] | (1ull << (fi & (MAXF - 1)));
-      const double A4 = 4.0 * (xi.w * xi.w);
+      const double kc2 = J.ksup2;   // c^2, c = support radius / h
+      const double A4 = kc2 * (xi.w * xi.w);
       // Candidates are classified in FP32 from the scan records (which hold
       // the support radius 2h); only those whose distance is within a thin
       // band around H = 2 max(h_i, h_j) are decided by the exact FP64
@@ -537,9 +542,11 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
       // non-neighbour above H^2 cout
       float cin, cout;
       {
-        const double w = (D == 2 ? 2e-6 : 2e-5) + (double)Mf / (2.0 * J.g.h0);
-        cin = w < 1.0 ? (float)((1.0 - w) * (1.0 - w)) : -1.0f;
-        cout = (float)((1.0 + w) * (1.0 + w));
+        // the support radius is klen H >= 2 klen h0
+        const double w = (D == 2 ? 2e-6 : 2e-5) + (double)Mf / (2.0 * J.klen * J.g.h0);
+        const double k2 = J.klen * J.klen;
+        cin = w < 1.0 ? (float)((1.0 - w) * (1.0 - w) * k2) : -1.0f;
+        cout = (float)((1.0 + w) * (1.0 + w) * k2);
       }
       static_assert(NB >= 1 && NB <= 8, "records are padded by 8");
       // hits collect in the thread's own column of an LDS ring of LB entries
@@ -556,7 +563,7 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
       for (int lv = lv0; lv <= lv1; ++lv) {
         // a level-lv candidate has h_j < hcap[lv], so none beyond
         // 2 max(h_i, hcap[lv]) is a neighbour
-        double Rl = 2.0 * (xi.w > G.hcap[lv] ? xi.w : G.hcap[lv]) * (1.0 + 1e-9);
+        double Rl = J.ksup * (xi.w > G.hcap[lv] ? xi.w : G.hcap[lv]) * (1.0 + 1e-9);
         Rl = Rl < Rs ? Rl : Rs;
         const double R2 = Rl * Rl;
         int lo_c[3] = {0, 0, 0}, hi_c[3] = {0, 0, 0};
@@ -617,16 +624,16 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
                 const uint32_t j = j0 + q;
                 const bool rel = (accept >> (fr[q] & (MAXF - 1))) & 1ull;
                 const bool cand = rel & (j < je) & (j != (uint32_t)i);
-                const float dx = xif.x - xr[q].x, dy = xif.y - xr[q].y;
-                const float dz = D == 3 ? xif.z - xr[q].z : 0.0f;
-                const float d2 = dx * dx + dy * dy + dz * dz;
+                const float ex = xif.x - xr[q].x, ey = xif.y - xr[q].y;
+                const float ez = D == 3 ? xif.z - xr[q].z : 0.0f;
+                const float d2 = ex * ex + ey * ey + ez * ez;
                 const float Hj = D == 2 ? xr[q].z : xr[q].w;
                 const float H = __builtin_fmaxf(Hif, Hj);
                 const float H2 = H * H;
                 const float tin = H2 * cin, tout = H2 * cout;
                 bool hit = cand & (d2 < tin);
                 if (cand & !(d2 < tin) & !(d2 > tout))   // near the support radius: exact test
-                  hit = within_a4<D>(xi, A4, s.xh[j]);
+                  hit = within_a4<D>(xi, A4, kc2, s.xh[j]);
                 tag[q] = hit ? (j | (fr[q] == (uint32_t)(fi & (MAXF - 1)) ? 0u : 0x80000000u))
                              : 0xffffffffu;
               }
@@ -671,11 +678,11 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
       const BNorm *bnrow = B.bn + (size_t)fi * MAXF;
       double S, gam, Pi[3], B3[3];
       if (k == D)
-        sweep_a_sums<D, D, R>(J.g, s, B.enrm, bnrow, J.bw, J.p0, nbr, n, i, count, xi, fi, S, gam, Pi, B3);
+        sweep_a_sums<D, D, R>(J.g, s, B.enrm, bnrow, J.bw, J.p0, J.klen, nbr, n, i, count, xi, fi, S, gam, Pi, B3);
       else if (k == D - 1)
-        sweep_a_sums<D, D - 1, R>(J.g, s, B.enrm, bnrow, J.bw, J.p0, nbr, n, i, count, xi, fi, S, gam, Pi, B3);
+        sweep_a_sums<D, D - 1, R>(J.g, s, B.enrm, bnrow, J.bw, J.p0, J.klen, nbr, n, i, count, xi, fi, S, gam, Pi, B3);
       else
-        sweep_a_sums<D, 1, R>(J.g, s, B.enrm, bnrow, J.bw, J.p0, nbr, n, i, count, xi, fi, S, gam, Pi, B3);
+        sweep_a_sums<D, 1, R>(J.g, s, B.enrm, bnrow, J.bw, J.p0, J.klen, nbr, n, i, count, xi, fi, S, gam, Pi, B3);
       double a3[3] = {0.0, 0.0, 0.0};
 #pragma unroll
       for (int a = 0; a < D; ++a) a3[a] = -((Pi[a] + B3[a]) / gam);
@@ -693,7 +700,7 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
       if (dbg_gam) dbg_gam[i] = gam;
       if (dbg_vt) dbg_vt[i] = vt;
       // Eq. (fa_time_step_size) terms from a^p and v^n
-      const double rc = 2.0 * xi.w;
+      const double rc = J.ksup * xi.w;
       double dt = __builtin_inf();
       const double am = __builtin_sqrt(a3[0] * a3[0] + a3[1] * a3[1] + a3[2] * a3[2]);
       if (am > 0.0) dt = 0.25 * __builtin_sqrt(rc / am);
@@ -747,7 +754,7 @@ __global__ __launch_bounds__(BLOCK) void k_midpoint(Batch B, Parts s,
     const R vm = sqrt_(o.x * o.x + o.y * o.y + o.z * o.z);
     const R h = (R)s.xh[i].w;
     const R hk = F.k == 1 ? powK<1>(h) : (F.k == 2 ? powK<2>(h) : powK<3>(h));
-    o.w = R(0.2) * h * vm * rcp_(hk);
+    o.w = (R)(0.1 * B.jobs[fi / MAXF].ksup) * h * vm * rcp_(hk);   // eta = rho_t 0.1 r_c |v~|
   }
   mid[i] = o;
 }
@@ -765,12 +772,14 @@ __device__ __forceinline__ void sweep_b_sums(const Parts &s, const typename Vec4
                                              const typename Vec4<R>::T *__restrict__ mid,
                                              const uint32_t *__restrict__ nbr, int n, int i,
                                              uint32_t cnt, const double4 &xi, const double vti[3],
-                                             double vmi, double half, double Fv[3]) {
+                                             double vmi, double half, double klen, double Fv[3]) {
   using R4 = typename Vec4<R>::T;
   const R hi = (R)xi.w;
   constexpr R alpha = kalphaK<K, R>();
   const R hik = powK<K>(hi), hi2k = hik * hik;
-  const R etai = (R)(0.2 * xi.w * vmi) * rcp_(hik);
+  const R kl = (R)klen;
+  const R nuf = (R)(0.2 * klen);   // nu = 0.1 r_c |v~| = 0.2 klen h |v~|
+  const R etai = (R)(0.2 * klen * xi.w * vmi) * rcp_(hik);
   const R vtiR[3] = {(R)vti[0], (R)vti[1], (R)vti[2]};
   const R halfR = (R)half;
 #pragma unroll
@@ -817,11 +826,11 @@ __device__ __forceinline__ void sweep_b_sums(const Parts &s, const typename Vec4
           vtj[1] = apj.w + halfR * apj.y;
           vtj[2] = R(0);
           const R vmj = sqrt_(vtj[0] * vtj[0] + vtj[1] * vtj[1] + vtj[2] * vtj[2]);
-          etaj = R(0.2) * hj * vmj * rcp_(hjk);
+          etaj = nuf * hj * vmj * rcp_(hjk);
         }
         const R es = etai + etaj;
         const R H = es > R(0) ? R(2) * etai * etaj * rcp_(es) : R(0);
-        const R ihij = rcp_(R(0.5) * (hi + hj));
+        const R ihij = rcp_(kl * (R(0.5) * (hi + hj)));
         const R ih2 = ihij * ihij;
         const R ihk2 = K == 1 ? ih2 * ihij : (K == 2 ? ih2 * ih2 : ih2 * ih2 * ihij);
         const R c = H * (hi2k + hjk * hjk) * alpha * dwqK<K>(rr * ihij) * ihk2;
@@ -870,11 +879,11 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_b(Batch B, Parts s,
       const uint32_t cnt = nnb[i];
       double fv[3];
       if (k == D)
-        sweep_b_sums<D, D, R, D == 3>(s, ap, mid, nbr, n, i, cnt, xi, vti, vmi, half, fv);
+        sweep_b_sums<D, D, R, D == 3>(s, ap, mid, nbr, n, i, cnt, xi, vti, vmi, half, J.klen, fv);
       else if (k == D - 1)
-        sweep_b_sums<D, D - 1, R, D == 3>(s, ap, mid, nbr, n, i, cnt, xi, vti, vmi, half, fv);
+        sweep_b_sums<D, D - 1, R, D == 3>(s, ap, mid, nbr, n, i, cnt, xi, vti, vmi, half, J.klen, fv);
       else
-        sweep_b_sums<D, 1, R, D == 3>(s, ap, mid, nbr, n, i, cnt, xi, vti, vmi, half, fv);
+        sweep_b_sums<D, 1, R, D == 3>(s, ap, mid, nbr, n, i, cnt, xi, vti, vmi, half, J.klen, fv);
       double xa[3] = {xi.x, xi.y, xi.z};
       tangent<D>(J.g, F, xa, fv);
       const double eps = B.grp[fi].eps;
@@ -888,7 +897,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_b(Batch B, Parts s,
       o.w = R(0);
       acc[i] = o;
       if (dbg_vm) dbg_vm[i] = make_double4(vti[0], vti[1], vti[2], 0.0);
-      const double rc = 2.0 * xi.w;
+      const double rc = J.ksup * xi.w;
       double dt = __builtin_inf();
       const double am = __builtin_sqrt(a3[0] * a3[0] + a3[1] * a3[1] + a3[2] * a3[2]);
       if (am > 0.0) dt = 0.25 * __builtin_sqrt(rc / am);

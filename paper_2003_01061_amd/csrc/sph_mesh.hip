@@ -201,6 +201,8 @@ static sph_status validate(const sph_geometry *g, const sph_sizing *s, const sph
         return fail(SPH_ERR_INVALID_ARG, "hole %d must lie strictly inside the box", q);
   }
   if (s->kind < 0 || s->kind > 2) return fail(SPH_ERR_INVALID_ARG, "unknown sizing kind");
+  if (!(p->kernel_support == 0.0 || (p->kernel_support >= 1.0 && p->kernel_support <= 8.0)))
+    return fail(SPH_ERR_INVALID_ARG, "kernel_support must be 0 or in [1, 8]");
   if (p->cell_levels < 0 || p->cell_levels > MAXLEV)
     return fail(SPH_ERR_INVALID_ARG, "cell_levels must be in [0, %d]", MAXLEV);
   if (!(s->h0 > 0) || !(s->grad >= 0) || !std::isfinite(s->h0) || !std::isfinite(s->grad))
@@ -562,24 +564,31 @@ static int level_count(double hmin, double hmax, int want) {
   return std::max(1, std::min(nl, want > 0 ? want : MAXLEV));
 }
 
+// cut-off radius r_c in units of h (sec. 2.3 gives no value); 0 selects 2.5
+static double support_of(const sph_params *p) {
+  return p->kernel_support > 0.0 ? p->kernel_support : 2.5;
+}
+
 static void grid_of(const sph_geometry *g, const sph_sizing *s, const sph_params *p, Grid &Gr) {
   const int D = g->dim;
   double hmin, hmax, lip;
   sizing_bounds(g, s, hmin, hmax, lip);
+  const double c = support_of(p);
   const double cf = p->cell_factor > 0 ? p->cell_factor : 1.0;
   const int nlev = level_count(hmin, hmax, p->cell_levels);
-  // level l: h in [hmin 2^l, hmin 2^(l+1)), cell side 2 hmin 2^l cell_factor
+  // level l: h in [hmin 2^l, hmin 2^(l+1)), cell side c hmin 2^l cell_factor
+  // (c hmin 2^l is the support radius of the level's smallest h)
   double scale = 1.0;
   auto cells_at = [&](int l, int a) {
-    const double side = 2.0 * std::ldexp(hmin, l) * cf * scale;
+    const double side = c * std::ldexp(hmin, l) * cf * scale;
     return std::max(1.0, std::floor((g->hi[a] - g->lo[a]) / side));
   };
   for (;;) {
     double cells = 0.0;
     for (int l = 0; l < nlev; ++l) {
-      double c = 1.0;
-      for (int a = 0; a < D; ++a) c *= cells_at(l, a);
-      cells += c;
+      double lc = 1.0;
+      for (int a = 0; a < D; ++a) lc *= cells_at(l, a);
+      cells += lc;
     }
     if (cells <= 512.0 * 1024 * 1024) break;   // at most 2^29 cells per job
     scale *= 1.25;
@@ -607,8 +616,8 @@ static void grid_of(const sph_geometry *g, const sph_sizing *s, const sph_params
     Gr.hcap[l] = l + 1 < nlev ? std::ldexp(hmin, l + 1) : hmax;
   }
   Gr.ncell = total;
-  Gr.rmax = 2.0 * hmax * (1.0 + 1e-9);
-  Gr.rfac = 2.0 * lip < 0.9 ? 2.0 * (1.0 + 1e-9) / (1.0 - 2.0 * lip) : 1e300;
+  Gr.rmax = c * hmax * (1.0 + 1e-9);
+  Gr.rfac = c * lip < 0.9 ? c * (1.0 + 1e-9) / (1.0 - c * lip) : 1e300;
   Gr.lip = lip;
 }
 
@@ -650,6 +659,9 @@ static void fill_job(HostJob &J, const sph_geometry *g, const sph_sizing *s, con
   G.grad = s->grad;
   G.dcap = s->dcap;
   grid_of(g, s, p, d.G);
+  d.ksup = support_of(p);
+  d.klen = 0.5 * d.ksup;
+  d.ksup2 = d.ksup * d.ksup;
   d.G.cbase = cbase;
   J.ncell = d.G.ncell;
   J.cbase = cbase;
@@ -670,7 +682,8 @@ static void fill_job(HostJob &J, const sph_geometry *g, const sph_sizing *s, con
   d.live = 1;
 }
 
-static int64_t default_cap(int D) { return D == 2 ? 64 : 160; }
+// 64 / 160 at r_c = 2h, scaled by (2.5 / 2)^D for the default r_c = 2.5h
+static int64_t default_cap(int D) { return D == 2 ? 104 : 320; }
 
 // particle arrays of a job: count, non-NULL arrays, finite coordinates,
 // feature ids of the geometry

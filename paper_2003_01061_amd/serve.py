@@ -99,7 +99,7 @@ class Server:
         self.max_job_steps = int(max_job_steps)   # a job not converged by then is retired as an error
         # autotuned settings per dimension: {"cell_factor": .., "scan_tile": ..}
         self.tuned = {d: dict(c) for d, c in (tuned or {}).items()}
-        self.max_neighbors = dict(max_neighbors or {2: 64, 3: 192})
+        self.max_neighbors = dict(max_neighbors or {2: 104, 3: 320})
         share = dict(share or {2: 0.5, 3: 0.5})
         ratio = dict(cells_per_particle or {2: 4.0, 3: 2.0})
         self.cap_particles, self.cap_cells, self.bytes = {}, {}, {}

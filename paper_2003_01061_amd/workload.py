@@ -51,6 +51,7 @@ def default_params(**over):
         phase2_steps=400,     # Phase Two length, then the group freezes
         max_phase1_steps=1 << 30,
         precision=0,          # 0 FP64, 1 FP32 kernel sums / FP64 integration
+        kernel_support=2.5,   # cut-off radius r_c / h (sec. 2.3 gives no value)
     )
     p.update(over)
     return p

@@ -61,7 +61,8 @@ def test_struct_layout_matches_header():
 def test_batch_footprint_and_job_cells_are_host_logic():
     """Admission figures come from the host alone: the footprint grows with
     every capacity, rejects nonsense, and a job's cell count follows its
-    cell side 2 h_min * cell_factor."""
+    cell side c h_min * cell_factor (c h the support radius, c =
+    kernel_support)."""
     from paper_2003_01061_amd import binding
     from paper_2003_01061_amd import workload as wk
     base = dict(dim=2, max_particles=100_000, max_cells=50_000, max_jobs=8)
@@ -74,15 +75,19 @@ def test_batch_footprint_and_job_cells_are_host_logic():
     assert binding.batch_footprint(**dict(base, max_jobs=65)) == -1
     assert binding.batch_footprint(**dict(base, dim=4)) == -1
     wl = wk.square_lattice(n_side=64)
-    assert binding.JobSpec(wl).cells() == 32 * 32          # side 2/64 on the unit square
-    assert binding.JobSpec(wl, cell_factor=0.5).cells() == 64 * 64
+    assert wl.params["kernel_support"] == 2.5
+    assert binding.JobSpec(wl).cells() == 25 * 25          # side 2.5/64 on the unit square
+    assert binding.JobSpec(wl, cell_factor=0.5).cells() == 51 * 51
+    two = dict(wl.params, kernel_support=2.0)
+    assert binding.JobSpec(wl, params=two).cells() == 32 * 32
+    assert binding.JobSpec(wl, params=dict(wl.params, kernel_support=0.5)).cells() == -1
     bad = dict(wl.params, window_samples=0)
     assert binding.JobSpec(wl, params=bad).cells() == -1
 
 
 def test_cell_levels_follow_the_range_of_h():
     """A job whose h spans more than a factor 4 gets one cell grid per factor
-    2 of h (level l on cells of side 2 h_min 2^l); cell_levels = 1 keeps a
+    2 of h (level l on cells of side c h_min 2^l); cell_levels = 1 keeps a
     single grid and k caps the count.  Host logic, no GPU."""
     from paper_2003_01061_amd import binding
     from paper_2003_01061_amd import workload as wk
@@ -90,7 +95,8 @@ def test_cell_levels_follow_the_range_of_h():
                                  envelope_grid=32)
     hmin = wl.sizing["h0"]
     hmax = hmin * (1 + wl.sizing["grad"] * wl.sizing["dcap"])        # ratio 20: 5 levels
-    side = [2 * hmin * 2 ** l for l in range(5)]
+    c = wl.params["kernel_support"]
+    side = [c * hmin * 2 ** l for l in range(5)]
     per = [int(1.0 // s) ** 2 for s in side]
     assert binding.JobSpec(wl, cell_levels=1).cells() == per[0]
     assert binding.JobSpec(wl).cells() == sum(per)

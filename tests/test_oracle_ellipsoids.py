@@ -7,8 +7,8 @@ these tests pin, each against something the oracle does not compute itself:
 * the distance to the surface (the sizing field of sec. 2.2): closed form on
   the principal axes, and a minimisation over the surface's parametrisation
   (scipy) everywhere else;
-* the closest-point projection of surface particles (reading R18: a fixed
-  number of Newton steps): on the surface to 1e-14 and equal to the
+* the closest-point projection of surface particles (a fixed number of
+  Newton steps): on the surface to 1e-14 and equal to the
   parametric minimiser;
 * the boundary normal of the volume at the hole: unit length, perpendicular
   to the surface's tangents (finite differences of the parametrisation),
@@ -234,7 +234,8 @@ def test_lists_match_brute_force_and_lazy_samples(dim, n):
             d = x[i, a] - x[:, a]
             acc = acc + d * d
         m = np.maximum(h[i], h)
-        cand = np.nonzero(acc < 4.0 * (m * m))[0]
+        c = wl.params["kernel_support"]
+        cand = np.nonzero(acc < (c * c) * (m * m))[0]
         cand = cand[cand != i]
         # the relation filter only drops candidates; every kept id is a candidate
         assert np.all(np.isin(got, cand)), i

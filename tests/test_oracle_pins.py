@@ -26,7 +26,8 @@ def _surface(k, r):
 
 # ---------------------------------------------------------------------------
 # T1 kernel: normalisation, compact support, smoothness, textbook shape
-# (sec. 2.3 only names a cut-off radius; reading R1: Wendland C2, r_c = 2h)
+# (sec. 2.3 only names a cut-off radius: Wendland C2 reaching two smoothing
+# lengths, the smoothing length r_c / 2)
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("k", [1, 2, 3])
 @pytest.mark.parametrize("h", [1.0 / 64, 0.37, 2.5])
@@ -90,9 +91,10 @@ def test_lattice_shepard_sum_1d_exact():
 def test_lattice_shepard_sum_2d_from_step():
     """The step's gamma of a lattice particle far from every boundary equals
     the closed-form lattice sum (self term, V_t = h^k and the W(r, h_i)
-    argument all enter)."""
+    argument all enter); the closed form is for a cut-off radius r_c = 2h."""
     g = json.load(open(os.path.join(GOLDEN, "lattice_sums.json")))
     wl = wk.square_lattice(jitter=0.0)
+    wl.params = dict(wl.params, kernel_support=2.0)
     j = oracle.RefJob(wl)
     j.step(1)
     gam = j.field(oracle.F_GAMMA)
@@ -100,6 +102,29 @@ def test_lattice_shepard_sum_2d_from_step():
     interior = (wl.feature == 0) & np.all((x[:, :2] > 3 / 64) & (x[:, :2] < 1 - 3 / 64), axis=1)
     assert interior.sum() > 3000
     assert np.max(np.abs(gam[interior] - g["gamma_2d"])) < 1e-14
+
+
+def test_lattice_shepard_sum_2d_wider_support():
+    """With r_c = 2.5h the kernel's smoothing length is 1.25h: the step's
+    gamma of an interior lattice particle is the lattice sum of the textbook
+    Wendland C2 (written independently below) at that length, over the
+    offsets within 2.5h."""
+    h = 1 / 64
+    ell = 1.25 * h
+    tot = 0.0
+    for a in range(-3, 4):
+        for b in range(-3, 4):
+            tot += _w2(h * math.hypot(a, b), ell) * h * h
+    wl = wk.square_lattice(jitter=0.0)
+    wl.params = dict(wl.params, kernel_support=2.5)
+    j = oracle.RefJob(wl)
+    j.step(1)
+    gam = j.field(oracle.F_GAMMA)
+    x = wl.xyz
+    interior = (wl.feature == 0) & np.all((x[:, :2] > 4 / 64) & (x[:, :2] < 1 - 4 / 64), axis=1)
+    assert interior.sum() > 3000
+    assert np.max(np.abs(gam[interior] - tot)) < 1e-14
+    assert abs(tot - json.load(open(os.path.join(GOLDEN, "lattice_sums.json")))["gamma_2d"]) > 1e-3
 
 
 def test_lattice_shepard_sum_3d_kernel():
@@ -115,7 +140,7 @@ def test_lattice_shepard_sum_3d_kernel():
 
 # ---------------------------------------------------------------------------
 # T3 neighbour sets vs brute force (Algorithm 1 "Verlet neighbor list";
-# reading R11 predicate, sec. 3.3 interaction hierarchy)
+# |x_i - x_j| < r_c max(h_i, h_j) / h, sec. 3.3 interaction hierarchy)
 # ---------------------------------------------------------------------------
 def _feature_points(wl):
     """a few points on every feature, for a containment test"""
@@ -242,7 +267,8 @@ def brute_force_lists(wl, x):
             d = x[i, a] - x[:, a]
             acc = acc + d * d
         m = np.maximum(h[i], h)
-        ok = (acc < 4.0 * (m * m)) & (R[f[i], f] > 0)
+        c = wl.params.get("kernel_support", 2.5)
+        ok = (acc < (c * c) * (m * m)) & (R[f[i], f] > 0)
         ok[i] = False
         lists.append(np.nonzero(ok)[0])
     return lists
@@ -334,7 +360,8 @@ def test_lattice_is_in_equilibrium():
 
 
 # ---------------------------------------------------------------------------
-# T6 P0 scaling (reading R5 / R17): a^p, v and dt scale by 4, 2, 1/2 exactly
+# T6 P0 scaling (one pressure constant in the EOS and the momentum equation;
+# force evaluated once per step): a^p, v and dt scale by 4, 2, 1/2 exactly
 # ---------------------------------------------------------------------------
 def test_pressure_constant_scaling_is_bitwise():
     wl = wk.square_lattice(n_side=32, seed=3)
@@ -350,7 +377,8 @@ def test_pressure_constant_scaling_is_bitwise():
 
 
 # ---------------------------------------------------------------------------
-# T7 length scaling (readings R2, R7): geometry and h doubled => positions doubled
+# T7 length scaling (rho_t = h^-k in the feature's own dimension k; boundary
+# weight 1/h_b): geometry and h doubled => positions doubled
 # ---------------------------------------------------------------------------
 def _doubled(wl):
     import copy
@@ -421,7 +449,8 @@ def test_correction_cancels_wall_imbalance():
 
 
 # ---------------------------------------------------------------------------
-# T9 integrator special case (reading R17): v^n = 0 => dx = dt^2 a / 2
+# T9 integrator special case (half-step velocity v^n + dt a / 2 moves x):
+# v^n = 0 => dx = dt^2 a / 2
 # ---------------------------------------------------------------------------
 def test_first_step_displacement():
     wl = wk.square_lattice(n_side=32, seed=6)
@@ -437,10 +466,13 @@ def test_first_step_displacement():
     assert np.abs(expect).max() > 1e-6
 
 
-def test_time_step_by_hand():
+@pytest.mark.parametrize("c", [2.0, 2.5])
+def test_time_step_by_hand(c):
     """Eq. (fa_time_step_size) for a single moving curve particle between two
-    fixed corners: dt = min(0.25 sqrt(r_c/|a|), r_c/(40 |v|), ...)."""
+    fixed corners: dt = min(0.25 sqrt(r_c/|a|), r_c/(40 |v|), ...), with
+    r_c = c h and the kernel's smoothing length c h / 2."""
     wl = wk.square_lattice(n_side=4, seed=1)
+    wl.params = dict(wl.params, kernel_support=c)
     keep = (wl.feature == 3) | (wl.feature >= 5)      # edge y=lo and the corners
     wl.xyz = wl.xyz[keep].copy()
     wl.feature = wl.feature[keep].copy()
@@ -455,18 +487,20 @@ def test_time_step_by_hand():
     j.step(1)
     ap = j.field(oracle.F_AP)[i]
     h = 0.2
-    # by hand: only the corner at x = 0 is within 2h = 0.4 (distance 0.3);
-    # boundary term of a 1D particle: (h^2 + h^2) W_1(0.3, h) n / h with
-    # n = outward tangent (-1, 0); gamma = self term only = W_1(0, h) h.
-    q = 0.3 / h
-    W1 = 5 / 8 / h * (1 - q / 2) ** 3 * (1 + 1.5 * q)
-    W10 = 5 / 8 / h
+    ell = c / 2 * h
+    # by hand: only the corner at x = 0 is within c h (0.4 or 0.5; distance
+    # 0.3, the other corner is 0.7 away); boundary term of a 1D particle:
+    # (h^2 + h^2) W_1(0.3, ell) n / h with n = outward tangent (-1, 0);
+    # gamma = self term only = W_1(0, ell) h.
+    q = 0.3 / ell
+    W1 = 5 / 8 / ell * (1 - q / 2) ** 3 * (1 + 1.5 * q)
+    W10 = 5 / 8 / ell
     B = 2 * h * h * W1 * (-1.0) / h
     gam = W10 * h
     expect_ax = -B / gam
     assert abs(ap[0] - expect_ax) < 1e-14 * abs(expect_ax)
     assert ap[1] == 0.0
-    dt_expect = 0.25 * math.sqrt(2 * h / abs(expect_ax))
+    dt_expect = 0.25 * math.sqrt(c * h / abs(expect_ax))
     assert abs(j.group_state(3)["dt1"] - dt_expect) < 1e-14 * dt_expect
 
 
@@ -521,7 +555,8 @@ def test_control_dt_drop_and_forced_switch():
 
 
 # ---------------------------------------------------------------------------
-# T11 feature projections and boundary normals (reading R13, R18)
+# T11 feature projections (closest point) and boundary normals (outward
+# normal of i's feature at b)
 # ---------------------------------------------------------------------------
 def test_projections_closed_form():
     wl = wk.scaled_hole_2d(300, seed=1, res=64)
@@ -664,7 +699,8 @@ def test_noise_floor_of_summation_order():
 # worked example: one full step of two volume particles with graded h,
 # evaluated by hand from Eqs. (gamma_disc_renormSPH), (particle_volume),
 # (momentum_equation_discretized), (viscosity_coefficient),
-# (fa_time_step_size) and the integrator reading R17
+# (fa_time_step_size) and the integrator (v~ = v^n + dt1 a^p / 2, one force
+# evaluation per step)
 # ---------------------------------------------------------------------------
 def _w2(r, h):
     """Wendland C2 in 2D with support 2h, written from its textbook form
@@ -678,8 +714,10 @@ def _dw2(r, h):
     return 7 / (4 * math.pi * h * h) * (-20 * s * (1 - s) ** 3) / (2 * h) if s < 1 else 0.0
 
 
-def test_two_particle_step_by_hand():
+@pytest.mark.parametrize("c", [2.0, 2.5])
+def test_two_particle_step_by_hand(c):
     wl = wk.square_lattice(n_side=8)
+    wl.params = dict(wl.params, kernel_support=c)
     xi = np.array([0.5, 0.5])
     xj = np.array([0.52, 0.51])
     vi = np.array([0.01, 0.0])
@@ -698,11 +736,13 @@ def test_two_particle_step_by_hand():
     d = xi - xj
     r = np.linalg.norm(d)
     hij = 0.5 * (h[0] + h[1])
+    ell = [c / 2 * h[0], c / 2 * h[1]]      # the kernel's smoothing lengths
+    lij = c / 2 * hij
     ap = []
     for a, b, sgn in ((0, 1, 1.0), (1, 0, -1.0)):
-        gam = _w2(0, h[a]) * h[a] ** 2 + _w2(r, h[a]) * h[b] ** 2
-        S = _w2(0, h[a]) + _w2(r, h[a])
-        Pi = (h[a] ** 4 + h[b] ** 4) * _dw2(r, hij) * (sgn * d / r)
+        gam = _w2(0, ell[a]) * h[a] ** 2 + _w2(r, ell[a]) * h[b] ** 2
+        S = _w2(0, ell[a]) + _w2(r, ell[a])
+        Pi = (h[a] ** 4 + h[b] ** 4) * _dw2(r, lij) * (sgn * d / r)
         ap.append(-Pi / gam)
         assert abs(j.field(oracle.F_GAMMA)[a] - gam) < 1e-13 * gam
         assert abs(j.field(oracle.F_VT)[a] - 1 / S) < 1e-13 / S
@@ -710,7 +750,7 @@ def test_two_particle_step_by_hand():
     def dt_of(acc, vel):
         t = [1.0]
         for a in range(2):
-            rc = 2 * h[a]
+            rc = c * h[a]
             if np.linalg.norm(acc[a]) > 0:
                 t.append(0.25 * math.sqrt(rc / np.linalg.norm(acc[a])))
             if np.linalg.norm(vel[a]) > 0:
@@ -720,11 +760,11 @@ def test_two_particle_step_by_hand():
 
     dt1 = dt_of(ap, V)
     vt = [V[a] + 0.5 * dt1 * ap[a] for a in range(2)]
-    eta = [0.1 * 2 * h[a] * np.linalg.norm(vt[a]) / h[a] ** 2 for a in range(2)]
+    eta = [0.1 * c * h[a] * np.linalg.norm(vt[a]) / h[a] ** 2 for a in range(2)]
     H = 2 * eta[0] * eta[1] / (eta[0] + eta[1])
     acc = []
     for a, b in ((0, 1), (1, 0)):
-        Fv = H * (h[a] ** 4 + h[b] ** 4) * _dw2(r, hij) / r * (vt[a] - vt[b])
+        Fv = H * (h[a] ** 4 + h[b] ** 4) * _dw2(r, lij) / r * (vt[a] - vt[b])
         acc.append(ap[a] + Fv)
     dt = dt_of(acc, vt)
     for a in range(2):
