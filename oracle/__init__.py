@@ -34,7 +34,7 @@ class Params(C.Structure):
                 ("window_samples", C.c_int32), ("ramp_steps", C.c_int32),
                 ("ramp_halving", C.c_int32), ("phase2_steps", C.c_int32),
                 ("max_phase1_steps", C.c_int32), ("sum_order", C.c_int32),
-                ("kernel_support", C.c_double)]
+                ("kernel_support", C.c_double), ("boundary_scale", C.c_double)]
 
 
 F_H, F_AP, F_A, F_VT, F_GAMMA, F_VMID = range(6)

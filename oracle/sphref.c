@@ -639,6 +639,18 @@ static double rc_ratio(const sphref_params *P) {
 }
 static double klen(const sphref_params *P) { return 0.5 * rc_ratio(P); }
 
+/* factor on the boundary term (sec. 3.3 gives the term's form, not its
+ * balance).  With factor 1 and weight 1/h_b the boundary sum is the surface
+ * integral of the by-parts identity, which for evenly spaced particles
+ * cancels the truncated interior sum: the particles then fill the domain up
+ * to the boundary, so the first particle off it sits half a spacing away and
+ * makes flat elements with the boundary particles.  The boundary particles
+ * are mesh vertices themselves; factor 2 places the first particle one
+ * spacing from them (exactly one h from a corner on a curve). */
+static double bscale(const sphref_params *P) {
+  return P->boundary_scale > 0.0 ? P->boundary_scale : 2.0;
+}
+
 /* the pair predicate (symmetric, and covering both kernel supports used,
  * W(., h_i) and W(., h_ij)): |x_i - x_j|^2 < c^2 max(h_i,h_j)^2 with
  * c = r_c / h, the squared distance summed over axes in order, no fused
@@ -885,6 +897,7 @@ static void sweep_a_particle(const sphref_job *J, int64_t i, const int32_t *nbl,
     } else {
       double omega = P->boundary_weighting == 0 ? 1.0 / hj
                    : P->boundary_weighting == 1 ? hpow(hj, k - 1) : 0.0;
+      omega = omega * bscale(P);
       double nb[3];
       bnormal(G, J->f[i], J->f[j], J->x + 3 * j, nb);
       double c = P->p0 * (hi2k + hj2k) * sphref_W(k, r, lij) * omega;

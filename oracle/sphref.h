@@ -76,6 +76,9 @@ typedef struct {
   double kernel_support;   /* cut-off radius r_c in units of h (sec. 2.3 gives
                               no value): the kernel's smoothing length is
                               r_c / 2; 0 = 2.5 */
+  double boundary_scale;   /* factor on the boundary term of the pressure
+                              force; 0 = 2 (the first particle off a boundary
+                              then sits one spacing from it) */
 } sphref_params;
 
 /* fields for sphref_get_field, all from the last completed step */

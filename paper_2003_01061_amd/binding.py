@@ -37,7 +37,8 @@ class Params(C.Structure):
                 ("max_phase1_steps", C.c_int32), ("precision", C.c_int32),
                 ("max_neighbors", C.c_int32), ("cell_factor", C.c_double),
                 ("scan_tile", C.c_int32), ("cell_levels", C.c_int32),
-                ("kernel_support", C.c_double), ("use_graph", C.c_int32),
+                ("kernel_support", C.c_double), ("boundary_scale", C.c_double),
+                ("use_graph", C.c_int32),
                 ("debug_fields", C.c_int32), ("stream", C.c_void_p)]
 
 

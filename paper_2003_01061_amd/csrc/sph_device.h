@@ -118,6 +118,7 @@ struct JobDev {
   // cut-off radius r_c = ksup h; the kernel's smoothing length is klen h
   // (klen = ksup / 2) and the pair predicate compares with ksup2 max(h)^2
   double ksup, klen, ksup2;
+  double bscale;   // factor on the boundary term of the pressure force
   int32_t bw, nf, live, pad;
 };
 

@@ -376,7 +376,7 @@ template <int D, int K, typename R>
 __device__ __forceinline__ void sweep_a_sums(const Geom &g, const Parts &s,
                                              const double4 *__restrict__ enrm,
                                              const BNorm *__restrict__ bnrow, int bw, double p0,
-                                             double klen,
+                                             double klen, double bscale,
                                              const uint32_t *__restrict__ nbr, int n, int i,
                                              uint32_t cnt, const double4 &xi, int fi, double &S,
                                              double &gam, double Pi[3], double B[3]) {
@@ -445,7 +445,7 @@ __device__ __forceinline__ void sweep_a_sums(const Geom &g, const Parts &s,
             nv[1] = N.n[1];
             nv[2] = N.n[2];
           }
-          const R om = bw == 0 ? rcp_(hj) : (bw == 1 ? powK<K>(hj) * rcp_(hj) : R(0));
+          const R om = (bw == 0 ? rcp_(hj) : (bw == 1 ? powK<K>(hj) * rcp_(hj) : R(0))) * (R)bscale;
           const R w = alpha * wshapeK<K>(qij) * powK<K>(ihij);          // W(r, h_ib)
           const double c = (double)(P0 * hsum * w * om);
           B[0] += c * nv[0];
@@ -678,11 +678,11 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
       const BNorm *bnrow = B.bn + (size_t)fi * MAXF;
       double S, gam, Pi[3], B3[3];
       if (k == D)
-        sweep_a_sums<D, D, R>(J.g, s, B.enrm, bnrow, J.bw, J.p0, J.klen, nbr, n, i, count, xi, fi, S, gam, Pi, B3);
+        sweep_a_sums<D, D, R>(J.g, s, B.enrm, bnrow, J.bw, J.p0, J.klen, J.bscale, nbr, n, i, count, xi, fi, S, gam, Pi, B3);
       else if (k == D - 1)
-        sweep_a_sums<D, D - 1, R>(J.g, s, B.enrm, bnrow, J.bw, J.p0, J.klen, nbr, n, i, count, xi, fi, S, gam, Pi, B3);
+        sweep_a_sums<D, D - 1, R>(J.g, s, B.enrm, bnrow, J.bw, J.p0, J.klen, J.bscale, nbr, n, i, count, xi, fi, S, gam, Pi, B3);
       else
-        sweep_a_sums<D, 1, R>(J.g, s, B.enrm, bnrow, J.bw, J.p0, J.klen, nbr, n, i, count, xi, fi, S, gam, Pi, B3);
+        sweep_a_sums<D, 1, R>(J.g, s, B.enrm, bnrow, J.bw, J.p0, J.klen, J.bscale, nbr, n, i, count, xi, fi, S, gam, Pi, B3);
       double a3[3] = {0.0, 0.0, 0.0};
 #pragma unroll
       for (int a = 0; a < D; ++a) a3[a] = -((Pi[a] + B3[a]) / gam);

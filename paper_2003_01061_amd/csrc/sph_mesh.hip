@@ -203,6 +203,8 @@ static sph_status validate(const sph_geometry *g, const sph_sizing *s, const sph
   if (s->kind < 0 || s->kind > 2) return fail(SPH_ERR_INVALID_ARG, "unknown sizing kind");
   if (!(p->kernel_support == 0.0 || (p->kernel_support >= 1.0 && p->kernel_support <= 8.0)))
     return fail(SPH_ERR_INVALID_ARG, "kernel_support must be 0 or in [1, 8]");
+  if (!(p->boundary_scale == 0.0 || (p->boundary_scale >= 0.25 && p->boundary_scale <= 8.0)))
+    return fail(SPH_ERR_INVALID_ARG, "boundary_scale must be 0 or in [0.25, 8]");
   if (p->cell_levels < 0 || p->cell_levels > MAXLEV)
     return fail(SPH_ERR_INVALID_ARG, "cell_levels must be in [0, %d]", MAXLEV);
   if (!(s->h0 > 0) || !(s->grad >= 0) || !std::isfinite(s->h0) || !std::isfinite(s->grad))
@@ -662,6 +664,7 @@ static void fill_job(HostJob &J, const sph_geometry *g, const sph_sizing *s, con
   d.ksup = support_of(p);
   d.klen = 0.5 * d.ksup;
   d.ksup2 = d.ksup * d.ksup;
+  d.bscale = p->boundary_scale > 0.0 ? p->boundary_scale : 2.0;
   d.G.cbase = cbase;
   J.ncell = d.G.ncell;
   J.cbase = cbase;

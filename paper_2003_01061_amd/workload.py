@@ -52,6 +52,7 @@ def default_params(**over):
         max_phase1_steps=1 << 30,
         precision=0,          # 0 FP64, 1 FP32 kernel sums / FP64 integration
         kernel_support=2.5,   # cut-off radius r_c / h (sec. 2.3 gives no value)
+        boundary_scale=2.0,   # factor on the boundary term (first particle one spacing off)
     )
     p.update(over)
     return p

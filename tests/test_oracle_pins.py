@@ -438,14 +438,35 @@ def test_correction_cancels_wall_imbalance():
     row1 = (wl.feature == 0) & (x[:, 1] < 1 / 64) & (x[:, 0] > 0.2) & (x[:, 0] < 0.8)
     res = {}
     for bw in (0, 2):
-        p = dict(wl.params); p["boundary_weighting"] = bw
+        # factor 1: the boundary sum is the by-parts surface integral
+        p = dict(wl.params, boundary_weighting=bw, boundary_scale=1.0)
         j = oracle.RefJob(wl, params=p)
         j.step(1)
         res[bw] = j.field(oracle.F_AP)[row1]
     # uncorrected: the lopsided support pushes the first row into the wall
     assert np.all(res[2][:, 1] < 0)
-    # corrected: the wall term removes almost all of it
+    # corrected: the wall term removes almost all of it (the lattice's first
+    # row sits half a spacing from the wall, where the particle volumes reach it)
     assert np.abs(res[0][:, 1]).max() < 0.05 * np.abs(res[2][:, 1]).min()
+
+
+@pytest.mark.parametrize("scale", [0.5, 2.0, 3.0])
+def test_boundary_scale_multiplies_the_boundary_term(scale):
+    """a^p is linear in the boundary sum: with the interior part a_off (term
+    off) and the unit-factor part a_1, factor s gives a_off + s (a_1 - a_off),
+    here for every particle of a graded 2D job with a hole (curves bounded by
+    corners, the volume by curves and the hole's circle)."""
+    wl = wk.scaled_hole_2d(900, seed=3, res=64)
+    ap = {}
+    for key, extra in (("off", dict(boundary_weighting=2, boundary_scale=1.0)),
+                       ("one", dict(boundary_scale=1.0)), ("s", dict(boundary_scale=scale))):
+        j = oracle.RefJob(wl, params=dict(wl.params, **extra))
+        j.step(1)
+        ap[key] = j.field(oracle.F_AP)
+    wall = ap["one"] - ap["off"]
+    assert np.abs(wall).max() > 1e-3 * np.abs(ap["off"]).max()
+    expect = ap["off"] + scale * wall
+    assert np.abs(ap["s"] - expect).max() <= 1e-12 * np.abs(ap["s"]).max()
 
 
 # ---------------------------------------------------------------------------
@@ -490,12 +511,14 @@ def test_time_step_by_hand(c):
     ell = c / 2 * h
     # by hand: only the corner at x = 0 is within c h (0.4 or 0.5; distance
     # 0.3, the other corner is 0.7 away); boundary term of a 1D particle:
-    # (h^2 + h^2) W_1(0.3, ell) n / h with n = outward tangent (-1, 0);
-    # gamma = self term only = W_1(0, ell) h.
+    # s (h^2 + h^2) W_1(0.3, ell) n / h with n = outward tangent (-1, 0) and s
+    # the boundary factor; gamma = self term only = W_1(0, ell) h.
+    s = wl.params["boundary_scale"]
+    assert s == 2.0
     q = 0.3 / ell
     W1 = 5 / 8 / ell * (1 - q / 2) ** 3 * (1 + 1.5 * q)
     W10 = 5 / 8 / ell
-    B = 2 * h * h * W1 * (-1.0) / h
+    B = s * 2 * h * h * W1 * (-1.0) / h
     gam = W10 * h
     expect_ax = -B / gam
     assert abs(ap[0] - expect_ax) < 1e-14 * abs(expect_ax)
