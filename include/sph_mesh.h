@@ -192,7 +192,8 @@ sph_status sph_mesh_set_state(sph_mesh *m, const double *xyz, const double *vel)
 sph_status sph_mesh_velocities(sph_mesh *m, double *vel);
 
 /* Neighbour lists N(i) of the current positions (Algorithm 1's "construct
- * Verlet neighbor list"): j != i with |x_i - x_j|^2 < 4 max(h_i, h_j)^2
+ * Verlet neighbor list"): j != i with |x_i - x_j|^2 < c^2 max(h_i, h_j)^2,
+ * c = kernel_support
  * (FP64, squared distance summed over axes in order, no fused operations)
  * and an interaction between the features (same feature: rel 1; j on the
  * boundary of i's feature and of lower dimension: rel 2).  CSR in caller

@@ -8,8 +8,9 @@
  *   geometry and features ........ sec. 3.1-3.2 (level set, feature tags,
  *                                   particle types P_si, P_c, P_s, P_+)
  *   target feature size .......... sec. 2.2, Eq. (target_mesh_gen)
- *   kernel ....................... Wendland C2 with support 2h (the paper only
- *                                   names a cut-off radius r_c, sec. 2.3)
+ *   kernel ....................... Wendland C2 reaching r_c = c h, c = 2.5 by
+ *                                   default (the paper only names a cut-off
+ *                                   radius r_c, sec. 2.3)
  *   Shepard term gamma ........... sec. 3.3, Eq. (gamma_disc_renormSPH)
  *   pressure force + boundary .... sec. 3.3, Eq. (sph_pressure_force_disc_weighted)
  *   viscous force ................ sec. 2.3, Eq. (momentum_equation_discretized),
@@ -674,7 +675,7 @@ static int cmp_i32(const void *a, const void *b) {
 static int cmp_i32_desc(const void *a, const void *b) { return cmp_i32(b, a); }
 
 /* Lists for every non-singular particle.  A uniform bucket grid of side
- * 2 max(h) only limits which pairs are tested; the set is exactly the pairs
+ * c max(h) only limits which pairs are tested; the set is exactly the pairs
  * that pass the predicate and have a relation.  Ids are sorted ascending. */
 static int build_lists(sphref_job *J) {
   int D = J->G.dim;
@@ -928,7 +929,7 @@ static double h_lipschitz(const sphref_sizing *S) {
 
 /* brute_list with h evaluated only where the predicate can hold: with L the
  * Lipschitz constant of h_t, h_j <= h_i + L r, so a j at distance
- * r >= R_i = 2 h_i / (1 - 2L) has 4 max(h_i, h_j)^2 <= r^2 and is no
+ * r >= R_i = c h_i / (1 - c L) has c^2 max(h_i, h_j)^2 <= r^2 and is no
  * neighbour (R_i^2 is widened by 1e-9 for rounding).  Same predicate and
  * relation as build_lists; ids ascending. */
 static int64_t brute_list_lazy(sphref_job *J, int64_t i, int32_t *ids, int8_t *rel, int64_t cap) {

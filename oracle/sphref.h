@@ -91,7 +91,8 @@ enum {
   SPHREF_F_VMID = 5    /* mid-point velocity v~        n x 3    */
 };
 
-/* kernel (Wendland C2, support 2h) of intrinsic dimension k = 1, 2, 3 */
+/* kernel (Wendland C2 at smoothing length h, support 2h) of intrinsic
+ * dimension k = 1, 2, 3 */
 double sphref_W(int32_t k, double r, double h);
 double sphref_dWdr(int32_t k, double r, double h);
 /* target feature size at a point */

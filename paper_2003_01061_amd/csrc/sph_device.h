@@ -135,7 +135,8 @@ struct Parts {
 // FP32 scan record of a particle (the rounding of its FP64 record)
 template <int D>
 __device__ __forceinline__ float4 scan_record(const double4 &xh, uint32_t f) {
-  // the support radius 2h (scaling by 2 commutes with the rounding)
+  // 2h (scaling by 2 commutes with the rounding); the support radius is
+  // klen 2h
   if (D == 2) return make_float4((float)xh.x, (float)xh.y, (float)(2.0 * xh.w), __uint_as_float(f));
   const uint32_t hb =
       (__float_as_uint((float)(2.0 * xh.w)) & ~(uint32_t)(MAXF - 1)) | (f & (MAXF - 1));
@@ -416,7 +417,8 @@ __device__ __forceinline__ int h_level(const Grid &G, double h) {
 }
 
 // ---------------------------------------------------------------------------
-// Wendland C2 kernel with support 2h in intrinsic dimension k (1, 2, 3):
+// Wendland C2 kernel at smoothing length h (support 2h) in intrinsic
+// dimension k (1, 2, 3):
 // W = alpha_k h^-k w(q), w = (1-q/2)^4 (1+2q) (k = 2, 3) or (1-q/2)^3 (1+3q/2)
 // (k = 1); (dW/dr)/r = alpha_k h^-(k+2) w'(q)/q with w'(q)/q = -5 (1-q/2)^3 or
 // -3 (1-q/2)^2, finite at r = 0.

@@ -510,8 +510,8 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
       const double kc2 = J.ksup2;   // c^2, c = support radius / h
       const double A4 = kc2 * (xi.w * xi.w);
       // Candidates are classified in FP32 from the scan records (which hold
-      // the support radius 2h); only those whose distance is within a thin
-      // band around H = 2 max(h_i, h_j) are decided by the exact FP64
+      // 2h); only those whose distance is within a thin band around the
+      // support radius klen H, H = 2 max(h_i, h_j), are decided by the exact FP64
       // predicate.  Bound: a coordinate of a candidate the scan visits is at
       // most Xb in magnitude (the job's box, or |x_i| + 2 R_i + 2 cells), so
       // each rounded coordinate is off by at most 2^-24 Xb and an FP32
@@ -562,7 +562,7 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
       const uint32_t nblk = (uint32_t)B.cap / LB;   // blocks of capacity
       for (int lv = lv0; lv <= lv1; ++lv) {
         // a level-lv candidate has h_j < hcap[lv], so none beyond
-        // 2 max(h_i, hcap[lv]) is a neighbour
+        // c max(h_i, hcap[lv]) is a neighbour
         double Rl = J.ksup * (xi.w > G.hcap[lv] ? xi.w : G.hcap[lv]) * (1.0 + 1e-9);
         Rl = Rl < Rs ? Rl : Rs;
         const double R2 = Rl * Rl;
