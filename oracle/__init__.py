@@ -19,7 +19,8 @@ _lib = None
 
 class Geometry(C.Structure):
     _fields_ = [("dim", C.c_int32), ("lo", C.c_double * 3), ("hi", C.c_double * 3),
-                ("n_holes", C.c_int32), ("holes", C.POINTER(C.c_double))]
+                ("n_holes", C.c_int32), ("holes", C.POINTER(C.c_double)),
+                ("domain", C.c_int32)]
 
 
 class Sizing(C.Structure):
@@ -89,7 +90,7 @@ def _err():
     return lib().sphref_last_error().decode()
 
 
-def make_geometry(dim, lo, hi, holes):
+def make_geometry(dim, lo, hi, holes, domain=0):
     holes = np.ascontiguousarray(np.asarray(holes, np.float64).reshape(-1, 15))
     g = Geometry()
     g.dim = dim
@@ -98,6 +99,7 @@ def make_geometry(dim, lo, hi, holes):
         g.hi[a] = float(hi[a]) if a < len(hi) else 0.0
     g.n_holes = holes.shape[0]
     g.holes = holes.ctypes.data_as(C.POINTER(C.c_double)) if holes.size else None
+    g.domain = int(domain)
     g._keep = holes
     return g
 
@@ -134,7 +136,7 @@ class RefJob:
     def __init__(self, wl, xyz=None, feature=None, params=None):
         L = lib()
         self.dim = wl.dim
-        self.geom = make_geometry(wl.dim, wl.lo, wl.hi, wl.holes)
+        self.geom = make_geometry(wl.dim, wl.lo, wl.hi, wl.holes, wl.domain)
         self.sizing = make_sizing(wl.sizing)
         self.params = make_params(params if params is not None else wl.params)
         xyz = np.ascontiguousarray(wl.xyz if xyz is None else xyz, dtype=np.float64)

@@ -44,7 +44,7 @@ const char *sphref_last_error(void) { return g_err; }
 /* features (sec. 3.2)                                                  */
 /* ------------------------------------------------------------------ */
 enum { T_SI = 0, T_C = 1, T_S = 2, T_V = 3 };
-enum { K_VOL, K_BOXSIDE, K_HOLE, K_EDGE3, K_CORNER };
+enum { K_VOL, K_BOXSIDE, K_HOLE, K_EDGE3, K_CORNER, K_SHELL };
 
 typedef struct {
   int type, k, kind;
@@ -62,6 +62,8 @@ typedef struct {
   int ell[MAXH];            /* 1: ellipsoid (unequal semi-axes), 0: ball */
   double ha[MAXH][3];       /* ellipsoid semi-axes */
   double hR[MAXH][9];       /* ellipsoid rotation, row-major: local = R (x - c) */
+  int domain;               /* 0 box minus holes, 1 the ball inscribed in the box */
+  double dc[3], dR;         /* ball domain: centre and radius */
   int nf;
   feat_t f[MAXF];
 } geo_t;
@@ -74,6 +76,21 @@ static int geo_build(const sphref_geometry *g, geo_t *G) {
   for (int a = 0; a < 3; ++a) { G->lo[a] = g->lo[a]; G->hi[a] = g->hi[a]; }
   for (int a = 0; a < g->dim; ++a)
     if (!(g->lo[a] < g->hi[a])) { set_err("empty box"); return -1; }
+  if (g->domain != 0 && g->domain != 1) { set_err("domain must be 0 or 1"); return -1; }
+  G->domain = g->domain;
+  if (G->domain == 1) {
+    /* the ball (disc) inscribed in a cubic box: features volume and sphere */
+    double e0 = g->hi[0] - g->lo[0];
+    for (int a = 1; a < g->dim; ++a)
+      if (fabs((g->hi[a] - g->lo[a]) - e0) > 1e-12 * e0) { set_err("ball domain needs a cubic box"); return -1; }
+    if (g->n_holes != 0) { set_err("ball domain takes no holes"); return -1; }
+    for (int a = 0; a < 3; ++a) G->dc[a] = a < g->dim ? 0.5 * (g->lo[a] + g->hi[a]) : 0.0;
+    G->dR = 0.5 * e0;
+    G->f[0] = (feat_t){.type = T_V, .k = g->dim, .kind = K_VOL};
+    G->f[1] = (feat_t){.type = g->dim == 2 ? T_C : T_S, .k = g->dim - 1, .kind = K_SHELL};
+    G->nf = 2;
+    return 0;
+  }
   G->nh = g->n_holes;
   for (int q = 0; q < G->nh; ++q) {
     const double *H = g->holes + 15 * q;
@@ -278,6 +295,12 @@ static void bnormal(const geo_t *G, int fi, int fb, const double *xb, double *n)
       for (int a = 0; a < D; ++a) { d[a] = G->hc[B->hole][a] - xb[a]; s = s + d[a] * d[a]; }
       double r = sqrt(s);
       for (int a = 0; a < D; ++a) n[a] = d[a] / r;
+    } else if (B->kind == K_SHELL) {
+      /* out of the ball domain: radially outwards */
+      double d[3] = {0, 0, 0}, s = 0.0;
+      for (int a = 0; a < D; ++a) { d[a] = xb[a] - G->dc[a]; s = s + d[a] * d[a]; }
+      double r = sqrt(s);
+      for (int a = 0; a < D; ++a) n[a] = d[a] / r;
     } else if (B->kind == K_EDGE3) {
       double inv = 1.0 / sqrt(2.0);
       n[B->fax[0]] = sg(B->fsd[0]) * inv;
@@ -349,6 +372,24 @@ static void tproject(const geo_t *G, int fi, const double *x, double *u) {
       }
       return;
     }
+    case K_SHELL: {
+      const double *c = G->dc;
+      if (D == 2) {                       /* keep the part along the circle's tangent */
+        double t0 = -(x[1] - c[1]), t1 = x[0] - c[0];
+        double tl = sqrt(t0 * t0 + t1 * t1);
+        t0 = t0 / tl; t1 = t1 / tl;
+        double ut = u[0] * t0 + u[1] * t1;
+        u[0] = ut * t0; u[1] = ut * t1;
+      } else {                            /* remove the radial part */
+        double m[3], s = 0.0;
+        for (int a = 0; a < 3; ++a) { m[a] = x[a] - c[a]; s = s + m[a] * m[a]; }
+        double r = sqrt(s);
+        for (int a = 0; a < 3; ++a) m[a] = m[a] / r;
+        double un = u[0] * m[0] + u[1] * m[1] + u[2] * m[2];
+        for (int a = 0; a < 3; ++a) u[a] = u[a] - un * m[a];
+      }
+      return;
+    }
     default: u[0] = u[1] = u[2] = 0.0; return;
   }
 }
@@ -383,13 +424,26 @@ static void pproject(const geo_t *G, int fi, double *x) {
     case K_CORNER:
       for (int a = 0; a < D; ++a) x[a] = ((A->bits >> a) & 1) ? G->hi[a] : G->lo[a];
       return;
+    case K_SHELL: {
+      double d[3] = {0, 0, 0}, s = 0.0;
+      for (int a = 0; a < D; ++a) { d[a] = x[a] - G->dc[a]; s = s + d[a] * d[a]; }
+      double r = sqrt(s);
+      for (int a = 0; a < D; ++a) x[a] = G->dc[a] + G->dR * (d[a] / r);
+      return;
+    }
     default: return;
   }
 }
 
-/* phi(x) > 0: strictly inside the box and strictly outside every hole (sec. 2.1) */
+/* phi(x) > 0: strictly inside the box and strictly outside every hole, or
+ * strictly inside the ball domain (sec. 2.1) */
 static int inside(const geo_t *G, const double *x) {
   int D = G->dim;
+  if (G->domain == 1) {
+    double s = 0.0;
+    for (int a = 0; a < D; ++a) { double d = x[a] - G->dc[a]; s = s + d * d; }
+    return s < G->dR * G->dR;
+  }
   for (int a = 0; a < D; ++a)
     if (!(x[a] > G->lo[a] && x[a] < G->hi[a])) return 0;
   for (int q = 0; q < G->nh; ++q) {
@@ -417,6 +471,11 @@ static double h_at(const geo_t *G, const sphref_sizing *S, const double *x) {
     double s = 0.0;
     for (int a = 0; a < D; ++a) { double d = x[a] - S->point[a]; s = s + d * d; }
     return S->h0 + S->grad * sqrt(s);
+  }
+  if (S->kind == 3) {     /* graded both ways from the sphere |x - point| = dcap */
+    double s = 0.0;
+    for (int a = 0; a < D; ++a) { double d = x[a] - S->point[a]; s = s + d * d; }
+    return S->h0 + S->grad * fabs(sqrt(s) - S->dcap);
   }
   double dmin = INFINITY;
   for (int q = 0; q < G->nh; ++q) {
@@ -923,7 +982,7 @@ static double h_of(sphref_job *J, int64_t j) {
 /* Lipschitz constant of h_t: |grad d| <= 1 for the distance to the holes */
 static double h_lipschitz(const sphref_sizing *S) {
   if (S->kind == 0) return 0.0;
-  if (S->kind == 1) return S->grad;
+  if (S->kind == 1 || S->kind == 3) return S->grad;
   return S->h0 * S->grad;
 }
 

@@ -45,12 +45,17 @@ typedef struct {
   double lo[3], hi[3];
   int32_t n_holes;
   const double *holes;
+  int32_t domain;        /* 0: the box minus the holes; 1: the ball (disc)
+                            inscribed in the box, which must be a cube, with
+                            no holes: features 0 volume | 1 sphere (circle) */
 } sphref_geometry;
 
 /* Target feature size h_t(x) (paper sec. 2.2).
  * kind 0: h = h0
  * kind 1: h = h0 + grad * |x - point|
- * kind 2: h = h0 * (1 + grad * min(d, dcap)), d = distance to the nearest hole */
+ * kind 2: h = h0 * (1 + grad * min(d, dcap)), d = distance to the nearest hole
+ * kind 3: h = h0 + grad * | |x - point| - dcap |, graded both ways from the
+ *         sphere of radius dcap about point */
 typedef struct {
   int32_t kind;
   double h0, grad, dcap;

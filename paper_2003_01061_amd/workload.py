@@ -31,7 +31,7 @@ import numpy as np
 SI, CURVE, SURF, VOL = 0, 1, 2, 3
 
 # sizing kinds
-H_CONST, H_LINEAR_FROM_POINT, H_GRADED_TO_HOLES = 0, 1, 2
+H_CONST, H_LINEAR_FROM_POINT, H_GRADED_TO_HOLES, H_SHELL = 0, 1, 2, 3
 
 
 def default_params(**over):
@@ -73,6 +73,7 @@ class Workload:
     counts: dict = field(default_factory=dict)
     scale: float = 1.0
     steps: int = 0
+    domain: int = 0                 # 0 box minus holes, 1 the ball inscribed in the box
 
     @property
     def n(self):
@@ -217,6 +218,10 @@ def _h_field(pts, dim, sizing, holes):
     if kind == H_LINEAR_FROM_POINT:
         p = np.asarray(sizing["point"][:dim])
         return sizing["h0"] + sizing["grad"] * np.linalg.norm(pts[:, :dim] - p, axis=1)
+    if kind == H_SHELL:
+        p = np.asarray(sizing["point"][:dim])
+        r = np.linalg.norm(pts[:, :dim] - p, axis=1)
+        return sizing["h0"] + sizing["grad"] * np.abs(r - sizing["dcap"])
     if not any(_is_ellipsoid(rec, dim) for rec in holes):
         d = np.full(pts.shape[0], np.inf)
         for rec in holes:
@@ -243,7 +248,7 @@ def _inside(pts, dim, lo, hi, holes):
 def _lipschitz(sizing):
     """Lipschitz constant of h (the distance to the holes is 1-Lipschitz)"""
     k = sizing["kind"]
-    return 0.0 if k == H_CONST else (sizing["grad"] if k == H_LINEAR_FROM_POINT
+    return 0.0 if k == H_CONST else (sizing["grad"] if k in (H_LINEAR_FROM_POINT, H_SHELL)
                                      else sizing["h0"] * sizing["grad"])
 
 
@@ -561,6 +566,85 @@ def _build(name, dim, lo, hi, holes, sizing, params, n_total, seed, steps, res,
                     scale=s, steps=steps)
 
 
+def _build_ball(name, dim, lo, hi, sizing, params, n_total, seed, steps, res):
+    """The ball (disc) inscribed in the cube [lo, hi]^dim: feature 0 the volume
+    inside, feature 1 its sphere (circle).  Counts from the mass integrals of
+    h^-k as for the box (reading R25); positions by rejection sampling with
+    probability proportional to rho_t (sec. 3.6)."""
+    lo = np.asarray(lo, float)
+    hi = np.asarray(hi, float)
+    c = 0.5 * (lo + hi)
+    R = 0.5 * (hi[0] - lo[0])
+    holes = np.zeros((0, 15))
+    types = np.asarray([VOL, CURVE if dim == 2 else SURF], np.int32)
+
+    def in_ball(p):
+        return np.sum((p[:, :dim] - c[:dim]) ** 2, axis=1) < R * R
+
+    def masses(sz):
+        axes = [lo[a] + (np.arange(res) + 0.5) * (hi[a] - lo[a]) / res for a in range(dim)]
+        cellv = ((hi[0] - lo[0]) / res) ** dim
+        M = {}
+        if dim == 2:
+            X, Y = np.meshgrid(axes[0], axes[1], indexing="ij")
+            pts = np.stack([X.ravel(), Y.ravel(), np.zeros(X.size)], 1)
+            M[0] = float(np.sum(_h_field(pts[in_ball(pts)], dim, sz, holes) ** -2.0) * cellv)
+            nseg = 4 * res
+            th = (np.arange(nseg) + 0.5) * 2 * np.pi / nseg
+            pts = np.stack([c[0] + R * np.cos(th), c[1] + R * np.sin(th), np.zeros(nseg)], 1)
+            M[1] = float(np.sum(_h_field(pts, dim, sz, holes) ** -1.0) * 2 * np.pi * R / nseg)
+        else:
+            tot = 0.0
+            for zi in axes[2]:
+                X, Y = np.meshgrid(axes[0], axes[1], indexing="ij")
+                pts = np.stack([X.ravel(), Y.ravel(), np.full(X.size, zi)], 1)
+                tot += float(np.sum(_h_field(pts[in_ball(pts)], dim, sz, holes) ** -3.0))
+            M[0] = tot * cellv
+            ct = -1 + (np.arange(res) + 0.5) * 2.0 / res          # equal-area bands
+            ph = (np.arange(2 * res) + 0.5) * np.pi / res
+            CT, PH = np.meshgrid(ct, ph, indexing="ij")
+            st = np.sqrt(1 - CT ** 2)
+            pts = np.stack([c[0] + R * st * np.cos(PH), c[1] + R * st * np.sin(PH),
+                            c[2] + R * CT], -1).reshape(-1, 3)
+            M[1] = float(np.sum(_h_field(pts, dim, sz, holes) ** -2.0) * 4 * np.pi * R * R
+                         / pts.shape[0])
+        return M
+
+    base = dict(sizing)
+    M = masses(base)
+    s = _solve_scale(M, types, n_total, dim)
+    sizing = dict(base)
+    if sizing["kind"] in (H_LINEAR_FROM_POINT, H_SHELL):
+        sizing["grad"] = base["grad"] * s
+    sizing["h0"] = base["h0"] * s
+    counts = _split_counts(M, types, s, n_total, dim)
+    rng = np.random.Generator(np.random.MT19937(seed))
+    hmin = _hmin(sizing, dim, lo, hi, holes)
+
+    def box_prop(m):
+        p = np.zeros((m, 3))
+        p[:, :dim] = lo[:dim] + rng.random((m, dim)) * (hi[:dim] - lo[:dim])
+        return p
+
+    def sphere_prop(m):
+        g = rng.standard_normal((m, dim))
+        g /= np.linalg.norm(g, axis=1, keepdims=True)
+        p = np.zeros((m, 3))
+        p[:, :dim] = c[:dim] + R * g
+        return p
+
+    pv = _sample_rejection(rng, counts[0], box_prop, dim, sizing, holes, dim, hmin,
+                           accept_mask=in_ball)
+    ps = _sample_rejection(rng, counts[1], sphere_prop, dim, sizing, holes, dim - 1, hmin)
+    xyz = np.ascontiguousarray(np.concatenate([pv, ps], 0))
+    feat = np.ascontiguousarray(np.concatenate([np.zeros(len(pv), np.int32),
+                                                np.ones(len(ps), np.int32)]))
+    assert xyz.shape[0] == n_total, (xyz.shape, n_total)
+    return Workload(name=name, dim=dim, lo=lo, hi=hi, holes=holes, sizing=sizing,
+                    params=params, xyz=xyz, feature=feat, ftype=types, counts=counts,
+                    scale=s, steps=steps, domain=1)
+
+
 def _hmin(sizing, dim, lo, hi, holes):
     """a lower bound of h over the domain (rejection sampling's envelope):
     every sizing kind here is h0 plus a non-negative term"""
@@ -697,6 +781,37 @@ def paper_square(n_total=2524, seed=6, res=512, **pover):
                   dict(kind=H_LINEAR_FROM_POINT, h0=hmin, grad=(hmax - hmin) / (100 * math.sqrt(2)),
                        dcap=np.inf, point=[100.0, 100.0, 0.0]),
                   default_params(**pover), n_total, seed, 0, res)
+
+
+def paper_sphere01(n_total=12540, seed=8, res=64, **pover):
+    """Sec. 4's "Sphere01": the ball of radius R = 45 (here centred in
+    [0,90]^3), h = h_min + (h_max - h_min) |x - x_1| / (2R) with x_1 the top
+    point of the sphere, h_min 0.375, h_max 7.5; 12,540 particles as in the
+    paper."""
+    R = 45.0
+    return _build_ball("paper_sphere01", 3, [0.0, 0.0, 0.0], [2 * R] * 3,
+                       dict(kind=H_LINEAR_FROM_POINT, h0=0.375, grad=(7.5 - 0.375) / (2 * R),
+                            dcap=np.inf, point=[R, R, 2 * R]),
+                       default_params(**pover), n_total, seed, 0, res)
+
+
+def paper_sphere02(n_total=26500, seed=9, res=64, **pover):
+    """Sec. 4's "Sphere02": the unit ball, h = 0.025 + 0.2 | |x| - 0.5 |
+    (h_min 0.025 on the sphere of radius 0.5, h_max 0.125).  The paper gives
+    no particle count (its mesh has 110,706 tetrahedra); 26,500 particles
+    put the sizing's scale at 1.000."""
+    return _build_ball("paper_sphere02", 3, [-1.0, -1.0, -1.0], [1.0, 1.0, 1.0],
+                       dict(kind=H_SHELL, h0=0.025, grad=0.2, dcap=0.5, point=[0.0, 0.0, 0.0]),
+                       default_params(**pover), n_total, seed, 0, res)
+
+
+def graded_disc(n_total=3000, seed=10, res=256, **pover):
+    """The unit disc (centred in [0,1]^2) with h graded linearly from a point
+    of its circle: a small 2D case of the ball domain."""
+    return _build_ball("graded_disc", 2, [0.0, 0.0, 0.0], [1.0, 1.0, 0.0],
+                       dict(kind=H_LINEAR_FROM_POINT, h0=0.01, grad=0.04, dcap=np.inf,
+                            point=[0.5, 1.0, 0.0]),
+                       default_params(**pover), n_total, seed, 0, res)
 
 
 def paper_cube(n_total=66038, seed=7, res=96, **pover):

@@ -5,6 +5,8 @@ of the domain size for the FP64 path and 1e-5 for the FP32-mixed path;
 control law identical.  Every case is seeded and synthetic (see
 paper_2003_01061_amd.workload).
 """
+import copy
+
 import numpy as np
 import pytest
 
@@ -123,6 +125,32 @@ def test_positions_after_k_steps_fp64(name):
     assert gpu.counters()["interactions"] == ref.counters()["interactions"]
     assert gpu.counters()["escaped"] == ref.counters()["escaped"]
     assert gpu.error()["step"] == K
+
+
+# other values of the two calibrated readings: the cut-off radius r_c = c h
+# (the kernel's reach) and the factor s on the boundary term
+READINGS = [("square64", 2.0, 1.0, 60), ("hole2d_20011", 3.0, 2.0, 20),
+            ("ball3d_30011", 2.0, 1.0, 8), ("paper_square", 2.25, 1.5, 60)]
+
+
+@pytest.mark.parametrize("name,c,s,K", READINGS)
+def test_kernel_reach_and_boundary_factor_follow_the_oracle(name, c, s, K):
+    wl = copy.copy(case(name))
+    wl.params = dict(wl.params, kernel_support=c, boundary_scale=s)
+    ref = oracle.RefJob(wl)
+    off_r, ids_r, rel_r = ref.neighbors()
+    gpu = binding.SphMesh(wl, use_graph=1)
+    off_g, ids_g, rel_g = gpu.neighbors()
+    assert np.array_equal(off_g, off_r)
+    assert np.array_equal(ids_g, ids_r)
+    assert np.array_equal(rel_g, rel_r)
+    ref.step(K)
+    gpu.step(K)
+    xr, _ = ref.state()
+    xg, _ = gpu.state()
+    err = np.abs(xg - xr).max() / domain(wl)
+    assert err <= TOL64, err
+    assert gpu.counters()["interactions"] == ref.counters()["interactions"]
 
 
 @pytest.mark.parametrize("name", list(CASES))
