@@ -57,7 +57,8 @@ typedef enum {
 } sph_status;
 
 enum { SPH_P_SINGULAR = 0, SPH_P_CURVE = 1, SPH_P_SURFACE = 2, SPH_P_VOLUME = 3 };
-enum { SPH_H_CONST = 0, SPH_H_LINEAR_FROM_POINT = 1, SPH_H_GRADED_TO_HOLES = 2 };
+enum { SPH_H_CONST = 0, SPH_H_LINEAR_FROM_POINT = 1, SPH_H_GRADED_TO_HOLES = 2, SPH_H_SHELL = 3 };
+enum { SPH_DOMAIN_BOX = 0, SPH_DOMAIN_BALL = 1 };
 enum { SPH_FP64 = 0, SPH_FP32_MIXED = 1 };
 
 /* Geometry (paper sec. 2.1 / 3.1): the level set phi > 0 is the box minus
@@ -75,6 +76,12 @@ typedef struct {
   double lo[3], hi[3];
   int32_t n_holes;
   const double *holes;
+  int32_t domain;            /* SPH_DOMAIN_BOX (0): the box minus the holes,
+                                features as numbered above.
+                                SPH_DOMAIN_BALL (1): the ball (disc) inscribed
+                                in the box, as for sec. 4's sphere cases; the
+                                box must be a cube and there are no holes;
+                                features 0 volume, 1 its sphere (circle) */
 } sph_geometry;
 
 /* Target feature size h_t(x) (paper sec. 2.2):
@@ -82,6 +89,9 @@ typedef struct {
  *   SPH_H_LINEAR_FROM_POINT: h = h0 + grad |x - point|
  *   SPH_H_GRADED_TO_HOLES:   h = h0 (1 + grad min(d, dcap)), d = distance to
  *                            the nearest hole boundary.
+ *   SPH_H_SHELL:             h = h0 + grad | |x - point| - dcap |, graded both
+ *                            ways from the sphere of radius dcap about point
+ *                            (sec. 4's Sphere02).
  * Evaluated in FP64 with the operation order: squared distances summed over
  * axes in order, then sqrt; no fused multiply-add. */
 typedef struct {

@@ -20,7 +20,8 @@ FIELD_H, FIELD_AP, FIELD_A, FIELD_VT, FIELD_GAMMA, FIELD_VMID = range(6)
 
 class Geometry(C.Structure):
     _fields_ = [("dim", C.c_int32), ("lo", C.c_double * 3), ("hi", C.c_double * 3),
-                ("n_holes", C.c_int32), ("holes", C.POINTER(C.c_double))]
+                ("n_holes", C.c_int32), ("holes", C.POINTER(C.c_double)),
+                ("domain", C.c_int32)]
 
 
 class Sizing(C.Structure):
@@ -120,7 +121,7 @@ def _check(fn, status):
         raise SphError(fn, status, lib().sph_mesh_last_error().decode())
 
 
-def make_geometry(dim, lo, hi, holes):
+def make_geometry(dim, lo, hi, holes, domain=0):
     holes = np.ascontiguousarray(np.asarray(holes, np.float64).reshape(-1, 15))
     g = Geometry()
     g.dim = dim
@@ -129,6 +130,7 @@ def make_geometry(dim, lo, hi, holes):
         g.hi[a] = float(hi[a]) if a < len(hi) else 0.0
     g.n_holes = holes.shape[0]
     g.holes = holes.ctypes.data_as(_dp) if holes.size else None
+    g.domain = int(domain)
     g._keep = holes
     return g
 
@@ -174,7 +176,7 @@ class SphMesh:
         p = dict(wl.params if params is None else params)
         p.update(over)
         self.dim = wl.dim
-        self._geom = make_geometry(wl.dim, wl.lo, wl.hi, wl.holes)
+        self._geom = make_geometry(wl.dim, wl.lo, wl.hi, wl.holes, wl.domain)
         self._sizing = make_sizing(wl.sizing)
         self._params = make_params(p, stream)
         xyz = np.ascontiguousarray(wl.xyz if xyz is None else xyz, np.float64)
@@ -305,7 +307,7 @@ class JobSpec:
         p = dict(wl.params if params is None else params)
         p.update(over)
         self.dim = wl.dim
-        self.geom = make_geometry(wl.dim, wl.lo, wl.hi, wl.holes)
+        self.geom = make_geometry(wl.dim, wl.lo, wl.hi, wl.holes, wl.domain)
         self.sizing = make_sizing(wl.sizing)
         self.params = make_params(p)
         self.xyz = np.ascontiguousarray(wl.xyz if xyz is None else xyz, np.float64)

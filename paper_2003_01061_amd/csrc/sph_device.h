@@ -36,7 +36,7 @@ static_assert(SPH_NBATCH >= 1 && SPH_NBATCH <= 8, "records are padded by 8");
 #endif
 
 enum : int { T_SI = 0, T_C = 1, T_S = 2, T_V = 3 };
-enum : int { K_VOL = 0, K_BOXSIDE = 1, K_HOLE = 2, K_EDGE3 = 3, K_CORNER = 4 };
+enum : int { K_VOL = 0, K_BOXSIDE = 1, K_HOLE = 2, K_EDGE3 = 3, K_CORNER = 4, K_SHELL = 5 };
 enum : int { PH_ONE = 1, PH_RAMP = 2, PH_TWO = 3, PH_FROZEN = 4 };
 
 // one feature: the paper's (type, index) pair and what its geometry is
@@ -45,8 +45,9 @@ struct Feat {
 };
 
 // outward normal n_b of feature fi's boundary at a particle of feature fb
-// (paper sec. 3.3): mode 0 no relation, 1 the constant vector n, 2 the unit
-// vector from the particle to the centre of hole `hole` (out of the domain)
+// (paper sec. 3.3): mode 0 no relation, 1 the constant vector n; 2 (a ball
+// hole), 3 (an ellipsoidal hole) and 4 (the ball domain's sphere) the
+// particle's own normal out of the domain, which k_rank_gather stores
 struct BNorm {
   int32_t mode, hole;
   double n[3];
@@ -62,6 +63,8 @@ struct Geom {
   double ha[MAXH][3];       // its semi-axes, and max over them
   double hamax[MAXH], hamin[MAXH];   // largest / smallest semi-axis of an ellipsoid
   double hR[MAXH][9];       // rotation, row-major: local y = R (x - c)
+  int32_t domain, pad;      // 0 box minus holes, 1 the ball inscribed in the box
+  double dc[3], dR;         // ball domain: centre and radius
 };
 
 // uniform cell grid over a job's box; its cells own the global cell ids
@@ -331,6 +334,14 @@ __device__ __forceinline__ double h_target(const Geom &g, const double *p) {
     }
     return g.h0 + g.grad * __builtin_sqrt(s);
   }
+  if (g.hkind == 3) {   // graded both ways from the sphere |x - point| = dcap
+    double s = 0.0;
+    for (int a = 0; a < D; ++a) {
+      double d = p[a] - g.hpt[a];
+      s = s + d * d;
+    }
+    return g.h0 + g.grad * __builtin_fabs(__builtin_sqrt(s) - g.dcap);
+  }
   // |x - c| - min a bounds an ellipsoid's distance from above (its inscribed
   // ball) and |x - c| - max a from below.  An ellipsoid whose lower bound
   // exceeds the smallest upper bound (or the cap) by a relative 1e-12 cannot
@@ -556,6 +567,29 @@ __device__ __forceinline__ void tangent(const Geom &g, const Feat &F, const doub
       }
       return;
     }
+    case K_SHELL: {   // the ball domain's sphere: as a ball hole about dc
+      const double *c = g.dc;
+      if (D == 2) {
+        double t0 = -(x[1] - c[1]), t1 = x[0] - c[0];
+        double il = 1.0 / __builtin_sqrt(t0 * t0 + t1 * t1);
+        t0 *= il;
+        t1 *= il;
+        double ut = u[0] * t0 + u[1] * t1;
+        u[0] = ut * t0;
+        u[1] = ut * t1;
+      } else {
+        double m0 = x[0] - c[0], m1 = x[1] - c[1], m2 = x[2] - c[2];
+        double il = 1.0 / __builtin_sqrt(m0 * m0 + m1 * m1 + m2 * m2);
+        m0 *= il;
+        m1 *= il;
+        m2 *= il;
+        double un = u[0] * m0 + u[1] * m1 + u[2] * m2;
+        u[0] -= un * m0;
+        u[1] -= un * m1;
+        u[2] -= un * m2;
+      }
+      return;
+    }
     default: u[0] = u[1] = u[2] = 0.0; return;
   }
 }
@@ -595,14 +629,33 @@ __device__ __forceinline__ void project(const Geom &g, const Feat &F, double *x)
     case K_CORNER:
       for (int a = 0; a < D; ++a) x[a] = ((F.bits >> a) & 1) ? g.hi[a] : g.lo[a];
       return;
+    case K_SHELL: {
+      double d[3] = {0.0, 0.0, 0.0}, s = 0.0;
+      for (int a = 0; a < D; ++a) {
+        d[a] = x[a] - g.dc[a];
+        s += d[a] * d[a];
+      }
+      double r = __builtin_sqrt(s);
+      for (int a = 0; a < D; ++a) x[a] = g.dc[a] + g.dR * (d[a] / r);
+      return;
+    }
     default: return;
   }
 }
 
-// phi(x) > 0: strictly inside the box, strictly outside every hole
+// phi(x) > 0: strictly inside the box, strictly outside every hole; or
+// strictly inside the ball domain
 template <int D>
 __device__ __forceinline__ bool inside(const Geom &g, const double *x) {
 #pragma clang fp contract(off)
+  if (g.domain == 1) {
+    double s = 0.0;
+    for (int a = 0; a < D; ++a) {
+      double d = x[a] - g.dc[a];
+      s = s + d * d;
+    }
+    return s < g.dR * g.dR;
+  }
   for (int a = 0; a < D; ++a)
     if (!(x[a] > g.lo[a] && x[a] < g.hi[a])) return false;
   for (int q = 0; q < g.nh; ++q) {

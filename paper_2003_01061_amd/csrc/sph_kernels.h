@@ -346,7 +346,12 @@ __global__ __launch_bounds__(BLOCK) void k_rank_gather(Batch B, int n, const uin
   // set's gradient for an ellipse or ellipsoid
   if (B.has_hole) {
     const Feat F = B.feat[f];
-    if (F.kind == K_HOLE) {
+    if (F.kind == K_SHELL) {   // the ball domain's sphere: radially outwards
+      const double *cc = B.jobs[f / MAXF].g.dc;
+      const double d0 = xh.x - cc[0], d1 = xh.y - cc[1], d2 = D == 3 ? xh.z - cc[2] : 0.0;
+      const double il = 1.0 / __builtin_sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+      B.enrm[dst] = make_double4(d0 * il, d1 * il, d2 * il, 0.0);
+    } else if (F.kind == K_HOLE) {
       const Geom &g = B.jobs[f / MAXF].g;
       double4 e;
       if (g.hell[F.hole]) {
@@ -435,7 +440,7 @@ __device__ __forceinline__ void sweep_a_sums(const Geom &g, const Parts &s,
           const int fj = s.f[u[q] & 0x7fffffffu];
           const BNorm N = bnrow[fj & (MAXF - 1)];
           double nv[3];
-          if (N.mode >= 2) {   // a hole's boundary: the normal k_rank_gather stored
+          if (N.mode >= 2) {   // a curved boundary: the normal k_rank_gather stored
             const double4 e = enrm[u[q] & 0x7fffffffu];
             nv[0] = e.x;
             nv[1] = e.y;

@@ -65,9 +65,13 @@ struct HFeat {
   int ell = 0;   // HOLE: the hole is an ellipsoid
 };
 
-std::vector<HFeat> make_features(int D, int nh) {
+std::vector<HFeat> make_features(int D, int nh, int domain) {
   std::vector<HFeat> F;
   F.push_back({T_V, D, K_VOL});
+  if (domain == SPH_DOMAIN_BALL) {   // the volume and its sphere
+    F.push_back({D == 2 ? T_C : T_S, D - 1, K_SHELL});
+    return F;
+  }
   for (int a = 0; a < D; ++a)
     for (int s = 0; s < 2; ++s) {
       HFeat f{D == 2 ? T_C : T_S, D - 1, K_BOXSIDE};
@@ -126,6 +130,8 @@ BNorm boundary_normal(int D, const HFeat &A, const HFeat &B) {
     } else if (B.kind == K_HOLE) {
       N.mode = B.ell ? 3 : 2;
       N.hole = B.hole;
+    } else if (B.kind == K_SHELL) {
+      N.mode = 4;   // radially out of the ball, stored per particle
     } else if (B.kind == K_EDGE3) {
       const double r = std::sqrt(0.5);
       N.n[B.fax[0]] = sg(B.fsd[0]) * r;
@@ -200,7 +206,18 @@ static sph_status validate(const sph_geometry *g, const sph_sizing *s, const sph
       if (!(H[a] - amax > g->lo[a] && H[a] + amax < g->hi[a]))
         return fail(SPH_ERR_INVALID_ARG, "hole %d must lie strictly inside the box", q);
   }
-  if (s->kind < 0 || s->kind > 2) return fail(SPH_ERR_INVALID_ARG, "unknown sizing kind");
+  if (g->domain != SPH_DOMAIN_BOX && g->domain != SPH_DOMAIN_BALL)
+    return fail(SPH_ERR_INVALID_ARG, "domain must be SPH_DOMAIN_BOX or SPH_DOMAIN_BALL");
+  if (g->domain == SPH_DOMAIN_BALL) {
+    if (g->n_holes != 0) return fail(SPH_ERR_INVALID_ARG, "a ball domain takes no holes");
+    const double e0 = g->hi[0] - g->lo[0];
+    for (int a = 1; a < g->dim; ++a)
+      if (!(std::fabs((g->hi[a] - g->lo[a]) - e0) <= 1e-12 * e0))
+        return fail(SPH_ERR_INVALID_ARG, "a ball domain needs a cubic box");
+  }
+  if (s->kind < 0 || s->kind > 3) return fail(SPH_ERR_INVALID_ARG, "unknown sizing kind");
+  if (s->kind == 3 && !std::isfinite(s->dcap))
+    return fail(SPH_ERR_INVALID_ARG, "shell sizing needs a finite radius dcap");
   if (!(p->kernel_support == 0.0 || (p->kernel_support >= 1.0 && p->kernel_support <= 8.0)))
     return fail(SPH_ERR_INVALID_ARG, "kernel_support must be 0 or in [1, 8]");
   if (!(p->boundary_scale == 0.0 || (p->boundary_scale >= 0.25 && p->boundary_scale <= 8.0)))
@@ -242,14 +259,16 @@ static void sizing_bounds(const sph_geometry *g, const sph_sizing *s, double &hm
     lip = 0.0;
     return;
   }
-  if (s->kind == 1) {
+  if (s->kind == 1 || s->kind == 3) {
     double far = 0.0;
     for (int c = 0; c < (1 << D); ++c) {
       double d2 = 0.0;
       for (int a = 0; a < D; ++a) d2 += (corner(c, a) - s->point[a]) * (corner(c, a) - s->point[a]);
       far = std::max(far, std::sqrt(d2));
     }
-    hmax = s->h0 + s->grad * far;
+    // the farthest point of the box from `point` bounds | |x - point| - dcap |
+    // by max(far - dcap, dcap)
+    hmax = s->h0 + s->grad * (s->kind == 1 ? far : std::max(far - s->dcap, s->dcap));
     lip = s->grad;
     return;
   }
@@ -372,7 +391,7 @@ struct sph_batch {
     B.has_hole = 0;
     for (int j = 0; j < njobs; ++j)
       if (jobs[j].live)
-        for (const HFeat &F : jobs[j].feats) B.has_hole |= F.kind == K_HOLE;
+        for (const HFeat &F : jobs[j].feats) B.has_hole |= F.kind == K_HOLE || F.kind == K_SHELL;
     return B;
   }
   uint32_t ntiles() const { return (ncell + SCAN_TILE - 1) / SCAN_TILE; }
@@ -626,7 +645,7 @@ static void grid_of(const sph_geometry *g, const sph_sizing *s, const sph_params
 static void fill_job(HostJob &J, const sph_geometry *g, const sph_sizing *s, const sph_params *p,
                      uint32_t cbase, int n) {
   const int D = g->dim;
-  J.feats = make_features(D, g->n_holes);
+  J.feats = make_features(D, g->n_holes, g->domain);
   for (HFeat &F : J.feats)
     if (F.kind == K_HOLE) F.ell = hole_is_ellipsoid(D, g->holes + 15 * F.hole) ? 1 : 0;
   J.nf = (int)J.feats.size();
@@ -638,6 +657,11 @@ static void fill_job(HostJob &J, const sph_geometry *g, const sph_sizing *s, con
   G.nf = J.nf;
   G.nh = g->n_holes;
   G.hkind = s->kind;
+  G.domain = g->domain;
+  if (g->domain == SPH_DOMAIN_BALL) {
+    for (int a = 0; a < D; ++a) G.dc[a] = 0.5 * (g->lo[a] + g->hi[a]);
+    G.dR = 0.5 * (g->hi[0] - g->lo[0]);
+  }
   for (int a = 0; a < 3; ++a) {
     G.lo[a] = g->lo[a];
     G.hi[a] = g->hi[a];
@@ -694,7 +718,7 @@ static sph_status check_particles(const sph_geometry *g, int64_t n, const double
                                   const int32_t *feature) {
   if (n < 0 || n > 0x7ffffff0ll || (n > 0 && (!xyz || !feature)))
     return fail(SPH_ERR_INVALID_ARG, "bad particle count or NULL particle arrays");
-  const int nf = (int)make_features(g->dim, g->n_holes).size();
+  const int nf = (int)make_features(g->dim, g->n_holes, g->domain).size();
   if (nf > MAXF) return fail(SPH_ERR_UNSUPPORTED, "too many features (%d > %d)", nf, MAXF);
   for (int64_t i = 0; i < n; ++i) {
     if (feature[i] < 0 || feature[i] >= nf)
@@ -858,7 +882,7 @@ extern "C" sph_status sph_batch_add(sph_batch *b, const sph_geometry *g, const s
   if (g->dim != b->D) return fail(SPH_ERR_INVALID_ARG, "job dimension %d != batch dimension %d",
                                   g->dim, b->D);
   if (sph_status st = check_particles(g, n, xyz, feature)) return st;
-  const int nf = (int)make_features(g->dim, g->n_holes).size();
+  const int nf = (int)make_features(g->dim, g->n_holes, g->domain).size();
   int slot = -1;
   for (int j = 0; j < b->jcap; ++j)
     if (!b->jobs[j].live) {

@@ -4,7 +4,7 @@ The particles are the mesh vertices.  As in the paper's sec. 4, connectivity
 is built only after the run, to measure quality: here a Delaunay
 triangulation / tetrahedralisation of the final positions (scipy, Qhull),
 keeping the elements whose centroid lies in the domain (the box minus its
-holes).  The relaxation never uses it.
+holes, or the ball inscribed in the box).  The relaxation never uses it.
 
 Triangles (sec. 4): G = 2 sqrt(3) S / (P H), with S the area, P the
 half-perimeter and H the longest edge (G = 1 for an equilateral triangle),
@@ -23,11 +23,16 @@ from __future__ import annotations
 import numpy as np
 
 
-def inside_domain(pts, dim, lo, hi, holes):
+def inside_domain(pts, dim, lo, hi, holes, domain=0):
     """Strictly inside the box [lo, hi]^dim and outside every hole (hole
     records: centre[3], semi-axes[3], rotation[9] row-major with local
-    coordinates y = rot (x - centre); the hole is sum (y_k / a_k)^2 <= 1)."""
+    coordinates y = rot (x - centre); the hole is sum (y_k / a_k)^2 <= 1);
+    for domain 1, strictly inside the ball inscribed in the box."""
     pts = np.asarray(pts, float)
+    if domain == 1:
+        c = 0.5 * (np.asarray(lo, float)[:dim] + np.asarray(hi, float)[:dim])
+        R = 0.5 * (float(hi[0]) - float(lo[0]))
+        return np.sum((pts[:, :dim] - c) ** 2, axis=1) < R * R
     ok = np.all((pts[:, :dim] > np.asarray(lo)[:dim]) & (pts[:, :dim] < np.asarray(hi)[:dim]), axis=1)
     for rec in np.asarray(holes, float).reshape(-1, 15):
         R = rec[6:15].reshape(3, 3)[:dim, :dim]
@@ -106,7 +111,7 @@ def summarize_tets(gamma, dih):
                 slivers={str(t): int(np.sum(dmin < t)) for t in (10, 20, 30, 40)})
 
 
-def mesh_quality(xyz, dim, lo, hi, holes, region=None):
+def mesh_quality(xyz, dim, lo, hi, holes, region=None, domain=0):
     """Delaunay mesh of the positions xyz (n x 3) and its quality summary.
     region = (rlo, rhi) restricts the measure to elements whose centroid lies
     in that sub-box (a sample of a mesh too large to tetrahedralise whole:
@@ -121,7 +126,7 @@ def mesh_quality(xyz, dim, lo, hi, holes, region=None):
     simp = Delaunay(P).simplices
     cen = np.zeros((len(simp), 3))
     cen[:, :dim] = P[simp].mean(1)
-    ok = inside_domain(cen, dim, lo, hi, holes)
+    ok = inside_domain(cen, dim, lo, hi, holes, domain)
     if region is not None:
         ok &= np.all((cen[:, :dim] > rlo) & (cen[:, :dim] < rhi), axis=1)
     simp = simp[ok]

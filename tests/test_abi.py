@@ -51,11 +51,33 @@ def test_invalid_arguments_fail_before_touching_the_gpu():
         binding.SphMesh(wl)
 
 
-def test_struct_layout_matches_header():
-    """ctypes mirrors of the header structs have the C sizes."""
+def test_struct_layout_matches_header(tmp_path):
+    """The ctypes mirrors have the header structs' size and every field's
+    offset, as a C compiler lays them out (gcc on include/sph_mesh.h)."""
+    import shutil
+    import subprocess
     from paper_2003_01061_amd import binding
-    assert ctypes.sizeof(binding.Geometry) == 4 + 4 + 48 + 8 + 8   # padded
-    assert ctypes.sizeof(binding.Sizing) == 8 + 24 + 24
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    pairs = [(binding.Geometry, "sph_geometry"), (binding.Sizing, "sph_sizing"),
+             (binding.Params, "sph_params"), (binding.BatchParams, "sph_batch_params")]
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "sph_mesh.h"', "int main(void) {"]
+    for cls, cname in pairs:
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    subprocess.run(["gcc", "-I", os.path.join(root, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(l.rsplit(" ", 1) for l in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                        text=True).stdout.splitlines())
+    for cls, cname in pairs:
+        assert int(got[f"{cname} size"]) == ctypes.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert int(got[f"{cname} {fname}"]) == getattr(cls, fname).offset, (cname, fname)
 
 
 def test_batch_footprint_and_job_cells_are_host_logic():

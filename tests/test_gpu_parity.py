@@ -33,9 +33,16 @@ CASES = {
     # linear from a corner, ratio 1:20 / 1:10
     "paper_square": lambda: wk.paper_square(),
     "paper_cube": lambda: wk.paper_cube(),
+    # the ball domain (sec. 4's sphere cases): a graded disc, Sphere01 (h
+    # linear from a point of the sphere) and Sphere02 (h graded both ways
+    # from the sphere of radius 0.5)
+    "graded_disc": lambda: wk.graded_disc(),
+    "paper_sphere01": lambda: wk.paper_sphere01(),
+    "paper_sphere02": lambda: wk.paper_sphere02(),
 }
 KSTEPS = {"square64": 200, "hole2d_20011": 60, "ball3d_30011": 25, "ell2d_20011": 60,
-          "ell3d_30011": 20, "paper_square": 150, "paper_cube": 6}
+          "ell3d_30011": 20, "paper_square": 150, "paper_cube": 6, "graded_disc": 60,
+          "paper_sphere01": 10, "paper_sphere02": 6}
 
 _wl_cache = {}
 

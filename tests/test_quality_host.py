@@ -97,3 +97,13 @@ def test_region_sample_matches_the_whole_mesh_inside_it():
                           region=([0.3, 0.3, 0.3], [0.7, 0.7, 0.7]))
     assert 0 < part["n_elements"] < whole["n_elements"]
     assert part["gamma_min"] >= whole["gamma_min"]
+
+
+def test_ball_domain_filter():
+    """domain 1: strictly inside the ball inscribed in the box"""
+    rng = np.random.default_rng(3)
+    xyz = rng.uniform(0.0, 2.0, (5000, 3))
+    keep = q.inside_domain(xyz, 3, [0, 0, 0], [2, 2, 2], np.zeros((0, 15)), domain=1)
+    assert np.array_equal(keep, np.sum((xyz - 1.0) ** 2, axis=1) < 1.0)
+    keep2 = q.inside_domain(xyz, 2, [0, 0, 0], [2, 2, 0], np.zeros((0, 15)), domain=1)
+    assert np.array_equal(keep2, np.sum((xyz[:, :2] - 1.0) ** 2, axis=1) < 1.0)
