@@ -464,6 +464,60 @@ static int inside(const geo_t *G, const double *x) {
 /* ------------------------------------------------------------------ */
 /* target feature size h_t(x) (sec. 2.2; h_i = h_t(x_i) each step)       */
 /* ------------------------------------------------------------------ */
+
+/* h sampled on a Cartesian background grid (sec. 2.2 computes h_t on the
+ * background mesh), interpolated multilinearly: along x between the nodes
+ * of the cell, then along y between those results, then along z */
+static double grid_h(const sphref_sizing *S, int D, const double *x) {
+  int c[3] = {0, 0, 0};
+  double t[3] = {0.0, 0.0, 0.0};
+  for (int a = 0; a < D; ++a) {
+    int n = S->grid_n[a];
+    double s = (double)(n - 1) / (S->grid_hi[a] - S->grid_lo[a]);
+    double u = (x[a] - S->grid_lo[a]) * s;
+    if (!(u > 0.0)) u = 0.0;                 /* also a NaN */
+    if (u > (double)(n - 1)) u = (double)(n - 1);
+    double f = floor(u);
+    if (f > (double)(n - 2)) f = (double)(n - 2);
+    c[a] = (int)f;
+    t[a] = u - f;
+  }
+  int nx = S->grid_n[0], ny = S->grid_n[1];
+  double v[2][2];                            /* [z corner][y corner], lerped along x */
+  for (int dz = 0; dz < (D == 3 ? 2 : 1); ++dz)
+    for (int dy = 0; dy < 2; ++dy) {
+      int64_t row = ((int64_t)(c[2] + dz) * ny + (c[1] + dy)) * nx + c[0];
+      double g0 = S->grid[row], g1 = S->grid[row + 1];
+      v[dz][dy] = g0 + t[0] * (g1 - g0);
+    }
+  double w0 = v[0][0] + t[1] * (v[0][1] - v[0][0]);
+  if (D == 2) return w0;
+  double w1 = v[1][0] + t[1] * (v[1][1] - v[1][0]);
+  return w0 + t[2] * (w1 - w0);
+}
+
+/* a bound of |grad h| for the gridded sizing: the multilinear interpolant's
+ * derivative along axis a is a weighted mean of node differences along a */
+static double grid_lipschitz(const sphref_sizing *S, int D) {
+  double sum = 0.0;
+  int n[3] = {S->grid_n[0], S->grid_n[1], D == 3 ? S->grid_n[2] : 1};
+  for (int a = 0; a < D; ++a) {
+    double m = 0.0;
+    int st = a == 0 ? 1 : (a == 1 ? n[0] : n[0] * n[1]);
+    for (int k = 0; k < n[2]; ++k)
+      for (int j = 0; j < n[1]; ++j)
+        for (int i = 0; i < n[0]; ++i) {
+          int id[3] = {i, j, k};
+          if (id[a] + 1 >= n[a]) continue;
+          int64_t p = ((int64_t)k * n[1] + j) * n[0] + i;
+          double d = fabs(S->grid[p + st] - S->grid[p]);
+          if (d > m) m = d;
+        }
+    double g = m * (double)(n[a] - 1) / (S->grid_hi[a] - S->grid_lo[a]);
+    sum = sum + g * g;
+  }
+  return sqrt(sum);
+}
 static double h_at(const geo_t *G, const sphref_sizing *S, const double *x) {
   int D = G->dim;
   if (S->kind == 0) return S->h0;
@@ -472,6 +526,7 @@ static double h_at(const geo_t *G, const sphref_sizing *S, const double *x) {
     for (int a = 0; a < D; ++a) { double d = x[a] - S->point[a]; s = s + d * d; }
     return S->h0 + S->grad * sqrt(s);
   }
+  if (S->kind == 4) return grid_h(S, D, x);
   if (S->kind == 3) {     /* graded both ways from the sphere |x - point| = dcap */
     double s = 0.0;
     for (int a = 0; a < D; ++a) { double d = x[a] - S->point[a]; s = s + d * d; }
@@ -980,9 +1035,10 @@ static double h_of(sphref_job *J, int64_t j) {
 }
 
 /* Lipschitz constant of h_t: |grad d| <= 1 for the distance to the holes */
-static double h_lipschitz(const sphref_sizing *S) {
+static double h_lipschitz(const sphref_sizing *S, int D) {
   if (S->kind == 0) return 0.0;
   if (S->kind == 1 || S->kind == 3) return S->grad;
+  if (S->kind == 4) return grid_lipschitz(S, D);
   return S->h0 * S->grad;
 }
 
@@ -996,7 +1052,7 @@ static int64_t brute_list_lazy(sphref_job *J, int64_t i, int32_t *ids, int8_t *r
   if (ftype(J, i) == T_SI) return 0;
   int D = J->G.dim;
   double hi = h_of(J, i);
-  double L = h_lipschitz(&J->S);
+  double L = h_lipschitz(&J->S, J->G.dim);
   double R2 = INFINITY;
   double cr = rc_ratio(&J->P);
   if (cr * L < 1.0) { double R = cr * hi / (1.0 - cr * L); R2 = R * R * (1.0 + 1e-9); }

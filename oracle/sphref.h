@@ -55,11 +55,19 @@ typedef struct {
  * kind 1: h = h0 + grad * |x - point|
  * kind 2: h = h0 * (1 + grad * min(d, dcap)), d = distance to the nearest hole
  * kind 3: h = h0 + grad * | |x - point| - dcap |, graded both ways from the
- *         sphere of radius dcap about point */
+ *         sphere of radius dcap about point
+ * kind 4: h sampled at the nodes of a Cartesian grid over [grid_lo, grid_hi]
+ *         (grid_n nodes per axis, x fastest), interpolated multilinearly:
+ *         per axis s = (n - 1) / (hi - lo), u = (x - lo) s clamped to
+ *         [0, n - 1], cell c = min(floor(u), n - 2), t = u - c; then
+ *         lerp(a, b, t) = a + t (b - a) along x, then y, then z */
 typedef struct {
   int32_t kind;
   double h0, grad, dcap;
   double point[3];
+  const double *grid;
+  int32_t grid_n[3];
+  double grid_lo[3], grid_hi[3];
 } sphref_sizing;
 
 typedef struct {

@@ -31,7 +31,7 @@ import numpy as np
 SI, CURVE, SURF, VOL = 0, 1, 2, 3
 
 # sizing kinds
-H_CONST, H_LINEAR_FROM_POINT, H_GRADED_TO_HOLES, H_SHELL = 0, 1, 2, 3
+H_CONST, H_LINEAR_FROM_POINT, H_GRADED_TO_HOLES, H_SHELL, H_GRID = 0, 1, 2, 3, 4
 
 
 def default_params(**over):
@@ -218,6 +218,8 @@ def _h_field(pts, dim, sizing, holes):
     if kind == H_LINEAR_FROM_POINT:
         p = np.asarray(sizing["point"][:dim])
         return sizing["h0"] + sizing["grad"] * np.linalg.norm(pts[:, :dim] - p, axis=1)
+    if kind == H_GRID:
+        return _grid_h(pts, dim, sizing)
     if kind == H_SHELL:
         p = np.asarray(sizing["point"][:dim])
         r = np.linalg.norm(pts[:, :dim] - p, axis=1)
@@ -235,6 +237,66 @@ def _h_field(pts, dim, sizing, holes):
     return sizing["h0"] * (1.0 + sizing["grad"] * d)
 
 
+def _grid_h(pts, dim, sizing):
+    """multilinear interpolation of the node values (the library's order:
+    along x, then y, then z; coordinates clamped to the grid box)"""
+    g = np.asarray(sizing["grid"], float).reshape(sizing["grid_n"][::-1])
+    c, t = [], []
+    for a in range(dim):
+        n = int(sizing["grid_n"][a])
+        sc = (n - 1) / (sizing["grid_hi"][a] - sizing["grid_lo"][a])
+        u = np.clip((pts[:, a] - sizing["grid_lo"][a]) * sc, 0.0, n - 1)
+        f = np.minimum(np.floor(u), n - 2)
+        c.append(f.astype(np.int64))
+        t.append(u - f)
+    if dim == 2:
+        g2 = g[0]
+        v0 = g2[c[1], c[0]] + t[0] * (g2[c[1], c[0] + 1] - g2[c[1], c[0]])
+        v1 = g2[c[1] + 1, c[0]] + t[0] * (g2[c[1] + 1, c[0] + 1] - g2[c[1] + 1, c[0]])
+        return v0 + t[1] * (v1 - v0)
+    w = []
+    for dz in (0, 1):
+        a0 = g[c[2] + dz, c[1], c[0]]
+        a1 = g[c[2] + dz, c[1], c[0] + 1]
+        b0 = g[c[2] + dz, c[1] + 1, c[0]]
+        b1 = g[c[2] + dz, c[1] + 1, c[0] + 1]
+        v0 = a0 + t[0] * (a1 - a0)
+        v1 = b0 + t[0] * (b1 - b0)
+        w.append(v0 + t[1] * (v1 - v0))
+    return w[0] + t[2] * (w[1] - w[0])
+
+
+def _grid_lipschitz(sizing, dim):
+    g = np.asarray(sizing["grid"], float).reshape(sizing["grid_n"][::-1])
+    tot = 0.0
+    for a in range(dim):
+        d = np.abs(np.diff(g, axis=2 - a)).max() if g.shape[2 - a] > 1 else 0.0
+        tot += (d * (sizing["grid_n"][a] - 1) / (sizing["grid_hi"][a] - sizing["grid_lo"][a])) ** 2
+    return math.sqrt(tot)
+
+
+def with_grid_sizing(wl, n):
+    """The workload with its sizing sampled at the nodes of an n^dim grid over
+    its box and interpolated multilinearly (sec. 2.2 keeps h_t on a Cartesian
+    background mesh).  Positions and features are kept."""
+    dim = wl.dim
+    gn = [n, n, n if dim == 3 else 1]
+    ax = [wl.lo[a] + np.arange(gn[a]) * (wl.hi[a] - wl.lo[a]) / (gn[a] - 1) if gn[a] > 1
+          else np.zeros(1) for a in range(3)]
+    Z, Y, X = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
+    pts = np.stack([X.ravel(), Y.ravel(), Z.ravel()], 1)
+    vals = _h_field(pts, dim, wl.sizing, wl.holes)
+    sz = dict(kind=H_GRID, h0=float(vals.min()), grad=0.0, dcap=0.0, point=[0.0, 0.0, 0.0],
+              grid=np.ascontiguousarray(vals), grid_n=gn,
+              grid_lo=[float(wl.lo[a]) if a < dim else 0.0 for a in range(3)],
+              grid_hi=[float(wl.hi[a]) if a < dim else 1.0 for a in range(3)])
+    import copy
+    out = copy.copy(wl)
+    out.name = wl.name + f"_grid{n}"
+    out.sizing = sz
+    return out
+
+
 def _inside(pts, dim, lo, hi, holes):
     ok = np.all((pts[:, :dim] > lo[:dim]) & (pts[:, :dim] < hi[:dim]), axis=1)
     for rec in holes:
@@ -248,6 +310,8 @@ def _inside(pts, dim, lo, hi, holes):
 def _lipschitz(sizing):
     """Lipschitz constant of h (the distance to the holes is 1-Lipschitz)"""
     k = sizing["kind"]
+    if k == H_GRID:
+        return _grid_lipschitz(sizing, len([a for a in sizing["grid_n"] if a > 1]))
     return 0.0 if k == H_CONST else (sizing["grad"] if k in (H_LINEAR_FROM_POINT, H_SHELL)
                                      else sizing["h0"] * sizing["grad"])
 
