@@ -57,7 +57,8 @@ typedef enum {
 } sph_status;
 
 enum { SPH_P_SINGULAR = 0, SPH_P_CURVE = 1, SPH_P_SURFACE = 2, SPH_P_VOLUME = 3 };
-enum { SPH_H_CONST = 0, SPH_H_LINEAR_FROM_POINT = 1, SPH_H_GRADED_TO_HOLES = 2, SPH_H_SHELL = 3 };
+enum { SPH_H_CONST = 0, SPH_H_LINEAR_FROM_POINT = 1, SPH_H_GRADED_TO_HOLES = 2, SPH_H_SHELL = 3,
+       SPH_H_GRID = 4 };
 enum { SPH_DOMAIN_BOX = 0, SPH_DOMAIN_BALL = 1 };
 enum { SPH_FP64 = 0, SPH_FP32_MIXED = 1 };
 
@@ -92,12 +93,27 @@ typedef struct {
  *   SPH_H_SHELL:             h = h0 + grad | |x - point| - dcap |, graded both
  *                            ways from the sphere of radius dcap about point
  *                            (sec. 4's Sphere02).
+ *   SPH_H_GRID:              h sampled at the nodes of a Cartesian background
+ *                            grid (sec. 2.2 keeps h_t on the background
+ *                            mesh): grid_n[a] nodes on axis a over
+ *                            [grid_lo[a], grid_hi[a]] (grid_n[2] = 1 in 2D),
+ *                            values x fastest, index (k ny + j) nx + i, all
+ *                            finite and positive.  Interpolated
+ *                            multilinearly: per axis s = (n - 1) /
+ *                            (hi - lo), u = (x - lo) s clamped to [0, n - 1],
+ *                            c = min(floor(u), n - 2), t = u - c; then
+ *                            a + t (b - a) along x, then y, then z.  The
+ *                            library copies the grid; the caller's array is
+ *                            only read during the call that adds the job.
  * Evaluated in FP64 with the operation order: squared distances summed over
  * axes in order, then sqrt; no fused multiply-add. */
 typedef struct {
   int32_t kind;
   double h0, grad, dcap;
   double point[3];
+  const double *grid;        /* SPH_H_GRID: node values (host memory) */
+  int32_t grid_n[3];
+  double grid_lo[3], grid_hi[3];
 } sph_sizing;
 
 /* Simulation parameters (paper sec. 2.3, 3.4, 3.5). */

@@ -26,7 +26,9 @@ class Geometry(C.Structure):
 
 class Sizing(C.Structure):
     _fields_ = [("kind", C.c_int32), ("h0", C.c_double), ("grad", C.c_double),
-                ("dcap", C.c_double), ("point", C.c_double * 3)]
+                ("dcap", C.c_double), ("point", C.c_double * 3),
+                ("grid", C.POINTER(C.c_double)), ("grid_n", C.c_int32 * 3),
+                ("grid_lo", C.c_double * 3), ("grid_hi", C.c_double * 3)]
 
 
 class Params(C.Structure):
@@ -143,6 +145,14 @@ def make_sizing(sz):
     s.dcap = float(sz.get("dcap", np.inf))
     for a in range(3):
         s.point[a] = float(sz.get("point", [0, 0, 0])[a])
+    if "grid" in sz:
+        g = np.ascontiguousarray(np.asarray(sz["grid"], np.float64).ravel())
+        s.grid = g.ctypes.data_as(C.POINTER(C.c_double))
+        s._keep = g
+        for a in range(3):
+            s.grid_n[a] = int(sz["grid_n"][a])
+            s.grid_lo[a] = float(sz["grid_lo"][a])
+            s.grid_hi[a] = float(sz["grid_hi"][a])
     return s
 
 

@@ -65,6 +65,9 @@ struct Geom {
   double hR[MAXH][9];       // rotation, row-major: local y = R (x - c)
   int32_t domain, pad;      // 0 box minus holes, 1 the ball inscribed in the box
   double dc[3], dR;         // ball domain: centre and radius
+  const double *grid;       // gridded sizing: node values (device), x fastest
+  int32_t gn[3], gpad;      // nodes per axis
+  double glo[3], gs[3];     // grid origin and (n - 1) / (hi - lo) per axis
 };
 
 // uniform cell grid over a job's box; its cells own the global cell ids
@@ -333,6 +336,32 @@ __device__ __forceinline__ double h_target(const Geom &g, const double *p) {
       s = s + d * d;
     }
     return g.h0 + g.grad * __builtin_sqrt(s);
+  }
+  if (g.hkind == 4) {   // node values of the background grid, multilinear
+    int c[3] = {0, 0, 0};
+    double t[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < D; ++a) {
+      const double top = (double)(g.gn[a] - 1);
+      double u = (p[a] - g.glo[a]) * g.gs[a];
+      u = u > 0.0 ? u : 0.0;   // also a NaN
+      u = u < top ? u : top;
+      double f = __builtin_floor(u);
+      f = f < top - 1.0 ? f : top - 1.0;
+      c[a] = (int)f;
+      t[a] = u - f;
+    }
+    const int nx = g.gn[0], ny = g.gn[1];
+    double v[2][2];
+    for (int dz = 0; dz < (D == 3 ? 2 : 1); ++dz)
+      for (int dy = 0; dy < 2; ++dy) {
+        const long long row = ((long long)(c[2] + dz) * ny + (c[1] + dy)) * nx + c[0];
+        const double g0 = g.grid[row], g1 = g.grid[row + 1];
+        v[dz][dy] = g0 + t[0] * (g1 - g0);
+      }
+    const double w0 = v[0][0] + t[1] * (v[0][1] - v[0][0]);
+    if (D == 2) return w0;
+    const double w1 = v[1][0] + t[1] * (v[1][1] - v[1][0]);
+    return w0 + t[2] * (w1 - w0);
   }
   if (g.hkind == 3) {   // graded both ways from the sphere |x - point| = dcap
     double s = 0.0;

@@ -215,7 +215,24 @@ static sph_status validate(const sph_geometry *g, const sph_sizing *s, const sph
       if (!(std::fabs((g->hi[a] - g->lo[a]) - e0) <= 1e-12 * e0))
         return fail(SPH_ERR_INVALID_ARG, "a ball domain needs a cubic box");
   }
-  if (s->kind < 0 || s->kind > 3) return fail(SPH_ERR_INVALID_ARG, "unknown sizing kind");
+  if (s->kind < 0 || s->kind > 4) return fail(SPH_ERR_INVALID_ARG, "unknown sizing kind");
+  if (s->kind == 4) {
+    if (!s->grid) return fail(SPH_ERR_INVALID_ARG, "gridded sizing needs a grid");
+    int64_t nodes = 1;
+    for (int a = 0; a < 3; ++a) {
+      const int want = a < g->dim ? 2 : 1;
+      if (s->grid_n[a] < want || s->grid_n[a] > 65536 || (a >= g->dim && s->grid_n[a] != 1))
+        return fail(SPH_ERR_INVALID_ARG, "grid_n[%d] out of range", a);
+      if (a < g->dim && !(s->grid_hi[a] > s->grid_lo[a] && std::isfinite(s->grid_lo[a]) &&
+                          std::isfinite(s->grid_hi[a])))
+        return fail(SPH_ERR_INVALID_ARG, "empty or non-finite grid box on axis %d", a);
+      nodes *= s->grid_n[a];
+    }
+    if (nodes > (1ll << 27)) return fail(SPH_ERR_INVALID_ARG, "grid has too many nodes");
+    for (int64_t k = 0; k < nodes; ++k)
+      if (!(s->grid[k] > 0.0) || !std::isfinite(s->grid[k]))
+        return fail(SPH_ERR_INVALID_ARG, "grid value %lld is not finite and positive", (long long)k);
+  }
   if (s->kind == 3 && !std::isfinite(s->dcap))
     return fail(SPH_ERR_INVALID_ARG, "shell sizing needs a finite radius dcap");
   if (!(p->kernel_support == 0.0 || (p->kernel_support >= 1.0 && p->kernel_support <= 8.0)))
@@ -254,6 +271,34 @@ static void sizing_bounds(const sph_geometry *g, const sph_sizing *s, double &hm
   const int D = g->dim;
   auto corner = [&](int c, int a) { return ((c >> a) & 1) ? g->hi[a] : g->lo[a]; };
   hmin = s->h0;
+  if (s->kind == 4) {
+    // the multilinear interpolant stays within the node values; its slope
+    // along axis a is a weighted mean of node differences along a
+    const int n[3] = {s->grid_n[0], s->grid_n[1], D == 3 ? s->grid_n[2] : 1};
+    const int64_t nodes = (int64_t)n[0] * n[1] * n[2];
+    hmin = hmax = s->grid[0];
+    for (int64_t k = 0; k < nodes; ++k) {
+      hmin = std::min(hmin, s->grid[k]);
+      hmax = std::max(hmax, s->grid[k]);
+    }
+    double sum = 0.0;
+    for (int a = 0; a < D; ++a) {
+      const int64_t st = a == 0 ? 1 : (a == 1 ? n[0] : (int64_t)n[0] * n[1]);
+      double m = 0.0;
+      for (int k = 0; k < n[2]; ++k)
+        for (int j = 0; j < n[1]; ++j)
+          for (int i = 0; i < n[0]; ++i) {
+            const int id[3] = {i, j, k};
+            if (id[a] + 1 >= n[a]) continue;
+            const int64_t q = ((int64_t)k * n[1] + j) * n[0] + i;
+            m = std::max(m, std::fabs(s->grid[q + st] - s->grid[q]));
+          }
+      const double gr = m * (double)(n[a] - 1) / (s->grid_hi[a] - s->grid_lo[a]);
+      sum += gr * gr;
+    }
+    lip = std::sqrt(sum);
+    return;
+  }
   if (s->kind == 0) {
     hmax = s->h0;
     lip = 0.0;
@@ -309,6 +354,7 @@ static hipError_t pull(std::vector<T> &h, const void *d, size_t count, hipStream
 struct HostJob {
   bool live = false;
   int n = 0;
+  double *d_grid = nullptr;   // gridded sizing: the job's copy of the node values
   uint32_t ncell = 0, cbase = 0;
   int nf = 0;
   std::vector<HFeat> feats;
@@ -365,6 +411,8 @@ struct sph_batch {
       (void)hipEventDestroy(e.b);
     }
     for (auto e : ev_pool) (void)hipEventDestroy(e);
+    for (HostJob &J : jobs)
+      if (J.d_grid) (void)hipFree(J.d_grid);
     for (void *p : owned) (void)hipFree(p);
     if (own_stream && stream) (void)hipStreamDestroy(stream);
   }
@@ -684,6 +732,12 @@ static void fill_job(HostJob &J, const sph_geometry *g, const sph_sizing *s, con
   G.h0 = s->h0;
   G.grad = s->grad;
   G.dcap = s->dcap;
+  if (s->kind == 4)
+    for (int a = 0; a < 3; ++a) {
+      G.gn[a] = a < D ? s->grid_n[a] : 1;
+      G.glo[a] = s->grid_lo[a];
+      G.gs[a] = a < D ? (double)(s->grid_n[a] - 1) / (s->grid_hi[a] - s->grid_lo[a]) : 0.0;
+    }
   grid_of(g, s, p, d.G);
   d.ksup = support_of(p);
   d.klen = 0.5 * d.ksup;
@@ -897,6 +951,18 @@ extern "C" sph_status sph_batch_add(sph_batch *b, const sph_geometry *g, const s
   if ((uint64_t)b->ncell + J.ncell > b->ccap)
     return fail(SPH_ERR_OUT_OF_MEMORY, "cell capacity %u exceeded (job needs %u)", b->ccap, J.ncell);
   HIPCHK(hipStreamSynchronize(b->stream));
+  if (s->kind == 4) {   // the job's own device copy of the sizing grid
+    const size_t bytes = sizeof(double) * (size_t)s->grid_n[0] * s->grid_n[1] * s->grid_n[2];
+    if (hipMalloc((void **)&J.d_grid, bytes) != hipSuccess)
+      return fail(SPH_ERR_OUT_OF_MEMORY, "no device memory for the sizing grid");
+    hipError_t ge = hipMemcpyAsync(J.d_grid, s->grid, bytes, hipMemcpyHostToDevice, b->stream);
+    if (ge == hipSuccess) ge = hipStreamSynchronize(b->stream);
+    if (ge != hipSuccess) {
+      (void)hipFree(J.d_grid);
+      return fail(SPH_ERR_DEVICE, "sizing grid upload failed: %s", hipGetErrorString(ge));
+    }
+    J.dev.g.grid = J.d_grid;
+  }
   const int D = b->D;
   // tables of the job's feature slots
   std::vector<Feat> hf(MAXF);
@@ -991,7 +1057,10 @@ extern "C" sph_status sph_batch_add(sph_batch *b, const sph_geometry *g, const s
   if (e == hipSuccess && J.ncell) e = hipMemsetAsync(b->cnt + b->ncell, 0, 4 * (size_t)J.ncell, q);
   if (e == hipSuccess) e = hipStreamSynchronize(q);
   else (void)hipStreamSynchronize(q);
-  if (e != hipSuccess) return fail(SPH_ERR_DEVICE, "job upload failed: %s", hipGetErrorString(e));
+  if (e != hipSuccess) {
+    if (J.d_grid) (void)hipFree(J.d_grid);
+    return fail(SPH_ERR_DEVICE, "job upload failed: %s", hipGetErrorString(e));
+  }
   J.live = true;
   b->jobs[slot] = J;
   const int i0 = b->n;
@@ -1039,11 +1108,16 @@ extern "C" sph_status sph_batch_remove(sph_batch *b, int32_t job) {
   HostJob &R = b->jobs[job];
   R.live = false;
   R.dev.live = 0;
+  R.dev.g.grid = nullptr;
   HIPCHK(hipMemsetAsync(b->d_grp + job * MAXF, 0, sizeof(Group) * MAXF, b->stream));
   HIPCHK(hipMemsetAsync(b->d_st + job, 0, sizeof(JobStat), b->stream));
   HIPCHK(hipMemcpyAsync(b->d_jobs + job, &R.dev, sizeof(JobDev), hipMemcpyHostToDevice, b->stream));
   HIPCHK(hipMemsetAsync(b->cnt, 0, 4 * (size_t)std::max(b->ncell, 1u), b->stream));
   HIPCHK(hipStreamSynchronize(b->stream));
+  if (R.d_grid) {   // no kernel that reads it is queued any more
+    (void)hipFree(R.d_grid);
+    R.d_grid = nullptr;
+  }
   b->cur = 1 - b->cur;
   b->n = (int)off;
   b->ncell = cb;

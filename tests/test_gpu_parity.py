@@ -39,10 +39,15 @@ CASES = {
     "graded_disc": lambda: wk.graded_disc(),
     "paper_sphere01": lambda: wk.paper_sphere01(),
     "paper_sphere02": lambda: wk.paper_sphere02(),
+    # h_t sampled on a Cartesian background grid, interpolated multilinearly
+    # (sec. 2.2): the square's linear field on 33^2 nodes, the 3D ball's
+    # hole-graded field on 17^3 nodes
+    "square_grid33": lambda: wk.with_grid_sizing(wk.paper_square(), 33),
+    "ball3d_grid17": lambda: wk.with_grid_sizing(wk.scaled_ball_3d(30011, seed=22, res=96), 17),
 }
 KSTEPS = {"square64": 200, "hole2d_20011": 60, "ball3d_30011": 25, "ell2d_20011": 60,
           "ell3d_30011": 20, "paper_square": 150, "paper_cube": 6, "graded_disc": 60,
-          "paper_sphere01": 10, "paper_sphere02": 6}
+          "paper_sphere01": 10, "paper_sphere02": 6, "square_grid33": 60, "ball3d_grid17": 10}
 
 _wl_cache = {}
 
