@@ -20,7 +20,8 @@ _lib = None
 class Geometry(C.Structure):
     _fields_ = [("dim", C.c_int32), ("lo", C.c_double * 3), ("hi", C.c_double * 3),
                 ("n_holes", C.c_int32), ("holes", C.POINTER(C.c_double)),
-                ("domain", C.c_int32)]
+                ("domain", C.c_int32), ("phi", C.POINTER(C.c_double)),
+                ("phi_n", C.c_int32 * 3), ("phi_lo", C.c_double * 3), ("phi_hi", C.c_double * 3)]
 
 
 class Sizing(C.Structure):
@@ -92,7 +93,7 @@ def _err():
     return lib().sphref_last_error().decode()
 
 
-def make_geometry(dim, lo, hi, holes, domain=0):
+def make_geometry(dim, lo, hi, holes, domain=0, level=None):
     holes = np.ascontiguousarray(np.asarray(holes, np.float64).reshape(-1, 15))
     g = Geometry()
     g.dim = dim
@@ -103,6 +104,14 @@ def make_geometry(dim, lo, hi, holes, domain=0):
     g.holes = holes.ctypes.data_as(C.POINTER(C.c_double)) if holes.size else None
     g.domain = int(domain)
     g._keep = holes
+    if level is not None:
+        ph = np.ascontiguousarray(np.asarray(level["phi"], np.float64).ravel())
+        g.phi = ph.ctypes.data_as(C.POINTER(C.c_double))
+        g._keep_phi = ph
+        for a in range(3):
+            g.phi_n[a] = int(level["n"][a])
+            g.phi_lo[a] = float(level["lo"][a])
+            g.phi_hi[a] = float(level["hi"][a])
     return g
 
 
@@ -146,7 +155,7 @@ class RefJob:
     def __init__(self, wl, xyz=None, feature=None, params=None):
         L = lib()
         self.dim = wl.dim
-        self.geom = make_geometry(wl.dim, wl.lo, wl.hi, wl.holes, wl.domain)
+        self.geom = make_geometry(wl.dim, wl.lo, wl.hi, wl.holes, wl.domain, wl.level)
         self.sizing = make_sizing(wl.sizing)
         self.params = make_params(params if params is not None else wl.params)
         xyz = np.ascontiguousarray(wl.xyz if xyz is None else xyz, dtype=np.float64)

@@ -44,7 +44,7 @@ const char *sphref_last_error(void) { return g_err; }
 /* features (sec. 3.2)                                                  */
 /* ------------------------------------------------------------------ */
 enum { T_SI = 0, T_C = 1, T_S = 2, T_V = 3 };
-enum { K_VOL, K_BOXSIDE, K_HOLE, K_EDGE3, K_CORNER, K_SHELL };
+enum { K_VOL, K_BOXSIDE, K_HOLE, K_EDGE3, K_CORNER, K_SHELL, K_LEVEL };
 
 typedef struct {
   int type, k, kind;
@@ -62,8 +62,12 @@ typedef struct {
   int ell[MAXH];            /* 1: ellipsoid (unequal semi-axes), 0: ball */
   double ha[MAXH][3];       /* ellipsoid semi-axes */
   double hR[MAXH][9];       /* ellipsoid rotation, row-major: local = R (x - c) */
-  int domain;               /* 0 box minus holes, 1 the ball inscribed in the box */
+  int domain;               /* 0 box minus holes, 1 the ball inscribed in the box,
+                               2 the positive phase of a gridded level set */
   double dc[3], dR;         /* ball domain: centre and radius */
+  const double *phi;        /* level-set domain: node values, counts and box */
+  int pn[3];
+  double plo[3], phi_hi[3];
   int nf;
   feat_t f[MAXF];
 } geo_t;
@@ -76,8 +80,24 @@ static int geo_build(const sphref_geometry *g, geo_t *G) {
   for (int a = 0; a < 3; ++a) { G->lo[a] = g->lo[a]; G->hi[a] = g->hi[a]; }
   for (int a = 0; a < g->dim; ++a)
     if (!(g->lo[a] < g->hi[a])) { set_err("empty box"); return -1; }
-  if (g->domain != 0 && g->domain != 1) { set_err("domain must be 0 or 1"); return -1; }
+  if (g->domain < 0 || g->domain > 2) { set_err("domain must be 0, 1 or 2"); return -1; }
   G->domain = g->domain;
+  if (G->domain == 2) {
+    if (g->n_holes != 0 || !g->phi) { set_err("level-set domain needs phi and no holes"); return -1; }
+    G->phi = g->phi;
+    for (int a = 0; a < 3; ++a) {
+      G->pn[a] = a < g->dim ? g->phi_n[a] : 1;
+      G->plo[a] = g->phi_lo[a];
+      G->phi_hi[a] = g->phi_hi[a];
+      if (a < g->dim && (G->pn[a] < 2 || !(g->phi_hi[a] > g->phi_lo[a]))) {
+        set_err("bad level-set grid"); return -1;
+      }
+    }
+    G->f[0] = (feat_t){.type = T_V, .k = g->dim, .kind = K_VOL};
+    G->f[1] = (feat_t){.type = g->dim == 2 ? T_C : T_S, .k = g->dim - 1, .kind = K_LEVEL};
+    G->nf = 2;
+    return 0;
+  }
   if (G->domain == 1) {
     /* the ball (disc) inscribed in a cubic box: features volume and sphere */
     double e0 = g->hi[0] - g->lo[0];
@@ -273,6 +293,82 @@ static void ell_normal(const geo_t *G, int q, const double *x, double *n) {
 
 static double sg(int side) { return side ? 1.0 : -1.0; }
 
+/* ------------------------------------------------------------------ */
+/* gridded level set (sec. 2.1: phi on a Cartesian background mesh)     */
+/* ------------------------------------------------------------------ */
+/* phi at x, multilinear in the grid cell of x (coordinates clamped to the
+ * grid box as for the gridded sizing), and its gradient: the derivative of
+ * that multilinear function inside the cell */
+static double ls_phi(const geo_t *G, const double *x, double *grad) {
+  int D = G->dim, c[3] = {0, 0, 0};
+  double t[3] = {0.0, 0.0, 0.0}, s[3] = {0.0, 0.0, 0.0};
+  for (int a = 0; a < D; ++a) {
+    int n = G->pn[a];
+    s[a] = (double)(n - 1) / (G->phi_hi[a] - G->plo[a]);
+    double u = (x[a] - G->plo[a]) * s[a];
+    if (!(u > 0.0)) u = 0.0;
+    if (u > (double)(n - 1)) u = (double)(n - 1);
+    double f = floor(u);
+    if (f > (double)(n - 2)) f = (double)(n - 2);
+    c[a] = (int)f;
+    t[a] = u - f;
+  }
+  int nx = G->pn[0], ny = G->pn[1], nz = D == 3 ? 2 : 1;
+  double g[2][2][2], v[2][2], d[2][2];
+  for (int dz = 0; dz < nz; ++dz)
+    for (int dy = 0; dy < 2; ++dy) {
+      int64_t row = ((int64_t)(c[2] + dz) * ny + (c[1] + dy)) * nx + c[0];
+      g[dz][dy][0] = G->phi[row];
+      g[dz][dy][1] = G->phi[row + 1];
+      d[dz][dy] = g[dz][dy][1] - g[dz][dy][0];             /* difference along x */
+      v[dz][dy] = g[dz][dy][0] + t[0] * d[dz][dy];          /* lerp along x */
+    }
+  double w[2], e[2], q[2];
+  for (int dz = 0; dz < nz; ++dz) {
+    q[dz] = v[dz][1] - v[dz][0];                            /* difference along y */
+    w[dz] = v[dz][0] + t[1] * q[dz];                        /* lerp along y */
+    e[dz] = d[dz][0] + t[1] * (d[dz][1] - d[dz][0]);        /* x-difference lerped along y */
+  }
+  grad[0] = grad[1] = grad[2] = 0.0;
+  if (D == 2) {
+    grad[0] = s[0] * e[0];
+    grad[1] = s[1] * q[0];
+    return w[0];
+  }
+  grad[0] = s[0] * (e[0] + t[2] * (e[1] - e[0]));
+  grad[1] = s[1] * (q[0] + t[2] * (q[1] - q[0]));
+  grad[2] = s[2] * (w[1] - w[0]);
+  return w[0] + t[2] * (w[1] - w[0]);
+}
+
+/* unit normal of the level set at x, pointing to increasing phi (into the
+ * domain); 0 where the gradient vanishes */
+static void ls_unit(const geo_t *G, const double *x, double *m) {
+  double gr[3];
+  ls_phi(G, x, gr);
+  double s = 0.0;
+  for (int a = 0; a < G->dim; ++a) s = s + gr[a] * gr[a];
+  double r = sqrt(s);
+  m[0] = m[1] = m[2] = 0.0;
+  if (!(r > 0.0)) return;
+  for (int a = 0; a < G->dim; ++a) m[a] = gr[a] / r;
+}
+
+/* closest point on the zero level set, read as a fixed count of Newton
+ * steps along the gradient, x <- x - phi grad / |grad|^2 (sec. 2.1 gives
+ * no iteration rule) */
+static void ls_project(const geo_t *G, double *x) {
+  int D = G->dim;
+  for (int it = 0; it < 12; ++it) {
+    double gr[3];
+    double p = ls_phi(G, x, gr);
+    double gg = 0.0;
+    for (int a = 0; a < D; ++a) gg = gg + gr[a] * gr[a];
+    if (!(gg > 0.0)) return;
+    for (int a = 0; a < D; ++a) x[a] = x[a] - p * gr[a] / gg;
+  }
+}
+
 /* outward normal n_b of feature fi's boundary at boundary particle b
  * (sec. 3.3, Eq. (gradient_operator_renormSPH_bypart): n points out of the
  * domain of i; at box edges and corners the normalised sum of the adjacent
@@ -295,6 +391,10 @@ static void bnormal(const geo_t *G, int fi, int fb, const double *xb, double *n)
       for (int a = 0; a < D; ++a) { d[a] = G->hc[B->hole][a] - xb[a]; s = s + d[a] * d[a]; }
       double r = sqrt(s);
       for (int a = 0; a < D; ++a) n[a] = d[a] / r;
+    } else if (B->kind == K_LEVEL) {
+      /* out of the domain = towards decreasing phi */
+      ls_unit(G, xb, n);
+      for (int a = 0; a < D; ++a) n[a] = -n[a];
     } else if (B->kind == K_SHELL) {
       /* out of the ball domain: radially outwards */
       double d[3] = {0, 0, 0}, s = 0.0;
@@ -372,6 +472,18 @@ static void tproject(const geo_t *G, int fi, const double *x, double *u) {
       }
       return;
     }
+    case K_LEVEL: {
+      double m[3];
+      ls_unit(G, x, m);
+      if (D == 2) {                       /* keep the part along the tangent (-m1, m0) */
+        double ut = u[0] * (-m[1]) + u[1] * m[0];
+        u[0] = ut * (-m[1]); u[1] = ut * m[0];
+      } else {                            /* remove the normal part */
+        double un = u[0] * m[0] + u[1] * m[1] + u[2] * m[2];
+        for (int a = 0; a < 3; ++a) u[a] = u[a] - un * m[a];
+      }
+      return;
+    }
     case K_SHELL: {
       const double *c = G->dc;
       if (D == 2) {                       /* keep the part along the circle's tangent */
@@ -424,6 +536,7 @@ static void pproject(const geo_t *G, int fi, double *x) {
     case K_CORNER:
       for (int a = 0; a < D; ++a) x[a] = ((A->bits >> a) & 1) ? G->hi[a] : G->lo[a];
       return;
+    case K_LEVEL: ls_project(G, x); return;
     case K_SHELL: {
       double d[3] = {0, 0, 0}, s = 0.0;
       for (int a = 0; a < D; ++a) { d[a] = x[a] - G->dc[a]; s = s + d[a] * d[a]; }
@@ -443,6 +556,12 @@ static int inside(const geo_t *G, const double *x) {
     double s = 0.0;
     for (int a = 0; a < D; ++a) { double d = x[a] - G->dc[a]; s = s + d * d; }
     return s < G->dR * G->dR;
+  }
+  if (G->domain == 2) {
+    for (int a = 0; a < D; ++a)
+      if (!(x[a] > G->lo[a] && x[a] < G->hi[a])) return 0;
+    double gr[3];
+    return ls_phi(G, x, gr) > 0.0;
   }
   for (int a = 0; a < D; ++a)
     if (!(x[a] > G->lo[a] && x[a] < G->hi[a])) return 0;

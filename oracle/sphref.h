@@ -47,7 +47,14 @@ typedef struct {
   const double *holes;
   int32_t domain;        /* 0: the box minus the holes; 1: the ball (disc)
                             inscribed in the box, which must be a cube, with
-                            no holes: features 0 volume | 1 sphere (circle) */
+                            no holes: features 0 volume | 1 sphere (circle);
+                            2: the positive phase of the level set phi
+                            below, within the box, no holes: features
+                            0 volume | 1 the zero level set */
+  const double *phi;     /* domain 2: phi at the nodes of a Cartesian grid,
+                            x fastest, interpolated like the gridded sizing */
+  int32_t phi_n[3];
+  double phi_lo[3], phi_hi[3];
 } sphref_geometry;
 
 /* Target feature size h_t(x) (paper sec. 2.2).

@@ -73,7 +73,9 @@ class Workload:
     counts: dict = field(default_factory=dict)
     scale: float = 1.0
     steps: int = 0
-    domain: int = 0                 # 0 box minus holes, 1 the ball inscribed in the box
+    domain: int = 0                 # 0 box minus holes, 1 the ball inscribed in the box,
+                                    # 2 the positive phase of a gridded level set
+    level: dict = None              # domain 2: {"phi": node values, "n", "lo", "hi"}
 
     @property
     def n(self):
@@ -707,6 +709,146 @@ def _build_ball(name, dim, lo, hi, sizing, params, n_total, seed, steps, res):
     return Workload(name=name, dim=dim, lo=lo, hi=hi, holes=holes, sizing=sizing,
                     params=params, xyz=xyz, feature=feat, ftype=types, counts=counts,
                     scale=s, steps=steps, domain=1)
+
+
+def _level_eval(level, dim, pts):
+    """the generator's own copy of the gridded level set: phi multilinear in
+    the grid cell (coordinates clamped), and its gradient in the cell"""
+    g = np.asarray(level["phi"], float).reshape(level["n"][::-1])
+    c, t, sc = [], [], []
+    for a in range(dim):
+        n = int(level["n"][a])
+        s_ = (n - 1) / (level["hi"][a] - level["lo"][a])
+        u = np.clip((pts[:, a] - level["lo"][a]) * s_, 0.0, n - 1)
+        f = np.minimum(np.floor(u), n - 2)
+        c.append(f.astype(np.int64)); t.append(u - f); sc.append(s_)
+    if dim == 2:
+        g00, g10 = g[0, c[1], c[0]], g[0, c[1], c[0] + 1]
+        g01, g11 = g[0, c[1] + 1, c[0]], g[0, c[1] + 1, c[0] + 1]
+        v0 = g00 + t[0] * (g10 - g00)
+        v1 = g01 + t[0] * (g11 - g01)
+        d0, d1 = g10 - g00, g11 - g01
+        grad = np.stack([sc[0] * (d0 + t[1] * (d1 - d0)), sc[1] * (v1 - v0)], 1)
+        return v0 + t[1] * (v1 - v0), grad
+    w, e, q = [], [], []
+    for dz in (0, 1):
+        a0, a1 = g[c[2] + dz, c[1], c[0]], g[c[2] + dz, c[1], c[0] + 1]
+        b0, b1 = g[c[2] + dz, c[1] + 1, c[0]], g[c[2] + dz, c[1] + 1, c[0] + 1]
+        v0, v1 = a0 + t[0] * (a1 - a0), b0 + t[0] * (b1 - b0)
+        q.append(v1 - v0)
+        w.append(v0 + t[1] * (v1 - v0))
+        e.append((a1 - a0) + t[1] * ((b1 - b0) - (a1 - a0)))
+    grad = np.stack([sc[0] * (e[0] + t[2] * (e[1] - e[0])), sc[1] * (q[0] + t[2] * (q[1] - q[0])),
+                     sc[2] * (w[1] - w[0])], 1)
+    return w[0] + t[2] * (w[1] - w[0]), grad
+
+
+def _build_level(name, dim, lo, hi, phi_fn, n_grid, sizing, params, n_total, seed, res):
+    """The positive phase of a level set sampled at the nodes of an n_grid^dim
+    Cartesian grid over the box (sec. 2.1): feature 0 the volume phi > 0,
+    feature 1 the zero level set.  Counts from the mass integrals of h^-k
+    (the surface one with a smeared delta function of phi); positions by
+    rejection sampling, the surface ones projected onto phi = 0 by Newton
+    steps first."""
+    lo = np.asarray(lo, float)
+    hi = np.asarray(hi, float)
+    holes = np.zeros((0, 15))
+    gn = [n_grid, n_grid, n_grid if dim == 3 else 1]
+    ax = [lo[a] + np.arange(gn[a]) * (hi[a] - lo[a]) / (gn[a] - 1) if gn[a] > 1 else np.zeros(1)
+          for a in range(3)]
+    Z, Y, X = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
+    level = dict(phi=np.ascontiguousarray(phi_fn(X.ravel(), Y.ravel(), Z.ravel())), n=gn,
+                 lo=[float(lo[a]) if a < dim else 0.0 for a in range(3)],
+                 hi=[float(hi[a]) if a < dim else 1.0 for a in range(3)])
+    types = np.asarray([VOL, CURVE if dim == 2 else SURF], np.int32)
+
+    def phi(p):
+        return _level_eval(level, dim, p)
+
+    def masses(sz):
+        axes = [lo[a] + (np.arange(res) + 0.5) * (hi[a] - lo[a]) / res for a in range(dim)]
+        cell = np.prod([(hi[a] - lo[a]) / res for a in range(dim)])
+        eps = 1.5 * max((hi[a] - lo[a]) / res for a in range(dim))
+        mv = ms = 0.0
+        zs = axes[2] if dim == 3 else [0.0]
+        for zi in zs:
+            Xg, Yg = np.meshgrid(axes[0], axes[1], indexing="ij")
+            pts = np.stack([Xg.ravel(), Yg.ravel(), np.full(Xg.size, zi)], 1)
+            f, gr = phi(pts)
+            h = _h_field(pts, dim, sz, holes)
+            mv += float(np.sum(h[f > 0] ** -float(dim)))
+            band = np.abs(f) < eps
+            ms += float(np.sum(h[band] ** -float(dim - 1) * np.linalg.norm(gr[band], axis=1))
+                        / (2 * eps))
+        return {0: mv * cell, 1: ms * cell}
+
+    base = dict(sizing)
+    M = masses(base)
+    s = _solve_scale(M, types, n_total, dim)
+    sizing = dict(base)
+    if sizing["kind"] in (H_LINEAR_FROM_POINT, H_SHELL):
+        sizing["grad"] = base["grad"] * s
+    sizing["h0"] = base["h0"] * s
+    counts = _split_counts(M, types, s, n_total, dim)
+    rng = np.random.Generator(np.random.MT19937(seed))
+    hmin = _hmin(sizing, dim, lo, hi, holes)
+
+    def box_prop(m):
+        p = np.zeros((m, 3))
+        p[:, :dim] = lo[:dim] + rng.random((m, dim)) * (hi[:dim] - lo[:dim])
+        return p
+
+    band_w = 2.0 * max((hi[a] - lo[a]) / (n_grid - 1) for a in range(dim))
+
+    def surf_prop(m):
+        p = box_prop(8 * m)
+        f, _ = phi(p)
+        p = p[np.abs(f) < band_w]
+        for _ in range(12):
+            f, gr = phi(p)
+            gg = np.sum(gr * gr, axis=1)
+            ok = gg > 0
+            p[ok, :dim] -= (f[ok] / gg[ok])[:, None] * gr[ok]
+        inb = np.all((p[:, :dim] > lo[:dim]) & (p[:, :dim] < hi[:dim]), axis=1)
+        return p[inb]
+
+    pv = _sample_rejection(rng, counts[0], box_prop, dim, sizing, holes, dim, hmin,
+                           accept_mask=lambda p: phi(p)[0] > 0)
+    ps = _sample_rejection(rng, counts[1], surf_prop, dim, sizing, holes, dim - 1, hmin)
+    xyz = np.ascontiguousarray(np.concatenate([pv, ps], 0))
+    feat = np.ascontiguousarray(np.concatenate([np.zeros(len(pv), np.int32),
+                                                np.ones(len(ps), np.int32)]))
+    assert xyz.shape[0] == n_total, (xyz.shape, n_total)
+    return Workload(name=name, dim=dim, lo=lo, hi=hi, holes=holes, sizing=sizing,
+                    params=params, xyz=xyz, feature=feat, ftype=types, counts=counts,
+                    scale=s, steps=0, domain=2, level=level)
+
+
+def level_peanut(n_total=4000, seed=11, n_grid=65, res=256, **pover):
+    """A 2D level-set domain: the union of two overlapping discs (radii 0.3
+    and 0.22 about (0.38, 0.5) and (0.68, 0.5)) given by phi = max of the
+    discs' signed distances, sampled on an n_grid^2 grid over the unit
+    square; h graded linearly from the peanut's left end."""
+    def phi(x, y, z):
+        a = 0.3 - np.hypot(x - 0.38, y - 0.5)
+        b = 0.22 - np.hypot(x - 0.68, y - 0.5)
+        return np.maximum(a, b)
+    return _build_level("level_peanut", 2, [0.0, 0.0, 0.0], [1.0, 1.0, 0.0], phi, n_grid,
+                        dict(kind=H_LINEAR_FROM_POINT, h0=0.008, grad=0.03, dcap=np.inf,
+                             point=[0.08, 0.5, 0.0]),
+                        default_params(**pover), n_total, seed, res)
+
+
+def level_torus(n_total=30000, seed=12, n_grid=49, res=96, **pover):
+    """A 3D level-set domain: the solid torus (radii 0.3 and 0.12 about the
+    centre of the unit cube, axis z), phi = 0.12 - distance to the core
+    circle, sampled on an n_grid^3 grid; h graded linearly along x."""
+    def phi(x, y, z):
+        return 0.12 - np.hypot(np.hypot(x - 0.5, y - 0.5) - 0.3, z - 0.5)
+    return _build_level("level_torus", 3, [0.0, 0.0, 0.0], [1.0, 1.0, 1.0], phi, n_grid,
+                        dict(kind=H_LINEAR_FROM_POINT, h0=0.01, grad=0.02, dcap=np.inf,
+                             point=[0.0, 0.5, 0.5]),
+                        default_params(**pover), n_total, seed, res)
 
 
 def _hmin(sizing, dim, lo, hi, holes):
