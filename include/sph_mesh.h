@@ -59,7 +59,7 @@ typedef enum {
 enum { SPH_P_SINGULAR = 0, SPH_P_CURVE = 1, SPH_P_SURFACE = 2, SPH_P_VOLUME = 3 };
 enum { SPH_H_CONST = 0, SPH_H_LINEAR_FROM_POINT = 1, SPH_H_GRADED_TO_HOLES = 2, SPH_H_SHELL = 3,
        SPH_H_GRID = 4 };
-enum { SPH_DOMAIN_BOX = 0, SPH_DOMAIN_BALL = 1 };
+enum { SPH_DOMAIN_BOX = 0, SPH_DOMAIN_BALL = 1, SPH_DOMAIN_LEVEL_SET = 2 };
 enum { SPH_FP64 = 0, SPH_FP32_MIXED = 1 };
 
 /* Geometry (paper sec. 2.1 / 3.1): the level set phi > 0 is the box minus
@@ -82,7 +82,22 @@ typedef struct {
                                 SPH_DOMAIN_BALL (1): the ball (disc) inscribed
                                 in the box, as for sec. 4's sphere cases; the
                                 box must be a cube and there are no holes;
-                                features 0 volume, 1 its sphere (circle) */
+                                features 0 volume, 1 its sphere (circle).
+                                SPH_DOMAIN_LEVEL_SET (2): the positive phase
+                                of the level set phi below, within the box,
+                                no holes (sec. 2.1); features 0 volume phi > 0,
+                                1 the zero level set.  A particle of feature 1
+                                is mapped onto phi = 0 by 12 Newton steps
+                                x <- x - phi grad / |grad|^2; the normal out of
+                                the domain is -grad / |grad| */
+  const double *phi;         /* SPH_DOMAIN_LEVEL_SET: phi at the nodes of a
+                                Cartesian grid (host memory, copied by the
+                                library), laid out and interpolated as the
+                                gridded sizing's values; grad is the
+                                derivative of that multilinear function in
+                                the cell of x */
+  int32_t phi_n[3];
+  double phi_lo[3], phi_hi[3];
 } sph_geometry;
 
 /* Target feature size h_t(x) (paper sec. 2.2):

@@ -21,7 +21,8 @@ FIELD_H, FIELD_AP, FIELD_A, FIELD_VT, FIELD_GAMMA, FIELD_VMID = range(6)
 class Geometry(C.Structure):
     _fields_ = [("dim", C.c_int32), ("lo", C.c_double * 3), ("hi", C.c_double * 3),
                 ("n_holes", C.c_int32), ("holes", C.POINTER(C.c_double)),
-                ("domain", C.c_int32)]
+                ("domain", C.c_int32), ("phi", C.POINTER(C.c_double)),
+                ("phi_n", C.c_int32 * 3), ("phi_lo", C.c_double * 3), ("phi_hi", C.c_double * 3)]
 
 
 class Sizing(C.Structure):
@@ -123,7 +124,7 @@ def _check(fn, status):
         raise SphError(fn, status, lib().sph_mesh_last_error().decode())
 
 
-def make_geometry(dim, lo, hi, holes, domain=0):
+def make_geometry(dim, lo, hi, holes, domain=0, level=None):
     holes = np.ascontiguousarray(np.asarray(holes, np.float64).reshape(-1, 15))
     g = Geometry()
     g.dim = dim
@@ -134,6 +135,14 @@ def make_geometry(dim, lo, hi, holes, domain=0):
     g.holes = holes.ctypes.data_as(_dp) if holes.size else None
     g.domain = int(domain)
     g._keep = holes
+    if level is not None:
+        ph = np.ascontiguousarray(np.asarray(level["phi"], np.float64).ravel())
+        g.phi = ph.ctypes.data_as(_dp)
+        g._keep_phi = ph
+        for a in range(3):
+            g.phi_n[a] = int(level["n"][a])
+            g.phi_lo[a] = float(level["lo"][a])
+            g.phi_hi[a] = float(level["hi"][a])
     return g
 
 
@@ -186,7 +195,7 @@ class SphMesh:
         p = dict(wl.params if params is None else params)
         p.update(over)
         self.dim = wl.dim
-        self._geom = make_geometry(wl.dim, wl.lo, wl.hi, wl.holes, wl.domain)
+        self._geom = make_geometry(wl.dim, wl.lo, wl.hi, wl.holes, wl.domain, wl.level)
         self._sizing = make_sizing(wl.sizing)
         self._params = make_params(p, stream)
         xyz = np.ascontiguousarray(wl.xyz if xyz is None else xyz, np.float64)
@@ -317,7 +326,7 @@ class JobSpec:
         p = dict(wl.params if params is None else params)
         p.update(over)
         self.dim = wl.dim
-        self.geom = make_geometry(wl.dim, wl.lo, wl.hi, wl.holes, wl.domain)
+        self.geom = make_geometry(wl.dim, wl.lo, wl.hi, wl.holes, wl.domain, wl.level)
         self.sizing = make_sizing(wl.sizing)
         self.params = make_params(p)
         self.xyz = np.ascontiguousarray(wl.xyz if xyz is None else xyz, np.float64)

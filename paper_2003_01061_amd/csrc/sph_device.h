@@ -36,7 +36,8 @@ static_assert(SPH_NBATCH >= 1 && SPH_NBATCH <= 8, "records are padded by 8");
 #endif
 
 enum : int { T_SI = 0, T_C = 1, T_S = 2, T_V = 3 };
-enum : int { K_VOL = 0, K_BOXSIDE = 1, K_HOLE = 2, K_EDGE3 = 3, K_CORNER = 4, K_SHELL = 5 };
+enum : int { K_VOL = 0, K_BOXSIDE = 1, K_HOLE = 2, K_EDGE3 = 3, K_CORNER = 4, K_SHELL = 5,
+              K_LEVEL = 6 };
 enum : int { PH_ONE = 1, PH_RAMP = 2, PH_TWO = 3, PH_FROZEN = 4 };
 
 // one feature: the paper's (type, index) pair and what its geometry is
@@ -68,7 +69,68 @@ struct Geom {
   const double *grid;       // gridded sizing: node values (device), x fastest
   int32_t gn[3], gpad;      // nodes per axis
   double glo[3], gs[3];     // grid origin and (n - 1) / (hi - lo) per axis
+  const double *phi;        // level-set domain: node values (device), x fastest
+  int32_t pn[3], ppad;
+  double plo[3], ps[3];
 };
+
+// the gridded level set of a level-set domain: phi multilinear in the grid
+// cell of x (coordinates clamped to the grid box), and its gradient, the
+// derivative of that multilinear function in the cell
+template <int D>
+__device__ __forceinline__ double ls_phi(const Geom &g, const double *x, double *gr) {
+#pragma clang fp contract(off)
+  int c[3] = {0, 0, 0};
+  double t[3] = {0.0, 0.0, 0.0};
+  for (int a = 0; a < D; ++a) {
+    const double top = (double)(g.pn[a] - 1);
+    double u = (x[a] - g.plo[a]) * g.ps[a];
+    u = u > 0.0 ? u : 0.0;
+    u = u < top ? u : top;
+    double f = __builtin_floor(u);
+    f = f < top - 1.0 ? f : top - 1.0;
+    c[a] = (int)f;
+    t[a] = u - f;
+  }
+  const int nx = g.pn[0], ny = g.pn[1];
+  double v[2][2], d[2][2];
+  for (int dz = 0; dz < (D == 3 ? 2 : 1); ++dz)
+    for (int dy = 0; dy < 2; ++dy) {
+      const long long row = ((long long)(c[2] + dz) * ny + (c[1] + dy)) * nx + c[0];
+      const double g0 = g.phi[row], g1 = g.phi[row + 1];
+      d[dz][dy] = g1 - g0;
+      v[dz][dy] = g0 + t[0] * d[dz][dy];
+    }
+  double w[2], e[2], q[2];
+  for (int dz = 0; dz < (D == 3 ? 2 : 1); ++dz) {
+    q[dz] = v[dz][1] - v[dz][0];
+    w[dz] = v[dz][0] + t[1] * q[dz];
+    e[dz] = d[dz][0] + t[1] * (d[dz][1] - d[dz][0]);
+  }
+  gr[0] = gr[1] = gr[2] = 0.0;
+  if (D == 2) {
+    gr[0] = g.ps[0] * e[0];
+    gr[1] = g.ps[1] * q[0];
+    return w[0];
+  }
+  gr[0] = g.ps[0] * (e[0] + t[2] * (e[1] - e[0]));
+  gr[1] = g.ps[1] * (q[0] + t[2] * (q[1] - q[0]));
+  gr[2] = g.ps[2] * (w[1] - w[0]);
+  return w[0] + t[2] * (w[1] - w[0]);
+}
+
+// unit normal of the level set towards increasing phi (0 where grad vanishes)
+template <int D>
+__device__ __forceinline__ void ls_unit(const Geom &g, const double *x, double *m) {
+  double gr[3];
+  (void)ls_phi<D>(g, x, gr);
+  double s = 0.0;
+  for (int a = 0; a < D; ++a) s += gr[a] * gr[a];
+  const double r = __builtin_sqrt(s);
+  m[0] = m[1] = m[2] = 0.0;
+  if (!(r > 0.0)) return;
+  for (int a = 0; a < D; ++a) m[a] = gr[a] / r;
+}
 
 // uniform cell grid over a job's box; its cells own the global cell ids
 // [cbase, cbase + ncell) of the batch; per-particle search radius
@@ -596,6 +658,21 @@ __device__ __forceinline__ void tangent(const Geom &g, const Feat &F, const doub
       }
       return;
     }
+    case K_LEVEL: {   // the zero level set: normal from the gradient
+      double m[3];
+      ls_unit<D>(g, x, m);
+      if (D == 2) {
+        const double ut = u[0] * (-m[1]) + u[1] * m[0];
+        u[0] = ut * (-m[1]);
+        u[1] = ut * m[0];
+      } else {
+        const double un = u[0] * m[0] + u[1] * m[1] + u[2] * m[2];
+        u[0] -= un * m[0];
+        u[1] -= un * m[1];
+        u[2] -= un * m[2];
+      }
+      return;
+    }
     case K_SHELL: {   // the ball domain's sphere: as a ball hole about dc
       const double *c = g.dc;
       if (D == 2) {
@@ -658,6 +735,16 @@ __device__ __forceinline__ void project(const Geom &g, const Feat &F, double *x)
     case K_CORNER:
       for (int a = 0; a < D; ++a) x[a] = ((F.bits >> a) & 1) ? g.hi[a] : g.lo[a];
       return;
+    case K_LEVEL:   // 12 Newton steps along the gradient onto phi = 0
+      for (int it = 0; it < 12; ++it) {
+        double gr[3];
+        const double p = ls_phi<D>(g, x, gr);
+        double gg = 0.0;
+        for (int a = 0; a < D; ++a) gg += gr[a] * gr[a];
+        if (!(gg > 0.0)) return;
+        for (int a = 0; a < D; ++a) x[a] -= p * gr[a] / gg;
+      }
+      return;
     case K_SHELL: {
       double d[3] = {0.0, 0.0, 0.0}, s = 0.0;
       for (int a = 0; a < D; ++a) {
@@ -684,6 +771,12 @@ __device__ __forceinline__ bool inside(const Geom &g, const double *x) {
       s = s + d * d;
     }
     return s < g.dR * g.dR;
+  }
+  if (g.domain == 2) {
+    for (int a = 0; a < D; ++a)
+      if (!(x[a] > g.lo[a] && x[a] < g.hi[a])) return false;
+    double gr[3];
+    return ls_phi<D>(g, x, gr) > 0.0;
   }
   for (int a = 0; a < D; ++a)
     if (!(x[a] > g.lo[a] && x[a] < g.hi[a])) return false;

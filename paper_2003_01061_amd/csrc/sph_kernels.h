@@ -346,7 +346,12 @@ __global__ __launch_bounds__(BLOCK) void k_rank_gather(Batch B, int n, const uin
   // set's gradient for an ellipse or ellipsoid
   if (B.has_hole) {
     const Feat F = B.feat[f];
-    if (F.kind == K_SHELL) {   // the ball domain's sphere: radially outwards
+    if (F.kind == K_LEVEL) {   // the zero level set: towards decreasing phi
+      const double x[3] = {xh.x, xh.y, xh.z};
+      double m[3];
+      ls_unit<D>(B.jobs[f / MAXF].g, x, m);
+      B.enrm[dst] = make_double4(-m[0], -m[1], -m[2], 0.0);
+    } else if (F.kind == K_SHELL) {   // the ball domain's sphere: radially outwards
       const double *cc = B.jobs[f / MAXF].g.dc;
       const double d0 = xh.x - cc[0], d1 = xh.y - cc[1], d2 = D == 3 ? xh.z - cc[2] : 0.0;
       const double il = 1.0 / __builtin_sqrt(d0 * d0 + d1 * d1 + d2 * d2);

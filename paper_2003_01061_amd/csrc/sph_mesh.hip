@@ -72,6 +72,10 @@ std::vector<HFeat> make_features(int D, int nh, int domain) {
     F.push_back({D == 2 ? T_C : T_S, D - 1, K_SHELL});
     return F;
   }
+  if (domain == SPH_DOMAIN_LEVEL_SET) {   // the volume and the zero level set
+    F.push_back({D == 2 ? T_C : T_S, D - 1, K_LEVEL});
+    return F;
+  }
   for (int a = 0; a < D; ++a)
     for (int s = 0; s < 2; ++s) {
       HFeat f{D == 2 ? T_C : T_S, D - 1, K_BOXSIDE};
@@ -132,6 +136,8 @@ BNorm boundary_normal(int D, const HFeat &A, const HFeat &B) {
       N.hole = B.hole;
     } else if (B.kind == K_SHELL) {
       N.mode = 4;   // radially out of the ball, stored per particle
+    } else if (B.kind == K_LEVEL) {
+      N.mode = 5;   // against the level set's gradient, stored per particle
     } else if (B.kind == K_EDGE3) {
       const double r = std::sqrt(0.5);
       N.n[B.fax[0]] = sg(B.fsd[0]) * r;
@@ -206,8 +212,26 @@ static sph_status validate(const sph_geometry *g, const sph_sizing *s, const sph
       if (!(H[a] - amax > g->lo[a] && H[a] + amax < g->hi[a]))
         return fail(SPH_ERR_INVALID_ARG, "hole %d must lie strictly inside the box", q);
   }
-  if (g->domain != SPH_DOMAIN_BOX && g->domain != SPH_DOMAIN_BALL)
-    return fail(SPH_ERR_INVALID_ARG, "domain must be SPH_DOMAIN_BOX or SPH_DOMAIN_BALL");
+  if (g->domain != SPH_DOMAIN_BOX && g->domain != SPH_DOMAIN_BALL &&
+      g->domain != SPH_DOMAIN_LEVEL_SET)
+    return fail(SPH_ERR_INVALID_ARG, "unknown domain kind");
+  if (g->domain == SPH_DOMAIN_LEVEL_SET) {
+    if (g->n_holes != 0) return fail(SPH_ERR_INVALID_ARG, "a level-set domain takes no holes");
+    if (!g->phi) return fail(SPH_ERR_INVALID_ARG, "a level-set domain needs phi");
+    int64_t nodes = 1;
+    for (int a = 0; a < 3; ++a) {
+      const int want = a < g->dim ? 2 : 1;
+      if (g->phi_n[a] < want || g->phi_n[a] > 65536 || (a >= g->dim && g->phi_n[a] != 1))
+        return fail(SPH_ERR_INVALID_ARG, "phi_n[%d] out of range", a);
+      if (a < g->dim && !(g->phi_hi[a] > g->phi_lo[a] && std::isfinite(g->phi_lo[a]) &&
+                          std::isfinite(g->phi_hi[a])))
+        return fail(SPH_ERR_INVALID_ARG, "empty or non-finite level-set grid on axis %d", a);
+      nodes *= g->phi_n[a];
+    }
+    if (nodes > (1ll << 27)) return fail(SPH_ERR_INVALID_ARG, "level-set grid has too many nodes");
+    for (int64_t k = 0; k < nodes; ++k)
+      if (!std::isfinite(g->phi[k])) return fail(SPH_ERR_INVALID_ARG, "phi is not finite");
+  }
   if (g->domain == SPH_DOMAIN_BALL) {
     if (g->n_holes != 0) return fail(SPH_ERR_INVALID_ARG, "a ball domain takes no holes");
     const double e0 = g->hi[0] - g->lo[0];
@@ -355,6 +379,7 @@ struct HostJob {
   bool live = false;
   int n = 0;
   double *d_grid = nullptr;   // gridded sizing: the job's copy of the node values
+  double *d_phi = nullptr;    // level-set domain: the job's copy of phi
   uint32_t ncell = 0, cbase = 0;
   int nf = 0;
   std::vector<HFeat> feats;
@@ -411,8 +436,10 @@ struct sph_batch {
       (void)hipEventDestroy(e.b);
     }
     for (auto e : ev_pool) (void)hipEventDestroy(e);
-    for (HostJob &J : jobs)
+    for (HostJob &J : jobs) {
       if (J.d_grid) (void)hipFree(J.d_grid);
+      if (J.d_phi) (void)hipFree(J.d_phi);
+    }
     for (void *p : owned) (void)hipFree(p);
     if (own_stream && stream) (void)hipStreamDestroy(stream);
   }
@@ -439,7 +466,8 @@ struct sph_batch {
     B.has_hole = 0;
     for (int j = 0; j < njobs; ++j)
       if (jobs[j].live)
-        for (const HFeat &F : jobs[j].feats) B.has_hole |= F.kind == K_HOLE || F.kind == K_SHELL;
+        for (const HFeat &F : jobs[j].feats)
+          B.has_hole |= F.kind == K_HOLE || F.kind == K_SHELL || F.kind == K_LEVEL;
     return B;
   }
   uint32_t ntiles() const { return (ncell + SCAN_TILE - 1) / SCAN_TILE; }
@@ -710,6 +738,12 @@ static void fill_job(HostJob &J, const sph_geometry *g, const sph_sizing *s, con
     for (int a = 0; a < D; ++a) G.dc[a] = 0.5 * (g->lo[a] + g->hi[a]);
     G.dR = 0.5 * (g->hi[0] - g->lo[0]);
   }
+  if (g->domain == SPH_DOMAIN_LEVEL_SET)
+    for (int a = 0; a < 3; ++a) {
+      G.pn[a] = a < D ? g->phi_n[a] : 1;
+      G.plo[a] = g->phi_lo[a];
+      G.ps[a] = a < D ? (double)(g->phi_n[a] - 1) / (g->phi_hi[a] - g->phi_lo[a]) : 0.0;
+    }
   for (int a = 0; a < 3; ++a) {
     G.lo[a] = g->lo[a];
     G.hi[a] = g->hi[a];
@@ -963,6 +997,18 @@ extern "C" sph_status sph_batch_add(sph_batch *b, const sph_geometry *g, const s
     }
     J.dev.g.grid = J.d_grid;
   }
+  if (g->domain == SPH_DOMAIN_LEVEL_SET) {   // the job's own device copy of phi
+    const size_t bytes = sizeof(double) * (size_t)g->phi_n[0] * g->phi_n[1] * g->phi_n[2];
+    hipError_t pe = hipMalloc((void **)&J.d_phi, bytes);
+    if (pe == hipSuccess) pe = hipMemcpyAsync(J.d_phi, g->phi, bytes, hipMemcpyHostToDevice, b->stream);
+    if (pe == hipSuccess) pe = hipStreamSynchronize(b->stream);
+    if (pe != hipSuccess) {
+      if (J.d_phi) (void)hipFree(J.d_phi);
+      if (J.d_grid) (void)hipFree(J.d_grid);
+      return fail(SPH_ERR_DEVICE, "level-set upload failed: %s", hipGetErrorString(pe));
+    }
+    J.dev.g.phi = J.d_phi;
+  }
   const int D = b->D;
   // tables of the job's feature slots
   std::vector<Feat> hf(MAXF);
@@ -1059,6 +1105,7 @@ extern "C" sph_status sph_batch_add(sph_batch *b, const sph_geometry *g, const s
   else (void)hipStreamSynchronize(q);
   if (e != hipSuccess) {
     if (J.d_grid) (void)hipFree(J.d_grid);
+    if (J.d_phi) (void)hipFree(J.d_phi);
     return fail(SPH_ERR_DEVICE, "job upload failed: %s", hipGetErrorString(e));
   }
   J.live = true;
@@ -1109,6 +1156,7 @@ extern "C" sph_status sph_batch_remove(sph_batch *b, int32_t job) {
   R.live = false;
   R.dev.live = 0;
   R.dev.g.grid = nullptr;
+  R.dev.g.phi = nullptr;
   HIPCHK(hipMemsetAsync(b->d_grp + job * MAXF, 0, sizeof(Group) * MAXF, b->stream));
   HIPCHK(hipMemsetAsync(b->d_st + job, 0, sizeof(JobStat), b->stream));
   HIPCHK(hipMemcpyAsync(b->d_jobs + job, &R.dev, sizeof(JobDev), hipMemcpyHostToDevice, b->stream));
@@ -1117,6 +1165,10 @@ extern "C" sph_status sph_batch_remove(sph_batch *b, int32_t job) {
   if (R.d_grid) {   // no kernel that reads it is queued any more
     (void)hipFree(R.d_grid);
     R.d_grid = nullptr;
+  }
+  if (R.d_phi) {
+    (void)hipFree(R.d_phi);
+    R.d_phi = nullptr;
   }
   b->cur = 1 - b->cur;
   b->n = (int)off;

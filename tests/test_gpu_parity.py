@@ -44,10 +44,15 @@ CASES = {
     # hole-graded field on 17^3 nodes
     "square_grid33": lambda: wk.with_grid_sizing(wk.paper_square(), 33),
     "ball3d_grid17": lambda: wk.with_grid_sizing(wk.scaled_ball_3d(30011, seed=22, res=96), 17),
+    # the positive phase of a level set kept on a Cartesian grid (sec. 2.1):
+    # a 2D peanut (two discs) on 65^2 nodes, a 3D torus on 49^3 nodes
+    "level_peanut": lambda: wk.level_peanut(),
+    "level_torus": lambda: wk.level_torus(),
 }
 KSTEPS = {"square64": 200, "hole2d_20011": 60, "ball3d_30011": 25, "ell2d_20011": 60,
           "ell3d_30011": 20, "paper_square": 150, "paper_cube": 6, "graded_disc": 60,
-          "paper_sphere01": 10, "paper_sphere02": 6, "square_grid33": 60, "ball3d_grid17": 10}
+          "paper_sphere01": 10, "paper_sphere02": 6, "square_grid33": 60, "ball3d_grid17": 10,
+          "level_peanut": 60, "level_torus": 8}
 
 _wl_cache = {}
 
