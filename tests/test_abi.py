@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -128,3 +129,41 @@ def test_cell_levels_follow_the_range_of_h():
     # h within a factor 4: one grid whatever the setting
     sq = wk.square_hole(n_total=20000, res=128)
     assert binding.JobSpec(sq).cells() == binding.JobSpec(sq, cell_levels=1).cells()
+
+
+def test_new_geometry_and_sizing_kinds_are_validated_on_the_host():
+    """Ball and level-set domains and the gridded sizing: accepted as built
+    by the generator, rejected (cell count -1) when malformed.  Host logic,
+    no GPU."""
+    import copy
+    from paper_2003_01061_amd import binding
+    from paper_2003_01061_amd import workload as wk
+    ball = wk.graded_disc(n_total=400, res=64)
+    assert binding.JobSpec(ball).cells() > 0
+    bad = copy.copy(ball)
+    bad.hi = np.array([1.0, 1.5, 0.0])                 # not a cube
+    assert binding.JobSpec(bad).cells() == -1
+    lev = wk.level_peanut(n_total=400, res=64)
+    assert binding.JobSpec(lev).cells() > 0
+    bad = copy.copy(lev)
+    bad.level = None                                   # no phi
+    assert binding.JobSpec(bad).cells() == -1
+    bad = copy.copy(lev)
+    bad.level = dict(lev.level, n=[1, 65, 1])          # too few nodes
+    assert binding.JobSpec(bad).cells() == -1
+    bad = copy.copy(lev)
+    ph = np.array(lev.level["phi"], float)
+    ph[7] = np.nan
+    bad.level = dict(lev.level, phi=ph)
+    assert binding.JobSpec(bad).cells() == -1
+    grid = wk.with_grid_sizing(wk.paper_square(n_total=600), 9)
+    assert binding.JobSpec(grid).cells() > 0
+    for key, val in (("grid_n", [9, 9, 2]), ("grid_hi", [100.0, -1.0, 1.0])):
+        bad = copy.copy(grid)
+        bad.sizing = dict(grid.sizing, **{key: val})
+        assert binding.JobSpec(bad).cells() == -1, key
+    bad = copy.copy(grid)
+    g = np.array(grid.sizing["grid"], float)
+    g[3] = -1.0
+    bad.sizing = dict(grid.sizing, grid=g)
+    assert binding.JobSpec(bad).cells() == -1
