@@ -176,3 +176,42 @@ def test_job_without_particles():
     assert b.positions(je).shape == (0, 3)
     xr, _, _ = alone(other, 10, binding.SPH_FP64)
     assert np.array_equal(b.positions(jo), xr)
+
+
+def test_domain_kinds_and_gridded_sizing_mix_in_one_batch():
+    """A box-with-hole job, a ball (disc) job, a level-set job and a job with
+    gridded h_t share a batch; the level-set job leaves mid-run (its device
+    copy of phi is freed) and a second gridded job takes its slot.  Every
+    job stays bit-identical to the same job run alone."""
+    wls = [wk.scaled_hole_2d(1501, seed=61), wk.graded_disc(n_total=1200, res=128),
+           wk.level_peanut(n_total=1500, res=128),
+           wk.with_grid_sizing(wk.paper_square(n_total=1000), 17),
+           wk.with_grid_sizing(wk.scaled_hole_2d(900, seed=62), 9)]
+    specs, npart, ncell = capacity(wls)
+    b = binding.SphBatch(2, binding.SPH_FP64, max_particles=npart, max_cells=ncell, max_jobs=4)
+    ids = [b.add(s) for s in specs[:4]]
+    b.step(8)
+    x_level = b.positions(ids[2])
+    b.remove(ids[2])
+    E = b.add(specs[4])
+    assert E == ids[2]
+    b.step(6)
+    got = [(b.positions(ids[0]), 14, 0), (b.positions(ids[1]), 14, 1), (x_level, 8, 2),
+           (b.positions(ids[3]), 14, 3), (b.positions(E), 6, 4)]
+    for x, k, w in got:
+        xr, _, _ = alone(wls[w], k, binding.SPH_FP64)
+        assert np.array_equal(x, xr), wls[w].name
+
+
+def test_3d_domain_kinds_mix_in_one_batch():
+    wls = [wk.paper_sphere01(n_total=3000, res=32), wk.level_torus(n_total=5000, res=48),
+           wk.with_grid_sizing(wk.scaled_ball_3d(4001, seed=63, res=48), 9)]
+    specs, npart, ncell = capacity(wls)
+    b = binding.SphBatch(3, binding.SPH_FP32_MIXED, max_particles=npart, max_cells=ncell,
+                         max_jobs=3, max_neighbors=512)
+    ids = [b.add(s) for s in specs]
+    b.step(6)
+    for j, wl in zip(ids, wls):
+        g = binding.SphMesh(wl, precision=binding.SPH_FP32_MIXED, use_graph=1, max_neighbors=512)
+        g.step(6)
+        assert np.array_equal(b.positions(j), g.positions()), wl.name
