@@ -44,7 +44,7 @@ const char *sphref_last_error(void) { return g_err; }
 /* features (sec. 3.2)                                                  */
 /* ------------------------------------------------------------------ */
 enum { T_SI = 0, T_C = 1, T_S = 2, T_V = 3 };
-enum { K_VOL, K_BOXSIDE, K_HOLE, K_EDGE3, K_CORNER, K_SHELL, K_LEVEL };
+enum { K_VOL, K_BOXSIDE, K_HOLE, K_EDGE3, K_CORNER, K_SHELL, K_LEVEL, K_POLY, K_PCORNER };
 
 typedef struct {
   int type, k, kind;
@@ -68,6 +68,10 @@ typedef struct {
   const double *phi;        /* level-set domain: node values, counts and box */
   int pn[3];
   double plo[3], phi_hi[3];
+  int ncv, ncr;             /* imported curves and corners (2D level-set domain) */
+  const int32_t *coff, *cend;
+  const double *cpts;
+  double cor[MAXF][3];
   int nf;
   feat_t f[MAXF];
 } geo_t;
@@ -94,6 +98,35 @@ static int geo_build(const sphref_geometry *g, geo_t *G) {
       }
     }
     G->f[0] = (feat_t){.type = T_V, .k = g->dim, .kind = K_VOL};
+    if (g->n_curves > 0) {
+      /* imported curves and corners replace the single zero-set feature */
+      if (g->dim != 2 || !g->curve_off || !g->curve_pts || !g->curve_ends ||
+          g->n_corners < 0 || (g->n_corners > 0 && !g->corners) ||
+          1 + g->n_curves + g->n_corners > MAXF) {
+        set_err("bad imported curves"); return -1;
+      }
+      G->ncv = g->n_curves;
+      G->ncr = g->n_corners;
+      G->coff = g->curve_off;
+      G->cend = g->curve_ends;
+      G->cpts = g->curve_pts;
+      for (int c = 0; c < G->ncv; ++c) {
+        if (g->curve_off[c + 1] - g->curve_off[c] < 2) { set_err("a curve needs two points"); return -1; }
+        for (int e = 0; e < 2; ++e)
+          if (g->curve_ends[2 * c + e] < -1 || g->curve_ends[2 * c + e] >= G->ncr) {
+            set_err("bad curve end"); return -1;
+          }
+      }
+      for (int m = 0; m < G->ncr; ++m)
+        for (int a = 0; a < 3; ++a) G->cor[m][a] = g->corners[3 * m + a];
+      int nf = 1;
+      for (int c = 0; c < G->ncv; ++c)
+        G->f[nf++] = (feat_t){.type = T_C, .k = 1, .kind = K_POLY, .hole = c};
+      for (int m = 0; m < G->ncr; ++m)
+        G->f[nf++] = (feat_t){.type = T_SI, .k = 0, .kind = K_PCORNER, .hole = m};
+      G->nf = nf;
+      return 0;
+    }
     G->f[1] = (feat_t){.type = g->dim == 2 ? T_C : T_S, .k = g->dim - 1, .kind = K_LEVEL};
     G->nf = 2;
     return 0;
@@ -177,6 +210,9 @@ static int bounds(const geo_t *G, int fi, int fb) {
         return ((B->bits >> A->fax[0]) & 1) == A->fsd[0] &&
                ((B->bits >> A->fax[1]) & 1) == A->fsd[1];
       return 0;
+    case K_POLY:          /* an imported curve is bounded by its end corners */
+      return B->kind == K_PCORNER &&
+             (G->cend[2 * A->hole] == B->hole || G->cend[2 * A->hole + 1] == B->hole);
     default: return 0;
   }
 }
@@ -341,6 +377,34 @@ static double ls_phi(const geo_t *G, const double *x, double *grad) {
   return w[0] + t[2] * (w[1] - w[0]);
 }
 
+/* imported curve c (a polyline, domain on its left): the segment whose
+ * closest point to x is nearest (the first one on ties), and that point */
+static int poly_closest(const geo_t *G, int c, const double *x, double *q) {
+  int best = -1;
+  double bd = INFINITY;
+  for (int k = G->coff[c]; k + 1 < G->coff[c + 1]; ++k) {
+    const double *p0 = G->cpts + 3 * k, *p1 = G->cpts + 3 * (k + 1);
+    double e0 = p1[0] - p0[0], e1 = p1[1] - p0[1];
+    double ee = e0 * e0 + e1 * e1;
+    double t = ee > 0.0 ? ((x[0] - p0[0]) * e0 + (x[1] - p0[1]) * e1) / ee : 0.0;
+    if (t < 0.0) t = 0.0;
+    if (t > 1.0) t = 1.0;
+    double c0 = p0[0] + t * e0, c1 = p0[1] + t * e1;
+    double d0 = x[0] - c0, d1 = x[1] - c1;
+    double d = d0 * d0 + d1 * d1;
+    if (d < bd) { bd = d; best = k; q[0] = c0; q[1] = c1; }
+  }
+  return best;
+}
+
+/* unit tangent of segment k of the imported curves (along the curve) */
+static void seg_tangent(const geo_t *G, int k, double *t) {
+  const double *p0 = G->cpts + 3 * k, *p1 = G->cpts + 3 * (k + 1);
+  double e0 = p1[0] - p0[0], e1 = p1[1] - p0[1];
+  double l = sqrt(e0 * e0 + e1 * e1);
+  t[0] = e0 / l; t[1] = e1 / l; t[2] = 0.0;
+}
+
 /* unit normal of the level set at x, pointing to increasing phi (into the
  * domain); 0 where the gradient vanishes */
 static void ls_unit(const geo_t *G, const double *x, double *m) {
@@ -391,6 +455,25 @@ static void bnormal(const geo_t *G, int fi, int fb, const double *xb, double *n)
       for (int a = 0; a < D; ++a) { d[a] = G->hc[B->hole][a] - xb[a]; s = s + d[a] * d[a]; }
       double r = sqrt(s);
       for (int a = 0; a < D; ++a) n[a] = d[a] / r;
+    } else if (B->kind == K_POLY) {
+      /* out of the domain = the right of the curve's closest segment */
+      double q[3], t[3];
+      seg_tangent(G, poly_closest(G, B->hole, xb, q), t);
+      n[0] = t[1]; n[1] = -t[0];
+    } else if (B->kind == K_PCORNER) {
+      /* the normalised sum of the outward normals of the end segments of
+       * the curves that meet at the corner */
+      double s0 = 0.0, s1 = 0.0;
+      for (int c = 0; c < G->ncv; ++c)
+        for (int e = 0; e < 2; ++e) {
+          if (G->cend[2 * c + e] != B->hole) continue;
+          int k = e == 0 ? G->coff[c] : G->coff[c + 1] - 2;
+          double t[3];
+          seg_tangent(G, k, t);
+          s0 = s0 + t[1]; s1 = s1 - t[0];
+        }
+      double l = sqrt(s0 * s0 + s1 * s1);
+      if (l > 0.0) { n[0] = s0 / l; n[1] = s1 / l; }
     } else if (B->kind == K_LEVEL) {
       /* out of the domain = towards decreasing phi */
       ls_unit(G, xb, n);
@@ -423,6 +506,18 @@ static void bnormal(const geo_t *G, int fi, int fb, const double *xb, double *n)
     n[o] = sg((B->bits >> o) & 1);
   } else if (A->kind == K_EDGE3) {
     n[A->axis] = sg((B->bits >> A->axis) & 1);
+  } else if (A->kind == K_POLY) {
+    /* out of the curve at its end corner: along the end segment, away from
+     * the curve's interior */
+    int c = A->hole;
+    double t[3];
+    if (G->cend[2 * c] == B->hole) {
+      seg_tangent(G, G->coff[c], t);
+      n[0] = -t[0]; n[1] = -t[1];
+    } else {
+      seg_tangent(G, G->coff[c + 1] - 2, t);
+      n[0] = t[0]; n[1] = t[1];
+    }
   }
 }
 
@@ -470,6 +565,13 @@ static void tproject(const geo_t *G, int fi, const double *x, double *u) {
         double un = u[0] * m[0] + u[1] * m[1] + u[2] * m[2];
         for (int a = 0; a < 3; ++a) u[a] = u[a] - un * m[a];
       }
+      return;
+    }
+    case K_POLY: {                        /* keep the part along the closest segment */
+      double q[3], t[3];
+      seg_tangent(G, poly_closest(G, A->hole, x, q), t);
+      double ut = u[0] * t[0] + u[1] * t[1];
+      u[0] = ut * t[0]; u[1] = ut * t[1]; u[2] = 0.0;
       return;
     }
     case K_LEVEL: {
@@ -537,6 +639,15 @@ static void pproject(const geo_t *G, int fi, double *x) {
       for (int a = 0; a < D; ++a) x[a] = ((A->bits >> a) & 1) ? G->hi[a] : G->lo[a];
       return;
     case K_LEVEL: ls_project(G, x); return;
+    case K_POLY: {
+      double q[3];
+      poly_closest(G, A->hole, x, q);
+      x[0] = q[0]; x[1] = q[1];
+      return;
+    }
+    case K_PCORNER:
+      for (int a = 0; a < 3; ++a) x[a] = G->cor[A->hole][a];
+      return;
     case K_SHELL: {
       double d[3] = {0, 0, 0}, s = 0.0;
       for (int a = 0; a < D; ++a) { d[a] = x[a] - G->dc[a]; s = s + d[a] * d[a]; }

@@ -55,6 +55,18 @@ typedef struct {
                             x fastest, interpolated like the gridded sizing */
   int32_t phi_n[3];
   double phi_lo[3], phi_hi[3];
+  /* domain 2 in 2D with imported feature curves (sec. 2.1's sharp edges as
+   * polylines, and singular points): curve c has the points
+   * curve_pts[3 k], k in [curve_off[c], curve_off[c+1]), runs with the
+   * domain on its left, and ends at the corners curve_ends[2c] (its first
+   * point) and curve_ends[2c+1] (its last), -1 for none.  Features are then
+   * 0 volume | 1..n_curves the curves | then the corners, in order. */
+  int32_t n_curves;
+  const int32_t *curve_off;
+  const double *curve_pts;
+  const int32_t *curve_ends;
+  int32_t n_corners;
+  const double *corners;
 } sphref_geometry;
 
 /* Target feature size h_t(x) (paper sec. 2.2).

@@ -851,6 +851,111 @@ def level_torus(n_total=30000, seed=12, n_grid=49, res=96, **pover):
                         default_params(**pover), n_total, seed, res)
 
 
+def zalesak_disc(n_total=3000, seed=13, n_grid=129, n_arc=256, res=256, **pover):
+    """Zalesak's slotted disc, the paper's example of the feature tags (sec.
+    2.1): the disc of radius 0.3 about (0.5, 0.5) minus the slot
+    [0.45, 0.55] x [0.45, 1], as a level set on an n_grid^2 grid plus the
+    imported sharp features: four curves (the big arc as an n_arc-segment
+    polyline, the slot's two walls and its bottom, each with the domain on
+    its left) meeting at four corners.  Nine features: the volume, four
+    curves, four singular points.  h graded linearly from the slot bottom."""
+    dim = 2
+    R, c0 = 0.3, np.array([0.5, 0.5])
+    xl, xr, yb = 0.45, 0.55, 0.45
+    ya = 0.5 + math.sqrt(R * R - 0.05 * 0.05)
+
+    def phi_fn(x, y, z):
+        disc = R - np.hypot(x - c0[0], y - c0[1])
+        # signed distance to the slot box [xl, xr] x [yb, 1.2], positive outside
+        qx = np.abs(x - 0.5) - 0.05
+        qy = np.abs(y - 0.825) - 0.375
+        box = np.hypot(np.maximum(qx, 0), np.maximum(qy, 0)) + np.minimum(np.maximum(qx, qy), 0)
+        return np.minimum(disc, box)
+
+    A, B, C, D = [xl, ya, 0.0], [xl, yb, 0.0], [xr, yb, 0.0], [xr, ya, 0.0]
+    ta = math.atan2(ya - 0.5, xl - 0.5)
+    td = math.atan2(ya - 0.5, xr - 0.5) + 2 * math.pi
+    th = np.linspace(ta, td, n_arc + 1)
+    arc = np.stack([c0[0] + R * np.cos(th), c0[1] + R * np.sin(th), np.zeros(n_arc + 1)], 1)
+    arc[0], arc[-1] = A, D
+    polys = [arc, np.array([D, C]), np.array([C, B]), np.array([B, A])]
+    off = np.cumsum([0] + [len(p) for p in polys]).astype(np.int32)
+    pts = np.concatenate(polys, 0)
+    ends = np.array([[0, 3], [3, 2], [2, 1], [1, 0]], np.int32)
+    corners = np.array([A, B, C, D], float)
+    lo, hi = np.array([0.0, 0.0, 0.0]), np.array([1.0, 1.0, 0.0])
+    gn = [n_grid, n_grid, 1]
+    ax = [lo[a] + np.arange(gn[a]) * (hi[a] - lo[a]) / (gn[a] - 1) for a in range(2)]
+    Y, X = np.meshgrid(ax[1], ax[0], indexing="ij")
+    level = dict(phi=np.ascontiguousarray(phi_fn(X.ravel(), Y.ravel(), 0.0)), n=gn,
+                 lo=[0.0, 0.0, 0.0], hi=[1.0, 1.0, 1.0],
+                 curves=dict(off=off, pts=pts, ends=ends, corners=corners))
+    types = np.asarray([VOL] + [CURVE] * 4 + [SI] * 4, np.int32)
+    holes = np.zeros((0, 15))
+    base = dict(kind=H_LINEAR_FROM_POINT, h0=0.006, grad=0.03, dcap=np.inf,
+                point=[0.5, yb, 0.0])
+
+    def phi(p):
+        return _level_eval(level, dim, p)[0]
+
+    def seg_samples(poly, m_per):
+        """midpoints and lengths of m_per sub-segments of every segment"""
+        mids, lens = [], []
+        for k in range(len(poly) - 1):
+            p0, p1 = poly[k], poly[k + 1]
+            u = (np.arange(m_per) + 0.5) / m_per
+            mids.append(p0 + u[:, None] * (p1 - p0))
+            lens.append(np.full(m_per, np.linalg.norm(p1 - p0) / m_per))
+        return np.concatenate(mids), np.concatenate(lens)
+
+    def masses(sz):
+        axv = [(np.arange(res) + 0.5) / res for a in range(2)]
+        Xg, Yg = np.meshgrid(axv[0], axv[1], indexing="ij")
+        P = np.stack([Xg.ravel(), Yg.ravel(), np.zeros(Xg.size)], 1)
+        M = {0: float(np.sum(_h_field(P[phi(P) > 0], dim, sz, holes) ** -2.0)) / res ** 2}
+        for k, poly in enumerate(polys):
+            mid, ln = seg_samples(poly, 64 if len(poly) == 2 else 4)
+            M[1 + k] = float(np.sum(_h_field(mid, dim, sz, holes) ** -1.0 * ln))
+        return M
+
+    M = masses(base)
+    sc = _solve_scale(M, types, n_total, dim)
+    sizing = dict(base, h0=base["h0"] * sc, grad=base["grad"] * sc)
+    counts = _split_counts(M, types, sc, n_total, dim)
+    rng = np.random.Generator(np.random.MT19937(seed))
+    hmin = sizing["h0"]
+
+    def box_prop(m):
+        p = np.zeros((m, 3))
+        p[:, :2] = rng.random((m, 2))
+        return p
+
+    xyz = [_sample_rejection(rng, counts[0], box_prop, dim, sizing, holes, 2, hmin,
+                             accept_mask=lambda p: phi(p) > 0)]
+    feat = [np.zeros(counts[0], np.int32)]
+    for k, poly in enumerate(polys):
+        seg = np.linalg.norm(np.diff(poly, axis=0), axis=1)
+        cum = np.concatenate([[0.0], np.cumsum(seg)])
+
+        def along(m, poly=poly, seg=seg, cum=cum):
+            sarc = rng.random(m) * cum[-1]
+            j = np.minimum(np.searchsorted(cum, sarc, side="right") - 1, len(seg) - 1)
+            t = (sarc - cum[j]) / seg[j]
+            return poly[j] + t[:, None] * (poly[j + 1] - poly[j])
+
+        p = _sample_rejection(rng, counts[1 + k], along, dim, sizing, holes, 1, hmin)
+        xyz.append(p)
+        feat.append(np.full(len(p), 1 + k, np.int32))
+    xyz.append(corners)
+    feat.append(np.arange(5, 9, dtype=np.int32))
+    xyz = np.ascontiguousarray(np.concatenate(xyz, 0))
+    feat = np.ascontiguousarray(np.concatenate(feat))
+    assert xyz.shape[0] == n_total, (xyz.shape, n_total)
+    return Workload(name="zalesak_disc", dim=2, lo=lo, hi=hi, holes=holes, sizing=sizing,
+                    params=default_params(**pover), xyz=xyz, feature=feat, ftype=types,
+                    counts=counts, scale=sc, steps=0, domain=2, level=level)
+
+
 def _hmin(sizing, dim, lo, hi, holes):
     """a lower bound of h over the domain (rejection sampling's envelope):
     every sizing kind here is h0 plus a non-negative term"""
