@@ -98,6 +98,26 @@ typedef struct {
                                 the cell of x */
   int32_t phi_n[3];
   double phi_lo[3], phi_hi[3];
+  /* SPH_DOMAIN_LEVEL_SET in 2D may import sharp features (sec. 2.1): feature
+   * curves as polylines and singular points.  Curve c has the points
+   * curve_pts[3 k .. 3 k + 2], k in [curve_off[c], curve_off[c + 1]) (at
+   * least 2, consecutive points distinct), runs with the domain on its left,
+   * and ends at the corners curve_ends[2 c] (first point) and
+   * curve_ends[2 c + 1] (last point), -1 for none; corners[3 m ..] is corner
+   * m.  Features are then 0 volume | 1 .. n_curves the curves | the corners,
+   * in order (no zero-level-set feature).  A curve particle is mapped to the
+   * closest point of its own polyline (the first segment on ties) and moves
+   * along that segment; the volume's normal at it is the segment's right
+   * normal; at a corner, the normalised sum of the right normals of the end
+   * segments meeting there; a curve's normal at its end corner runs along
+   * its end segment, away from the curve.  n_curves = 0: no imported
+   * features.  All arrays are host memory, copied by the library. */
+  int32_t n_curves;
+  const int32_t *curve_off;
+  const double *curve_pts;
+  const int32_t *curve_ends;
+  int32_t n_corners;
+  const double *corners;
 } sph_geometry;
 
 /* Target feature size h_t(x) (paper sec. 2.2):

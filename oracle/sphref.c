@@ -380,7 +380,8 @@ static double ls_phi(const geo_t *G, const double *x, double *grad) {
 /* imported curve c (a polyline, domain on its left): the segment whose
  * closest point to x is nearest (the first one on ties), and that point */
 static int poly_closest(const geo_t *G, int c, const double *x, double *q) {
-  int best = -1;
+  int best = G->coff[c];                     /* also when no distance compares */
+  q[0] = G->cpts[3 * best]; q[1] = G->cpts[3 * best + 1];
   double bd = INFINITY;
   for (int k = G->coff[c]; k + 1 < G->coff[c + 1]; ++k) {
     const double *p0 = G->cpts + 3 * k, *p1 = G->cpts + 3 * (k + 1);

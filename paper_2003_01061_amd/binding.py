@@ -22,7 +22,10 @@ class Geometry(C.Structure):
     _fields_ = [("dim", C.c_int32), ("lo", C.c_double * 3), ("hi", C.c_double * 3),
                 ("n_holes", C.c_int32), ("holes", C.POINTER(C.c_double)),
                 ("domain", C.c_int32), ("phi", C.POINTER(C.c_double)),
-                ("phi_n", C.c_int32 * 3), ("phi_lo", C.c_double * 3), ("phi_hi", C.c_double * 3)]
+                ("phi_n", C.c_int32 * 3), ("phi_lo", C.c_double * 3), ("phi_hi", C.c_double * 3),
+                ("n_curves", C.c_int32), ("curve_off", C.POINTER(C.c_int32)),
+                ("curve_pts", C.POINTER(C.c_double)), ("curve_ends", C.POINTER(C.c_int32)),
+                ("n_corners", C.c_int32), ("corners", C.POINTER(C.c_double))]
 
 
 class Sizing(C.Structure):
@@ -143,6 +146,19 @@ def make_geometry(dim, lo, hi, holes, domain=0, level=None):
             g.phi_n[a] = int(level["n"][a])
             g.phi_lo[a] = float(level["lo"][a])
             g.phi_hi[a] = float(level["hi"][a])
+        if level.get("curves"):
+            cv = level["curves"]
+            off = np.ascontiguousarray(np.asarray(cv["off"], np.int32))
+            pts = np.ascontiguousarray(np.asarray(cv["pts"], np.float64).reshape(-1, 3))
+            ends = np.ascontiguousarray(np.asarray(cv["ends"], np.int32).reshape(-1, 2))
+            cor = np.ascontiguousarray(np.asarray(cv["corners"], np.float64).reshape(-1, 3))
+            g.n_curves = len(off) - 1
+            g.curve_off = off.ctypes.data_as(C.POINTER(C.c_int32))
+            g.curve_pts = pts.ctypes.data_as(C.POINTER(C.c_double))
+            g.curve_ends = ends.ctypes.data_as(C.POINTER(C.c_int32))
+            g.n_corners = cor.shape[0]
+            g.corners = cor.ctypes.data_as(C.POINTER(C.c_double))
+            g._keep_curves = (off, pts, ends, cor)
     return g
 
 

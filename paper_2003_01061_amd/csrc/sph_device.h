@@ -37,7 +37,7 @@ static_assert(SPH_NBATCH >= 1 && SPH_NBATCH <= 8, "records are padded by 8");
 
 enum : int { T_SI = 0, T_C = 1, T_S = 2, T_V = 3 };
 enum : int { K_VOL = 0, K_BOXSIDE = 1, K_HOLE = 2, K_EDGE3 = 3, K_CORNER = 4, K_SHELL = 5,
-              K_LEVEL = 6 };
+              K_LEVEL = 6, K_POLY = 7, K_PCORNER = 8 };
 enum : int { PH_ONE = 1, PH_RAMP = 2, PH_TWO = 3, PH_FROZEN = 4 };
 
 // one feature: the paper's (type, index) pair and what its geometry is
@@ -72,7 +72,46 @@ struct Geom {
   const double *phi;        // level-set domain: node values (device), x fastest
   int32_t pn[3], ppad;
   double plo[3], ps[3];
+  const double *cpts;       // imported curves: points (x, y, z per point, device)
+  const int32_t *coff;      // curve c owns the points [coff[c], coff[c + 1])
 };
+
+// imported curve c (a polyline, domain on its left): the segment whose
+// closest point to x is nearest (the first on ties), that point in q
+__device__ __forceinline__ int poly_closest(const Geom &g, int c, const double *x, double *q) {
+  // start from the first point, so that a segment is returned even when no
+  // distance compares (a non-finite x)
+  int best = g.coff[c];
+  q[0] = g.cpts[3 * best];
+  q[1] = g.cpts[3 * best + 1];
+  double bd = __builtin_inf();
+  for (int k = g.coff[c]; k + 1 < g.coff[c + 1]; ++k) {
+    const double *p0 = g.cpts + 3 * k, *p1 = g.cpts + 3 * (k + 1);
+    const double e0 = p1[0] - p0[0], e1 = p1[1] - p0[1];
+    const double ee = e0 * e0 + e1 * e1;
+    double t = ee > 0.0 ? ((x[0] - p0[0]) * e0 + (x[1] - p0[1]) * e1) / ee : 0.0;
+    t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+    const double c0 = p0[0] + t * e0, c1 = p0[1] + t * e1;
+    const double d0 = x[0] - c0, d1 = x[1] - c1;
+    const double d = d0 * d0 + d1 * d1;
+    if (d < bd) {
+      bd = d;
+      best = k;
+      q[0] = c0;
+      q[1] = c1;
+    }
+  }
+  return best;
+}
+
+// unit tangent of segment k of the imported curves
+__device__ __forceinline__ void seg_tangent(const Geom &g, int k, double *t) {
+  const double *p0 = g.cpts + 3 * k, *p1 = g.cpts + 3 * (k + 1);
+  const double e0 = p1[0] - p0[0], e1 = p1[1] - p0[1];
+  const double l = __builtin_sqrt(e0 * e0 + e1 * e1);
+  t[0] = e0 / l;
+  t[1] = e1 / l;
+}
 
 // the gridded level set of a level-set domain: phi multilinear in the grid
 // cell of x (coordinates clamped to the grid box), and its gradient, the
@@ -658,6 +697,15 @@ __device__ __forceinline__ void tangent(const Geom &g, const Feat &F, const doub
       }
       return;
     }
+    case K_POLY: {    // an imported curve: keep the part along the closest segment
+      double q[2], t[2];
+      seg_tangent(g, poly_closest(g, F.hole, x, q), t);
+      const double ut = u[0] * t[0] + u[1] * t[1];
+      u[0] = ut * t[0];
+      u[1] = ut * t[1];
+      u[2] = 0.0;
+      return;
+    }
     case K_LEVEL: {   // the zero level set: normal from the gradient
       double m[3];
       ls_unit<D>(g, x, m);
@@ -735,6 +783,13 @@ __device__ __forceinline__ void project(const Geom &g, const Feat &F, double *x)
     case K_CORNER:
       for (int a = 0; a < D; ++a) x[a] = ((F.bits >> a) & 1) ? g.hi[a] : g.lo[a];
       return;
+    case K_POLY: {   // the closest point of the particle's own polyline
+      double q[2];
+      (void)poly_closest(g, F.hole, x, q);
+      x[0] = q[0];
+      x[1] = q[1];
+      return;
+    }
     case K_LEVEL:   // 12 Newton steps along the gradient onto phi = 0
       for (int it = 0; it < 12; ++it) {
         double gr[3];

@@ -346,7 +346,13 @@ __global__ __launch_bounds__(BLOCK) void k_rank_gather(Batch B, int n, const uin
   // set's gradient for an ellipse or ellipsoid
   if (B.has_hole) {
     const Feat F = B.feat[f];
-    if (F.kind == K_LEVEL) {   // the zero level set: towards decreasing phi
+    if (F.kind == K_POLY) {   // an imported curve: the closest segment's right normal
+      const Geom &gg = B.jobs[f / MAXF].g;
+      const double x[3] = {xh.x, xh.y, xh.z};
+      double q[2], t[2];
+      seg_tangent(gg, poly_closest(gg, F.hole, x, q), t);
+      B.enrm[dst] = make_double4(t[1], -t[0], 0.0, 0.0);
+    } else if (F.kind == K_LEVEL) {   // the zero level set: towards decreasing phi
       const double x[3] = {xh.x, xh.y, xh.z};
       double m[3];
       ls_unit<D>(B.jobs[f / MAXF].g, x, m);

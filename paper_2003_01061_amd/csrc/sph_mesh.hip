@@ -63,6 +63,10 @@ const char *kKernelNames[KID_COUNT] = {
 struct HFeat {
   int type, k, kind, axis = 0, side = 0, fax[2] = {0, 0}, fsd[2] = {0, 0}, hole = 0, bits = 0;
   int ell = 0;   // HOLE: the hole is an ellipsoid
+  // POLY: the corners at the first and last point (-1: none) and the unit
+  // tangents of the first and last segments; PCORNER: the volume's normal
+  int end[2] = {-1, -1};
+  double t_first[2] = {0.0, 0.0}, t_last[2] = {0.0, 0.0}, n_vol[2] = {0.0, 0.0};
 };
 
 std::vector<HFeat> make_features(int D, int nh, int domain) {
@@ -107,10 +111,54 @@ std::vector<HFeat> make_features(int D, int nh, int domain) {
   return F;
 }
 
+// the features of a geometry, with the imported curves and corners of a 2D
+// level-set domain and the constant data their normals need
+std::vector<HFeat> make_features_of(const sph_geometry *g) {
+  if (g->domain != SPH_DOMAIN_LEVEL_SET || g->n_curves <= 0)
+    return make_features(g->dim, g->n_holes, g->domain);
+  std::vector<HFeat> F;
+  F.push_back({T_V, 2, K_VOL});
+  auto tangent_of = [&](int k, double *t) {
+    const double *p0 = g->curve_pts + 3 * k, *p1 = g->curve_pts + 3 * (k + 1);
+    const double e0 = p1[0] - p0[0], e1 = p1[1] - p0[1], l = std::sqrt(e0 * e0 + e1 * e1);
+    t[0] = e0 / l;
+    t[1] = e1 / l;
+  };
+  for (int c = 0; c < g->n_curves; ++c) {
+    HFeat f{T_C, 1, K_POLY};
+    f.hole = c;
+    f.end[0] = g->curve_ends[2 * c];
+    f.end[1] = g->curve_ends[2 * c + 1];
+    tangent_of(g->curve_off[c], f.t_first);
+    tangent_of(g->curve_off[c + 1] - 2, f.t_last);
+    F.push_back(f);
+  }
+  for (int m = 0; m < g->n_corners; ++m) {
+    HFeat f{T_SI, 0, K_PCORNER};
+    f.hole = m;
+    double s0 = 0.0, s1 = 0.0;
+    for (int c = 0; c < g->n_curves; ++c)
+      for (int e = 0; e < 2; ++e) {
+        if (F[1 + c].end[e] != m) continue;
+        const double *t = e == 0 ? F[1 + c].t_first : F[1 + c].t_last;
+        s0 += t[1];   // the right normal (t1, -t0)
+        s1 -= t[0];
+      }
+    const double l = std::sqrt(s0 * s0 + s1 * s1);
+    if (l > 0.0) {
+      f.n_vol[0] = s0 / l;
+      f.n_vol[1] = s1 / l;
+    }
+    F.push_back(f);
+  }
+  return F;
+}
+
 // does the lower-dimensional feature B lie on the boundary of feature A?
 bool on_boundary_of(const HFeat &A, const HFeat &B) {
   if (B.k >= A.k) return false;
   if (A.kind == K_VOL) return true;
+  if (A.kind == K_POLY) return B.kind == K_PCORNER && (A.end[0] == B.hole || A.end[1] == B.hole);
   if (A.kind == K_BOXSIDE) {
     if (B.kind == K_CORNER) return ((B.bits >> A.axis) & 1) == A.side;
     if (B.kind == K_EDGE3)
@@ -138,6 +186,11 @@ BNorm boundary_normal(int D, const HFeat &A, const HFeat &B) {
       N.mode = 4;   // radially out of the ball, stored per particle
     } else if (B.kind == K_LEVEL) {
       N.mode = 5;   // against the level set's gradient, stored per particle
+    } else if (B.kind == K_POLY) {
+      N.mode = 6;   // the closest segment's right normal, stored per particle
+    } else if (B.kind == K_PCORNER) {
+      N.n[0] = B.n_vol[0];
+      N.n[1] = B.n_vol[1];
     } else if (B.kind == K_EDGE3) {
       const double r = std::sqrt(0.5);
       N.n[B.fax[0]] = sg(B.fsd[0]) * r;
@@ -160,6 +213,14 @@ BNorm boundary_normal(int D, const HFeat &A, const HFeat &B) {
     N.n[o] = sg((B.bits >> o) & 1);
   } else if (A.kind == K_EDGE3) {
     N.n[A.axis] = sg((B.bits >> A.axis) & 1);
+  } else if (A.kind == K_POLY) {   // along the end segment, away from the curve
+    if (A.end[0] == B.hole) {
+      N.n[0] = -A.t_first[0];
+      N.n[1] = -A.t_first[1];
+    } else {
+      N.n[0] = A.t_last[0];
+      N.n[1] = A.t_last[1];
+    }
   }
   return N;
 }
@@ -231,6 +292,32 @@ static sph_status validate(const sph_geometry *g, const sph_sizing *s, const sph
     if (nodes > (1ll << 27)) return fail(SPH_ERR_INVALID_ARG, "level-set grid has too many nodes");
     for (int64_t k = 0; k < nodes; ++k)
       if (!std::isfinite(g->phi[k])) return fail(SPH_ERR_INVALID_ARG, "phi is not finite");
+    if (g->n_curves < 0 || g->n_corners < 0) return fail(SPH_ERR_INVALID_ARG, "negative curve count");
+    if (g->n_curves > 0) {
+      if (g->dim != 2) return fail(SPH_ERR_INVALID_ARG, "imported curves are 2D only");
+      if (!g->curve_off || !g->curve_pts || !g->curve_ends || (g->n_corners > 0 && !g->corners))
+        return fail(SPH_ERR_INVALID_ARG, "imported curves: NULL array");
+      if (1 + g->n_curves + g->n_corners > MAXF)
+        return fail(SPH_ERR_UNSUPPORTED, "too many imported features");
+      if (g->curve_off[0] != 0) return fail(SPH_ERR_INVALID_ARG, "curve_off[0] must be 0");
+      for (int c = 0; c < g->n_curves; ++c) {
+        const int a0 = g->curve_off[c], a1 = g->curve_off[c + 1];
+        if (a1 - a0 < 2 || a1 > (1 << 24))
+          return fail(SPH_ERR_INVALID_ARG, "curve %d needs 2 to 2^24 points", c);
+        for (int e = 0; e < 2; ++e)
+          if (g->curve_ends[2 * c + e] < -1 || g->curve_ends[2 * c + e] >= g->n_corners)
+            return fail(SPH_ERR_INVALID_ARG, "curve %d: bad end corner", c);
+        for (int k = a0; k < a1; ++k) {
+          const double *pt = g->curve_pts + 3 * k;
+          if (!std::isfinite(pt[0]) || !std::isfinite(pt[1]))
+            return fail(SPH_ERR_INVALID_ARG, "curve %d: non-finite point", c);
+          if (k + 1 < a1 && pt[0] == pt[3] && pt[1] == pt[4])
+            return fail(SPH_ERR_INVALID_ARG, "curve %d: repeated point", c);
+        }
+      }
+      for (int m = 0; m < 3 * g->n_corners; ++m)
+        if (!std::isfinite(g->corners[m])) return fail(SPH_ERR_INVALID_ARG, "non-finite corner");
+    }
   }
   if (g->domain == SPH_DOMAIN_BALL) {
     if (g->n_holes != 0) return fail(SPH_ERR_INVALID_ARG, "a ball domain takes no holes");
@@ -380,6 +467,8 @@ struct HostJob {
   int n = 0;
   double *d_grid = nullptr;   // gridded sizing: the job's copy of the node values
   double *d_phi = nullptr;    // level-set domain: the job's copy of phi
+  double *d_cpts = nullptr;   // imported curves: the job's copy of their points
+  int32_t *d_coff = nullptr;  // ... and of their offsets
   uint32_t ncell = 0, cbase = 0;
   int nf = 0;
   std::vector<HFeat> feats;
@@ -439,6 +528,8 @@ struct sph_batch {
     for (HostJob &J : jobs) {
       if (J.d_grid) (void)hipFree(J.d_grid);
       if (J.d_phi) (void)hipFree(J.d_phi);
+      if (J.d_cpts) (void)hipFree(J.d_cpts);
+      if (J.d_coff) (void)hipFree(J.d_coff);
     }
     for (void *p : owned) (void)hipFree(p);
     if (own_stream && stream) (void)hipStreamDestroy(stream);
@@ -467,7 +558,8 @@ struct sph_batch {
     for (int j = 0; j < njobs; ++j)
       if (jobs[j].live)
         for (const HFeat &F : jobs[j].feats)
-          B.has_hole |= F.kind == K_HOLE || F.kind == K_SHELL || F.kind == K_LEVEL;
+          B.has_hole |= F.kind == K_HOLE || F.kind == K_SHELL || F.kind == K_LEVEL ||
+                        F.kind == K_POLY;
     return B;
   }
   uint32_t ntiles() const { return (ncell + SCAN_TILE - 1) / SCAN_TILE; }
@@ -721,7 +813,7 @@ static void grid_of(const sph_geometry *g, const sph_sizing *s, const sph_params
 static void fill_job(HostJob &J, const sph_geometry *g, const sph_sizing *s, const sph_params *p,
                      uint32_t cbase, int n) {
   const int D = g->dim;
-  J.feats = make_features(D, g->n_holes, g->domain);
+  J.feats = make_features_of(g);
   for (HFeat &F : J.feats)
     if (F.kind == K_HOLE) F.ell = hole_is_ellipsoid(D, g->holes + 15 * F.hole) ? 1 : 0;
   J.nf = (int)J.feats.size();
@@ -806,7 +898,7 @@ static sph_status check_particles(const sph_geometry *g, int64_t n, const double
                                   const int32_t *feature) {
   if (n < 0 || n > 0x7ffffff0ll || (n > 0 && (!xyz || !feature)))
     return fail(SPH_ERR_INVALID_ARG, "bad particle count or NULL particle arrays");
-  const int nf = (int)make_features(g->dim, g->n_holes, g->domain).size();
+  const int nf = (int)make_features_of(g).size();
   if (nf > MAXF) return fail(SPH_ERR_UNSUPPORTED, "too many features (%d > %d)", nf, MAXF);
   for (int64_t i = 0; i < n; ++i) {
     if (feature[i] < 0 || feature[i] >= nf)
@@ -970,7 +1062,7 @@ extern "C" sph_status sph_batch_add(sph_batch *b, const sph_geometry *g, const s
   if (g->dim != b->D) return fail(SPH_ERR_INVALID_ARG, "job dimension %d != batch dimension %d",
                                   g->dim, b->D);
   if (sph_status st = check_particles(g, n, xyz, feature)) return st;
-  const int nf = (int)make_features(g->dim, g->n_holes, g->domain).size();
+  const int nf = (int)make_features_of(g).size();
   int slot = -1;
   for (int j = 0; j < b->jcap; ++j)
     if (!b->jobs[j].live) {
@@ -1008,6 +1100,22 @@ extern "C" sph_status sph_batch_add(sph_batch *b, const sph_geometry *g, const s
       return fail(SPH_ERR_DEVICE, "level-set upload failed: %s", hipGetErrorString(pe));
     }
     J.dev.g.phi = J.d_phi;
+  }
+  if (g->domain == SPH_DOMAIN_LEVEL_SET && g->n_curves > 0) {   // imported curves
+    const size_t np = (size_t)g->curve_off[g->n_curves];
+    const size_t pb = sizeof(double) * 3 * np, ob = sizeof(int32_t) * (size_t)(g->n_curves + 1);
+    hipError_t ce = hipMalloc((void **)&J.d_cpts, pb);
+    if (ce == hipSuccess) ce = hipMalloc((void **)&J.d_coff, ob);
+    if (ce == hipSuccess) ce = hipMemcpyAsync(J.d_cpts, g->curve_pts, pb, hipMemcpyHostToDevice, b->stream);
+    if (ce == hipSuccess) ce = hipMemcpyAsync(J.d_coff, g->curve_off, ob, hipMemcpyHostToDevice, b->stream);
+    if (ce == hipSuccess) ce = hipStreamSynchronize(b->stream);
+    if (ce != hipSuccess) {
+      for (void *buf : {(void *)J.d_cpts, (void *)J.d_coff, (void *)J.d_phi, (void *)J.d_grid})
+        if (buf) (void)hipFree(buf);
+      return fail(SPH_ERR_DEVICE, "curve upload failed: %s", hipGetErrorString(ce));
+    }
+    J.dev.g.cpts = J.d_cpts;
+    J.dev.g.coff = J.d_coff;
   }
   const int D = b->D;
   // tables of the job's feature slots
@@ -1104,8 +1212,8 @@ extern "C" sph_status sph_batch_add(sph_batch *b, const sph_geometry *g, const s
   if (e == hipSuccess) e = hipStreamSynchronize(q);
   else (void)hipStreamSynchronize(q);
   if (e != hipSuccess) {
-    if (J.d_grid) (void)hipFree(J.d_grid);
-    if (J.d_phi) (void)hipFree(J.d_phi);
+    for (void *buf : {(void *)J.d_cpts, (void *)J.d_coff, (void *)J.d_phi, (void *)J.d_grid})
+      if (buf) (void)hipFree(buf);
     return fail(SPH_ERR_DEVICE, "job upload failed: %s", hipGetErrorString(e));
   }
   J.live = true;
@@ -1157,6 +1265,8 @@ extern "C" sph_status sph_batch_remove(sph_batch *b, int32_t job) {
   R.dev.live = 0;
   R.dev.g.grid = nullptr;
   R.dev.g.phi = nullptr;
+  R.dev.g.cpts = nullptr;
+  R.dev.g.coff = nullptr;
   HIPCHK(hipMemsetAsync(b->d_grp + job * MAXF, 0, sizeof(Group) * MAXF, b->stream));
   HIPCHK(hipMemsetAsync(b->d_st + job, 0, sizeof(JobStat), b->stream));
   HIPCHK(hipMemcpyAsync(b->d_jobs + job, &R.dev, sizeof(JobDev), hipMemcpyHostToDevice, b->stream));
@@ -1169,6 +1279,14 @@ extern "C" sph_status sph_batch_remove(sph_batch *b, int32_t job) {
   if (R.d_phi) {
     (void)hipFree(R.d_phi);
     R.d_phi = nullptr;
+  }
+  if (R.d_cpts) {
+    (void)hipFree(R.d_cpts);
+    R.d_cpts = nullptr;
+  }
+  if (R.d_coff) {
+    (void)hipFree(R.d_coff);
+    R.d_coff = nullptr;
   }
   b->cur = 1 - b->cur;
   b->n = (int)off;

@@ -48,11 +48,14 @@ CASES = {
     # a 2D peanut (two discs) on 65^2 nodes, a 3D torus on 49^3 nodes
     "level_peanut": lambda: wk.level_peanut(),
     "level_torus": lambda: wk.level_torus(),
+    # imported sharp features on a level set: Zalesak's slotted disc, four
+    # polyline curves and four singular points
+    "zalesak_disc": lambda: wk.zalesak_disc(),
 }
 KSTEPS = {"square64": 200, "hole2d_20011": 60, "ball3d_30011": 25, "ell2d_20011": 60,
           "ell3d_30011": 20, "paper_square": 150, "paper_cube": 6, "graded_disc": 60,
           "paper_sphere01": 10, "paper_sphere02": 6, "square_grid33": 60, "ball3d_grid17": 10,
-          "level_peanut": 60, "level_torus": 8}
+          "level_peanut": 60, "level_torus": 8, "zalesak_disc": 60}
 
 _wl_cache = {}
 
