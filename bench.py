@@ -134,7 +134,7 @@ def quality(wl, x):
     d, _ = cKDTree(pts).query(pts, k=2)
     h = _h_field(x, wl.dim, wl.sizing, wl.holes)
     r = d[:, 1] / h
-    return dict(mesh=mq.mesh_quality(x, wl.dim, wl.lo, wl.hi, wl.holes, domain=wl.domain),
+    return dict(mesh=mq.mesh_quality(x, wl.dim, wl.lo, wl.hi, wl.holes, domain=wl.domain, level=wl.level),
                 nn_over_h_mean=float(r.mean()), nn_over_h_p1=float(np.percentile(r, 1)),
                 nn_over_h_min=float(r.min()))
 
@@ -244,6 +244,9 @@ PAPER_VALIDATION = {
     "paper_sphere01": dict(theta_min=22.33, theta_max=150.78, gamma_min=0.32, gamma_avg=0.91,
                            theta_min_avg=56.24, slivers={"10": 0, "20": 0, "30": 12, "40": 478},
                            n_elements=68757, runtime_s=448.35, n_iter=4600),
+    "zalesak_disc": dict(G_avg=0.92, G_min=0.65, theta_max=97.73, theta_min=37.23,
+                         theta_min_avg=53.50, n_theta_below_30=0, n_elements=4551,
+                         runtime_s=15.00, n_iter=4200),
     "paper_sphere02": dict(theta_min=26.25, theta_max=143.78, gamma_min=0.32, gamma_avg=0.91,
                            slivers={"10": 0, "20": 0, "30": 18, "40": 1873},
                            n_elements=110706, runtime_s=236.42, n_iter=3800),
@@ -251,7 +254,7 @@ PAPER_VALIDATION = {
 
 
 def validation_run(args):
-    """The paper's square, cube and spheres run through both phases to convergence in
+    """The paper's square, cube, spheres and slotted disc run through both phases to convergence in
     FP32-mixed: the step at which every feature has left Phase One, the
     converged step, the wall time and the mesh quality, beside the paper's
     table values (context: other hardware, other meshing)."""
@@ -262,7 +265,7 @@ def validation_run(args):
     out = {}
     for name, make in (("paper_square", wk.paper_square), ("paper_cube", wk.paper_cube),
                        ("paper_sphere01", wk.paper_sphere01),
-                       ("paper_sphere02", wk.paper_sphere02)):
+                       ("paper_sphere02", wk.paper_sphere02), ("zalesak_disc", wk.zalesak_disc)):
         # E_sys plateaus near 1e-3 in Phase One under these readings, above
         # the paper's 5e-6, so Phase One ends at the step cap used elsewhere
         wl = make(max_phase1_steps=1200)
@@ -291,7 +294,7 @@ def validation_run(args):
                          phase_one_cap=1200,
                          converged=e["converged"], steps=int(c["steps"]), seconds=sec,
                          interactions_per_s=c["interactions"] / sec, e_sys=e["e_sys"],
-                         mesh=mq.mesh_quality(x, wl.dim, wl.lo, wl.hi, wl.holes, domain=wl.domain),
+                         mesh=mq.mesh_quality(x, wl.dim, wl.lo, wl.hi, wl.holes, domain=wl.domain, level=wl.level),
                          paper=PAPER_VALIDATION[name])
         print(f"[bench] {name}: {json.dumps(out[name])}", file=sys.stderr, flush=True)
     print(json.dumps({"metric": "steps and time to the converged mesh, mesh quality",

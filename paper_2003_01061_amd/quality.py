@@ -4,7 +4,8 @@ The particles are the mesh vertices.  As in the paper's sec. 4, connectivity
 is built only after the run, to measure quality: here a Delaunay
 triangulation / tetrahedralisation of the final positions (scipy, Qhull),
 keeping the elements whose centroid lies in the domain (the box minus its
-holes, or the ball inscribed in the box).  The relaxation never uses it.
+holes, the ball inscribed in the box, or the positive phase of a gridded
+level set).  The relaxation never uses it.
 
 Triangles (sec. 4): G = 2 sqrt(3) S / (P H), with S the area, P the
 half-perimeter and H the longest edge (G = 1 for an equilateral triangle),
@@ -23,12 +24,17 @@ from __future__ import annotations
 import numpy as np
 
 
-def inside_domain(pts, dim, lo, hi, holes, domain=0):
+def inside_domain(pts, dim, lo, hi, holes, domain=0, level=None):
     """Strictly inside the box [lo, hi]^dim and outside every hole (hole
     records: centre[3], semi-axes[3], rotation[9] row-major with local
     coordinates y = rot (x - centre); the hole is sum (y_k / a_k)^2 <= 1);
-    for domain 1, strictly inside the ball inscribed in the box."""
+    for domain 1, strictly inside the ball inscribed in the box; for domain
+    2, inside the box where the gridded level set `level` is positive."""
     pts = np.asarray(pts, float)
+    if domain == 2:
+        from .workload import _level_eval
+        ok = np.all((pts[:, :dim] > np.asarray(lo)[:dim]) & (pts[:, :dim] < np.asarray(hi)[:dim]), axis=1)
+        return ok & (_level_eval(level, dim, pts)[0] > 0)
     if domain == 1:
         c = 0.5 * (np.asarray(lo, float)[:dim] + np.asarray(hi, float)[:dim])
         R = 0.5 * (float(hi[0]) - float(lo[0]))
@@ -111,7 +117,7 @@ def summarize_tets(gamma, dih):
                 slivers={str(t): int(np.sum(dmin < t)) for t in (10, 20, 30, 40)})
 
 
-def mesh_quality(xyz, dim, lo, hi, holes, region=None, domain=0):
+def mesh_quality(xyz, dim, lo, hi, holes, region=None, domain=0, level=None):
     """Delaunay mesh of the positions xyz (n x 3) and its quality summary.
     region = (rlo, rhi) restricts the measure to elements whose centroid lies
     in that sub-box (a sample of a mesh too large to tetrahedralise whole:
@@ -126,7 +132,7 @@ def mesh_quality(xyz, dim, lo, hi, holes, region=None, domain=0):
     simp = Delaunay(P).simplices
     cen = np.zeros((len(simp), 3))
     cen[:, :dim] = P[simp].mean(1)
-    ok = inside_domain(cen, dim, lo, hi, holes, domain)
+    ok = inside_domain(cen, dim, lo, hi, holes, domain, level)
     if region is not None:
         ok &= np.all((cen[:, :dim] > rlo) & (cen[:, :dim] < rhi), axis=1)
     simp = simp[ok]

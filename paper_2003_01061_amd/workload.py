@@ -851,24 +851,28 @@ def level_torus(n_total=30000, seed=12, n_grid=49, res=96, **pover):
                         default_params(**pover), n_total, seed, res)
 
 
-def zalesak_disc(n_total=3000, seed=13, n_grid=129, n_arc=256, res=256, **pover):
-    """Zalesak's slotted disc, the paper's example of the feature tags (sec.
-    2.1): the disc of radius 0.3 about (0.5, 0.5) minus the slot
-    [0.45, 0.55] x [0.45, 1], as a level set on an n_grid^2 grid plus the
-    imported sharp features: four curves (the big arc as an n_arc-segment
-    polyline, the slot's two walls and its bottom, each with the domain on
-    its left) meeting at four corners.  Nine features: the volume, four
-    curves, four singular points.  h graded linearly from the slot bottom."""
+def zalesak_disc(n_total=2400, seed=13, n_grid=129, n_arc=256, res=256, uniform=True, **pover):
+    """Zalesak's slotted disc (sec. 2.1's tag example and sec. 4.2's
+    validation case), in the paper's proportions scaled by 0.02: the disc of
+    radius 0.3 (15) about (0.5, 0.5) minus a slot 0.1 (5) wide and 0.5 (25)
+    long from the top, as a level set on an n_grid^2 grid plus the imported
+    sharp features: four curves (the big arc as an n_arc-segment polyline,
+    the slot's two walls and its bottom, each with the domain on its left)
+    meeting at four corners.  Nine features: the volume, four curves, four
+    singular points.  The paper's sizing for this case is defined in a cited
+    work that is not available; h here grows linearly from the slot bottom.
+    As in the paper, the volume particles start uniformly distributed
+    (uniform=False samples them with probability proportional to rho_t)."""
     dim = 2
     R, c0 = 0.3, np.array([0.5, 0.5])
-    xl, xr, yb = 0.45, 0.55, 0.45
+    xl, xr, yb = 0.45, 0.55, 0.3
     ya = 0.5 + math.sqrt(R * R - 0.05 * 0.05)
 
     def phi_fn(x, y, z):
         disc = R - np.hypot(x - c0[0], y - c0[1])
         # signed distance to the slot box [xl, xr] x [yb, 1.2], positive outside
         qx = np.abs(x - 0.5) - 0.05
-        qy = np.abs(y - 0.825) - 0.375
+        qy = np.abs(y - 0.5 * (yb + 1.2)) - 0.5 * (1.2 - yb)
         box = np.hypot(np.maximum(qx, 0), np.maximum(qy, 0)) + np.minimum(np.maximum(qx, qy), 0)
         return np.minimum(disc, box)
 
@@ -930,8 +934,8 @@ def zalesak_disc(n_total=3000, seed=13, n_grid=129, n_arc=256, res=256, **pover)
         p[:, :2] = rng.random((m, 2))
         return p
 
-    xyz = [_sample_rejection(rng, counts[0], box_prop, dim, sizing, holes, 2, hmin,
-                             accept_mask=lambda p: phi(p) > 0)]
+    xyz = [_sample_rejection(rng, counts[0], box_prop, dim, sizing, holes, 0 if uniform else 2,
+                             hmin, accept_mask=lambda p: phi(p) > 0)]
     feat = [np.zeros(counts[0], np.int32)]
     for k, poly in enumerate(polys):
         seg = np.linalg.norm(np.diff(poly, axis=0), axis=1)

@@ -107,3 +107,17 @@ def test_ball_domain_filter():
     assert np.array_equal(keep, np.sum((xyz - 1.0) ** 2, axis=1) < 1.0)
     keep2 = q.inside_domain(xyz, 2, [0, 0, 0], [2, 2, 0], np.zeros((0, 15)), domain=1)
     assert np.array_equal(keep2, np.sum((xyz[:, :2] - 1.0) ** 2, axis=1) < 1.0)
+
+
+def test_level_set_domain_filter():
+    """domain 2: inside the box where the interpolated level set is positive"""
+    from paper_2003_01061_amd import workload as wk
+    wl = wk.zalesak_disc(n_total=800)
+    rng = np.random.default_rng(4)
+    xyz = np.zeros((4000, 3))
+    xyz[:, :2] = rng.random((4000, 2))
+    keep = q.inside_domain(xyz, 2, wl.lo, wl.hi, wl.holes, domain=2, level=wl.level)
+    assert np.array_equal(keep, wk._level_eval(wl.level, 2, xyz)[0] > 0)
+    # the slot is outside: points in its middle are dropped
+    slot = np.array([[0.5, 0.6, 0.0], [0.5, 0.75, 0.0]])
+    assert not np.any(q.inside_domain(slot, 2, wl.lo, wl.hi, wl.holes, domain=2, level=wl.level))
