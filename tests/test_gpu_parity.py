@@ -51,11 +51,15 @@ CASES = {
     # imported sharp features on a level set: Zalesak's slotted disc, four
     # polyline curves and four singular points
     "zalesak_disc": lambda: wk.zalesak_disc(),
+    # both background grids at once: a level-set domain with gridded h_t
+    "peanut_grid33": lambda: wk.with_grid_sizing(wk.level_peanut(), 33),
+    "torus_grid17": lambda: wk.with_grid_sizing(wk.level_torus(n_total=12000, res=64), 17),
 }
 KSTEPS = {"square64": 200, "hole2d_20011": 60, "ball3d_30011": 25, "ell2d_20011": 60,
           "ell3d_30011": 20, "paper_square": 150, "paper_cube": 6, "graded_disc": 60,
           "paper_sphere01": 10, "paper_sphere02": 6, "square_grid33": 60, "ball3d_grid17": 10,
-          "level_peanut": 60, "level_torus": 8, "zalesak_disc": 60}
+          "level_peanut": 60, "level_torus": 8, "zalesak_disc": 60,
+          "peanut_grid33": 40, "torus_grid17": 8}
 
 _wl_cache = {}
 
