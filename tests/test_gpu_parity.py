@@ -226,6 +226,38 @@ def test_edge_cases():
     assert np.abs(g.positions() - ref.state()[0]).max() <= TOL64
 
 
+def test_edge_cases_of_the_ball_and_level_set_domains():
+    def subset(wl, keep):
+        wl.xyz, wl.feature = wl.xyz[keep].copy(), wl.feature[keep].copy()
+        return wl
+
+    def against_oracle(wl, k):
+        ref = oracle.RefJob(wl)
+        ref.step(k)
+        g = binding.SphMesh(wl)
+        g.step(k)
+        assert np.abs(g.positions() - ref.state()[0]).max() <= TOL64
+        return g
+    # a disc with circle particles only (no volume)
+    wl = wk.graded_disc(n_total=600, res=64)
+    against_oracle(subset(wl, wl.feature == 1), 20)
+    # the slotted disc's four corners only: nothing moves, converged at once
+    wl = wk.zalesak_disc(n_total=800)
+    wl = subset(wl, wl.feature >= 5)
+    g = binding.SphMesh(wl)
+    g.step(5)
+    assert np.array_equal(g.positions(), wl.xyz)
+    assert g.error()["converged"]
+    # one imported curve (the slot's bottom) with its two end corners
+    wl = wk.zalesak_disc(n_total=800)
+    against_oracle(subset(wl, (wl.feature == 3) | (wl.feature == 6) | (wl.feature == 7)), 20)
+    # a single volume particle in a level-set domain
+    wl = wk.level_peanut(n_total=800, res=64)
+    first = np.zeros(wl.n, bool)
+    first[np.nonzero(wl.feature == 0)[0][0]] = True
+    against_oracle(subset(wl, first), 10)
+
+
 def test_full_size_square_hole_250k():
     """The benchmark workload at full size: bit-exact lists, 5 steps in FP64
     and FP32-mixed, in the launch configuration the benchmark times."""
