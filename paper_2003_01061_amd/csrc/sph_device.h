@@ -542,6 +542,22 @@ __device__ __forceinline__ int xcd_block() {
 #endif
 }
 
+// the cells of a row (fixed y, z) are consecutive and run along x.  In 3D,
+// a level with at least 64 cells along y and z numbers its rows in 8 x 8
+// tiles of (y, z): the 64 rows of a tile are consecutive and the tiles
+// follow each other row-major.  Rows close in space are then close in the
+// cell order, so the particles the sweeps gather from stay in cache.  The
+// tiles pad y and z to multiples of 8 (the padding rows hold no particle).
+__host__ __device__ __forceinline__ bool rows_tiled(int D, const int *nc) {
+  return D == 3 && nc[1] >= 64 && nc[2] >= 64;
+}
+template <int D>
+__device__ __forceinline__ uint32_t cell_row(const Grid &G, int l, uint32_t cy, uint32_t cz) {
+  if (!rows_tiled(D, G.nc[l])) return cz * (uint32_t)G.nc[l][1] + cy;
+  const uint32_t nyt = ((uint32_t)G.nc[l][1] + 7u) >> 3;
+  return (((cz >> 3) * nyt + (cy >> 3)) << 6) + ((cz & 7u) << 3) + (cy & 7u);
+}
+
 __device__ __forceinline__ int cell_coord(const Grid &G, int l, int a, double p) {
   double t = __builtin_floor((p - G.lo[a]) * G.inv_c[l][a]);
   t = t >= 0.0 ? t : 0.0;   // also maps NaN to cell 0

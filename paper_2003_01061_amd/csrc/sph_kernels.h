@@ -117,7 +117,7 @@ __device__ __forceinline__ void hash_one(const Geom &g, const Grid &G, double4 &
   int c1 = cell_coord(G, l, 1, p[1]);
   int c2 = D == 3 ? cell_coord(G, l, 2, p[2]) : 0;
   cell = G.cbase + G.lbase[l] +
-         ((uint32_t)c2 * (uint32_t)G.nc[l][1] + (uint32_t)c1) * (uint32_t)G.nc[l][0] + (uint32_t)c0;
+         cell_row<D>(G, l, (uint32_t)c1, (uint32_t)c2) * (uint32_t)G.nc[l][0] + (uint32_t)c0;
 }
 
 // Rank of a particle inside its cell.  Lanes of a wave that hold the same
@@ -620,7 +620,7 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
             t1 = t1 >= 0.0 ? t1 : 0.0;
             t0 = t0 < top0 ? t0 : top0;
             t1 = t1 < top0 ? t1 : top0;
-            const uint32_t row = cbase + ((uint32_t)cz * nc1 + (uint32_t)cy) * nc0;
+            const uint32_t row = cbase + cell_row<D>(G, lv, (uint32_t)cy, (uint32_t)cz) * nc0;
             const uint32_t jb = cstart[row + (uint32_t)t0], je = cstart[row + (uint32_t)t1 + 1];
             // NB candidates per pass: records loaded together (the arrays are
             // padded by 8 past the capacity), the predicate evaluated for all of

@@ -772,13 +772,16 @@ static void grid_of(const sph_geometry *g, const sph_sizing *s, const sph_params
     const double side = c * std::ldexp(hmin, l) * cf * scale;
     return std::max(1.0, std::floor((g->hi[a] - g->lo[a]) / side));
   };
+  // cells of a level, with the padding of tiled rows (sph_device.h)
+  auto level_cells = [&](double n0, double n1, double n2) {
+    const int nn[3] = {(int)n0, (int)n1, (int)n2};
+    if (rows_tiled(D, nn)) return n0 * (std::ceil(n1 / 8.0) * 8.0) * (std::ceil(n2 / 8.0) * 8.0);
+    return n0 * n1 * n2;
+  };
   for (;;) {
     double cells = 0.0;
-    for (int l = 0; l < nlev; ++l) {
-      double lc = 1.0;
-      for (int a = 0; a < D; ++a) lc *= cells_at(l, a);
-      cells += lc;
-    }
+    for (int l = 0; l < nlev; ++l)
+      cells += level_cells(cells_at(l, 0), cells_at(l, 1), D == 3 ? cells_at(l, 2) : 1.0);
     if (cells <= 512.0 * 1024 * 1024) break;   // at most 2^29 cells per job
     scale *= 1.25;
   }
@@ -788,7 +791,6 @@ static void grid_of(const sph_geometry *g, const sph_sizing *s, const sph_params
   uint32_t total = 0;
   for (int l = 0; l < nlev; ++l) {
     Gr.lbase[l] = total;
-    uint32_t nl = 1;
     for (int a = 0; a < 3; ++a) {
       if (a < D) {
         Gr.nc[l][a] = (int)cells_at(l, a);
@@ -798,9 +800,8 @@ static void grid_of(const sph_geometry *g, const sph_sizing *s, const sph_params
       } else {
         Gr.nc[l][a] = 1;
       }
-      nl *= (uint32_t)Gr.nc[l][a];
     }
-    total += nl;
+    total += (uint32_t)level_cells(Gr.nc[l][0], Gr.nc[l][1], Gr.nc[l][2]);
     Gr.hthr[l] = l == 0 ? 0.0 : std::ldexp(hmin, l);
     Gr.hcap[l] = l + 1 < nlev ? std::ldexp(hmin, l + 1) : hmax;
   }
