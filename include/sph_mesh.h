@@ -168,7 +168,9 @@ typedef struct {
   int32_t max_phase1_steps;  /* forced end of Phase One */
   int32_t precision;         /* SPH_FP64, or SPH_FP32_MIXED: FP32 kernel sums with
                                 compensated accumulation, FP64 positions,
-                                integration and projection */
+                                integration and projection (the viscous
+                                pair terms take neighbour positions and h
+                                from their FP32 records) */
   int32_t max_neighbors;     /* neighbour-list capacity per particle, rounded up
                                 to a multiple of 8; 0 = 104 in 2D, 320 in 3D */
   double cell_factor;        /* cell side = r_c,min cell_factor, r_c,min the

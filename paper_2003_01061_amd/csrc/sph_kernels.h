@@ -782,7 +782,12 @@ __global__ __launch_bounds__(BLOCK) void k_midpoint(Batch B, Parts s,
 // ---------------------------------------------------------------------------
 // MID: neighbours' v~ and eta come from their mid-point records (3D);
 // otherwise they are formed here from the a^p record, which in 2D also holds
-// v (an extra pass for mid-point records costs more than it saves in 2D)
+// v (an extra pass for mid-point records costs more than it saves in 2D).
+// XF (FP32 sums): a neighbour's position and h come from its 16-byte FP32
+// scan record instead of the 32-byte FP64 one, so the pair differences are
+// those of FP32-rounded coordinates; in 3D that record's h carries the
+// feature id in its 6 low mantissa bits (relative change below 2^-17).  The
+// FP64 mode gathers the FP64 record.
 template <int D, int K, typename R, bool MID>
 __device__ __forceinline__ void sweep_b_sums(const Parts &s, const typename Vec4<R>::T *__restrict__ ap,
                                              const typename Vec4<R>::T *__restrict__ mid,
@@ -798,6 +803,8 @@ __device__ __forceinline__ void sweep_b_sums(const Parts &s, const typename Vec4
   const R etai = (R)(0.2 * klen * xi.w * vmi) * rcp_(hik);
   const R vtiR[3] = {(R)vti[0], (R)vti[1], (R)vti[2]};
   const R halfR = (R)half;
+  constexpr bool XF = sizeof(R) == 4;
+  const float3 xfi = make_float3((float)xi.x, (float)xi.y, (float)xi.z);
 #pragma unroll
   for (int a = 0; a < 3; ++a) Fv[a] = 0.0;
   constexpr int NB = SPH_NBATCH;
@@ -813,21 +820,31 @@ __device__ __forceinline__ void sweep_b_sums(const Parts &s, const typename Vec4
 #pragma unroll
       for (int q = 0; q < NB; ++q) u[q] = e0 + q < cnt ? ub[hb + q] : 0x80000000u;
       double4 xr[NB];
+      float4 fr[NB];
       R4 mr[NB];
 #pragma unroll
       for (int q = 0; q < NB; ++q) {
         const uint32_t j = u[q] & 0x7fffffffu;   // boundary entries fetch a valid slot, unused
-        xr[q] = s.xh[j];
+        if constexpr (XF) fr[q] = s.xf[j]; else xr[q] = s.xh[j];
         mr[q] = MID ? mid[j] : ap[j];
       }
 #pragma unroll
       for (int q = 0; q < NB; ++q) {
         if (u[q] >> 31) continue;
-        const double4 xj = xr[q];
-        const R dx0 = (R)(xi.x - xj.x), dx1 = (R)(xi.y - xj.y);
-        const R dx2 = D == 3 ? (R)(xi.z - xj.z) : R(0);
+        R dx0, dx1, dx2, hj;
+        if constexpr (XF) {
+          dx0 = (R)(xfi.x - fr[q].x);
+          dx1 = (R)(xfi.y - fr[q].y);
+          dx2 = D == 3 ? (R)(xfi.z - fr[q].z) : R(0);
+          hj = (R)(0.5f * (D == 3 ? fr[q].w : fr[q].z));
+        } else {
+          const double4 xj = xr[q];
+          dx0 = (R)(xi.x - xj.x);
+          dx1 = (R)(xi.y - xj.y);
+          dx2 = D == 3 ? (R)(xi.z - xj.z) : R(0);
+          hj = (R)xj.w;
+        }
         const R rr = sqrt_(dx0 * dx0 + dx1 * dx1 + dx2 * dx2);
-        const R hj = (R)xj.w;
         const R hjk = powK<K>(hj);
         R vtj[3], etaj;
         if (MID) {
