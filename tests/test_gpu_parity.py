@@ -134,6 +134,32 @@ def test_first_step_fields(name):
         assert abs(gs["dt"] - rs["dt"]) <= 1e-12 * rs["dt"]
 
 
+@pytest.mark.parametrize("name", ["hole2d_20011", "paper_square", "ball3d_30011", "ell3d_30011"])
+def test_first_step_fields_fp32_mixed(name):
+    """The FP32-mixed path's first-step fields, including the force a that
+    the viscous sweep completes from FP32 neighbour records, within the
+    FP32 field bar (1e-5 of the field's maximum) of the FP64 oracle."""
+    wl = case(name)
+    ref = oracle.RefJob(wl)
+    ref.step(1)
+    gpu = binding.SphMesh(wl, precision=binding.SPH_FP32_MIXED, debug_fields=1)
+    gpu.step(1)
+    pairs = [(binding.FIELD_AP, oracle.F_AP), (binding.FIELD_A, oracle.F_A),
+             (binding.FIELD_VT, oracle.F_VT), (binding.FIELD_GAMMA, oracle.F_GAMMA)]
+    for fg, fr in pairs:
+        g = gpu.field(fg)
+        r = ref.field(fr)
+        scale = np.abs(r).max()
+        assert scale > 0
+        assert np.abs(g - r).max() <= TOL32 * scale, (fg, np.abs(g - r).max() / scale)
+    for f in range(len(wl.ftype)):
+        gs, rs = gpu.group_state(f), ref.group_state(f)
+        if wl.ftype[f] == wk.SI or not np.any(wl.feature == f):
+            continue
+        assert abs(gs["dt1"] - rs["dt1"]) <= TOL32 * rs["dt1"]
+        assert abs(gs["dt"] - rs["dt"]) <= TOL32 * rs["dt"]
+
+
 @pytest.mark.parametrize("name", list(CASES))
 def test_positions_after_k_steps_fp64(name):
     wl = case(name)
