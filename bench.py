@@ -386,7 +386,9 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--pmc-cell-factor", type=float, default=1.0,
-                    help="cell factor of the 'step' counter pass (scan tile 4)")
+                    help="cell factor of the 'step' counter pass")
+    ap.add_argument("--pmc-scan-tile", type=int, default=4, choices=[2, 4, 8],
+                    help="scan tile of the 'step' counter pass")
     ap.add_argument("--pmc-pass", choices=["step", "step3d", "copy"], default=None,
                     help="counter-collection pass for rocprofv3 --pmc: 'step' runs --steps "
                          "eagerly launched FP32-mixed steps of the workload (default tuning), "
@@ -441,7 +443,7 @@ def main():
     wl = wk.square_hole(n_total=args.n)
     if args.pmc_pass == "step":
         j = binding.SphMesh(wl, precision=binding.SPH_FP32_MIXED, use_graph=0,
-                            cell_factor=args.pmc_cell_factor)
+                            cell_factor=args.pmc_cell_factor, scan_tile=args.pmc_scan_tile)
         j.step(args.steps)
         j.sync()
         c = j.counters()
