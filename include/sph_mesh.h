@@ -191,12 +191,16 @@ typedef struct {
                                 the kernel is Wendland C2 at smoothing length
                                 r_c / 2, neighbours satisfy |x_i - x_j| <
                                 r_c max(h_i, h_j) / h, and r_c enters the time
-                                step and the viscosity.  0 = 2.5; [1, 8] */
+                                step and the viscosity.  0 = 2 (smoothing
+                                length h); [1, 8].  2.5 is a mesh-quality
+                                calibration (more regular triangles on the
+                                paper's square) */
   double boundary_scale;     /* factor on the boundary term of the pressure
-                                force (sec. 3.3).  Factor 1 balances the
-                                truncated interior sum exactly, leaving the
-                                first particle half a spacing off a boundary;
-                                0 = 2, which places it one spacing off;
+                                force (sec. 3.3).  0 = 1, the term as printed:
+                                it balances the truncated interior sum
+                                exactly, leaving the first particle half a
+                                spacing off a boundary.  2 is a mesh-quality
+                                calibration that places it one spacing off;
                                 [0.25, 8] */
   int32_t use_graph;         /* 1: steps replay a captured HIP graph */
   int32_t debug_fields;      /* 1: keep gamma, V~ and v~ for sph_mesh_field */

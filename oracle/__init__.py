@@ -49,13 +49,27 @@ F_H, F_AP, F_A, F_VT, F_GAMMA, F_VMID = range(6)
 _dp = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
 
 
-def lib():
-    global _lib
+_lib_omp = None
+
+
+def lib(openmp=False):
+    """The oracle library; openmp=True loads the build whose per-particle
+    loops run on OpenMP threads (bit-identical results, for timing)."""
+    global _lib, _lib_omp
+    if openmp:
+        if _lib_omp is None:
+            _lib_omp = _load(_build.LIB_OMP, openmp=True)
+        return _lib_omp
     if _lib is None:
-        path = _build.LIB
-        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(
-                os.path.join(_build.HERE, "sphref.c")):
-            _build.build()
+        _lib = _load(_build.LIB, openmp=False)
+    return _lib
+
+
+def _load(path, openmp):
+    if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(
+            os.path.join(_build.HERE, "sphref.c")):
+        _build.build(openmp=openmp)
+    if True:
         L = C.CDLL(path)
         L.sphref_W.restype = C.c_double
         L.sphref_W.argtypes = [C.c_int32, C.c_double, C.c_double]
@@ -88,8 +102,7 @@ def lib():
         L.sphref_sample.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                                     C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]
         L.sphref_last_error.restype = C.c_char_p
-        _lib = L
-    return _lib
+    return L
 
 
 def _err():
@@ -168,8 +181,8 @@ def dWdr(k, r, h):
 class RefJob:
     """One relaxation job on the CPU oracle."""
 
-    def __init__(self, wl, xyz=None, feature=None, params=None):
-        L = lib()
+    def __init__(self, wl, xyz=None, feature=None, params=None, openmp=False):
+        L = self.L = lib(openmp)
         self.dim = wl.dim
         self.geom = make_geometry(wl.dim, wl.lo, wl.hi, wl.holes, wl.domain, wl.level)
         self.sizing = make_sizing(wl.sizing)
@@ -181,51 +194,51 @@ class RefJob:
         rc = L.sphref_create(C.byref(self.geom), C.byref(self.sizing), C.byref(self.params),
                              self.n, xyz, feature, C.byref(h))
         if rc:
-            raise RuntimeError("sphref_create: " + _err())
+            raise RuntimeError("sphref_create: " + L.sphref_last_error().decode())
         self.h = h
         self.feature = feature
 
     def __del__(self):
         if getattr(self, "h", None):
-            lib().sphref_destroy(self.h)
+            self.L.sphref_destroy(self.h)
             self.h = None
 
     def step(self, n=1):
-        rc = lib().sphref_step(self.h, n)
+        rc = self.L.sphref_step(self.h, n)
         if rc:
-            raise RuntimeError("sphref_step: " + _err())
+            raise RuntimeError("sphref_step: " + self.L.sphref_last_error().decode())
 
     def set_state(self, xyz=None, vel=None):
         x = None if xyz is None else np.ascontiguousarray(xyz, np.float64)
         v = None if vel is None else np.ascontiguousarray(vel, np.float64)
-        lib().sphref_set_state(self.h, None if x is None else x.ctypes.data,
+        self.L.sphref_set_state(self.h, None if x is None else x.ctypes.data,
                                None if v is None else v.ctypes.data)
 
     def state(self):
         x = np.zeros((self.n, 3))
         v = np.zeros((self.n, 3))
-        lib().sphref_get_state(self.h, x.ctypes.data, v.ctypes.data)
+        self.L.sphref_get_state(self.h, x.ctypes.data, v.ctypes.data)
         return x, v
 
     def field(self, which):
         shape = (self.n, 3) if which in (F_AP, F_A, F_VMID) else (self.n,)
         out = np.zeros(shape)
-        if lib().sphref_get_field(self.h, which, out):
-            raise RuntimeError(_err())
+        if self.L.sphref_get_field(self.h, which, out):
+            raise RuntimeError(self.L.sphref_last_error().decode())
         return out
 
     def neighbors(self):
         """CSR (offsets, ids, rel) of the current positions, ids ascending."""
-        L = lib()
+        L = self.L
         npairs = C.c_int64()
         off = np.zeros(self.n + 1, np.int64)
         if L.sphref_neighbors(self.h, off.ctypes.data, None, None, 0, C.byref(npairs)):
-            raise RuntimeError(_err())
+            raise RuntimeError(self.L.sphref_last_error().decode())
         ids = np.zeros(max(npairs.value, 1), np.int32)
         rel = np.zeros(max(npairs.value, 1), np.int8)
         if L.sphref_neighbors(self.h, off.ctypes.data, ids.ctypes.data, rel.ctypes.data,
                               ids.size, C.byref(npairs)):
-            raise RuntimeError(_err())
+            raise RuntimeError(self.L.sphref_last_error().decode())
         return off, ids[:npairs.value], rel[:npairs.value]
 
     def sample(self, idx, cap_per=256):
@@ -240,10 +253,10 @@ class RefJob:
         ap = np.zeros((m, 3))
         vt = np.zeros(m)
         gam = np.zeros(m)
-        if lib().sphref_sample(self.h, m, idx.ctypes.data, off.ctypes.data, ids.ctypes.data,
+        if self.L.sphref_sample(self.h, m, idx.ctypes.data, off.ctypes.data, ids.ctypes.data,
                                rel.ctypes.data, cap, ap.ctypes.data, vt.ctypes.data,
                                gam.ctypes.data):
-            raise RuntimeError(_err())
+            raise RuntimeError(self.L.sphref_last_error().decode())
         return off, ids[:off[-1]], rel[:off[-1]], ap, vt, gam
 
     def error(self):
@@ -251,18 +264,18 @@ class RefJob:
         ph = C.c_int32()
         conv = C.c_int32()
         st = C.c_int64()
-        lib().sphref_error(self.h, C.byref(e), C.byref(ph), C.byref(conv), C.byref(st))
+        self.L.sphref_error(self.h, C.byref(e), C.byref(ph), C.byref(conv), C.byref(st))
         return dict(e_sys=e.value, phase=ph.value, converged=bool(conv.value), step=st.value)
 
     def group_state(self, f):
         out = np.zeros(10)
-        lib().sphref_group_state(self.h, f, out)
+        self.L.sphref_group_state(self.h, f, out)
         keys = ["phase", "n_ph", "e_sys", "dt1", "dt", "vbar", "reset_next", "a_last", "a_prev", "n_windows"]
         return dict(zip(keys, out.tolist()))
 
     def counters(self):
         out = np.zeros(4)
-        lib().sphref_counters(self.h, out)
+        self.L.sphref_counters(self.h, out)
         return dict(steps=int(out[0]), escaped=int(out[1]), interactions=int(out[2]),
                     interactions_last=int(out[3]))
 

@@ -976,25 +976,23 @@ static int relation(const sphref_job *J, int64_t i, int64_t j) {
   return bounds(&J->G, J->f[i], J->f[j]) ? 2 : 0;
 }
 
-/* cut-off radius r_c in units of h (sec. 2.3 gives no value; 2.5 by
- * default, calibrated on the mesh quality of sec. 4.1's square), and the
- * kernel's smoothing length per unit h (the kernel reaches 2 smoothing
- * lengths) */
+/* cut-off radius r_c in units of h (sec. 2.3 gives no value; 2 by
+ * default, the Wendland kernel's own support of two smoothing lengths at
+ * smoothing length h), and the kernel's smoothing length per unit h (the
+ * kernel reaches 2 smoothing lengths) */
 static double rc_ratio(const sphref_params *P) {
-  return P->kernel_support > 0.0 ? P->kernel_support : 2.5;
+  return P->kernel_support > 0.0 ? P->kernel_support : 2.0;
 }
 static double klen(const sphref_params *P) { return 0.5 * rc_ratio(P); }
 
-/* factor on the boundary term (sec. 3.3 gives the term's form, not its
- * balance).  With factor 1 and weight 1/h_b the boundary sum is the surface
- * integral of the by-parts identity, which for evenly spaced particles
- * cancels the truncated interior sum: the particles then fill the domain up
- * to the boundary, so the first particle off it sits half a spacing away and
- * makes flat elements with the boundary particles.  The boundary particles
- * are mesh vertices themselves; factor 2 places the first particle one
- * spacing from them (exactly one h from a corner on a curve). */
+/* factor on the boundary term.  Eq. (sph_pressure_force_disc_weighted)
+ * carries none: with factor 1 (the default) and weight 1/h_b the boundary
+ * sum is the surface integral of Eq. (gradient_operator_renormSPH_bypart),
+ * which for evenly spaced particles cancels the truncated interior sum.  A
+ * factor above 1 is a calibration, not a reading: factor 2 moves the first
+ * particle off a boundary from half a spacing to one spacing. */
 static double bscale(const sphref_params *P) {
-  return P->boundary_scale > 0.0 ? P->boundary_scale : 2.0;
+  return P->boundary_scale > 0.0 ? P->boundary_scale : 1.0;
 }
 
 /* the pair predicate (symmetric, and covering both kernel supports used,
@@ -1019,9 +1017,46 @@ static int cmp_i32(const void *a, const void *b) {
 }
 static int cmp_i32_desc(const void *a, const void *b) { return cmp_i32(b, a); }
 
+/* candidates of particle i from the bucket grid that pass the predicate and
+ * have a relation; writes their ids to out (if not NULL) and returns how
+ * many there are */
+typedef struct {
+  int64_t nc[3];
+  const int64_t *cstart, *cell, *bucket;
+} buckets_t;
+
+static int64_t scan_particle(const sphref_job *J, const buckets_t *B, int64_t i, int32_t *out) {
+  int D = J->G.dim;
+  int64_t ci[3] = {0, 0, 0};
+  int64_t c = B->cell[i];
+  for (int a = 0; a < D; ++a) { ci[a] = c % B->nc[a]; c /= B->nc[a]; }
+  int64_t m = 0;
+  for (int64_t dz = (D == 3 ? -1 : 0); dz <= (D == 3 ? 1 : 0); ++dz)
+    for (int64_t dy = -1; dy <= 1; ++dy)
+      for (int64_t dx = -1; dx <= 1; ++dx) {
+        int64_t q[3] = {ci[0] + dx, ci[1] + dy, ci[2] + dz};
+        int ok = 1;
+        for (int a = 0; a < D; ++a) if (q[a] < 0 || q[a] >= B->nc[a]) ok = 0;
+        if (!ok) continue;
+        int64_t cc = 0;
+        for (int a = D - 1; a >= 0; --a) cc = cc * B->nc[a] + q[a];
+        for (int64_t t = B->cstart[cc]; t < B->cstart[cc + 1]; ++t) {
+          int64_t j = B->bucket[t];
+          if (j == i || !within(J, i, j)) continue;
+          if (!relation(J, i, j)) continue;
+          if (out) out[m] = (int32_t)j;
+          m++;
+        }
+      }
+  return m;
+}
+
 /* Lists for every non-singular particle.  A uniform bucket grid of side
  * c max(h) only limits which pairs are tested; the set is exactly the pairs
- * that pass the predicate and have a relation.  Ids are sorted ascending. */
+ * that pass the predicate and have a relation.  Ids are sorted ascending.
+ * Each particle's list depends on nothing but the positions and h, so the
+ * count and fill passes may run over particles in any order (in parallel in
+ * the OpenMP build). */
 static int build_lists(sphref_job *J) {
   int D = J->G.dim;
   int64_t n = J->n;
@@ -1046,7 +1081,11 @@ static int build_lists(sphref_job *J) {
   int64_t *cell = malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
   int64_t *bucket = malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
   int64_t *fill = calloc((size_t)ncell, sizeof(int64_t));
-  if (!cstart || !cell || !bucket || !fill) { set_err("out of memory"); return -1; }
+  if (!cstart || !cell || !bucket || !fill) {
+    free(cstart); free(cell); free(bucket); free(fill);
+    set_err("out of memory");
+    return -1;
+  }
   for (int64_t i = 0; i < n; ++i) {
     int64_t c = 0;
     for (int a = D - 1; a >= 0; --a) {
@@ -1059,56 +1098,40 @@ static int build_lists(sphref_job *J) {
   }
   for (int64_t c = 0; c < ncell; ++c) cstart[c + 1] += cstart[c];
   for (int64_t i = 0; i < n; ++i) bucket[cstart[cell[i]] + fill[cell[i]]++] = i;
+  buckets_t B = {{nc[0], nc[1], nc[2]}, cstart, cell, bucket};
 
-  /* count first, then fill */
-  int64_t total = 0;
-  for (int pass = 0; pass < 2; ++pass) {
-    total = 0;
-    for (int64_t i = 0; i < n; ++i) {
-      J->off[i] = total;
-      if (ftype(J, i) == T_SI) continue;
-      int64_t ci[3] = {0, 0, 0};
-      int64_t c = cell[i];
-      for (int a = 0; a < D; ++a) { ci[a] = c % nc[a]; c /= nc[a]; }
-      int64_t begin = total;
-      for (int64_t dz = (D == 3 ? -1 : 0); dz <= (D == 3 ? 1 : 0); ++dz)
-        for (int64_t dy = -1; dy <= 1; ++dy)
-          for (int64_t dx = -1; dx <= 1; ++dx) {
-            int64_t q[3] = {ci[0] + dx, ci[1] + dy, ci[2] + dz};
-            int ok = 1;
-            for (int a = 0; a < D; ++a) if (q[a] < 0 || q[a] >= nc[a]) ok = 0;
-            if (!ok) continue;
-            int64_t cc = 0;
-            for (int a = D - 1; a >= 0; --a) cc = cc * nc[a] + q[a];
-            for (int64_t t = cstart[cc]; t < cstart[cc + 1]; ++t) {
-              int64_t j = bucket[t];
-              if (j == i || !within(J, i, j)) continue;
-              int r = relation(J, i, j);
-              if (!r) continue;
-              if (pass == 1) J->nb[total] = (int32_t)j;
-              total++;
-            }
-          }
-      if (pass == 1)
-        qsort(J->nb + begin, (size_t)(total - begin), sizeof(int32_t),
-              J->P.sum_order ? cmp_i32_desc : cmp_i32);
-    }
-    J->off[n] = total;
-    if (pass == 0 && total > J->cap) {
-      free(J->nb); free(J->rel);
-      J->cap = total + total / 4 + 16;
-      J->nb = malloc(sizeof(int32_t) * (size_t)J->cap);
-      J->rel = malloc(sizeof(int8_t) * (size_t)J->cap);
-      if (!J->nb || !J->rel) { set_err("out of memory"); return -1; }
+  /* count, then offsets, then fill */
+#pragma omp parallel for schedule(dynamic, 256)
+  for (int64_t i = 0; i < n; ++i)
+    J->off[i + 1] = ftype(J, i) == T_SI ? 0 : scan_particle(J, &B, i, NULL);
+  J->off[0] = 0;
+  for (int64_t i = 0; i < n; ++i) J->off[i + 1] += J->off[i];
+  int64_t total = J->off[n];
+  if (total > J->cap) {
+    free(J->nb); free(J->rel);
+    J->cap = total + total / 4 + 16;
+    J->nb = malloc(sizeof(int32_t) * (size_t)J->cap);
+    J->rel = malloc(sizeof(int8_t) * (size_t)J->cap);
+    if (!J->nb || !J->rel) {
+      free(cstart); free(cell); free(bucket); free(fill);
+      set_err("out of memory");
+      return -1;
     }
   }
-  for (int64_t i = 0; i < n; ++i)
-    for (int64_t t = J->off[i]; t < J->off[i + 1]; ++t) J->rel[t] = (int8_t)relation(J, i, J->nb[t]);
+#pragma omp parallel for schedule(dynamic, 256)
+  for (int64_t i = 0; i < n; ++i) {
+    if (ftype(J, i) == T_SI) continue;
+    int32_t *out = J->nb + J->off[i];
+    int64_t m = scan_particle(J, &B, i, out);
+    qsort(out, (size_t)m, sizeof(int32_t), J->P.sum_order ? cmp_i32_desc : cmp_i32);
+    for (int64_t t = 0; t < m; ++t) J->rel[J->off[i] + t] = (int8_t)relation(J, i, out[t]);
+  }
   free(cstart); free(cell); free(bucket); free(fill);
   return 0;
 }
 
 static void compute_h(sphref_job *J) {
+#pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < J->n; ++i) J->h[i] = h_at(&J->G, &J->S, J->x + 3 * i);
 }
 
@@ -1373,6 +1396,7 @@ static int one_step(sphref_job *J) {
       for (int a = 0; a < 3; ++a) J->v[3 * i + a] = 0.0;
 
   int64_t inter = 0;
+#pragma omp parallel for schedule(dynamic, 256) reduction(+ : inter)
   for (int64_t i = 0; i < n; ++i) {
     if (!act[i]) continue;
     int64_t cnt = J->off[i + 1] - J->off[i];
@@ -1398,12 +1422,14 @@ static int one_step(sphref_job *J) {
 
   /* viscous force with the mid-point velocity (nu_i = 0.1 r_c |v~_i| per
    * particle, combined by the harmonic mean of eta) */
+#pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; ++i) {
     if (!act[i]) continue;
     int k = G->f[J->f[i]].k;
     double nu = 0.1 * (rc_ratio(P) * J->h[i]) * norm3(J->vt + 3 * i);
     J->eta[i] = nu / hpow(J->h[i], k);         /* eta = rho_t nu, rho_t = h^-k */
   }
+#pragma omp parallel for schedule(dynamic, 256)
   for (int64_t i = 0; i < n; ++i) {
     if (!act[i]) continue;
     int k = G->f[J->f[i]].k;
@@ -1437,34 +1463,42 @@ static int one_step(sphref_job *J) {
     g->dt = dt_terms(g->dt, rc_ratio(P), J->h[i], norm3(J->a + 3 * i), norm3(J->vt + 3 * i));
   }
 
-  /* integrate (v~ = v^n + dt1 a^p / 2; v^(n+1/2) = v^n + dt a / 2;
-   * x* = x^n + dt v^(n+1/2); v^(n+1) = T (v^(n+1/2) + dt a / 2)) and map onto
-   * the feature */
+  /* integrate and map onto the feature.  Algorithm 1 updates, in order, the
+   * mid-point velocity v~ = v^n + dt1 a^p / 2 (formed above, cited Eq. 26),
+   * the predicted velocity v^(n+1/2) = v^n + dt a / 2 (cited Eq. 27) and the
+   * position x* = x^n + dt v^(n+1/2) (cited Eq. 28), then maps x* onto the
+   * feature; it lists no further velocity update, so the velocity carried
+   * into the next step is v^(n+1/2), tangent to the feature at x^(n+1) */
+  int64_t escaped = 0, nonfinite = 0;
+#pragma omp parallel for schedule(static) reduction(+ : escaped, nonfinite)
   for (int64_t i = 0; i < n; ++i) {
     if (!act[i]) continue;
     double dt = J->g[J->f[i]].dt;
     double vh[3] = {0, 0, 0}, xs[3] = {0, 0, 0};
+    int finite = 1;
     for (int a = 0; a < D; ++a) {
       vh[a] = J->v[3 * i + a] + 0.5 * dt * J->a[3 * i + a];
       xs[a] = J->x[3 * i + a] + dt * vh[a];
+      if (!isfinite(xs[a])) finite = 0;
     }
-    for (int a = 0; a < D; ++a)
-      if (!isfinite(xs[a])) { J->state_error = 1; set_err("non-finite position"); free(act); return -2; }
+    if (!finite) { nonfinite++; continue; }  /* the job stops after this step */
     int type = ftype(J, i);
     if (type == T_V) {
       if (!inside(G, xs)) {                  /* rejected move: stays, velocity zeroed */
         for (int a = 0; a < 3; ++a) J->v[3 * i + a] = 0.0;
-        J->escaped++;
+        escaped++;
         continue;
       }
     } else {
       pproject(G, J->f[i], xs);
     }
     double vn[3] = {0, 0, 0};
-    for (int a = 0; a < D; ++a) vn[a] = vh[a] + 0.5 * dt * J->a[3 * i + a];
+    for (int a = 0; a < D; ++a) vn[a] = vh[a];
     tproject(G, J->f[i], xs, vn);
     for (int a = 0; a < D; ++a) { J->x[3 * i + a] = xs[a]; J->v[3 * i + a] = vn[a]; }
   }
+  J->escaped += escaped;
+  if (nonfinite) { J->state_error = 1; set_err("non-finite position"); free(act); return -2; }
 
   /* V-bar per group and the control law */
   double vbar[MAXF];

@@ -107,10 +107,11 @@ typedef struct {
                               divergence is the noise floor of a trajectory) */
   double kernel_support;   /* cut-off radius r_c in units of h (sec. 2.3 gives
                               no value): the kernel's smoothing length is
-                              r_c / 2; 0 = 2.5 */
+                              r_c / 2; 0 = 2 (smoothing length h) */
   double boundary_scale;   /* factor on the boundary term of the pressure
-                              force; 0 = 2 (the first particle off a boundary
-                              then sits one spacing from it) */
+                              force; 0 = 1 (the term as printed; 2 is a
+                              mesh-quality calibration that moves the first
+                              particle off a boundary to one spacing) */
 } sphref_params;
 
 /* fields for sphref_get_field, all from the last completed step */

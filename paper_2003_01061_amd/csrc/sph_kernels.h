@@ -16,7 +16,7 @@
 //   k_group_reduce   fold the striped accumulators per feature (dt_1, V~ sum)
 //   k_sweep_b        mid-point velocity on the fly, viscous force -> a
 //   k_group_reduce   fold the striped minima of dt
-//   k_integrate_hash v_{n+1/2}, x_{n+1}, projection / rejection, v_{n+1},
+//   k_integrate_hash v_{n+1/2}, x_{n+1}, projection / rejection,
 //                    then h, cell and rank of every particle for the next step
 //   k_control        E_sys, phases, resets, damping of every feature (1 block)
 // A launch covers every job of a batch: particles carry a global feature id
@@ -1032,9 +1032,10 @@ __global__ __launch_bounds__(BLOCK) void k_integrate_hash(
         s.v[i] = make_double4(0.0, 0.0, 0.0, 0.0);
       } else {
         if (F.kind != K_VOL) project<D>(J.g, F, xs);
-        double vn[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-        for (int a = 0; a < D; ++a) vn[a] = vh[a] + 0.5 * dt * a3[a];
+        // the velocity carried into the next step is v^{n+1/2}, tangent to
+        // the feature at x^{n+1}: Algorithm 1 updates the predicted velocity
+        // and the position, and no velocity after them
+        double vn[3] = {vh[0], vh[1], vh[2]};
         if (F.kind != K_VOL) tangent<D>(J.g, F, xs, vn);
         xh.x = xs[0];
         xh.y = xs[1];

@@ -753,9 +753,10 @@ static int level_count(double hmin, double hmax, int want) {
   return std::max(1, std::min(nl, want > 0 ? want : MAXLEV));
 }
 
-// cut-off radius r_c in units of h (sec. 2.3 gives no value); 0 selects 2.5
+// cut-off radius r_c in units of h (sec. 2.3 gives no value); 0 selects 2,
+// the kernel support at smoothing length h
 static double support_of(const sph_params *p) {
-  return p->kernel_support > 0.0 ? p->kernel_support : 2.5;
+  return p->kernel_support > 0.0 ? p->kernel_support : 2.0;
 }
 
 static void grid_of(const sph_geometry *g, const sph_sizing *s, const sph_params *p, Grid &Gr) {
@@ -869,7 +870,7 @@ static void fill_job(HostJob &J, const sph_geometry *g, const sph_sizing *s, con
   d.ksup = support_of(p);
   d.klen = 0.5 * d.ksup;
   d.ksup2 = d.ksup * d.ksup;
-  d.bscale = p->boundary_scale > 0.0 ? p->boundary_scale : 2.0;
+  d.bscale = p->boundary_scale > 0.0 ? p->boundary_scale : 1.0;
   d.G.cbase = cbase;
   J.ncell = d.G.ncell;
   J.cbase = cbase;

@@ -98,11 +98,12 @@ def test_batch_footprint_and_job_cells_are_host_logic():
     assert binding.batch_footprint(**dict(base, max_jobs=65)) == -1
     assert binding.batch_footprint(**dict(base, dim=4)) == -1
     wl = wk.square_lattice(n_side=64)
-    assert wl.params["kernel_support"] == 2.5
-    assert binding.JobSpec(wl).cells() == 25 * 25          # side 2.5/64 on the unit square
-    assert binding.JobSpec(wl, cell_factor=0.5).cells() == 51 * 51
-    two = dict(wl.params, kernel_support=2.0)
-    assert binding.JobSpec(wl, params=two).cells() == 32 * 32
+    assert wl.params["kernel_support"] == 2.0
+    assert binding.JobSpec(wl).cells() == 32 * 32          # side 2/64 on the unit square
+    assert binding.JobSpec(wl, cell_factor=0.5).cells() == 64 * 64
+    wide = dict(wl.params, kernel_support=2.5)
+    assert binding.JobSpec(wl, params=wide).cells() == 25 * 25     # side 2.5/64
+    assert binding.JobSpec(wl, params=dict(wide, kernel_support=0.0)).cells() == 32 * 32
     assert binding.JobSpec(wl, params=dict(wl.params, kernel_support=0.5)).cells() == -1
     bad = dict(wl.params, window_samples=0)
     assert binding.JobSpec(wl, params=bad).cells() == -1

@@ -487,8 +487,8 @@ def test_first_step_displacement():
     assert np.abs(expect).max() > 1e-6
 
 
-@pytest.mark.parametrize("c", [2.0, 2.5])
-def test_time_step_by_hand(c):
+@pytest.mark.parametrize("c,s", [(2.0, 1.0), (2.5, 1.0), (2.5, 2.0)])
+def test_time_step_by_hand(c, s):
     """Eq. (fa_time_step_size) for a single moving curve particle between two
     fixed corners: dt = min(0.25 sqrt(r_c/|a|), r_c/(40 |v|), ...), with
     r_c = c h and the kernel's smoothing length c h / 2."""
@@ -504,6 +504,7 @@ def test_time_step_by_hand(c):
     i = int(np.nonzero(wl.feature == 3)[0][0])
     wl.xyz[i] = [0.3, 0.0, 0.0]
     wl.sizing = dict(kind=wk.H_CONST, h0=0.2, grad=0, dcap=0, point=[0, 0, 0])
+    wl.params = dict(wl.params, boundary_scale=s)
     j = oracle.RefJob(wl)
     j.step(1)
     ap = j.field(oracle.F_AP)[i]
@@ -513,8 +514,6 @@ def test_time_step_by_hand(c):
     # 0.3, the other corner is 0.7 away); boundary term of a 1D particle:
     # s (h^2 + h^2) W_1(0.3, ell) n / h with n = outward tangent (-1, 0) and s
     # the boundary factor; gamma = self term only = W_1(0, ell) h.
-    s = wl.params["boundary_scale"]
-    assert s == 2.0
     q = 0.3 / ell
     W1 = 5 / 8 / ell * (1 - q / 2) ** 3 * (1 + 1.5 * q)
     W10 = 5 / 8 / ell
@@ -575,6 +574,52 @@ def test_control_dt_drop_and_forced_switch():
     ph, rs, es = oracle.control_replay(p, vb, dt)
     assert rs[50] == 1 and rs[60] == 0 and rs[49] == 0
     assert np.all(ph[:249] == 1) and ph[249] == 2
+
+
+def test_damping_schedule_through_the_transition():
+    """Eq. (momentum_equation_new) with the transition reading: the damping
+    term is -eps v^n in Phase One, falls linearly to zero over the transition
+    (eps (1 - n / ramp_steps) at its n-th step) and vanishes in Phase Two.
+    Two jobs step from the same state, one with eps and one without; nothing
+    else in a step depends on eps, so their accelerations differ by exactly
+    -eps_n v^n, with v^n zero on the steps that reset the velocity."""
+    eps, ramp = 0.1, 8
+    wl = wk.square_lattice(n_side=16, seed=3)
+    p = dict(wl.params, max_phase1_steps=4, ramp_steps=ramp, ramp_halving=2, phase2_steps=3)
+    rng = np.random.default_rng(7)
+    v0 = np.zeros((wl.n, 3))
+    v0[:, :2] = rng.normal(scale=1e-3, size=(wl.n, 2))
+    v0[wl.feature >= 5] = 0.0                          # corners do not move
+    for f in range(1, 5):                              # edge particles move along their edge
+        v0[wl.feature == f, 0 if f <= 2 else 1] = 0.0
+    A = oracle.RefJob(wl, params=dict(p, eps_damp=eps))
+    B = oracle.RefJob(wl, params=dict(p, eps_damp=0.0))
+    A.set_state(vel=v0)
+    moving = wl.feature < 5
+    seen = set()
+    for _ in range(16):
+        g = A.group_state(0)
+        assert B.group_state(0)["phase"] == g["phase"]
+        x, v = A.state()
+        B.set_state(x, v)
+        if g["phase"] == 1:
+            e = eps
+        elif g["phase"] == 2:
+            e = eps * (1.0 - g["n_ph"] / ramp)
+        else:
+            e = 0.0
+        vn = np.zeros_like(v) if g["reset_next"] else v
+        A.step(1)
+        B.step(1)
+        aA, aB = A.field(oracle.F_A)[moving], B.field(oracle.F_A)[moving]
+        diff = aA - aB
+        scale = np.abs(aB).max()
+        assert np.abs(diff - (-e * vn[moving])).max() <= 4e-16 * scale
+        if e > 0 and not g["reset_next"]:
+            assert np.abs(diff).max() > 1e-9 * scale
+        seen.add((int(g["phase"]), e > 0 and not g["reset_next"]))
+    # Phase One and transition steps with damping, and undamped Phase Two steps
+    assert {(1, True), (2, True), (3, False)} <= seen
 
 
 # ---------------------------------------------------------------------------
@@ -737,10 +782,10 @@ def _dw2(r, h):
     return 7 / (4 * math.pi * h * h) * (-20 * s * (1 - s) ** 3) / (2 * h) if s < 1 else 0.0
 
 
-@pytest.mark.parametrize("c", [2.0, 2.5])
-def test_two_particle_step_by_hand(c):
+@pytest.mark.parametrize("c,eps", [(2.0, 0.0), (2.5, 0.0), (2.0, 0.15)])
+def test_two_particle_step_by_hand(c, eps):
     wl = wk.square_lattice(n_side=8)
-    wl.params = dict(wl.params, kernel_support=c)
+    wl.params = dict(wl.params, kernel_support=c, eps_damp=eps)
     xi = np.array([0.5, 0.5])
     xj = np.array([0.52, 0.51])
     vi = np.array([0.01, 0.0])
@@ -788,13 +833,15 @@ def test_two_particle_step_by_hand(c):
     acc = []
     for a, b in ((0, 1), (1, 0)):
         Fv = H * (h[a] ** 4 + h[b] ** 4) * _dw2(r, lij) / r * (vt[a] - vt[b])
-        acc.append(ap[a] + Fv)
+        # Eq. (momentum_equation_new): Phase One damping of the velocity v^n
+        acc.append(ap[a] + Fv - eps * V[a])
     dt = dt_of(acc, vt)
     for a in range(2):
+        # Algorithm 1: predicted velocity, position; v^(n+1/2) is carried on
         vh = V[a] + 0.5 * dt * acc[a]
         xn = X[a] + dt * vh
-        vn = vh + 0.5 * dt * acc[a]
         assert np.abs(x1[a, :2] - xn).max() < 1e-15
-        assert np.abs(v1[a, :2] - vn).max() < 1e-12 * np.abs(vn).max()
+        assert np.abs(v1[a, :2] - vh).max() < 1e-12 * np.abs(vh).max()
+        assert np.abs(j.field(oracle.F_A)[a, :2] - acc[a]).max() < 1e-12 * np.abs(acc[a]).max()
     assert abs(j.group_state(0)["dt1"] - dt1) < 1e-13 * dt1
     assert abs(j.group_state(0)["dt"] - dt) < 1e-13 * dt
