@@ -33,17 +33,44 @@ HBM_PEAK_GBS = 8000.0
 # VALU issue peak in wave64 instructions/s: 256 CUs x 4 SIMDs, a wave64 VALU
 # instruction occupies a 16-lane SIMD for 4 cycles, 2.4 GHz
 VALU_PEAK_WAVE_INSTS = 256 * 4 * 2.4e9 / 4
+# the same peak in lane operations (64 per wave64 instruction): 39.3e12/s
+VALU_PEAK_LANE_OPS = VALU_PEAK_WAVE_INSTS * 64
 COUNTERS_MD = os.path.join(ROOT, "profiles", "nbr_forces_square_hole_250k_counters.md")
+COUNTERS_3D_MD = os.path.join(ROOT, "profiles", "cube_ball_2m_counters.md")
 KERNEL_SOURCES = ("paper_2003_01061_amd/csrc/sph_device.h", "paper_2003_01061_amd/csrc/sph_kernels.h")
 
 
-def profiled_counters(cfg):
+def roofline(kernel, byts, avg_s, ctr, launches):
+    """Roofline block of the dominant kernel.  Both fractions are computed:
+    algorithmic HBM bytes per launch over the launch time against 8 TB/s, and
+    (when counters of the current sources exist) VALU lane operations issued
+    per launch over the launch time against the VALU issue peak.  The larger
+    one names the bound."""
+    hbm = byts / avg_s / 1e9
+    blk = {"kernel": kernel, "avg_launch_us": avg_s * 1e6, "bytes_per_launch": byts,
+           "launches": launches, "hbm_achieved_gbs": hbm, "hbm_frac": hbm / HBM_PEAK_GBS,
+           "traffic": None, "traffic_frac": None, "valu_issue_frac": None}
+    if ctr is not None:
+        blk["traffic"] = ctr["traffic"]
+        blk["traffic_frac"] = ctr["traffic"] / avg_s / 1e9 / HBM_PEAK_GBS
+        blk["valu_issue_frac"] = ctr["valu"] / avg_s / VALU_PEAK_WAVE_INSTS
+    if blk["valu_issue_frac"] is not None and blk["valu_issue_frac"] > blk["hbm_frac"]:
+        ops = ctr["valu"] * 64 / avg_s / 1e12
+        blk.update(bound="alu", achieved=ops, peak=VALU_PEAK_LANE_OPS / 1e12, unit="TOP/s",
+                   frac=ops * 1e12 / VALU_PEAK_LANE_OPS)
+    else:
+        blk.update(bound="hbm", achieved=hbm, peak=HBM_PEAK_GBS, unit="GB/s",
+                   frac=hbm / HBM_PEAK_GBS)
+    return blk
+
+
+def profiled_counters(cfg, path=COUNTERS_MD):
     """Counter figures of the dominant kernel from the committed rocprofv3
     summary, or None when the kernel sources changed since they were taken or
     the benchmark runs another configuration."""
     import hashlib
     try:
-        text = open(COUNTERS_MD).read()
+        text = open(path).read()
     except OSError:
         return None
     h = hashlib.sha256()
@@ -112,6 +139,77 @@ def run_timed(wl, precision, steps, warmup, graph=True, cfg=None):
                 converged=e["converged"], positions=x)
 
 
+def phase_one_ends(j, wl, steps, seen):
+    """Record, per moving feature, the step at which it left Phase One (read
+    from its control state while it is in the transition or Phase Two)."""
+    p = wl.params
+    for f in range(len(wl.ftype)):
+        if f in seen or wl.ftype[f] == 0 or not np.any(wl.feature == f):
+            continue
+        g = j.group_state(f)
+        if g["phase"] == 2:
+            seen[f] = steps - int(g["n_ph"])
+        elif g["phase"] == 3:
+            seen[f] = steps - p["ramp_steps"] - int(g["n_ph"])
+
+
+def converge_run(wl, precision, cfg=None, max_steps=6000, chunk=20):
+    """Run a job through both phases until every feature has converged (or
+    max_steps): steps, wall time, and for every feature the step at which
+    Phase One ended, and whether the error criterion (E_sys below the
+    threshold) or the Phase One step cap ended it."""
+    from paper_2003_01061_amd import binding
+    import torch
+    j = binding.SphMesh(wl, precision=precision, use_graph=1, **(cfg or {}))
+    j.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    steps, ends = 0, {}
+    while steps < max_steps:
+        j.step(chunk)
+        steps += chunk
+        phase_one_ends(j, wl, steps, ends)
+        if j.error()["converged"]:
+            break
+    j.sync()
+    sec = time.perf_counter() - t0
+    c, e = j.counters(), j.error()
+    x = j.positions()
+    j.close()
+    cap = wl.params["max_phase1_steps"]
+    return dict(steps=int(c["steps"]), seconds=sec, converged=e["converged"], e_sys=e["e_sys"],
+                escaped=c["escaped"], interactions_per_s=c["interactions"] / sec,
+                phase_one_end={str(f): {"step": s_, "by": "cap" if s_ >= cap else "criterion"}
+                               for f, s_ in sorted(ends.items())},
+                phase_one_cap=cap, positions=x)
+
+
+def cube_ball_leg(args):
+    """The 3D workload (unit cube minus a ball, 2,000,000 particles), FP32
+    sums + FP64 integration: timed steps and the neighbour kernel's roofline.
+    Its working set (~0.5 GB) is larger than the 256 MB Infinity Cache."""
+    from paper_2003_01061_amd import binding
+    from paper_2003_01061_amd import workload as wk
+    wl = wk.cube_ball()
+    prec = binding.SPH_FP32_MIXED
+    r = run_timed(wl, prec, args.steps_3d, 3)
+    stats, pc = profile_kernels(wl, prec, 5)
+    per = {k: (ms / cnt if cnt else 0.0, cnt) for k, (ms, cnt) in stats.items()}
+    n_active = int(np.sum(wl.ftype[wl.feature] != wk.SI))
+    inter_step = pc["interactions"] / max(pc["steps"], 1)
+    byts = kernel_bytes("nbr_forces", wl, n_active, inter_step, 4)
+    ctr = profiled_counters({}, COUNTERS_3D_MD)
+    return {"workload": "cube_ball_3d", "n_particles": wl.n, "steps": args.steps_3d,
+            "value": r["interactions"] / r["seconds"], "unit": "interactions/s",
+            "ms_per_step": r["seconds"] / args.steps_3d * 1e3,
+            "interactions_per_step": r["interactions"] / args.steps_3d,
+            "kernel_support": wl.params["kernel_support"],
+            "boundary_scale": wl.params["boundary_scale"],
+            "roofline": roofline("nbr_forces", byts, per["nbr_forces"][0] * 1e-3, ctr,
+                                 per["nbr_forces"][1]),
+            "kernel_avg_us": {k: round(v[0] * 1e3, 2) for k, v in per.items()}}
+
+
 def profile_kernels(wl, precision, steps, cfg=None):
     """Per-kernel durations from HIP events recorded on the library's stream."""
     from paper_2003_01061_amd import binding
@@ -139,9 +237,9 @@ def quality(wl, x):
                 nn_over_h_min=float(r.min()))
 
 
-def cpu_baseline(wl, budget_s):
+def _oracle_leg(wl, budget_s, openmp):
     import oracle
-    j = oracle.RefJob(wl)
+    j = oracle.RefJob(wl, openmp=openmp)
     t0 = time.perf_counter()
     steps = 0
     while True:
@@ -150,10 +248,24 @@ def cpu_baseline(wl, budget_s):
         if time.perf_counter() - t0 > budget_s:
             break
     t = time.perf_counter() - t0
-    c = j.counters()
-    return dict(value=c["interactions"] / t, unit="interactions/s", cores=1, kind="oracle",
-                sample=f"first {steps} steps of the same workload, single-threaded FP64 oracle, "
-                       f"{t:.1f} s")
+    return j.counters()["interactions"] / t, steps, t
+
+
+def cpu_baseline(wl, budget_s):
+    """The FP64 oracle on this host: the plain single-threaded build and the
+    OpenMP build (the same arithmetic, per-particle loops on every core the
+    process may use), each on the first steps of the same workload."""
+    nproc = os.cpu_count()
+    avail = len(os.sched_getaffinity(0))
+    threads = int(os.environ.get("OMP_NUM_THREADS") or avail)
+    v1, s1, t1 = _oracle_leg(wl, budget_s, False)
+    vn, sn, tn = _oracle_leg(wl, budget_s, True)
+    return dict(value=vn, unit="interactions/s", cores=threads, kind="oracle",
+                sample=f"first {sn} steps of the same workload, FP64 oracle, OpenMP over "
+                       f"particles on {threads} threads, {tn:.1f} s",
+                nproc=nproc, cpus_available=avail,
+                single_thread={"value": v1, "cores": 1,
+                               "sample": f"first {s1} steps, single-threaded, {t1:.1f} s"})
 
 
 def ellipsoid_run(args):
@@ -253,53 +365,50 @@ PAPER_VALIDATION = {
 }
 
 
+VALIDATION_PRESETS = {
+    # the readings as printed: reach 2h, boundary term factor 1, no damping
+    "printed": {},
+    # the mesh-quality calibration (reach 2.5h, boundary factor 2)
+    "calibrated": {"kernel_support": 2.5, "boundary_scale": 2.0},
+    # the same with Phase One damping (eps = 0.1, sec. 3.4.3's range) and a
+    # time-step cap of 0.3 (the setting under which every feature of the
+    # square leaves Phase One by the error criterion on the oracle)
+    "calibrated_damped": {"kernel_support": 2.5, "boundary_scale": 2.0, "eps_damp": 0.1,
+                          "dt_max": 0.3},
+}
+
+
 def validation_run(args):
-    """The paper's square, cube, spheres and slotted disc run through both phases to convergence in
-    FP32-mixed: the step at which every feature has left Phase One, the
-    converged step, the wall time and the mesh quality, beside the paper's
-    table values (context: other hardware, other meshing)."""
-    import torch
+    """The paper's square, cube, spheres and slotted disc run through both
+    phases to convergence in FP32-mixed, under the printed readings and the
+    calibrated presets: for every feature the step at which Phase One ended
+    and whether the error criterion or the step cap ended it, the converged
+    step, the wall time and the mesh quality, beside the paper's table values
+    (context: other hardware, other meshing)."""
     from paper_2003_01061_amd import binding
     from paper_2003_01061_amd import quality as mq
     from paper_2003_01061_amd import workload as wk
     out = {}
+    cap = args.validation_cap
     for name, make in (("paper_square", wk.paper_square), ("paper_cube", wk.paper_cube),
                        ("paper_sphere01", wk.paper_sphere01),
                        ("paper_sphere02", wk.paper_sphere02), ("zalesak_disc", wk.zalesak_disc)):
-        # E_sys plateaus near 1e-3 in Phase One under these readings, above
-        # the paper's 5e-6, so Phase One ends at the step cap used elsewhere
-        wl = make(max_phase1_steps=1200)
-        # Sphere02's sizing changes h by half per support radius: its lists
-        # reach ~330 entries during the relaxation, above the 3D default
-        j = binding.SphMesh(wl, precision=binding.SPH_FP32_MIXED, use_graph=1,
-                            max_neighbors=512 if wl.dim == 3 else 0)
-        j.sync()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        steps, phase_two = 0, None
-        while steps < args.max_steps:
-            j.step(20)
-            steps += 20
-            e = j.error()
-            if phase_two is None and e["phase"] >= 2:
-                phase_two = steps
-            if e["converged"]:
-                break
-        j.sync()
-        sec = time.perf_counter() - t0
-        c, e = j.counters(), j.error()
-        x = j.positions()
-        j.close()
-        out[name] = dict(particles=wl.n, h_scale=wl.scale, phase_one_ended_by_step=phase_two,
-                         phase_one_cap=1200,
-                         converged=e["converged"], steps=int(c["steps"]), seconds=sec,
-                         interactions_per_s=c["interactions"] / sec, e_sys=e["e_sys"],
-                         mesh=mq.mesh_quality(x, wl.dim, wl.lo, wl.hi, wl.holes, domain=wl.domain, level=wl.level),
-                         paper=PAPER_VALIDATION[name])
-        print(f"[bench] {name}: {json.dumps(out[name])}", file=sys.stderr, flush=True)
+        out[name] = {"paper": PAPER_VALIDATION[name]}
+        for preset, over in VALIDATION_PRESETS.items():
+            wl = make(max_phase1_steps=cap, **over)
+            # Sphere02's sizing changes h by half per support radius: its lists
+            # reach ~330 entries during the relaxation, above the 3D default
+            cfg = {"max_neighbors": 512} if wl.dim == 3 else {}
+            r = converge_run(wl, binding.SPH_FP32_MIXED, cfg, max_steps=cap + 1000)
+            x = r.pop("positions")
+            r.update(particles=wl.n, h_scale=wl.scale, params=over,
+                     mesh=mq.mesh_quality(x, wl.dim, wl.lo, wl.hi, wl.holes, domain=wl.domain,
+                                          level=wl.level))
+            out[name][preset] = r
+            print(f"[bench] {name} {preset}: {json.dumps(r)}", file=sys.stderr, flush=True)
     print(json.dumps({"metric": "steps and time to the converged mesh, mesh quality",
                       "data": "synthetic", "precision": "fp32 sums + fp64 integration",
-                      "cases": out}))
+                      "phase_one_cap": cap, "cases": out}))
 
 
 def _build_job(desc):
@@ -399,8 +508,13 @@ def main():
                     help="ellipsoids: the 20M-particle inclusion workload run to convergence; "
                          "validation: the paper's square and cube run to convergence "
                          "(each its own JSON line; not the headline)")
-    ap.add_argument("--max-steps", type=int, default=3000,
-                    help="step cap of the ellipsoid run")
+    ap.add_argument("--max-steps", type=int, default=6000,
+                    help="step cap of the runs to the converged mesh")
+    ap.add_argument("--steps-3d", type=int, default=20,
+                    help="timed steps of the 2M-particle 3D leg")
+    ap.add_argument("--no-3d", action="store_true")
+    ap.add_argument("--validation-cap", type=int, default=4000,
+                    help="Phase One step cap of the validation runs")
     ap.add_argument("--serve-jobs", type=int, default=256)
     ap.add_argument("--serve-rates", type=float, nargs="*", default=[0.9])
     ap.add_argument("--serve-pool-gib", type=float, default=8.0)
@@ -475,10 +589,26 @@ def main():
     inter_step = pc["interactions"] / max(pc["steps"], 1)
     byts = kernel_bytes(dom, wl, n_active, inter_step, 4)
     avg_s = per[dom][0] * 1e-3
-    achieved = byts / avg_s / 1e9
     ctr = profiled_counters(cfg) if dom == "nbr_forces" else None
     print(f"[bench] profile: " + ", ".join(f"{k}={v[0]*1e3:.1f}us" for k, v in per.items()),
           file=sys.stderr, flush=True)
+
+    # the same workload run to the converged mesh in both precisions, whatever
+    # --steps is: FP32-mixed against FP64 at equal converged quality
+    conv = {}
+    for tag, prec in (("fp32", binding.SPH_FP32_MIXED), ("fp64", binding.SPH_FP64)):
+        if tag == "fp64" and args.no_fp64:
+            continue
+        c_ = converge_run(wl, prec, cfg, max_steps=args.max_steps)
+        c_["quality"] = quality(wl, c_.pop("positions"))
+        conv[tag] = c_
+        print(f"[bench] converged {tag}: {c_['steps']} steps {c_['seconds']:.2f}s "
+              f"{c_['interactions_per_s']:.3g}/s", file=sys.stderr, flush=True)
+
+    leg3d = None if args.no_3d else cube_ball_leg(args)
+    if leg3d is not None:
+        print(f"[bench] cube_ball 3D: {leg3d['value']:.3g}/s, nbr_forces "
+              f"{leg3d['roofline']['avg_launch_us']:.0f}us", file=sys.stderr, flush=True)
 
     srv = None if args.no_serve else serving(args)
     lat = None
@@ -505,6 +635,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": "square_hole_2d", "n_particles": wl.n, "h0": 1.0 / 1024,
                    "h_scale": round(wl.scale, 6), "grad": 4.0, "hole_radius": 0.25,
+                   "kernel_support": wl.params["kernel_support"],
+                   "boundary_scale": wl.params["boundary_scale"],
+                   "max_phase1_steps": wl.params["max_phase1_steps"],
                    "steps": args.steps, "precision": "fp32 sums + fp64 integration",
                    "parallelism": "single GPU", "tuned": cfg},
         "autotune": tuned,
@@ -518,19 +651,18 @@ def main():
             "e_sys": r64["e_sys"], "phase": r64["phase"],
             "max_abs_position_diff_vs_fp32": float(np.abs(r64["positions"] - r32["positions"]).max()),
         },
-        "convergence": {"e_sys": r32["e_sys"], "phase": r32["phase"],
-                        "converged": r32["converged"], "escaped": r32["escaped"]},
-        "quality": {"fp32": quality(wl, r32["positions"]),
-                    "fp64": None if r64 is None else quality(wl, r64["positions"])},
+        "timed_region_state": {"e_sys": r32["e_sys"], "phase": r32["phase"],
+                               "converged": r32["converged"], "escaped": r32["escaped"]},
+        "converged": conv,
+        "fp32_vs_fp64_at_convergence": None if "fp64" not in conv else {
+            "interactions_per_s_ratio": conv["fp32"]["interactions_per_s"] / conv["fp64"]["interactions_per_s"],
+            "G_avg": [conv["fp32"]["quality"]["mesh"].get("G_avg"), conv["fp64"]["quality"]["mesh"].get("G_avg")],
+            "theta_min_avg": [conv["fp32"]["quality"]["mesh"].get("theta_min_avg"),
+                              conv["fp64"]["quality"]["mesh"].get("theta_min_avg")]},
+        "cube_ball_3d": leg3d,
         "latency_p50_p99_s": lat,
         "serving": srv,
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None if ctr is None else ctr["traffic"],
-                     "traffic_frac": None if ctr is None else ctr["traffic"] / avg_s / 1e9 / HBM_PEAK_GBS,
-                     "valu_issue_frac": None if ctr is None else ctr["valu"] / avg_s / VALU_PEAK_WAVE_INSTS,
-                     "avg_launch_us": per[dom][0] * 1e3, "bytes_per_launch": byts,
-                     "launches": per[dom][1]},
+        "roofline": roofline(dom, byts, avg_s, ctr, per[dom][1]),
         "kernel_avg_us": {k: round(v[0] * 1e3, 2) for k, v in per.items()},
         "cpu_baseline": cpu,
     }
