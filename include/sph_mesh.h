@@ -304,6 +304,23 @@ sph_status sph_mesh_control_replay(const sph_params *params, int32_t n,
                                    const double *vbar, const double *dt,
                                    int32_t *phase, int32_t *reset, double *e_sys);
 
+/* sph_mesh_control_replay without any allocation, for callers that cannot
+ * allocate (code under HIP graph capture, serving loops that must not call
+ * hipMalloc).  Same law and results as sph_mesh_control_replay, but vbar, dt
+ * (n doubles each), phase, reset (n int32 each) and e_sys (n doubles) are
+ * DEVICE pointers owned by the caller, and the work is enqueued on stream
+ * (a hipStream_t; NULL = the null stream) without waiting: the outputs are
+ * ready when the stream reaches this point.  n <= 1,000,000 (larger series:
+ * SPH_ERR_INVALID_ARG).  The only scratch is one feature's control state in
+ * a fixed device array of the library (about 700 bytes per GPU, kept until
+ * the process ends), re-initialised by every call; calls that overlap on one
+ * GPU (other streams, other threads) race on it and must be serialised by
+ * the caller.  Errors: SPH_ERR_INVALID_ARG, SPH_ERR_DEVICE (launch failure). */
+sph_status sph_mesh_control_replay_noalloc(const sph_params *params, int32_t n,
+                                           const double *vbar, const double *dt,
+                                           int32_t *phase, int32_t *reset, double *e_sys,
+                                           void *stream);
+
 /* Kernel timing with HIP events on the handle's stream.  enable != 0 makes
  * later steps launch without a graph and bracket every kernel with events;
  * sph_mesh_kernel_stats waits for the stream and returns, for kernel `kid`

@@ -92,6 +92,8 @@ def lib():
         L.sph_mesh_group_state.argtypes = [vp, C.c_int32, vp]
         L.sph_mesh_counters.argtypes = [vp, vp]
         L.sph_mesh_control_replay.argtypes = [C.POINTER(Params), C.c_int32, vp, vp, vp, vp, vp]
+        L.sph_mesh_control_replay_noalloc.argtypes = [C.POINTER(Params), C.c_int32, vp, vp, vp,
+                                                      vp, vp, vp]
         L.sph_mesh_profile.argtypes = [vp, C.c_int32]
         L.sph_mesh_kernel_stats.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         L.sph_mesh_kernel_count.restype = C.c_int32
@@ -459,12 +461,21 @@ def control_replay(params, vbar, dt):
     return ph, rs, es
 
 
+def control_replay_noalloc(params, n, vbar, dt, phase, reset, e_sys, stream=None):
+    """sph_mesh_control_replay_noalloc: every array argument is a DEVICE
+    address (an int, e.g. a torch tensor's data_ptr()); enqueued on stream
+    (a hipStream_t handle as an int; None = the null stream)."""
+    p = make_params(params)
+    _check("sph_mesh_control_replay_noalloc", lib().sph_mesh_control_replay_noalloc(
+        C.byref(p), int(n), vbar, dt, phase, reset, e_sys, stream))
+
+
 def exported_symbols():
     """Names the header declares (checked by the CPU test of the ABI)."""
     return ["sph_mesh_create", "sph_mesh_step", "sph_mesh_positions", "sph_mesh_error",
             "sph_mesh_destroy", "sph_mesh_last_error", "sph_mesh_set_state", "sph_mesh_velocities",
             "sph_mesh_neighbors", "sph_mesh_neighbors_of", "sph_mesh_field", "sph_mesh_group_state", "sph_mesh_counters",
-            "sph_mesh_control_replay", "sph_mesh_profile", "sph_mesh_kernel_stats",
+            "sph_mesh_control_replay", "sph_mesh_control_replay_noalloc", "sph_mesh_profile", "sph_mesh_kernel_stats",
             "sph_mesh_kernel_count", "sph_mesh_kernel_name", "sph_mesh_sync",
             "sph_mesh_device_bytes", "sph_batch_footprint", "sph_job_cells", "sph_batch_create",
             "sph_batch_add", "sph_batch_remove", "sph_batch_step", "sph_batch_status",

@@ -1054,13 +1054,24 @@ __global__ __launch_bounds__(BLOCK) void k_integrate_hash(
 }
 
 // ---------------------------------------------------------------------------
-// the control law alone over a synthetic series (test entry point)
+// the control law alone over a synthetic series (test entry point); state is
+// the control state of the one feature replayed, set to a fresh feature's
+// (Phase One, no window yet) before the series
 __global__ void k_control_replay(Ctl P, int n, const double *__restrict__ vbar,
                                  const double *__restrict__ dt, int32_t *__restrict__ phase,
                                  int32_t *__restrict__ reset, double *__restrict__ esys,
-                                 Group *scratch) {
+                                 Group *state) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  Group &G = *scratch;
+  Group &G = *state;
+  {
+    Group g0;
+    unsigned char *z = reinterpret_cast<unsigned char *>(&g0);
+    for (size_t b = 0; b < sizeof g0; ++b) z[b] = 0;
+    g0.phase = PH_ONE;
+    g0.esys = __builtin_inf();
+    g0.tracked = 1;
+    G = g0;
+  }
   for (int k = 0; k < n; ++k) {
     if (G.phase != PH_FROZEN) control_law(P, G, vbar[k], dt[k]);
     phase[k] = G.phase;

@@ -19,6 +19,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1739,15 +1740,18 @@ extern "C" const char *sph_mesh_kernel_name(int32_t kid) {
   return kid >= 0 && kid < KID_COUNT ? kKernelNames[kid] : "";
 }
 
-extern "C" sph_status sph_mesh_control_replay(const sph_params *p, int32_t n, const double *vbar,
-                                              const double *dt, int32_t *phase, int32_t *reset,
-                                              double *e_sys) {
-  if (!p || n < 0 || n > 1000000 || (n && (!vbar || !dt || !phase || !reset || !e_sys)))
-    return fail(SPH_ERR_INVALID_ARG, "bad argument");
+// the longest series a control replay takes
+constexpr int32_t kReplayMax = 1000000;
+
+// arguments of a control replay checked, and the control record built
+static sph_status replay_setup(const sph_params *p, int32_t n, bool bufs, Ctl &C) {
+  if (n > kReplayMax)
+    return fail(SPH_ERR_INVALID_ARG, "series of %d steps exceeds the maximum of %d", n, kReplayMax);
+  if (!p || n < 0 || (n && !bufs)) return fail(SPH_ERR_INVALID_ARG, "bad argument");
   if (p->window_samples < 1 || p->window_samples > MAXRING || p->sample_every < 1 ||
       p->reset_period < 1 || p->ramp_halving < 1 || p->ramp_steps < 1)
     return fail(SPH_ERR_INVALID_ARG, "bad control parameters");
-  Ctl C{};
+  C = Ctl{};
   C.tol = p->tol;
   C.eps_damp = p->eps_damp;
   C.dt_max = p->dt_max;
@@ -1758,23 +1762,26 @@ extern "C" sph_status sph_mesh_control_replay(const sph_params *p, int32_t n, co
   C.ramp_halving = p->ramp_halving;
   C.phase2_steps = p->phase2_steps;
   C.max_phase1_steps = p->max_phase1_steps;
-  Group G0;
-  std::memset(&G0, 0, sizeof G0);
-  G0.phase = PH_ONE;
-  G0.esys = HUGE_VAL;
-  G0.tracked = 1;
+  return SPH_OK;
+}
+
+extern "C" sph_status sph_mesh_control_replay(const sph_params *p, int32_t n, const double *vbar,
+                                              const double *dt, int32_t *phase, int32_t *reset,
+                                              double *e_sys) {
+  Ctl C;
+  if (sph_status st = replay_setup(p, n, vbar && dt && phase && reset && e_sys, C)) return st;
   void *buf = nullptr;
   const size_t nn = std::max(n, 1);
   const size_t bytes = sizeof(Group) + nn * (8 + 8 + 4 + 4 + 8);
   HIPCHK(hipMalloc(&buf, bytes));
   char *b = (char *)buf;
-  Group *dg = (Group *)b;
+  Group *dg = (Group *)b;     // the control state (the kernel initialises it)
   double *dv = (double *)(b + sizeof(Group));
   double *dd = dv + nn;
   double *de = dd + nn;
   int32_t *dp = (int32_t *)(de + nn);
   int32_t *dr = dp + nn;
-  hipError_t e = hipMemcpy(dg, &G0, sizeof G0, hipMemcpyHostToDevice);
+  hipError_t e = hipSuccess;
   if (e == hipSuccess && n) e = hipMemcpy(dv, vbar, n * 8, hipMemcpyHostToDevice);
   if (e == hipSuccess && n) e = hipMemcpy(dd, dt, n * 8, hipMemcpyHostToDevice);
   if (e == hipSuccess) {
@@ -1788,5 +1795,47 @@ extern "C" sph_status sph_mesh_control_replay(const sph_params *p, int32_t n, co
   if (e == hipSuccess && n) e = hipMemcpy(e_sys, de, n * 8, hipMemcpyDeviceToHost);
   (void)hipFree(buf);
   if (e != hipSuccess) return fail(SPH_ERR_DEVICE, "control replay: %s", hipGetErrorString(e));
+  return SPH_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Control replay without allocation.  Its only scratch is the control state
+// the replay kernel evolves (one Group); it lives in this file-scope device
+// array, one copy per GPU for the life of the process.  In host code the
+// array's name is not a device address: each device's address is looked up
+// once with hipGetSymbolAddress (with that device current) and kept.
+static __device__ __align__(256) Group scratch[1];
+static_assert(sizeof(Group) <= 768, "the no-allocation scratch is documented as ~700 bytes");
+
+static std::mutex g_scratch_mu;
+static Group *g_scratch_dev[64];   // address of scratch on device d, or null
+
+static sph_status scratch_on_current_device(Group **out) {
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(SPH_ERR_UNSUPPORTED, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void *ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(SPH_ERR_DEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch_dev[dev] = static_cast<Group *>(ptr);
+  }
+  *out = g_scratch_dev[dev];
+  return SPH_OK;
+}
+
+extern "C" sph_status sph_mesh_control_replay_noalloc(const sph_params *p, int32_t n,
+                                                      const double *vbar, const double *dt,
+                                                      int32_t *phase, int32_t *reset,
+                                                      double *e_sys, void *stream) {
+  Ctl C;
+  if (sph_status st = replay_setup(p, n, vbar && dt && phase && reset && e_sys, C)) return st;
+  Group *state = nullptr;
+  if (sph_status st = scratch_on_current_device(&state)) return st;
+  hipLaunchKernelGGL(k_control_replay, dim3(1), dim3(64), 0, (hipStream_t)stream, C, n, vbar, dt,
+                     phase, reset, e_sys, state);
+  HIPCHK(hipGetLastError());
   return SPH_OK;
 }
