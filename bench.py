@@ -193,6 +193,11 @@ def cube_ball_leg(args):
     wl = wk.cube_ball()
     prec = binding.SPH_FP32_MIXED
     r = run_timed(wl, prec, args.steps_3d, 3)
+    others = {}
+    for tag, p_ in (("fp64", binding.SPH_FP64), ("fp32_compensated", binding.SPH_FP32_COMPENSATED)):
+        o = run_timed(wl, p_, args.steps_3d, 3)
+        others[tag] = {"value": o["interactions"] / o["seconds"],
+                       "ms_per_step": o["seconds"] / args.steps_3d * 1e3}
     stats, pc = profile_kernels(wl, prec, 5)
     per = {k: (ms / cnt if cnt else 0.0, cnt) for k, (ms, cnt) in stats.items()}
     n_active = int(np.sum(wl.ftype[wl.feature] != wk.SI))
@@ -205,6 +210,7 @@ def cube_ball_leg(args):
             "interactions_per_step": r["interactions"] / args.steps_3d,
             "kernel_support": wl.params["kernel_support"],
             "boundary_scale": wl.params["boundary_scale"],
+            "other_precisions": others,
             "roofline": roofline("nbr_forces", byts, per["nbr_forces"][0] * 1e-3, ctr,
                                  per["nbr_forces"][1]),
             "kernel_avg_us": {k: round(v[0] * 1e3, 2) for k, v in per.items()}}
@@ -498,6 +504,10 @@ def main():
                     help="cell factor of the 'step' counter pass")
     ap.add_argument("--pmc-scan-tile", type=int, default=4, choices=[2, 4, 8],
                     help="scan tile of the 'step' counter pass")
+    ap.add_argument("--pmc-precision", choices=["mixed", "compensated", "fp64"], default="mixed",
+                    help="precision of the 'step' and 'step3d' counter passes")
+    ap.add_argument("--no-converge", action="store_true",
+                    help="skip the runs to the converged mesh (profiling runs)")
     ap.add_argument("--pmc-pass", choices=["step", "step3d", "copy"], default=None,
                     help="counter-collection pass for rocprofv3 --pmc: 'step' runs --steps "
                          "eagerly launched FP32-mixed steps of the workload (default tuning), "
@@ -547,16 +557,18 @@ def main():
     if args.workload == "validation":
         validation_run(args)
         return
+    pmc_prec = {"mixed": binding.SPH_FP32_MIXED, "compensated": binding.SPH_FP32_COMPENSATED,
+                "fp64": binding.SPH_FP64}[args.pmc_precision]
     if args.pmc_pass == "step3d":
         wl3 = wk.cube_ball()
-        j = binding.SphMesh(wl3, precision=binding.SPH_FP32_MIXED, use_graph=0)
+        j = binding.SphMesh(wl3, precision=pmc_prec, use_graph=0)
         j.step(args.steps)
         j.sync()
         print(f"[bench] step3d pass: {args.steps} steps", file=sys.stderr, flush=True)
         return
     wl = wk.square_hole(n_total=args.n)
     if args.pmc_pass == "step":
-        j = binding.SphMesh(wl, precision=binding.SPH_FP32_MIXED, use_graph=0,
+        j = binding.SphMesh(wl, precision=pmc_prec, use_graph=0,
                             cell_factor=args.pmc_cell_factor, scan_tile=args.pmc_scan_tile)
         j.step(args.steps)
         j.sync()
@@ -579,6 +591,8 @@ def main():
     if not args.no_fp64:
         r64 = run_timed(wl, binding.SPH_FP64, args.steps, args.warmup, cfg=cfg)
         print(f"[bench] fp64 {r64['seconds']:.3f}s", file=sys.stderr, flush=True)
+    r32c = run_timed(wl, binding.SPH_FP32_COMPENSATED, args.steps, args.warmup, cfg=cfg)
+    print(f"[bench] fp32-compensated {r32c['seconds']:.3f}s", file=sys.stderr, flush=True)
     value = r32["interactions"] / r32["seconds"]
 
     stats, pc = profile_kernels(wl, binding.SPH_FP32_MIXED, args.profile_steps, cfg)
@@ -597,7 +611,7 @@ def main():
     # --steps is: FP32-mixed against FP64 at equal converged quality
     conv = {}
     for tag, prec in (("fp32", binding.SPH_FP32_MIXED), ("fp64", binding.SPH_FP64)):
-        if tag == "fp64" and args.no_fp64:
+        if (tag == "fp64" and args.no_fp64) or args.no_converge:
             continue
         c_ = converge_run(wl, prec, cfg, max_steps=args.max_steps)
         c_["quality"] = quality(wl, c_.pop("positions"))
@@ -653,8 +667,16 @@ def main():
         },
         "timed_region_state": {"e_sys": r32["e_sys"], "phase": r32["phase"],
                                "converged": r32["converged"], "escaped": r32["escaped"]},
+        "fp32_compensated": {
+            "value": r32c["interactions"] / r32c["seconds"],
+            "ms_per_step": r32c["seconds"] / args.steps * 1e3,
+            "note": "FP32 pair terms summed in FP32 with Neumaier compensation (the reported "
+                    "value sums FP32 terms in FP64)",
+            "max_abs_position_diff_vs_fp32": float(np.abs(r32c["positions"] - r32["positions"]).max()),
+            "max_abs_position_diff_vs_fp64": None if r64 is None else
+            float(np.abs(r32c["positions"] - r64["positions"]).max())},
         "converged": conv,
-        "fp32_vs_fp64_at_convergence": None if "fp64" not in conv else {
+        "fp32_vs_fp64_at_convergence": None if "fp64" not in conv or "fp32" not in conv else {
             "interactions_per_s_ratio": conv["fp32"]["interactions_per_s"] / conv["fp64"]["interactions_per_s"],
             "G_avg": [conv["fp32"]["quality"]["mesh"].get("G_avg"), conv["fp64"]["quality"]["mesh"].get("G_avg")],
             "theta_min_avg": [conv["fp32"]["quality"]["mesh"].get("theta_min_avg"),

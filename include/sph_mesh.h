@@ -60,7 +60,7 @@ enum { SPH_P_SINGULAR = 0, SPH_P_CURVE = 1, SPH_P_SURFACE = 2, SPH_P_VOLUME = 3 
 enum { SPH_H_CONST = 0, SPH_H_LINEAR_FROM_POINT = 1, SPH_H_GRADED_TO_HOLES = 2, SPH_H_SHELL = 3,
        SPH_H_GRID = 4 };
 enum { SPH_DOMAIN_BOX = 0, SPH_DOMAIN_BALL = 1, SPH_DOMAIN_LEVEL_SET = 2 };
-enum { SPH_FP64 = 0, SPH_FP32_MIXED = 1 };
+enum { SPH_FP64 = 0, SPH_FP32_MIXED = 1, SPH_FP32_COMPENSATED = 2 };
 
 /* Geometry (paper sec. 2.1 / 3.1): the level set phi > 0 is the box minus
  * the holes.  holes: n_holes x 15 doubles, centre[3], semi_axes[3], rot[9]
@@ -166,11 +166,15 @@ typedef struct {
   int32_t ramp_halving;      /* steps between halvings of the reset period (20) */
   int32_t phase2_steps;      /* Phase Two length before a feature freezes (400) */
   int32_t max_phase1_steps;  /* forced end of Phase One */
-  int32_t precision;         /* SPH_FP64, or SPH_FP32_MIXED: FP32 kernel sums with
-                                compensated accumulation, FP64 positions,
-                                integration and projection (the viscous
-                                pair terms take neighbour positions and h
-                                from their FP32 records) */
+  int32_t precision;         /* SPH_FP64: every step in FP64.
+                                SPH_FP32_MIXED: kernel evaluations and pair
+                                terms in FP32, their sums accumulated in FP64;
+                                FP64 positions, integration and projection
+                                (the viscous pair terms take neighbour
+                                positions and h from their FP32 records).
+                                SPH_FP32_COMPENSATED: as SPH_FP32_MIXED with
+                                the sums in FP32 too, each with Neumaier
+                                compensation */
   int32_t max_neighbors;     /* neighbour-list capacity per particle, rounded up
                                 to a multiple of 8; 0 = 104 in 2D, 320 in 3D */
   double cell_factor;        /* cell side = r_c,min cell_factor, r_c,min the
@@ -346,7 +350,8 @@ typedef struct sph_batch sph_batch;
 
 typedef struct {
   int32_t dim;               /* 2 or 3, shared by every job of the batch */
-  int32_t precision;         /* SPH_FP64 or SPH_FP32_MIXED, shared */
+  int32_t precision;         /* SPH_FP64, SPH_FP32_MIXED or SPH_FP32_COMPENSATED,
+                                shared */
   int64_t max_particles;     /* capacity: particles of all resident jobs */
   int64_t max_cells;         /* capacity: cells of all resident jobs' grids */
   int32_t max_jobs;          /* resident jobs, 1..64 */

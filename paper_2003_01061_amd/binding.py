@@ -14,7 +14,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsphmesh.so")
 
-SPH_FP64, SPH_FP32_MIXED = 0, 1
+SPH_FP64, SPH_FP32_MIXED, SPH_FP32_COMPENSATED = 0, 1, 2
 FIELD_H, FIELD_AP, FIELD_A, FIELD_VT, FIELD_GAMMA, FIELD_VMID = range(6)
 
 

@@ -117,7 +117,7 @@ __device__ __forceinline__ void seg_tangent(const Geom &g, int k, double *t) {
 // cell of x (coordinates clamped to the grid box), and its gradient, the
 // derivative of that multilinear function in the cell
 template <int D>
-__device__ __forceinline__ double ls_phi(const Geom &g, const double *x, double *gr) {
+__host__ __device__ __forceinline__ double ls_phi(const Geom &g, const double *x, double *gr) {
 #pragma clang fp contract(off)
   int c[3] = {0, 0, 0};
   double t[3] = {0.0, 0.0, 0.0};
@@ -293,7 +293,7 @@ struct Vec4<double> {
 // the same steps.
 // ---------------------------------------------------------------------------
 template <int D>
-__device__ __forceinline__ void ell_local(const Geom &g, int q, const double *x, double *y) {
+__host__ __device__ __forceinline__ void ell_local(const Geom &g, int q, const double *x, double *y) {
 #pragma clang fp contract(off)
 #pragma unroll
   for (int k = 0; k < D; ++k) {
@@ -305,7 +305,7 @@ __device__ __forceinline__ void ell_local(const Geom &g, int q, const double *x,
 }
 
 template <int D>
-__device__ __forceinline__ double ell_level(const Geom &g, int q, const double *y) {
+__host__ __device__ __forceinline__ double ell_level(const Geom &g, int q, const double *y) {
 #pragma clang fp contract(off)
   double s = 0.0;
 #pragma unroll
@@ -319,7 +319,7 @@ __device__ __forceinline__ double ell_level(const Geom &g, int q, const double *
 // Newton step on g(t) = sum_k (a_k y_k / (a_k^2 + t))^2 - 1, whose root t
 // gives the closest surface point z_k = a_k^2 y_k / (a_k^2 + t)
 template <int D>
-__device__ __forceinline__ double ell_newton(const Geom &g, int q, const double *y, double t) {
+__host__ __device__ __forceinline__ double ell_newton(const Geom &g, int q, const double *y, double t) {
 #pragma clang fp contract(off)
   double gv = -1.0, dg = 0.0;
 #pragma unroll
@@ -339,7 +339,7 @@ __device__ __forceinline__ double ell_newton(const Geom &g, int q, const double 
 // t0 = max(0, |a y| - max a^2) (left of the root) rises monotonically to it
 // and stops when t no longer increases (64 steps at most)
 template <int D>
-__device__ __forceinline__ double ell_dist(const Geom &g, int q, const double *x) {
+__host__ __device__ __forceinline__ double ell_dist(const Geom &g, int q, const double *x) {
 #pragma clang fp contract(off)
   double y[3] = {0.0, 0.0, 0.0};
   ell_local<D>(g, q, x, y);
@@ -416,7 +416,7 @@ __device__ __forceinline__ void ell_normal(const Geom &g, int q, const double *x
 
 // |x - c_q| in FP32 (for bounds that only prune)
 template <int D>
-__device__ __forceinline__ float center_dist32(const Geom &g, int q, const double *p) {
+__host__ __device__ __forceinline__ float center_dist32(const Geom &g, int q, const double *p) {
   float s = 0.0f;
 #pragma unroll
   for (int a = 0; a < D; ++a) {
@@ -427,7 +427,7 @@ __device__ __forceinline__ float center_dist32(const Geom &g, int q, const doubl
 }
 
 template <int D>
-__device__ __forceinline__ double h_target(const Geom &g, const double *p) {
+__host__ __device__ __forceinline__ double h_target(const Geom &g, const double *p) {
 #pragma clang fp contract(off)
   if (g.hkind == 0) return g.h0;
   if (g.hkind == 1) {
@@ -578,31 +578,9 @@ __device__ __forceinline__ int h_level(const Grid &G, double h) {
 // dimension k (1, 2, 3):
 // W = alpha_k h^-k w(q), w = (1-q/2)^4 (1+2q) (k = 2, 3) or (1-q/2)^3 (1+3q/2)
 // (k = 1); (dW/dr)/r = alpha_k h^-(k+2) w'(q)/q with w'(q)/q = -5 (1-q/2)^3 or
-// -3 (1-q/2)^2, finite at r = 0.
+// -3 (1-q/2)^2, finite at r = 0.  The intrinsic dimension K is a template
+// argument.
 // ---------------------------------------------------------------------------
-template <typename R>
-__device__ __forceinline__ R kalpha(int k) {
-  return k == 1 ? R(0.625) : (k == 2 ? R(0.55704230082163367519) : R(0.41778172561622525639));
-}
-template <typename R>
-__device__ __forceinline__ R wshape(int k, R q) {
-  if (!(q < R(2))) return R(0);
-  R t = R(1) - R(0.5) * q;
-  R t2 = t * t;
-  return k == 1 ? t2 * t * (R(1) + R(1.5) * q) : t2 * t2 * (R(1) + R(2) * q);
-}
-template <typename R>
-__device__ __forceinline__ R dwq(int k, R q) {
-  if (!(q < R(2))) return R(0);
-  R t = R(1) - R(0.5) * q;
-  return k == 1 ? R(-3) * t * t : R(-5) * t * t * t;
-}
-template <typename R>
-__device__ __forceinline__ R powk(R h, int k) {
-  return k == 1 ? h : (k == 2 ? h * h : h * h * h);
-}
-
-// the same with the intrinsic dimension K known at compile time
 template <int K, typename R>
 __device__ __forceinline__ constexpr R kalphaK() {
   return K == 1 ? R(0.625) : (K == 2 ? R(0.55704230082163367519) : R(0.41778172561622525639));
@@ -631,37 +609,39 @@ __device__ __forceinline__ float rcp_(float x) { return __builtin_amdgcn_rcpf(x)
 __device__ __forceinline__ double sqrt_(double x) { return __builtin_sqrt(x); }
 __device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
 
-__device__ __forceinline__ double abs_(double x) { return __builtin_fabs(x); }
-__device__ __forceinline__ float abs_(float x) { return __builtin_fabsf(x); }
-
-// compensated (Neumaier) accumulator for FP32 sums; plain sum for FP64
-template <typename R>
-struct Acc {
-  R s, c;
-  __device__ __forceinline__ void init(R v) { s = v; c = R(0); }
-  __device__ __forceinline__ void add(R v) {
-    R t = s + v;
-    const bool sb = abs_(s) >= abs_(v);
-    R big = sb ? s : v;
-    R small = sb ? v : s;
-    c += (big - t) + small;
-    s = t;
-  }
-  __device__ __forceinline__ R get() const { return s + c; }
-};
+// Accumulation of pair terms.  Sum<false>: the terms (FP64, or FP32 in the
+// FP32-mixed mode) are added in FP64.  Sum<true> (FP32-compensated mode): FP32
+// terms added in FP32 with Neumaier's compensation (Neumaier 1974): the
+// rounding error of every addition is recovered exactly, from whichever of the
+// running sum and the term is larger, and kept in a second FP32 word.
+template <bool CMP>
+struct Sum;
 template <>
-struct Acc<double> {
+struct Sum<false> {
   double s;
   __device__ __forceinline__ void init(double v) { s = v; }
-  __device__ __forceinline__ void add(double v) { s += v; }
+  template <typename T>
+  __device__ __forceinline__ void add(T v) { s += (double)v; }
   __device__ __forceinline__ double get() const { return s; }
+};
+template <>
+struct Sum<true> {
+  float s, c;
+  __device__ __forceinline__ void init(double v) {
+    s = (float)v;
+    c = 0.0f;
+  }
+  __device__ __forceinline__ void add(float v) {
+    const float t = s + v;
+    c += __builtin_fabsf(s) >= __builtin_fabsf(v) ? (s - t) + v : (v - t) + s;
+    s = t;
+  }
+  __device__ __forceinline__ double get() const { return (double)s + (double)c; }
 };
 
 // ---------------------------------------------------------------------------
 // feature geometry: tangent projection and closest-point projection
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double sgn_side(int s) { return s ? 1.0 : -1.0; }
-
 // u <- T_i u: identity on the volume, drop the normal part on a surface, keep
 // the tangent part on a curve, zero on a singular point
 template <int D>
@@ -833,7 +813,7 @@ __device__ __forceinline__ void project(const Geom &g, const Feat &F, double *x)
 // phi(x) > 0: strictly inside the box, strictly outside every hole; or
 // strictly inside the ball domain
 template <int D>
-__device__ __forceinline__ bool inside(const Geom &g, const double *x) {
+__host__ __device__ __forceinline__ bool inside(const Geom &g, const double *x) {
 #pragma clang fp contract(off)
   if (g.domain == 1) {
     double s = 0.0;

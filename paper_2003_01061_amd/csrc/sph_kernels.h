@@ -384,11 +384,10 @@ __global__ __launch_bounds__(BLOCK) void k_rank_gather(Batch B, int n, const uin
 // ---------------------------------------------------------------------------
 // Pair sums of sweep A (Eqs. (gamma_disc_renormSPH), (particle_volume),
 // (sph_pressure_force_disc_weighted)) of particle i of intrinsic dimension K
-// over its neighbour list.  Pair terms are evaluated in R; sums accumulate in
-// FP64 (for R = float this is the compensated accumulation: a few dozen FP32
-// terms add exactly in a 53-bit accumulator).
+// over its neighbour list.  Pair terms are evaluated in R and accumulated by
+// Sum<CMP>: in FP64, or (CMP, R = float) in FP32 with Neumaier compensation.
 // ---------------------------------------------------------------------------
-template <int D, int K, typename R>
+template <int D, int K, typename R, bool CMP>
 __device__ __forceinline__ void sweep_a_sums(const Geom &g, const Parts &s,
                                              const double4 *__restrict__ enrm,
                                              const BNorm *__restrict__ bnrow, int bw, double p0,
@@ -406,10 +405,14 @@ __device__ __forceinline__ void sweep_a_sums(const Geom &g, const Parts &s,
   const R ihik = powK<K>(ihi);
   const R P0 = (R)p0;
   const R wself = alpha * ihik;
-  S = (double)wself;
-  gam = (double)(wself * hik);
+  Sum<CMP> aS, aG, aP[3], aB[3];
+  aS.init((double)wself);
+  aG.init((double)(wself * hik));
 #pragma unroll
-  for (int a = 0; a < 3; ++a) Pi[a] = B[a] = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    aP[a].init(0.0);
+    aB[a].init(0.0);
+  }
   constexpr int NB = SPH_NBATCH;
   static_assert(LB % NB == 0, "record batches tile a list block");
   const uint4 *blk = reinterpret_cast<const uint4 *>(nbr) + (size_t)i * (LB / 4);
@@ -439,14 +442,14 @@ __device__ __forceinline__ void sweep_a_sums(const Geom &g, const Parts &s,
         const R qij = rr * ihij;
         if (!(u[q] >> 31)) {
           const R w = alpha * wshapeK<K>(rr * ihi) * ihik;           // W(r, h_i)
-          S += (double)w;
-          gam += (double)(w * hjk);
+          aS.add(w);
+          aG.add(w * hjk);
           const R ih2 = ihij * ihij;
           const R ihk2 = K == 1 ? ih2 * ihij : (K == 2 ? ih2 * ih2 : ih2 * ih2 * ihij);
           const R c = P0 * hsum * alpha * dwqK<K>(qij) * ihk2;       // (dW/dr)/r at h_ij
-          Pi[0] += (double)(c * dx0);
-          Pi[1] += (double)(c * dx1);
-          if (D == 3) Pi[2] += (double)(c * dx2);
+          aP[0].add(c * dx0);
+          aP[1].add(c * dx1);
+          if (D == 3) aP[2].add(c * dx2);
         } else {
           const int fj = s.f[u[q] & 0x7fffffffu];
           const BNorm N = bnrow[fj & (MAXF - 1)];
@@ -463,13 +466,27 @@ __device__ __forceinline__ void sweep_a_sums(const Geom &g, const Parts &s,
           }
           const R om = (bw == 0 ? rcp_(hj) : (bw == 1 ? powK<K>(hj) * rcp_(hj) : R(0))) * (R)bscale;
           const R w = alpha * wshapeK<K>(qij) * powK<K>(ihij);          // W(r, h_ib)
-          const double c = (double)(P0 * hsum * w * om);
-          B[0] += c * nv[0];
-          B[1] += c * nv[1];
-          if (D == 3) B[2] += c * nv[2];
+          if constexpr (CMP) {   // FP32 terms: the normal rounded to FP32
+            const float c = (float)(P0 * hsum * w * om);
+            aB[0].add(c * (float)nv[0]);
+            aB[1].add(c * (float)nv[1]);
+            if (D == 3) aB[2].add(c * (float)nv[2]);
+          } else {
+            const double c = (double)(P0 * hsum * w * om);
+            aB[0].add(c * nv[0]);
+            aB[1].add(c * nv[1]);
+            if (D == 3) aB[2].add(c * nv[2]);
+          }
         }
       }
     }
+  }
+  S = aS.get();
+  gam = aG.get();
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    Pi[a] = aP[a].get();
+    B[a] = aB[a].get();
   }
 }
 
@@ -483,7 +500,7 @@ __device__ __forceinline__ void sweep_a_sums(const Geom &g, const Parts &s,
 // neighbour instead of once per candidate.  Every particle reads its own
 // job's geometry and grid; cells of different jobs never meet.
 // ---------------------------------------------------------------------------
-template <int D, typename R, bool FORCES, int NB>
+template <int D, typename R, bool FORCES, int NB, bool CMP = false>
 __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
     Batch B, Parts s, const uint32_t *__restrict__ cstart, int all, uint32_t *__restrict__ nbr,
     uint32_t *__restrict__ nnb, typename Vec4<R>::T *__restrict__ ap,
@@ -694,11 +711,11 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
       const BNorm *bnrow = B.bn + (size_t)fi * MAXF;
       double S, gam, Pi[3], B3[3];
       if (k == D)
-        sweep_a_sums<D, D, R>(J.g, s, B.enrm, bnrow, J.bw, J.p0, J.klen, J.bscale, nbr, n, i, count, xi, fi, S, gam, Pi, B3);
+        sweep_a_sums<D, D, R, CMP>(J.g, s, B.enrm, bnrow, J.bw, J.p0, J.klen, J.bscale, nbr, n, i, count, xi, fi, S, gam, Pi, B3);
       else if (k == D - 1)
-        sweep_a_sums<D, D - 1, R>(J.g, s, B.enrm, bnrow, J.bw, J.p0, J.klen, J.bscale, nbr, n, i, count, xi, fi, S, gam, Pi, B3);
+        sweep_a_sums<D, D - 1, R, CMP>(J.g, s, B.enrm, bnrow, J.bw, J.p0, J.klen, J.bscale, nbr, n, i, count, xi, fi, S, gam, Pi, B3);
       else
-        sweep_a_sums<D, 1, R>(J.g, s, B.enrm, bnrow, J.bw, J.p0, J.klen, J.bscale, nbr, n, i, count, xi, fi, S, gam, Pi, B3);
+        sweep_a_sums<D, 1, R, CMP>(J.g, s, B.enrm, bnrow, J.bw, J.p0, J.klen, J.bscale, nbr, n, i, count, xi, fi, S, gam, Pi, B3);
       double a3[3] = {0.0, 0.0, 0.0};
 #pragma unroll
       for (int a = 0; a < D; ++a) a3[a] = -((Pi[a] + B3[a]) / gam);
@@ -788,7 +805,7 @@ __global__ __launch_bounds__(BLOCK) void k_midpoint(Batch B, Parts s,
 // those of FP32-rounded coordinates; in 3D that record's h carries the
 // feature id in its 6 low mantissa bits (relative change below 2^-17).  The
 // FP64 mode gathers the FP64 record.
-template <int D, int K, typename R, bool MID>
+template <int D, int K, typename R, bool MID, bool CMP>
 __device__ __forceinline__ void sweep_b_sums(const Parts &s, const typename Vec4<R>::T *__restrict__ ap,
                                              const typename Vec4<R>::T *__restrict__ mid,
                                              const uint32_t *__restrict__ nbr, int n, int i,
@@ -805,8 +822,9 @@ __device__ __forceinline__ void sweep_b_sums(const Parts &s, const typename Vec4
   const R halfR = (R)half;
   constexpr bool XF = sizeof(R) == 4;
   const float3 xfi = make_float3((float)xi.x, (float)xi.y, (float)xi.z);
+  Sum<CMP> aF[3];
 #pragma unroll
-  for (int a = 0; a < 3; ++a) Fv[a] = 0.0;
+  for (int a = 0; a < 3; ++a) aF[a].init(0.0);
   constexpr int NB = SPH_NBATCH;
   static_assert(LB % NB == 0, "record batches tile a list block");
   const uint4 *blk = reinterpret_cast<const uint4 *>(nbr) + (size_t)i * (LB / 4);
@@ -868,16 +886,18 @@ __device__ __forceinline__ void sweep_b_sums(const Parts &s, const typename Vec4
         const R ihk2 = K == 1 ? ih2 * ihij : (K == 2 ? ih2 * ih2 : ih2 * ih2 * ihij);
         const R c = H * (hi2k + hjk * hjk) * alpha * dwqK<K>(rr * ihij) * ihk2;
 #pragma unroll
-        for (int a = 0; a < D; ++a) Fv[a] += (double)(c * (vtiR[a] - vtj[a]));
+        for (int a = 0; a < D; ++a) aF[a].add(c * (vtiR[a] - vtj[a]));
       }
     }
   }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) Fv[a] = aF[a].get();
 }
 
 // ---------------------------------------------------------------------------
 // sweep B: mid-point velocity, viscous force, damping
 // ---------------------------------------------------------------------------
-template <int D, typename R>
+template <int D, typename R, bool CMP = false>
 __global__ __launch_bounds__(BLOCK) void k_sweep_b(Batch B, Parts s,
                                                    const uint32_t *__restrict__ nbr,
                                                    const uint32_t *__restrict__ nnb,
@@ -912,11 +932,11 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_b(Batch B, Parts s,
       const uint32_t cnt = nnb[i];
       double fv[3];
       if (k == D)
-        sweep_b_sums<D, D, R, D == 3>(s, ap, mid, nbr, n, i, cnt, xi, vti, vmi, half, J.klen, fv);
+        sweep_b_sums<D, D, R, D == 3, CMP>(s, ap, mid, nbr, n, i, cnt, xi, vti, vmi, half, J.klen, fv);
       else if (k == D - 1)
-        sweep_b_sums<D, D - 1, R, D == 3>(s, ap, mid, nbr, n, i, cnt, xi, vti, vmi, half, J.klen, fv);
+        sweep_b_sums<D, D - 1, R, D == 3, CMP>(s, ap, mid, nbr, n, i, cnt, xi, vti, vmi, half, J.klen, fv);
       else
-        sweep_b_sums<D, 1, R, D == 3>(s, ap, mid, nbr, n, i, cnt, xi, vti, vmi, half, J.klen, fv);
+        sweep_b_sums<D, 1, R, D == 3, CMP>(s, ap, mid, nbr, n, i, cnt, xi, vti, vmi, half, J.klen, fv);
       double xa[3] = {xi.x, xi.y, xi.z};
       tangent<D>(J.g, F, xa, fv);
       const double eps = B.grp[fi].eps;

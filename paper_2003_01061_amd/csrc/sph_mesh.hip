@@ -366,8 +366,10 @@ static sph_status validate(const sph_geometry *g, const sph_sizing *s, const sph
     return fail(SPH_ERR_INVALID_ARG, "need dt_max > 0, tol >= 0, p0 > 0");
   if (p->boundary_weighting < 0 || p->boundary_weighting > 2)
     return fail(SPH_ERR_INVALID_ARG, "boundary_weighting must be 0, 1 or 2");
-  if (p->precision != SPH_FP64 && p->precision != SPH_FP32_MIXED)
-    return fail(SPH_ERR_INVALID_ARG, "precision must be SPH_FP64 or SPH_FP32_MIXED");
+  if (p->precision != SPH_FP64 && p->precision != SPH_FP32_MIXED &&
+      p->precision != SPH_FP32_COMPENSATED)
+    return fail(SPH_ERR_INVALID_ARG,
+                "precision must be SPH_FP64, SPH_FP32_MIXED or SPH_FP32_COMPENSATED");
   if (p->max_neighbors < 0 || p->max_neighbors > 4096)
     return fail(SPH_ERR_INVALID_ARG, "max_neighbors must be in [0, 4096]");
   if (p->scan_tile != 0 && p->scan_tile != 2 && p->scan_tile != 4 && p->scan_tile != 8)
@@ -638,30 +640,30 @@ struct sph_batch {
   }
 
   // the neighbour + sweep A kernel for the batch's scan tile
-  template <int DD, typename R>
+  template <int DD, typename R, bool CMP>
   hipError_t launch_nbr_forces(const Batch &B, const Parts &s) {
     using R4 = typename Vec4<R>::T;
     auto go = [&](auto kern) {
       return launch(KID_NBR_FORCES, kern, blocks8(n), BLOCK, B, s, (const uint32_t *)cstart, 0,
                     nbr, nnb, (R4 *)ap, dbg_gam, dbg_vt);
     };
-    if (tile == 2) return go(k_nbr_forces<DD, R, true, 2>);
-    if (tile == 8) return go(k_nbr_forces<DD, R, true, 8>);
-    return go(k_nbr_forces<DD, R, true, 4>);
+    if (tile == 2) return go(k_nbr_forces<DD, R, true, 2, CMP>);
+    if (tile == 8) return go(k_nbr_forces<DD, R, true, 8, CMP>);
+    return go(k_nbr_forces<DD, R, true, 4, CMP>);
   }
 
-  template <int DD, typename R>
+  template <int DD, typename R, bool CMP = false>
   sph_status enqueue_forces() {
     using R4 = typename Vec4<R>::T;
     const Batch B = dev();
     const Parts &s = P[cur];
     const unsigned gslots = (unsigned)((njobs * MAXF + BLOCK / 64 - 1) / (BLOCK / 64));
-    HIPCHK((launch_nbr_forces<DD, R>(B, s)));
+    HIPCHK((launch_nbr_forces<DD, R, CMP>(B, s)));
     HIPCHK(launch(KID_REDUCE_A, k_group_reduce, gslots, BLOCK, B, 0));
     if (DD == 3)   // 3D sweep B gathers precomputed mid-point records
       HIPCHK(launch(KID_MIDPOINT, k_midpoint<DD, R>, blocks(n), BLOCK, B, s, (const R4 *)ap,
                     (R4 *)mid));
-    HIPCHK(launch(KID_SWEEP_B, k_sweep_b<DD, R>, blocks8(n), BLOCK, B, s, (const uint32_t *)nbr,
+    HIPCHK(launch(KID_SWEEP_B, k_sweep_b<DD, R, CMP>, blocks8(n), BLOCK, B, s, (const uint32_t *)nbr,
                   (const uint32_t *)nnb, (const R4 *)ap, (const R4 *)mid, (R4 *)acc, dbg_vm));
     HIPCHK(launch(KID_REDUCE_B, k_group_reduce, gslots, BLOCK, B, 1));
     HIPCHK(launch(KID_INTEGRATE_HASH, k_integrate_hash<DD, R>, blocks(n), BLOCK, B, s,
@@ -673,8 +675,13 @@ struct sph_batch {
   sph_status enqueue_step() {
     if (n == 0) return SPH_OK;
     if (sph_status st = enqueue_sort()) return st;
-    if (D == 2) return prec == SPH_FP64 ? enqueue_forces<2, double>() : enqueue_forces<2, float>();
-    return prec == SPH_FP64 ? enqueue_forces<3, double>() : enqueue_forces<3, float>();
+    if (D == 2)
+      return prec == SPH_FP64 ? enqueue_forces<2, double>()
+             : prec == SPH_FP32_COMPENSATED ? enqueue_forces<2, float, true>()
+                                            : enqueue_forces<2, float>();
+    return prec == SPH_FP64 ? enqueue_forces<3, double>()
+           : prec == SPH_FP32_COMPENSATED ? enqueue_forces<3, float, true>()
+                                          : enqueue_forces<3, float>();
   }
 
   sph_status build_graph() {
@@ -950,8 +957,10 @@ extern "C" sph_status sph_batch_create(const sph_batch_params *bp, sph_batch **o
   if (!out) return fail(SPH_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
   if (sph_batch_footprint(bp) < 0) return fail(SPH_ERR_INVALID_ARG, "bad batch parameters");
-  if (bp->precision != SPH_FP64 && bp->precision != SPH_FP32_MIXED)
-    return fail(SPH_ERR_INVALID_ARG, "precision must be SPH_FP64 or SPH_FP32_MIXED");
+  if (bp->precision != SPH_FP64 && bp->precision != SPH_FP32_MIXED &&
+      bp->precision != SPH_FP32_COMPENSATED)
+    return fail(SPH_ERR_INVALID_ARG,
+                "precision must be SPH_FP64, SPH_FP32_MIXED or SPH_FP32_COMPENSATED");
   if (bp->max_particles > 0x7ffffff0ll || bp->max_cells > 0x7ffffff0ll)
     return fail(SPH_ERR_UNSUPPORTED, "capacity above 2^31");
   if (bp->max_neighbors > 4096) return fail(SPH_ERR_INVALID_ARG, "max_neighbors above 4096");

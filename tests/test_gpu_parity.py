@@ -152,15 +152,20 @@ def test_first_step_fields(name):
         assert abs(gs["dt"] - rs["dt"]) <= 1e-12 * rs["dt"]
 
 
+FP32_MODES = [binding.SPH_FP32_MIXED, binding.SPH_FP32_COMPENSATED]
+
+
+@pytest.mark.parametrize("precision", FP32_MODES)
 @pytest.mark.parametrize("name", ["hole2d_20011", "paper_square", "ball3d_30011", "ell3d_30011"])
-def test_first_step_fields_fp32_mixed(name):
-    """The FP32-mixed path's first-step fields, including the force a that
-    the viscous sweep completes from FP32 neighbour records, within the
-    FP32 field bar (1e-5 of the field's maximum) of the FP64 oracle."""
+def test_first_step_fields_fp32_mixed(name, precision):
+    """The FP32 paths' first-step fields (FP32 pair terms summed in FP64, or
+    in FP32 with Neumaier compensation), including the force a that the
+    viscous sweep completes from FP32 neighbour records, within the FP32
+    field bar (1e-5 of the field's maximum) of the FP64 oracle."""
     wl = case(name)
     ref = oracle.RefJob(wl)
     ref.step(1)
-    gpu = binding.SphMesh(wl, precision=binding.SPH_FP32_MIXED, debug_fields=1)
+    gpu = binding.SphMesh(wl, precision=precision, debug_fields=1)
     gpu.step(1)
     pairs = [(binding.FIELD_AP, oracle.F_AP), (binding.FIELD_A, oracle.F_A),
              (binding.FIELD_VT, oracle.F_VT), (binding.FIELD_GAMMA, oracle.F_GAMMA)]
@@ -329,6 +334,21 @@ def test_positions_after_k_steps_fp32_mixed(name):
     ref = oracle.RefJob(wl)
     ref.step(K)
     gpu = binding.SphMesh(wl, precision=binding.SPH_FP32_MIXED, use_graph=1)
+    gpu.step(K)
+    err = np.abs(gpu.positions() - ref.state()[0]).max() / domain(wl)
+    assert err <= TOL32, err
+
+
+@pytest.mark.parametrize("name", ["hole2d_20011", "ball3d_30011", "ell3d_30011", "paper_square",
+                                  "zalesak_disc"])
+def test_positions_after_k_steps_fp32_compensated(name):
+    """FP32 pair terms and FP32 sums with Neumaier compensation: positions
+    within the FP32 bar of the FP64 oracle after the same horizons."""
+    wl = case(name)
+    K = KSTEPS[name]
+    ref = oracle.RefJob(wl)
+    ref.step(K)
+    gpu = binding.SphMesh(wl, precision=binding.SPH_FP32_COMPENSATED, use_graph=1)
     gpu.step(K)
     err = np.abs(gpu.positions() - ref.state()[0]).max() / domain(wl)
     assert err <= TOL32, err
