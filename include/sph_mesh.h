@@ -211,18 +211,82 @@ typedef struct {
   void *stream;              /* hipStream_t to run on (e.g. PyTorch's current
                                 stream), default priority; NULL = the library
                                 creates its own */
+  /* Problem statement of sph_mesh_create (Algorithm 1's set-up; ignored by
+   * the calls that take the caller's particles): */
+  int64_t n_particles;       /* particle budget, split over the features by
+                                their masses (sec. 3.2) with h scaled to fit
+                                it (reading R25); 0 = the masses as they are */
+  uint64_t seed;             /* seed of the 64-bit Mersenne Twister of the
+                                initial sampling (sec. 3.6) */
+  int32_t init;              /* SPH_INIT_DENSITY: positions drawn with
+                                probability proportional to rho_t (sec. 3.6);
+                                SPH_INIT_UNIFORM: uniform on each feature */
+  int32_t mass_res;          /* points per axis of the mass quadrature; 0 =
+                                1024 in 2D, 128 in 3D */
+  /* Device memory: dev_alloc(bytes, alloc_ctx) returns device memory (or
+   * NULL), dev_free(ptr, alloc_ctx) releases it; for instance PyTorch's
+   * caching allocator.  Both NULL = hipMalloc / hipFree.  The library frees
+   * only after its stream has drained. */
+  void *(*dev_alloc)(size_t bytes, void *ctx);
+  void (*dev_free)(void *ptr, void *ctx);
+  void *alloc_ctx;
 } sph_params;
 
-/* sph_mesh_create -- Algorithm 1's set-up with the caller's initial particles.
- * n particles at xyz (n x 3) with feature index feature[i] (numbering above;
- * the feature fixes the particle type P_si / P_c / P_s / P_+, sec. 3.2).
- * Copies everything to the device, builds the feature tables and the cell
- * grid, and returns a handle in *out (library-owned until destroy).
- * Errors: SPH_ERR_INVALID_ARG for a bad description or a feature index out of
- * range, SPH_ERR_OUT_OF_MEMORY, SPH_ERR_DEVICE.  *out is NULL on failure. */
+enum { SPH_INIT_DENSITY = 0, SPH_INIT_UNIFORM = 1 };
+
+/* sph_mesh_create -- Algorithm 1's set-up from the problem statement: the
+ * geometry (sec. 2.1), the target feature size h_t (sec. 2.2) and the
+ * simulation parameters.  The host integrates rho_t = h^-k over every
+ * feature (sec. 3.2's masses M_k; midpoint sums on params->mass_res points per
+ * axis), splits params->n_particles over the features at unit mass with h
+ * scaled by the s that makes sum_k M_k / s^k equal the budget (h0 and the
+ * slope of the linear and two-way sizings multiply by s), places one fixed
+ * particle on every box corner, and draws the others from a 64-bit Mersenne
+ * Twister seeded with params->seed, with probability proportional to rho_t
+ * (params->init = SPH_INIT_DENSITY, sec. 3.6) or uniformly
+ * (SPH_INIT_UNIFORM); then it creates the job as
+ * sph_mesh_create_with_particles does.  sph_mesh_setup_info reports s and
+ * the counts.  Box and ball domains with the analytic sizings;
+ * SPH_ERR_UNSUPPORTED for a level-set domain or a gridded sizing (give their
+ * particles to sph_mesh_create_with_particles).  Errors as below; *out is
+ * NULL on failure. */
 sph_status sph_mesh_create(const sph_geometry *geometry, const sph_sizing *sizing,
-                           const sph_params *params, int64_t n, const double *xyz,
-                           const int32_t *feature, sph_mesh **out);
+                           const sph_params *params, sph_mesh **out);
+
+/* sph_mesh_setup_info -- for a job made by sph_mesh_create: the factor h_t
+ * was scaled by and the particles placed on every feature (counts[f], cap =
+ * capacity of counts; *n_features receives the feature count).  Any output
+ * may be NULL; a job made from the caller's particles reports s = 1 and no
+ * features. */
+sph_status sph_mesh_setup_info(sph_mesh *m, double *h_scale, int64_t *counts, int32_t cap,
+                               int32_t *n_features);
+
+/* sph_job_setup -- the host part of sph_mesh_create alone, with no GPU
+ * call: *h_scale = s, the scaled h0 and slope (*h0_scaled, *grad_scaled:
+ * the sizing the job runs with), the particles per feature (counts[f],
+ * counts_cap its capacity, *n_features the feature count) and, when xyz or
+ * feature is not NULL, the initial particles themselves (xyz: n x 3 host
+ * doubles, feature: n int32, capacity = their particle capacity; *n_out = n),
+ * for instance to add the job to a batch with sph_batch_add.  Any output may
+ * be NULL.  Errors as sph_mesh_create, and SPH_ERR_INVALID_ARG for a capacity
+ * below the counts. */
+sph_status sph_job_setup(const sph_geometry *geometry, const sph_sizing *sizing,
+                         const sph_params *params, double *h_scale, double *h0_scaled,
+                         double *grad_scaled, int64_t *counts, int32_t counts_cap,
+                         int32_t *n_features, double *xyz, int32_t *feature, int64_t capacity,
+                         int64_t *n_out);
+
+/* sph_mesh_create_with_particles -- the same set-up with the caller's
+ * initial particles: n particles at xyz (n x 3) with feature index
+ * feature[i] (numbering above; the feature fixes the particle type P_si /
+ * P_c / P_s / P_+, sec. 3.2).  Copies everything to the device, builds the
+ * feature tables and the cell grid, and returns a handle in *out
+ * (library-owned until destroy).  Errors: SPH_ERR_INVALID_ARG for a bad
+ * description or a feature index out of range, SPH_ERR_OUT_OF_MEMORY,
+ * SPH_ERR_DEVICE.  *out is NULL on failure. */
+sph_status sph_mesh_create_with_particles(const sph_geometry *geometry, const sph_sizing *sizing,
+                                          const sph_params *params, int64_t n, const double *xyz,
+                                          const int32_t *feature, sph_mesh **out);
 
 /* sph_mesh_step -- enqueue n_steps relaxation steps (Algorithm 1's loop body
  * for every feature that has not converged, all features read x^n) on the
@@ -360,6 +424,9 @@ typedef struct {
   int32_t use_graph;         /* 1: steps replay a captured graph of two steps */
   int32_t debug_fields;      /* keep gamma, V~, v~ (single-job inspection) */
   void *stream;              /* hipStream_t; NULL = the batch creates its own */
+  void *(*dev_alloc)(size_t bytes, void *ctx);   /* as in sph_params; both NULL = */
+  void (*dev_free)(void *ptr, void *ctx);        /* hipMalloc / hipFree       */
+  void *alloc_ctx;
 } sph_batch_params;
 
 /* Device bytes a batch with these capacities allocates (admission control);
@@ -375,7 +442,7 @@ int64_t sph_job_cells(const sph_geometry *geometry, const sph_sizing *sizing,
  * fit; *out is NULL on failure. */
 sph_status sph_batch_create(const sph_batch_params *bp, sph_batch **out);
 
-/* Add a job (same arguments as sph_mesh_create; the batch's dimension,
+/* Add a job (same arguments as sph_mesh_create_with_particles; the batch's dimension,
  * precision, neighbour capacity, graph, debug and stream settings apply, the
  * job's own ones are ignored).  Waits for the stream.  *job receives the
  * job's slot id.  SPH_ERR_OUT_OF_MEMORY when the batch has no room for its

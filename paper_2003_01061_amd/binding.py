@@ -46,13 +46,22 @@ class Params(C.Structure):
                 ("scan_tile", C.c_int32), ("cell_levels", C.c_int32),
                 ("kernel_support", C.c_double), ("boundary_scale", C.c_double),
                 ("use_graph", C.c_int32),
-                ("debug_fields", C.c_int32), ("stream", C.c_void_p)]
+                ("debug_fields", C.c_int32), ("stream", C.c_void_p),
+                ("n_particles", C.c_int64), ("seed", C.c_uint64), ("init", C.c_int32),
+                ("mass_res", C.c_int32), ("dev_alloc", C.c_void_p), ("dev_free", C.c_void_p),
+                ("alloc_ctx", C.c_void_p)]
+
+# device allocator callbacks (void *alloc(size_t, void *ctx), void free(void *, void *ctx))
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+SPH_INIT_DENSITY, SPH_INIT_UNIFORM = 0, 1
 
 
 class BatchParams(C.Structure):
     _fields_ = [("dim", C.c_int32), ("precision", C.c_int32), ("max_particles", C.c_int64),
                 ("max_cells", C.c_int64), ("max_jobs", C.c_int32), ("max_neighbors", C.c_int32),
-                ("scan_tile", C.c_int32), ("use_graph", C.c_int32), ("debug_fields", C.c_int32), ("stream", C.c_void_p)]
+                ("scan_tile", C.c_int32), ("use_graph", C.c_int32), ("debug_fields", C.c_int32), ("stream", C.c_void_p),
+                ("dev_alloc", C.c_void_p), ("dev_free", C.c_void_p), ("alloc_ctx", C.c_void_p)]
 
 
 class SphError(RuntimeError):
@@ -74,8 +83,17 @@ def lib():
                               "or python paper_2003_01061_amd/build.py")
         L = C.CDLL(LIB_PATH)
         vp = C.c_void_p
+        L.sph_mesh_create_with_particles.argtypes = [C.POINTER(Geometry), C.POINTER(Sizing),
+                                                     C.POINTER(Params), C.c_int64, vp, vp,
+                                                     C.POINTER(vp)]
         L.sph_mesh_create.argtypes = [C.POINTER(Geometry), C.POINTER(Sizing), C.POINTER(Params),
-                                      C.c_int64, vp, vp, C.POINTER(vp)]
+                                      C.POINTER(vp)]
+        L.sph_mesh_setup_info.argtypes = [vp, C.POINTER(C.c_double), vp, C.c_int32,
+                                          C.POINTER(C.c_int32)]
+        L.sph_job_setup.argtypes = [C.POINTER(Geometry), C.POINTER(Sizing), C.POINTER(Params),
+                                    C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                    C.POINTER(C.c_double), vp, C.c_int32, C.POINTER(C.c_int32),
+                                    vp, vp, C.c_int64, C.POINTER(C.c_int64)]
         L.sph_mesh_step.argtypes = [vp, C.c_int32]
         L.sph_mesh_positions.argtypes = [vp, vp, vp, C.c_int64, C.POINTER(C.c_int64)]
         L.sph_mesh_error.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int32),
@@ -183,14 +201,40 @@ def make_sizing(sz):
     return s
 
 
-def make_params(p, stream=None):
+_POINTERS = ("stream", "dev_alloc", "dev_free", "alloc_ctx")
+
+
+def make_params(p, stream=None, allocator=None):
+    """sph_params from a dict; allocator = (ALLOC_FN, FREE_FN) callbacks kept
+    alive by the caller, or None for hipMalloc / hipFree."""
     q = Params()
     for name, typ in Params._fields_:
-        if name == "stream":
+        if name in _POINTERS:
             continue
         setattr(q, name, typ(p.get(name, 0)).value)
     q.stream = stream
+    if allocator is not None:
+        q.dev_alloc = C.cast(allocator[0], C.c_void_p)
+        q.dev_free = C.cast(allocator[1], C.c_void_p)
     return q
+
+
+def torch_allocator():
+    """Callbacks that take device memory from PyTorch's caching allocator on
+    the current device and stream (keep the returned pair alive while the
+    handle that uses it exists)."""
+    import torch
+
+    def alloc(nbytes, ctx):
+        try:
+            return int(torch.cuda.caching_allocator_alloc(int(nbytes)))
+        except Exception:
+            return None
+
+    def free(ptr, ctx):
+        torch.cuda.caching_allocator_delete(int(ptr))
+
+    return ALLOC_FN(alloc), FREE_FN(free)
 
 
 def current_torch_stream():
@@ -208,23 +252,55 @@ def current_torch_stream():
 class SphMesh:
     """One relaxation job on the GPU (libsphmesh.so handle)."""
 
-    def __init__(self, wl, params=None, xyz=None, feature=None, stream=None, **over):
+    def __init__(self, wl, params=None, xyz=None, feature=None, stream=None, allocator=None,
+                 **over):
         L = lib()
         p = dict(wl.params if params is None else params)
         p.update(over)
         self.dim = wl.dim
         self._geom = make_geometry(wl.dim, wl.lo, wl.hi, wl.holes, wl.domain, wl.level)
         self._sizing = make_sizing(wl.sizing)
-        self._params = make_params(p, stream)
+        self._alloc = allocator
+        self._params = make_params(p, stream, allocator)
         xyz = np.ascontiguousarray(wl.xyz if xyz is None else xyz, np.float64)
         feature = np.ascontiguousarray(wl.feature if feature is None else feature, np.int32)
         self.n = int(xyz.shape[0])
         h = C.c_void_p()
-        _check("sph_mesh_create", L.sph_mesh_create(C.byref(self._geom), C.byref(self._sizing),
-                                                    C.byref(self._params), self.n,
-                                                    xyz.ctypes.data, feature.ctypes.data,
-                                                    C.byref(h)))
+        _check("sph_mesh_create_with_particles", L.sph_mesh_create_with_particles(
+            C.byref(self._geom), C.byref(self._sizing), C.byref(self._params), self.n,
+            xyz.ctypes.data, feature.ctypes.data, C.byref(h)))
         self.h = h
+
+    @classmethod
+    def from_problem(cls, dim, lo, hi, holes, sizing, params, domain=0, stream=None,
+                     allocator=None):
+        """sph_mesh_create: the particles are placed by the library from the
+        problem statement (params["n_particles"], "seed", "init",
+        "mass_res")."""
+        L = lib()
+        self = cls.__new__(cls)
+        self.dim = dim
+        self._geom = make_geometry(dim, lo, hi, holes, domain, None)
+        self._sizing = make_sizing(sizing)
+        self._alloc = allocator
+        self._params = make_params(params, stream, allocator)
+        h = C.c_void_p()
+        _check("sph_mesh_create", L.sph_mesh_create(C.byref(self._geom), C.byref(self._sizing),
+                                                    C.byref(self._params), C.byref(h)))
+        self.h = h
+        info = self.setup_info()
+        self.n = int(sum(info["counts"]))
+        return self
+
+    def setup_info(self):
+        L = lib()
+        s = C.c_double()
+        nf = C.c_int32()
+        _check("sph_mesh_setup_info", L.sph_mesh_setup_info(self.h, C.byref(s), None, 0, C.byref(nf)))
+        counts = np.zeros(max(nf.value, 1), np.int64)
+        _check("sph_mesh_setup_info", L.sph_mesh_setup_info(self.h, C.byref(s), counts.ctypes.data,
+                                                            counts.size, C.byref(nf)))
+        return dict(h_scale=s.value, counts=counts[:nf.value].tolist())
 
     def close(self):
         if getattr(self, "h", None):
@@ -357,14 +433,43 @@ class JobSpec:
 
 
 def batch_params(dim, precision=SPH_FP64, max_particles=0, max_cells=1, max_jobs=1,
-                 max_neighbors=0, use_graph=1, debug_fields=0, stream=None, scan_tile=0):
+                 max_neighbors=0, use_graph=1, debug_fields=0, stream=None, scan_tile=0,
+                 allocator=None):
     bp = BatchParams()
     bp.dim, bp.precision = dim, precision
     bp.max_particles, bp.max_cells, bp.max_jobs = max_particles, max_cells, max_jobs
     bp.max_neighbors, bp.use_graph, bp.debug_fields = max_neighbors, use_graph, debug_fields
     bp.scan_tile = scan_tile
     bp.stream = stream
+    if allocator is not None:
+        bp.dev_alloc = C.cast(allocator[0], C.c_void_p)
+        bp.dev_free = C.cast(allocator[1], C.c_void_p)
     return bp
+
+
+def job_setup(dim, lo, hi, holes, sizing, params, domain=0, particles=True):
+    """sph_job_setup (host only): the split of params["n_particles"] over the
+    features, the scale of h and, if particles, the initial particles."""
+    L = lib()
+    g = make_geometry(dim, lo, hi, holes, domain, None)
+    sz = make_sizing(sizing)
+    p = make_params(params)
+    s, h0, gr = C.c_double(), C.c_double(), C.c_double()
+    nf, n = C.c_int32(), C.c_int64()
+    counts = np.zeros(256, np.int64)
+    _check("sph_job_setup", L.sph_job_setup(C.byref(g), C.byref(sz), C.byref(p), C.byref(s),
+                                            C.byref(h0), C.byref(gr), counts.ctypes.data,
+                                            counts.size, C.byref(nf), None, None, 0, C.byref(n)))
+    out = dict(h_scale=s.value, h0=h0.value, grad=gr.value, counts=counts[:nf.value].tolist(),
+               n=int(n.value))
+    if particles:
+        xyz = np.zeros((n.value, 3))
+        feat = np.zeros(n.value, np.int32)
+        _check("sph_job_setup", L.sph_job_setup(C.byref(g), C.byref(sz), C.byref(p), None, None,
+                                                None, None, 0, None, xyz.ctypes.data,
+                                                feat.ctypes.data, n.value, None))
+        out.update(xyz=xyz, feature=feat)
+    return out
 
 
 def batch_footprint(**kw):
@@ -378,9 +483,10 @@ class SphBatch:
     sequence per step (libsphmesh.so batch handle)."""
 
     def __init__(self, dim, precision=SPH_FP64, max_particles=0, max_cells=1, max_jobs=1,
-                 max_neighbors=0, use_graph=1, stream=None, scan_tile=0):
+                 max_neighbors=0, use_graph=1, stream=None, scan_tile=0, allocator=None):
+        self._alloc = allocator
         self.bp = batch_params(dim, precision, max_particles, max_cells, max_jobs,
-                               max_neighbors, use_graph, 0, stream, scan_tile)
+                               max_neighbors, use_graph, 0, stream, scan_tile, allocator)
         self.max_jobs = max_jobs
         h = C.c_void_p()
         _check("sph_batch_create", lib().sph_batch_create(C.byref(self.bp), C.byref(h)))
@@ -472,7 +578,9 @@ def control_replay_noalloc(params, n, vbar, dt, phase, reset, e_sys, stream=None
 
 def exported_symbols():
     """Names the header declares (checked by the CPU test of the ABI)."""
-    return ["sph_mesh_create", "sph_mesh_step", "sph_mesh_positions", "sph_mesh_error",
+    return ["sph_mesh_create", "sph_mesh_create_with_particles", "sph_mesh_setup_info",
+            "sph_job_setup",
+            "sph_mesh_step", "sph_mesh_positions", "sph_mesh_error",
             "sph_mesh_destroy", "sph_mesh_last_error", "sph_mesh_set_state", "sph_mesh_velocities",
             "sph_mesh_neighbors", "sph_mesh_neighbors_of", "sph_mesh_field", "sph_mesh_group_state", "sph_mesh_counters",
             "sph_mesh_control_replay", "sph_mesh_control_replay_noalloc", "sph_mesh_profile", "sph_mesh_kernel_stats",

@@ -226,12 +226,35 @@ BNorm boundary_normal(int D, const HFeat &A, const HFeat &B) {
   return N;
 }
 
+// Device memory: from the caller's allocator (for instance PyTorch's caching
+// allocator) when the parameters give one, from hipMalloc / hipFree otherwise.
+// Memory is only released after the stream that used it has drained.
+struct DevAlloc {
+  void *(*alloc)(size_t, void *) = nullptr;
+  void (*release)(void *, void *) = nullptr;
+  void *ctx = nullptr;
+  hipError_t get(void **p, size_t b) const {
+    if (alloc) {
+      *p = alloc(b, ctx);
+      return *p ? hipSuccess : hipErrorOutOfMemory;
+    }
+    return hipMalloc(p, b);
+  }
+  void put(void *p) const {
+    if (!p) return;
+    if (release)
+      release(p, ctx);
+    else
+      (void)hipFree(p);
+  }
+};
+
 template <typename T>
-T *dalloc(size_t count, std::vector<void *> &owned, size_t &bytes) {
+T *dalloc(const DevAlloc &mem, size_t count, std::vector<void *> &owned, size_t &bytes) {
   void *p = nullptr;
   size_t b = std::max<size_t>(count, 1) * sizeof(T);
   b = (b + 255) & ~size_t(255);
-  if (hipMalloc(&p, b) != hipSuccess) return nullptr;
+  if (mem.get(&p, b) != hipSuccess) return nullptr;
   owned.push_back(p);
   bytes += b;
   return (T *)p;
@@ -487,6 +510,7 @@ struct sph_batch {
   bool own_stream = false;
   std::vector<void *> owned;
   size_t bytes = 0;
+  DevAlloc mem;
   Parts P[2]{};
   int cur = 0;
   uint32_t *cell = nullptr, *rank = nullptr, *psrc = nullptr, *pkey = nullptr;
@@ -529,12 +553,12 @@ struct sph_batch {
     }
     for (auto e : ev_pool) (void)hipEventDestroy(e);
     for (HostJob &J : jobs) {
-      if (J.d_grid) (void)hipFree(J.d_grid);
-      if (J.d_phi) (void)hipFree(J.d_phi);
-      if (J.d_cpts) (void)hipFree(J.d_cpts);
-      if (J.d_coff) (void)hipFree(J.d_coff);
+      mem.put(J.d_grid);
+      mem.put(J.d_phi);
+      mem.put(J.d_cpts);
+      mem.put(J.d_coff);
     }
-    for (void *p : owned) (void)hipFree(p);
+    for (void *p : owned) mem.put(p);
     if (own_stream && stream) (void)hipStreamDestroy(stream);
   }
 
@@ -749,6 +773,8 @@ struct sph_batch {
 
   bool valid_job(int j) const { return j >= 0 && j < njobs && jobs[j].live; }
 };
+
+#include "sph_setup.h"
 
 // ---------------------------------------------------------------------------
 // job description -> host job record
@@ -966,7 +992,12 @@ extern "C" sph_status sph_batch_create(const sph_batch_params *bp, sph_batch **o
   if (bp->max_neighbors > 4096) return fail(SPH_ERR_INVALID_ARG, "max_neighbors above 4096");
   if (bp->scan_tile != 0 && bp->scan_tile != 2 && bp->scan_tile != 4 && bp->scan_tile != 8)
     return fail(SPH_ERR_INVALID_ARG, "scan_tile must be 0, 2, 4 or 8");
+  if ((bp->dev_alloc == nullptr) != (bp->dev_free == nullptr))
+    return fail(SPH_ERR_INVALID_ARG, "dev_alloc and dev_free must be given together");
   auto *B = new sph_batch();
+  B->mem.alloc = bp->dev_alloc;
+  B->mem.release = bp->dev_free;
+  B->mem.ctx = bp->alloc_ctx;
   B->D = bp->dim;
   B->prec = bp->precision;
   // capacity in whole list blocks
@@ -994,45 +1025,45 @@ extern "C" sph_status sph_batch_create(const sph_batch_params *bp, sph_batch **o
   const size_t slots = (size_t)B->jcap * MAXF;
   bool ok = true;
   for (int b = 0; b < 2; ++b) {   // records padded past capacity: unclamped batched loads
-    B->P[b].xh = dalloc<double4>(NPAD, ow, by);
-    B->P[b].v = dalloc<double4>(NPAD, ow, by);
-    B->P[b].f = dalloc<uint16_t>(NPAD, ow, by);
-    B->P[b].oid = dalloc<uint32_t>(NPAD, ow, by);
-    B->P[b].xf = dalloc<float4>(NPAD, ow, by);
+    B->P[b].xh = dalloc<double4>(B->mem, NPAD, ow, by);
+    B->P[b].v = dalloc<double4>(B->mem, NPAD, ow, by);
+    B->P[b].f = dalloc<uint16_t>(B->mem, NPAD, ow, by);
+    B->P[b].oid = dalloc<uint32_t>(B->mem, NPAD, ow, by);
+    B->P[b].xf = dalloc<float4>(B->mem, NPAD, ow, by);
     ok = ok && B->P[b].xh && B->P[b].v && B->P[b].f && B->P[b].oid && B->P[b].xf;
   }
-  B->cell = dalloc<uint32_t>(N, ow, by);
-  B->rank = dalloc<uint32_t>(N, ow, by);
-  B->psrc = dalloc<uint32_t>(N, ow, by);
-  B->pkey = dalloc<uint32_t>(N, ow, by);
-  B->cnt = dalloc<uint32_t>(C, ow, by);
-  B->cstart = dalloc<uint32_t>(C + 1, ow, by);
-  B->scan_status = dalloc<unsigned long long>(tiles, ow, by);
-  B->ticket = dalloc<uint32_t>(1, ow, by);
-  B->nbr = dalloc<uint32_t>(N * (size_t)B->cap, ow, by);
-  B->nnb = dalloc<uint32_t>(N, ow, by);
+  B->cell = dalloc<uint32_t>(B->mem, N, ow, by);
+  B->rank = dalloc<uint32_t>(B->mem, N, ow, by);
+  B->psrc = dalloc<uint32_t>(B->mem, N, ow, by);
+  B->pkey = dalloc<uint32_t>(B->mem, N, ow, by);
+  B->cnt = dalloc<uint32_t>(B->mem, C, ow, by);
+  B->cstart = dalloc<uint32_t>(B->mem, C + 1, ow, by);
+  B->scan_status = dalloc<unsigned long long>(B->mem, tiles, ow, by);
+  B->ticket = dalloc<uint32_t>(B->mem, 1, ow, by);
+  B->nbr = dalloc<uint32_t>(B->mem, N * (size_t)B->cap, ow, by);
+  B->nnb = dalloc<uint32_t>(B->mem, N, ow, by);
   const size_t r4 = B->prec == SPH_FP64 ? sizeof(double4) : sizeof(float4);
-  B->ap = dalloc<char>(N * r4, ow, by);
-  B->acc = dalloc<char>(N * r4, ow, by);
-  if (B->D == 3) B->mid = dalloc<char>(N * r4, ow, by);   // mid-point records (3D sweep B)
-  B->enrm = dalloc<double4>(N, ow, by);
+  B->ap = dalloc<char>(B->mem, N * r4, ow, by);
+  B->acc = dalloc<char>(B->mem, N * r4, ow, by);
+  if (B->D == 3) B->mid = dalloc<char>(B->mem, N * r4, ow, by);   // mid-point records (3D sweep B)
+  B->enrm = dalloc<double4>(B->mem, N, ow, by);
   if (B->debug) {
-    B->dbg_gam = dalloc<double>(N, ow, by);
-    B->dbg_vt = dalloc<double>(N, ow, by);
-    B->dbg_vm = dalloc<double4>(N, ow, by);
+    B->dbg_gam = dalloc<double>(B->mem, N, ow, by);
+    B->dbg_vt = dalloc<double>(B->mem, N, ow, by);
+    B->dbg_vm = dalloc<double4>(B->mem, N, ow, by);
     ok = ok && B->dbg_gam && B->dbg_vt && B->dbg_vm;
   }
-  B->d_jobs = dalloc<JobDev>(B->jcap, ow, by);
-  B->d_feat = dalloc<Feat>(slots, ow, by);
-  B->d_bmask = dalloc<unsigned long long>(slots, ow, by);
-  B->d_bn = dalloc<BNorm>(slots * MAXF, ow, by);
-  B->d_grp = dalloc<Group>(slots, ow, by);
-  B->d_st = dalloc<JobStat>(B->jcap, ow, by);
-  B->d_gflags = dalloc<unsigned int>(4, ow, by);
-  B->smin = dalloc<unsigned long long>(slots * NSTRIPE, ow, by);
-  B->ssum = dalloc<unsigned long long>(slots * NSTRIPE, ow, by);
-  B->scnt = dalloc<unsigned long long>((size_t)B->jcap * NSTRIPE, ow, by);
-  B->sesc = dalloc<unsigned long long>((size_t)B->jcap * NSTRIPE, ow, by);
+  B->d_jobs = dalloc<JobDev>(B->mem, B->jcap, ow, by);
+  B->d_feat = dalloc<Feat>(B->mem, slots, ow, by);
+  B->d_bmask = dalloc<unsigned long long>(B->mem, slots, ow, by);
+  B->d_bn = dalloc<BNorm>(B->mem, slots * MAXF, ow, by);
+  B->d_grp = dalloc<Group>(B->mem, slots, ow, by);
+  B->d_st = dalloc<JobStat>(B->mem, B->jcap, ow, by);
+  B->d_gflags = dalloc<unsigned int>(B->mem, 4, ow, by);
+  B->smin = dalloc<unsigned long long>(B->mem, slots * NSTRIPE, ow, by);
+  B->ssum = dalloc<unsigned long long>(B->mem, slots * NSTRIPE, ow, by);
+  B->scnt = dalloc<unsigned long long>(B->mem, (size_t)B->jcap * NSTRIPE, ow, by);
+  B->sesc = dalloc<unsigned long long>(B->mem, (size_t)B->jcap * NSTRIPE, ow, by);
   ok = ok && B->cell && B->rank && B->psrc && B->pkey && B->cnt && B->cstart && B->scan_status &&
        B->ticket && B->nbr && B->nnb && B->ap && B->acc && (B->mid || B->D == 2) && B->enrm && B->d_jobs && B->d_feat && B->d_bmask &&
        B->d_bn && B->d_grp && B->d_st && B->d_gflags && B->smin && B->ssum && B->scnt && B->sesc;
@@ -1091,24 +1122,24 @@ extern "C" sph_status sph_batch_add(sph_batch *b, const sph_geometry *g, const s
   HIPCHK(hipStreamSynchronize(b->stream));
   if (s->kind == 4) {   // the job's own device copy of the sizing grid
     const size_t bytes = sizeof(double) * (size_t)s->grid_n[0] * s->grid_n[1] * s->grid_n[2];
-    if (hipMalloc((void **)&J.d_grid, bytes) != hipSuccess)
+    if (b->mem.get((void **)&J.d_grid, bytes) != hipSuccess)
       return fail(SPH_ERR_OUT_OF_MEMORY, "no device memory for the sizing grid");
     hipError_t ge = hipMemcpyAsync(J.d_grid, s->grid, bytes, hipMemcpyHostToDevice, b->stream);
     if (ge == hipSuccess) ge = hipStreamSynchronize(b->stream);
     if (ge != hipSuccess) {
-      (void)hipFree(J.d_grid);
+      b->mem.put(J.d_grid);
       return fail(SPH_ERR_DEVICE, "sizing grid upload failed: %s", hipGetErrorString(ge));
     }
     J.dev.g.grid = J.d_grid;
   }
   if (g->domain == SPH_DOMAIN_LEVEL_SET) {   // the job's own device copy of phi
     const size_t bytes = sizeof(double) * (size_t)g->phi_n[0] * g->phi_n[1] * g->phi_n[2];
-    hipError_t pe = hipMalloc((void **)&J.d_phi, bytes);
+    hipError_t pe = b->mem.get((void **)&J.d_phi, bytes);
     if (pe == hipSuccess) pe = hipMemcpyAsync(J.d_phi, g->phi, bytes, hipMemcpyHostToDevice, b->stream);
     if (pe == hipSuccess) pe = hipStreamSynchronize(b->stream);
     if (pe != hipSuccess) {
-      if (J.d_phi) (void)hipFree(J.d_phi);
-      if (J.d_grid) (void)hipFree(J.d_grid);
+      b->mem.put(J.d_phi);
+      b->mem.put(J.d_grid);
       return fail(SPH_ERR_DEVICE, "level-set upload failed: %s", hipGetErrorString(pe));
     }
     J.dev.g.phi = J.d_phi;
@@ -1116,14 +1147,14 @@ extern "C" sph_status sph_batch_add(sph_batch *b, const sph_geometry *g, const s
   if (g->domain == SPH_DOMAIN_LEVEL_SET && g->n_curves > 0) {   // imported curves
     const size_t np = (size_t)g->curve_off[g->n_curves];
     const size_t pb = sizeof(double) * 3 * np, ob = sizeof(int32_t) * (size_t)(g->n_curves + 1);
-    hipError_t ce = hipMalloc((void **)&J.d_cpts, pb);
-    if (ce == hipSuccess) ce = hipMalloc((void **)&J.d_coff, ob);
+    hipError_t ce = b->mem.get((void **)&J.d_cpts, pb);
+    if (ce == hipSuccess) ce = b->mem.get((void **)&J.d_coff, ob);
     if (ce == hipSuccess) ce = hipMemcpyAsync(J.d_cpts, g->curve_pts, pb, hipMemcpyHostToDevice, b->stream);
     if (ce == hipSuccess) ce = hipMemcpyAsync(J.d_coff, g->curve_off, ob, hipMemcpyHostToDevice, b->stream);
     if (ce == hipSuccess) ce = hipStreamSynchronize(b->stream);
     if (ce != hipSuccess) {
       for (void *buf : {(void *)J.d_cpts, (void *)J.d_coff, (void *)J.d_phi, (void *)J.d_grid})
-        if (buf) (void)hipFree(buf);
+        b->mem.put(buf);
       return fail(SPH_ERR_DEVICE, "curve upload failed: %s", hipGetErrorString(ce));
     }
     J.dev.g.cpts = J.d_cpts;
@@ -1225,7 +1256,7 @@ extern "C" sph_status sph_batch_add(sph_batch *b, const sph_geometry *g, const s
   else (void)hipStreamSynchronize(q);
   if (e != hipSuccess) {
     for (void *buf : {(void *)J.d_cpts, (void *)J.d_coff, (void *)J.d_phi, (void *)J.d_grid})
-      if (buf) (void)hipFree(buf);
+      b->mem.put(buf);
     return fail(SPH_ERR_DEVICE, "job upload failed: %s", hipGetErrorString(e));
   }
   J.live = true;
@@ -1284,22 +1315,15 @@ extern "C" sph_status sph_batch_remove(sph_batch *b, int32_t job) {
   HIPCHK(hipMemcpyAsync(b->d_jobs + job, &R.dev, sizeof(JobDev), hipMemcpyHostToDevice, b->stream));
   HIPCHK(hipMemsetAsync(b->cnt, 0, 4 * (size_t)std::max(b->ncell, 1u), b->stream));
   HIPCHK(hipStreamSynchronize(b->stream));
-  if (R.d_grid) {   // no kernel that reads it is queued any more
-    (void)hipFree(R.d_grid);
-    R.d_grid = nullptr;
-  }
-  if (R.d_phi) {
-    (void)hipFree(R.d_phi);
-    R.d_phi = nullptr;
-  }
-  if (R.d_cpts) {
-    (void)hipFree(R.d_cpts);
-    R.d_cpts = nullptr;
-  }
-  if (R.d_coff) {
-    (void)hipFree(R.d_coff);
-    R.d_coff = nullptr;
-  }
+  // no kernel that reads them is queued any more
+  b->mem.put(R.d_grid);
+  b->mem.put(R.d_phi);
+  b->mem.put(R.d_cpts);
+  b->mem.put(R.d_coff);
+  R.d_grid = nullptr;
+  R.d_phi = nullptr;
+  R.d_cpts = nullptr;
+  R.d_coff = nullptr;
   b->cur = 1 - b->cur;
   b->n = (int)off;
   b->ncell = cb;
@@ -1414,17 +1438,25 @@ extern "C" sph_status sph_batch_counters(sph_batch *b, int32_t job, double *out)
 struct sph_mesh {
   sph_batch *b = nullptr;
   int job = 0;
+  // set-up from the problem statement: the factor h was scaled by, and the
+  // particles placed per feature
+  double h_scale = 1.0;
+  std::vector<int64_t> counts;
   ~sph_mesh() { delete b; }
 };
 
-extern "C" sph_status sph_mesh_create(const sph_geometry *g, const sph_sizing *s,
-                                      const sph_params *p, int64_t n, const double *xyz,
-                                      const int32_t *feature, sph_mesh **out) {
+extern "C" sph_status sph_mesh_create_with_particles(const sph_geometry *g, const sph_sizing *s,
+                                                     const sph_params *p, int64_t n,
+                                                     const double *xyz, const int32_t *feature,
+                                                     sph_mesh **out) {
   if (!out) return fail(SPH_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
   if (sph_status st = validate(g, s, p)) return st;
   if (sph_status st = check_particles(g, n, xyz, feature)) return st;
   sph_batch_params bp{};
+  bp.dev_alloc = p->dev_alloc;
+  bp.dev_free = p->dev_free;
+  bp.alloc_ctx = p->alloc_ctx;
   bp.dim = g->dim;
   bp.precision = p->precision;
   bp.max_particles = std::max<int64_t>(n, 1);
@@ -1445,6 +1477,115 @@ extern "C" sph_status sph_mesh_create(const sph_geometry *g, const sph_sizing *s
     return st;
   }
   *out = M;
+  return SPH_OK;
+}
+
+// Algorithm 1's set-up from the problem statement: feature masses and the
+// particle split (sec. 3.2), h scaled to the budget (reading R25), and, when
+// want_particles, the initial particles drawn from a Mersenne Twister
+// (sec. 3.6).  Host work only.
+static sph_status problem_setup(const sph_geometry *g, const sph_sizing *s, const sph_params *p,
+                                bool want_particles, setup::Plan &P, sph_sizing &s2,
+                                std::vector<double> &xyz, std::vector<int32_t> &feat) {
+  if (sph_status st = validate(g, s, p)) return st;
+  if (g->domain != SPH_DOMAIN_BOX && g->domain != SPH_DOMAIN_BALL)
+    return fail(SPH_ERR_UNSUPPORTED, "set-up from the problem statement takes a box or ball "
+                                     "domain; give a level-set domain's particles to "
+                                     "sph_mesh_create_with_particles");
+  if (s->kind == SPH_H_GRID)
+    return fail(SPH_ERR_UNSUPPORTED, "set-up from the problem statement takes an analytic "
+                                     "sizing; give gridded sizing's particles to "
+                                     "sph_mesh_create_with_particles");
+  if (p->init != SPH_INIT_DENSITY && p->init != SPH_INIT_UNIFORM)
+    return fail(SPH_ERR_INVALID_ARG, "init must be SPH_INIT_DENSITY or SPH_INIT_UNIFORM");
+  if (p->n_particles < 0 || p->n_particles > 0x7ffffff0ll)
+    return fail(SPH_ERR_INVALID_ARG, "n_particles out of range");
+  const int D = g->dim;
+  const int res = p->mass_res > 0 ? p->mass_res : (D == 2 ? 1024 : 128);
+  if (res > (D == 2 ? 16384 : 1024)) return fail(SPH_ERR_INVALID_ARG, "mass_res too large");
+  HostJob J0;
+  fill_job(J0, g, s, p, 0, 0);
+  const std::vector<double> M = setup::masses(J0.dev.g, J0.feats, res);
+  P = setup::plan(J0.feats, M, p->n_particles);
+  int64_t total = 0;
+  for (size_t f = 0; f < P.count.size(); ++f) {
+    if (P.count[f] < 0)
+      return fail(SPH_ERR_INVALID_ARG, "feature %zu gets a negative particle count", f);
+    total += P.count[f];
+  }
+  if (total > 0x7ffffff0ll) return fail(SPH_ERR_INVALID_ARG, "too many particles");
+  s2 = *s;   // h scaled by P.scale
+  s2.h0 = s->h0 * P.scale;
+  if (s->kind == SPH_H_LINEAR_FROM_POINT || s->kind == SPH_H_SHELL) s2.grad = s->grad * P.scale;
+  if (!want_particles) return SPH_OK;
+  HostJob J1;
+  fill_job(J1, g, &s2, p, 0, 0);
+  double hmin = 0.0, hmax = 0.0, lip = 0.0;
+  sizing_bounds(g, &s2, hmin, hmax, lip);
+  return setup::sample(J1.dev.g, J1.feats, P, p->init, lip, p->seed, xyz, feat);
+}
+
+extern "C" sph_status sph_job_setup(const sph_geometry *g, const sph_sizing *s,
+                                    const sph_params *p, double *h_scale, double *h0_scaled,
+                                    double *grad_scaled, int64_t *counts, int32_t counts_cap,
+                                    int32_t *n_features, double *xyz, int32_t *feature,
+                                    int64_t capacity, int64_t *n_out) {
+  setup::Plan P;
+  sph_sizing s2{};
+  std::vector<double> x;
+  std::vector<int32_t> f;
+  if (sph_status st = problem_setup(g, s, p, xyz != nullptr || feature != nullptr, P, s2, x, f))
+    return st;
+  const int32_t nf = (int32_t)P.count.size();
+  int64_t total = 0;
+  for (int64_t c : P.count) total += c;
+  if (h_scale) *h_scale = P.scale;
+  if (h0_scaled) *h0_scaled = s2.h0;
+  if (grad_scaled) *grad_scaled = s2.grad;
+  if (n_features) *n_features = nf;
+  if (n_out) *n_out = total;
+  if (counts) {
+    if (counts_cap < nf) return fail(SPH_ERR_INVALID_ARG, "capacity %d < %d features", counts_cap, nf);
+    for (int32_t q = 0; q < nf; ++q) counts[q] = P.count[q];
+  }
+  if (xyz || feature) {
+    if (capacity < (int64_t)f.size())
+      return fail(SPH_ERR_INVALID_ARG, "capacity %lld < %zu particles", (long long)capacity, f.size());
+    if (xyz) std::memcpy(xyz, x.data(), sizeof(double) * x.size());
+    if (feature) std::memcpy(feature, f.data(), sizeof(int32_t) * f.size());
+  }
+  return SPH_OK;
+}
+
+extern "C" sph_status sph_mesh_create(const sph_geometry *g, const sph_sizing *s,
+                                      const sph_params *p, sph_mesh **out) {
+  if (!out) return fail(SPH_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  setup::Plan P;
+  sph_sizing s2{};
+  std::vector<double> xyz;
+  std::vector<int32_t> feat;
+  if (sph_status st = problem_setup(g, s, p, true, P, s2, xyz, feat)) return st;
+  sph_mesh *m = nullptr;
+  if (sph_status st = sph_mesh_create_with_particles(g, &s2, p, (int64_t)feat.size(), xyz.data(),
+                                                     feat.data(), &m))
+    return st;
+  m->h_scale = P.scale;
+  m->counts = P.count;
+  *out = m;
+  return SPH_OK;
+}
+
+extern "C" sph_status sph_mesh_setup_info(sph_mesh *m, double *h_scale, int64_t *counts,
+                                          int32_t cap, int32_t *n_features) {
+  if (!m) return fail(SPH_ERR_INVALID_ARG, "null handle");
+  if (h_scale) *h_scale = m->h_scale;
+  const int32_t nf = (int32_t)m->counts.size();
+  if (n_features) *n_features = nf;
+  if (counts) {
+    if (cap < nf) return fail(SPH_ERR_INVALID_ARG, "capacity %d < %d features", cap, nf);
+    for (int32_t f = 0; f < nf; ++f) counts[f] = m->counts[f];
+  }
   return SPH_OK;
 }
 
