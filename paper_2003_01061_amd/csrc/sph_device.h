@@ -78,7 +78,7 @@ struct Geom {
 
 // imported curve c (a polyline, domain on its left): the segment whose
 // closest point to x is nearest (the first on ties), that point in q
-__device__ __forceinline__ int poly_closest(const Geom &g, int c, const double *x, double *q) {
+__host__ __device__ __forceinline__ int poly_closest(const Geom &g, int c, const double *x, double *q) {
   // start from the first point, so that a segment is returned even when no
   // distance compares (a non-finite x)
   int best = g.coff[c];
@@ -105,7 +105,7 @@ __device__ __forceinline__ int poly_closest(const Geom &g, int c, const double *
 }
 
 // unit tangent of segment k of the imported curves
-__device__ __forceinline__ void seg_tangent(const Geom &g, int k, double *t) {
+__host__ __device__ __forceinline__ void seg_tangent(const Geom &g, int k, double *t) {
   const double *p0 = g.cpts + 3 * k, *p1 = g.cpts + 3 * (k + 1);
   const double e0 = p1[0] - p0[0], e1 = p1[1] - p0[1];
   const double l = __builtin_sqrt(e0 * e0 + e1 * e1);
@@ -160,7 +160,7 @@ __host__ __device__ __forceinline__ double ls_phi(const Geom &g, const double *x
 
 // unit normal of the level set towards increasing phi (0 where grad vanishes)
 template <int D>
-__device__ __forceinline__ void ls_unit(const Geom &g, const double *x, double *m) {
+__host__ __device__ __forceinline__ void ls_unit(const Geom &g, const double *x, double *m) {
   double gr[3];
   (void)ls_phi<D>(g, x, gr);
   double s = 0.0;
@@ -372,7 +372,7 @@ __host__ __device__ __forceinline__ double ell_dist(const Geom &g, int q, const 
 
 // closest surface point to a point near the surface: 8 Newton steps from t = 0
 template <int D>
-__device__ __forceinline__ void ell_project(const Geom &g, int q, double *x) {
+__host__ __device__ __forceinline__ void ell_project(const Geom &g, int q, double *x) {
   double y[3] = {0.0, 0.0, 0.0}, z[3] = {0.0, 0.0, 0.0};
   ell_local<D>(g, q, x, y);
   double t = 0.0;
@@ -394,7 +394,7 @@ __device__ __forceinline__ void ell_project(const Geom &g, int q, double *x) {
 
 // unit normal of the hole's level set at x, pointing out of the hole
 template <int D>
-__device__ __forceinline__ void ell_normal(const Geom &g, int q, const double *x, double *n) {
+__host__ __device__ __forceinline__ void ell_normal(const Geom &g, int q, const double *x, double *n) {
   double y[3] = {0.0, 0.0, 0.0};
   ell_local<D>(g, q, x, y);
   double gy[3] = {0.0, 0.0, 0.0};
@@ -516,7 +516,7 @@ __host__ __device__ __forceinline__ double h_target(const Geom &g, const double 
 // products), so the predicate holds exactly when s is below either.  The
 // squared distance is summed over axes in order, without contraction.
 template <int D>
-__device__ __forceinline__ bool within_a4(const double4 &a, double A4, double c2,
+__host__ __device__ __forceinline__ bool within_a4(const double4 &a, double A4, double c2,
                                           const double4 &b) {
 #pragma clang fp contract(off)
   double d = a.x - b.x;
@@ -552,13 +552,13 @@ __host__ __device__ __forceinline__ bool rows_tiled(int D, const int *nc) {
   return D == 3 && nc[1] >= 64 && nc[2] >= 64;
 }
 template <int D>
-__device__ __forceinline__ uint32_t cell_row(const Grid &G, int l, uint32_t cy, uint32_t cz) {
+__host__ __device__ __forceinline__ uint32_t cell_row(const Grid &G, int l, uint32_t cy, uint32_t cz) {
   if (!rows_tiled(D, G.nc[l])) return cz * (uint32_t)G.nc[l][1] + cy;
   const uint32_t nyt = ((uint32_t)G.nc[l][1] + 7u) >> 3;
   return (((cz >> 3) * nyt + (cy >> 3)) << 6) + ((cz & 7u) << 3) + (cy & 7u);
 }
 
-__device__ __forceinline__ int cell_coord(const Grid &G, int l, int a, double p) {
+__host__ __device__ __forceinline__ int cell_coord(const Grid &G, int l, int a, double p) {
   double t = __builtin_floor((p - G.lo[a]) * G.inv_c[l][a]);
   t = t >= 0.0 ? t : 0.0;   // also maps NaN to cell 0
   double top = (double)(G.nc[l][a] - 1);
@@ -567,7 +567,7 @@ __device__ __forceinline__ int cell_coord(const Grid &G, int l, int a, double p)
 }
 
 // cell level of smoothing length h (thresholds ascending; NaN -> level 0)
-__device__ __forceinline__ int h_level(const Grid &G, double h) {
+__host__ __device__ __forceinline__ int h_level(const Grid &G, double h) {
   int l = 0;
   for (int q = 1; q < G.nlev; ++q) l += h >= G.hthr[q] ? 1 : 0;
   return l;
@@ -582,31 +582,31 @@ __device__ __forceinline__ int h_level(const Grid &G, double h) {
 // argument.
 // ---------------------------------------------------------------------------
 template <int K, typename R>
-__device__ __forceinline__ constexpr R kalphaK() {
+__host__ __device__ __forceinline__ constexpr R kalphaK() {
   return K == 1 ? R(0.625) : (K == 2 ? R(0.55704230082163367519) : R(0.41778172561622525639));
 }
 template <int K, typename R>
-__device__ __forceinline__ R wshapeK(R q) {   // w(q), caller guarantees q < 2 or clamps t
+__host__ __device__ __forceinline__ R wshapeK(R q) {   // w(q), caller guarantees q < 2 or clamps t
   R t = R(1) - R(0.5) * q;
   t = t > R(0) ? t : R(0);
   const R t2 = t * t;
   return K == 1 ? t2 * t * (R(1) + R(1.5) * q) : t2 * t2 * (R(1) + R(2) * q);
 }
 template <int K, typename R>
-__device__ __forceinline__ R dwqK(R q) {      // w'(q)/q
+__host__ __device__ __forceinline__ R dwqK(R q) {      // w'(q)/q
   R t = R(1) - R(0.5) * q;
   t = t > R(0) ? t : R(0);
   return K == 1 ? R(-3) * t * t : R(-5) * t * t * t;
 }
 template <int K, typename R>
-__device__ __forceinline__ R powK(R h) {
+__host__ __device__ __forceinline__ R powK(R h) {
   return K == 1 ? h : (K == 2 ? h * h : h * h * h);
 }
 
 // fast reciprocal / square root per precision
-__device__ __forceinline__ double rcp_(double x) { return 1.0 / x; }
+__host__ __device__ __forceinline__ double rcp_(double x) { return 1.0 / x; }
 __device__ __forceinline__ float rcp_(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ __forceinline__ double sqrt_(double x) { return __builtin_sqrt(x); }
+__host__ __device__ __forceinline__ double sqrt_(double x) { return __builtin_sqrt(x); }
 __device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
 
 // Accumulation of pair terms.  Sum<false>: the terms (FP64, or FP32 in the
@@ -619,10 +619,10 @@ struct Sum;
 template <>
 struct Sum<false> {
   double s;
-  __device__ __forceinline__ void init(double v) { s = v; }
+  __host__ __device__ __forceinline__ void init(double v) { s = v; }
   template <typename T>
-  __device__ __forceinline__ void add(T v) { s += (double)v; }
-  __device__ __forceinline__ double get() const { return s; }
+  __host__ __device__ __forceinline__ void add(T v) { s += (double)v; }
+  __host__ __device__ __forceinline__ double get() const { return s; }
 };
 template <>
 struct Sum<true> {
@@ -645,7 +645,7 @@ struct Sum<true> {
 // u <- T_i u: identity on the volume, drop the normal part on a surface, keep
 // the tangent part on a curve, zero on a singular point
 template <int D>
-__device__ __forceinline__ void tangent(const Geom &g, const Feat &F, const double *x, double *u) {
+__host__ __device__ __forceinline__ void tangent(const Geom &g, const Feat &F, const double *x, double *u) {
   switch (F.kind) {
     case K_VOL: return;
     case K_BOXSIDE: u[F.axis] = 0.0; return;
@@ -744,13 +744,13 @@ __device__ __forceinline__ void tangent(const Geom &g, const Feat &F, const doub
   }
 }
 
-__device__ __forceinline__ double clamp_(double v, double lo, double hi) {
+__host__ __device__ __forceinline__ double clamp_(double v, double lo, double hi) {
   return v < lo ? lo : (v > hi ? hi : v);
 }
 
 // closest point of feature F to x (in place)
 template <int D>
-__device__ __forceinline__ void project(const Geom &g, const Feat &F, double *x) {
+__host__ __device__ __forceinline__ void project(const Geom &g, const Feat &F, double *x) {
   switch (F.kind) {
     case K_BOXSIDE:
       for (int a = 0; a < D; ++a) x[a] = clamp_(x[a], g.lo[a], g.hi[a]);

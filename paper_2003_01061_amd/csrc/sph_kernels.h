@@ -388,7 +388,7 @@ __global__ __launch_bounds__(BLOCK) void k_rank_gather(Batch B, int n, const uin
 // Sum<CMP>: in FP64, or (CMP, R = float) in FP32 with Neumaier compensation.
 // ---------------------------------------------------------------------------
 template <int D, int K, typename R, bool CMP>
-__device__ __forceinline__ void sweep_a_sums(const Geom &g, const Parts &s,
+__host__ __device__ __forceinline__ void sweep_a_sums(const Geom &g, const Parts &s,
                                              const double4 *__restrict__ enrm,
                                              const BNorm *__restrict__ bnrow, int bw, double p0,
                                              double klen, double bscale,

@@ -68,7 +68,8 @@ CALIBRATED = dict(kernel_support=2.5, boundary_scale=2.0)
 
 
 def calibrated(**over):
-    """default_params with the mesh-quality calibration applied first."""
+    """The mesh-quality calibration plus over, as keyword overrides for a
+    workload builder (wk.square_hole(**wk.calibrated()))."""
     p = dict(CALIBRATED)
     p.update(over)
     return p
