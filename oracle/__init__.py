@@ -24,7 +24,8 @@ class Geometry(C.Structure):
                 ("phi_n", C.c_int32 * 3), ("phi_lo", C.c_double * 3), ("phi_hi", C.c_double * 3),
                 ("n_curves", C.c_int32), ("curve_off", C.POINTER(C.c_int32)),
                 ("curve_pts", C.POINTER(C.c_double)), ("curve_ends", C.POINTER(C.c_int32)),
-                ("n_corners", C.c_int32), ("corners", C.POINTER(C.c_double))]
+                ("n_corners", C.c_int32), ("corners", C.POINTER(C.c_double)),
+                ("n_patches", C.c_int32), ("curve_patches", C.POINTER(C.c_int32))]
 
 
 class Sizing(C.Structure):
@@ -81,6 +82,11 @@ def _load(path, openmp):
         L.sphref_n_features.argtypes = [C.POINTER(Geometry)]
         L.sphref_feature_type.argtypes = [C.POINTER(Geometry), C.c_int32]
         L.sphref_boundary_normal.argtypes = [C.POINTER(Geometry), C.c_int32, C.c_int32, _dp, _dp]
+        L.sphref_boundary_normal_at.argtypes = [C.POINTER(Geometry), C.c_int32, C.c_int32, _dp,
+                                                _dp, _dp]
+        _ip = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
+        L.sphref_tags.argtypes = [C.POINTER(Geometry), _ip, _ip, C.POINTER(C.c_int32),
+                                  C.POINTER(C.c_int32), C.c_void_p]
         L.sphref_create.argtypes = [C.POINTER(Geometry), C.POINTER(Sizing), C.POINTER(Params),
                                     C.c_int64, _dp, np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS"),
                                     C.POINTER(C.c_void_p)]
@@ -141,7 +147,32 @@ def make_geometry(dim, lo, hi, holes, domain=0, level=None):
             g.n_corners = cor.shape[0]
             g.corners = cor.ctypes.data_as(C.POINTER(C.c_double))
             g._keep_curves = (off, pts, ends, cor)
+            if "patches" in cv:
+                cp = np.ascontiguousarray(np.asarray(cv["patches"], np.int32).reshape(-1, 2))
+                g.n_patches = int(cv["n_patches"])
+                g.curve_patches = cp.ctypes.data_as(C.POINTER(C.c_int32))
+                g._keep_patches = cp
     return g
+
+
+def tags(geom, n_curves=0):
+    """The cell tag system of a level-set geometry: (ctype, cindex) per grid
+    cell (x fastest), the volume and patch counts, and the two patches
+    beside each curve."""
+    L = lib()
+    nc = [max(int(geom.phi_n[a]) - 1, 1) for a in range(3)]
+    if geom.dim == 2:
+        nc[2] = 1
+    ncell = nc[0] * nc[1] * nc[2]
+    ct = np.empty(ncell, np.int32)
+    ci = np.empty(ncell, np.int32)
+    nv, npch = C.c_int32(), C.c_int32()
+    cp = np.full(2 * max(n_curves, 1), -1, np.int32)
+    rc = L.sphref_tags(C.byref(geom), ct, ci, C.byref(nv), C.byref(npch), cp.ctypes.data)
+    if rc:
+        raise RuntimeError("sphref_tags: " + L.sphref_last_error().decode())
+    shape = (nc[2], nc[1], nc[0])
+    return ct.reshape(shape), ci.reshape(shape), nv.value, npch.value, cp[:2 * n_curves].reshape(-1, 2)
 
 
 def make_sizing(sz):

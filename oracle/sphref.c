@@ -68,8 +68,9 @@ typedef struct {
   const double *phi;        /* level-set domain: node values, counts and box */
   int pn[3];
   double plo[3], phi_hi[3];
-  int ncv, ncr;             /* imported curves and corners (2D level-set domain) */
-  const int32_t *coff, *cend;
+  int ncv, ncr;             /* imported curves and corners (level-set domain) */
+  int np;                   /* 3D: surface patches the curves split the zero set into */
+  const int32_t *coff, *cend, *cpat;
   const double *cpts;
   double cor[MAXF][3];
   int nf;
@@ -99,27 +100,45 @@ static int geo_build(const sphref_geometry *g, geo_t *G) {
     }
     G->f[0] = (feat_t){.type = T_V, .k = g->dim, .kind = K_VOL};
     if (g->n_curves > 0) {
-      /* imported curves and corners replace the single zero-set feature */
-      if (g->dim != 2 || !g->curve_off || !g->curve_pts || !g->curve_ends ||
+      /* imported curves and corners replace the single zero-set feature; in
+       * 3D the curves split the zero set into surface patches */
+      int np = g->dim == 3 ? g->n_patches : 0;
+      if (!g->curve_off || !g->curve_pts || !g->curve_ends ||
           g->n_corners < 0 || (g->n_corners > 0 && !g->corners) ||
-          1 + g->n_curves + g->n_corners > MAXF) {
+          (g->dim == 2 && g->n_patches != 0) ||
+          (g->dim == 3 && (np < 1 || !g->curve_patches)) ||
+          1 + np + g->n_curves + g->n_corners > MAXF) {
         set_err("bad imported curves"); return -1;
       }
       G->ncv = g->n_curves;
       G->ncr = g->n_corners;
+      G->np = np;
       G->coff = g->curve_off;
       G->cend = g->curve_ends;
+      G->cpat = g->curve_patches;
       G->cpts = g->curve_pts;
       for (int c = 0; c < G->ncv; ++c) {
         if (g->curve_off[c + 1] - g->curve_off[c] < 2) { set_err("a curve needs two points"); return -1; }
-        for (int e = 0; e < 2; ++e)
+        for (int k = g->curve_off[c]; k + 1 < g->curve_off[c + 1]; ++k) {
+          const double *p0 = g->curve_pts + 3 * k, *p1 = p0 + 3;
+          if (p0[0] == p1[0] && p0[1] == p1[1] && (g->dim == 2 || p0[2] == p1[2])) {
+            set_err("consecutive curve points must differ"); return -1;
+          }
+        }
+        for (int e = 0; e < 2; ++e) {
           if (g->curve_ends[2 * c + e] < -1 || g->curve_ends[2 * c + e] >= G->ncr) {
             set_err("bad curve end"); return -1;
           }
+          if (np > 0 && (g->curve_patches[2 * c + e] < -1 || g->curve_patches[2 * c + e] >= np)) {
+            set_err("bad curve patch"); return -1;
+          }
+        }
       }
       for (int m = 0; m < G->ncr; ++m)
         for (int a = 0; a < 3; ++a) G->cor[m][a] = g->corners[3 * m + a];
       int nf = 1;
+      for (int p = 0; p < np; ++p)
+        G->f[nf++] = (feat_t){.type = T_S, .k = 2, .kind = K_LEVEL, .hole = p};
       for (int c = 0; c < G->ncv; ++c)
         G->f[nf++] = (feat_t){.type = T_C, .k = 1, .kind = K_POLY, .hole = c};
       for (int m = 0; m < G->ncr; ++m)
@@ -213,6 +232,14 @@ static int bounds(const geo_t *G, int fi, int fb) {
     case K_POLY:          /* an imported curve is bounded by its end corners */
       return B->kind == K_PCORNER &&
              (G->cend[2 * A->hole] == B->hole || G->cend[2 * A->hole + 1] == B->hole);
+    case K_LEVEL:         /* a surface patch: by the curves beside it and their end corners */
+      if (G->np == 0) return 0;
+      for (int c = 0; c < G->ncv; ++c) {
+        if (G->cpat[2 * c] != A->hole && G->cpat[2 * c + 1] != A->hole) continue;
+        if (B->kind == K_POLY && B->hole == c) return 1;
+        if (B->kind == K_PCORNER && (G->cend[2 * c] == B->hole || G->cend[2 * c + 1] == B->hole)) return 1;
+      }
+      return 0;
     default: return 0;
   }
 }
@@ -328,6 +355,7 @@ static void ell_normal(const geo_t *G, int q, const double *x, double *n) {
 }
 
 static double sg(int side) { return side ? 1.0 : -1.0; }
+static double norm3(const double *u) { return sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]); }
 
 /* ------------------------------------------------------------------ */
 /* gridded level set (sec. 2.1: phi on a Cartesian background mesh)     */
@@ -377,23 +405,31 @@ static double ls_phi(const geo_t *G, const double *x, double *grad) {
   return w[0] + t[2] * (w[1] - w[0]);
 }
 
-/* imported curve c (a polyline, domain on its left): the segment whose
- * closest point to x is nearest (the first one on ties), and that point */
+/* imported curve c (a polyline; in 2D with the domain on its left): the
+ * segment whose closest point to x is nearest (the first one on ties), and
+ * that point */
 static int poly_closest(const geo_t *G, int c, const double *x, double *q) {
+  int D = G->dim;
   int best = G->coff[c];                     /* also when no distance compares */
-  q[0] = G->cpts[3 * best]; q[1] = G->cpts[3 * best + 1];
+  for (int a = 0; a < 3; ++a) q[a] = a < D ? G->cpts[3 * best + a] : 0.0;
   double bd = INFINITY;
   for (int k = G->coff[c]; k + 1 < G->coff[c + 1]; ++k) {
     const double *p0 = G->cpts + 3 * k, *p1 = G->cpts + 3 * (k + 1);
-    double e0 = p1[0] - p0[0], e1 = p1[1] - p0[1];
-    double ee = e0 * e0 + e1 * e1;
-    double t = ee > 0.0 ? ((x[0] - p0[0]) * e0 + (x[1] - p0[1]) * e1) / ee : 0.0;
+    double e[3] = {0, 0, 0}, ee = 0.0, xe = 0.0;
+    for (int a = 0; a < D; ++a) {
+      e[a] = p1[a] - p0[a];
+      ee = ee + e[a] * e[a];
+      xe = xe + (x[a] - p0[a]) * e[a];
+    }
+    double t = ee > 0.0 ? xe / ee : 0.0;
     if (t < 0.0) t = 0.0;
     if (t > 1.0) t = 1.0;
-    double c0 = p0[0] + t * e0, c1 = p0[1] + t * e1;
-    double d0 = x[0] - c0, d1 = x[1] - c1;
-    double d = d0 * d0 + d1 * d1;
-    if (d < bd) { bd = d; best = k; q[0] = c0; q[1] = c1; }
+    double cp[3] = {0, 0, 0}, d = 0.0;
+    for (int a = 0; a < D; ++a) {
+      cp[a] = p0[a] + t * e[a];
+      d = d + (x[a] - cp[a]) * (x[a] - cp[a]);
+    }
+    if (d < bd) { bd = d; best = k; for (int a = 0; a < 3; ++a) q[a] = cp[a]; }
   }
   return best;
 }
@@ -401,9 +437,10 @@ static int poly_closest(const geo_t *G, int c, const double *x, double *q) {
 /* unit tangent of segment k of the imported curves (along the curve) */
 static void seg_tangent(const geo_t *G, int k, double *t) {
   const double *p0 = G->cpts + 3 * k, *p1 = G->cpts + 3 * (k + 1);
-  double e0 = p1[0] - p0[0], e1 = p1[1] - p0[1];
-  double l = sqrt(e0 * e0 + e1 * e1);
-  t[0] = e0 / l; t[1] = e1 / l; t[2] = 0.0;
+  double e[3] = {0, 0, 0}, s = 0.0;
+  for (int a = 0; a < G->dim; ++a) { e[a] = p1[a] - p0[a]; s = s + e[a] * e[a]; }
+  double l = sqrt(s);
+  for (int a = 0; a < 3; ++a) t[a] = e[a] / l;
 }
 
 /* unit normal of the level set at x, pointing to increasing phi (into the
@@ -439,7 +476,7 @@ static void ls_project(const geo_t *G, double *x) {
  * domain of i; at box edges and corners the normalised sum of the adjacent
  * face normals, within a face the in-face conormal, on a curve the outward
  * tangent). */
-static void bnormal(const geo_t *G, int fi, int fb, const double *xb, double *n) {
+static void bnormal(const geo_t *G, int fi, int fb, const double *xb, const double *xi, double *n) {
   const feat_t *A = &G->f[fi], *B = &G->f[fb];
   int D = G->dim;
   n[0] = n[1] = n[2] = 0.0;
@@ -456,6 +493,14 @@ static void bnormal(const geo_t *G, int fi, int fb, const double *xb, double *n)
       for (int a = 0; a < D; ++a) { d[a] = G->hc[B->hole][a] - xb[a]; s = s + d[a] * d[a]; }
       double r = sqrt(s);
       for (int a = 0; a < D; ++a) n[a] = d[a] / r;
+    } else if (B->kind == K_POLY && D == 3) {
+      /* a 3D curve on the zero set: towards decreasing phi, as on a patch */
+      ls_unit(G, xb, n);
+      for (int a = 0; a < 3; ++a) n[a] = -n[a];
+    } else if (B->kind == K_PCORNER && D == 3) {
+      /* a 3D corner: towards decreasing phi at the corner point */
+      ls_unit(G, G->cor[B->hole], n);
+      for (int a = 0; a < 3; ++a) n[a] = -n[a];
     } else if (B->kind == K_POLY) {
       /* out of the domain = the right of the curve's closest segment */
       double q[3], t[3];
@@ -514,11 +559,32 @@ static void bnormal(const geo_t *G, int fi, int fb, const double *xb, double *n)
     double t[3];
     if (G->cend[2 * c] == B->hole) {
       seg_tangent(G, G->coff[c], t);
-      n[0] = -t[0]; n[1] = -t[1];
+      for (int a = 0; a < 3; ++a) n[a] = -t[a];
     } else {
       seg_tangent(G, G->coff[c + 1] - 2, t);
-      n[0] = t[0]; n[1] = t[1];
+      for (int a = 0; a < 3; ++a) n[a] = t[a];
     }
+  } else if (A->kind == K_LEVEL) {
+    /* a 3D surface patch at a curve or corner beside it: the direction from
+     * the particle i to b within i's tangent plane (the patch normal m at x_i
+     * removed), and at a curve also without the part along the curve's
+     * tangent t at b (its closest segment), normalised:
+     *   n = (I - t t^T)(I - m m^T)(x_b - x_i) / |.|
+     * For a flat patch and a straight curve this is the patch's outward
+     * conormal, as the in-face normal at a box edge. */
+    double m[3], d[3], dm = 0.0;
+    ls_unit(G, xi, m);
+    for (int a = 0; a < 3; ++a) { d[a] = xb[a] - xi[a]; dm = dm + d[a] * m[a]; }
+    for (int a = 0; a < 3; ++a) d[a] = d[a] - dm * m[a];
+    if (B->kind == K_POLY) {
+      double q[3], t[3], dt = 0.0;
+      seg_tangent(G, poly_closest(G, B->hole, xb, q), t);
+      for (int a = 0; a < 3; ++a) dt = dt + d[a] * t[a];
+      for (int a = 0; a < 3; ++a) d[a] = d[a] - dt * t[a];
+    }
+    double l = norm3(d);
+    if (l > 0.0)
+      for (int a = 0; a < 3; ++a) n[a] = d[a] / l;
   }
 }
 
@@ -571,8 +637,13 @@ static void tproject(const geo_t *G, int fi, const double *x, double *u) {
     case K_POLY: {                        /* keep the part along the closest segment */
       double q[3], t[3];
       seg_tangent(G, poly_closest(G, A->hole, x, q), t);
-      double ut = u[0] * t[0] + u[1] * t[1];
-      u[0] = ut * t[0]; u[1] = ut * t[1]; u[2] = 0.0;
+      if (D == 2) {
+        double ut = u[0] * t[0] + u[1] * t[1];
+        u[0] = ut * t[0]; u[1] = ut * t[1]; u[2] = 0.0;
+      } else {
+        double ut = u[0] * t[0] + u[1] * t[1] + u[2] * t[2];
+        for (int a = 0; a < 3; ++a) u[a] = ut * t[a];
+      }
       return;
     }
     case K_LEVEL: {
@@ -643,7 +714,7 @@ static void pproject(const geo_t *G, int fi, double *x) {
     case K_POLY: {
       double q[3];
       poly_closest(G, A->hole, x, q);
-      x[0] = q[0]; x[1] = q[1];
+      for (int a = 0; a < D; ++a) x[a] = q[a];
       return;
     }
     case K_PCORNER:
@@ -869,13 +940,18 @@ int32_t sphref_project(const sphref_geometry *g, int32_t f, double *x) {
   pproject(&G, f, x);
   return 0;
 }
-int32_t sphref_boundary_normal(const sphref_geometry *g, int32_t fi, int32_t fb,
-                               const double *xb, double *n) {
+int32_t sphref_boundary_normal_at(const sphref_geometry *g, int32_t fi, int32_t fb,
+                                  const double *xb, const double *xi, double *n) {
   geo_t G;
   if (geo_build(g, &G) || fi < 0 || fb < 0 || fi >= G.nf || fb >= G.nf) return -1;
   if (!bounds(&G, fi, fb)) { n[0] = n[1] = n[2] = 0.0; return 0; }
-  bnormal(&G, fi, fb, xb, n);
+  if (G.f[fi].kind == K_LEVEL && !xi) { set_err("this normal depends on x_i"); return -1; }
+  bnormal(&G, fi, fb, xb, xi, n);
   return 1;
+}
+int32_t sphref_boundary_normal(const sphref_geometry *g, int32_t fi, int32_t fb,
+                               const double *xb, double *n) {
+  return sphref_boundary_normal_at(g, fi, fb, xb, NULL, n);
 }
 
 static void grp_init(grp_t *g) {
@@ -1231,7 +1307,6 @@ int32_t sphref_control_replay(const sphref_params *p, int32_t n_steps,
   return 0;
 }
 
-static double norm3(const double *u) { return sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]); }
 
 /* Shepard term, particle volume, pressure force with the boundary term,
  * mapped onto the feature (Eqs. (gamma_disc_renormSPH), (particle_volume),
@@ -1268,7 +1343,7 @@ static void sweep_a_particle(const sphref_job *J, int64_t i, const int32_t *nbl,
                    : P->boundary_weighting == 1 ? hpow(hj, k - 1) : 0.0;
       omega = omega * bscale(P);
       double nb[3];
-      bnormal(G, J->f[i], J->f[j], J->x + 3 * j, nb);
+      bnormal(G, J->f[i], J->f[j], J->x + 3 * j, J->x + 3 * i, nb);
       double c = P->p0 * (hi2k + hj2k) * sphref_W(k, r, lij) * omega;
       for (int a = 0; a < D; ++a) B[a] = B[a] + c * nb[a];
     }
@@ -1564,5 +1639,184 @@ int32_t sphref_counters(sphref_job *J, double *out) {
   out[1] = (double)J->escaped;
   out[2] = (double)J->inter_total;
   out[3] = (double)J->inter_last;
+  return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* the tag system of the background grid (sec. 3.2): cell types and     */
+/* feature indices of a level-set domain                                */
+/* ------------------------------------------------------------------ */
+enum { C_NEG = 0, C_POS = 1, C_SURF = 2, C_CURVE = 3, C_SING = 4 };
+
+/* cell of point x (clamped to the grid), as (i, j, k) */
+static void tag_cell_of(const geo_t *G, const int *nc, const double *x, int *ijk) {
+  for (int a = 0; a < 3; ++a) {
+    ijk[a] = 0;
+    if (a >= G->dim) continue;
+    double s = (double)(G->pn[a] - 1) / (G->phi_hi[a] - G->plo[a]);
+    double u = floor((x[a] - G->plo[a]) * s);
+    if (!(u > 0.0)) u = 0.0;
+    if (u > (double)(nc[a] - 1)) u = (double)(nc[a] - 1);
+    ijk[a] = (int)u;
+  }
+}
+
+/* give cell (i, j, k) type t and index v unless a cell of that type already
+ * holds it; curve marks do not replace corner marks */
+static void tag_mark(int32_t *ctype, int32_t *cindex, const int *nc, int i, int j, int k,
+                     int t, int v) {
+  if (i < 0 || j < 0 || k < 0 || i >= nc[0] || j >= nc[1] || k >= nc[2]) return;
+  int64_t id = ((int64_t)k * nc[1] + j) * nc[0] + i;
+  if (ctype[id] == C_SING || (ctype[id] == C_CURVE && t == C_CURVE)) return;
+  ctype[id] = t;
+  cindex[id] = v;
+}
+
+/* number the face-connected components of the cells of type t in the order
+ * of their first cell; returns their count */
+static int tag_components(int32_t *ctype, int32_t *cindex, const int *nc, int t, int64_t *stack) {
+  int64_t ncell = (int64_t)nc[0] * nc[1] * nc[2];
+  int count = 0;
+  for (int64_t s = 0; s < ncell; ++s) {
+    if (ctype[s] != t || cindex[s] >= 0) continue;
+    int64_t top = 0;
+    stack[top++] = s;
+    cindex[s] = count;
+    while (top > 0) {
+      int64_t id = stack[--top];
+      int i = (int)(id % nc[0]), j = (int)((id / nc[0]) % nc[1]), k = (int)(id / ((int64_t)nc[0] * nc[1]));
+      const int off[6][3] = {{-1, 0, 0}, {1, 0, 0}, {0, -1, 0}, {0, 1, 0}, {0, 0, -1}, {0, 0, 1}};
+      for (int q = 0; q < 6; ++q) {
+        int a = i + off[q][0], b = j + off[q][1], c = k + off[q][2];
+        if (a < 0 || b < 0 || c < 0 || a >= nc[0] || b >= nc[1] || c >= nc[2]) continue;
+        int64_t nb = ((int64_t)c * nc[1] + b) * nc[0] + a;
+        if (ctype[nb] != t || cindex[nb] >= 0) continue;
+        cindex[nb] = count;
+        stack[top++] = nb;
+      }
+    }
+    ++count;
+  }
+  return count;
+}
+
+int32_t sphref_tags(const sphref_geometry *g, int32_t *ctype, int32_t *cindex,
+                    int32_t *n_volumes, int32_t *n_patches, int32_t *curve_patches) {
+  /* the patches are what this finds: a 3D geometry may leave them unset */
+  geo_t G;
+  sphref_geometry gg;
+  int32_t *unset = NULL;
+  if (g && g->dim == 3 && g->n_curves > 0 && (g->n_patches < 1 || !g->curve_patches)) {
+    gg = *g;
+    unset = malloc(2 * (size_t)g->n_curves * sizeof(int32_t));
+    if (!unset) { set_err("out of memory"); return -1; }
+    for (int q = 0; q < 2 * g->n_curves; ++q) unset[q] = -1;
+    gg.n_patches = 1;
+    gg.curve_patches = unset;
+    g = &gg;
+  }
+  int bad = geo_build(g, &G);
+  free(unset);
+  if (bad) return -1;
+  if (G.domain != 2) { set_err("the tag system needs a level-set domain"); return -1; }
+  if (!ctype || !cindex || !n_volumes || !n_patches || (G.ncv > 0 && !curve_patches)) {
+    set_err("bad argument"); return -1;
+  }
+  int D = G.dim, nc[3] = {1, 1, 1};
+  for (int a = 0; a < D; ++a) nc[a] = G.pn[a] - 1;
+  int64_t ncell = (int64_t)nc[0] * nc[1] * nc[2];
+  /* phi at the cell's nodes: all positive, all negative, or mixed */
+  for (int k = 0; k < nc[2]; ++k)
+    for (int j = 0; j < nc[1]; ++j)
+      for (int i = 0; i < nc[0]; ++i) {
+        int pos = 0, neg = 0, nn = D == 3 ? 8 : 4;
+        for (int q = 0; q < nn; ++q) {
+          int a = i + (q & 1), b = j + ((q >> 1) & 1), c = k + ((q >> 2) & 1);
+          double v = G.phi[((int64_t)c * G.pn[1] + b) * G.pn[0] + a];
+          pos += v > 0.0;
+          neg += v < 0.0;
+        }
+        int64_t id = ((int64_t)k * nc[1] + j) * nc[0] + i;
+        ctype[id] = pos == nn ? C_POS : (neg == nn ? C_NEG : C_SURF);
+        cindex[id] = -1;
+      }
+  /* curves: the cells of points along each segment, a quarter of the
+   * smallest cell side apart, and their face neighbours */
+  double side = INFINITY;
+  for (int a = 0; a < D; ++a) {
+    double w = (G.phi_hi[a] - G.plo[a]) / (double)nc[a];
+    if (w < side) side = w;
+  }
+  for (int c = 0; c < G.ncv; ++c)
+    for (int s = G.coff[c]; s + 1 < G.coff[c + 1]; ++s) {
+      const double *p0 = G.cpts + 3 * s, *p1 = p0 + 3;
+      double e[3] = {0, 0, 0}, l2 = 0.0;
+      for (int a = 0; a < D; ++a) { e[a] = p1[a] - p0[a]; l2 = l2 + e[a] * e[a]; }
+      int64_t ns = (int64_t)ceil(sqrt(l2) / (0.25 * side));
+      if (ns < 1) ns = 1;
+      for (int64_t q = 0; q <= ns; ++q) {
+        double x[3] = {0, 0, 0}, tq = (double)q / (double)ns;
+        for (int a = 0; a < D; ++a) x[a] = p0[a] + tq * e[a];
+        int ijk[3];
+        tag_cell_of(&G, nc, x, ijk);
+        tag_mark(ctype, cindex, nc, ijk[0], ijk[1], ijk[2], C_CURVE, c);
+        for (int a = 0; a < D; ++a)
+          for (int sd = -1; sd <= 1; sd += 2) {
+            int o[3] = {ijk[0], ijk[1], ijk[2]};
+            o[a] += sd;
+            tag_mark(ctype, cindex, nc, o[0], o[1], o[2], C_CURVE, c);
+          }
+      }
+    }
+  /* corners: their cell and all its neighbours */
+  for (int m = 0; m < G.ncr; ++m) {
+    int ijk[3];
+    tag_cell_of(&G, nc, G.cor[m], ijk);
+    for (int dk = (D == 3 ? -1 : 0); dk <= (D == 3 ? 1 : 0); ++dk)
+      for (int dj = -1; dj <= 1; ++dj)
+        for (int di = -1; di <= 1; ++di) {
+          int i = ijk[0] + di, j = ijk[1] + dj, k = ijk[2] + dk;
+          if (i < 0 || j < 0 || k < 0 || i >= nc[0] || j >= nc[1] || k >= nc[2]) continue;
+          int64_t id = ((int64_t)k * nc[1] + j) * nc[0] + i;
+          if (ctype[id] == C_SING) continue;
+          ctype[id] = C_SING;
+          cindex[id] = m;
+        }
+  }
+  int64_t *stack = malloc((size_t)ncell * sizeof(int64_t));
+  if (!stack) { set_err("out of memory"); return -1; }
+  *n_patches = tag_components(ctype, cindex, nc, C_SURF, stack);
+  *n_volumes = tag_components(ctype, cindex, nc, C_POS, stack);
+  free(stack);
+  /* the patches beside each curve: face neighbours of its cells */
+  for (int c = 0; c < G.ncv; ++c) {
+    int found[3] = {-1, -1, -1}, nfound = 0;
+    for (int64_t id = 0; id < ncell; ++id) {
+      if (ctype[id] != C_CURVE || cindex[id] != c) continue;
+      int i = (int)(id % nc[0]), j = (int)((id / nc[0]) % nc[1]), k = (int)(id / ((int64_t)nc[0] * nc[1]));
+      for (int a = 0; a < D; ++a)
+        for (int sd = -1; sd <= 1; sd += 2) {
+          int o[3] = {i, j, k};
+          o[a] += sd;
+          if (o[a] < 0 || o[a] >= nc[a]) continue;
+          int64_t nb = ((int64_t)o[2] * nc[1] + o[1]) * nc[0] + o[0];
+          if (ctype[nb] != C_SURF) continue;
+          int p = cindex[nb], seen = 0;
+          for (int q = 0; q < nfound && q < 3; ++q) seen |= found[q] == p;
+          if (!seen) {
+            if (nfound < 3) found[nfound] = p;
+            ++nfound;
+          }
+        }
+    }
+    if (nfound > 2) {
+      curve_patches[2 * c] = -2;
+      curve_patches[2 * c + 1] = -1;
+      continue;
+    }
+    if (nfound == 2 && found[1] < found[0]) { int t = found[0]; found[0] = found[1]; found[1] = t; }
+    curve_patches[2 * c] = found[0];
+    curve_patches[2 * c + 1] = found[1];
+  }
   return 0;
 }

@@ -67,6 +67,14 @@ typedef struct {
   const int32_t *curve_ends;
   int32_t n_corners;
   const double *corners;
+  /* domain 2 in 3D with imported curves (sec. 2.1's sharp edges on a 3D
+   * level set): the curves split the zero level set into n_patches surface
+   * patches; curve c separates patches curve_patches[2c] and
+   * curve_patches[2c+1] (0-based, -1 for none).  Features are then
+   * 0 volume | 1..n_patches the patches | the curves | the corners.  A
+   * curve may be closed (its last point equal to its first, no corners). */
+  int32_t n_patches;
+  const int32_t *curve_patches;
 } sphref_geometry;
 
 /* Target feature size h_t(x) (paper sec. 2.2).
@@ -136,9 +144,32 @@ int32_t sphref_project(const sphref_geometry *g, int32_t f, double *x);
 int32_t sphref_n_features(const sphref_geometry *g);
 int32_t sphref_feature_type(const sphref_geometry *g, int32_t f);
 /* outward normal n_{b|f}: of feature fi's boundary at boundary particle
- * position xb of feature fb; returns 1 if fb bounds fi, 0 otherwise */
+ * position xb of feature fb; returns 1 if fb bounds fi, 0 otherwise, -1 for
+ * a pair whose normal depends on the particle of fi (below) */
 int32_t sphref_boundary_normal(const sphref_geometry *g, int32_t fi, int32_t fb,
                                const double *xb, double *n);
+/* the same seen from a particle of fi at xi: a 3D surface patch's normal at
+ * its curves and corners depends on xi */
+int32_t sphref_boundary_normal_at(const sphref_geometry *g, int32_t fi, int32_t fb,
+                                  const double *xb, const double *xi, double *n);
+/* Tag system of the background grid of a level-set domain (sec. 3.2), one
+ * entry per grid cell (cells between the nodes of phi, x fastest):
+ *   ctype: 0 negative cell (C-), 1 positive cell (C+), 2 surface cell (C_s),
+ *          3 curve cell (C_c), 4 singular cell (C_si)
+ *   cindex: the feature index within its type (volume component, surface
+ *          patch, curve, corner), -1 for a negative cell.
+ * A cell is positive when phi > 0 at all its nodes, negative when phi < 0 at
+ * all of them, a surface cell otherwise.  A curve marks the cells its points
+ * (sampled at a quarter of the smallest cell side) lie in and their face
+ * neighbours; a corner marks its cell and all neighbours; the first curve
+ * (corner) in order keeps a cell, corners win over curves.  Surface cells
+ * that remain form patches, positive cells volumes: components over face
+ * neighbours, numbered in the order of their first cell.  Curve c touches
+ * patch p when one of its cells is a face neighbour of a cell of p; the
+ * two touched patches go to curve_patches[2c], [2c+1] (ascending, -1 for
+ * none; -2 in [2c] if more than two).  Counts go to *n_volumes, *n_patches. */
+int32_t sphref_tags(const sphref_geometry *g, int32_t *ctype, int32_t *cindex,
+                    int32_t *n_volumes, int32_t *n_patches, int32_t *curve_patches);
 
 int32_t sphref_create(const sphref_geometry *g, const sphref_sizing *s,
                       const sphref_params *p, int64_t n, const double *xyz,

@@ -977,6 +977,236 @@ def zalesak_disc(n_total=2400, seed=13, n_grid=129, n_arc=256, res=256, uniform=
                     counts=counts, scale=sc, steps=0, domain=2, level=level)
 
 
+def level_cylinder(n_total=12000, seed=14, n_grid=33, n_circ=128, res=64, **pover):
+    """A 3D level-set domain with imported sharp edges: the solid cylinder of
+    radius 0.3 about the axis x = y = 0.5, 0.2 <= z <= 0.8, phi = min(0.3 - r,
+    z - 0.2, 0.8 - z) on an n_grid^3 grid over the unit cube, plus its two rim
+    circles as closed n_circ-segment polylines (sec. 2.1's imported feature
+    curves, here on a 3D level set).  The rims split the zero set into three
+    surface patches, numbered as the tag system numbers them (in the order of
+    their first grid cell): 0 the bottom disc, 1 the side, 2 the top disc;
+    curve 0 (bottom rim) lies between patches 0 and 1, curve 1 (top rim)
+    between 1 and 2.  Six features: the volume, the three patches, the two
+    rims; no singular points.  h grows linearly from the bottom centre."""
+    dim = 3
+    R, z0, z1, cx = 0.3, 0.2, 0.8, 0.5
+
+    def phi_fn(x, y, z):
+        return np.minimum(np.minimum(R - np.hypot(x - cx, y - cx), z - z0), z1 - z)
+
+    th = np.linspace(0.0, 2 * math.pi, n_circ + 1)
+    rims = []
+    for zc in (z0, z1):
+        c = np.stack([cx + R * np.cos(th), cx + R * np.sin(th), np.full(n_circ + 1, zc)], 1)
+        c[-1] = c[0]
+        rims.append(c)
+    off = np.array([0, n_circ + 1, 2 * (n_circ + 1)], np.int32)
+    lo, hi = np.zeros(3), np.ones(3)
+    gn = [n_grid] * 3
+    ax = [np.arange(n_grid) / (n_grid - 1) for _ in range(3)]
+    Z, Y, X = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
+    level = dict(phi=np.ascontiguousarray(phi_fn(X.ravel(), Y.ravel(), Z.ravel())), n=gn,
+                 lo=[0.0, 0.0, 0.0], hi=[1.0, 1.0, 1.0],
+                 curves=dict(off=off, pts=np.concatenate(rims, 0),
+                             ends=np.full((2, 2), -1, np.int32), corners=np.zeros((0, 3)),
+                             n_patches=3, patches=np.array([[0, 1], [1, 2]], np.int32)))
+    types = np.asarray([VOL, SURF, SURF, SURF, CURVE, CURVE], np.int32)
+    holes = np.zeros((0, 15))
+    base = dict(kind=H_LINEAR_FROM_POINT, h0=0.012, grad=0.03, dcap=np.inf,
+                point=[cx, cx, z0])
+
+    def phi(p):
+        return _level_eval(level, dim, p)[0]
+
+    # sample points of the analytic faces and rims with their measures, for
+    # the mass integrals of sec. 3.2
+    u = (np.arange(res) + 0.5) / res
+    rr, aa = np.meshgrid(R * np.sqrt(u), 2 * math.pi * u, indexing="ij")
+    disc_w = math.pi * R * R / rr.size
+
+    def disc_pts(zc):
+        return np.stack([cx + rr.ravel() * np.cos(aa.ravel()), cx + rr.ravel() * np.sin(aa.ravel()),
+                         np.full(rr.size, zc)], 1)
+
+    za, ab = np.meshgrid(z0 + (z1 - z0) * u, 2 * math.pi * u, indexing="ij")
+    side_pts = np.stack([cx + R * np.cos(ab.ravel()), cx + R * np.sin(ab.ravel()), za.ravel()], 1)
+    side_w = 2 * math.pi * R * (z1 - z0) / za.size
+    rim_u = 2 * math.pi * (np.arange(4 * res) + 0.5) / (4 * res)
+    rim_w = 2 * math.pi * R / rim_u.size
+
+    def rim_pts(zc):
+        return np.stack([cx + R * np.cos(rim_u), cx + R * np.sin(rim_u), np.full(rim_u.size, zc)], 1)
+
+    def masses(sz):
+        g = (np.arange(res) + 0.5) / res
+        Xg, Yg, Zg = np.meshgrid(g, g, g, indexing="ij")
+        P = np.stack([Xg.ravel(), Yg.ravel(), Zg.ravel()], 1)
+        M = {0: float(np.sum(_h_field(P[phi(P) > 0], dim, sz, holes) ** -3.0)) / res ** 3}
+        M[1] = float(np.sum(_h_field(disc_pts(z0), dim, sz, holes) ** -2.0)) * disc_w
+        M[2] = float(np.sum(_h_field(side_pts, dim, sz, holes) ** -2.0)) * side_w
+        M[3] = float(np.sum(_h_field(disc_pts(z1), dim, sz, holes) ** -2.0)) * disc_w
+        M[4] = float(np.sum(_h_field(rim_pts(z0), dim, sz, holes) ** -1.0)) * rim_w
+        M[5] = float(np.sum(_h_field(rim_pts(z1), dim, sz, holes) ** -1.0)) * rim_w
+        return M
+
+    M = masses(base)
+    sc = _solve_scale(M, types, n_total, dim)
+    sizing = dict(base, h0=base["h0"] * sc, grad=base["grad"] * sc)
+    counts = _split_counts(M, types, sc, n_total, dim)
+    rng = np.random.Generator(np.random.MT19937(seed))
+    hmin = sizing["h0"]
+
+    def box_prop(m):
+        return rng.random((m, 3))
+
+    def disc_prop(zc):
+        def prop(m):
+            r_, a_ = R * np.sqrt(rng.random(m)), 2 * math.pi * rng.random(m)
+            return np.stack([cx + r_ * np.cos(a_), cx + r_ * np.sin(a_), np.full(m, zc)], 1)
+        return prop
+
+    def side_prop(m):
+        a_, z_ = 2 * math.pi * rng.random(m), z0 + (z1 - z0) * rng.random(m)
+        return np.stack([cx + R * np.cos(a_), cx + R * np.sin(a_), z_], 1)
+
+    def rim_prop(poly):
+        seg = np.linalg.norm(np.diff(poly, axis=0), axis=1)
+        cum = np.concatenate([[0.0], np.cumsum(seg)])
+
+        def along(m):
+            sarc = rng.random(m) * cum[-1]
+            j = np.minimum(np.searchsorted(cum, sarc, side="right") - 1, len(seg) - 1)
+            t = (sarc - cum[j]) / seg[j]
+            return poly[j] + t[:, None] * (poly[j + 1] - poly[j])
+        return along
+
+    props = [(box_prop, 3), (disc_prop(z0), 2), (side_prop, 2), (disc_prop(z1), 2),
+             (rim_prop(rims[0]), 1), (rim_prop(rims[1]), 1)]
+    xyz, feat = [], []
+    for f, (prop, k) in enumerate(props):
+        p = _sample_rejection(rng, counts[f], prop, dim, sizing, holes, k, hmin,
+                              accept_mask=(lambda q: phi(q) > 0) if f == 0 else None)
+        xyz.append(p)
+        feat.append(np.full(len(p), f, np.int32))
+    xyz = np.ascontiguousarray(np.concatenate(xyz, 0))
+    feat = np.ascontiguousarray(np.concatenate(feat))
+    assert xyz.shape[0] == n_total, (xyz.shape, n_total)
+    return Workload(name="level_cylinder", dim=3, lo=lo, hi=hi, holes=holes, sizing=sizing,
+                    params=default_params(**pover), xyz=xyz, feature=feat, ftype=types,
+                    counts=counts, scale=sc, steps=0, domain=2, level=level)
+
+
+def level_cube_sharp(n_total=8000, seed=15, n_grid=41, res=48, **pover):
+    """The cube [0.2125, 0.7875]^3 as a 3D level-set domain with all its
+    sharp features imported: phi = min over the six faces of the signed
+    distance inside, on an n_grid^3 grid over the unit cube (the faces lie
+    half-way between grid nodes for n_grid = 41), the twelve edges as
+    two-point curves from their lower to their upper end and the eight
+    vertices as singular points (bit a of a vertex's number set when it lies
+    on the upper side along axis a).  The edges split the zero set into the
+    six faces, numbered as the tag system numbers them (in the order of their
+    first grid cell): 0 z-, 1 y-, 2 x-, 3 x+, 4 y+, 5 z+.  Features: the
+    volume, the six faces, the twelve edges (along x with (y, z) sides
+    (-,-), (+,-), (-,+), (+,+), then along y with (x, z) sides, then along z
+    with (x, y) sides), the eight vertices: 27.  h grows linearly from the
+    lower vertex, so that the case is not symmetric."""
+    dim = 3
+    a0, a1 = 0.2125, 0.7875
+    lo, hi = np.zeros(3), np.ones(3)
+
+    def phi_fn(x, y, z):
+        return np.minimum.reduce([x - a0, a1 - x, y - a0, a1 - y, z - a0, a1 - z])
+
+    face_of = {(2, 0): 0, (1, 0): 1, (0, 0): 2, (0, 1): 3, (1, 1): 4, (2, 1): 5}
+    corners = np.array([[a1 if (m >> a) & 1 else a0 for a in range(3)] for m in range(8)])
+    polys, ends, pat = [], [], []
+    for ax_ in range(3):
+        o = [b for b in range(3) if b != ax_]
+        for q in range(4):
+            sd = (q & 1, (q >> 1) & 1)
+            bits = (sd[0] << o[0]) | (sd[1] << o[1])
+            m0, m1 = bits, bits | (1 << ax_)
+            polys.append(np.array([corners[m0], corners[m1]]))
+            ends.append([m0, m1])
+            pat.append(sorted([face_of[(o[0], sd[0])], face_of[(o[1], sd[1])]]))
+    off = np.arange(0, 2 * 12 + 1, 2, dtype=np.int32)
+    gn = [n_grid] * 3
+    ax = [np.arange(n_grid) / (n_grid - 1) for _ in range(3)]
+    Z, Y, X = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
+    level = dict(phi=np.ascontiguousarray(phi_fn(X.ravel(), Y.ravel(), Z.ravel())), n=gn,
+                 lo=[0.0, 0.0, 0.0], hi=[1.0, 1.0, 1.0],
+                 curves=dict(off=off, pts=np.concatenate(polys, 0),
+                             ends=np.array(ends, np.int32), corners=corners,
+                             n_patches=6, patches=np.array(pat, np.int32)))
+    types = np.asarray([VOL] + [SURF] * 6 + [CURVE] * 12 + [SI] * 8, np.int32)
+    holes = np.zeros((0, 15))
+    base = dict(kind=H_LINEAR_FROM_POINT, h0=0.012, grad=0.04, dcap=np.inf,
+                point=list(corners[0]))
+    # the faces as (normal axis, side), in patch order
+    faces = sorted(face_of, key=lambda k: face_of[k])
+    u = a0 + (a1 - a0) * (np.arange(res) + 0.5) / res
+
+    def face_pts(axis, side, uu):
+        o = [b for b in range(3) if b != axis]
+        A, B = np.meshgrid(uu, uu, indexing="ij")
+        p = np.zeros((A.size, 3))
+        p[:, o[0]], p[:, o[1]] = A.ravel(), B.ravel()
+        p[:, axis] = a1 if side else a0
+        return p
+
+    def masses(sz):
+        Xg, Yg, Zg = np.meshgrid(u, u, u, indexing="ij")
+        P = np.stack([Xg.ravel(), Yg.ravel(), Zg.ravel()], 1)
+        w3, w2, w1 = ((a1 - a0) / res) ** 3, ((a1 - a0) / res) ** 2, (a1 - a0) / (4 * res)
+        M = {0: float(np.sum(_h_field(P, dim, sz, holes) ** -3.0)) * w3}
+        for f, (axis, side) in enumerate(faces):
+            M[1 + f] = float(np.sum(_h_field(face_pts(axis, side, u), dim, sz, holes) ** -2.0)) * w2
+        t = (np.arange(4 * res) + 0.5) / (4 * res)
+        for c, poly in enumerate(polys):
+            pts_ = poly[0] + t[:, None] * (poly[1] - poly[0])
+            M[7 + c] = float(np.sum(_h_field(pts_, dim, sz, holes) ** -1.0)) * w1
+        return M
+
+    M = masses(base)
+    sc = _solve_scale(M, types, n_total, dim)
+    sizing = dict(base, h0=base["h0"] * sc, grad=base["grad"] * sc)
+    counts = _split_counts(M, types, sc, n_total, dim)
+    rng = np.random.Generator(np.random.MT19937(seed))
+    hmin = sizing["h0"]
+
+    def vol_prop(m):
+        return a0 + (a1 - a0) * rng.random((m, 3))
+
+    def face_prop(axis, side):
+        def prop(m):
+            p = a0 + (a1 - a0) * rng.random((m, 3))
+            p[:, axis] = a1 if side else a0
+            return p
+        return prop
+
+    def edge_prop(poly):
+        def prop(m):
+            return poly[0] + rng.random(m)[:, None] * (poly[1] - poly[0])
+        return prop
+
+    xyz, feat = [], []
+    jobs = [(vol_prop, 3)] + [(face_prop(*fc), 2) for fc in faces] + [(edge_prop(p_), 1) for p_ in polys]
+    for f, (prop, k) in enumerate(jobs):
+        p = _sample_rejection(rng, counts[f], prop, dim, sizing, holes, k, hmin,
+                              accept_mask=(lambda q: _level_eval(level, dim, q)[0] > 0)
+                              if f == 0 else None)
+        xyz.append(p)
+        feat.append(np.full(len(p), f, np.int32))
+    xyz.append(corners)
+    feat.append(np.arange(19, 27, dtype=np.int32))
+    xyz = np.ascontiguousarray(np.concatenate(xyz, 0))
+    feat = np.ascontiguousarray(np.concatenate(feat))
+    assert xyz.shape[0] == n_total, (xyz.shape, n_total)
+    return Workload(name="level_cube_sharp", dim=3, lo=lo, hi=hi, holes=holes, sizing=sizing,
+                    params=default_params(**pover), xyz=xyz, feature=feat, ftype=types,
+                    counts=counts, scale=sc, steps=0, domain=2, level=level)
+
+
 def _hmin(sizing, dim, lo, hi, holes):
     """a lower bound of h over the domain (rejection sampling's envelope):
     every sizing kind here is h0 plus a non-negative term"""
