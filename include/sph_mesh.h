@@ -98,26 +98,39 @@ typedef struct {
                                 the cell of x */
   int32_t phi_n[3];
   double phi_lo[3], phi_hi[3];
-  /* SPH_DOMAIN_LEVEL_SET in 2D may import sharp features (sec. 2.1): feature
+  /* SPH_DOMAIN_LEVEL_SET may import sharp features (sec. 2.1): feature
    * curves as polylines and singular points.  Curve c has the points
    * curve_pts[3 k .. 3 k + 2], k in [curve_off[c], curve_off[c + 1]) (at
-   * least 2, consecutive points distinct), runs with the domain on its left,
-   * and ends at the corners curve_ends[2 c] (first point) and
+   * least 2, consecutive points distinct), in 2D runs with the domain on its
+   * left, and ends at the corners curve_ends[2 c] (first point) and
    * curve_ends[2 c + 1] (last point), -1 for none; corners[3 m ..] is corner
-   * m.  Features are then 0 volume | 1 .. n_curves the curves | the corners,
-   * in order (no zero-level-set feature).  A curve particle is mapped to the
-   * closest point of its own polyline (the first segment on ties) and moves
-   * along that segment; the volume's normal at it is the segment's right
-   * normal; at a corner, the normalised sum of the right normals of the end
-   * segments meeting there; a curve's normal at its end corner runs along
-   * its end segment, away from the curve.  n_curves = 0: no imported
-   * features.  All arrays are host memory, copied by the library. */
+   * m.  A curve particle is mapped to the closest point of its own polyline
+   * (the first segment on ties) and moves along that segment; a curve's
+   * normal at its end corner runs along its end segment, away from the
+   * curve.  n_curves = 0: no imported features.  All arrays are host memory,
+   * copied by the library.
+   * 2D: features 0 volume | 1 .. n_curves the curves | the corners (no
+   * zero-level-set feature); the volume's normal at a curve particle is the
+   * segment's right normal; at a corner, the normalised sum of the right
+   * normals of the end segments meeting there.  n_patches must be 0.
+   * 3D: the curves split the zero set into n_patches >= 1 surface patches
+   * (sph_tags finds them); curve c lies between patches curve_patches[2 c]
+   * and curve_patches[2 c + 1] (-1 for none).  Features: 0 volume |
+   * 1 .. n_patches the patches | the curves | the corners.  A patch particle
+   * is mapped onto phi = 0 as above; a patch is bounded by the curves beside
+   * it and their end corners, with the normal
+   * (I - t t^T)(I - m m^T)(x_b - x_i), normalised (m the patch's unit normal
+   * at the particle x_i, t the unit tangent of b's closest segment; at a
+   * corner without the t part); the volume's normal at a curve or corner
+   * particle is -grad / |grad| of phi there. */
   int32_t n_curves;
   const int32_t *curve_off;
   const double *curve_pts;
   const int32_t *curve_ends;
   int32_t n_corners;
   const double *corners;
+  int32_t n_patches;
+  const int32_t *curve_patches;
 } sph_geometry;
 
 /* Target feature size h_t(x) (paper sec. 2.2):
@@ -275,6 +288,32 @@ sph_status sph_job_setup(const sph_geometry *geometry, const sph_sizing *sizing,
                          double *grad_scaled, int64_t *counts, int32_t counts_cap,
                          int32_t *n_features, double *xyz, int32_t *feature, int64_t capacity,
                          int64_t *n_out);
+
+/* sph_tags -- the tag system of a level-set domain's background grid
+ * (sec. 3.2), host only (no GPU call).  The cells lie between the nodes of
+ * phi, (phi_n[0] - 1) x (phi_n[1] - 1) x (phi_n[2] - 1 in 3D, else 1), x
+ * fastest; ctype and cindex (caller-owned host arrays of that many int32)
+ * receive per cell:
+ *   ctype  0 negative (C-), 1 positive (C+), 2 surface (C_s), 3 curve (C_c),
+ *          4 singular (C_si);
+ *   cindex the index within its type (volume, patch, curve, corner), -1 for
+ *          a negative cell.
+ * A cell is positive when phi > 0 at all its nodes, negative when phi < 0 at
+ * all of them, surface otherwise.  A curve marks the cells of points along
+ * each segment (ceil(length / (s / 4)) steps, s the smallest cell side, both
+ * ends included) and their face neighbours; a corner its cell and all its
+ * neighbours.  The first curve (corner) in order keeps a cell; corners win
+ * over curves.  The remaining surface cells form patches, the positive cells
+ * volumes: components under face adjacency, numbered in the order of their
+ * first cell.  curve_patches[2 c], [2 c + 1] (2 n_curves int32, may be NULL
+ * when n_curves = 0) receive the patches with a cell face-adjacent to a cell
+ * of curve c, ascending, -1 for none, -2 in [2 c] for more than two; *n_volumes
+ * and *n_patches the counts.  In 3D the geometry's own n_patches and
+ * curve_patches may be unset (0 / NULL): the result is how to set them.
+ * Errors: SPH_ERR_INVALID_ARG for a bad geometry, a domain other than
+ * SPH_DOMAIN_LEVEL_SET or a NULL output. */
+sph_status sph_tags(const sph_geometry *geometry, int32_t *ctype, int32_t *cindex,
+                    int32_t *n_volumes, int32_t *n_patches, int32_t *curve_patches);
 
 /* sph_mesh_create_with_particles -- the same set-up with the caller's
  * initial particles: n particles at xyz (n x 3) with feature index

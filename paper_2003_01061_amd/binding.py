@@ -25,7 +25,8 @@ class Geometry(C.Structure):
                 ("phi_n", C.c_int32 * 3), ("phi_lo", C.c_double * 3), ("phi_hi", C.c_double * 3),
                 ("n_curves", C.c_int32), ("curve_off", C.POINTER(C.c_int32)),
                 ("curve_pts", C.POINTER(C.c_double)), ("curve_ends", C.POINTER(C.c_int32)),
-                ("n_corners", C.c_int32), ("corners", C.POINTER(C.c_double))]
+                ("n_corners", C.c_int32), ("corners", C.POINTER(C.c_double)),
+                ("n_patches", C.c_int32), ("curve_patches", C.POINTER(C.c_int32))]
 
 
 class Sizing(C.Structure):
@@ -94,6 +95,8 @@ def lib():
                                     C.POINTER(C.c_double), C.POINTER(C.c_double),
                                     C.POINTER(C.c_double), vp, C.c_int32, C.POINTER(C.c_int32),
                                     vp, vp, C.c_int64, C.POINTER(C.c_int64)]
+        L.sph_tags.argtypes = [C.POINTER(Geometry), vp, vp, C.POINTER(C.c_int32),
+                               C.POINTER(C.c_int32), vp]
         L.sph_mesh_step.argtypes = [vp, C.c_int32]
         L.sph_mesh_positions.argtypes = [vp, vp, vp, C.c_int64, C.POINTER(C.c_int64)]
         L.sph_mesh_error.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int32),
@@ -179,6 +182,11 @@ def make_geometry(dim, lo, hi, holes, domain=0, level=None):
             g.n_corners = cor.shape[0]
             g.corners = cor.ctypes.data_as(C.POINTER(C.c_double))
             g._keep_curves = (off, pts, ends, cor)
+            if "patches" in cv:
+                cp = np.ascontiguousarray(np.asarray(cv["patches"], np.int32).reshape(-1, 2))
+                g.n_patches = int(cv["n_patches"])
+                g.curve_patches = cp.ctypes.data_as(C.POINTER(C.c_int32))
+                g._keep_patches = cp
     return g
 
 
@@ -472,6 +480,25 @@ def job_setup(dim, lo, hi, holes, sizing, params, domain=0, particles=True):
     return out
 
 
+def tags(dim, level):
+    """sph_tags (host only): the cell tag system of a level-set domain with
+    the description level (phi, n, lo, hi and optional curves): per cell
+    (z, y, x) its type and feature index, the volume and patch counts and
+    the two patches beside each curve."""
+    L = lib()
+    g = make_geometry(dim, [0, 0, 0], [1, 1, 1], np.zeros((0, 15)), 2, level)
+    nc = [int(level["n"][a]) - 1 if a < dim else 1 for a in range(3)]
+    ct = np.empty(nc[0] * nc[1] * nc[2], np.int32)
+    ci = np.empty_like(ct)
+    ncv = int(g.n_curves)
+    cp = np.full(2 * max(ncv, 1), -1, np.int32)
+    nv, npch = C.c_int32(), C.c_int32()
+    _check("sph_tags", L.sph_tags(C.byref(g), ct.ctypes.data, ci.ctypes.data, C.byref(nv),
+                                  C.byref(npch), cp.ctypes.data))
+    shape = (nc[2], nc[1], nc[0])
+    return ct.reshape(shape), ci.reshape(shape), nv.value, npch.value, cp[:2 * ncv].reshape(-1, 2)
+
+
 def batch_footprint(**kw):
     """Device bytes of a batch with these capacities (-1 if invalid)."""
     bp = batch_params(**kw)
@@ -579,7 +606,7 @@ def control_replay_noalloc(params, n, vbar, dt, phase, reset, e_sys, stream=None
 def exported_symbols():
     """Names the header declares (checked by the CPU test of the ABI)."""
     return ["sph_mesh_create", "sph_mesh_create_with_particles", "sph_mesh_setup_info",
-            "sph_job_setup",
+            "sph_job_setup", "sph_tags",
             "sph_mesh_step", "sph_mesh_positions", "sph_mesh_error",
             "sph_mesh_destroy", "sph_mesh_last_error", "sph_mesh_set_state", "sph_mesh_velocities",
             "sph_mesh_neighbors", "sph_mesh_neighbors_of", "sph_mesh_field", "sph_mesh_group_state", "sph_mesh_counters",

@@ -13,6 +13,7 @@ LIB = os.path.join(HERE, "libsphmesh.so")
 SOURCES = [os.path.join(HERE, "csrc", "sph_mesh.hip")]
 DEPS = SOURCES + [os.path.join(HERE, "csrc", "sph_device.h"), os.path.join(HERE, "csrc", "sph_kernels.h"),
                   os.path.join(HERE, "csrc", "sph_setup.h"),
+                  os.path.join(HERE, "csrc", "sph_tags.h"),
                   os.path.join(ROOT, "include", "sph_mesh.h")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("SPH_OFFLOAD_ARCH", "gfx950")

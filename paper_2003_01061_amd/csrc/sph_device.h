@@ -47,8 +47,10 @@ struct Feat {
 
 // outward normal n_b of feature fi's boundary at a particle of feature fb
 // (paper sec. 3.3): mode 0 no relation, 1 the constant vector n; 2 (a ball
-// hole), 3 (an ellipsoidal hole) and 4 (the ball domain's sphere) the
-// particle's own normal out of the domain, which k_rank_gather stores
+// hole), 3 (an ellipsoidal hole), 4 (the ball domain's sphere), 5 (the zero
+// level set) and 6 (an imported curve) the particle's own normal out of the
+// domain, which k_rank_gather stores; 7 (a 3D patch at a curve beside it) and
+// 8 (at a vertex) depend on the pair and are computed in the sweep
 struct BNorm {
   int32_t mode, hole;
   double n[3];
@@ -76,41 +78,47 @@ struct Geom {
   const int32_t *coff;      // curve c owns the points [coff[c], coff[c + 1])
 };
 
-// imported curve c (a polyline, domain on its left): the segment whose
-// closest point to x is nearest (the first on ties), that point in q
+// imported curve c (a polyline; in 2D with the domain on its left): the
+// segment whose closest point to x is nearest (the first on ties), that
+// point in q (D components)
+template <int D>
 __host__ __device__ __forceinline__ int poly_closest(const Geom &g, int c, const double *x, double *q) {
   // start from the first point, so that a segment is returned even when no
   // distance compares (a non-finite x)
   int best = g.coff[c];
-  q[0] = g.cpts[3 * best];
-  q[1] = g.cpts[3 * best + 1];
+  for (int a = 0; a < D; ++a) q[a] = g.cpts[3 * best + a];
   double bd = __builtin_inf();
   for (int k = g.coff[c]; k + 1 < g.coff[c + 1]; ++k) {
     const double *p0 = g.cpts + 3 * k, *p1 = g.cpts + 3 * (k + 1);
-    const double e0 = p1[0] - p0[0], e1 = p1[1] - p0[1];
-    const double ee = e0 * e0 + e1 * e1;
-    double t = ee > 0.0 ? ((x[0] - p0[0]) * e0 + (x[1] - p0[1]) * e1) / ee : 0.0;
+    const double e0 = p1[0] - p0[0], e1 = p1[1] - p0[1], e2 = D == 3 ? p1[2] - p0[2] : 0.0;
+    const double ee = D == 3 ? e0 * e0 + e1 * e1 + e2 * e2 : e0 * e0 + e1 * e1;
+    const double xe = D == 3 ? (x[0] - p0[0]) * e0 + (x[1] - p0[1]) * e1 + (x[2] - p0[2]) * e2
+                             : (x[0] - p0[0]) * e0 + (x[1] - p0[1]) * e1;
+    double t = ee > 0.0 ? xe / ee : 0.0;
     t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
-    const double c0 = p0[0] + t * e0, c1 = p0[1] + t * e1;
-    const double d0 = x[0] - c0, d1 = x[1] - c1;
-    const double d = d0 * d0 + d1 * d1;
+    const double c0 = p0[0] + t * e0, c1 = p0[1] + t * e1, c2 = D == 3 ? p0[2] + t * e2 : 0.0;
+    const double d0 = x[0] - c0, d1 = x[1] - c1, d2 = D == 3 ? x[2] - c2 : 0.0;
+    const double d = D == 3 ? d0 * d0 + d1 * d1 + d2 * d2 : d0 * d0 + d1 * d1;
     if (d < bd) {
       bd = d;
       best = k;
       q[0] = c0;
       q[1] = c1;
+      if (D == 3) q[D - 1] = c2;
     }
   }
   return best;
 }
 
-// unit tangent of segment k of the imported curves
+// unit tangent of segment k of the imported curves (D components)
+template <int D>
 __host__ __device__ __forceinline__ void seg_tangent(const Geom &g, int k, double *t) {
   const double *p0 = g.cpts + 3 * k, *p1 = g.cpts + 3 * (k + 1);
-  const double e0 = p1[0] - p0[0], e1 = p1[1] - p0[1];
-  const double l = __builtin_sqrt(e0 * e0 + e1 * e1);
+  const double e0 = p1[0] - p0[0], e1 = p1[1] - p0[1], e2 = D == 3 ? p1[2] - p0[2] : 0.0;
+  const double l = __builtin_sqrt(D == 3 ? e0 * e0 + e1 * e1 + e2 * e2 : e0 * e0 + e1 * e1);
   t[0] = e0 / l;
   t[1] = e1 / l;
+  if (D == 3) t[D - 1] = e2 / l;
 }
 
 // the gridded level set of a level-set domain: phi multilinear in the grid
@@ -694,12 +702,19 @@ __host__ __device__ __forceinline__ void tangent(const Geom &g, const Feat &F, c
       return;
     }
     case K_POLY: {    // an imported curve: keep the part along the closest segment
-      double q[2], t[2];
-      seg_tangent(g, poly_closest(g, F.hole, x, q), t);
-      const double ut = u[0] * t[0] + u[1] * t[1];
-      u[0] = ut * t[0];
-      u[1] = ut * t[1];
-      u[2] = 0.0;
+      double q[D], t[D];
+      seg_tangent<D>(g, poly_closest<D>(g, F.hole, x, q), t);
+      if (D == 2) {
+        const double ut = u[0] * t[0] + u[1] * t[1];
+        u[0] = ut * t[0];
+        u[1] = ut * t[1];
+        u[2] = 0.0;
+      } else {
+        const double ut = u[0] * t[0] + u[1] * t[1] + u[2] * t[D - 1];
+        u[0] = ut * t[0];
+        u[1] = ut * t[1];
+        u[2] = ut * t[D - 1];
+      }
       return;
     }
     case K_LEVEL: {   // the zero level set: normal from the gradient
@@ -780,10 +795,9 @@ __host__ __device__ __forceinline__ void project(const Geom &g, const Feat &F, d
       for (int a = 0; a < D; ++a) x[a] = ((F.bits >> a) & 1) ? g.hi[a] : g.lo[a];
       return;
     case K_POLY: {   // the closest point of the particle's own polyline
-      double q[2];
-      (void)poly_closest(g, F.hole, x, q);
-      x[0] = q[0];
-      x[1] = q[1];
+      double q[D];
+      (void)poly_closest<D>(g, F.hole, x, q);
+      for (int a = 0; a < D; ++a) x[a] = q[a];
       return;
     }
     case K_LEVEL:   // 12 Newton steps along the gradient onto phi = 0

@@ -346,12 +346,20 @@ __global__ __launch_bounds__(BLOCK) void k_rank_gather(Batch B, int n, const uin
   // set's gradient for an ellipse or ellipsoid
   if (B.has_hole) {
     const Feat F = B.feat[f];
-    if (F.kind == K_POLY) {   // an imported curve: the closest segment's right normal
+    if (F.kind == K_POLY && D == 2) {   // an imported curve: the closest segment's right normal
       const Geom &gg = B.jobs[f / MAXF].g;
       const double x[3] = {xh.x, xh.y, xh.z};
       double q[2], t[2];
-      seg_tangent(gg, poly_closest(gg, F.hole, x, q), t);
+      seg_tangent<2>(gg, poly_closest<2>(gg, F.hole, x, q), t);
       B.enrm[dst] = make_double4(t[1], -t[0], 0.0, 0.0);
+    } else if (F.kind == K_POLY) {   // a 3D curve on the zero set: towards decreasing
+                                      // phi, and its closest segment in w
+      const Geom &gg = B.jobs[f / MAXF].g;
+      const double x[3] = {xh.x, xh.y, xh.z};
+      double q[3], m[3];
+      const int k = poly_closest<3>(gg, F.hole, x, q);
+      ls_unit<3>(gg, x, m);
+      B.enrm[dst] = make_double4(-m[0], -m[1], -m[2], (double)k);
     } else if (F.kind == K_LEVEL) {   // the zero level set: towards decreasing phi
       const double x[3] = {xh.x, xh.y, xh.z};
       double m[3];
@@ -393,8 +401,8 @@ __host__ __device__ __forceinline__ void sweep_a_sums(const Geom &g, const Parts
                                              const BNorm *__restrict__ bnrow, int bw, double p0,
                                              double klen, double bscale,
                                              const uint32_t *__restrict__ nbr, int n, int i,
-                                             uint32_t cnt, const double4 &xi, int fi, double &S,
-                                             double &gam, double Pi[3], double B[3]) {
+                                             uint32_t cnt, const double4 &xi, int fi, bool pair_normals,
+                                             double &S, double &gam, double Pi[3], double B[3]) {
   // h enters rho_t = h^-k; the kernel is evaluated at the smoothing length
   // klen h (cut-off radius 2 klen h)
   const R hi = (R)xi.w;
@@ -454,6 +462,7 @@ __host__ __device__ __forceinline__ void sweep_a_sums(const Geom &g, const Parts
           const int fj = s.f[u[q] & 0x7fffffffu];
           const BNorm N = bnrow[fj & (MAXF - 1)];
           double nv[3];
+          if (D == 3 && N.mode >= 7) continue;   // normal of the pair: the pass below
           if (N.mode >= 2) {   // a curved boundary: the normal k_rank_gather stored
             const double4 e = enrm[u[q] & 0x7fffffffu];
             nv[0] = e.x;
@@ -477,6 +486,59 @@ __host__ __device__ __forceinline__ void sweep_a_sums(const Geom &g, const Parts
             aB[1].add(c * nv[1]);
             if (D == 3) aB[2].add(c * nv[2]);
           }
+        }
+      }
+    }
+  }
+  if constexpr (D == 3) {
+    // A 3D surface patch at a curve (mode 7) or vertex (8) beside it: the
+    // normal is the direction to b within i's tangent plane (i's stored
+    // normal removed), at a curve also without the part along b's closest
+    // segment, normalised.  Only patch particles of a geometry with imported
+    // curves take this pass, which keeps its registers out of the main loop.
+    if (pair_normals) {
+      const double4 ei = enrm[i];
+      for (uint32_t e = 0; e < cnt; ++e) {
+        const uint32_t v = nbr[((size_t)(e / LB) * n + i) * LB + e % LB];
+        if (!(v >> 31)) continue;
+        const uint32_t b = v & 0x7fffffffu;
+        const BNorm N = bnrow[s.f[b] & (MAXF - 1)];
+        if (N.mode < 7) continue;
+        const double4 xj = s.xh[b];
+        const R dx0 = (R)(xi.x - xj.x), dx1 = (R)(xi.y - xj.y), dx2 = (R)(xi.z - xj.z);
+        const R rr = sqrt_(dx0 * dx0 + dx1 * dx1 + dx2 * dx2);
+        double d0 = xj.x - xi.x, d1 = xj.y - xi.y, d2 = xj.z - xi.z;
+        const double dm = d0 * ei.x + d1 * ei.y + d2 * ei.z;
+        d0 -= dm * ei.x;
+        d1 -= dm * ei.y;
+        d2 -= dm * ei.z;
+        if (N.mode == 7) {
+          double t[3];
+          seg_tangent<3>(g, (int)enrm[b].w, t);
+          const double dt = d0 * t[0] + d1 * t[1] + d2 * t[2];
+          d0 -= dt * t[0];
+          d1 -= dt * t[1];
+          d2 -= dt * t[2];
+        }
+        const double l = __builtin_sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+        const double il = l > 0.0 ? 1.0 / l : 0.0;
+        const double nv[3] = {d0 * il, d1 * il, d2 * il};
+        const R hj = (R)xj.w;
+        const R hjk = powK<K>(hj);
+        const R hsum = hi2k + hjk * hjk;
+        const R ihij = rcp_(kl * (R(0.5) * (hi + hj)));
+        const R om = (bw == 0 ? rcp_(hj) : (bw == 1 ? powK<K>(hj) * rcp_(hj) : R(0))) * (R)bscale;
+        const R w = alpha * wshapeK<K>(rr * ihij) * powK<K>(ihij);      // W(r, h_ib)
+        if constexpr (CMP) {
+          const float c = (float)(P0 * hsum * w * om);
+          aB[0].add(c * (float)nv[0]);
+          aB[1].add(c * (float)nv[1]);
+          aB[2].add(c * (float)nv[2]);
+        } else {
+          const double c = (double)(P0 * hsum * w * om);
+          aB[0].add(c * nv[0]);
+          aB[1].add(c * nv[1]);
+          aB[2].add(c * nv[2]);
         }
       }
     }
@@ -709,13 +771,15 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
         s.v[i] = v4;
       }
       const BNorm *bnrow = B.bn + (size_t)fi * MAXF;
+      // a 3D patch of a level set with imported curves: pair-dependent normals
+      const bool pairn = D == 3 && F.kind == K_LEVEL && J.g.cpts != nullptr;
       double S, gam, Pi[3], B3[3];
       if (k == D)
-        sweep_a_sums<D, D, R, CMP>(J.g, s, B.enrm, bnrow, J.bw, J.p0, J.klen, J.bscale, nbr, n, i, count, xi, fi, S, gam, Pi, B3);
+        sweep_a_sums<D, D, R, CMP>(J.g, s, B.enrm, bnrow, J.bw, J.p0, J.klen, J.bscale, nbr, n, i, count, xi, fi, pairn, S, gam, Pi, B3);
       else if (k == D - 1)
-        sweep_a_sums<D, D - 1, R, CMP>(J.g, s, B.enrm, bnrow, J.bw, J.p0, J.klen, J.bscale, nbr, n, i, count, xi, fi, S, gam, Pi, B3);
+        sweep_a_sums<D, D - 1, R, CMP>(J.g, s, B.enrm, bnrow, J.bw, J.p0, J.klen, J.bscale, nbr, n, i, count, xi, fi, pairn, S, gam, Pi, B3);
       else
-        sweep_a_sums<D, 1, R, CMP>(J.g, s, B.enrm, bnrow, J.bw, J.p0, J.klen, J.bscale, nbr, n, i, count, xi, fi, S, gam, Pi, B3);
+        sweep_a_sums<D, 1, R, CMP>(J.g, s, B.enrm, bnrow, J.bw, J.p0, J.klen, J.bscale, nbr, n, i, count, xi, fi, pairn, S, gam, Pi, B3);
       double a3[3] = {0.0, 0.0, 0.0};
 #pragma unroll
       for (int a = 0; a < D; ++a) a3[a] = -((Pi[a] + B3[a]) / gam);

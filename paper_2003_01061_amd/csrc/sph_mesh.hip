@@ -64,10 +64,12 @@ const char *kKernelNames[KID_COUNT] = {
 struct HFeat {
   int type, k, kind, axis = 0, side = 0, fax[2] = {0, 0}, fsd[2] = {0, 0}, hole = 0, bits = 0;
   int ell = 0;   // HOLE: the hole is an ellipsoid
-  // POLY: the corners at the first and last point (-1: none) and the unit
-  // tangents of the first and last segments; PCORNER: the volume's normal
-  int end[2] = {-1, -1};
-  double t_first[2] = {0.0, 0.0}, t_last[2] = {0.0, 0.0}, n_vol[2] = {0.0, 0.0};
+  // POLY: the corners at the first and last point (-1: none), the unit
+  // tangents of the first and last segments and (3D) the patches beside it;
+  // PCORNER: the volume's normal and (3D) the patches its curves lie beside
+  int end[2] = {-1, -1}, pat[2] = {-1, -1};
+  double t_first[3] = {0.0, 0.0, 0.0}, t_last[3] = {0.0, 0.0, 0.0}, n_vol[3] = {0.0, 0.0, 0.0};
+  unsigned long long pmask = 0ull;
 };
 
 std::vector<HFeat> make_features(int D, int nh, int domain) {
@@ -112,43 +114,80 @@ std::vector<HFeat> make_features(int D, int nh, int domain) {
   return F;
 }
 
-// the features of a geometry, with the imported curves and corners of a 2D
-// level-set domain and the constant data their normals need
+// the features of a geometry, with the imported curves and corners of a
+// level-set domain (and in 3D the surface patches the curves split its zero
+// set into) and the constant data their normals need
 std::vector<HFeat> make_features_of(const sph_geometry *g) {
   if (g->domain != SPH_DOMAIN_LEVEL_SET || g->n_curves <= 0)
     return make_features(g->dim, g->n_holes, g->domain);
+  const int D = g->dim, np = D == 3 ? g->n_patches : 0;
   std::vector<HFeat> F;
-  F.push_back({T_V, 2, K_VOL});
+  F.push_back({T_V, D, K_VOL});
+  for (int p = 0; p < np; ++p) {   // patches: the zero set's projection and normal
+    HFeat f{T_S, 2, K_LEVEL};
+    f.hole = p;
+    F.push_back(f);
+  }
   auto tangent_of = [&](int k, double *t) {
     const double *p0 = g->curve_pts + 3 * k, *p1 = g->curve_pts + 3 * (k + 1);
-    const double e0 = p1[0] - p0[0], e1 = p1[1] - p0[1], l = std::sqrt(e0 * e0 + e1 * e1);
-    t[0] = e0 / l;
-    t[1] = e1 / l;
+    double e[3] = {0.0, 0.0, 0.0}, ss = 0.0;
+    for (int a = 0; a < D; ++a) {
+      e[a] = p1[a] - p0[a];
+      ss += e[a] * e[a];
+    }
+    const double l = std::sqrt(ss);
+    for (int a = 0; a < D; ++a) t[a] = e[a] / l;
   };
+  const int c0 = 1 + np;   // the first curve's feature
   for (int c = 0; c < g->n_curves; ++c) {
     HFeat f{T_C, 1, K_POLY};
     f.hole = c;
     f.end[0] = g->curve_ends[2 * c];
     f.end[1] = g->curve_ends[2 * c + 1];
+    if (np > 0) {
+      f.pat[0] = g->curve_patches[2 * c];
+      f.pat[1] = g->curve_patches[2 * c + 1];
+    }
     tangent_of(g->curve_off[c], f.t_first);
     tangent_of(g->curve_off[c + 1] - 2, f.t_last);
     F.push_back(f);
   }
+  // the level set's geometry on the host, for the normal at a 3D vertex
+  Geom hg{};
+  hg.dim = D;
+  hg.phi = g->phi;
+  for (int a = 0; a < 3; ++a) {
+    hg.pn[a] = a < D ? g->phi_n[a] : 1;
+    hg.plo[a] = g->phi_lo[a];
+    hg.ps[a] = a < D ? (double)(g->phi_n[a] - 1) / (g->phi_hi[a] - g->phi_lo[a]) : 0.0;
+  }
   for (int m = 0; m < g->n_corners; ++m) {
     HFeat f{T_SI, 0, K_PCORNER};
     f.hole = m;
-    double s0 = 0.0, s1 = 0.0;
-    for (int c = 0; c < g->n_curves; ++c)
-      for (int e = 0; e < 2; ++e) {
-        if (F[1 + c].end[e] != m) continue;
-        const double *t = e == 0 ? F[1 + c].t_first : F[1 + c].t_last;
-        s0 += t[1];   // the right normal (t1, -t0)
-        s1 -= t[0];
+    for (int c = 0; c < g->n_curves; ++c) {
+      const HFeat &C = F[c0 + c];
+      if (C.end[0] != m && C.end[1] != m) continue;
+      for (int e = 0; e < 2; ++e)
+        if (C.pat[e] >= 0) f.pmask |= 1ull << C.pat[e];
+    }
+    if (D == 3) {   // towards decreasing phi at the vertex
+      double mv[3];
+      ls_unit<3>(hg, g->corners + 3 * m, mv);
+      for (int a = 0; a < 3; ++a) f.n_vol[a] = -mv[a];
+    } else {   // the normalised sum of the right normals of the end segments
+      double s0 = 0.0, s1 = 0.0;
+      for (int c = 0; c < g->n_curves; ++c)
+        for (int e = 0; e < 2; ++e) {
+          if (F[c0 + c].end[e] != m) continue;
+          const double *t = e == 0 ? F[c0 + c].t_first : F[c0 + c].t_last;
+          s0 += t[1];   // the right normal (t1, -t0)
+          s1 -= t[0];
+        }
+      const double l = std::sqrt(s0 * s0 + s1 * s1);
+      if (l > 0.0) {
+        f.n_vol[0] = s0 / l;
+        f.n_vol[1] = s1 / l;
       }
-    const double l = std::sqrt(s0 * s0 + s1 * s1);
-    if (l > 0.0) {
-      f.n_vol[0] = s0 / l;
-      f.n_vol[1] = s1 / l;
     }
     F.push_back(f);
   }
@@ -160,6 +199,11 @@ bool on_boundary_of(const HFeat &A, const HFeat &B) {
   if (B.k >= A.k) return false;
   if (A.kind == K_VOL) return true;
   if (A.kind == K_POLY) return B.kind == K_PCORNER && (A.end[0] == B.hole || A.end[1] == B.hole);
+  if (A.kind == K_LEVEL) {   // a 3D patch: the curves beside it and their end vertices
+    if (B.kind == K_POLY) return B.pat[0] == A.hole || B.pat[1] == A.hole;
+    if (B.kind == K_PCORNER) return ((B.pmask >> A.hole) & 1ull) != 0;
+    return false;
+  }
   if (A.kind == K_BOXSIDE) {
     if (B.kind == K_CORNER) return ((B.bits >> A.axis) & 1) == A.side;
     if (B.kind == K_EDGE3)
@@ -188,10 +232,10 @@ BNorm boundary_normal(int D, const HFeat &A, const HFeat &B) {
     } else if (B.kind == K_LEVEL) {
       N.mode = 5;   // against the level set's gradient, stored per particle
     } else if (B.kind == K_POLY) {
-      N.mode = 6;   // the closest segment's right normal, stored per particle
+      N.mode = 6;   // stored per particle: in 2D the closest segment's right
+                    // normal, in 3D against the level set's gradient
     } else if (B.kind == K_PCORNER) {
-      N.n[0] = B.n_vol[0];
-      N.n[1] = B.n_vol[1];
+      for (int a = 0; a < 3; ++a) N.n[a] = B.n_vol[a];
     } else if (B.kind == K_EDGE3) {
       const double r = std::sqrt(0.5);
       N.n[B.fax[0]] = sg(B.fsd[0]) * r;
@@ -215,13 +259,9 @@ BNorm boundary_normal(int D, const HFeat &A, const HFeat &B) {
   } else if (A.kind == K_EDGE3) {
     N.n[A.axis] = sg((B.bits >> A.axis) & 1);
   } else if (A.kind == K_POLY) {   // along the end segment, away from the curve
-    if (A.end[0] == B.hole) {
-      N.n[0] = -A.t_first[0];
-      N.n[1] = -A.t_first[1];
-    } else {
-      N.n[0] = A.t_last[0];
-      N.n[1] = A.t_last[1];
-    }
+    for (int a = 0; a < 3; ++a) N.n[a] = A.end[0] == B.hole ? -A.t_first[a] : A.t_last[a];
+  } else if (A.kind == K_LEVEL) {   // a patch: depends on the pair, computed in the sweep
+    N.mode = B.kind == K_POLY ? 7 : 8;
   }
   return N;
 }
@@ -268,8 +308,8 @@ static bool hole_is_ellipsoid(int D, const double *H) {
   return D == 2 ? H[4] != H[3] : (H[4] != H[3] || H[5] != H[3]);
 }
 
-static sph_status validate(const sph_geometry *g, const sph_sizing *s, const sph_params *p) {
-  if (!g || !s || !p) return fail(SPH_ERR_INVALID_ARG, "null geometry, sizing or params");
+static sph_status validate_geometry(const sph_geometry *g) {
+  if (!g) return fail(SPH_ERR_INVALID_ARG, "null geometry");
   if (g->dim != 2 && g->dim != 3) return fail(SPH_ERR_INVALID_ARG, "dim must be 2 or 3");
   for (int a = 0; a < g->dim; ++a)
     if (!(g->lo[a] < g->hi[a]) || !std::isfinite(g->lo[a]) || !std::isfinite(g->hi[a]))
@@ -318,24 +358,31 @@ static sph_status validate(const sph_geometry *g, const sph_sizing *s, const sph
       if (!std::isfinite(g->phi[k])) return fail(SPH_ERR_INVALID_ARG, "phi is not finite");
     if (g->n_curves < 0 || g->n_corners < 0) return fail(SPH_ERR_INVALID_ARG, "negative curve count");
     if (g->n_curves > 0) {
-      if (g->dim != 2) return fail(SPH_ERR_INVALID_ARG, "imported curves are 2D only");
+      const int np = g->dim == 3 ? g->n_patches : 0;
+      if (g->dim == 2 && g->n_patches != 0)
+        return fail(SPH_ERR_INVALID_ARG, "n_patches must be 0 in 2D");
+      if (g->dim == 3 && (g->n_patches < 1 || !g->curve_patches))
+        return fail(SPH_ERR_INVALID_ARG, "3D imported curves need n_patches >= 1 and curve_patches");
       if (!g->curve_off || !g->curve_pts || !g->curve_ends || (g->n_corners > 0 && !g->corners))
         return fail(SPH_ERR_INVALID_ARG, "imported curves: NULL array");
-      if (1 + g->n_curves + g->n_corners > MAXF)
+      if (1 + np + g->n_curves + g->n_corners > MAXF)
         return fail(SPH_ERR_UNSUPPORTED, "too many imported features");
       if (g->curve_off[0] != 0) return fail(SPH_ERR_INVALID_ARG, "curve_off[0] must be 0");
       for (int c = 0; c < g->n_curves; ++c) {
         const int a0 = g->curve_off[c], a1 = g->curve_off[c + 1];
         if (a1 - a0 < 2 || a1 > (1 << 24))
           return fail(SPH_ERR_INVALID_ARG, "curve %d needs 2 to 2^24 points", c);
-        for (int e = 0; e < 2; ++e)
+        for (int e = 0; e < 2; ++e) {
           if (g->curve_ends[2 * c + e] < -1 || g->curve_ends[2 * c + e] >= g->n_corners)
             return fail(SPH_ERR_INVALID_ARG, "curve %d: bad end corner", c);
+          if (np > 0 && (g->curve_patches[2 * c + e] < -1 || g->curve_patches[2 * c + e] >= np))
+            return fail(SPH_ERR_INVALID_ARG, "curve %d: bad patch", c);
+        }
         for (int k = a0; k < a1; ++k) {
           const double *pt = g->curve_pts + 3 * k;
-          if (!std::isfinite(pt[0]) || !std::isfinite(pt[1]))
-            return fail(SPH_ERR_INVALID_ARG, "curve %d: non-finite point", c);
-          if (k + 1 < a1 && pt[0] == pt[3] && pt[1] == pt[4])
+          for (int a = 0; a < g->dim; ++a)
+            if (!std::isfinite(pt[a])) return fail(SPH_ERR_INVALID_ARG, "curve %d: non-finite point", c);
+          if (k + 1 < a1 && pt[0] == pt[3] && pt[1] == pt[4] && (g->dim == 2 || pt[2] == pt[5]))
             return fail(SPH_ERR_INVALID_ARG, "curve %d: repeated point", c);
         }
       }
@@ -350,6 +397,12 @@ static sph_status validate(const sph_geometry *g, const sph_sizing *s, const sph
       if (!(std::fabs((g->hi[a] - g->lo[a]) - e0) <= 1e-12 * e0))
         return fail(SPH_ERR_INVALID_ARG, "a ball domain needs a cubic box");
   }
+  return SPH_OK;
+}
+
+static sph_status validate(const sph_geometry *g, const sph_sizing *s, const sph_params *p) {
+  if (!g || !s || !p) return fail(SPH_ERR_INVALID_ARG, "null geometry, sizing or params");
+  if (sph_status st = validate_geometry(g)) return st;
   if (s->kind < 0 || s->kind > 4) return fail(SPH_ERR_INVALID_ARG, "unknown sizing kind");
   if (s->kind == 4) {
     if (!s->grid) return fail(SPH_ERR_INVALID_ARG, "gridded sizing needs a grid");
@@ -775,6 +828,7 @@ struct sph_batch {
 };
 
 #include "sph_setup.h"
+#include "sph_tags.h"
 
 // ---------------------------------------------------------------------------
 // job description -> host job record
@@ -1554,6 +1608,29 @@ extern "C" sph_status sph_job_setup(const sph_geometry *g, const sph_sizing *s,
     if (xyz) std::memcpy(xyz, x.data(), sizeof(double) * x.size());
     if (feature) std::memcpy(feature, f.data(), sizeof(int32_t) * f.size());
   }
+  return SPH_OK;
+}
+
+// the tag system of a level-set domain's background grid (sec. 3.2)
+extern "C" sph_status sph_tags(const sph_geometry *g, int32_t *ctype, int32_t *cindex,
+                               int32_t *n_volumes, int32_t *n_patches, int32_t *curve_patches) {
+  if (!g) return fail(SPH_ERR_INVALID_ARG, "null geometry");
+  // the patches are what this finds: a 3D geometry may leave them unset
+  sph_geometry gg = *g;
+  std::vector<int32_t> unset;
+  if (gg.dim == 3 && gg.n_curves > 0 && (gg.n_patches < 1 || !gg.curve_patches)) {
+    unset.assign(2 * (size_t)gg.n_curves, -1);
+    gg.n_patches = 1;
+    gg.curve_patches = unset.data();
+  }
+  if (sph_status st = validate_geometry(&gg)) return st;
+  if (gg.domain != SPH_DOMAIN_LEVEL_SET)
+    return fail(SPH_ERR_INVALID_ARG, "the tag system needs a level-set domain");
+  if (!ctype || !cindex || !n_volumes || !n_patches || (gg.n_curves > 0 && !curve_patches))
+    return fail(SPH_ERR_INVALID_ARG, "NULL output");
+  tags::build(gg.dim, gg.phi_n, gg.phi_lo, gg.phi_hi, gg.phi, gg.n_curves, gg.curve_off,
+              gg.curve_pts, gg.n_corners, gg.corners, ctype, cindex, n_volumes, n_patches,
+              curve_patches);
   return SPH_OK;
 }
 

@@ -155,18 +155,19 @@ int main(int argc, char **argv) {
     const uint32_t cnt = (uint32_t)(off[t + 1] - off[t]);
     double S, gam, Pi[3], B3[3];
     const JobDev &JD = J.dev;
+    const bool pairn = D == 3 && F.kind == K_LEVEL && G.cpts != nullptr;
     if (D == 3) {
       if (F.k == 3)
-        sweep_a_sums<3, 3, double, false>(G, P, enrm.data(), bnrow, JD.bw, JD.p0, JD.klen, JD.bscale, nbr.data(), n, i, cnt, xh[i], fi, S, gam, Pi, B3);
+        sweep_a_sums<3, 3, double, false>(G, P, enrm.data(), bnrow, JD.bw, JD.p0, JD.klen, JD.bscale, nbr.data(), n, i, cnt, xh[i], fi, pairn, S, gam, Pi, B3);
       else if (F.k == 2)
-        sweep_a_sums<3, 2, double, false>(G, P, enrm.data(), bnrow, JD.bw, JD.p0, JD.klen, JD.bscale, nbr.data(), n, i, cnt, xh[i], fi, S, gam, Pi, B3);
+        sweep_a_sums<3, 2, double, false>(G, P, enrm.data(), bnrow, JD.bw, JD.p0, JD.klen, JD.bscale, nbr.data(), n, i, cnt, xh[i], fi, pairn, S, gam, Pi, B3);
       else
-        sweep_a_sums<3, 1, double, false>(G, P, enrm.data(), bnrow, JD.bw, JD.p0, JD.klen, JD.bscale, nbr.data(), n, i, cnt, xh[i], fi, S, gam, Pi, B3);
+        sweep_a_sums<3, 1, double, false>(G, P, enrm.data(), bnrow, JD.bw, JD.p0, JD.klen, JD.bscale, nbr.data(), n, i, cnt, xh[i], fi, pairn, S, gam, Pi, B3);
     } else {
       if (F.k == 2)
-        sweep_a_sums<2, 2, double, false>(G, P, enrm.data(), bnrow, JD.bw, JD.p0, JD.klen, JD.bscale, nbr.data(), n, i, cnt, xh[i], fi, S, gam, Pi, B3);
+        sweep_a_sums<2, 2, double, false>(G, P, enrm.data(), bnrow, JD.bw, JD.p0, JD.klen, JD.bscale, nbr.data(), n, i, cnt, xh[i], fi, pairn, S, gam, Pi, B3);
       else
-        sweep_a_sums<2, 1, double, false>(G, P, enrm.data(), bnrow, JD.bw, JD.p0, JD.klen, JD.bscale, nbr.data(), n, i, cnt, xh[i], fi, S, gam, Pi, B3);
+        sweep_a_sums<2, 1, double, false>(G, P, enrm.data(), bnrow, JD.bw, JD.p0, JD.klen, JD.bscale, nbr.data(), n, i, cnt, xh[i], fi, pairn, S, gam, Pi, B3);
     }
     double a3[3] = {0.0, 0.0, 0.0};
     for (int a = 0; a < D; ++a) a3[a] = -((Pi[a] + B3[a]) / gam);

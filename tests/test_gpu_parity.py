@@ -51,6 +51,11 @@ CASES = {
     # imported sharp features on a level set: Zalesak's slotted disc, four
     # polyline curves and four singular points
     "zalesak_disc": lambda: wk.zalesak_disc(),
+    # 3D imported sharp features on a level set: a cube with its edges and
+    # vertices (six face patches) and a cylinder with its two rims (three
+    # patches)
+    "level_cube_sharp": lambda: wk.level_cube_sharp(),
+    "level_cylinder": lambda: wk.level_cylinder(),
     # both background grids at once: a level-set domain with gridded h_t
     "peanut_grid33": lambda: wk.with_grid_sizing(wk.level_peanut(), 33),
     "torus_grid17": lambda: wk.with_grid_sizing(wk.level_torus(n_total=12000, res=64), 17),
@@ -59,6 +64,7 @@ KSTEPS = {"square64": 200, "hole2d_20011": 60, "ball3d_30011": 25, "ell2d_20011"
           "ell3d_30011": 20, "paper_square": 150, "paper_cube": 6, "graded_disc": 60,
           "paper_sphere01": 10, "paper_sphere02": 6, "square_grid33": 60, "ball3d_grid17": 10,
           "level_peanut": 60, "level_torus": 8, "zalesak_disc": 60,
+          "level_cube_sharp": 12, "level_cylinder": 10,
           "peanut_grid33": 40, "torus_grid17": 8}
 
 _wl_cache = {}
@@ -156,7 +162,8 @@ FP32_MODES = [binding.SPH_FP32_MIXED, binding.SPH_FP32_COMPENSATED]
 
 
 @pytest.mark.parametrize("precision", FP32_MODES)
-@pytest.mark.parametrize("name", ["hole2d_20011", "paper_square", "ball3d_30011", "ell3d_30011"])
+@pytest.mark.parametrize("name", ["hole2d_20011", "paper_square", "ball3d_30011", "ell3d_30011",
+                                  "level_cube_sharp"])
 def test_first_step_fields_fp32_mixed(name, precision):
     """The FP32 paths' first-step fields (FP32 pair terms summed in FP64, or
     in FP32 with Neumaier compensation), including the force a that the
