@@ -243,6 +243,15 @@ typedef struct {
   void *(*dev_alloc)(size_t bytes, void *ctx);
   void (*dev_free)(void *ptr, void *ctx);
   void *alloc_ctx;
+  double verlet_skin;        /* Algorithm 1's Verlet neighbour list as a
+                                candidate list of reach (r_c / h + skin) h,
+                                built with a re-sort of the particles only when
+                                some particle has moved farther than the skin
+                                allows since the last build (decided on the
+                                device), and filtered into the neighbour list
+                                every step; the lists stay those of the cut-off
+                                radius.  0 = no candidate list (a cell scan and
+                                a sort every step); [0, 2] */
 } sph_params;
 
 enum { SPH_INIT_DENSITY = 0, SPH_INIT_UNIFORM = 1 };
@@ -403,6 +412,11 @@ sph_status sph_mesh_group_state(sph_mesh *m, int32_t feature, double *out);
  * steps, out[3] interactions of the last step. */
 sph_status sph_mesh_counters(sph_mesh *m, double *out);
 
+/* Verlet candidate lists built since creation (each build also re-sorts the
+ * particles), for a job created with verlet_skin > 0; 0 otherwise.  Waits
+ * for the stream. */
+sph_status sph_mesh_list_builds(sph_mesh *m, int64_t *builds);
+
 /* Run the device control law of one feature over a synthetic series of
  * per-step V-bar samples and final time steps (no particles), writing per
  * step the phase after it, whether the velocity is reset at the next step,
@@ -466,6 +480,10 @@ typedef struct {
   void *(*dev_alloc)(size_t bytes, void *ctx);   /* as in sph_params; both NULL = */
   void (*dev_free)(void *ptr, void *ctx);        /* hipMalloc / hipFree       */
   void *alloc_ctx;
+  double verlet_skin;        /* as in sph_params, for every job of the batch
+                                (the jobs' own values are not used); the
+                                candidate lists hold up to max_neighbors
+                                ((2 + skin) / 2)^dim entries per particle */
 } sph_batch_params;
 
 /* Device bytes a batch with these capacities allocates (admission control);
@@ -507,6 +525,10 @@ sph_status sph_batch_positions(sph_batch *b, int32_t job, double *xyz, int32_t *
 sph_status sph_batch_error(sph_batch *b, int32_t job, double *e_sys, int32_t *phase,
                            int32_t *converged, int64_t *step);
 sph_status sph_batch_counters(sph_batch *b, int32_t job, double *out);
+
+/* Verlet candidate lists the batch has built (all its jobs at once), as
+ * sph_mesh_list_builds. */
+sph_status sph_batch_list_builds(sph_batch *b, int64_t *builds);
 
 /* Wait until every step enqueued on the batch's stream has finished. */
 sph_status sph_batch_sync(sph_batch *b);

@@ -50,7 +50,7 @@ class Params(C.Structure):
                 ("debug_fields", C.c_int32), ("stream", C.c_void_p),
                 ("n_particles", C.c_int64), ("seed", C.c_uint64), ("init", C.c_int32),
                 ("mass_res", C.c_int32), ("dev_alloc", C.c_void_p), ("dev_free", C.c_void_p),
-                ("alloc_ctx", C.c_void_p)]
+                ("alloc_ctx", C.c_void_p), ("verlet_skin", C.c_double)]
 
 # device allocator callbacks (void *alloc(size_t, void *ctx), void free(void *, void *ctx))
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -62,7 +62,8 @@ class BatchParams(C.Structure):
     _fields_ = [("dim", C.c_int32), ("precision", C.c_int32), ("max_particles", C.c_int64),
                 ("max_cells", C.c_int64), ("max_jobs", C.c_int32), ("max_neighbors", C.c_int32),
                 ("scan_tile", C.c_int32), ("use_graph", C.c_int32), ("debug_fields", C.c_int32), ("stream", C.c_void_p),
-                ("dev_alloc", C.c_void_p), ("dev_free", C.c_void_p), ("alloc_ctx", C.c_void_p)]
+                ("dev_alloc", C.c_void_p), ("dev_free", C.c_void_p), ("alloc_ctx", C.c_void_p),
+                ("verlet_skin", C.c_double)]
 
 
 class SphError(RuntimeError):
@@ -402,6 +403,12 @@ class SphMesh:
         return dict(steps=int(out[0]), escaped=int(out[1]), interactions=int(out[2]),
                     interactions_last=int(out[3]))
 
+    def list_builds(self):
+        """Verlet candidate lists built so far (0 without a skin)."""
+        v = C.c_int64()
+        _check("sph_mesh_list_builds", lib().sph_mesh_list_builds(self.h, C.byref(v)))
+        return int(v.value)
+
     def profile(self, enable=True):
         _check("sph_mesh_profile", lib().sph_mesh_profile(self.h, 1 if enable else 0))
 
@@ -442,9 +449,10 @@ class JobSpec:
 
 def batch_params(dim, precision=SPH_FP64, max_particles=0, max_cells=1, max_jobs=1,
                  max_neighbors=0, use_graph=1, debug_fields=0, stream=None, scan_tile=0,
-                 allocator=None):
+                 allocator=None, verlet_skin=0.0):
     bp = BatchParams()
     bp.dim, bp.precision = dim, precision
+    bp.verlet_skin = float(verlet_skin)
     bp.max_particles, bp.max_cells, bp.max_jobs = max_particles, max_cells, max_jobs
     bp.max_neighbors, bp.use_graph, bp.debug_fields = max_neighbors, use_graph, debug_fields
     bp.scan_tile = scan_tile
@@ -510,10 +518,12 @@ class SphBatch:
     sequence per step (libsphmesh.so batch handle)."""
 
     def __init__(self, dim, precision=SPH_FP64, max_particles=0, max_cells=1, max_jobs=1,
-                 max_neighbors=0, use_graph=1, stream=None, scan_tile=0, allocator=None):
+                 max_neighbors=0, use_graph=1, stream=None, scan_tile=0, allocator=None,
+                 verlet_skin=0.0):
         self._alloc = allocator
         self.bp = batch_params(dim, precision, max_particles, max_cells, max_jobs,
-                               max_neighbors, use_graph, 0, stream, scan_tile, allocator)
+                               max_neighbors, use_graph, 0, stream, scan_tile, allocator,
+                               verlet_skin)
         self.max_jobs = max_jobs
         h = C.c_void_p()
         _check("sph_batch_create", lib().sph_batch_create(C.byref(self.bp), C.byref(h)))
@@ -573,6 +583,11 @@ class SphBatch:
                                                         C.byref(ph), C.byref(conv), C.byref(st)))
         return dict(e_sys=e.value, phase=ph.value, converged=bool(conv.value), step=st.value)
 
+    def list_builds(self):
+        v = C.c_int64()
+        _check("sph_batch_list_builds", lib().sph_batch_list_builds(self.h, C.byref(v)))
+        return int(v.value)
+
     def counters(self, job):
         out = np.zeros(4)
         _check("sph_batch_counters", lib().sph_batch_counters(self.h, int(job), out.ctypes.data))
@@ -615,4 +630,4 @@ def exported_symbols():
             "sph_mesh_device_bytes", "sph_batch_footprint", "sph_job_cells", "sph_batch_create",
             "sph_batch_add", "sph_batch_remove", "sph_batch_step", "sph_batch_status",
             "sph_batch_positions", "sph_batch_error", "sph_batch_counters", "sph_batch_destroy",
-            "sph_batch_sync"]
+            "sph_batch_sync", "sph_mesh_list_builds", "sph_batch_list_builds"]

@@ -222,6 +222,7 @@ struct Group {
 struct JobStat {
   unsigned long long escaped, inter_total, inter_last, steps;
   unsigned int nan_flag, nan_oid, overflow, overflow_max;
+  unsigned int skin_overflow, skin_max;   // the Verlet candidate list's overflow
   int32_t converged, live;
 };
 
@@ -234,6 +235,10 @@ struct JobDev {
   // (klen = ksup / 2) and the pair predicate compares with ksup2 max(h)^2
   double ksup, klen, ksup2;
   double bscale;   // factor on the boundary term of the pressure force
+  // Verlet candidate list (skin delta h): its reach ksup_s = ksup + delta, the
+  // scan radius factor and cap at that reach, and the displacement since the
+  // list's build, in units of the particle's h then, that forces a rebuild
+  double ksup_s, rfac_s, rmax_s, move_eps;
   int32_t bw, nf, live, pad;
 };
 
@@ -275,7 +280,17 @@ struct Batch {
   uint32_t ncell, ntiles;
   int njobs;                          // job slots in use: [0, njobs)
   int has_hole;                       // some resident job has a hole
+  // Verlet candidate lists (skin_on): built when vstate[VS_REBUILD] is set,
+  // filtered into the neighbour list every step; particles keep their slots
+  // between builds
+  int skin_on, skin_cap;
+  uint32_t *skin, *nsk;               // [skin_cap / 8][n][8] blocked like the list; counts
+  double4 *xref;                      // [n] x and h at the last build
+  unsigned long long *vstate;         // [NSTRIPE] striped maxima of the displacement
+                                      // ratio, [VS_REBUILD] the rebuild flag,
+                                      // [VS_BUILDS] builds so far
 };
+constexpr int VS_REBUILD = NSTRIPE, VS_BUILDS = NSTRIPE + 1, VS_WORDS = NSTRIPE + 2;
 
 template <typename R>
 struct Vec4;

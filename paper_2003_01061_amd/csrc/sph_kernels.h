@@ -202,7 +202,11 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *l
 __global__ __launch_bounds__(BLOCK) void k_scan(const uint32_t *__restrict__ in,
                                                 uint32_t *__restrict__ out, uint32_t n,
                                                 unsigned long long *status, uint32_t *ticket,
-                                                uint32_t ntiles, unsigned int *gflags) {
+                                                uint32_t ntiles, unsigned int *gflags,
+                                                const unsigned long long *__restrict__ vstate) {
+  // with Verlet candidate lists, particles are re-sorted only when the lists
+  // are rebuilt
+  if (vstate && !vstate[VS_REBUILD]) return;
   __shared__ uint32_t lds[BLOCK / 64];
   __shared__ uint32_t s_tile, s_prefix;
   // tile in LDS, one padding word per SCAN_PER so that the per-thread reads
@@ -300,7 +304,9 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(int n, const uint32_t *__rest
                                                    uint32_t *__restrict__ psrc,
                                                    uint32_t *__restrict__ pkey,
                                                    unsigned long long *__restrict__ status,
-                                                   uint32_t ntiles, uint32_t *__restrict__ ticket) {
+                                                   uint32_t ntiles, uint32_t *__restrict__ ticket,
+                                                   const unsigned long long *__restrict__ vstate) {
+  if (vstate && !vstate[VS_REBUILD]) return;   // no sort between list builds
   const int i = blockIdx.x * BLOCK + threadIdx.x;
   for (uint32_t t = (uint32_t)i; t < ntiles; t += gridDim.x * BLOCK) status[t] = 0ull;
   if (i == 0) *ticket = 0u;
@@ -313,7 +319,9 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(int n, const uint32_t *__rest
 
 // Entry u of a cell (filled in atomic order) finds its rank among the cell's
 // caller ids and copies its particle to that slot; the first entry of a cell
-// clears the cell's count for the next hash.
+// clears the cell's count for the next hash.  With Verlet candidate lists and
+// no rebuild due, every particle keeps its slot (a plain copy) and clears
+// its cell's count; at a rebuild the new slot also records x and h.
 template <int D>
 __global__ __launch_bounds__(BLOCK) void k_rank_gather(Batch B, int n, const uint32_t *__restrict__ psrc,
                                                        const uint32_t *__restrict__ pkey,
@@ -323,16 +331,23 @@ __global__ __launch_bounds__(BLOCK) void k_rank_gather(Batch B, int n, const uin
                                                        Parts b) {
   const int u = blockIdx.x * BLOCK + threadIdx.x;
   if (u >= n) return;
-  const uint32_t src = psrc[u];
-  if (src >= (uint32_t)n) return;
-  const uint32_t c = cell[src];
-  const uint32_t lo = cstart[c], hi = cstart[c + 1];
-  const uint32_t key = pkey[u];
-  uint32_t r = 0;
-  for (uint32_t v = lo; v < hi; ++v) r += pkey[v] < key ? 1u : 0u;
-  if ((uint32_t)u == lo) cnt[c] = 0u;
-  const uint32_t dst = lo + r;
-  if (dst >= (uint32_t)n) return;
+  const bool sorted = !B.skin_on || B.vstate[VS_REBUILD] != 0ull;
+  uint32_t src = (uint32_t)u, dst = (uint32_t)u, key;
+  if (sorted) {
+    src = psrc[u];
+    if (src >= (uint32_t)n) return;
+    const uint32_t c = cell[src];
+    const uint32_t lo = cstart[c], hi = cstart[c + 1];
+    key = pkey[u];
+    uint32_t r = 0;
+    for (uint32_t v = lo; v < hi; ++v) r += pkey[v] < key ? 1u : 0u;
+    if ((uint32_t)u == lo) cnt[c] = 0u;
+    dst = lo + r;
+    if (dst >= (uint32_t)n) return;
+  } else {
+    key = a.oid[u];
+    cnt[cell[u]] = 0u;
+  }
   const double4 xh = a.xh[src];
   const uint32_t f = a.f[src];
   b.xh[dst] = xh;
@@ -340,6 +355,7 @@ __global__ __launch_bounds__(BLOCK) void k_rank_gather(Batch B, int n, const uin
   b.f[dst] = (uint16_t)f;
   b.oid[dst] = key;
   b.xf[dst] = scan_record<D>(xh, f);
+  if (B.skin_on && sorted) B.xref[dst] = xh;
   // the normal out of the domain of a particle on a hole's boundary, for the
   // sweep that follows (computed there, it would hold registers inside the
   // neighbour loop): towards the centre of a disc or ball, against the level
@@ -562,11 +578,22 @@ __host__ __device__ __forceinline__ void sweep_a_sums(const Geom &g, const Parts
 // neighbour instead of once per candidate.  Every particle reads its own
 // job's geometry and grid; cells of different jobs never meet.
 // ---------------------------------------------------------------------------
-template <int D, typename R, bool FORCES, int NB, bool CMP = false>
+// MODE 0: candidates from the cell scan, as above.  MODE 1 (FORCES = false,
+// only when a rebuild is due): the Verlet candidate list of every
+// non-singular particle, the cell scan at the reach (c + delta) h with the
+// FP32 test alone, widened by its error bound so that it keeps every pair
+// within that reach.  MODE 2: candidates from the particle's Verlet list
+// instead of the cell scan, classified and summed as in MODE 0.
+template <int D, typename R, bool FORCES, int NB, bool CMP = false, int MODE = 0>
 __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
     Batch B, Parts s, const uint32_t *__restrict__ cstart, int all, uint32_t *__restrict__ nbr,
     uint32_t *__restrict__ nnb, typename Vec4<R>::T *__restrict__ ap,
     double *__restrict__ dbg_gam, double *__restrict__ dbg_vt) {
+  static_assert(MODE == 0 || (MODE == 1 && !FORCES) || MODE == 2, "candidate list modes");
+  if (MODE == 1) {
+    if (B.vstate[VS_REBUILD] == 0ull) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0) B.vstate[VS_BUILDS] += 1ull;
+  }
   using R4 = typename Vec4<R>::T;
   const int n = B.n;
   const int i = xcd_block() * BLOCK + threadIdx.x;
@@ -579,14 +606,17 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
     const JobDev &J = B.jobs[job];
     const Feat F = B.feat[fi];
     const bool moving = F.type != T_SI && B.grp[fi].active;
-    const bool want = F.type != T_SI && (all || B.grp[fi].active);
+    const bool want = F.type != T_SI && (all || MODE == 1 || B.grp[fi].active);
     act = FORCES && moving;
     uint32_t count = 0;
     const double4 xi = s.xh[i];
     if (want) {
       const Grid &G = J.G;
-      double Rs = G.rfac * xi.w;
-      Rs = Rs < G.rmax ? Rs : G.rmax;
+      // scan reach: the cut-off radius, or the Verlet list's in MODE 1
+      const double ksup = MODE == 1 ? J.ksup_s : J.ksup;
+      double Rs = (MODE == 1 ? J.rfac_s : G.rfac) * xi.w;
+      const double rmax = MODE == 1 ? J.rmax_s : G.rmax;
+      Rs = Rs < rmax ? Rs : rmax;
       const double pc[3] = {xi.x, xi.y, xi.z};
       // cell levels that can hold a neighbour: h is L-Lipschitz, so a
       // neighbour (r < R_i) has |h_j - h_i| <= L R_i (widened for rounding)
@@ -639,7 +669,8 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
       {
         // the support radius is klen H >= 2 klen h0
         const double w = (D == 2 ? 2e-6 : 2e-5) + (double)Mf / (2.0 * J.klen * J.g.h0);
-        const double k2 = J.klen * J.klen;
+        const double kl = MODE == 1 ? 0.5 * J.ksup_s : J.klen;
+        const double k2 = kl * kl;
         cin = w < 1.0 ? (float)((1.0 - w) * (1.0 - w) * k2) : -1.0f;
         cout = (float)((1.0 + w) * (1.0 + w) * k2);
       }
@@ -652,13 +683,66 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
       // any lane of the wave hits.
       static_assert(LB == 8, "the ring is flushed as two 16-byte stores");
       __shared__ uint32_t ring[LB][BLOCK];
-      uint4 *wp = reinterpret_cast<uint4 *>(nbr) + (size_t)i * (LB / 4);
+      uint4 *wp = reinterpret_cast<uint4 *>(MODE == 1 ? B.skin : nbr) + (size_t)i * (LB / 4);
       const uint32_t wstep = (uint32_t)n * (LB / 4);
-      const uint32_t nblk = (uint32_t)B.cap / LB;   // blocks of capacity
+      const uint32_t nblk = (uint32_t)(MODE == 1 ? B.skin_cap : B.cap) / LB;   // blocks of capacity
+      if constexpr (MODE == 2) {
+        // the Verlet list: every pair within the cut-off is on it (its reach
+        // covers the displacements since its build), so filtering it with the
+        // same predicate gives the list the cell scan would
+        const uint32_t ns = B.nsk[i];
+        const uint4 *sp = reinterpret_cast<const uint4 *>(B.skin) + (size_t)i * (LB / 4);
+        for (uint32_t b0 = 0; b0 < ns; b0 += LB, sp += (size_t)n * (LB / 4)) {
+          const uint4 w0 = sp[0], w1 = sp[1];
+          const uint32_t ub[LB] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
+#pragma unroll
+          for (int hb = 0; hb < LB; hb += NB) {
+            float4 xr[NB];
+            uint32_t jr[NB];
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+              // entries past the count read the particle's own record
+              jr[q] = b0 + hb + q < ns ? (ub[hb + q] & 0x7fffffffu) : (uint32_t)i;
+              xr[q] = s.xf[jr[q]];
+            }
+            uint32_t tag[NB];
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+              const bool cand = b0 + hb + q < ns;
+              const float ex = xif.x - xr[q].x, ey = xif.y - xr[q].y;
+              const float ez = D == 3 ? xif.z - xr[q].z : 0.0f;
+              const float d2 = ex * ex + ey * ey + ez * ez;
+              const float Hj = D == 2 ? xr[q].z : xr[q].w;
+              const float H = __builtin_fmaxf(Hif, Hj);
+              const float H2 = H * H;
+              const float tin = H2 * cin, tout = H2 * cout;
+              bool hit = cand & (d2 < tin);
+              if (cand & !(d2 < tin) & !(d2 > tout))   // near the support radius: exact test
+                hit = within_a4<D>(xi, A4, kc2, s.xh[jr[q]]);
+              tag[q] = hit ? ub[hb + q] : 0xffffffffu;
+            }
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+              if (tag[q] != 0xffffffffu) {
+                const uint32_t k = count % LB;
+                ring[k][threadIdx.x] = tag[q];
+                ++count;
+                if (k == LB - 1 && count / LB <= nblk) {
+                  wp[0] = make_uint4(ring[0][threadIdx.x], ring[1][threadIdx.x],
+                                     ring[2][threadIdx.x], ring[3][threadIdx.x]);
+                  wp[1] = make_uint4(ring[4][threadIdx.x], ring[5][threadIdx.x],
+                                     ring[6][threadIdx.x], ring[7][threadIdx.x]);
+                  wp += wstep;
+                }
+              }
+            }
+          }
+        }
+      } else
       for (int lv = lv0; lv <= lv1; ++lv) {
         // a level-lv candidate has h_j < hcap[lv], so none beyond
         // c max(h_i, hcap[lv]) is a neighbour
-        double Rl = J.ksup * (xi.w > G.hcap[lv] ? xi.w : G.hcap[lv]) * (1.0 + 1e-9);
+        double Rl = ksup * (xi.w > G.hcap[lv] ? xi.w : G.hcap[lv]) * (1.0 + 1e-9);
         Rl = Rl < Rs ? Rl : Rs;
         const double R2 = Rl * Rl;
         int lo_c[3] = {0, 0, 0}, hi_c[3] = {0, 0, 0};
@@ -726,9 +810,14 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
                 const float H = __builtin_fmaxf(Hif, Hj);
                 const float H2 = H * H;
                 const float tin = H2 * cin, tout = H2 * cout;
-                bool hit = cand & (d2 < tin);
-                if (cand & !(d2 < tin) & !(d2 > tout))   // near the support radius: exact test
-                  hit = within_a4<D>(xi, A4, kc2, s.xh[j]);
+                bool hit;
+                if constexpr (MODE == 1) {   // Verlet list: all that may lie within reach
+                  hit = cand & !(d2 > tout);
+                } else {
+                  hit = cand & (d2 < tin);
+                  if (cand & !(d2 < tin) & !(d2 > tout))   // near the support radius: exact test
+                    hit = within_a4<D>(xi, A4, kc2, s.xh[j]);
+                }
                 tag[q] = hit ? (j | (fr[q] == (uint32_t)(fi & (MAXF - 1)) ? 0u : 0x80000000u))
                              : 0xffffffffu;
               }
@@ -757,7 +846,11 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
         wp[1] = make_uint4(ring[4][threadIdx.x], ring[5][threadIdx.x], ring[6][threadIdx.x],
                            ring[7][threadIdx.x]);
       }
-      if ((int)count > B.cap) {
+      if (MODE == 1 && (int)count > B.skin_cap) {
+        atomicMax(&B.st[job].skin_max, count);
+        atomicExch(&B.st[job].skin_overflow, 1u);
+        count = B.skin_cap;
+      } else if (MODE != 1 && (int)count > B.cap) {
         atomicMax(&B.st[job].overflow_max, count);
         atomicExch(&B.st[job].overflow, 1u);
         count = B.cap;
@@ -815,8 +908,12 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
       if (dbg_gam) dbg_gam[i] = 0.0;
       if (dbg_vt) dbg_vt[i] = 0.0;
     }
-    nnb[i] = count;
-    mine = count;
+    if (MODE == 1) {
+      B.nsk[i] = count;
+    } else {
+      nnb[i] = count;
+      mine = count;
+    }
   }
   if (FORCES) {
     wave_commit(act, fi, dtb, vfix, B.smin, B.ssum);
@@ -1073,6 +1170,16 @@ __global__ __launch_bounds__(BLOCK) void k_control(Batch B) {
       S.converged = moving[j] ? 0 : 1;
     }
   }
+  // Verlet lists: rebuild before the next step once some particle has moved
+  // as far as its list's reach allows
+  if (B.skin_on && threadIdx.x < 64) {
+    unsigned long long m = take(B.vstate + threadIdx.x, 0ull);
+    for (int o = 32; o > 0; o >>= 1) {
+      const unsigned long long t = __shfl_xor(m, o);
+      m = t > m ? t : m;
+    }
+    if (threadIdx.x == 0) B.vstate[VS_REBUILD] = m > dbits(1.0) ? 1ull : 0ull;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1088,6 +1195,7 @@ __global__ __launch_bounds__(BLOCK) void k_integrate_hash(
   bool escaped = false;
   int job = 0;
   uint32_t cc = 0;
+  double moved = 0.0;
   if (i < n) {
     const int fi = s.f[i];
     job = fi / MAXF;
@@ -1131,10 +1239,25 @@ __global__ __launch_bounds__(BLOCK) void k_integrate_hash(
     s.xh[i] = xh;
     s.xf[i] = scan_record<D>(xh, (uint32_t)fi);
     cell[i] = cc;
+    if (B.skin_on) {   // displacement since the Verlet list's build, in units of its limit
+      const double4 r = B.xref[i];
+      const double d0 = xh.x - r.x, d1 = xh.y - r.y, d2 = D == 3 ? xh.z - r.z : 0.0;
+      const double d = __builtin_sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+      moved = d > 0.0 ? d / (J.move_eps * r.w) : 0.0;
+    }
   }
   const uint32_t r = rank_in_cell(cc, i < n, cnt);
   if (i < n) rank[i] = r;
   wave_commit(escaped, job, 0ull, 1ull, nullptr, B.sesc);
+  if (B.skin_on) {   // striped maximum (non-negative doubles order as their bits)
+    unsigned long long m = dbits(moved);
+    for (int o = 32; o > 0; o >>= 1) {
+      const unsigned long long t = __shfl_xor(m, o);
+      m = t > m ? t : m;
+    }
+    if (__lane_id() == 0)
+      atomicMax(&B.vstate[(blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6)) & (NSTRIPE - 1)], m);
+  }
 }
 
 // ---------------------------------------------------------------------------

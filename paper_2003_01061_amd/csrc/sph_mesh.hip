@@ -52,11 +52,12 @@ sph_status fail(sph_status st, const char *fmt, ...) {
 
 enum KernelId {
   KID_SCAN = 0, KID_SCATTER, KID_RANK_GATHER, KID_NBR_FORCES, KID_REDUCE_A, KID_MIDPOINT,
-  KID_SWEEP_B, KID_REDUCE_B, KID_INTEGRATE_HASH, KID_CONTROL, KID_HASH, KID_NBR_LISTS, KID_COUNT
+  KID_SWEEP_B, KID_REDUCE_B, KID_INTEGRATE_HASH, KID_CONTROL, KID_HASH, KID_NBR_LISTS, KID_SKIN,
+  KID_COUNT
 };
 const char *kKernelNames[KID_COUNT] = {
     "scan", "scatter", "rank_gather", "nbr_forces", "reduce_a", "midpoint", "sweep_b",
-    "reduce_b", "integrate_hash", "control", "hash", "nbr_lists"};
+    "reduce_b", "integrate_hash", "control", "hash", "nbr_lists", "verlet_build"};
 
 // ---------------------------------------------------------------------------
 // features of a box-minus-holes geometry (numbering of sph_mesh.h)
@@ -427,6 +428,8 @@ static sph_status validate(const sph_geometry *g, const sph_sizing *s, const sph
     return fail(SPH_ERR_INVALID_ARG, "kernel_support must be 0 or in [1, 8]");
   if (!(p->boundary_scale == 0.0 || (p->boundary_scale >= 0.25 && p->boundary_scale <= 8.0)))
     return fail(SPH_ERR_INVALID_ARG, "boundary_scale must be 0 or in [0.25, 8]");
+  if (!(p->verlet_skin >= 0.0 && p->verlet_skin <= 2.0))
+    return fail(SPH_ERR_INVALID_ARG, "verlet_skin must be in [0, 2]");
   if (p->cell_levels < 0 || p->cell_levels > MAXLEV)
     return fail(SPH_ERR_INVALID_ARG, "cell_levels must be in [0, %d]", MAXLEV);
   if (!(s->h0 > 0) || !(s->grad >= 0) || !std::isfinite(s->h0) || !std::isfinite(s->grad))
@@ -570,6 +573,13 @@ struct sph_batch {
   uint32_t *cnt = nullptr, *cstart = nullptr, *ticket = nullptr;
   unsigned long long *scan_status = nullptr;
   uint32_t *nbr = nullptr, *nnb = nullptr;
+  // Verlet candidate lists (skin > 0): lists, counts, x and h at the build,
+  // displacement stripes and the rebuild flag
+  double skin = 0.0;
+  int skin_cap = 0;
+  uint32_t *skin_list = nullptr, *nsk = nullptr;
+  double4 *xref = nullptr;
+  unsigned long long *vstate = nullptr;
   void *ap = nullptr, *acc = nullptr, *mid = nullptr;              // {ax, ay, az, 0} in the sweep precision
   double4 *enrm = nullptr;   // boundary normals of particles on holes (cell order)
   double *dbg_gam = nullptr, *dbg_vt = nullptr;
@@ -634,6 +644,12 @@ struct sph_batch {
     B.ntiles = ntiles();
     B.njobs = njobs;
     B.enrm = enrm;
+    B.skin_on = skin > 0.0 ? 1 : 0;
+    B.skin_cap = skin_cap;
+    B.skin = skin_list;
+    B.nsk = nsk;
+    B.xref = xref;
+    B.vstate = vstate;
     B.has_hole = 0;
     for (int j = 0; j < njobs; ++j)
       if (jobs[j].live)
@@ -678,7 +694,17 @@ struct sph_batch {
     return e;
   }
 
+  // the next step re-sorts the particles and rebuilds the Verlet lists
+  // (after any change of the particles made outside a step; never captured)
+  sph_status force_rebuild() {
+    static const unsigned long long one = 1ull;
+    if (skin > 0.0)
+      HIPCHK(hipMemcpyAsync(vstate + VS_REBUILD, &one, sizeof one, hipMemcpyHostToDevice, stream));
+    return SPH_OK;
+  }
+
   sph_status hash_range(int i0, int i1) {
+    if (sph_status st = force_rebuild()) return st;
     if (i1 <= i0) return SPH_OK;
     if (D == 2)
       HIPCHK(launch(KID_HASH, k_hash<2>, blocks(i1 - i0), BLOCK, dev(), P[cur], i0, i1, cell, rank, cnt));
@@ -691,11 +717,12 @@ struct sph_batch {
   // needs cell / rank / cnt of the current buffer, leaves cnt cleared
   sph_status enqueue_sort() {
     const Batch B = dev();
+    const unsigned long long *vs = skin > 0.0 ? vstate : nullptr;
     HIPCHK(launch(KID_SCAN, k_scan, B.ntiles, BLOCK, (const uint32_t *)cnt, cstart, ncell,
-                  scan_status, ticket, B.ntiles, d_gflags));
+                  scan_status, ticket, B.ntiles, d_gflags, vs));
     HIPCHK(launch(KID_SCATTER, k_scatter, blocks(n), BLOCK, n, (const uint32_t *)cell,
                   (const uint32_t *)rank, (const uint32_t *)cstart, (const uint32_t *)P[cur].oid,
-                  psrc, pkey, scan_status, B.ntiles, ticket));
+                  psrc, pkey, scan_status, B.ntiles, ticket, vs));
     if (D == 2)
       HIPCHK(launch(KID_RANK_GATHER, k_rank_gather<2>, blocks(n), BLOCK, B, n, (const uint32_t *)psrc,
                     (const uint32_t *)pkey, (const uint32_t *)cell, (const uint32_t *)cstart, cnt,
@@ -716,17 +743,28 @@ struct sph_batch {
     return SPH_OK;
   }
 
-  // the neighbour + sweep A kernel for the batch's scan tile
+  // the neighbour + sweep A kernel for the batch's scan tile; with Verlet
+  // lists, their build (which returns at once unless a rebuild is due) and
+  // the kernel that filters them
   template <int DD, typename R, bool CMP>
   hipError_t launch_nbr_forces(const Batch &B, const Parts &s) {
     using R4 = typename Vec4<R>::T;
-    auto go = [&](auto kern) {
-      return launch(KID_NBR_FORCES, kern, blocks8(n), BLOCK, B, s, (const uint32_t *)cstart, 0,
-                    nbr, nnb, (R4 *)ap, dbg_gam, dbg_vt);
+    auto go = [&](int kid, auto kern) {
+      return launch(kid, kern, blocks8(n), BLOCK, B, s, (const uint32_t *)cstart, 0, nbr, nnb,
+                    (R4 *)ap, dbg_gam, dbg_vt);
     };
-    if (tile == 2) return go(k_nbr_forces<DD, R, true, 2, CMP>);
-    if (tile == 8) return go(k_nbr_forces<DD, R, true, 8, CMP>);
-    return go(k_nbr_forces<DD, R, true, 4, CMP>);
+    if (skin > 0.0) {
+      hipError_t e = tile == 2   ? go(KID_SKIN, k_nbr_forces<DD, R, false, 2, CMP, 1>)
+                     : tile == 8 ? go(KID_SKIN, k_nbr_forces<DD, R, false, 8, CMP, 1>)
+                                 : go(KID_SKIN, k_nbr_forces<DD, R, false, 4, CMP, 1>);
+      if (e != hipSuccess) return e;
+      if (tile == 2) return go(KID_NBR_FORCES, k_nbr_forces<DD, R, true, 2, CMP, 2>);
+      if (tile == 8) return go(KID_NBR_FORCES, k_nbr_forces<DD, R, true, 8, CMP, 2>);
+      return go(KID_NBR_FORCES, k_nbr_forces<DD, R, true, 4, CMP, 2>);
+    }
+    if (tile == 2) return go(KID_NBR_FORCES, k_nbr_forces<DD, R, true, 2, CMP>);
+    if (tile == 8) return go(KID_NBR_FORCES, k_nbr_forces<DD, R, true, 8, CMP>);
+    return go(KID_NBR_FORCES, k_nbr_forces<DD, R, true, 4, CMP>);
   }
 
   template <int DD, typename R, bool CMP = false>
@@ -821,6 +859,9 @@ struct sph_batch {
     if (s.overflow)
       return fail(SPH_ERR_STATE, "neighbour list overflow: %u neighbours > capacity %d "
                                  "(raise max_neighbors)", s.overflow_max, cap);
+    if (s.skin_overflow)
+      return fail(SPH_ERR_STATE, "Verlet list overflow: %u candidates > capacity %d "
+                                 "(raise max_neighbors or lower verlet_skin)", s.skin_max, skin_cap);
     return SPH_OK;
   }
 
@@ -982,6 +1023,27 @@ static void fill_job(HostJob &J, const sph_geometry *g, const sph_sizing *s, con
 // 64 / 160 at r_c = 2h, scaled by (2.5 / 2)^D for the default r_c = 2.5h
 static int64_t default_cap(int D) { return D == 2 ? 104 : 320; }
 
+// entries of a Verlet candidate list: the neighbour capacity scaled by the
+// reach's volume ratio at r_c = 2h (the largest ratio over r_c >= 2h), in
+// whole blocks
+static int64_t skin_capacity(int64_t cap, int D, double skin) {
+  const double r = (2.0 + skin) / 2.0;
+  const double m = std::ceil((double)cap * (D == 2 ? r * r : r * r * r));
+  return ((int64_t)m + LB - 1) / LB * LB;
+}
+
+// the Verlet list's reach and rebuild limit of a job (skin delta): a pair
+// closer than c max(h_i, h_j) now was closer than (c + delta) max(h) at the
+// build if every particle has moved at most eps h (h at the build), eps =
+// delta / (c L + 2), since h is L-Lipschitz
+static void set_skin(JobDev &d, double skin) {
+  const double c = d.ksup, cs = c + skin, lip = d.G.lip;
+  d.ksup_s = cs;
+  d.rfac_s = cs * lip < 0.9 ? cs * (1.0 + 1e-9) / (1.0 - cs * lip) : 1e300;
+  d.rmax_s = d.G.rmax / c * cs;
+  d.move_eps = skin > 0.0 ? skin / (c * lip + 2.0) * (1.0 - 1e-6) : 0.0;
+}
+
 // particle arrays of a job: count, non-NULL arrays, finite coordinates,
 // feature ids of the geometry
 static sph_status check_particles(const sph_geometry *g, int64_t n, const double *xyz,
@@ -1023,6 +1085,10 @@ extern "C" int64_t sph_batch_footprint(const sph_batch_params *bp) {
   b += bp->max_jobs * (int64_t)sizeof(JobDev) + slots * (int64_t)(sizeof(Feat) + 8 + sizeof(Group)) +
        slots * MAXF * (int64_t)sizeof(BNorm) + bp->max_jobs * (int64_t)sizeof(JobStat);
   b += 2 * slots * NSTRIPE * 8 + 2 * (int64_t)bp->max_jobs * NSTRIPE * 8;
+  if (!(bp->verlet_skin >= 0.0 && bp->verlet_skin <= 2.0)) return -1;
+  if (bp->verlet_skin > 0.0)   // candidate lists, counts, x at the build, flags
+    b += N * skin_capacity(cap, bp->dim, bp->verlet_skin) * 4 + N * 4 + N * 32 +
+         VS_WORDS * 8;
   return b;
 }
 
@@ -1101,6 +1167,15 @@ extern "C" sph_status sph_batch_create(const sph_batch_params *bp, sph_batch **o
   B->acc = dalloc<char>(B->mem, N * r4, ow, by);
   if (B->D == 3) B->mid = dalloc<char>(B->mem, N * r4, ow, by);   // mid-point records (3D sweep B)
   B->enrm = dalloc<double4>(B->mem, N, ow, by);
+  B->skin = bp->verlet_skin;
+  if (B->skin > 0.0) {
+    B->skin_cap = (int)skin_capacity(B->cap, B->D, B->skin);
+    B->skin_list = dalloc<uint32_t>(B->mem, N * (size_t)B->skin_cap, ow, by);
+    B->nsk = dalloc<uint32_t>(B->mem, N, ow, by);
+    B->xref = dalloc<double4>(B->mem, N, ow, by);
+    B->vstate = dalloc<unsigned long long>(B->mem, VS_WORDS, ow, by);
+    ok = ok && B->skin_list && B->nsk && B->xref && B->vstate;
+  }
   if (B->debug) {
     B->dbg_gam = dalloc<double>(B->mem, N, ow, by);
     B->dbg_vt = dalloc<double>(B->mem, N, ow, by);
@@ -1140,6 +1215,11 @@ extern "C" sph_status sph_batch_create(const sph_batch_params *bp, sph_batch **o
   if (e == hipSuccess) e = hipMemset(B->P[1].f, 0, 2 * NPAD);
   if (e == hipSuccess) e = hipMemset(B->P[0].xf, 0, sizeof(float4) * NPAD);
   if (e == hipSuccess) e = hipMemset(B->P[1].xf, 0, sizeof(float4) * NPAD);
+  if (e == hipSuccess && B->skin > 0.0) {
+    e = hipMemset(B->vstate, 0, 8 * VS_WORDS);
+    if (e == hipSuccess) e = hipMemset(B->nsk, 0, 4 * std::max<size_t>(N, 1));
+    if (e == hipSuccess) e = hipMemset(B->xref, 0, sizeof(double4) * std::max<size_t>(N, 1));
+  }
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     delete B;
@@ -1169,6 +1249,7 @@ extern "C" sph_status sph_batch_add(sph_batch *b, const sph_geometry *g, const s
   if (slot < 0) return fail(SPH_ERR_OUT_OF_MEMORY, "no free job slot (max_jobs %d)", b->jcap);
   HostJob J;
   fill_job(J, g, s, p, b->ncell, (int)n);
+  set_skin(J.dev, b->skin);
   if ((int64_t)b->n + n > b->ncap)
     return fail(SPH_ERR_OUT_OF_MEMORY, "particle capacity %d exceeded", b->ncap);
   if ((uint64_t)b->ncell + J.ncell > b->ccap)
@@ -1521,6 +1602,7 @@ extern "C" sph_status sph_mesh_create_with_particles(const sph_geometry *g, cons
   bp.use_graph = p->use_graph;
   bp.debug_fields = p->debug_fields;
   bp.stream = p->stream;
+  bp.verlet_skin = p->verlet_skin;
   auto *M = new sph_mesh();
   if (sph_status st = sph_batch_create(&bp, &M->b)) {
     delete M;
@@ -1698,6 +1780,22 @@ extern "C" sph_status sph_mesh_counters(sph_mesh *m, double *out) {
   return sph_batch_counters(m->b, m->job, out);
 }
 
+extern "C" sph_status sph_batch_list_builds(sph_batch *b, int64_t *builds) {
+  if (!b || !builds) return fail(SPH_ERR_INVALID_ARG, "null argument");
+  unsigned long long v = 0;
+  if (b->skin > 0.0) {
+    HIPCHK(hipMemcpyAsync(&v, b->vstate + VS_BUILDS, sizeof v, hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(hipStreamSynchronize(b->stream));
+  }
+  *builds = (int64_t)v;
+  return SPH_OK;
+}
+
+extern "C" sph_status sph_mesh_list_builds(sph_mesh *m, int64_t *builds) {
+  if (!m) return fail(SPH_ERR_INVALID_ARG, "null handle");
+  return sph_batch_list_builds(m->b, builds);
+}
+
 extern "C" sph_status sph_mesh_velocities(sph_mesh *m, double *vel) {
   if (!m || !vel) return fail(SPH_ERR_INVALID_ARG, "null argument");
   sph_batch *b = m->b;
@@ -1756,7 +1854,8 @@ extern "C" sph_status sph_mesh_set_state(sph_mesh *m, const double *xyz, const d
 static sph_status build_lists_now(sph_mesh *m) {
   sph_batch *b = m->b;
   b->invalidate_graph();
-  sph_status st = b->enqueue_sort();
+  sph_status st = b->force_rebuild();   // a real sort, whatever the Verlet lists' state
+  if (!st) st = b->enqueue_sort();
   if (!st) st = b->D == 2 ? b->enqueue_lists_only<2>() : b->enqueue_lists_only<3>();
   if (!st) st = b->hash_range(0, b->n);
   if (st) return st;
