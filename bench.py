@@ -37,6 +37,7 @@ VALU_PEAK_WAVE_INSTS = 256 * 4 * 2.4e9 / 4
 VALU_PEAK_LANE_OPS = VALU_PEAK_WAVE_INSTS * 64
 COUNTERS_MD = os.path.join(ROOT, "profiles", "nbr_forces_square_hole_250k_counters.md")
 COUNTERS_3D_MD = os.path.join(ROOT, "profiles", "cube_ball_2m_counters.md")
+VERLET_SKIN_3D = 0.5   # the Verlet list skin the 3D leg also times (units of h)
 KERNEL_SOURCES = ("paper_2003_01061_amd/csrc/sph_device.h", "paper_2003_01061_amd/csrc/sph_kernels.h")
 
 
@@ -76,6 +77,8 @@ def profiled_counters(cfg, path=COUNTERS_MD):
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         h.update(open(os.path.join(ROOT, f), "rb").read())
+    if float(cfg.get("verlet_skin", 0.0)) > 0.0:
+        return None   # the counters were taken on the cell-scan kernel
     want = "cell_factor={} scan_tile={}".format(float(cfg.get("cell_factor", 1.0)),
                                                 int(cfg.get("scan_tile", 4)))
     # one fenced block of "key: value" lines per profiled configuration
@@ -131,12 +134,13 @@ def run_timed(wl, precision, steps, warmup, graph=True, cfg=None):
     t2 = time.perf_counter()
     c = j.counters()
     e = j.error()
+    builds = j.list_builds()
     j.close()
     # seconds: the timed region (inputs resident in HBM); with_io adds the
     # creation (host -> device copy, initial hash) and the host copy of the result
     return dict(seconds=t1 - t0, seconds_with_io=t2 - tc, interactions=c["interactions"],
                 escaped=c["escaped"], steps=c["steps"], e_sys=e["e_sys"], phase=e["phase"],
-                converged=e["converged"], positions=x)
+                converged=e["converged"], positions=x, builds=builds)
 
 
 def phase_one_ends(j, wl, steps, seen):
@@ -162,10 +166,14 @@ def converge_run(wl, precision, cfg=None, max_steps=6000, chunk=100):
     import torch
     j = binding.SphMesh(wl, precision=precision, use_graph=1, **(cfg or {}))
     j.sync()
+    # the first two steps capture the step graph (set-up, untimed)
+    j.step(2)
+    j.sync()
     torch.cuda.synchronize()
+    c0 = j.counters()["interactions"]
     # the time of the steps alone: the control-state queries between chunks
     # (host round trips, one per feature) are left out
-    sec, steps, ends = 0.0, 0, {}
+    sec, steps, ends = 0.0, 2, {}
     while steps < max_steps:
         t0 = time.perf_counter()
         j.step(chunk)
@@ -180,7 +188,7 @@ def converge_run(wl, precision, cfg=None, max_steps=6000, chunk=100):
     j.close()
     cap = wl.params["max_phase1_steps"]
     return dict(steps=int(c["steps"]), seconds=sec, converged=e["converged"], e_sys=e["e_sys"],
-                escaped=c["escaped"], interactions_per_s=c["interactions"] / sec,
+                escaped=c["escaped"], interactions_per_s=(c["interactions"] - c0) / sec,
                 phase_one_end={str(f): {"step": s_, "by": "cap" if s_ >= cap else "criterion"}
                                for f, s_ in sorted(ends.items())},
                 phase_one_cap=cap, positions=x)
@@ -206,6 +214,16 @@ def cube_ball_leg(args):
     inter_step = pc["interactions"] / max(pc["steps"], 1)
     byts = kernel_bytes("nbr_forces", wl, n_active, inter_step, 4)
     ctr = profiled_counters({}, COUNTERS_3D_MD)
+    # Verlet candidate lists (skin 0.5 h): the same steps, the particles
+    # re-sorted and the lists rebuilt only when some particle has moved far
+    # enough; the kernels' average over steps with and without a rebuild
+    vcfg = {"verlet_skin": VERLET_SKIN_3D}
+    rv = run_timed(wl, prec, args.steps_3d, 3, cfg=vcfg)
+    vstats, vpc = profile_kernels(wl, prec, 10, vcfg)
+    vper = {k: (ms / max(vpc["steps"], 1), cnt) for k, (ms, cnt) in vstats.items()}
+    verlet = {"verlet_skin": VERLET_SKIN_3D, "value": rv["interactions"] / rv["seconds"],
+              "ms_per_step": rv["seconds"] / args.steps_3d * 1e3, "list_builds": rv["builds"],
+              "kernel_us_per_step": {k: round(v[0] * 1e3, 2) for k, v in vper.items() if v[1]}}
     return {"workload": "cube_ball_3d", "n_particles": wl.n, "steps": args.steps_3d,
             "value": r["interactions"] / r["seconds"], "unit": "interactions/s",
             "ms_per_step": r["seconds"] / args.steps_3d * 1e3,
@@ -213,6 +231,7 @@ def cube_ball_leg(args):
             "kernel_support": wl.params["kernel_support"],
             "boundary_scale": wl.params["boundary_scale"],
             "other_precisions": others,
+            "verlet": verlet,
             "roofline": roofline("nbr_forces", byts, per["nbr_forces"][0] * 1e-3, ctr,
                                  per["nbr_forces"][1]),
             "kernel_avg_us": {k: round(v[0] * 1e3, 2) for k, v in per.items()}}
@@ -292,7 +311,7 @@ def ellipsoid_run(args):
     prec = binding.SPH_FP32_MIXED
     cfg, tuned = {}, None
     if not args.no_tune:
-        tr = autotune.tune([binding.JobSpec(wl)], 3, prec, steps=5, warmup=2)
+        tr = autotune.tune([binding.JobSpec(wl)], 3, prec, steps=10, warmup=2)
         cfg, tuned = tr.best, dict(best=tr.best, speedup_over_default=tr.speedup_over_default(),
                                    table=tr.table)
         print(f"[bench] tuned {json.dumps(cfg)}", file=sys.stderr, flush=True)
@@ -451,8 +470,9 @@ def serving(args):
             if not ds:
                 continue
             med = ds[len(ds) // 2]
+            # serving batches keep the cell scan (no Verlet lists): no skins
             r = autotune.tune([specs[med.idx]], d, binding.SPH_FP32_MIXED, steps=10, warmup=2,
-                              max_neighbors=320 if d == 3 else 104)
+                              max_neighbors=320 if d == 3 else 104, skins=())
             tuned[d] = r.best
             tuning[str(d)] = dict(job_particles=med.n, best=r.best,
                                   speedup_over_default=r.speedup_over_default())
@@ -522,7 +542,7 @@ def main():
                          "(each its own JSON line; not the headline)")
     ap.add_argument("--max-steps", type=int, default=6000,
                     help="step cap of the runs to the converged mesh")
-    ap.add_argument("--steps-3d", type=int, default=20,
+    ap.add_argument("--steps-3d", type=int, default=40,
                     help="timed steps of the 2M-particle 3D leg")
     ap.add_argument("--no-3d", action="store_true")
     ap.add_argument("--validation-cap", type=int, default=4000,

@@ -9,15 +9,20 @@ The knobs are the ones that change speed but not the method:
   rounding of the force sums, never the list itself.
 * ``scan_tile`` -- candidate records the neighbour scan loads and tests per
   pass (2, 4 or 8; per batch).  Results are bit-identical for every value.
+* ``verlet_skin`` -- reach of the Verlet candidate lists beyond the cut-off
+  radius, in units of h (0: a cell scan and a sort every step).  A wider skin
+  means fewer rebuilds but more candidates to filter every step.  The lists
+  are the cut-off lists whatever the skin; only the summation order changes.
 
 The workgroup size is fixed at 256 (the kernels' occupancy is bounded by
 their registers, and the per-wave accumulator stripes assume it) and the
 list format is ELL, so neither is searched.
 
-``tune`` times every configuration of the grid on a trial batch holding the
-given jobs (the graph-replayed step, after warm-up steps) and returns the
-fastest; ties keep the earlier (default-first) entry.  The timing source is
-injectable so that the selection logic is testable without a GPU.
+``tune`` times every (cell_factor, scan_tile) configuration of the grid on a
+trial batch holding the given jobs (the graph-replayed step, after warm-up
+steps), then the skins at the fastest of them, and returns the fastest; ties
+keep the earlier (default-first) entry.  The timing sources are injectable so
+that the selection logic is testable without a GPU.
 """
 from __future__ import annotations
 
@@ -26,9 +31,10 @@ import time
 from dataclasses import dataclass, field
 from typing import Callable, Optional, Sequence
 
-DEFAULT = {"cell_factor": 1.0, "scan_tile": 4}
+DEFAULT = {"cell_factor": 1.0, "scan_tile": 4, "verlet_skin": 0.0}
 CELL_FACTORS = (1.0, 0.75, 1.25)
 SCAN_TILES = (4, 2, 8)
+SKINS = (0.3, 0.5, 0.8)
 
 
 @dataclass
@@ -42,7 +48,8 @@ class TuneResult:
     def speedup_over_default(self):
         base = next(r["ms_per_step"] for r in self.table
                     if r["cell_factor"] == DEFAULT["cell_factor"]
-                    and r["scan_tile"] == DEFAULT["scan_tile"])
+                    and r["scan_tile"] == DEFAULT["scan_tile"]
+                    and r["verlet_skin"] == DEFAULT["verlet_skin"])
         return base / min(r["ms_per_step"] for r in self.table)
 
 
@@ -57,12 +64,13 @@ def with_cell_factor(spec, cf):
     return out
 
 
-def _time_config(specs, dim, precision, cf, tile, steps, warmup, max_neighbors):
+def _time_config(specs, dim, precision, cf, tile, steps, warmup, max_neighbors, skin=0.0):
     from . import binding
     sp = [with_cell_factor(s, cf) for s in specs]
     b = binding.SphBatch(dim, precision, max_particles=sum(s.n for s in sp),
                          max_cells=sum(s.cells() for s in sp), max_jobs=len(sp),
-                         max_neighbors=max_neighbors, use_graph=1, scan_tile=tile)
+                         max_neighbors=max_neighbors, use_graph=1, scan_tile=tile,
+                         verlet_skin=skin)
     try:
         for s in sp:
             b.add(s)
@@ -78,26 +86,44 @@ def _time_config(specs, dim, precision, cf, tile, steps, warmup, max_neighbors):
 
 def tune(specs: Sequence, dim: int, precision: int, cell_factors=CELL_FACTORS,
          scan_tiles=SCAN_TILES, steps=20, warmup=4, max_neighbors=0,
-         measure: Optional[Callable] = None, min_gain=0.02) -> TuneResult:
-    """Time every (cell_factor, scan_tile) pair on a batch of ``specs`` and
-    return the fastest; the default stays unless another configuration is
-    faster by more than ``min_gain`` (timing noise must not flip the choice).
-    ``measure(cf, tile) -> ms per step`` replaces the GPU timing when given."""
+         measure: Optional[Callable] = None, min_gain=0.02, skins=SKINS,
+         measure_skin: Optional[Callable] = None) -> TuneResult:
+    """Time every (cell_factor, scan_tile) pair on a batch of ``specs``, then
+    every skin at the fastest pair, and return the fastest; the default stays
+    unless another configuration is faster by more than ``min_gain`` (timing
+    noise must not flip the choice), and so does no skin.  ``measure(cf, tile)
+    -> ms per step`` and ``measure_skin(cf, tile, skin)`` replace the GPU
+    timing when given (an injected ``measure`` alone skips the skins)."""
     if not specs:
         raise ValueError("tune needs at least one job")
     if measure is None:
         def measure(cf, tile):
             return _time_config(specs, dim, precision, cf, tile, steps, warmup, max_neighbors)
+        if measure_skin is None:
+            def measure_skin(cf, tile, skin):
+                return _time_config(specs, dim, precision, cf, tile, steps, warmup,
+                                    max_neighbors, skin)
     grid = [(cf, t) for cf in cell_factors for t in scan_tiles]
     if (DEFAULT["cell_factor"], DEFAULT["scan_tile"]) not in grid:
         grid.insert(0, (DEFAULT["cell_factor"], DEFAULT["scan_tile"]))
     table = []
     for cf, t in grid:
-        table.append({"cell_factor": cf, "scan_tile": t, "ms_per_step": float(measure(cf, t))})
+        table.append({"cell_factor": cf, "scan_tile": t, "verlet_skin": 0.0,
+                      "ms_per_step": float(measure(cf, t))})
     best = min(table, key=lambda r: r["ms_per_step"])   # first minimum wins ties
     default = table[grid.index((DEFAULT["cell_factor"], DEFAULT["scan_tile"]))]
     if best["ms_per_step"] * (1.0 + min_gain) > default["ms_per_step"]:
         best = default
+    if measure_skin is not None:
+        for sk in skins:
+            r = {"cell_factor": best["cell_factor"], "scan_tile": best["scan_tile"],
+                 "verlet_skin": float(sk),
+                 "ms_per_step": float(measure_skin(best["cell_factor"], best["scan_tile"], sk))}
+            table.append(r)
+        with_skin = min(table[len(grid):], key=lambda r: r["ms_per_step"], default=None)
+        if with_skin is not None and with_skin["ms_per_step"] * (1.0 + min_gain) <= best["ms_per_step"]:
+            best = with_skin
     return TuneResult(dim, precision, int(sum(s.n for s in specs)),
-                      {"cell_factor": best["cell_factor"], "scan_tile": best["scan_tile"]},
+                      {"cell_factor": best["cell_factor"], "scan_tile": best["scan_tile"],
+                       "verlet_skin": best["verlet_skin"]},
                       table)

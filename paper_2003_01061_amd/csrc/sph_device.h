@@ -286,11 +286,11 @@ struct Batch {
   int skin_on, skin_cap;
   uint32_t *skin, *nsk;               // [skin_cap / 8][n][8] blocked like the list; counts
   double4 *xref;                      // [n] x and h at the last build
-  unsigned long long *vstate;         // [NSTRIPE] striped maxima of the displacement
-                                      // ratio, [VS_REBUILD] the rebuild flag,
-                                      // [VS_BUILDS] builds so far
+  unsigned long long *vstate;         // [VS_REBUILD] the rebuild flag, [VS_BUILDS]
+                                      // builds so far, [VS_TRIP] set by the
+                                      // integration when a particle moved too far
 };
-constexpr int VS_REBUILD = NSTRIPE, VS_BUILDS = NSTRIPE + 1, VS_WORDS = NSTRIPE + 2;
+constexpr int VS_REBUILD = 0, VS_BUILDS = 1, VS_TRIP = 2, VS_WORDS = 3;
 
 template <typename R>
 struct Vec4;

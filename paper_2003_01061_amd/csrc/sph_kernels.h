@@ -691,10 +691,20 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
         // covers the displacements since its build), so filtering it with the
         // same predicate gives the list the cell scan would
         const uint32_t ns = B.nsk[i];
+        const size_t sstep = (size_t)n * (LB / 4);
         const uint4 *sp = reinterpret_cast<const uint4 *>(B.skin) + (size_t)i * (LB / 4);
-        for (uint32_t b0 = 0; b0 < ns; b0 += LB, sp += (size_t)n * (LB / 4)) {
-          const uint4 w0 = sp[0], w1 = sp[1];
+        uint4 w0 = make_uint4(0u, 0u, 0u, 0u), w1 = w0;
+        if (ns > 0) {
+          w0 = sp[0];
+          w1 = sp[1];
+        }
+        for (uint32_t b0 = 0; b0 < ns; b0 += LB) {
           const uint32_t ub[LB] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
+          if (b0 + LB < ns) {   // the next block's entries, loaded ahead
+            sp += sstep;
+            w0 = sp[0];
+            w1 = sp[1];
+          }
 #pragma unroll
           for (int hb = 0; hb < LB; hb += NB) {
             float4 xr[NB];
@@ -1172,13 +1182,9 @@ __global__ __launch_bounds__(BLOCK) void k_control(Batch B) {
   }
   // Verlet lists: rebuild before the next step once some particle has moved
   // as far as its list's reach allows
-  if (B.skin_on && threadIdx.x < 64) {
-    unsigned long long m = take(B.vstate + threadIdx.x, 0ull);
-    for (int o = 32; o > 0; o >>= 1) {
-      const unsigned long long t = __shfl_xor(m, o);
-      m = t > m ? t : m;
-    }
-    if (threadIdx.x == 0) B.vstate[VS_REBUILD] = m > dbits(1.0) ? 1ull : 0ull;
+  if (B.skin_on && threadIdx.x == 0) {
+    B.vstate[VS_REBUILD] = B.vstate[VS_TRIP];
+    B.vstate[VS_TRIP] = 0ull;
   }
 }
 
@@ -1249,15 +1255,9 @@ __global__ __launch_bounds__(BLOCK) void k_integrate_hash(
   const uint32_t r = rank_in_cell(cc, i < n, cnt);
   if (i < n) rank[i] = r;
   wave_commit(escaped, job, 0ull, 1ull, nullptr, B.sesc);
-  if (B.skin_on) {   // striped maximum (non-negative doubles order as their bits)
-    unsigned long long m = dbits(moved);
-    for (int o = 32; o > 0; o >>= 1) {
-      const unsigned long long t = __shfl_xor(m, o);
-      m = t > m ? t : m;
-    }
-    if (__lane_id() == 0)
-      atomicMax(&B.vstate[(blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6)) & (NSTRIPE - 1)], m);
-  }
+  // a wave with a particle past its limit (or non-finite) raises the trip
+  // word; every writer stores the same value
+  if (B.skin_on && __ballot(!(moved <= 1.0)) && __lane_id() == 0) B.vstate[VS_TRIP] = 1ull;
 }
 
 // ---------------------------------------------------------------------------

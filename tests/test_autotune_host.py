@@ -11,7 +11,7 @@ class Spec:
 def test_picks_the_fastest_configuration():
     times = {(1.0, 4): 3.0, (0.75, 2): 2.0, (1.25, 8): 2.5}
     r = autotune.tune([Spec()], 2, 1, measure=lambda cf, t: times.get((cf, t), 9.0))
-    assert r.best == {"cell_factor": 0.75, "scan_tile": 2}
+    assert r.best == {"cell_factor": 0.75, "scan_tile": 2, "verlet_skin": 0.0}
     assert len(r.table) == len(autotune.CELL_FACTORS) * len(autotune.SCAN_TILES)
     assert r.speedup_over_default() == pytest.approx(1.5)
 
@@ -33,4 +33,22 @@ def test_a_gain_within_the_noise_keeps_the_default():
     r = autotune.tune([Spec()], 2, 1, measure=lambda cf, t: times.get((cf, t), 9.0))
     assert r.best == autotune.DEFAULT
     r = autotune.tune([Spec()], 2, 1, measure=lambda cf, t: times.get((cf, t), 9.0), min_gain=0.0)
-    assert r.best == {"cell_factor": 0.75, "scan_tile": 2}
+    assert r.best == {"cell_factor": 0.75, "scan_tile": 2, "verlet_skin": 0.0}
+
+
+def test_skins_are_timed_at_the_best_pair_and_kept_only_when_faster():
+    times = {(1.0, 4): 3.0, (0.75, 2): 2.0}
+    seen = []
+
+    def skin_time(cf, t, sk):
+        seen.append((cf, t, sk))
+        return {0.3: 1.9, 0.5: 1.5, 0.8: 1.7}[sk]
+    r = autotune.tune([Spec()], 3, 1, measure=lambda cf, t: times.get((cf, t), 9.0),
+                      measure_skin=skin_time)
+    assert seen == [(0.75, 2, sk) for sk in autotune.SKINS]
+    assert r.best == {"cell_factor": 0.75, "scan_tile": 2, "verlet_skin": 0.5}
+    assert r.speedup_over_default() == pytest.approx(2.0)
+    # a skin within the noise of the best pair is not taken
+    r = autotune.tune([Spec()], 3, 1, measure=lambda cf, t: times.get((cf, t), 9.0),
+                      measure_skin=lambda cf, t, sk: 1.99)
+    assert r.best["verlet_skin"] == 0.0
