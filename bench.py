@@ -77,10 +77,10 @@ def profiled_counters(cfg, path=COUNTERS_MD):
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         h.update(open(os.path.join(ROOT, f), "rb").read())
-    if float(cfg.get("verlet_skin", 0.0)) > 0.0:
-        return None   # the counters were taken on the cell-scan kernel
     want = "cell_factor={} scan_tile={}".format(float(cfg.get("cell_factor", 1.0)),
                                                 int(cfg.get("scan_tile", 4)))
+    if float(cfg.get("verlet_skin", 0.0)) > 0.0:   # the kernel that filters Verlet lists
+        want += " verlet_skin={}".format(float(cfg["verlet_skin"]))
     # one fenced block of "key: value" lines per profiled configuration
     for block in re.findall(r"```\n(kernel: .*?)```", text, flags=re.S):
         kv = dict(re.findall(r"^(\w+): (.+)$", block, flags=re.M))
@@ -526,6 +526,8 @@ def main():
                     help="cell factor of the 'step' counter pass")
     ap.add_argument("--pmc-scan-tile", type=int, default=4, choices=[2, 4, 8],
                     help="scan tile of the 'step' counter pass")
+    ap.add_argument("--pmc-skin", type=float, default=0.0,
+                    help="Verlet list skin of the counter passes (units of h; 0 = cell scan)")
     ap.add_argument("--pmc-precision", choices=["mixed", "compensated", "fp64"], default="mixed",
                     help="precision of the 'step' and 'step3d' counter passes")
     ap.add_argument("--no-converge", action="store_true",
@@ -583,7 +585,7 @@ def main():
                 "fp64": binding.SPH_FP64}[args.pmc_precision]
     if args.pmc_pass == "step3d":
         wl3 = wk.cube_ball()
-        j = binding.SphMesh(wl3, precision=pmc_prec, use_graph=0)
+        j = binding.SphMesh(wl3, precision=pmc_prec, use_graph=0, verlet_skin=args.pmc_skin)
         j.step(args.steps)
         j.sync()
         print(f"[bench] step3d pass: {args.steps} steps", file=sys.stderr, flush=True)
@@ -591,7 +593,8 @@ def main():
     wl = wk.square_hole(n_total=args.n)
     if args.pmc_pass == "step":
         j = binding.SphMesh(wl, precision=pmc_prec, use_graph=0,
-                            cell_factor=args.pmc_cell_factor, scan_tile=args.pmc_scan_tile)
+                            cell_factor=args.pmc_cell_factor, scan_tile=args.pmc_scan_tile,
+                            verlet_skin=args.pmc_skin)
         j.step(args.steps)
         j.sync()
         c = j.counters()

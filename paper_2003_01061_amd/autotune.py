@@ -20,7 +20,8 @@ list format is ELL, so neither is searched.
 
 ``tune`` times every (cell_factor, scan_tile) configuration of the grid on a
 trial batch holding the given jobs (the graph-replayed step, after warm-up
-steps), then the skins at the fastest of them, and returns the fastest; ties
+steps), then every (skin, scan_tile) pair at the fastest cell factor, and
+returns the fastest; ties
 keep the earlier (default-first) entry.  The timing sources are injectable so
 that the selection logic is testable without a GPU.
 """
@@ -89,7 +90,8 @@ def tune(specs: Sequence, dim: int, precision: int, cell_factors=CELL_FACTORS,
          measure: Optional[Callable] = None, min_gain=0.02, skins=SKINS,
          measure_skin: Optional[Callable] = None) -> TuneResult:
     """Time every (cell_factor, scan_tile) pair on a batch of ``specs``, then
-    every skin at the fastest pair, and return the fastest; the default stays
+    every (skin, scan_tile) pair at the fastest cell factor, and return the
+    fastest; the default stays
     unless another configuration is faster by more than ``min_gain`` (timing
     noise must not flip the choice), and so does no skin.  ``measure(cf, tile)
     -> ms per step`` and ``measure_skin(cf, tile, skin)`` replace the GPU
@@ -115,11 +117,12 @@ def tune(specs: Sequence, dim: int, precision: int, cell_factors=CELL_FACTORS,
     if best["ms_per_step"] * (1.0 + min_gain) > default["ms_per_step"]:
         best = default
     if measure_skin is not None:
+        # the filter's batches differ from the scan's, so the tile is searched again
         for sk in skins:
-            r = {"cell_factor": best["cell_factor"], "scan_tile": best["scan_tile"],
-                 "verlet_skin": float(sk),
-                 "ms_per_step": float(measure_skin(best["cell_factor"], best["scan_tile"], sk))}
-            table.append(r)
+            for t in scan_tiles:
+                r = {"cell_factor": best["cell_factor"], "scan_tile": t, "verlet_skin": float(sk),
+                     "ms_per_step": float(measure_skin(best["cell_factor"], t, sk))}
+                table.append(r)
         with_skin = min(table[len(grid):], key=lambda r: r["ms_per_step"], default=None)
         if with_skin is not None and with_skin["ms_per_step"] * (1.0 + min_gain) <= best["ms_per_step"]:
             best = with_skin

@@ -350,12 +350,14 @@ __global__ __launch_bounds__(BLOCK) void k_rank_gather(Batch B, int n, const uin
   }
   const double4 xh = a.xh[src];
   const uint32_t f = a.f[src];
-  b.xh[dst] = xh;
-  b.v[dst] = a.v[src];
   b.f[dst] = (uint16_t)f;
   b.oid[dst] = key;
-  b.xf[dst] = scan_record<D>(xh, f);
-  if (B.skin_on && sorted) B.xref[dst] = xh;
+  if (sorted) {   // without a re-sort the integration has written the rest already
+    b.xh[dst] = xh;
+    b.v[dst] = a.v[src];
+    b.xf[dst] = scan_record<D>(xh, f);
+    if (B.skin_on) B.xref[dst] = xh;
+  }
   // the normal out of the domain of a particle on a hole's boundary, for the
   // sweep that follows (computed there, it would hold registers inside the
   // neighbour loop): towards the centre of a disc or ball, against the level
@@ -1194,8 +1196,8 @@ __global__ __launch_bounds__(BLOCK) void k_control(Batch B) {
 // ---------------------------------------------------------------------------
 template <int D, typename R>
 __global__ __launch_bounds__(BLOCK) void k_integrate_hash(
-    Batch B, Parts s, const typename Vec4<R>::T *__restrict__ acc, uint32_t *__restrict__ cell,
-    uint32_t *__restrict__ rank, uint32_t *__restrict__ cnt) {
+    Batch B, Parts s, Parts o, const typename Vec4<R>::T *__restrict__ acc,
+    uint32_t *__restrict__ cell, uint32_t *__restrict__ rank, uint32_t *__restrict__ cnt) {
   const int n = B.n;
   const int i = blockIdx.x * BLOCK + threadIdx.x;
   bool escaped = false;
@@ -1208,10 +1210,10 @@ __global__ __launch_bounds__(BLOCK) void k_integrate_hash(
     const JobDev &J = B.jobs[job];
     const Feat F = B.feat[fi];
     double4 xh = s.xh[i];
+    double4 v4 = s.v[i];
     if (F.type != T_SI && B.grp[fi].active) {
       const double dt = bitsd(B.grp[fi].dt_bits);
       const auto a4 = acc[i];
-      const double4 v4 = s.v[i];
       const double a3[3] = {(double)a4.x, (double)a4.y, (double)a4.z};
       const double x[3] = {xh.x, xh.y, xh.z};
       const double v[3] = {v4.x, v4.y, v4.z};
@@ -1227,7 +1229,7 @@ __global__ __launch_bounds__(BLOCK) void k_integrate_hash(
         if (atomicExch(&B.st[job].nan_flag, 1u) == 0u) B.st[job].nan_oid = s.oid[i];
       } else if (F.kind == K_VOL && !inside<D>(J.g, xs)) {
         escaped = true;                                   // rejected move: stay, stop
-        s.v[i] = make_double4(0.0, 0.0, 0.0, 0.0);
+        v4 = make_double4(0.0, 0.0, 0.0, 0.0);
       } else {
         if (F.kind != K_VOL) project<D>(J.g, F, xs);
         // the velocity carried into the next step is v^{n+1/2}, tangent to
@@ -1238,13 +1240,22 @@ __global__ __launch_bounds__(BLOCK) void k_integrate_hash(
         xh.x = xs[0];
         xh.y = xs[1];
         if (D == 3) xh.z = xs[2];
-        s.v[i] = make_double4(vn[0], vn[1], D == 3 ? vn[2] : 0.0, 0.0);
+        v4 = make_double4(vn[0], vn[1], D == 3 ? vn[2] : 0.0, 0.0);
       }
     }
     hash_one<D>(J.g, J.G, xh, cc);
+    const float4 rec = scan_record<D>(xh, (uint32_t)fi);
     s.xh[i] = xh;
-    s.xf[i] = scan_record<D>(xh, (uint32_t)fi);
+    s.v[i] = v4;
+    s.xf[i] = rec;
     cell[i] = cc;
+    if (B.skin_on) {
+      // the other buffer gets the same state, so that a step without a
+      // re-sort only has to carry the feature and caller ids over
+      o.xh[i] = xh;
+      o.v[i] = v4;
+      o.xf[i] = rec;
+    }
     if (B.skin_on) {   // displacement since the Verlet list's build, in units of its limit
       const double4 r = B.xref[i];
       const double d0 = xh.x - r.x, d1 = xh.y - r.y, d2 = D == 3 ? xh.z - r.z : 0.0;

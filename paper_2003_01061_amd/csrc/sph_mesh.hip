@@ -782,7 +782,7 @@ struct sph_batch {
                   (const uint32_t *)nnb, (const R4 *)ap, (const R4 *)mid, (R4 *)acc, dbg_vm));
     HIPCHK(launch(KID_REDUCE_B, k_group_reduce, gslots, BLOCK, B, 1));
     HIPCHK(launch(KID_INTEGRATE_HASH, k_integrate_hash<DD, R>, blocks(n), BLOCK, B, s,
-                  (const R4 *)acc, cell, rank, cnt));
+                  P[1 - cur], (const R4 *)acc, cell, rank, cnt));
     HIPCHK(launch(KID_CONTROL, k_control, 1u, BLOCK, B));
     return SPH_OK;
   }

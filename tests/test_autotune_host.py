@@ -42,11 +42,11 @@ def test_skins_are_timed_at_the_best_pair_and_kept_only_when_faster():
 
     def skin_time(cf, t, sk):
         seen.append((cf, t, sk))
-        return {0.3: 1.9, 0.5: 1.5, 0.8: 1.7}[sk]
+        return {0.3: 1.9, 0.5: 1.5, 0.8: 1.7}[sk] + (0.0 if t == 8 else 0.1)
     r = autotune.tune([Spec()], 3, 1, measure=lambda cf, t: times.get((cf, t), 9.0),
                       measure_skin=skin_time)
-    assert seen == [(0.75, 2, sk) for sk in autotune.SKINS]
-    assert r.best == {"cell_factor": 0.75, "scan_tile": 2, "verlet_skin": 0.5}
+    assert seen == [(0.75, t, sk) for sk in autotune.SKINS for t in autotune.SCAN_TILES]
+    assert r.best == {"cell_factor": 0.75, "scan_tile": 8, "verlet_skin": 0.5}
     assert r.speedup_over_default() == pytest.approx(2.0)
     # a skin within the noise of the best pair is not taken
     r = autotune.tune([Spec()], 3, 1, measure=lambda cf, t: times.get((cf, t), 9.0),

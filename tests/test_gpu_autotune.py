@@ -47,7 +47,9 @@ def test_tuned_configuration_runs_and_matches_the_oracle():
     wl = wk.scaled_hole_2d(20011, seed=63)
     spec = binding.JobSpec(wl)
     r = autotune.tune([spec], 2, binding.SPH_FP64, steps=6, warmup=2)
-    assert len(r.table) == 9 and all(t["ms_per_step"] > 0 for t in r.table)
+    n_grid = len(autotune.CELL_FACTORS) * len(autotune.SCAN_TILES)
+    assert len(r.table) == n_grid + len(autotune.SKINS) * len(autotune.SCAN_TILES)
+    assert all(t["ms_per_step"] > 0 for t in r.table)
     best = r.best
     g = binding.SphMesh(wl, use_graph=1, **best)
     g.step(20)
