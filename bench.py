@@ -115,15 +115,15 @@ def run_timed(wl, precision, steps, warmup, graph=True, cfg=None):
     from paper_2003_01061_amd import binding
     import torch
     cfg = cfg or {}
-    if warmup:
-        w = binding.SphMesh(wl, precision=precision, use_graph=int(graph), **cfg)
-        w.step(warmup)
-        w.sync()
-        w.close()
     torch.cuda.synchronize()
     tc = time.perf_counter()
     j = binding.SphMesh(wl, precision=precision, use_graph=int(graph), **cfg)
     j.sync()
+    tw = time.perf_counter()
+    # the warmup steps (untimed) also capture the step graphs
+    j.step(warmup)
+    j.sync()
+    c0 = j.counters()["interactions"]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     j.step(steps)
@@ -138,7 +138,8 @@ def run_timed(wl, precision, steps, warmup, graph=True, cfg=None):
     j.close()
     # seconds: the timed region (inputs resident in HBM); with_io adds the
     # creation (host -> device copy, initial hash) and the host copy of the result
-    return dict(seconds=t1 - t0, seconds_with_io=t2 - tc, interactions=c["interactions"],
+    interactions = c["interactions"] - c0
+    return dict(seconds=t1 - t0, seconds_with_io=(tw - tc) + (t2 - t0), interactions=interactions,
                 escaped=c["escaped"], steps=c["steps"], e_sys=e["e_sys"], phase=e["phase"],
                 converged=e["converged"], positions=x, builds=builds)
 
@@ -221,9 +222,16 @@ def cube_ball_leg(args):
     rv = run_timed(wl, prec, args.steps_3d, 3, cfg=vcfg)
     vstats, vpc = profile_kernels(wl, prec, 10, vcfg)
     vper = {k: (ms / max(vpc["steps"], 1), cnt) for k, (ms, cnt) in vstats.items()}
+    # the filter kernel's roofline: the same algorithmic bytes (its candidate
+    # lists are extra traffic of the Verlet scheme, counted in "traffic")
+    vms, vcnt = vstats["nbr_forces"]
+    vinter = vpc["interactions"] / max(vpc["steps"], 1)
     verlet = {"verlet_skin": VERLET_SKIN_3D, "value": rv["interactions"] / rv["seconds"],
               "ms_per_step": rv["seconds"] / args.steps_3d * 1e3, "list_builds": rv["builds"],
-              "kernel_us_per_step": {k: round(v[0] * 1e3, 2) for k, v in vper.items() if v[1]}}
+              "kernel_us_per_step": {k: round(v[0] * 1e3, 2) for k, v in vper.items() if v[1]},
+              "roofline": roofline("nbr_forces", kernel_bytes("nbr_forces", wl, n_active, vinter, 4),
+                                   vms / max(vcnt, 1) * 1e-3, profiled_counters(vcfg, COUNTERS_3D_MD),
+                                   vcnt)}
     return {"workload": "cube_ball_3d", "n_particles": wl.n, "steps": args.steps_3d,
             "value": r["interactions"] / r["seconds"], "unit": "interactions/s",
             "ms_per_step": r["seconds"] / args.steps_3d * 1e3,
@@ -310,7 +318,9 @@ def ellipsoid_run(args):
           file=sys.stderr, flush=True)
     prec = binding.SPH_FP32_MIXED
     cfg, tuned = {}, None
-    if not args.no_tune:
+    if args.config is not None:
+        cfg = json.loads(args.config)
+    elif not args.no_tune:
         tr = autotune.tune([binding.JobSpec(wl)], 3, prec, steps=10, warmup=2)
         cfg, tuned = tr.best, dict(best=tr.best, speedup_over_default=tr.speedup_over_default(),
                                    table=tr.table)
@@ -522,6 +532,9 @@ def main():
     ap.add_argument("--n", type=int, default=250_000)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--config", type=str, default=None,
+                    help="JSON tuning of the headline job (cell_factor, scan_tile, verlet_skin) "
+                         "used instead of the autotuner's choice, e.g. for profiling runs")
     ap.add_argument("--pmc-cell-factor", type=float, default=1.0,
                     help="cell factor of the 'step' counter pass")
     ap.add_argument("--pmc-scan-tile", type=int, default=4, choices=[2, 4, 8],
@@ -603,7 +616,9 @@ def main():
         return
     print(f"[bench] workload square_hole n={wl.n} scale={wl.scale:.4f}", file=sys.stderr, flush=True)
     cfg, tuned = {}, None
-    if not args.no_tune:
+    if args.config is not None:
+        cfg = json.loads(args.config)
+    elif not args.no_tune:
         from paper_2003_01061_amd import autotune
         t = autotune.tune([binding.JobSpec(wl)], 2, binding.SPH_FP32_MIXED, steps=20, warmup=4)
         cfg = t.best

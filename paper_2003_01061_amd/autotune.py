@@ -21,8 +21,9 @@ list format is ELL, so neither is searched.
 ``tune`` times every (cell_factor, scan_tile) configuration of the grid on a
 trial batch holding the given jobs (the graph-replayed step, after warm-up
 steps), then every (skin, scan_tile) pair at the fastest cell factor, and
-returns the fastest; ties
-keep the earlier (default-first) entry.  The timing sources are injectable so
+returns the fastest; ties keep the earlier (default-first) entry, and a
+configuration replaces the default (or, at a skin, the best pair's tile) only
+when it is faster by more than a noise margin.  The timing sources are injectable so
 that the selection logic is testable without a GPU.
 """
 from __future__ import annotations
@@ -123,7 +124,16 @@ def tune(specs: Sequence, dim: int, precision: int, cell_factors=CELL_FACTORS,
                 r = {"cell_factor": best["cell_factor"], "scan_tile": t, "verlet_skin": float(sk),
                      "ms_per_step": float(measure_skin(best["cell_factor"], t, sk))}
                 table.append(r)
-        with_skin = min(table[len(grid):], key=lambda r: r["ms_per_step"], default=None)
+        # per skin, the tile of the best pair unless another tile beats it by
+        # more than min_gain (so timing noise between near-equal tiles does
+        # not decide); then the fastest skin
+        per_skin = []
+        for sk in skins:
+            rows = [r for r in table[len(grid):] if r["verlet_skin"] == float(sk)]
+            ref = next((r for r in rows if r["scan_tile"] == best["scan_tile"]), rows[0])
+            fast = min(rows, key=lambda r: r["ms_per_step"])
+            per_skin.append(fast if fast["ms_per_step"] * (1.0 + min_gain) <= ref["ms_per_step"] else ref)
+        with_skin = min(per_skin, key=lambda r: r["ms_per_step"], default=None)
         if with_skin is not None and with_skin["ms_per_step"] * (1.0 + min_gain) <= best["ms_per_step"]:
             best = with_skin
     return TuneResult(dim, precision, int(sum(s.n for s in specs)),

@@ -25,8 +25,14 @@ constexpr int MAXRING = 64;     // samples per averaging window
 constexpr int BLOCK = 256;
 constexpr int NSTRIPE = 64;     // copies of each atomic accumulator (spreads contention)
 
-// tuning knobs (compile time): records loaded together per neighbour batch,
-// and whether blocks are remapped so that each XCD gets a contiguous range
+// tuning knobs (compile time): entries of a particle's neighbour list the
+// neighbour kernel keeps in LDS for its pair sums (a multiple of LB; 256
+// threads x 32 x 4 bytes = 32 KB per block), records loaded together per
+// neighbour batch, and whether blocks are remapped so that each XCD gets a
+// contiguous range
+#ifndef SPH_LDS_LIST
+#define SPH_LDS_LIST 32
+#endif
 #ifndef SPH_NBATCH
 #define SPH_NBATCH 4
 #endif

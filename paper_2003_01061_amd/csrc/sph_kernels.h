@@ -420,7 +420,9 @@ __host__ __device__ __forceinline__ void sweep_a_sums(const Geom &g, const Parts
                                              double klen, double bscale,
                                              const uint32_t *__restrict__ nbr, int n, int i,
                                              uint32_t cnt, const double4 &xi, int fi, bool pair_normals,
-                                             double &S, double &gam, double Pi[3], double B[3]) {
+                                             double &S, double &gam, double Pi[3], double B[3],
+                                             const uint32_t *ring = nullptr, uint32_t ring_len = 0,
+                                             uint32_t ring_stride = 0) {
   // h enters rho_t = h^-k; the kernel is evaluated at the smoothing length
   // klen h (cut-off radius 2 klen h)
   const R hi = (R)xi.w;
@@ -440,17 +442,33 @@ __host__ __device__ __forceinline__ void sweep_a_sums(const Geom &g, const Parts
     aB[a].init(0.0);
   }
   constexpr int NB = SPH_NBATCH;
-  static_assert(LB % NB == 0, "record batches tile a list block");
-  const uint4 *blk = reinterpret_cast<const uint4 *>(nbr) + (size_t)i * (LB / 4);
-  for (uint32_t b0 = 0; b0 < cnt; b0 += LB, blk += (size_t)n * (LB / 4)) {
-    const uint4 w0 = blk[0], w1 = blk[1];
-    const uint32_t ub[LB] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
-#pragma unroll
-    for (int hb = 0; hb < LB; hb += NB) {
-      const uint32_t e0 = b0 + hb;
+  static_assert(NB == 4 || NB == LB, "record batches of 4 or 8 tile a list block");
+  // The list's last entries may also sit in the caller's LDS ring (entry e
+  // in slot e % ring_len, column stride ring_stride): entries from lbase on
+  // are read there, the ones before from the list in memory (whole blocks,
+  // as lbase is a multiple of LB).  Either way every entry is read in list
+  // order, so the sums are the same.
+  uint32_t lbase = cnt;
+  if (ring != nullptr) lbase = cnt > ring_len ? (cnt - ring_len + LB - 1) / LB * LB : 0u;
+  const uint4 *gl = reinterpret_cast<const uint4 *>(nbr) + (size_t)i * (LB / 4);
+  for (uint32_t e0 = 0; e0 < cnt; e0 += NB) {
+    {
       uint32_t u[NB];
+      if (e0 < lbase) {   // NB entries of a block in memory: 16-byte loads
 #pragma unroll
-      for (int q = 0; q < NB; ++q) u[q] = e0 + q < cnt ? ub[hb + q] : 0u;
+        for (int h = 0; h < NB / 4; ++h) {
+          const uint4 w = gl[(size_t)(e0 / LB) * n * (LB / 4) + (e0 % LB) / 4 + h];
+          u[4 * h] = w.x;
+          u[4 * h + 1] = w.y;
+          u[4 * h + 2] = w.z;
+          u[4 * h + 3] = w.w;
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < NB; ++q) u[q] = ring[((e0 + q) % ring_len) * ring_stride];
+      }
+#pragma unroll
+      for (int q = 0; q < NB; ++q) u[q] = e0 + q < cnt ? u[q] : 0u;
       double4 xr[NB];
 #pragma unroll
       for (int q = 0; q < NB; ++q) xr[q] = s.xh[u[q] & 0x7fffffffu];
@@ -597,6 +615,15 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
     if (blockIdx.x == 0 && threadIdx.x == 0) B.vstate[VS_BUILDS] += 1ull;
   }
   using R4 = typename Vec4<R>::T;
+  // hits collect in the thread's own column of an LDS ring of LR entries (a
+  // multiple of LB; see the append below); it keeps the last LR entries, so
+  // that in the FP32 modes a list no longer than LR stays whole in LDS,
+  // where the pair sums read it (the FP64 sums read the list from memory:
+  // the ring's addressing would cost them a wave per SIMD)
+  constexpr bool LDS_SUMS = FORCES && sizeof(R) == 4;
+  constexpr int LR = LDS_SUMS ? SPH_LDS_LIST : LB;
+  static_assert(LR % LB == 0, "the ring holds whole blocks");
+  __shared__ uint32_t ring[LR][BLOCK];
   const int n = B.n;
   const int i = xcd_block() * BLOCK + threadIdx.x;
   bool act = false;
@@ -677,14 +704,13 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
         cout = (float)((1.0 + w) * (1.0 + w) * k2);
       }
       static_assert(NB >= 1 && NB <= 8, "records are padded by 8");
-      // hits collect in the thread's own column of an LDS ring of LB entries
-      // (entry-major, so the lanes of a wave hit distinct banks whatever
-      // their fill), stored as one 32-byte sector when full (and once more,
-      // partly filled, at the end).  One LDS write per hit replaces a
-      // select over LB registers, which every lane would execute whenever
-      // any lane of the wave hits.
+      // hits collect in the thread's own column of the LDS ring (entry-major,
+      // so the lanes of a wave hit distinct banks whatever their fill); each
+      // block of LB entries is stored as one 32-byte sector when full (and
+      // the last once more, partly filled, at the end).  One LDS write per
+      // hit replaces a select over LB registers, which every lane would
+      // execute whenever any lane of the wave hits.
       static_assert(LB == 8, "the ring is flushed as two 16-byte stores");
-      __shared__ uint32_t ring[LB][BLOCK];
       uint4 *wp = reinterpret_cast<uint4 *>(MODE == 1 ? B.skin : nbr) + (size_t)i * (LB / 4);
       const uint32_t wstep = (uint32_t)n * (LB / 4);
       const uint32_t nblk = (uint32_t)(MODE == 1 ? B.skin_cap : B.cap) / LB;   // blocks of capacity
@@ -736,14 +762,15 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
 #pragma unroll
             for (int q = 0; q < NB; ++q) {
               if (tag[q] != 0xffffffffu) {
-                const uint32_t k = count % LB;
+                const uint32_t k = count % LR;
                 ring[k][threadIdx.x] = tag[q];
                 ++count;
-                if (k == LB - 1 && count / LB <= nblk) {
-                  wp[0] = make_uint4(ring[0][threadIdx.x], ring[1][threadIdx.x],
-                                     ring[2][threadIdx.x], ring[3][threadIdx.x]);
-                  wp[1] = make_uint4(ring[4][threadIdx.x], ring[5][threadIdx.x],
-                                     ring[6][threadIdx.x], ring[7][threadIdx.x]);
+                if (k % LB == LB - 1 && count / LB <= nblk) {
+                  const uint32_t k0 = k - (LB - 1);
+                  wp[0] = make_uint4(ring[k0][threadIdx.x], ring[k0 + 1][threadIdx.x],
+                                     ring[k0 + 2][threadIdx.x], ring[k0 + 3][threadIdx.x]);
+                  wp[1] = make_uint4(ring[k0 + 4][threadIdx.x], ring[k0 + 5][threadIdx.x],
+                                     ring[k0 + 6][threadIdx.x], ring[k0 + 7][threadIdx.x]);
                   wp += wstep;
                 }
               }
@@ -836,14 +863,15 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
   #pragma unroll
               for (int q = 0; q < NB; ++q) {
                 if (tag[q] != 0xffffffffu) {
-                  const uint32_t k = count % LB;
+                  const uint32_t k = count % LR;
                   ring[k][threadIdx.x] = tag[q];
                   ++count;
-                  if (k == LB - 1 && count / LB <= nblk) {
-                    wp[0] = make_uint4(ring[0][threadIdx.x], ring[1][threadIdx.x],
-                                       ring[2][threadIdx.x], ring[3][threadIdx.x]);
-                    wp[1] = make_uint4(ring[4][threadIdx.x], ring[5][threadIdx.x],
-                                       ring[6][threadIdx.x], ring[7][threadIdx.x]);
+                  if (k % LB == LB - 1 && count / LB <= nblk) {
+                    const uint32_t k0 = k - (LB - 1);
+                    wp[0] = make_uint4(ring[k0][threadIdx.x], ring[k0 + 1][threadIdx.x],
+                                       ring[k0 + 2][threadIdx.x], ring[k0 + 3][threadIdx.x]);
+                    wp[1] = make_uint4(ring[k0 + 4][threadIdx.x], ring[k0 + 5][threadIdx.x],
+                                       ring[k0 + 6][threadIdx.x], ring[k0 + 7][threadIdx.x]);
                     wp += wstep;
                   }
                 }
@@ -853,10 +881,11 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
         }
       }
       if (count % LB != 0 && count / LB < nblk) {   // the last, partly filled block
-        wp[0] = make_uint4(ring[0][threadIdx.x], ring[1][threadIdx.x], ring[2][threadIdx.x],
-                           ring[3][threadIdx.x]);
-        wp[1] = make_uint4(ring[4][threadIdx.x], ring[5][threadIdx.x], ring[6][threadIdx.x],
-                           ring[7][threadIdx.x]);
+        const uint32_t k0 = (count / LB * LB) % LR;
+        wp[0] = make_uint4(ring[k0][threadIdx.x], ring[k0 + 1][threadIdx.x], ring[k0 + 2][threadIdx.x],
+                           ring[k0 + 3][threadIdx.x]);
+        wp[1] = make_uint4(ring[k0 + 4][threadIdx.x], ring[k0 + 5][threadIdx.x], ring[k0 + 6][threadIdx.x],
+                           ring[k0 + 7][threadIdx.x]);
       }
       if (MODE == 1 && (int)count > B.skin_cap) {
         atomicMax(&B.st[job].skin_max, count);
@@ -880,11 +909,14 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
       const bool pairn = D == 3 && F.kind == K_LEVEL && J.g.cpts != nullptr;
       double S, gam, Pi[3], B3[3];
       if (k == D)
-        sweep_a_sums<D, D, R, CMP>(J.g, s, B.enrm, bnrow, J.bw, J.p0, J.klen, J.bscale, nbr, n, i, count, xi, fi, pairn, S, gam, Pi, B3);
+        sweep_a_sums<D, D, R, CMP>(J.g, s, B.enrm, bnrow, J.bw, J.p0, J.klen, J.bscale, nbr, n, i, count, xi, fi, pairn, S, gam, Pi, B3,
+                                        LDS_SUMS ? &ring[0][threadIdx.x] : nullptr, LR, BLOCK);
       else if (k == D - 1)
-        sweep_a_sums<D, D - 1, R, CMP>(J.g, s, B.enrm, bnrow, J.bw, J.p0, J.klen, J.bscale, nbr, n, i, count, xi, fi, pairn, S, gam, Pi, B3);
+        sweep_a_sums<D, D - 1, R, CMP>(J.g, s, B.enrm, bnrow, J.bw, J.p0, J.klen, J.bscale, nbr, n, i, count, xi, fi, pairn, S, gam, Pi, B3,
+                                        LDS_SUMS ? &ring[0][threadIdx.x] : nullptr, LR, BLOCK);
       else
-        sweep_a_sums<D, 1, R, CMP>(J.g, s, B.enrm, bnrow, J.bw, J.p0, J.klen, J.bscale, nbr, n, i, count, xi, fi, pairn, S, gam, Pi, B3);
+        sweep_a_sums<D, 1, R, CMP>(J.g, s, B.enrm, bnrow, J.bw, J.p0, J.klen, J.bscale, nbr, n, i, count, xi, fi, pairn, S, gam, Pi, B3,
+                                        LDS_SUMS ? &ring[0][threadIdx.x] : nullptr, LR, BLOCK);
       double a3[3] = {0.0, 0.0, 0.0};
 #pragma unroll
       for (int a = 0; a < D; ++a) a3[a] = -((Pi[a] + B3[a]) / gam);

@@ -595,7 +595,11 @@ struct sph_batch {
   std::vector<HostJob> jobs;
   int n = 0, njobs = 0;
   uint32_t ncell = 0;
-  hipGraphExec_t gexec = nullptr;
+  // captured step graphs: GRAPH_LONG steps and 2 steps (both start and end at
+  // buffer parity 0); long runs replay the long one, so the gap the runtime
+  // leaves between two graph launches comes once per GRAPH_LONG steps
+  static constexpr int GRAPH_LONG = 16;
+  hipGraphExec_t gexec = nullptr, gexec_long = nullptr;
   // profiling
   bool profiling = false;
   struct Ev {
@@ -610,6 +614,7 @@ struct sph_batch {
   ~sph_batch() {
     if (stream) (void)hipStreamSynchronize(stream);
     if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (gexec_long) (void)hipGraphExecDestroy(gexec_long);
     for (auto &e : ev_live) {
       (void)hipEventDestroy(e.a);
       (void)hipEventDestroy(e.b);
@@ -664,7 +669,8 @@ struct sph_batch {
 
   void invalidate_graph() {
     if (gexec) (void)hipGraphExecDestroy(gexec);
-    gexec = nullptr;
+    if (gexec_long) (void)hipGraphExecDestroy(gexec_long);
+    gexec = gexec_long = nullptr;
   }
 
   hipEvent_t get_event() {
@@ -799,13 +805,14 @@ struct sph_batch {
                                           : enqueue_forces<3, float>();
   }
 
-  sph_status build_graph() {
-    if (gexec) return SPH_OK;
+  // capture `steps` (even) steps into *out, unless already captured
+  sph_status build_graph(hipGraphExec_t *out, int steps) {
+    if (*out) return SPH_OK;
     const int saved = cur;
     hipGraph_t graph = nullptr;
     HIPCHK(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
-    sph_status st = enqueue_step();
-    if (!st) st = enqueue_step();
+    sph_status st = SPH_OK;
+    for (int k = 0; k < steps && !st; ++k) st = enqueue_step();
     hipError_t e = hipStreamEndCapture(stream, &graph);
     cur = saved;
     if (st) {
@@ -813,10 +820,10 @@ struct sph_batch {
       return st;
     }
     if (e != hipSuccess) return fail(SPH_ERR_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
-    e = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e != hipSuccess) {
-      gexec = nullptr;
+      *out = nullptr;
       return fail(SPH_ERR_DEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
     }
     return SPH_OK;
@@ -831,7 +838,11 @@ struct sph_batch {
         --left;
       }
       if (left >= 2) {
-        if (sph_status st = build_graph()) return st;
+        // both graphs are captured on first use, so that a later, longer
+        // call does not capture inside its run
+        if (sph_status st = build_graph(&gexec, 2)) return st;
+        if (sph_status st = build_graph(&gexec_long, GRAPH_LONG)) return st;
+        for (; left >= GRAPH_LONG; left -= GRAPH_LONG) HIPCHK(hipGraphLaunch(gexec_long, stream));
         for (; left >= 2; left -= 2) HIPCHK(hipGraphLaunch(gexec, stream));
       }
     }

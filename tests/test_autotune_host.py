@@ -52,3 +52,14 @@ def test_skins_are_timed_at_the_best_pair_and_kept_only_when_faster():
     r = autotune.tune([Spec()], 3, 1, measure=lambda cf, t: times.get((cf, t), 9.0),
                       measure_skin=lambda cf, t, sk: 1.99)
     assert r.best["verlet_skin"] == 0.0
+
+
+def test_at_a_skin_a_tile_within_the_noise_keeps_the_best_pairs_tile():
+    times = {(1.0, 4): 3.0}
+
+    def skin_time(cf, t, sk):
+        # skin 0.8 is the fastest; at it tile 8 is 1% faster than tile 4
+        return {0.3: 2.5, 0.5: 2.2, 0.8: 2.0}[sk] - (0.02 if t == 8 else 0.0)
+    r = autotune.tune([Spec()], 2, 1, measure=lambda cf, t: times.get((cf, t), 9.0),
+                      measure_skin=skin_time)
+    assert r.best == {"cell_factor": 1.0, "scan_tile": 4, "verlet_skin": 0.8}

@@ -368,6 +368,7 @@ def test_graph_replay_equals_eager_and_is_deterministic():
         g = binding.SphMesh(wl, use_graph=graph)
         g.step(7)          # odd count: one eager step, then graph pairs
         g.step(6)
+        g.step(37)         # one eager step, two 16-step graphs, two pairs
         runs.append(g.positions())
     assert np.array_equal(runs[0], runs[1])
     assert np.array_equal(runs[1], runs[2])
