@@ -319,9 +319,11 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(int n, const uint32_t *__rest
 
 // Entry u of a cell (filled in atomic order) finds its rank among the cell's
 // caller ids and copies its particle to that slot; the first entry of a cell
-// clears the cell's count for the next hash.  With Verlet candidate lists and
-// no rebuild due, every particle keeps its slot (a plain copy) and clears
-// its cell's count; at a rebuild the new slot also records x and h.
+// clears the cell's count for the next hash.  With Verlet candidate lists the
+// particles live in buffer a between rebuilds: with no rebuild due, every
+// particle keeps its slot, clears its cell's count and refreshes its boundary
+// normal; at a rebuild the sorted copy goes to b (whose slot also records x
+// and h), and the list build copies it back into a.
 template <int D>
 __global__ __launch_bounds__(BLOCK) void k_rank_gather(Batch B, int n, const uint32_t *__restrict__ psrc,
                                                        const uint32_t *__restrict__ pkey,
@@ -332,27 +334,26 @@ __global__ __launch_bounds__(BLOCK) void k_rank_gather(Batch B, int n, const uin
   const int u = blockIdx.x * BLOCK + threadIdx.x;
   if (u >= n) return;
   const bool sorted = !B.skin_on || B.vstate[VS_REBUILD] != 0ull;
-  uint32_t src = (uint32_t)u, dst = (uint32_t)u, key;
+  uint32_t src = (uint32_t)u, dst = (uint32_t)u;
   if (sorted) {
     src = psrc[u];
     if (src >= (uint32_t)n) return;
     const uint32_t c = cell[src];
     const uint32_t lo = cstart[c], hi = cstart[c + 1];
-    key = pkey[u];
+    const uint32_t key = pkey[u];
     uint32_t r = 0;
     for (uint32_t v = lo; v < hi; ++v) r += pkey[v] < key ? 1u : 0u;
     if ((uint32_t)u == lo) cnt[c] = 0u;
     dst = lo + r;
     if (dst >= (uint32_t)n) return;
+    b.oid[dst] = key;
   } else {
-    key = a.oid[u];
     cnt[cell[u]] = 0u;
   }
   const double4 xh = a.xh[src];
   const uint32_t f = a.f[src];
-  b.f[dst] = (uint16_t)f;
-  b.oid[dst] = key;
-  if (sorted) {   // without a re-sort the integration has written the rest already
+  if (sorted) {   // without a re-sort the particle stays where it is, in a
+    b.f[dst] = (uint16_t)f;
     b.xh[dst] = xh;
     b.v[dst] = a.v[src];
     b.xf[dst] = scan_record<D>(xh, f);
@@ -608,11 +609,21 @@ template <int D, typename R, bool FORCES, int NB, bool CMP = false, int MODE = 0
 __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
     Batch B, Parts s, const uint32_t *__restrict__ cstart, int all, uint32_t *__restrict__ nbr,
     uint32_t *__restrict__ nnb, typename Vec4<R>::T *__restrict__ ap,
-    double *__restrict__ dbg_gam, double *__restrict__ dbg_vt) {
+    double *__restrict__ dbg_gam, double *__restrict__ dbg_vt, Parts home) {
   static_assert(MODE == 0 || (MODE == 1 && !FORCES) || MODE == 2, "candidate list modes");
   if (MODE == 1) {
     if (B.vstate[VS_REBUILD] == 0ull) return;
     if (blockIdx.x == 0 && threadIdx.x == 0) B.vstate[VS_BUILDS] += 1ull;
+    // s holds the particles just sorted; they go back to the buffer the
+    // steps use between rebuilds (no kernel of this launch reads it)
+    const int c = xcd_block() * BLOCK + threadIdx.x;
+    if (c < B.n) {
+      home.xh[c] = s.xh[c];
+      home.v[c] = s.v[c];
+      home.f[c] = s.f[c];
+      home.oid[c] = s.oid[c];
+      home.xf[c] = s.xf[c];
+    }
   }
   using R4 = typename Vec4<R>::T;
   // hits collect in the thread's own column of an LDS ring of LR entries (a
@@ -1228,7 +1239,7 @@ __global__ __launch_bounds__(BLOCK) void k_control(Batch B) {
 // ---------------------------------------------------------------------------
 template <int D, typename R>
 __global__ __launch_bounds__(BLOCK) void k_integrate_hash(
-    Batch B, Parts s, Parts o, const typename Vec4<R>::T *__restrict__ acc,
+    Batch B, Parts s, const typename Vec4<R>::T *__restrict__ acc,
     uint32_t *__restrict__ cell, uint32_t *__restrict__ rank, uint32_t *__restrict__ cnt) {
   const int n = B.n;
   const int i = blockIdx.x * BLOCK + threadIdx.x;
@@ -1281,13 +1292,6 @@ __global__ __launch_bounds__(BLOCK) void k_integrate_hash(
     s.v[i] = v4;
     s.xf[i] = rec;
     cell[i] = cc;
-    if (B.skin_on) {
-      // the other buffer gets the same state, so that a step without a
-      // re-sort only has to carry the feature and caller ids over
-      o.xh[i] = xh;
-      o.v[i] = v4;
-      o.xf[i] = rec;
-    }
     if (B.skin_on) {   // displacement since the Verlet list's build, in units of its limit
       const double4 r = B.xref[i];
       const double d0 = xh.x - r.x, d1 = xh.y - r.y, d2 = D == 3 ? xh.z - r.z : 0.0;

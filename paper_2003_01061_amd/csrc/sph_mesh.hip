@@ -737,7 +737,9 @@ struct sph_batch {
       HIPCHK(launch(KID_RANK_GATHER, k_rank_gather<3>, blocks(n), BLOCK, B, n, (const uint32_t *)psrc,
                     (const uint32_t *)pkey, (const uint32_t *)cell, (const uint32_t *)cstart, cnt,
                     P[cur], P[1 - cur]));
-    cur = 1 - cur;
+    // with Verlet lists the particles stay in P[cur]: a rebuild sorts them
+    // into P[1 - cur] and the list build copies them back
+    if (skin <= 0.0) cur = 1 - cur;
     return SPH_OK;
   }
 
@@ -745,7 +747,7 @@ struct sph_batch {
   sph_status enqueue_lists_only() {
     HIPCHK(launch(KID_NBR_LISTS, k_nbr_forces<DD, double, false, 4>, blocks8(n), BLOCK, dev(),
                   P[cur], (const uint32_t *)cstart, 1, nbr, nnb, (double4 *)nullptr,
-                  (double *)nullptr, (double *)nullptr));
+                  (double *)nullptr, (double *)nullptr, P[cur]));
     return SPH_OK;
   }
 
@@ -757,12 +759,19 @@ struct sph_batch {
     using R4 = typename Vec4<R>::T;
     auto go = [&](int kid, auto kern) {
       return launch(kid, kern, blocks8(n), BLOCK, B, s, (const uint32_t *)cstart, 0, nbr, nnb,
-                    (R4 *)ap, dbg_gam, dbg_vt);
+                    (R4 *)ap, dbg_gam, dbg_vt, s);
     };
     if (skin > 0.0) {
-      hipError_t e = tile == 2   ? go(KID_SKIN, k_nbr_forces<DD, R, false, 2, CMP, 1>)
-                     : tile == 8 ? go(KID_SKIN, k_nbr_forces<DD, R, false, 8, CMP, 1>)
-                                 : go(KID_SKIN, k_nbr_forces<DD, R, false, 4, CMP, 1>);
+      // the build reads the particles a rebuild has just sorted into the
+      // other buffer and copies them back into s
+      const Parts &t = P[1 - cur];
+      auto build = [&](auto kern) {
+        return launch(KID_SKIN, kern, blocks8(n), BLOCK, B, t, (const uint32_t *)cstart, 0, nbr,
+                      nnb, (R4 *)ap, dbg_gam, dbg_vt, s);
+      };
+      hipError_t e = tile == 2   ? build(k_nbr_forces<DD, R, false, 2, CMP, 1>)
+                     : tile == 8 ? build(k_nbr_forces<DD, R, false, 8, CMP, 1>)
+                                 : build(k_nbr_forces<DD, R, false, 4, CMP, 1>);
       if (e != hipSuccess) return e;
       if (tile == 2) return go(KID_NBR_FORCES, k_nbr_forces<DD, R, true, 2, CMP, 2>);
       if (tile == 8) return go(KID_NBR_FORCES, k_nbr_forces<DD, R, true, 8, CMP, 2>);
@@ -788,7 +797,7 @@ struct sph_batch {
                   (const uint32_t *)nnb, (const R4 *)ap, (const R4 *)mid, (R4 *)acc, dbg_vm));
     HIPCHK(launch(KID_REDUCE_B, k_group_reduce, gslots, BLOCK, B, 1));
     HIPCHK(launch(KID_INTEGRATE_HASH, k_integrate_hash<DD, R>, blocks(n), BLOCK, B, s,
-                  P[1 - cur], (const R4 *)acc, cell, rank, cnt));
+                  (const R4 *)acc, cell, rank, cnt));
     HIPCHK(launch(KID_CONTROL, k_control, 1u, BLOCK, B));
     return SPH_OK;
   }
@@ -833,7 +842,9 @@ struct sph_batch {
     int left = n_steps;
     if (n == 0) return SPH_OK;
     if (use_graph && !profiling) {
-      if (left > 0 && cur != 0) {   // graphs are captured at parity 0
+      // graphs are captured at buffer parity 0 (steps with Verlet lists keep
+      // the parity, so any parity will do for them)
+      if (left > 0 && cur != 0 && skin <= 0.0) {
         if (sph_status st = enqueue_step()) return st;
         --left;
       }
@@ -1867,6 +1878,9 @@ static sph_status build_lists_now(sph_mesh *m) {
   b->invalidate_graph();
   sph_status st = b->force_rebuild();   // a real sort, whatever the Verlet lists' state
   if (!st) st = b->enqueue_sort();
+  // with Verlet lists the sorted particles are in the other buffer (a step's
+  // list build would copy them back); make it the current one
+  if (b->skin > 0.0) b->cur = 1 - b->cur;
   if (!st) st = b->D == 2 ? b->enqueue_lists_only<2>() : b->enqueue_lists_only<3>();
   if (!st) st = b->hash_range(0, b->n);
   if (st) return st;
