@@ -286,6 +286,35 @@ def _oracle_leg(wl, budget_s, openmp):
     return j.counters()["interactions"] / t, steps, t
 
 
+def square_4352_leg():
+    """The 4,352-particle unit square (h = 1/64, cut-off 2h) in plain FP64 for
+    200 steps: a launch-bound job, timed like the headline."""
+    from paper_2003_01061_amd import binding
+    from paper_2003_01061_amd import workload as wk
+    wl = wk.square_lattice()
+    r = run_timed(wl, binding.SPH_FP64, 200, 5)
+    return {"workload": "square_lattice_4352", "n_particles": wl.n, "precision": "fp64",
+            "kernel_support": wl.params["kernel_support"], "steps": 200,
+            "value": r["interactions"] / r["seconds"], "unit": "interactions/s",
+            "ms_per_step": r["seconds"] / 200 * 1e3}
+
+
+def cpu_baseline_3d(threads):
+    """The OpenMP oracle on the first step of the 2M-particle cube minus a ball
+    (its neighbour search from scratch included), one step being the bounded
+    sample (~20 s on 16 threads)."""
+    import oracle
+    from paper_2003_01061_amd import workload as wk
+    wl = wk.cube_ball()
+    j = oracle.RefJob(wl, openmp=True)
+    t0 = time.perf_counter()
+    j.step(1)
+    t = time.perf_counter() - t0
+    return {"value": j.counters()["interactions"] / t, "unit": "interactions/s", "cores": threads,
+            "kind": "oracle", "sample": f"first step of the 2M-particle 3D job, FP64 oracle, "
+                                        f"OpenMP over particles on {threads} threads, {t:.1f} s"}
+
+
 def cpu_baseline(wl, budget_s):
     """The FP64 oracle on this host: the plain single-threaded build and the
     OpenMP build (the same arithmetic, per-particle loops on every core the
@@ -300,7 +329,8 @@ def cpu_baseline(wl, budget_s):
                        f"particles on {threads} threads, {tn:.1f} s",
                 nproc=nproc, cpus_available=avail,
                 single_thread={"value": v1, "cores": 1,
-                               "sample": f"first {s1} steps, single-threaded, {t1:.1f} s"})
+                               "sample": f"first {s1} steps, single-threaded, {t1:.1f} s"},
+                cube_ball_3d=cpu_baseline_3d(threads))
 
 
 def ellipsoid_run(args):
@@ -660,6 +690,9 @@ def main():
               f"{c_['interactions_per_s']:.3g}/s", file=sys.stderr, flush=True)
 
     leg3d = None if args.no_3d else cube_ball_leg(args)
+    leg_c1 = square_4352_leg()
+    print(f"[bench] square 4352 FP64: {leg_c1['value']:.3g}/s, {leg_c1['ms_per_step']:.4f} ms/step",
+          file=sys.stderr, flush=True)
     if leg3d is not None:
         print(f"[bench] cube_ball 3D: {leg3d['value']:.3g}/s, nbr_forces "
               f"{leg3d['roofline']['avg_launch_us']:.0f}us", file=sys.stderr, flush=True)
@@ -722,6 +755,7 @@ def main():
             "theta_min_avg": [conv["fp32"]["quality"]["mesh"].get("theta_min_avg"),
                               conv["fp64"]["quality"]["mesh"].get("theta_min_avg")]},
         "cube_ball_3d": leg3d,
+        "square_4352_fp64": leg_c1,
         "latency_p50_p99_s": lat,
         "serving": srv,
         "roofline": roofline(dom, byts, avg_s, ctr, per[dom][1]),
