@@ -245,7 +245,8 @@ struct JobDev {
   // scan radius factor and cap at that reach, and the displacement since the
   // list's build, in units of the particle's h then, that forces a rebuild
   double ksup_s, rfac_s, rmax_s, move_eps;
-  int32_t bw, nf, live, pad;
+  int32_t bw, nf, live;
+  int32_t vol;   // the job's volume feature (local id), -1 if none
 };
 
 struct Parts {
@@ -280,12 +281,12 @@ struct Batch {
   unsigned int *gflags;               // [0] a scan tile gave up waiting (never expected)
   unsigned long long *smin, *ssum;    // [MAXJ * MAXF][NSTRIPE] group minima / sums
   unsigned long long *scnt, *sesc;    // [MAXJ][NSTRIPE] interactions / rejected moves
-  double4 *enrm;                      // [n] cell order: for a particle on a hole's
-                                      // boundary, the normal out of the domain (k_rank_gather)
+  double4 *enrm;                      // [n] cell order: for a particle of a feature of
+                                      // lower dimension than the domain, the domain's outward
+                                      // normal there (k_rank_gather)
   int n, cap;
   uint32_t ncell, ntiles;
   int njobs;                          // job slots in use: [0, njobs)
-  int has_hole;                       // some resident job has a hole
   // Verlet candidate lists (skin_on): built when vstate[VS_REBUILD] is set,
   // filtered into the neighbour list every step; particles keep their slots
   // between builds

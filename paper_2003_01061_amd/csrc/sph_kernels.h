@@ -359,12 +359,14 @@ __global__ __launch_bounds__(BLOCK) void k_rank_gather(Batch B, int n, const uin
     b.xf[dst] = scan_record<D>(xh, f);
     if (B.skin_on) B.xref[dst] = xh;
   }
-  // the normal out of the domain of a particle on a hole's boundary, for the
-  // sweep that follows (computed there, it would hold registers inside the
-  // neighbour loop): towards the centre of a disc or ball, against the level
-  // set's gradient for an ellipse or ellipsoid
-  if (B.has_hole) {
-    const Feat F = B.feat[f];
+  // the domain's outward normal at a particle of a feature of lower dimension
+  // than the domain, for the pressure sweep of the volume particles beside it
+  // (computed there, it would hold registers inside the neighbour loop):
+  // towards the centre of a disc or ball, against the level set's gradient for
+  // an ellipse or ellipsoid, the closest segment's for an imported curve, and
+  // for a box face, edge or corner the constant normal of the volume's table
+  const Feat F = B.feat[f];
+  if (F.k < D) {
     if (F.kind == K_POLY && D == 2) {   // an imported curve: the closest segment's right normal
       const Geom &gg = B.jobs[f / MAXF].g;
       const double x[3] = {xh.x, xh.y, xh.z};
@@ -404,6 +406,12 @@ __global__ __launch_bounds__(BLOCK) void k_rank_gather(Batch B, int n, const uin
         e = make_double4(d0 * il, d1 * il, d2 * il, 0.0);
       }
       B.enrm[dst] = e;
+    } else {   // a box face, edge or corner, an imported corner: the table's constant
+      const int job = f / MAXF, vol = B.jobs[job].vol;
+      if (vol >= 0) {
+        const BNorm N = B.bn[(size_t)(job * MAXF + vol) * MAXF + (f & (MAXF - 1))];
+        B.enrm[dst] = make_double4(N.n[0], N.n[1], N.n[2], 0.0);
+      }
     }
   }
 }
@@ -496,19 +504,26 @@ __host__ __device__ __forceinline__ void sweep_a_sums(const Geom &g, const Parts
           aP[1].add(c * dx1);
           if (D == 3) aP[2].add(c * dx2);
         } else {
-          const int fj = s.f[u[q] & 0x7fffffffu];
-          const BNorm N = bnrow[fj & (MAXF - 1)];
           double nv[3];
-          if (D == 3 && N.mode >= 7) continue;   // normal of the pair: the pass below
-          if (N.mode >= 2) {   // a curved boundary: the normal k_rank_gather stored
+          if constexpr (K == D) {   // the volume: the domain's normal k_rank_gather stored at b
             const double4 e = enrm[u[q] & 0x7fffffffu];
             nv[0] = e.x;
             nv[1] = e.y;
             nv[2] = e.z;
           } else {
-            nv[0] = N.n[0];
-            nv[1] = N.n[1];
-            nv[2] = N.n[2];
+            const int fj = s.f[u[q] & 0x7fffffffu];
+            const BNorm N = bnrow[fj & (MAXF - 1)];
+            if (D == 3 && N.mode >= 7) continue;   // normal of the pair: the pass below
+            if (N.mode >= 2) {   // a curved boundary: the normal k_rank_gather stored
+              const double4 e = enrm[u[q] & 0x7fffffffu];
+              nv[0] = e.x;
+              nv[1] = e.y;
+              nv[2] = e.z;
+            } else {
+              nv[0] = N.n[0];
+              nv[1] = N.n[1];
+              nv[2] = N.n[2];
+            }
           }
           const R om = (bw == 0 ? rcp_(hj) : (bw == 1 ? powK<K>(hj) * rcp_(hj) : R(0))) * (R)bscale;
           const R w = alpha * wshapeK<K>(qij) * powK<K>(ihij);          // W(r, h_ib)

@@ -655,12 +655,6 @@ struct sph_batch {
     B.nsk = nsk;
     B.xref = xref;
     B.vstate = vstate;
-    B.has_hole = 0;
-    for (int j = 0; j < njobs; ++j)
-      if (jobs[j].live)
-        for (const HFeat &F : jobs[j].feats)
-          B.has_hole |= F.kind == K_HOLE || F.kind == K_SHELL || F.kind == K_LEVEL ||
-                        F.kind == K_POLY;
     return B;
   }
   uint32_t ntiles() const { return (ncell + SCAN_TILE - 1) / SCAN_TILE; }
@@ -1040,6 +1034,12 @@ static void fill_job(HostJob &J, const sph_geometry *g, const sph_sizing *s, con
   d.bw = p->boundary_weighting;
   d.nf = J.nf;
   d.live = 1;
+  d.vol = -1;
+  for (int f = 0; f < J.nf; ++f)
+    if (J.feats[f].kind == K_VOL) {
+      d.vol = f;
+      break;
+    }
 }
 
 // 64 / 160 at r_c = 2h, scaled by (2.5 / 2)^D for the default r_c = 2.5h

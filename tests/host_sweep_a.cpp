@@ -126,6 +126,14 @@ int main(int argc, char **argv) {
         const double il = 1.0 / std::sqrt(d0 * d0 + d1 * d1 + d2 * d2);
         enrm[i] = make_double4(d0 * il, d1 * il, d2 * il, 0.0);
       }
+    } else if (F.k < D) {   // a box face, edge or corner: the volume's constant normal
+      int vol = -1;
+      for (int q = 0; q < nf && vol < 0; ++q)
+        if (hf[q].kind == K_VOL) vol = q;
+      if (vol >= 0) {
+        const BNorm &N = hb[(size_t)vol * MAXF + feat[i]];
+        enrm[i] = make_double4(N.n[0], N.n[1], N.n[2], 0.0);
+      }
     }
   }
   Parts P{};
