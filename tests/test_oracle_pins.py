@@ -719,9 +719,13 @@ def test_mirror_symmetry():
 
 # ---------------------------------------------------------------------------
 # T13 ablation of the correction (sec. 4.1: without it particles are lost
-# at the boundary once momentum is kept)
+# at the boundary once momentum is kept; with it they stay in the domain)
 # ---------------------------------------------------------------------------
 def test_particles_escape_without_correction():
+    """On the jittered lattice of the 4,352-particle square: without the
+    boundary term thousands of volume-particle moves leave the domain in 60
+    steps; with it (the printed readings) at most one or two moves are
+    rejected (the particle stays where it was and stops, so none is lost)."""
     wl = wk.square_lattice()
     esc = {}
     for bw in (0, 2):
@@ -730,7 +734,7 @@ def test_particles_escape_without_correction():
         j.step(60)
         esc[bw] = j.counters()["escaped"]
     assert esc[2] > 1000
-    assert esc[0] * 100 < esc[2]
+    assert esc[0] <= 2
 
 
 # ---------------------------------------------------------------------------
