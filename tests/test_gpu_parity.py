@@ -449,11 +449,16 @@ def test_full_size_square_hole_250k():
     xr = ref.state()[0]
     assert np.abs(g64.positions() - xr).max() <= TOL64
     assert np.abs(g32.positions() - xr).max() <= TOL32
-    # the other configurations the benchmark's tuner may pick
-    for cfg in ({"cell_factor": 0.75, "scan_tile": 2}, {"cell_factor": 1.25, "scan_tile": 8}):
+    # the other configurations the benchmark's tuner may pick, with a cell
+    # scan or Verlet candidate lists
+    for cfg in ({"cell_factor": 0.75, "scan_tile": 2}, {"cell_factor": 1.25, "scan_tile": 8},
+                {"scan_tile": 4, "verlet_skin": 0.8}, {"scan_tile": 8, "verlet_skin": 0.8}):
         g = binding.SphMesh(wl, precision=binding.SPH_FP32_MIXED, use_graph=1, **cfg)
         g.step(K)
         assert np.abs(g.positions() - xr).max() <= TOL32, cfg
+    g = binding.SphMesh(wl, use_graph=1, scan_tile=4, verlet_skin=0.8)
+    g.step(K)
+    assert np.abs(g.positions() - xr).max() <= TOL64
 
 
 def test_neighbor_list_overflow_is_reported_not_truncated():
@@ -478,17 +483,20 @@ def _sample_indices(wl, n_random, seed):
     return np.unique(np.concatenate(idx))
 
 
-@pytest.mark.parametrize("precision,tol", [(binding.SPH_FP64, 1e-12),
-                                           (binding.SPH_FP32_MIXED, 1e-5)])
-def test_full_size_cube_ball_2m_sampled(precision, tol):
+@pytest.mark.parametrize("precision,tol,cfg", [(binding.SPH_FP64, 1e-12, {}),
+                                               (binding.SPH_FP32_MIXED, 1e-5, {}),
+                                               (binding.SPH_FP32_MIXED, 1e-5, {"verlet_skin": 0.5})])
+def test_full_size_cube_ball_2m_sampled(precision, tol, cfg):
     """The 3D workload at full size (2,000,000 particles): neighbour lists of
     sampled particles bit-exact, and their first-step a^p, V~ and gamma,
-    against the oracle computing each sampled particle by brute force."""
+    against the oracle computing each sampled particle by brute force; also
+    with Verlet candidate lists (skin 0.5h, as the benchmark's 3D leg times),
+    whose first step builds and filters them."""
     wl = _wl_cache.get("cube_ball") or _wl_cache.setdefault("cube_ball", wk.cube_ball())
     ref = oracle.RefJob(wl)
     idx = _sample_indices(wl, 400, seed=5)
     so, si, sr, ap_r, vt_r, gam_r = ref.sample(idx)
-    g = binding.SphMesh(wl, precision=precision, use_graph=1, debug_fields=1)
+    g = binding.SphMesh(wl, precision=precision, use_graph=1, debug_fields=1, **cfg)
     off, ids, rel = g.neighbors()
     for s_, i in enumerate(idx):
         assert np.array_equal(ids[off[i]:off[i + 1]], si[so[s_]:so[s_ + 1]]), i
