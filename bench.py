@@ -37,6 +37,7 @@ VALU_PEAK_WAVE_INSTS = 256 * 4 * 2.4e9 / 4
 VALU_PEAK_LANE_OPS = VALU_PEAK_WAVE_INSTS * 64
 COUNTERS_MD = os.path.join(ROOT, "profiles", "nbr_forces_square_hole_250k_counters.md")
 COUNTERS_3D_MD = os.path.join(ROOT, "profiles", "cube_ball_2m_counters.md")
+COUNTERS_ELL_MD = os.path.join(ROOT, "profiles", "ellipsoid_inclusions_20m_counters.md")
 VERLET_SKIN_3D = 0.5   # the Verlet list skin the 3D leg also times (units of h)
 KERNEL_SOURCES = ("paper_2003_01061_amd/csrc/sph_device.h", "paper_2003_01061_amd/csrc/sph_kernels.h")
 
@@ -403,9 +404,8 @@ def ellipsoid_run(args):
         "quality_sample": {"particles": int(len(q)), "nn_over_h_mean": float(r.mean()),
                            "nn_over_h_p1": float(np.percentile(r, 1)),
                            "mesh_region": region, "mesh": mesh},
-        # no counters are committed for this job: the block gives the HBM
-        # fraction on algorithmic bytes only
-        "roofline": roofline("nbr_forces", byts, avg_s, None, per["nbr_forces"][1]),
+        "roofline": roofline("nbr_forces", byts, avg_s, profiled_counters(cfg, COUNTERS_ELL_MD),
+                             per["nbr_forces"][1]),
         "kernel_avg_us": {k: round(v[0] * 1e3, 2) for k, v in per.items()},
     }
     print(json.dumps(out))
@@ -575,10 +575,11 @@ def main():
                     help="precision of the 'step' and 'step3d' counter passes")
     ap.add_argument("--no-converge", action="store_true",
                     help="skip the runs to the converged mesh (profiling runs)")
-    ap.add_argument("--pmc-pass", choices=["step", "step3d", "copy"], default=None,
+    ap.add_argument("--pmc-pass", choices=["step", "step3d", "stepell", "copy"], default=None,
                     help="counter-collection pass for rocprofv3 --pmc: 'step' runs --steps "
                          "eagerly launched FP32-mixed steps of the workload (default tuning), "
-                         "'step3d' the same on the 2M-particle cube minus a ball, "
+                         "'step3d' the same on the 2M-particle cube minus a ball, 'stepell' on "
+                         "the 20M-particle ellipsoid job (tuning from --config), "
                          "'copy' one 256 MiB device copy (counter calibration); prints no JSON")
     ap.add_argument("--workload", choices=["square_hole", "ellipsoids", "validation"],
                     default="square_hole",
@@ -626,6 +627,14 @@ def main():
         return
     pmc_prec = {"mixed": binding.SPH_FP32_MIXED, "compensated": binding.SPH_FP32_COMPENSATED,
                 "fp64": binding.SPH_FP64}[args.pmc_precision]
+    if args.pmc_pass == "stepell":
+        wle = wk.ellipsoid_inclusions(max_phase1_steps=1200)
+        cfg = json.loads(args.config) if args.config else {}
+        j = binding.SphMesh(wle, precision=pmc_prec, use_graph=0, **cfg)
+        j.step(args.steps)
+        j.sync()
+        print(f"[bench] stepell pass: {args.steps} steps {json.dumps(cfg)}", file=sys.stderr, flush=True)
+        return
     if args.pmc_pass == "step3d":
         wl3 = wk.cube_ball()
         j = binding.SphMesh(wl3, precision=pmc_prec, use_graph=0, verlet_skin=args.pmc_skin)
