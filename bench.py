@@ -300,6 +300,21 @@ def square_4352_leg():
             "ms_per_step": r["seconds"] / 200 * 1e3}
 
 
+def cpu_baseline_square(threads):
+    """The oracle on the whole 200-step run of the 4,352-particle square (the
+    plain build, one thread)."""
+    import oracle
+    from paper_2003_01061_amd import workload as wk
+    wl = wk.square_lattice()
+    j = oracle.RefJob(wl)
+    t0 = time.perf_counter()
+    j.step(200)
+    t = time.perf_counter() - t0
+    return {"value": j.counters()["interactions"] / t, "unit": "interactions/s", "cores": 1,
+            "kind": "oracle", "sample": f"all 200 steps of the 4,352-particle square, FP64 oracle, "
+                                        f"single-threaded, {t:.1f} s"}
+
+
 def cpu_baseline_3d(threads):
     """The OpenMP oracle on the first step of the 2M-particle cube minus a ball
     (its neighbour search from scratch included), one step being the bounded
@@ -331,7 +346,8 @@ def cpu_baseline(wl, budget_s):
                 nproc=nproc, cpus_available=avail,
                 single_thread={"value": v1, "cores": 1,
                                "sample": f"first {s1} steps, single-threaded, {t1:.1f} s"},
-                cube_ball_3d=cpu_baseline_3d(threads))
+                cube_ball_3d=cpu_baseline_3d(threads),
+                square_4352=cpu_baseline_square(threads))
 
 
 def ellipsoid_run(args):
