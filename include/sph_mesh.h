@@ -219,7 +219,8 @@ typedef struct {
                                 spacing off a boundary.  2 is a mesh-quality
                                 calibration that places it one spacing off;
                                 [0.25, 8] */
-  int32_t use_graph;         /* 1: steps replay a captured HIP graph */
+  int32_t use_graph;         /* 1: steps replay captured HIP graphs (of 16
+                                and 2 steps) */
   int32_t debug_fields;      /* 1: keep gamma, V~ and v~ for sph_mesh_field */
   void *stream;              /* hipStream_t to run on (e.g. PyTorch's current
                                 stream), default priority; NULL = the library
@@ -474,7 +475,8 @@ typedef struct {
   int32_t max_jobs;          /* resident jobs, 1..64 */
   int32_t max_neighbors;     /* 0 = 104 in 2D, 320 in 3D */
   int32_t scan_tile;         /* 2, 4 or 8 (0 = 4), as in sph_params */
-  int32_t use_graph;         /* 1: steps replay a captured graph of two steps */
+  int32_t use_graph;         /* 1: steps replay captured graphs of 16 and 2
+                                steps (captured on the first multi-step call) */
   int32_t debug_fields;      /* keep gamma, V~, v~ (single-job inspection) */
   void *stream;              /* hipStream_t; NULL = the batch creates its own */
   void *(*dev_alloc)(size_t bytes, void *ctx);   /* as in sph_params; both NULL = */
