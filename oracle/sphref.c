@@ -1339,6 +1339,10 @@ static void sweep_a_particle(const sphref_job *J, int64_t i, const int32_t *nbl,
       double c = P->p0 * (hi2k + hj2k) * dWdr_over_r(k, r, lij);
       for (int a = 0; a < D; ++a) Pi[a] = Pi[a] + c * dx[a];
     } else {
+      /* the particle volume of Eq. (particle_volume) is the inverse of i's
+       * number density: every particle that acts on i counts, the boundary
+       * particles too */
+      S = S + sphref_W(k, r, li);
       double omega = P->boundary_weighting == 0 ? 1.0 / hj
                    : P->boundary_weighting == 1 ? hpow(hj, k - 1) : 0.0;
       omega = omega * bscale(P);

@@ -504,6 +504,9 @@ __host__ __device__ __forceinline__ void sweep_a_sums(const Geom &g, const Parts
           aP[1].add(c * dx1);
           if (D == 3) aP[2].add(c * dx2);
         } else {
+          // the particle volume (Eq. (particle_volume)) is the inverse of i's
+          // number density: the boundary particles that act on i count too
+          aS.add(alpha * wshapeK<K>(rr * ihi) * ihik);
           double nv[3];
           if constexpr (K == D) {   // the volume: the domain's normal k_rank_gather stored at b
             const double4 e = enrm[u[q] & 0x7fffffffu];
@@ -819,7 +822,7 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
         // grid values the row loop needs, kept in registers
         const double c0 = G.c[lv][0], inv0 = G.inv_c[lv][0], lo1 = G.lo[1], c1 = G.c[lv][1];
         const double lo2 = D == 3 ? G.lo[2] : 0.0, c2 = D == 3 ? G.c[lv][2] : 0.0;
-        const uint32_t nc0 = (uint32_t)G.nc[lv][0], nc1 = (uint32_t)G.nc[lv][1];
+        const uint32_t nc0 = (uint32_t)G.nc[lv][0];
         const uint32_t cbase = G.cbase + G.lbase[lv];
         const double u0 = (pc[0] - G.lo[0]) * inv0;     // x of i in cell units
         const double top0 = (double)(G.nc[lv][0] - 1);

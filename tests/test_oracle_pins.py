@@ -849,3 +849,26 @@ def test_two_particle_step_by_hand(c, eps):
         assert np.abs(j.field(oracle.F_A)[a, :2] - acc[a]).max() < 1e-12 * np.abs(acc[a]).max()
     assert abs(j.group_state(0)["dt1"] - dt1) < 1e-13 * dt1
     assert abs(j.group_state(0)["dt"] - dt) < 1e-13 * dt
+
+
+def test_particle_volume_counts_boundary_neighbours_by_hand():
+    """Eq. (particle_volume): V~_i is the inverse of i's number density, so a
+    volume particle next to the boundary counts the boundary particles acting
+    on it (the Shepard renormalisation gamma of Eq. (gamma_disc_renormSPH)
+    stays an in-domain sum); a boundary particle, on which volume particles do
+    not act, counts its own feature only (its 1D kernel)."""
+    wl = wk.square_lattice(n_side=8)          # h = 1/8 everywhere, reach 2h
+    xa, xc = np.array([0.5, 0.05]), np.array([0.6, 0.1])
+    xb, xb2 = np.array([0.55, 0.0]), np.array([0.3, 0.0])
+    wl.xyz = np.array([[*xa, 0.0], [*xc, 0.0], [*xb, 0.0], [*xb2, 0.0]])
+    wl.feature = np.array([0, 0, 3, 3], np.int32)      # volume, volume, bottom edge x2
+    j = oracle.RefJob(wl)
+    j.step(1)
+    h = 1.0 / 8
+    Sa = _w2(0, h) + _w2(np.linalg.norm(xa - xc), h) + _w2(np.linalg.norm(xa - xb), h) + \
+        _w2(np.linalg.norm(xa - xb2), h)
+    assert abs(j.field(oracle.F_VT)[0] - 1 / Sa) < 1e-13 / Sa
+    gam_a = (_w2(0, h) + _w2(np.linalg.norm(xa - xc), h)) * h * h
+    assert abs(j.field(oracle.F_GAMMA)[0] - gam_a) < 1e-13 * gam_a
+    w1_0 = 5.0 / (8.0 * h)                    # the 1D kernel at r = 0 (T1's normalisation)
+    assert abs(j.field(oracle.F_VT)[2] - 1 / w1_0) < 1e-13 / w1_0
