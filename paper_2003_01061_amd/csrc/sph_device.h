@@ -37,6 +37,15 @@ constexpr int NSTRIPE = 64;     // copies of each atomic accumulator (spreads co
 #define SPH_NBATCH 4
 #endif
 static_assert(SPH_NBATCH >= 1 && SPH_NBATCH <= 8, "records are padded by 8");
+#ifndef SPH_GBATCH
+#define SPH_GBATCH 4
+#endif
+// lanes per particle of the FP32 Verlet filter-and-sweep kernel in 3D (1 or
+// 2; 2D keeps one: its short lists do not pay for the per-particle work that
+// both lanes repeat)
+#ifndef SPH_VERLET_LANES
+#define SPH_VERLET_LANES 2
+#endif
 #ifndef SPH_XCD_REMAP
 #define SPH_XCD_REMAP 1
 #endif
@@ -570,6 +579,15 @@ __device__ __forceinline__ int xcd_block() {
 #else
   return (int)blockIdx.x;
 #endif
+}
+
+// Lanes of one wave that exchange data through LDS: the writes before this
+// point are visible to the reads after it (a wave's LDS operations complete in
+// order; the fences keep the compiler from moving them across).
+__device__ __forceinline__ void lane_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // the cells of a row (fixed y, z) are consecutive and run along x.  In 3D,

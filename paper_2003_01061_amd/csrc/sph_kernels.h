@@ -431,7 +431,8 @@ __host__ __device__ __forceinline__ void sweep_a_sums(const Geom &g, const Parts
                                              uint32_t cnt, const double4 &xi, int fi, bool pair_normals,
                                              double &S, double &gam, double Pi[3], double B[3],
                                              const uint32_t *ring = nullptr, uint32_t ring_len = 0,
-                                             uint32_t ring_stride = 0) {
+                                             uint32_t ring_stride = 0, uint32_t lane = 0,
+                                             uint32_t nlanes = 1) {
   // h enters rho_t = h^-k; the kernel is evaluated at the smoothing length
   // klen h (cut-off radius 2 klen h)
   const R hi = (R)xi.w;
@@ -442,9 +443,11 @@ __host__ __device__ __forceinline__ void sweep_a_sums(const Geom &g, const Parts
   const R ihik = powK<K>(ihi);
   const R P0 = (R)p0;
   const R wself = alpha * ihik;
+  // with several lanes per particle, lane l sums the batches l, l + nlanes,
+  // ... of the list (the self term in lane 0); the caller adds the lanes' sums
   Sum<CMP> aS, aG, aP[3], aB[3];
-  aS.init((double)wself);
-  aG.init((double)(wself * hik));
+  aS.init(lane == 0 ? (double)wself : 0.0);
+  aG.init(lane == 0 ? (double)(wself * hik) : 0.0);
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     aP[a].init(0.0);
@@ -452,6 +455,9 @@ __host__ __device__ __forceinline__ void sweep_a_sums(const Geom &g, const Parts
   }
   constexpr int NB = SPH_NBATCH;
   static_assert(NB == 4 || NB == LB, "record batches of 4 or 8 tile a list block");
+  // records gathered together: GB of a batch's NB (fewer live registers)
+  constexpr int GB = SPH_GBATCH < NB ? SPH_GBATCH : NB;
+  static_assert(NB % GB == 0, "gather groups tile a batch");
   // The list's last entries may also sit in the caller's LDS ring (entry e
   // in slot e % ring_len, column stride ring_stride): entries from lbase on
   // are read there, the ones before from the list in memory (whole blocks,
@@ -460,7 +466,7 @@ __host__ __device__ __forceinline__ void sweep_a_sums(const Geom &g, const Parts
   uint32_t lbase = cnt;
   if (ring != nullptr) lbase = cnt > ring_len ? (cnt - ring_len + LB - 1) / LB * LB : 0u;
   const uint4 *gl = reinterpret_cast<const uint4 *>(nbr) + (size_t)i * (LB / 4);
-  for (uint32_t e0 = 0; e0 < cnt; e0 += NB) {
+  for (uint32_t e0 = NB * lane; e0 < cnt; e0 += NB * nlanes) {
     {
       uint32_t u[NB];
       if (e0 < lbase) {   // NB entries of a block in memory: 16-byte loads
@@ -478,13 +484,16 @@ __host__ __device__ __forceinline__ void sweep_a_sums(const Geom &g, const Parts
       }
 #pragma unroll
       for (int q = 0; q < NB; ++q) u[q] = e0 + q < cnt ? u[q] : 0u;
-      double4 xr[NB];
 #pragma unroll
-      for (int q = 0; q < NB; ++q) xr[q] = s.xh[u[q] & 0x7fffffffu];
+      for (int g0 = 0; g0 < NB; g0 += GB) {
+      double4 xr[GB];
 #pragma unroll
-      for (int q = 0; q < NB; ++q) {
+      for (int q = 0; q < GB; ++q) xr[q] = s.xh[u[g0 + q] & 0x7fffffffu];
+#pragma unroll
+      for (int qg = 0; qg < GB; ++qg) {
+        const int q = g0 + qg;
         if (e0 + q >= cnt) break;
-        const double4 xj = xr[q];
+        const double4 xj = xr[qg];
         const R dx0 = (R)(xi.x - xj.x), dx1 = (R)(xi.y - xj.y);
         const R dx2 = D == 3 ? (R)(xi.z - xj.z) : R(0);
         const R rr = sqrt_(dx0 * dx0 + dx1 * dx1 + dx2 * dx2);
@@ -543,6 +552,7 @@ __host__ __device__ __forceinline__ void sweep_a_sums(const Geom &g, const Parts
           }
         }
       }
+      }
     }
   }
   if constexpr (D == 3) {
@@ -553,7 +563,7 @@ __host__ __device__ __forceinline__ void sweep_a_sums(const Geom &g, const Parts
     // curves take this pass, which keeps its registers out of the main loop.
     if (pair_normals) {
       const double4 ei = enrm[i];
-      for (uint32_t e = 0; e < cnt; ++e) {
+      for (uint32_t e = lane; e < cnt; e += nlanes) {
         const uint32_t v = nbr[((size_t)(e / LB) * n + i) * LB + e % LB];
         if (!(v >> 31)) continue;
         const uint32_t b = v & 0x7fffffffu;
@@ -607,6 +617,55 @@ __host__ __device__ __forceinline__ void sweep_a_sums(const Geom &g, const Parts
   }
 }
 
+// Appends the hits among tag[0, NB) (0xffffffff: no hit) to a particle's
+// column of the LDS ring (slot k at rc[k * stride], slot = entry mod LR) and
+// stores each list block they complete to *wp as two 16-byte writes, while
+// the capacity of nblk blocks allows.  With a ring of two blocks or more the
+// block a batch completes is still whole after the batch (NB <= LB hits
+// reach at most LB - 1 entries into the next block), so the test for a
+// store runs once per batch instead of once per hit.
+template <int NB, int LR>
+__device__ __forceinline__ void append_hits(const uint32_t (&tag)[NB], uint32_t *rc, int stride,
+                                            uint32_t &count, uint4 *&wp, uint32_t wstep,
+                                            uint32_t nblk) {
+  static_assert(NB <= LB && LR % LB == 0, "a batch completes at most one block");
+  if constexpr (LR >= 2 * LB) {
+    const uint32_t c0 = count;
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      if (tag[q] != 0xffffffffu) {
+        rc[(count % LR) * stride] = tag[q];
+        ++count;
+      }
+    }
+    if (count / LB != c0 / LB && count / LB <= nblk) {
+      const uint32_t k0 = (c0 / LB * LB) % LR;
+      wp[0] = make_uint4(rc[k0 * stride], rc[(k0 + 1) * stride], rc[(k0 + 2) * stride],
+                         rc[(k0 + 3) * stride]);
+      wp[1] = make_uint4(rc[(k0 + 4) * stride], rc[(k0 + 5) * stride], rc[(k0 + 6) * stride],
+                         rc[(k0 + 7) * stride]);
+      wp += wstep;
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      if (tag[q] != 0xffffffffu) {
+        const uint32_t k = count % LR;
+        rc[k * stride] = tag[q];
+        ++count;
+        if (k % LB == LB - 1 && count / LB <= nblk) {
+          const uint32_t k0 = k - (LB - 1);
+          wp[0] = make_uint4(rc[k0 * stride], rc[(k0 + 1) * stride], rc[(k0 + 2) * stride],
+                             rc[(k0 + 3) * stride]);
+          wp[1] = make_uint4(rc[(k0 + 4) * stride], rc[(k0 + 5) * stride], rc[(k0 + 6) * stride],
+                             rc[(k0 + 7) * stride]);
+          wp += wstep;
+        }
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // neighbour list (Algorithm 1 "construct Verlet neighbor list") and, in the
 // same launch, sweep A over it; FORCES = false builds the lists only (test
@@ -623,7 +682,7 @@ __host__ __device__ __forceinline__ void sweep_a_sums(const Geom &g, const Parts
 // FP32 test alone, widened by its error bound so that it keeps every pair
 // within that reach.  MODE 2: candidates from the particle's Verlet list
 // instead of the cell scan, classified and summed as in MODE 0.
-template <int D, typename R, bool FORCES, int NB, bool CMP = false, int MODE = 0>
+template <int D, typename R, bool FORCES, int NB, bool CMP = false, int MODE = 0, int LPP = 1>
 __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
     Batch B, Parts s, const uint32_t *__restrict__ cstart, int all, uint32_t *__restrict__ nbr,
     uint32_t *__restrict__ nnb, typename Vec4<R>::T *__restrict__ ap,
@@ -652,9 +711,17 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
   constexpr bool LDS_SUMS = FORCES && sizeof(R) == 4;
   constexpr int LR = LDS_SUMS ? SPH_LDS_LIST : LB;
   static_assert(LR % LB == 0, "the ring holds whole blocks");
-  __shared__ uint32_t ring[LR][BLOCK];
+  // LPP lanes per particle (2: the Verlet filter and the sums split between
+  // two adjacent lanes, which doubles the waves that hide the gathers'
+  // latency); the particle's lanes share its ring column
+  static_assert(LPP == 1 || (LPP == 2 && MODE == 2 && LDS_SUMS && LB == 8),
+                "two lanes per particle: the Verlet filter with the sums in LDS");
+  constexpr int PB = BLOCK / LPP;
+  __shared__ uint32_t ring[LR][PB];
+  const int col = (int)threadIdx.x / LPP;
+  const int lane = (int)threadIdx.x % LPP;
   const int n = B.n;
-  const int i = xcd_block() * BLOCK + threadIdx.x;
+  const int i = (xcd_block() * BLOCK + (int)threadIdx.x) / LPP;
   bool act = false;
   int fi = 0, job = 0;
   unsigned long long dtb = ~0ull, vfix = 0ull, mine = 0ull;
@@ -750,6 +817,66 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
         const uint32_t ns = B.nsk[i];
         const size_t sstep = (size_t)n * (LB / 4);
         const uint4 *sp = reinterpret_cast<const uint4 *>(B.skin) + (size_t)i * (LB / 4);
+        if constexpr (LPP == 2) {
+          // of each block of LB candidates the first lane takes the first
+          // four and the second lane the last four; a block's hits enter the
+          // ring in list order (the first lane's, then the second's), so the
+          // list is the one a single lane writes.  Both lanes of a particle
+          // run this loop alike (same particle, same count).
+          uint4 w = make_uint4(0u, 0u, 0u, 0u);
+          if (ns > 0) w = sp[lane];
+          for (uint32_t b0 = 0; b0 < ns; b0 += LB) {
+            const uint32_t ub[4] = {w.x, w.y, w.z, w.w};
+            if (b0 + LB < ns) {   // the next block's entries, loaded ahead
+              sp += sstep;
+              w = sp[lane];
+            }
+            const uint32_t e0 = b0 + 4u * (uint32_t)lane;
+            float4 xr[4];
+            uint32_t jr[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              jr[q] = e0 + q < ns ? (ub[q] & 0x7fffffffu) : (uint32_t)i;
+              xr[q] = s.xf[jr[q]];
+            }
+            uint32_t tag[4], nh = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const bool cand = e0 + q < ns;
+              const float ex = xif.x - xr[q].x, ey = xif.y - xr[q].y;
+              const float ez = D == 3 ? xif.z - xr[q].z : 0.0f;
+              const float d2 = ex * ex + ey * ey + ez * ez;
+              const float Hj = D == 2 ? xr[q].z : xr[q].w;
+              const float H = __builtin_fmaxf(Hif, Hj);
+              const float H2 = H * H;
+              const float tin = H2 * cin, tout = H2 * cout;
+              bool hit = cand & (d2 < tin);
+              if (cand & !(d2 < tin) & !(d2 > tout))   // near the support radius: exact test
+                hit = within_a4<D>(xi, A4, kc2, s.xh[jr[q]]);
+              tag[q] = hit ? ub[q] : 0xffffffffu;
+              nh += hit ? 1u : 0u;
+            }
+            // the other lane's hits of this block (lanes 2p and 2p + 1 swap)
+            const uint32_t nother = (uint32_t)__shfl_xor((int)nh, 1);
+            uint32_t k = count + (lane ? nother : 0u);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              if (tag[q] != 0xffffffffu) {
+                ring[k % LR][col] = tag[q];
+                ++k;
+              }
+            }
+            const uint32_t cnew = count + nh + nother;
+            lane_sync();   // the other lane's ring entries are read below
+            // at most LB hits per block: at most one list block completes
+            if (cnew / LB != count / LB && cnew / LB <= nblk) {
+              const uint32_t k0 = (count / LB * LB) % LR + 4u * (uint32_t)lane;
+              wp[lane] = make_uint4(ring[k0][col], ring[k0 + 1][col], ring[k0 + 2][col], ring[k0 + 3][col]);
+              wp += wstep;
+            }
+            count = cnew;
+          }
+        } else {
         uint4 w0 = make_uint4(0u, 0u, 0u, 0u), w1 = w0;
         if (ns > 0) {
           w0 = sp[0];
@@ -788,23 +915,9 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
                 hit = within_a4<D>(xi, A4, kc2, s.xh[jr[q]]);
               tag[q] = hit ? ub[hb + q] : 0xffffffffu;
             }
-#pragma unroll
-            for (int q = 0; q < NB; ++q) {
-              if (tag[q] != 0xffffffffu) {
-                const uint32_t k = count % LR;
-                ring[k][threadIdx.x] = tag[q];
-                ++count;
-                if (k % LB == LB - 1 && count / LB <= nblk) {
-                  const uint32_t k0 = k - (LB - 1);
-                  wp[0] = make_uint4(ring[k0][threadIdx.x], ring[k0 + 1][threadIdx.x],
-                                     ring[k0 + 2][threadIdx.x], ring[k0 + 3][threadIdx.x]);
-                  wp[1] = make_uint4(ring[k0 + 4][threadIdx.x], ring[k0 + 5][threadIdx.x],
-                                     ring[k0 + 6][threadIdx.x], ring[k0 + 7][threadIdx.x]);
-                  wp += wstep;
-                }
-              }
-            }
+            append_hits<NB, LR>(tag, &ring[0][col], PB, count, wp, wstep, nblk);
           }
+        }
         }
       } else
       for (int lv = lv0; lv <= lv1; ++lv) {
@@ -889,40 +1002,32 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
                 tag[q] = hit ? (j | (fr[q] == (uint32_t)(fi & (MAXF - 1)) ? 0u : 0x80000000u))
                              : 0xffffffffu;
               }
-  #pragma unroll
-              for (int q = 0; q < NB; ++q) {
-                if (tag[q] != 0xffffffffu) {
-                  const uint32_t k = count % LR;
-                  ring[k][threadIdx.x] = tag[q];
-                  ++count;
-                  if (k % LB == LB - 1 && count / LB <= nblk) {
-                    const uint32_t k0 = k - (LB - 1);
-                    wp[0] = make_uint4(ring[k0][threadIdx.x], ring[k0 + 1][threadIdx.x],
-                                       ring[k0 + 2][threadIdx.x], ring[k0 + 3][threadIdx.x]);
-                    wp[1] = make_uint4(ring[k0 + 4][threadIdx.x], ring[k0 + 5][threadIdx.x],
-                                       ring[k0 + 6][threadIdx.x], ring[k0 + 7][threadIdx.x]);
-                    wp += wstep;
-                  }
-                }
-              }
+              append_hits<NB, LR>(tag, &ring[0][col], PB, count, wp, wstep, nblk);
             }
           }
         }
       }
       if (count % LB != 0 && count / LB < nblk) {   // the last, partly filled block
         const uint32_t k0 = (count / LB * LB) % LR;
-        wp[0] = make_uint4(ring[k0][threadIdx.x], ring[k0 + 1][threadIdx.x], ring[k0 + 2][threadIdx.x],
-                           ring[k0 + 3][threadIdx.x]);
-        wp[1] = make_uint4(ring[k0 + 4][threadIdx.x], ring[k0 + 5][threadIdx.x], ring[k0 + 6][threadIdx.x],
-                           ring[k0 + 7][threadIdx.x]);
+        if constexpr (LPP == 2) {
+          const uint32_t kl = k0 + 4u * (uint32_t)lane;
+          wp[lane] = make_uint4(ring[kl][col], ring[kl + 1][col], ring[kl + 2][col], ring[kl + 3][col]);
+        } else {
+          wp[0] = make_uint4(ring[k0][col], ring[k0 + 1][col], ring[k0 + 2][col],
+                             ring[k0 + 3][col]);
+          wp[1] = make_uint4(ring[k0 + 4][col], ring[k0 + 5][col], ring[k0 + 6][col],
+                             ring[k0 + 7][col]);
+        }
       }
       if (MODE == 1 && (int)count > B.skin_cap) {
         atomicMax(&B.st[job].skin_max, count);
         atomicExch(&B.st[job].skin_overflow, 1u);
         count = B.skin_cap;
       } else if (MODE != 1 && (int)count > B.cap) {
-        atomicMax(&B.st[job].overflow_max, count);
-        atomicExch(&B.st[job].overflow, 1u);
+        if (lane == 0) {
+          atomicMax(&B.st[job].overflow_max, count);
+          atomicExch(&B.st[job].overflow, 1u);
+        }
         count = B.cap;
       }
     }
@@ -931,7 +1036,7 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
       double4 v4 = s.v[i];
       if (B.grp[fi].reset_now) {
         v4 = make_double4(0.0, 0.0, 0.0, 0.0);
-        s.v[i] = v4;
+        if (lane == 0) s.v[i] = v4;
       }
       const BNorm *bnrow = B.bn + (size_t)fi * MAXF;
       // a 3D patch of a level set with imported curves: pair-dependent normals
@@ -939,13 +1044,22 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
       double S, gam, Pi[3], B3[3];
       if (k == D)
         sweep_a_sums<D, D, R, CMP>(J.g, s, B.enrm, bnrow, J.bw, J.p0, J.klen, J.bscale, nbr, n, i, count, xi, fi, pairn, S, gam, Pi, B3,
-                                        LDS_SUMS ? &ring[0][threadIdx.x] : nullptr, LR, BLOCK);
+                                        LDS_SUMS ? &ring[0][col] : nullptr, LR, PB, lane, LPP);
       else if (k == D - 1)
         sweep_a_sums<D, D - 1, R, CMP>(J.g, s, B.enrm, bnrow, J.bw, J.p0, J.klen, J.bscale, nbr, n, i, count, xi, fi, pairn, S, gam, Pi, B3,
-                                        LDS_SUMS ? &ring[0][threadIdx.x] : nullptr, LR, BLOCK);
+                                        LDS_SUMS ? &ring[0][col] : nullptr, LR, PB, lane, LPP);
       else
         sweep_a_sums<D, 1, R, CMP>(J.g, s, B.enrm, bnrow, J.bw, J.p0, J.klen, J.bscale, nbr, n, i, count, xi, fi, pairn, S, gam, Pi, B3,
-                                        LDS_SUMS ? &ring[0][threadIdx.x] : nullptr, LR, BLOCK);
+                                        LDS_SUMS ? &ring[0][col] : nullptr, LR, PB, lane, LPP);
+      if constexpr (LPP == 2) {   // both lanes get the same totals (a + b = b + a)
+        S += __shfl_xor(S, 1);
+        gam += __shfl_xor(gam, 1);
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          Pi[a] += __shfl_xor(Pi[a], 1);
+          B3[a] += __shfl_xor(B3[a], 1);
+        }
+      }
       double a3[3] = {0.0, 0.0, 0.0};
 #pragma unroll
       for (int a = 0; a < D; ++a) a3[a] = -((Pi[a] + B3[a]) / gam);
@@ -958,10 +1072,12 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
       o.y = (R)a3[1];
       o.z = D == 2 ? (R)v4.x : (R)a3[2];
       o.w = D == 2 ? (R)v4.y : R(0);
-      ap[i] = o;
       const double vt = 1.0 / S;
-      if (dbg_gam) dbg_gam[i] = gam;
-      if (dbg_vt) dbg_vt[i] = vt;
+      if (lane == 0) {
+        ap[i] = o;
+        if (dbg_gam) dbg_gam[i] = gam;
+        if (dbg_vt) dbg_vt[i] = vt;
+      }
       // Eq. (fa_time_step_size) terms from a^p and v^n
       const double rc = J.ksup * xi.w;
       double dt = __builtin_inf();
@@ -974,7 +1090,7 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
       }
       dtb = dbits(dt);
       vfix = (unsigned long long)__builtin_llrint(vt * B.grp[fi].vscale);
-    } else if (FORCES) {
+    } else if (FORCES && lane == 0) {
       R4 z;
       z.x = z.y = z.z = z.w = R(0);
       ap[i] = z;
@@ -983,13 +1099,13 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
     }
     if (MODE == 1) {
       B.nsk[i] = count;
-    } else {
+    } else if (lane == 0) {
       nnb[i] = count;
       mine = count;
     }
   }
   if (FORCES) {
-    wave_commit(act, fi, dtb, vfix, B.smin, B.ssum);
+    wave_commit(act && lane == 0, fi, dtb, vfix, B.smin, B.ssum);
     wave_commit(i < n && mine != 0ull, job, 0ull, mine, nullptr, B.scnt);
   }
 }

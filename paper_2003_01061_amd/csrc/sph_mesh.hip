@@ -767,6 +767,11 @@ struct sph_batch {
                      : tile == 8 ? build(k_nbr_forces<DD, R, false, 8, CMP, 1>)
                                  : build(k_nbr_forces<DD, R, false, 4, CMP, 1>);
       if (e != hipSuccess) return e;
+      // 3D: two lanes per particle (the tile sets only the build's batch)
+      if constexpr (sizeof(R) == 4 && DD == 3 && SPH_VERLET_LANES == 2) {
+        return launch(KID_NBR_FORCES, k_nbr_forces<DD, R, true, 4, CMP, 2, 2>, blocks8(2 * (size_t)n),
+                      BLOCK, B, s, (const uint32_t *)cstart, 0, nbr, nnb, (R4 *)ap, dbg_gam, dbg_vt, s);
+      }
       if (tile == 2) return go(KID_NBR_FORCES, k_nbr_forces<DD, R, true, 2, CMP, 2>);
       if (tile == 8) return go(KID_NBR_FORCES, k_nbr_forces<DD, R, true, 8, CMP, 2>);
       return go(KID_NBR_FORCES, k_nbr_forces<DD, R, true, 4, CMP, 2>);

@@ -14,6 +14,7 @@
 // Output file: double ap[m * 3], vt[m], gam[m]
 #include "../paper_2003_01061_amd/csrc/sph_mesh.hip"
 
+#include <cstdlib>
 #include <fstream>
 
 template <typename T>
@@ -26,7 +27,9 @@ static void get(std::ifstream &in, T *p, size_t n) {
 }
 
 int main(int argc, char **argv) {
-  if (argc != 3) return 2;
+  if (argc != 3 && argc != 4) return 2;
+  const uint32_t lanes = argc == 4 ? (uint32_t)std::atoi(argv[3]) : 1u;   // lanes per particle
+  if (lanes < 1 || lanes > 2) return 2;
   std::ifstream in(argv[1], std::ios::binary);
   int32_t hdr[4];
   get(in, hdr, 4);
@@ -161,21 +164,32 @@ int main(int argc, char **argv) {
     if (F.type == T_SI) continue;
     const BNorm *bnrow = hb.data() + (size_t)fi * MAXF;
     const uint32_t cnt = (uint32_t)(off[t + 1] - off[t]);
-    double S, gam, Pi[3], B3[3];
+    double S = 0.0, gam = 0.0, Pi[3] = {0.0, 0.0, 0.0}, B3[3] = {0.0, 0.0, 0.0};
     const JobDev &JD = J.dev;
     const bool pairn = D == 3 && F.kind == K_LEVEL && G.cpts != nullptr;
-    if (D == 3) {
-      if (F.k == 3)
-        sweep_a_sums<3, 3, double, false>(G, P, enrm.data(), bnrow, JD.bw, JD.p0, JD.klen, JD.bscale, nbr.data(), n, i, cnt, xh[i], fi, pairn, S, gam, Pi, B3);
-      else if (F.k == 2)
-        sweep_a_sums<3, 2, double, false>(G, P, enrm.data(), bnrow, JD.bw, JD.p0, JD.klen, JD.bscale, nbr.data(), n, i, cnt, xh[i], fi, pairn, S, gam, Pi, B3);
-      else
-        sweep_a_sums<3, 1, double, false>(G, P, enrm.data(), bnrow, JD.bw, JD.p0, JD.klen, JD.bscale, nbr.data(), n, i, cnt, xh[i], fi, pairn, S, gam, Pi, B3);
-    } else {
-      if (F.k == 2)
-        sweep_a_sums<2, 2, double, false>(G, P, enrm.data(), bnrow, JD.bw, JD.p0, JD.klen, JD.bscale, nbr.data(), n, i, cnt, xh[i], fi, pairn, S, gam, Pi, B3);
-      else
-        sweep_a_sums<2, 1, double, false>(G, P, enrm.data(), bnrow, JD.bw, JD.p0, JD.klen, JD.bscale, nbr.data(), n, i, cnt, xh[i], fi, pairn, S, gam, Pi, B3);
+    // the list split over `lanes` lanes as the kernel's lanes of one particle
+    // split it, their sums added
+    for (uint32_t l = 0; l < lanes; ++l) {
+      double s1, g1, p1[3], b1[3];
+      if (D == 3) {
+        if (F.k == 3)
+          sweep_a_sums<3, 3, double, false>(G, P, enrm.data(), bnrow, JD.bw, JD.p0, JD.klen, JD.bscale, nbr.data(), n, i, cnt, xh[i], fi, pairn, s1, g1, p1, b1, nullptr, 0, 0, l, lanes);
+        else if (F.k == 2)
+          sweep_a_sums<3, 2, double, false>(G, P, enrm.data(), bnrow, JD.bw, JD.p0, JD.klen, JD.bscale, nbr.data(), n, i, cnt, xh[i], fi, pairn, s1, g1, p1, b1, nullptr, 0, 0, l, lanes);
+        else
+          sweep_a_sums<3, 1, double, false>(G, P, enrm.data(), bnrow, JD.bw, JD.p0, JD.klen, JD.bscale, nbr.data(), n, i, cnt, xh[i], fi, pairn, s1, g1, p1, b1, nullptr, 0, 0, l, lanes);
+      } else {
+        if (F.k == 2)
+          sweep_a_sums<2, 2, double, false>(G, P, enrm.data(), bnrow, JD.bw, JD.p0, JD.klen, JD.bscale, nbr.data(), n, i, cnt, xh[i], fi, pairn, s1, g1, p1, b1, nullptr, 0, 0, l, lanes);
+        else
+          sweep_a_sums<2, 1, double, false>(G, P, enrm.data(), bnrow, JD.bw, JD.p0, JD.klen, JD.bscale, nbr.data(), n, i, cnt, xh[i], fi, pairn, s1, g1, p1, b1, nullptr, 0, 0, l, lanes);
+      }
+      S += s1;
+      gam += g1;
+      for (int a = 0; a < 3; ++a) {
+        Pi[a] += p1[a];
+        B3[a] += b1[a];
+      }
     }
     double a3[3] = {0.0, 0.0, 0.0};
     for (int a = 0; a < D; ++a) a3[a] = -((Pi[a] + B3[a]) / gam);

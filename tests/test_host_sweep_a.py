@@ -4,7 +4,8 @@ AddressSanitizer and UndefinedBehaviorSanitizer and fed the oracle's
 neighbour lists: a^p, V~ and gamma of every box-edge particle (intrinsic
 dimension 1), a sample of the face, sphere and volume particles of the
 2,000,000-particle cube minus a ball (kernel reach 2.5h, boundary factor 2,
-FP64), against the oracle to 1e-12.  No GPU."""
+FP64), against the oracle to 1e-12, with the list summed by one lane and
+split over two lanes as the 3D Verlet kernel splits it.  No GPU."""
 import os
 import shutil
 import subprocess
@@ -33,7 +34,7 @@ def harness(tmp_path_factory):
     return out
 
 
-def _run(harness, tmp, wl, idx, lists, params):
+def _run(harness, tmp, wl, idx, lists, params, lanes=1):
     so, si, sr = lists
     path = tmp / "in.bin"
     with open(path, "wb") as f:
@@ -52,7 +53,7 @@ def _run(harness, tmp, wl, idx, lists, params):
         np.ascontiguousarray(so, np.int64).tofile(f)
         np.ascontiguousarray(si, np.int32).tofile(f)
         np.ascontiguousarray(sr, np.int8).tofile(f)
-    res = subprocess.run([str(harness), str(path), str(tmp / "out.bin")], capture_output=True,
+    res = subprocess.run([str(harness), str(path), str(tmp / "out.bin"), str(lanes)], capture_output=True,
                          text=True, env=dict(os.environ, ASAN_OPTIONS="detect_leaks=0"))
     assert res.returncode == 0, res.stderr[-4000:]
     assert "runtime error" not in res.stderr, res.stderr[-4000:]
@@ -82,6 +83,14 @@ def test_sweep_a_on_the_host_matches_the_oracle(harness, tmp_path):
         err = np.abs(got - want)
         scale = np.abs(want).max()
         assert err.max() <= 1e-12 * scale, (name, float(err.max() / scale))
+    # the list split over two lanes per particle (alternate batches of four
+    # entries, the self term in the first lane), as the Verlet kernel does
+    ap2, vt2, gam2 = _run(harness, tmp_path, wl, idx, (so, si, sr), wl.params, lanes=2)
+    for got, want, name in ((ap2, ap_r, "a^p"), (vt2, vt_r, "V~"), (gam2, gam_r, "gamma")):
+        err = np.abs(got - want)
+        scale = np.abs(want).max()
+        assert err.max() <= 1e-12 * scale, (name, "two lanes", float(err.max() / scale))
+    assert not np.array_equal(ap2, ap)   # the split changes the order of the terms
     # every edge particle with a neighbour has a non-zero pressure
     # acceleration here and in the oracle (a build of the neighbour kernel
     # bounded to 4 waves per SIMD once returned 0 for one of them); those
