@@ -249,6 +249,7 @@ struct JobDev {
   // cut-off radius r_c = ksup h; the kernel's smoothing length is klen h
   // (klen = ksup / 2) and the pair predicate compares with ksup2 max(h)^2
   double ksup, klen, ksup2;
+  double iband;    // 1 / (2 klen h0): the FP32 band's rounding bound per unit of M
   double bscale;   // factor on the boundary term of the pressure force
   // Verlet candidate list (skin delta h): its reach ksup_s = ksup + delta, the
   // scan radius factor and cap at that reach, and the displacement since the

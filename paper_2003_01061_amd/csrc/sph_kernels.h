@@ -37,6 +37,35 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
   return v;
 }
 
+// The particle's terms of Eq. (fa_time_step_size) from |a|^2 and |v|^2 (the
+// third term can never be the smallest, so it is left out): min(0.25
+// sqrt(r_c / |a|), r_c / (40 |v|)), infinite when both vanish.  F32: in
+// FP32 (the FP32 modes hold the time steps to 1e-5).
+template <bool F32>
+__device__ __forceinline__ double step_terms(double rc, double a2, double v2) {
+  if constexpr (F32) {
+    const float rcf = (float)rc, am = __builtin_amdgcn_sqrtf((float)a2),
+                vm = __builtin_amdgcn_sqrtf((float)v2);
+    float dt = __builtin_inff();
+    if (am > 0.0f) dt = 0.25f * __builtin_amdgcn_sqrtf(rcf * __builtin_amdgcn_rcpf(am));
+    if (vm > 0.0f) {
+      const float t = rcf * __builtin_amdgcn_rcpf(40.0f * vm);
+      dt = t < dt ? t : dt;
+    }
+    return (double)dt;
+  } else {
+    double dt = __builtin_inf();
+    const double am = __builtin_sqrt(a2);
+    if (am > 0.0) dt = 0.25 * __builtin_sqrt(rc / am);
+    const double vm = __builtin_sqrt(v2);
+    if (vm > 0.0) {
+      const double t = rc / (40.0 * vm);
+      dt = t < dt ? t : dt;
+    }
+    return dt;
+  }
+}
+
 // Per-key reduction of one wave: each distinct key (a feature, or a job)
 // among the valid lanes is reduced with xor shuffles and committed by one lane
 // with a device atomic into one of NSTRIPE copies of the accumulator (chosen
@@ -793,7 +822,7 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
       float cin, cout;
       {
         // the support radius is klen H >= 2 klen h0
-        const double w = (D == 2 ? 2e-6 : 2e-5) + (double)Mf / (2.0 * J.klen * J.g.h0);
+        const double w = (D == 2 ? 2e-6 : 2e-5) + (double)Mf * J.iband;
         const double kl = MODE == 1 ? 0.5 * J.ksup_s : J.klen;
         const double k2 = kl * kl;
         cin = w < 1.0 ? (float)((1.0 - w) * (1.0 - w) * k2) : -1.0f;
@@ -1060,9 +1089,13 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
           B3[a] += __shfl_xor(B3[a], 1);
         }
       }
+      // the FP32 modes store a^p in FP32 and hold V~ and the time steps to
+      // 1e-5: FP32 reciprocals and roots suffice there (relative error 2^-23)
+      constexpr bool F32 = sizeof(R) == 4;
       double a3[3] = {0.0, 0.0, 0.0};
+      const double ig = F32 ? (double)rcp_((float)gam) : 0.0;
 #pragma unroll
-      for (int a = 0; a < D; ++a) a3[a] = -((Pi[a] + B3[a]) / gam);
+      for (int a = 0; a < D; ++a) a3[a] = F32 ? -((Pi[a] + B3[a]) * ig) : -((Pi[a] + B3[a]) / gam);
       double xa[3] = {xi.x, xi.y, xi.z};
       tangent<D>(J.g, F, xa, a3);
       // in 2D the record's free slots carry v^n (after any reset) in the
@@ -1072,7 +1105,7 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
       o.y = (R)a3[1];
       o.z = D == 2 ? (R)v4.x : (R)a3[2];
       o.w = D == 2 ? (R)v4.y : R(0);
-      const double vt = 1.0 / S;
+      const double vt = F32 ? (double)rcp_((float)S) : 1.0 / S;
       if (lane == 0) {
         ap[i] = o;
         if (dbg_gam) dbg_gam[i] = gam;
@@ -1080,14 +1113,8 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
       }
       // Eq. (fa_time_step_size) terms from a^p and v^n
       const double rc = J.ksup * xi.w;
-      double dt = __builtin_inf();
-      const double am = __builtin_sqrt(a3[0] * a3[0] + a3[1] * a3[1] + a3[2] * a3[2]);
-      if (am > 0.0) dt = 0.25 * __builtin_sqrt(rc / am);
-      const double vm = __builtin_sqrt(v4.x * v4.x + v4.y * v4.y + v4.z * v4.z);
-      if (vm > 0.0) {
-        const double t = rc / (40.0 * vm);
-        dt = t < dt ? t : dt;
-      }
+      const double dt = step_terms<F32>(rc, a3[0] * a3[0] + a3[1] * a3[1] + a3[2] * a3[2],
+                                        v4.x * v4.x + v4.y * v4.y + v4.z * v4.z);
       dtb = dbits(dt);
       vfix = (unsigned long long)__builtin_llrint(vt * B.grp[fi].vscale);
     } else if (FORCES && lane == 0) {
@@ -1301,13 +1328,8 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_b(Batch B, Parts s,
       acc[i] = o;
       if (dbg_vm) dbg_vm[i] = make_double4(vti[0], vti[1], vti[2], 0.0);
       const double rc = J.ksup * xi.w;
-      double dt = __builtin_inf();
-      const double am = __builtin_sqrt(a3[0] * a3[0] + a3[1] * a3[1] + a3[2] * a3[2]);
-      if (am > 0.0) dt = 0.25 * __builtin_sqrt(rc / am);
-      if (vmi > 0.0) {
-        const double t = rc / (40.0 * vmi);
-        dt = t < dt ? t : dt;
-      }
+      const double dt = step_terms<sizeof(R) == 4>(rc, a3[0] * a3[0] + a3[1] * a3[1] + a3[2] * a3[2],
+                                                   vmi * vmi);
       dtb = dbits(dt);
     } else {
       R4 z;

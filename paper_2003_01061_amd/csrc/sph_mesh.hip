@@ -1020,6 +1020,7 @@ static void fill_job(HostJob &J, const sph_geometry *g, const sph_sizing *s, con
   d.ksup = support_of(p);
   d.klen = 0.5 * d.ksup;
   d.ksup2 = d.ksup * d.ksup;
+  d.iband = 1.0 / (2.0 * d.klen * s->h0);   // J.g.h0
   d.bscale = p->boundary_scale > 0.0 ? p->boundary_scale : 1.0;
   d.G.cbase = cbase;
   J.ncell = d.G.ncell;
