@@ -161,19 +161,24 @@ def test_first_step_fields(name):
 FP32_MODES = [binding.SPH_FP32_MIXED, binding.SPH_FP32_COMPENSATED]
 
 
+@pytest.mark.parametrize("skin", [0.0, 0.3])
 @pytest.mark.parametrize("precision", FP32_MODES)
 @pytest.mark.parametrize("name", ["hole2d_20011", "paper_square", "ball3d_30011", "ell3d_30011",
                                   "level_cube_sharp"])
-def test_first_step_fields_fp32_mixed(name, precision):
+def test_first_step_fields_fp32_mixed(name, precision, skin):
     """The FP32 paths' first-step fields (FP32 pair terms summed in FP64, or
     in FP32 with Neumaier compensation), including the force a that the
     viscous sweep completes from FP32 neighbour records, within the FP32
-    field bar (1e-5 of the field's maximum) of the FP64 oracle."""
+    field bar (1e-5 of the field's maximum) of the FP64 oracle; with a
+    Verlet skin the candidate lists are filtered (in 3D by two lanes per
+    particle, the pair-normal pass of the sharp level-set cube included) and
+    the step's interaction count equals the oracle's."""
     wl = case(name)
     ref = oracle.RefJob(wl)
     ref.step(1)
-    gpu = binding.SphMesh(wl, precision=precision, debug_fields=1)
+    gpu = binding.SphMesh(wl, precision=precision, debug_fields=1, verlet_skin=skin)
     gpu.step(1)
+    assert gpu.counters()["interactions_last"] == ref.counters()["interactions_last"]
     pairs = [(binding.FIELD_AP, oracle.F_AP), (binding.FIELD_A, oracle.F_A),
              (binding.FIELD_VT, oracle.F_VT), (binding.FIELD_GAMMA, oracle.F_GAMMA)]
     for fg, fr in pairs:
@@ -344,6 +349,22 @@ def test_positions_after_k_steps_fp32_mixed(name):
     gpu.step(K)
     err = np.abs(gpu.positions() - ref.state()[0]).max() / domain(wl)
     assert err <= TOL32, err
+
+
+@pytest.mark.parametrize("precision", FP32_MODES)
+@pytest.mark.parametrize("name", ["ball3d_30011", "ell3d_30011", "level_cube_sharp"])
+def test_positions_after_k_steps_fp32_verlet_3d(name, precision):
+    """The 3D FP32 Verlet kernel (two lanes per particle) over the parity
+    horizons, through list rebuilds: positions within the FP32 bar."""
+    wl = case(name)
+    K = KSTEPS[name]
+    ref = oracle.RefJob(wl)
+    ref.step(K)
+    gpu = binding.SphMesh(wl, precision=precision, use_graph=1, verlet_skin=0.3)
+    gpu.step(K)
+    err = np.abs(gpu.positions() - ref.state()[0]).max() / domain(wl)
+    assert err <= TOL32, err
+    assert gpu.list_builds() >= 1
 
 
 @pytest.mark.parametrize("name", ["hole2d_20011", "ball3d_30011", "ell3d_30011", "paper_square",
