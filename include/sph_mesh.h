@@ -184,7 +184,9 @@ typedef struct {
                                 terms in FP32, their sums accumulated in FP64;
                                 FP64 positions, integration and projection
                                 (the viscous pair terms take neighbour
-                                positions and h from their FP32 records).
+                                positions and h from their FP32 records; the
+                                per-particle division by gamma, 1 / S and the
+                                time-step terms use FP32 reciprocals and roots).
                                 SPH_FP32_COMPENSATED: as SPH_FP32_MIXED with
                                 the sums in FP32 too, each with Neumaier
                                 compensation */
