@@ -451,6 +451,10 @@ PAPER_VALIDATION = {
 VALIDATION_PRESETS = {
     # the readings as printed: reach 2h, boundary term factor 1, no damping
     "printed": {},
+    # the same with Phase One damping at the top of sec. 3.4.3's range
+    # (eps = 0.2: every feature of the square leaves Phase One by the error
+    # criterion on the oracle)
+    "printed_damped": {"eps_damp": 0.2},
     # the mesh-quality calibration (reach 2.5h, boundary factor 2)
     "calibrated": {"kernel_support": 2.5, "boundary_scale": 2.0},
     # the same with Phase One damping (eps = 0.1, sec. 3.4.3's range) and a
