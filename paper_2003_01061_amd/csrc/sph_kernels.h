@@ -736,9 +736,10 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_forces(
   // multiple of LB; see the append below); it keeps the last LR entries, so
   // that in the FP32 modes a list no longer than LR stays whole in LDS,
   // where the pair sums read it (the FP64 sums read the list from memory:
-  // the ring's addressing would cost them a wave per SIMD)
+  // the ring's addressing would cost them a wave per SIMD); the Verlet build
+  // keeps two blocks, so that its block stores are tested once per batch
   constexpr bool LDS_SUMS = FORCES && sizeof(R) == 4;
-  constexpr int LR = LDS_SUMS ? SPH_LDS_LIST : LB;
+  constexpr int LR = LDS_SUMS ? SPH_LDS_LIST : (MODE == 1 ? 2 * LB : LB);
   static_assert(LR % LB == 0, "the ring holds whole blocks");
   // LPP lanes per particle (2: the Verlet filter and the sums split between
   // two adjacent lanes, which doubles the waves that hide the gathers'
