@@ -654,9 +654,9 @@ __host__ __device__ __forceinline__ void sweep_a_sums(const Geom &g, const Parts
 // reach at most LB - 1 entries into the next block), so the test for a
 // store runs once per batch instead of once per hit.
 template <int NB, int LR>
-__device__ __forceinline__ void append_hits(const uint32_t (&tag)[NB], uint32_t *rc, int stride,
-                                            uint32_t &count, uint4 *&wp, uint32_t wstep,
-                                            uint32_t nblk) {
+__host__ __device__ __forceinline__ void append_hits(const uint32_t (&tag)[NB], uint32_t *rc,
+                                                     int stride, uint32_t &count, uint4 *&wp,
+                                                     uint32_t wstep, uint32_t nblk) {
   static_assert(NB <= LB && LR % LB == 0, "a batch completes at most one block");
   if constexpr (LR >= 2 * LB) {
     const uint32_t c0 = count;
