@@ -43,6 +43,10 @@ static_assert(SPH_NBATCH >= 1 && SPH_NBATCH <= 8, "records are padded by 8");
 // lanes per particle of the FP32 Verlet filter-and-sweep kernel in 3D (1 or
 // 2; 2D keeps one: its short lists do not pay for the per-particle work that
 // both lanes repeat)
+// lanes per particle of the 3D viscous sweep (1 or 2)
+#ifndef SPH_SWEEPB_LANES
+#define SPH_SWEEPB_LANES 2
+#endif
 #ifndef SPH_VERLET_LANES
 #define SPH_VERLET_LANES 2
 #endif

@@ -1183,12 +1183,13 @@ __global__ __launch_bounds__(BLOCK) void k_midpoint(Batch B, Parts s,
 // those of FP32-rounded coordinates; in 3D that record's h carries the
 // feature id in its 6 low mantissa bits (relative change below 2^-17).  The
 // FP64 mode gathers the FP64 record.
-template <int D, int K, typename R, bool MID, bool CMP>
+template <int D, int K, typename R, bool MID, bool CMP, int NL = 1>
 __device__ __forceinline__ void sweep_b_sums(const Parts &s, const typename Vec4<R>::T *__restrict__ ap,
                                              const typename Vec4<R>::T *__restrict__ mid,
                                              const uint32_t *__restrict__ nbr, int n, int i,
                                              uint32_t cnt, const double4 &xi, const double vti[3],
-                                             double vmi, double half, double klen, double Fv[3]) {
+                                             double vmi, double half, double klen, double Fv[3],
+                                             int lane = 0) {
   using R4 = typename Vec4<R>::T;
   const R hi = (R)xi.w;
   constexpr R alpha = kalphaK<K, R>();
@@ -1205,13 +1206,24 @@ __device__ __forceinline__ void sweep_b_sums(const Parts &s, const typename Vec4
   for (int a = 0; a < 3; ++a) aF[a].init(0.0);
   constexpr int NB = SPH_NBATCH;
   static_assert(LB % NB == 0, "record batches tile a list block");
+  // with NL = 2 lanes per particle, lane l takes entries 4l .. 4l + 3 of
+  // every block (the caller adds the lanes' sums)
+  static_assert(NL == 1 || (NL == 2 && NB <= 4), "two lanes: a lane's half block in batches");
+  constexpr int PER = LB / NL;   // entries of a block per lane
   const uint4 *blk = reinterpret_cast<const uint4 *>(nbr) + (size_t)i * (LB / 4);
   for (uint32_t b0 = 0; b0 < cnt; b0 += LB, blk += (size_t)n * (LB / 4)) {
-    const uint4 w0 = blk[0], w1 = blk[1];
-    const uint32_t ub[LB] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
+    uint32_t ub[PER];
+    if constexpr (NL == 1) {
+      const uint4 w0 = blk[0], w1 = blk[1];
+      ub[0] = w0.x; ub[1] = w0.y; ub[2] = w0.z; ub[3] = w0.w;
+      ub[4] = w1.x; ub[5] = w1.y; ub[6] = w1.z; ub[7] = w1.w;
+    } else {
+      const uint4 w = blk[lane];
+      ub[0] = w.x; ub[1] = w.y; ub[2] = w.z; ub[3] = w.w;
+    }
 #pragma unroll
-    for (int hb = 0; hb < LB; hb += NB) {
-      const uint32_t e0 = b0 + hb;
+    for (int hb = 0; hb < PER; hb += NB) {
+      const uint32_t e0 = b0 + (uint32_t)(PER * lane) + hb;
       uint32_t u[NB];
 #pragma unroll
       for (int q = 0; q < NB; ++q) u[q] = e0 + q < cnt ? ub[hb + q] : 0x80000000u;
@@ -1275,7 +1287,7 @@ __device__ __forceinline__ void sweep_b_sums(const Parts &s, const typename Vec4
 // ---------------------------------------------------------------------------
 // sweep B: mid-point velocity, viscous force, damping
 // ---------------------------------------------------------------------------
-template <int D, typename R, bool CMP = false>
+template <int D, typename R, bool CMP = false, int LPP = 1>
 __global__ __launch_bounds__(BLOCK) void k_sweep_b(Batch B, Parts s,
                                                    const uint32_t *__restrict__ nbr,
                                                    const uint32_t *__restrict__ nnb,
@@ -1284,8 +1296,11 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_b(Batch B, Parts s,
                                                    typename Vec4<R>::T *__restrict__ acc,
                                                    double4 *__restrict__ dbg_vm) {
   using R4 = typename Vec4<R>::T;
+  // LPP lanes per particle (2: the neighbour sums split between adjacent lanes)
+  static_assert(LPP == 1 || LPP == 2, "one or two lanes per particle");
   const int n = B.n;
-  const int i = xcd_block() * BLOCK + threadIdx.x;
+  const int i = (xcd_block() * BLOCK + (int)threadIdx.x) / LPP;
+  const int lane = (int)threadIdx.x % LPP;
   bool act = false;
   int fi = 0;
   unsigned long long dtb = ~0ull;
@@ -1310,11 +1325,15 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_b(Batch B, Parts s,
       const uint32_t cnt = nnb[i];
       double fv[3];
       if (k == D)
-        sweep_b_sums<D, D, R, D == 3, CMP>(s, ap, mid, nbr, n, i, cnt, xi, vti, vmi, half, J.klen, fv);
+        sweep_b_sums<D, D, R, D == 3, CMP, LPP>(s, ap, mid, nbr, n, i, cnt, xi, vti, vmi, half, J.klen, fv, lane);
       else if (k == D - 1)
-        sweep_b_sums<D, D - 1, R, D == 3, CMP>(s, ap, mid, nbr, n, i, cnt, xi, vti, vmi, half, J.klen, fv);
+        sweep_b_sums<D, D - 1, R, D == 3, CMP, LPP>(s, ap, mid, nbr, n, i, cnt, xi, vti, vmi, half, J.klen, fv, lane);
       else
-        sweep_b_sums<D, 1, R, D == 3, CMP>(s, ap, mid, nbr, n, i, cnt, xi, vti, vmi, half, J.klen, fv);
+        sweep_b_sums<D, 1, R, D == 3, CMP, LPP>(s, ap, mid, nbr, n, i, cnt, xi, vti, vmi, half, J.klen, fv, lane);
+      if constexpr (LPP == 2) {   // both lanes get the same totals (a + b = b + a)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) fv[a] += __shfl_xor(fv[a], 1);
+      }
       double xa[3] = {xi.x, xi.y, xi.z};
       tangent<D>(J.g, F, xa, fv);
       const double eps = B.grp[fi].eps;
@@ -1326,20 +1345,22 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_b(Batch B, Parts s,
       o.y = (R)a3[1];
       o.z = (R)a3[2];
       o.w = R(0);
-      acc[i] = o;
-      if (dbg_vm) dbg_vm[i] = make_double4(vti[0], vti[1], vti[2], 0.0);
+      if (lane == 0) {
+        acc[i] = o;
+        if (dbg_vm) dbg_vm[i] = make_double4(vti[0], vti[1], vti[2], 0.0);
+      }
       const double rc = J.ksup * xi.w;
       const double dt = step_terms<sizeof(R) == 4>(rc, a3[0] * a3[0] + a3[1] * a3[1] + a3[2] * a3[2],
                                                    vmi * vmi);
       dtb = dbits(dt);
-    } else {
+    } else if (lane == 0) {
       R4 z;
       z.x = z.y = z.z = z.w = R(0);
       acc[i] = z;
       if (dbg_vm) dbg_vm[i] = make_double4(0.0, 0.0, 0.0, 0.0);
     }
   }
-  wave_commit(act, fi, dtb, 0ull, B.smin, nullptr);
+  wave_commit(act && lane == 0, fi, dtb, 0ull, B.smin, nullptr);
 }
 
 // ---------------------------------------------------------------------------

@@ -792,8 +792,13 @@ struct sph_batch {
     if (DD == 3)   // 3D sweep B gathers precomputed mid-point records
       HIPCHK(launch(KID_MIDPOINT, k_midpoint<DD, R>, blocks(n), BLOCK, B, s, (const R4 *)ap,
                     (R4 *)mid));
-    HIPCHK(launch(KID_SWEEP_B, k_sweep_b<DD, R, CMP>, blocks8(n), BLOCK, B, s, (const uint32_t *)nbr,
-                  (const uint32_t *)nnb, (const R4 *)ap, (const R4 *)mid, (R4 *)acc, dbg_vm));
+    if (DD == 3 && SPH_SWEEPB_LANES == 2)   // 3D: two lanes per particle
+      HIPCHK(launch(KID_SWEEP_B, k_sweep_b<DD, R, CMP, 2>, blocks8(2 * (size_t)n), BLOCK, B, s,
+                    (const uint32_t *)nbr, (const uint32_t *)nnb, (const R4 *)ap, (const R4 *)mid,
+                    (R4 *)acc, dbg_vm));
+    else
+      HIPCHK(launch(KID_SWEEP_B, k_sweep_b<DD, R, CMP>, blocks8(n), BLOCK, B, s, (const uint32_t *)nbr,
+                    (const uint32_t *)nnb, (const R4 *)ap, (const R4 *)mid, (R4 *)acc, dbg_vm));
     HIPCHK(launch(KID_REDUCE_B, k_group_reduce, gslots, BLOCK, B, 1));
     HIPCHK(launch(KID_INTEGRATE_HASH, k_integrate_hash<DD, R>, blocks(n), BLOCK, B, s,
                   (const R4 *)acc, cell, rank, cnt));
