@@ -40,10 +40,12 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
 // The particle's terms of Eq. (fa_time_step_size) from |a|^2 and |v|^2 (the
 // third term can never be the smallest, so it is left out): min(0.25
 // sqrt(r_c / |a|), r_c / (40 |v|)), infinite when both vanish.  F32: in
-// FP32 (the FP32 modes hold the time steps to 1e-5).
+// FP32 (the FP32 modes hold the time steps to 1e-5), unless a square is
+// beyond FP32's range, where FP32 would give a time step of 0.
 template <bool F32>
 __device__ __forceinline__ double step_terms(double rc, double a2, double v2) {
   if constexpr (F32) {
+    if (!(a2 < 1e36 && v2 < 1e36)) return step_terms<false>(rc, a2, v2);
     const float rcf = (float)rc, am = __builtin_amdgcn_sqrtf((float)a2),
                 vm = __builtin_amdgcn_sqrtf((float)v2);
     float dt = __builtin_inff();
