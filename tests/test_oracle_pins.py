@@ -872,3 +872,31 @@ def test_particle_volume_counts_boundary_neighbours_by_hand():
     assert abs(j.field(oracle.F_GAMMA)[0] - gam_a) < 1e-13 * gam_a
     w1_0 = 5.0 / (8.0 * h)                    # the 1D kernel at r = 0 (T1's normalisation)
     assert abs(j.field(oracle.F_VT)[2] - 1 / w1_0) < 1e-13 / w1_0
+
+
+def _w3(r, h):
+    """Wendland C2 in 3D with support 2h, from its textbook form
+    psi(s) = (1-s)^4 (4s+1), s = r/2h, normalised to unit integral (T1)."""
+    s = r / (2 * h)
+    return 21 / (16 * math.pi * h ** 3) * (1 - s) ** 4 * (4 * s + 1) if s < 1 else 0.0
+
+
+def test_particle_volume_counts_boundary_neighbours_by_hand_3d():
+    """Eq. (particle_volume) in 3D: a volume particle of the paper's cube next
+    to a face particle counts it in its number density (V~ = 1/S), while its
+    Shepard gamma of Eq. (gamma_disc_renormSPH) sums the volume particles only
+    (V_j = h_j^3); h from the oracle's own sizing field (pinned by T14-T16)."""
+    wl = wk.paper_cube()
+    face = int(np.nonzero(wl.ftype == wk.SURF)[0][0])
+    xa, xc = np.array([50.0, 50.0, 1.0]), np.array([51.0, 50.5, 1.2])
+    xb = np.array([50.5, 50.3, 0.0])
+    wl.xyz = np.array([xa, xc, xb])
+    wl.feature = np.array([0, 0, face], np.int32)
+    j = oracle.RefJob(wl)
+    j.step(1)
+    h = j.field(oracle.F_H)
+    assert 2 * h[0] > np.linalg.norm(xa - xb) and 2 * h[0] > np.linalg.norm(xa - xc)
+    Sa = _w3(0, h[0]) + _w3(np.linalg.norm(xa - xc), h[0]) + _w3(np.linalg.norm(xa - xb), h[0])
+    assert abs(j.field(oracle.F_VT)[0] - 1 / Sa) < 1e-13 / Sa
+    gam_a = _w3(0, h[0]) * h[0] ** 3 + _w3(np.linalg.norm(xa - xc), h[0]) * h[1] ** 3
+    assert abs(j.field(oracle.F_GAMMA)[0] - gam_a) < 1e-13 * gam_a
