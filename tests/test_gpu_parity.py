@@ -506,7 +506,8 @@ def _sample_indices(wl, n_random, seed):
 
 @pytest.mark.parametrize("precision,tol,cfg", [(binding.SPH_FP64, 1e-12, {}),
                                                (binding.SPH_FP32_MIXED, 1e-5, {}),
-                                               (binding.SPH_FP32_MIXED, 1e-5, {"verlet_skin": 0.5})])
+                                               (binding.SPH_FP32_MIXED, 1e-5, {"verlet_skin": 0.5}),
+                                               (binding.SPH_FP32_COMPENSATED, 1e-5, {"verlet_skin": 0.5})])
 def test_full_size_cube_ball_2m_sampled(precision, tol, cfg):
     """The 3D workload at full size (2,000,000 particles): neighbour lists of
     sampled particles bit-exact, and their first-step a^p, V~ and gamma,
