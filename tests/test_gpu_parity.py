@@ -575,12 +575,14 @@ def _list_report(wl, g, idx, which, got, want):
 @pytest.mark.timeout(400)
 @pytest.mark.parametrize("precision,tol,cfg", [
     (binding.SPH_FP32_MIXED, 1e-5, {}),
-    (binding.SPH_FP64, 1e-12, {"cell_factor": 1.25, "scan_tile": 8})])
+    (binding.SPH_FP64, 1e-12, {"cell_factor": 1.25, "scan_tile": 8}),
+    (binding.SPH_FP32_MIXED, 1e-5, {"cell_factor": 1.25, "scan_tile": 8, "verlet_skin": 0.8})])
 def test_full_size_ellipsoids_20m_sampled(precision, tol, cfg):
     """The 16-ellipsoid workload at full size (20,000,000 particles, h ratio
     1:20): lists of sampled particles bit-exact and their first-step a^p, V~
-    and gamma against the oracle's brute force, in the default and in a
-    tuned launch configuration."""
+    and gamma against the oracle's brute force, in the default and in tuned
+    launch configurations (the last the benchmark's: Verlet lists of skin
+    0.8h, filtered by the two-lane kernel)."""
     wl, idx, (so, si, sr, ap_r, vt_r, gam_r) = _ellipsoids_20m()
     g = binding.SphMesh(wl, precision=precision, use_graph=1, debug_fields=1, **cfg)
     off, ids, rel = g.neighbors_of(idx)
